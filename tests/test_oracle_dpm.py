@@ -1,0 +1,199 @@
+"""Pins of the DPM oracle (oracle/dpm.py, oracle/pks.py) against the paper's theorems.
+
+Paper, Sec. 2: P_gamma is a projection; Thm "BEP" (full BEP <=> trace of a solution),
+Prop. "rank" (rank = |gamma_in|), Thm "reduced BEP", Prop. "discrete generalized Green's
+formula"; positivity theorem (CFL-type condition); Sec. 4 initial data of Test A.
+"""
+import numpy as np
+import pytest
+
+import dpm_inputs as inp
+from oracle import aux, dpm, pks
+from oracle import basis as ob
+from oracle import geometry as og
+
+
+@pytest.fixture(scope="module")
+def small():
+    n = 15
+    h, x0 = inp.grid(n)
+    z, y, x = inp.mesh(n)
+    ps = og.PointSets(og.inside_sphere(z, y, x, radius=1.0))
+    assert ps.margin_ok
+    sigma = 1.0 / (0.5 * h * h)
+    P = dpm.projection_matrix(ps, sigma, h)
+    return dict(n=n, h=h, x0=x0, ps=ps, sigma=sigma, P=P)
+
+
+def test_projection_idempotent(small):
+    P = small["P"]
+    assert np.max(np.abs(P @ P - P)) < 1e-12 * max(1.0, np.max(np.abs(P)))
+
+
+def test_rank_is_gamma_in(small):
+    ps, P = small["ps"], small["P"]
+    I = np.eye(ps.n_gamma)
+    s = np.linalg.svd(I - P, compute_uv=False)
+    rank = int(np.sum(s > 1e-10 * s[0]))
+    assert rank == ps.n_gamma_in
+    # reduced BEP rows (gamma_in) are independent and span the full BEP row space
+    rows_in = (I - P)[ps.is_in]
+    s_in = np.linalg.svd(rows_in, compute_uv=False)
+    assert int(np.sum(s_in > 1e-10 * s_in[0])) == ps.n_gamma_in
+
+
+def _random_solution(small, seed=0):
+    """A random grid function u on N+ and its right-hand side f with L u = f on M+."""
+    ps, sigma, h = small["ps"], small["sigma"], small["h"]
+    rng = np.random.default_rng(seed)
+    u = np.where(ps.n_plus, rng.uniform(-1, 1, size=ps.m_plus.shape), 0.0)
+    f = np.where(ps.m_plus, aux.apply_operator(u, sigma, h) / sigma, 0.0)   # L = dt (sigma - Lap)
+    return u, f
+
+
+def test_bep_identity_and_green_formula(small):
+    ps, sigma, h, P = small["ps"], small["sigma"], small["h"], small["P"]
+    u, f = _random_solution(small)
+    u_g = dpm.trace(u, ps.idx)
+    Gf = dpm.particular_solution(f, ps, sigma, h)
+    # Thm BEP: u_gamma - P_gamma u_gamma = Tr_gamma G f
+    assert np.max(np.abs(u_g - P @ u_g - dpm.trace(Gf, ps.idx))) < 1e-12
+    # Green's formula reproduces u on N+
+    w = dpm.green_formula(u_g, f, ps, sigma, h)
+    assert np.max(np.abs(np.where(ps.n_plus, w - u, 0.0))) < 1e-12
+    # a density that is not a trace violates the BEP on gamma_in (reduced BEP detects it)
+    bad = u_g + np.where(ps.is_in, 0.0, 1.0)
+    r = bad - P @ bad - dpm.trace(Gf, ps.idx)
+    assert np.max(np.abs(r[ps.is_in])) > 1e-3
+
+
+def test_bep_matrix_and_lsq(small):
+    ps, sigma, h, x0, P = small["ps"], small["sigma"], small["h"], small["x0"], small["P"]
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    d, th, ph = og.project_sphere(gz, gy, gx)
+    B = ob.basis_matrix(d, th, ph, lmax=2, beta=1)
+    A = dpm.bep_matrix(B, ps, sigma, h)
+    # columns equal Tr_gin (I - P_gamma) phi computed through the dense projection
+    ref = ((np.eye(ps.n_gamma) - P) @ B.T)[ps.is_in]
+    assert np.max(np.abs(A - ref)) < 1e-12
+    g = np.random.default_rng(4).normal(size=ps.n_gamma_in)
+    C = dpm.least_squares(A, g)
+    assert np.max(np.abs(A.T @ (A @ C - g))) < 1e-9 * np.linalg.norm(A) ** 2 * np.linalg.norm(C)
+    Q, R = np.linalg.qr(A)
+    assert np.allclose(C, np.linalg.solve(R, Q.T @ g), atol=1e-10)
+
+
+# ----------------------------------------------------------------------------- PKS forcing
+
+def test_minmod():
+    a = np.array([1.0, -1.0, 1.0, 0.0, 3.0, -3.0])
+    b = np.array([2.0, -2.0, -1.0, 1.0, 2.0, -5.0])
+    c = np.array([3.0, -0.5, 1.0, 1.0, 1.0, -4.0])
+    assert np.array_equal(pks.minmod3(a, b, c), [1.0, -0.5, 0.0, 0.0, 1.0, -3.0])
+
+
+def _sphere_case(n=31):
+    h, x0 = inp.grid(n)
+    z, y, x = inp.mesh(n)
+    ps = og.PointSets(og.inside_sphere(z, y, x))
+    return h, x0, (z, y, x), ps
+
+
+def test_forcing_closed_forms():
+    h, _, (z, y, x), ps = _sphere_case()
+    chi = 0.7
+    # constant rho, quadratic c: g = chi rho0 Lap_h c = 6 chi rho0 (exact for quadratics)
+    rho = np.where(ps.n_plus, 2.0, 0.0)
+    c = np.where(ps.n_plus, x**2 + y**2 + z**2, 0.0)
+    g = pks.convective_term(rho, c, ps.m_plus, h, chi)
+    assert np.allclose(g[ps.m_plus], 6 * chi * 2.0, rtol=1e-11)
+    # linear positive rho (minmod keeps the exact slope away from gamma_ex), linear c
+    rho = np.where(ps.n_plus, 3.0 + 0.5 * x - 0.25 * y + 0.2 * z, 0.0)
+    c = np.where(ps.n_plus, 2.0 * x + 1.5 * y - 1.0 * z, 0.0)
+    g = pks.convective_term(rho, c, ps.m_plus, h, chi)
+    interior = ps.m_plus & ~ps.gamma_in
+    P = np.pad(interior, 1)
+    deep = interior.copy()
+    for s in [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]:
+        deep &= P[1 + s[0]:1 + s[0] + interior.shape[0], 1 + s[1]:1 + s[1] + interior.shape[0],
+                  1 + s[2]:1 + s[2] + interior.shape[0]]
+    expect = chi * (2.0 * 0.5 + 1.5 * -0.25 + -1.0 * 0.2)
+    assert np.allclose(g[deep], expect, rtol=1e-9, atol=1e-9)
+
+
+def test_forcing_conservative():
+    """Fluxes telescope: with data supported away from gamma, the sum of g over M+ vanishes."""
+    h, _, (z, y, x), ps = _sphere_case()
+    r2 = x**2 + y**2 + z**2
+    rho = np.where(ps.n_plus, 1000 * np.exp(-100 * r2), 0.0)
+    c = np.where(ps.n_plus, 500 * np.exp(-50 * r2), 0.0)
+    g = pks.convective_term(rho, c, ps.m_plus, h, 1.0)
+    assert abs(g.sum()) < 1e-9 * np.abs(g).sum()
+    assert np.abs(g).max() > 1.0
+
+
+def test_forcing_positive_under_cfl():
+    """Positivity theorem: rho >= 0 and dt at the CFL bound give f_rho >= 0 (upwind choice)."""
+    h, _, (z, y, x), ps = _sphere_case(23)
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        rho = np.where(ps.n_plus, rng.uniform(0, 1, ps.m_plus.shape) ** 8, 0.0)
+        c = np.where(ps.n_plus, rng.normal(size=ps.m_plus.shape), 0.0)
+        dt = pks.cfl_dt(c, ps.m_plus, h, 1.0)
+        f_rho, _ = pks.pks_rhs(rho, c, ps.m_plus, h, dt, 1.0)
+        assert f_rho[ps.m_plus].min() > -1e-12 * rho.max()
+        # beyond the bound the same data goes negative (the check has power)
+        f_big, _ = pks.pks_rhs(rho, c, ps.m_plus, h, 20 * dt, 1.0)
+        assert f_big[ps.m_plus].min() < 0
+
+
+def test_forcing_reflection_symmetry():
+    h, _, (z, y, x), ps = _sphere_case()
+    r2 = x**2 + y**2 + z**2
+    rho = np.where(ps.n_plus, 1000 * np.exp(-100 * r2), 0.0)
+    c = np.where(ps.n_plus, 500 * np.exp(-50 * r2), 0.0)
+    f_rho, f_c = pks.pks_rhs(rho, c, ps.m_plus, h, 1e-6, 1.0)
+    for f in (f_rho, f_c):
+        assert np.allclose(f, f[::-1, :, :], rtol=1e-12, atol=1e-9)
+        assert np.allclose(f, f[:, :, ::-1], rtol=1e-12, atol=1e-9)
+        assert np.allclose(f, np.transpose(f, (2, 1, 0)), rtol=1e-12, atol=1e-9)
+
+
+def test_dpm_step_constant_state():
+    """A constant state is an exact discrete Neumann solution, representable by Y_00."""
+    n = 15
+    h, x0 = inp.grid(n)
+    z, y, x = inp.mesh(n)
+    ps = og.PointSets(og.inside_sphere(z, y, x))
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    d, th, ph = og.project_sphere(gz, gy, gx)
+    B = ob.basis_matrix(d, th, ph, lmax=2, beta=1)
+    dt = 0.01
+    A = dpm.bep_matrix(B, ps, 1.0 / dt, h)
+    rho0, c0 = 3.0, 5.0
+    rho = np.where(ps.n_plus, rho0, 0.0)
+    c = np.where(ps.n_plus, c0, 0.0)
+    r1, c1, _ = pks.dpm_step(rho, c, ps, B, A, h, dt, 1.0)
+    assert np.allclose(r1[ps.n_plus], rho0, rtol=1e-11)
+    assert np.allclose(c1[ps.n_plus], (1 - dt) * c0 + dt * rho0, rtol=1e-11)
+    assert np.all(r1[~ps.n_plus] == 0)
+
+
+def test_dpm_step_symmetry_and_positivity():
+    """Test A data on a centred sphere stays symmetric and non-negative for a CFL-sized step."""
+    n = 15
+    h, x0 = inp.grid(n)
+    z, y, x = inp.mesh(n)
+    ps = og.PointSets(og.inside_sphere(z, y, x))
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    d, th, ph = og.project_sphere(gz, gy, gx)
+    B = ob.basis_matrix(d, th, ph, lmax=0, beta=1)
+    r2 = x**2 + y**2 + z**2
+    rho = np.where(ps.n_plus, 10 * np.exp(-2 * r2), 0.0)
+    c = np.where(ps.n_plus, 5 * np.exp(-1 * r2), 0.0)
+    dt = min(pks.cfl_dt(c, ps.m_plus, h, 1.0), 0.5 * h * h)
+    A = dpm.bep_matrix(B, ps, 1.0 / dt, h)
+    r1, c1, coefs = pks.dpm_step(rho, c, ps, B, A, h, dt, 1.0)
+    for f in (r1, c1):
+        assert np.allclose(f, f[::-1], atol=1e-10) and np.allclose(f, np.transpose(f, (1, 2, 0)), atol=1e-10)
+        assert f[ps.n_plus].min() >= -1e-12
