@@ -1,0 +1,199 @@
+/*
+ * dpm.h -- C ABI of the MI355X (gfx950) auxiliary-problem solver of the Difference Potentials
+ * Method for the 3D Patlak-Keller-Segel system (Epshteyn & Xia, arXiv 1811.03557).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Grid: N interior nodes per axis of a cube (the set M0), spacing h, coordinate x0 of the
+ *    first interior node (the same on all three axes).  Nodes on the ghost layer (N0 \ M0) carry
+ *    zero Dirichlet data.  Volumes are C-ordered [z][y][x] (x fastest) over M0 only; batches are
+ *    [nrhs][z][y][x].
+ *  - Every pointer argument named "device" is device memory owned by the caller (for example a
+ *    torch tensor); the library never frees it.  Pointers must be 16-byte aligned.
+ *  - stream: a hipStream_t passed as void* (NULL = the default stream).  Work is enqueued
+ *    asynchronously; results are valid after the stream is synchronised, unless the call says
+ *    it synchronises.
+ *  - Every call validates all of its arguments before it enqueues anything; on an error nothing
+ *    is launched and dpm_last_error() returns a thread-local message.
+ *  - dpm_status codes: DPM_OK success; DPM_EINVAL bad argument; DPM_ENOMEM allocation failed;
+ *    DPM_EHIP a HIP runtime error; DPM_ENOTCONV iterative refinement did not reach rtol (the
+ *    last iterate is in u); DPM_EGEOM invalid geometry (empty gamma or no margin to the ghost
+ *    layer); DPM_ERANK the boundary least-squares matrix is rank deficient.
+ */
+#ifndef DPM_H
+#define DPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DPM_OK = 0,
+  DPM_EINVAL = 1,
+  DPM_ENOMEM = 2,
+  DPM_EHIP = 3,
+  DPM_ENOTCONV = 4,
+  DPM_EGEOM = 5,
+  DPM_ERANK = 6
+} dpm_status;
+
+/* Arithmetic of the per-axis sine transforms. */
+typedef enum {
+  DPM_FP64 = 0,   /* FP64 transforms */
+  DPM_FP32 = 1,   /* FP32 transforms (FP64 residual refinement when io_fp64 and max_refine > 0) */
+  DPM_BF16X3 = 2  /* split bf16 hi/lo dense-DST on MFMA, FP32 accumulation (N <= 256) */
+} dpm_precision;
+
+typedef struct {
+  int32_t n;     /* interior nodes per axis, 1 <= n <= 1023 */
+  double h;      /* mesh spacing, > 0 */
+  double sigma;  /* shift of the operator sigma I - Lap_h, >= 0 and finite */
+  double x0;     /* coordinate of the first interior node (geometry calls only) */
+} dpm_grid;
+
+typedef struct {
+  int32_t prec;        /* dpm_precision */
+  int32_t io_fp64;     /* 1: b and u are FP64; 0: FP32 (only with DPM_FP32 and max_refine == 0) */
+  double rtol;         /* refinement target ||u_k - u||/||u|| (estimated), e.g. 1e-10 */
+  int32_t max_refine;  /* refinement iterations after the first solve (0 = none) */
+  int32_t rhs_chunk;   /* right-hand sides per batched launch (0 = library choice) */
+  void* workspace;     /* device scratch of >= workspace_bytes, from dpm_workspace_size */
+  size_t workspace_bytes;
+} dpm_opts;
+
+typedef struct {
+  int32_t refine_iters;  /* refinement iterations actually applied (max over the batch) */
+  double est_rel_err;    /* max over the batch of ||last correction||_inf / ||u||_inf */
+} dpm_info;
+
+/* Scratch bytes needed by aux_solve / aux_solve_batched for these arguments (host call). */
+dpm_status dpm_workspace_size(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts,
+                              size_t* bytes);
+
+/* Builds the per-(device, n) tables (sine/twiddle and eigenvalue tables) ahead of time.  The
+ * first solve of a size does this by itself; call it first when that solve is captured into a
+ * HIP graph, since building uploads with synchronous copies. */
+dpm_status dpm_prepare(int32_t n);
+
+/*
+ * aux_solve -- the discrete auxiliary problem (paper Sec. 2, Definition of the AP, eqs
+ * discrete_ap and discrete_ap_boundary) in sigma-form:
+ *     (sigma I - Lap_h) u = b on M0,  u = 0 on N0 \ M0,
+ * with Lap_h the 7-point Laplacian (eq stencil:7-point).  The paper's AP with operator
+ * L = I - dt Lap_h and right-hand side q is this call with sigma = 1/dt and b = q/dt.
+ * b, u: device, N^3 values, FP64 when opts->io_fp64 else FP32.  b and u must not overlap.
+ * info: host, nullable; when given, the call synchronises the stream to fill it.
+ */
+dpm_status aux_solve(const dpm_grid* grid, const void* b, void* u, const dpm_opts* opts,
+                     void* stream, dpm_info* info);
+
+/* nrhs independent auxiliary problems with the same grid and sigma: b, u are [nrhs][N^3]. */
+dpm_status aux_solve_batched(const dpm_grid* grid, int32_t nrhs, const void* b, void* u,
+                             const dpm_opts* opts, void* stream, dpm_info* info);
+
+/* Geometry of the domain Omega inside the cube: a sphere (axes[0] = radius) or an ellipsoid
+ * with semi-axes (axes[0], axes[1], axes[2]) along (x, y, z). */
+typedef struct {
+  int32_t kind;       /* 0 sphere, 1 ellipsoid */
+  double center[3];   /* (x, y, z) */
+  double axes[3];
+} dpm_geometry;
+
+/* M+ mask (paper Def. "point sets"): m_plus[i] = 1 if node i lies strictly inside Omega, else
+ * 0.  m_plus: device, N^3 uint8. */
+dpm_status dpm_classify(const dpm_grid* grid, const dpm_geometry* geom, uint8_t* m_plus,
+                        void* stream);
+
+/*
+ * dpm_gamma_points -- the discrete grid boundary gamma = N+ cap N-, gamma_in = M+ cap gamma
+ * (paper Def. "point sets").  Two-call pattern: with idx == NULL only the counts are returned;
+ * otherwise idx (device, n_gamma int32) receives the linear indices of gamma in ascending order
+ * and is_in (device, n_gamma uint8) flags gamma_in.  m_plus: device N^3 uint8.  Synchronises
+ * the stream (the counts are host values).  DPM_EGEOM if gamma is empty or N+ touches the
+ * ghost layer.
+ */
+dpm_status dpm_gamma_points(const dpm_grid* grid, const uint8_t* m_plus, int32_t* n_gamma,
+                            int32_t* n_gamma_in, int32_t* idx, uint8_t* is_in, void* stream);
+
+/*
+ * dpm_basis -- spectral densities of the extension operator (paper Sec. 2, eqs
+ * extension_operator1, spectral_approximation_sd, extension_operator_recast): for each gamma
+ * node, its projection onto Gamma (signed distance d, positive outside; polar/azimuthal angles
+ * of the foot point, parametric angles for an ellipsoid) and the real orthonormal spherical
+ * harmonics Y_lm, l <= lmax, m = -l..l, without Condon-Shortley phase.  basis: device,
+ * n_basis x n_gamma FP64 (row nu contiguous), n_basis = (beta + 1)(lmax + 1)^2; rows
+ * (lmax+1)^2 .. carry (d^2/2) Y_lm when beta = 1.  d_out (nullable, device n_gamma FP64)
+ * receives d.
+ */
+dpm_status dpm_basis(const dpm_grid* grid, const dpm_geometry* geom, int32_t n_gamma,
+                     const int32_t* idx, int32_t lmax, int32_t beta, double* basis,
+                     double* d_out, void* stream);
+
+typedef struct dpm_bep dpm_bep; /* library-owned: mask, gamma lists, basis, BEP matrix, QR */
+
+/*
+ * dpm_build_boundary_matrix -- paper Algorithm "Main Steps", Step 2: the reduced-BEP matrix
+ * (eq BEP_recast) A[:, nu] = Tr_gamma_in (I - P_gamma) basis_nu, one AP solve per column with
+ * right-hand side 1_{M-} (sigma - Lap_h)[basis_nu extended by zero] (Def. "DP" in sigma-form),
+ * followed by an FP64 Householder QR of A kept in the handle.
+ * m_plus: device N^3 uint8; basis: device n_basis x n_gamma FP64 in the order of
+ * dpm_gamma_points.  opts selects the precision of the solves (refinement applies).
+ * A_out: nullable device |gamma_in| x n_basis FP64, column-major.  Allocates the handle's
+ * device memory and synchronises the stream.  Release with dpm_bep_destroy.
+ */
+dpm_status dpm_build_boundary_matrix(const dpm_grid* grid, const uint8_t* m_plus,
+                                     int32_t n_basis, const double* basis, const dpm_opts* opts,
+                                     void* stream, dpm_bep** out, double* A_out);
+
+/* Counts of a built handle (host values). */
+dpm_status dpm_bep_info(const dpm_bep* bep, int32_t* n_gamma, int32_t* n_gamma_in,
+                        int32_t* n_basis, double* min_abs_rdiag, double* max_abs_rdiag);
+
+/*
+ * dpm_bep_solve -- paper Step 5: least-squares coefficients C = argmin ||A C - g||_2 of the
+ * reduced BEP (eq BEP_recast) from the QR kept in the handle.  g: device nvec x |gamma_in| FP64;
+ * C: device nvec x n_basis FP64.  Asynchronous.
+ */
+dpm_status dpm_bep_solve(const dpm_bep* bep, int32_t nvec, const double* g, double* C,
+                         void* stream);
+
+/* Scratch bytes needed by dpm_step with these options. */
+dpm_status dpm_step_workspace_size(const dpm_bep* bep, const dpm_opts* opts, size_t* bytes);
+
+/*
+ * dpm_step -- one IMEX time step of the DPM (paper Algorithm "Main Steps", Steps 4a, 5, 6, 7)
+ * for both species with L = I - dt Lap_h (the handle must have been built with sigma = 1/dt):
+ *   f_rho = rho - dt g (upwind, minmod; eqs discrete_convective_term .. slope_limiter),
+ *   f_c = (1 - dt) c + dt rho on M+ (eq discrete_chemotaxis, alpha = gamma_rho = gamma_c = 1);
+ *   particular solutions G f, Tr_gamma_in G f, coefficients by least squares, densities
+ *   u_gamma = basis^T C, and the discrete generalized Green's formula u = P u_gamma + G f on
+ *   N+ (computed as one AP solve per species by linearity).
+ * rho_in, c_in: device N^3 FP64 values on N+ (other entries ignored); rho_out, c_out: device
+ * N^3 FP64, zero off N+; they may alias the inputs.  chi: chemotactic sensitivity.
+ * info: host, nullable (synchronises when given).
+ */
+dpm_status dpm_step(const dpm_bep* bep, double dt, double chi, const double* rho_in,
+                    const double* c_in, double* rho_out, double* c_out, const dpm_opts* opts,
+                    void* stream, dpm_info* info);
+
+/*
+ * dpm_gauss_state -- initial data amp * exp(-rate |x - center|^2) (paper Sec. 4, Tests A and B)
+ * at the nodes of M+ and, on gamma, at the projection of each node onto Gamma (paper eq
+ * boundary_approx); zero elsewhere.  out: device N^3 FP64.
+ */
+dpm_status dpm_gauss_state(const dpm_bep* bep, const dpm_geometry* geom, double amp,
+                           double rate, const double center[3], double* out, void* stream);
+
+void dpm_bep_destroy(dpm_bep* bep);
+
+/* Thread-local text of the last error (empty string when none). */
+const char* dpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPM_H */

@@ -1,0 +1,93 @@
+"""ctypes view of libdpm.so (the C ABI declared in include/dpm.h).
+
+Argument marshalling only.  Loading fails loudly when the library has not been built: there
+is no CPU fallback anywhere in the product path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpm.so")
+
+DPM_OK, DPM_EINVAL, DPM_ENOMEM, DPM_EHIP, DPM_ENOTCONV, DPM_EGEOM, DPM_ERANK = range(7)
+DPM_FP64, DPM_FP32, DPM_BF16X3 = 0, 1, 2
+STATUS_NAMES = {0: "DPM_OK", 1: "DPM_EINVAL", 2: "DPM_ENOMEM", 3: "DPM_EHIP",
+                4: "DPM_ENOTCONV", 5: "DPM_EGEOM", 6: "DPM_ERANK"}
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int32), ("h", C.c_double), ("sigma", C.c_double), ("x0", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("io_fp64", C.c_int32), ("rtol", C.c_double),
+                ("max_refine", C.c_int32), ("rhs_chunk", C.c_int32),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+
+
+class Info(C.Structure):
+    _fields_ = [("refine_iters", C.c_int32), ("est_rel_err", C.c_double)]
+
+
+class Geometry(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("center", C.c_double * 3), ("axes", C.c_double * 3)]
+
+
+# exported symbol -> (restype, argtypes)
+_P = C.c_void_p
+_I = C.c_int32
+_D = C.c_double
+SIGNATURES = {
+    "dpm_workspace_size": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
+    "dpm_prepare": (C.c_int, [_I]),
+    "aux_solve": (C.c_int, [C.POINTER(Grid), _P, _P, C.POINTER(Opts), _P, C.POINTER(Info)]),
+    "aux_solve_batched": (C.c_int, [C.POINTER(Grid), _I, _P, _P, C.POINTER(Opts), _P, C.POINTER(Info)]),
+    "dpm_classify": (C.c_int, [C.POINTER(Grid), C.POINTER(Geometry), _P, _P]),
+    "dpm_gamma_points": (C.c_int, [C.POINTER(Grid), _P, C.POINTER(_I), C.POINTER(_I), _P, _P, _P]),
+    "dpm_basis": (C.c_int, [C.POINTER(Grid), C.POINTER(Geometry), _I, _P, _I, _I, _P, _P, _P]),
+    "dpm_build_boundary_matrix": (C.c_int, [C.POINTER(Grid), _P, _I, _P, C.POINTER(Opts), _P,
+                                            C.POINTER(_P), _P]),
+    "dpm_bep_info": (C.c_int, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I), C.POINTER(_D),
+                               C.POINTER(_D)]),
+    "dpm_bep_solve": (C.c_int, [_P, _I, _P, _P, _P]),
+    "dpm_step_workspace_size": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
+    "dpm_step": (C.c_int, [_P, _D, _D, _P, _P, _P, _P, C.POINTER(Opts), _P, C.POINTER(Info)]),
+    "dpm_gauss_state": (C.c_int, [_P, C.POINTER(Geometry), _D, _D, C.POINTER(_D), _P, _P]),
+    "dpm_bep_destroy": (None, [_P]),
+    "dpm_last_error": (C.c_char_p, []),
+}
+
+
+class DPMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libdpm.so once; raises if it is missing (build it with paper_1811_03557_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build the HIP library first "
+                           "(python -m paper_1811_03557_amd.build)")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != DPM_OK:
+        msg = load().dpm_last_error()
+        raise DPMError(status, msg.decode() if msg else "")

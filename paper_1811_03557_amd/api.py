@@ -1,0 +1,144 @@
+"""Python binding of libdpm with the names of the C ABI; torch tensors carry device memory.
+
+Every function marshals tensors to device pointers and calls the library: the arithmetic of
+every step runs in the HIP kernels.  Tensors must be CUDA (HIP) tensors, contiguous, FP64
+unless stated.  Workspaces are allocated through torch's caching allocator.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+PRECISIONS = {"fp64": L.DPM_FP64, "fp32": L.DPM_FP32, "bf16x3": L.DPM_BF16X3}
+
+
+def _stream(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def grid(n: int, h: float, sigma: float = 0.0, x0: float = 0.0) -> L.Grid:
+    return L.Grid(int(n), float(h), float(sigma), float(x0))
+
+
+def opts(prec: str = "fp64", io_fp64: bool = True, rtol: float = 1e-10, max_refine: int = 0,
+         rhs_chunk: int = 0) -> L.Opts:
+    return L.Opts(PRECISIONS[prec], 1 if io_fp64 else 0, float(rtol), int(max_refine),
+                  int(rhs_chunk), None, 0)
+
+
+def workspace_size(g: L.Grid, nrhs: int, o: L.Opts) -> int:
+    lib = L.load()
+    nb = C.c_size_t(0)
+    L.check(lib.dpm_workspace_size(C.byref(g), int(nrhs), C.byref(o), C.byref(nb)))
+    return int(nb.value)
+
+
+def prepare(n: int) -> None:
+    L.check(L.load().dpm_prepare(int(n)))
+
+
+def aux_solve_batched(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64",
+                      rtol: float = 1e-10, max_refine: int = 0, out: torch.Tensor | None = None,
+                      workspace: torch.Tensor | None = None, stream=None, info: bool = False,
+                      rhs_chunk: int = 0):
+    """Solve (sigma I - Lap_h) u = b for b of shape (nrhs, n, n, n) (or (n, n, n)).
+
+    Returns u (and a dpm_info dict when info=True; that synchronises the stream).
+    """
+    lib = L.load()
+    single = b.dim() == 3
+    bb = b.unsqueeze(0) if single else b
+    if bb.dim() != 4 or not (bb.shape[1] == bb.shape[2] == bb.shape[3]):
+        raise ValueError("b must have shape (nrhs, n, n, n) or (n, n, n)")
+    nrhs, n = int(bb.shape[0]), int(bb.shape[1])
+    io_fp64 = bb.dtype == torch.float64
+    if not io_fp64 and bb.dtype != torch.float32:
+        raise ValueError("b must be float64 or float32")
+    if out is None:
+        out = torch.empty_like(bb)
+    uu = out.view(bb.shape) if out.dim() == 3 else out
+    g = grid(n, h, sigma)
+    o = opts(prec, io_fp64, rtol, max_refine, rhs_chunk)
+    nbytes = workspace_size(g, nrhs, o)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=bb.device)
+    o.workspace = C.c_void_p(workspace.data_ptr())
+    o.workspace_bytes = workspace.numel()
+    inf = L.Info()
+    st = lib.aux_solve_batched(C.byref(g), nrhs, C.c_void_p(_dev(bb, "b")),
+                               C.c_void_p(_dev(uu, "u", bb.dtype)), C.byref(o),
+                               C.c_void_p(_stream(stream)), C.byref(inf) if info else None)
+    L.check(st)
+    res = out if not single else out.view(n, n, n)
+    if info:
+        return res, {"refine_iters": inf.refine_iters, "est_rel_err": inf.est_rel_err}
+    return res
+
+
+def aux_solve(b: torch.Tensor, sigma: float, h: float, **kw):
+    """Single right-hand side (n, n, n); see aux_solve_batched."""
+    if b.dim() != 3:
+        raise ValueError("aux_solve takes one (n, n, n) right-hand side")
+    return aux_solve_batched(b, sigma, h, **kw)
+
+
+def geometry(kind: str = "sphere", center=(0.0, 0.0, 0.0), axes=(1.0, 1.0, 1.0)) -> L.Geometry:
+    k = {"sphere": 0, "ellipsoid": 1}[kind]
+    ax = (axes, axes, axes) if isinstance(axes, (int, float)) else tuple(axes)
+    if len(ax) == 1:
+        ax = (ax[0], ax[0], ax[0])
+    return L.Geometry(k, (C.c_double * 3)(*center), (C.c_double * 3)(*ax))
+
+
+def classify(n: int, h: float, x0: float, geo: L.Geometry, device="cuda", stream=None):
+    """M+ mask (uint8, n^3) of the nodes strictly inside the geometry."""
+    m = torch.empty((n, n, n), dtype=torch.uint8, device=device)
+    g = grid(n, h, 0.0, x0)
+    L.check(L.load().dpm_classify(C.byref(g), C.byref(geo), C.c_void_p(m.data_ptr()),
+                                  C.c_void_p(_stream(stream))))
+    return m
+
+
+def gamma_points(m_plus: torch.Tensor, h: float = 1.0, x0: float = 0.0, stream=None):
+    """(idx int32, is_in uint8) of the discrete grid boundary, ascending linear index."""
+    lib = L.load()
+    n = int(m_plus.shape[-1])
+    g = grid(n, h, 0.0, x0)
+    ng, ngi = C.c_int32(0), C.c_int32(0)
+    mp = C.c_void_p(_dev(m_plus, "m_plus", torch.uint8))
+    L.check(lib.dpm_gamma_points(C.byref(g), mp, C.byref(ng), C.byref(ngi), None, None,
+                                 C.c_void_p(_stream(stream))))
+    idx = torch.empty(ng.value, dtype=torch.int32, device=m_plus.device)
+    is_in = torch.empty(ng.value, dtype=torch.uint8, device=m_plus.device)
+    L.check(lib.dpm_gamma_points(C.byref(g), mp, C.byref(ng), C.byref(ngi),
+                                 C.c_void_p(idx.data_ptr()), C.c_void_p(is_in.data_ptr()),
+                                 C.c_void_p(_stream(stream))))
+    return idx, is_in
+
+
+def basis(n: int, h: float, x0: float, geo: L.Geometry, idx: torch.Tensor, lmax: int,
+          beta: int = 1, stream=None):
+    """(basis (n_basis, n_gamma) FP64, d (n_gamma) FP64) of the spectral densities."""
+    ng = int(idx.numel())
+    nb = (beta + 1) * (lmax + 1) ** 2
+    B = torch.empty((nb, ng), dtype=torch.float64, device=idx.device)
+    d = torch.empty(ng, dtype=torch.float64, device=idx.device)
+    g = grid(n, h, 0.0, x0)
+    L.check(L.load().dpm_basis(C.byref(g), C.byref(geo), ng, C.c_void_p(_dev(idx, "idx", torch.int32)),
+                               int(lmax), int(beta), C.c_void_p(B.data_ptr()),
+                               C.c_void_p(d.data_ptr()), C.c_void_p(_stream(stream))))
+    return B, d

@@ -1,0 +1,253 @@
+// Driver of the auxiliary-problem solve: sweep sequence, FP64 iterative refinement with a
+// device-side stop test (no host synchronisation, fixed launch count), batching in chunks.
+#include <cmath>
+
+#include "common.h"
+
+namespace dpm {
+
+namespace {
+
+// Per right-hand-side refinement state lives at the start of the workspace.
+struct FlagLayout {
+  size_t done, iters, cmax, umax, prev, est, total;
+};
+FlagLayout flag_layout(int nrhs) {
+  FlagLayout f;
+  size_t o = 0;
+  f.done = o; o = align_up(o + sizeof(int) * nrhs, 256);
+  f.iters = o; o = align_up(o + sizeof(int) * nrhs, 256);
+  f.cmax = o; o = align_up(o + 8 * nrhs, 256);
+  f.umax = o; o = align_up(o + 8 * nrhs, 256);
+  f.prev = o; o = align_up(o + 8 * nrhs, 256);
+  f.est = o; o = align_up(o + 8 * nrhs, 256);
+  f.total = o;
+  return f;
+}
+
+__global__ void k_flags_reset(SolveFlags f, int nrhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nrhs) {
+    f.done[i] = 0;
+    f.iters[i] = 0;
+    f.cmax[i] = 0ull;
+    f.umax[i] = 0ull;
+    f.prev[i] = 0.0;
+    f.est[i] = 1.0;
+  }
+}
+
+// After solve k (k = 0: the first solve, whose "correction" is u itself): the error left after
+// the update is estimated from the geometric contraction of the corrections,
+// est_k = ||c_k||^2 / (||c_{k-1}|| ||u_k||); refinement stops once est_k <= 0.1 rtol.
+__global__ void k_flags_check(SolveFlags f, int rhs0, int nb, int k, double rtol) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int r = rhs0 + i;
+  if (f.done[r]) return;
+  const double c = __longlong_as_double((long long)f.cmax[r]);
+  const double u = __longlong_as_double((long long)f.umax[r]);
+  if (k > 0) {
+    f.iters[r] = k;
+    const double pc = f.prev[r];
+    double est = (u > 0.0 && pc > 0.0) ? (c / u) * (c / pc) : (c == 0.0 ? 0.0 : 1.0);
+    if (!(est == est)) est = 1.0;  // NaN: not converged
+    f.est[r] = est;
+    if (est <= 0.1 * rtol) f.done[r] = 1;
+  } else {
+    f.est[r] = 1.0;
+  }
+  f.prev[r] = c;
+  f.cmax[r] = 0ull;
+  f.umax[r] = 0ull;
+}
+
+int default_chunk(int n, int nrhs, int real_bytes, bool need_ws) {
+  if (!need_ws) return nrhs;
+  const double vol = (double)n * n * n * real_bytes;
+  int c = (int)std::floor(64.0e6 / vol);
+  if (c < 1) c = 1;
+  if (c > nrhs) c = nrhs;
+  if (c > 65535) c = 65535;
+  return c;
+}
+
+bool needs_ws(const dpm_opts& o) {
+  if (o.prec == DPM_FP32) return o.io_fp64 != 0;
+  if (o.prec == DPM_FP64) return o.max_refine > 0;
+  return true;  // BF16X3: FP32 tile workspace
+}
+
+int real_bytes_of(const dpm_opts& o) { return o.prec == DPM_FP64 ? 8 : 4; }
+
+}  // namespace
+
+size_t flags_bytes(int nrhs) { return flag_layout(nrhs).total; }
+
+dpm_status validate_grid(const dpm_grid* g) {
+  if (!g) { set_error("grid is NULL"); return DPM_EINVAL; }
+  if (g->n < 1 || g->n > 1023) { set_error("n = %d out of range [1, 1023]", g->n); return DPM_EINVAL; }
+  if (!fft_size_supported(g->n)) {
+    set_error("n = %d: n + 1 must be a power of two with 7 <= n <= 1023", g->n);
+    return DPM_EINVAL;
+  }
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) { set_error("h must be finite and > 0"); return DPM_EINVAL; }
+  if (!(g->sigma >= 0.0) || !std::isfinite(g->sigma)) {
+    set_error("sigma must be finite and >= 0");
+    return DPM_EINVAL;
+  }
+  if (!std::isfinite(g->x0)) { set_error("x0 must be finite"); return DPM_EINVAL; }
+  return DPM_OK;
+}
+
+dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o) {
+  if (!o) { set_error("opts is NULL"); return DPM_EINVAL; }
+  if (o->prec != DPM_FP64 && o->prec != DPM_FP32 && o->prec != DPM_BF16X3) {
+    set_error("unknown precision %d", o->prec);
+    return DPM_EINVAL;
+  }
+  if (o->io_fp64 != 0 && o->io_fp64 != 1) { set_error("io_fp64 must be 0 or 1"); return DPM_EINVAL; }
+  if (!o->io_fp64 && !(o->prec == DPM_FP32 && o->max_refine == 0)) {
+    set_error("FP32 input/output requires prec = DPM_FP32 and max_refine = 0");
+    return DPM_EINVAL;
+  }
+  if (o->max_refine < 0 || o->max_refine > 64) { set_error("max_refine out of range [0, 64]"); return DPM_EINVAL; }
+  if (o->max_refine > 0 && !(o->rtol > 0.0 && std::isfinite(o->rtol))) {
+    set_error("rtol must be finite and > 0 when refining");
+    return DPM_EINVAL;
+  }
+  if (o->rhs_chunk < 0) { set_error("rhs_chunk must be >= 0"); return DPM_EINVAL; }
+  if (o->prec == DPM_BF16X3 && g.n > 255) { set_error("DPM_BF16X3 supports n <= 255"); return DPM_EINVAL; }
+  return DPM_OK;
+}
+
+dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes) {
+  const int rb = real_bytes_of(o);
+  const bool ws = needs_ws(o);
+  int chunk = o.rhs_chunk > 0 ? (o.rhs_chunk < nrhs ? o.rhs_chunk : nrhs) : default_chunk(g.n, nrhs, rb, ws);
+  size_t vol = (size_t)g.n * g.n * g.n;
+  size_t total = flags_bytes(nrhs);
+  if (ws) total += align_up(vol * (size_t)chunk * (size_t)rb, 256);
+  *bytes = total;
+  return DPM_OK;
+}
+
+// One solve (five sweeps) of nb right-hand sides.  in_kind/out_kind select the first and last
+// sweeps; vol_in/vol_out are the first sweep's source and the last sweep's destination, ws the
+// volume the middle sweeps work on.
+static dpm_status five_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind in_kind,
+                              const void* src, OutKind out_kind, void* dst, void* ws,
+                              const double* b, const double* u, const SolveFlags* fl, int rhs0,
+                              int nb, bool gated, bool bf16, hipStream_t s) {
+  PassArgs a{};
+  a.tw = rb == 4 ? (const void*)pl->tw_f : (const void*)pl->tw_d;
+  a.lam_hat = pl->lam;
+  a.sigma = g.sigma;
+  a.inv_h2 = 1.0 / (g.h * g.h);
+  a.done = gated ? fl->done : nullptr;
+  a.rhs0 = rhs0;
+  a.b = b;
+  a.u = u;
+  auto pass = [&](AxisKind ax, bool z, InKind ik, OutKind ok, const void* i, void* o, bool track) {
+    PassArgs q = a;
+    q.in = i;
+    q.out = o;
+    q.cmax = track ? fl->cmax : nullptr;
+    q.umax = track ? fl->umax : nullptr;
+    if (bf16) return launch_bf16x3_pass(g.n, ax, z, ik, ok, q, pl, nb, s);
+    return launch_dst_pass(rb, g.n, ax, z, ik, ok, q, nb, s);
+  };
+  DPM_TRY(pass(AX_X, false, in_kind, OUT_WS, src, ws, false));
+  DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, ws, ws, false));
+  DPM_TRY(pass(AX_Z, true, IN_WS, OUT_WS, ws, ws, false));
+  DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, ws, ws, false));
+  DPM_TRY(pass(AX_X, false, IN_WS, out_kind, ws, dst, fl != nullptr));
+  return DPM_OK;
+}
+
+dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, const dpm_opts& o,
+                          hipStream_t s, dpm_info* info) {
+  const Plan* pl = nullptr;
+  DPM_TRY(get_plan(g.n, &pl));
+  const int rb = real_bytes_of(o);
+  const bool bf16 = o.prec == DPM_BF16X3;
+  const bool ws_needed = needs_ws(o);
+  const int chunk = o.rhs_chunk > 0 ? (o.rhs_chunk < nrhs ? o.rhs_chunk : nrhs)
+                                    : default_chunk(g.n, nrhs, rb, ws_needed);
+  size_t need = 0;
+  DPM_TRY(workspace_size_impl(g, nrhs, o, &need));
+  if (o.workspace_bytes < need || (need > 0 && o.workspace == nullptr)) {
+    set_error("workspace too small: %zu bytes given, %zu needed", o.workspace_bytes, need);
+    return DPM_EINVAL;
+  }
+  char* wsb = static_cast<char*>(o.workspace);
+  const FlagLayout fo = flag_layout(nrhs);
+  SolveFlags fl;
+  fl.done = reinterpret_cast<int*>(wsb + fo.done);
+  fl.iters = reinterpret_cast<int*>(wsb + fo.iters);
+  fl.cmax = reinterpret_cast<unsigned long long*>(wsb + fo.cmax);
+  fl.umax = reinterpret_cast<unsigned long long*>(wsb + fo.umax);
+  fl.prev = reinterpret_cast<double*>(wsb + fo.prev);
+  fl.est = reinterpret_cast<double*>(wsb + fo.est);
+  void* vol_ws = ws_needed ? (void*)(wsb + fo.total) : nullptr;
+
+  hipLaunchKernelGGL(k_flags_reset, dim3((nrhs + 255) / 256), dim3(256), 0, s, fl, nrhs);
+  DPM_TRY_HIP(hipGetLastError());
+
+  const size_t vol = (size_t)g.n * g.n * g.n;
+  const size_t io_bytes = o.io_fp64 ? 8 : 4;
+  const bool refine = o.max_refine > 0;
+  for (int c0 = 0; c0 < nrhs; c0 += chunk) {
+    const int nb = (nrhs - c0) < chunk ? (nrhs - c0) : chunk;
+    const char* bc = static_cast<const char*>(b) + (size_t)c0 * vol * io_bytes;
+    char* uc = static_cast<char*>(u) + (size_t)c0 * vol * io_bytes;
+    if (o.prec == DPM_FP64 && !refine) {
+      // FP64 transforms in place in u: no workspace traffic beyond u itself
+      DPM_TRY(five_sweeps(pl, 8, g, IN_WS, bc, OUT_F64, uc, uc, nullptr, nullptr, &fl, c0, nb,
+                          false, false, s));
+    } else if (o.prec == DPM_FP32 && !o.io_fp64) {
+      DPM_TRY(five_sweeps(pl, 4, g, IN_WS, bc, OUT_WS, uc, uc, nullptr, nullptr, nullptr, c0, nb,
+                          false, false, s));
+    } else {
+      // reduced-precision (or FP64) transforms on the workspace, FP64 iterate in u
+      const double* bd = reinterpret_cast<const double*>(bc);
+      double* ud = reinterpret_cast<double*>(uc);
+      DPM_TRY(five_sweeps(pl, rb, g, IN_F64, bc, OUT_F64, uc, vol_ws, nullptr, nullptr, &fl, c0,
+                          nb, false, bf16, s));
+      hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, 0, o.rtol);
+      DPM_TRY_HIP(hipGetLastError());
+      for (int k = 1; k <= o.max_refine; ++k) {
+        DPM_TRY(five_sweeps(pl, rb, g, IN_RESID, nullptr, OUT_UPD, uc, vol_ws, bd, ud, &fl, c0,
+                            nb, true, bf16, s));
+        hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, k, o.rtol);
+        DPM_TRY_HIP(hipGetLastError());
+      }
+    }
+  }
+
+  if (info) {
+    DPM_TRY_HIP(hipStreamSynchronize(s));
+    std::vector<int> it(nrhs), dn(nrhs);
+    std::vector<double> est(nrhs);
+    DPM_TRY_HIP(hipMemcpy(it.data(), fl.iters, sizeof(int) * nrhs, hipMemcpyDeviceToHost));
+    DPM_TRY_HIP(hipMemcpy(dn.data(), fl.done, sizeof(int) * nrhs, hipMemcpyDeviceToHost));
+    DPM_TRY_HIP(hipMemcpy(est.data(), fl.est, sizeof(double) * nrhs, hipMemcpyDeviceToHost));
+    info->refine_iters = 0;
+    info->est_rel_err = 0.0;
+    bool all_done = true;
+    for (int i = 0; i < nrhs; ++i) {
+      if (it[i] > info->refine_iters) info->refine_iters = it[i];
+      if (est[i] > info->est_rel_err || !(est[i] == est[i])) info->est_rel_err = est[i];
+      if (!dn[i]) all_done = false;
+    }
+    if (!refine) info->est_rel_err = 0.0;
+    if (refine && !all_done) {
+      set_error("refinement did not reach rtol = %g in %d iterations (estimate %g)", o.rtol,
+                o.max_refine, info->est_rel_err);
+      return DPM_ENOTCONV;
+    }
+  }
+  return DPM_OK;
+}
+
+}  // namespace dpm

@@ -1,0 +1,105 @@
+// Internal declarations shared by the HIP sources of libdpm (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <vector>
+
+#include "dpm.h"
+
+namespace dpm {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define DPM_TRY_HIP(call)                                                        \
+  do {                                                                           \
+    hipError_t e__ = (call);                                                     \
+    if (e__ != hipSuccess) {                                                     \
+      ::dpm::set_error("%s failed: %s", #call, hipGetErrorString(e__));          \
+      return DPM_EHIP;                                                           \
+    }                                                                            \
+  } while (0)
+
+#define DPM_TRY(expr)                \
+  do {                               \
+    dpm_status s__ = (expr);         \
+    if (s__ != DPM_OK) return s__;   \
+  } while (0)
+
+// ---------------------------------------------------------------- small types
+template <typename T>
+struct C2 {
+  T x, y;
+};
+
+// ---------------------------------------------------------------- per-(device, n) tables
+struct Plan {
+  int n = 0;
+  int log2L = 0;             // complex FFT length L = 2(n+1) = 2^log2L
+  C2<float>* tw_f = nullptr;  // exp(-2 pi i e / L), e = 0..L-1
+  C2<double>* tw_d = nullptr;
+  double* lam = nullptr;     // lambda_k = (4/h^2) sin^2(pi k / (2(n+1))) * h^2, k = 1..n
+                             // (stored without the 1/h^2 factor: lam_hat = 4 sin^2(...))
+  // split-bf16 dense sine matrix for the MFMA path: [Mpad][Mpad] bf16 hi and lo
+  uint16_t* s_hi = nullptr;
+  uint16_t* s_lo = nullptr;
+  int mpad = 0;
+};
+
+// Returns the plan of the current device for size n (creating it on first use).
+dpm_status get_plan(int n, const Plan** out);
+
+bool fft_size_supported(int n);  // n + 1 a power of two and 7 <= n <= 1023
+
+// ---------------------------------------------------------------- DST pass kernels
+enum InKind { IN_WS = 0, IN_F64 = 1, IN_RESID = 2 };
+enum OutKind { OUT_WS = 0, OUT_F64 = 1, OUT_UPD = 2 };
+enum AxisKind { AX_X = 0, AX_Y = 1, AX_Z = 2 };
+
+struct PassArgs {
+  const void* in;            // input volume (chunk base)
+  void* out;                 // output volume (chunk base)
+  const double* b;           // residual mode: right-hand sides (chunk base)
+  const double* u;           // residual mode: current iterate (chunk base)
+  const void* tw;            // twiddles of the transform precision
+  const double* lam_hat;     // 4 sin^2(pi k/(2(n+1))), k = 1..n
+  double sigma;
+  double inv_h2;
+  const int* done;           // per right-hand side: skip the whole pass when set (nullable)
+  unsigned long long* cmax;  // per rhs: max |correction| (update/store passes, nullable)
+  unsigned long long* umax;  // per rhs: max |u_new|
+  int rhs0;                  // index of the chunk's first right-hand side in the batch
+};
+
+// Launch one sweep over `nrhs` consecutive volumes.  real_bytes = 4 (FP32) or 8 (FP64).
+dpm_status launch_dst_pass(int real_bytes, int n, AxisKind ax, bool zpass, InKind in,
+                           OutKind out, const PassArgs& a, int nrhs, hipStream_t s);
+
+// ---------------------------------------------------------------- BF16x3 MFMA dense DST
+dpm_status launch_bf16x3_pass(int n, AxisKind ax, bool zpass, InKind in, OutKind out,
+                              const PassArgs& a, const Plan* plan, int nrhs, hipStream_t s);
+
+// ---------------------------------------------------------------- solver internals
+struct SolveFlags {
+  int* done;
+  int* iters;
+  unsigned long long* cmax;
+  unsigned long long* umax;
+  double* prev;  // ||c_{k-1}||_inf
+  double* est;   // estimated relative error after the last update
+};
+
+size_t flags_bytes(int nrhs);
+dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u,
+                          const dpm_opts& o, hipStream_t s, dpm_info* info);
+dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes);
+dpm_status validate_grid(const dpm_grid* g);
+dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace dpm

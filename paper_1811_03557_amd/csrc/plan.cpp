@@ -1,0 +1,126 @@
+// Per-(device, n) tables of the sine transforms: FFT twiddles, the 1D Dirichlet eigenvalues
+// and the split-bf16 dense sine matrix.  Computed on the host in FP64 from their definitions
+// (std::sin / std::cos), uploaded once and kept until the process ends.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+
+#include "common.h"
+
+namespace dpm {
+
+namespace {
+thread_local std::string g_err;
+std::mutex g_plan_mu;
+std::map<std::pair<int, int>, Plan*> g_plans;
+
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+float bf16_to_f(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+}  // namespace
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+const char* last_error_text() { return g_err.c_str(); }
+
+bool fft_size_supported(int n) {
+  if (n < 7 || n > 1023) return false;
+  int m = n + 1;
+  return (m & (m - 1)) == 0;
+}
+
+static dpm_status build_plan(int n, Plan* p) {
+  p->n = n;
+  const int M = n + 1;
+  const int L = 2 * M;
+  int lg = 0;
+  while ((1 << lg) < L) ++lg;
+  p->log2L = lg;
+  const double pi = std::acos(-1.0);
+  std::vector<C2<double>> twd(L);
+  std::vector<C2<float>> twf(L);
+  for (int e = 0; e < L; ++e) {
+    double a = -2.0 * pi * (double)e / (double)L;
+    twd[e] = {std::cos(a), std::sin(a)};
+    twf[e] = {(float)twd[e].x, (float)twd[e].y};
+  }
+  std::vector<double> lam(n);
+  for (int k = 1; k <= n; ++k) {
+    double s = std::sin(pi * k / (2.0 * M));
+    lam[k - 1] = 4.0 * s * s;
+  }
+  // dense orthonormal DST-I matrix padded to a multiple of 32, split into bf16 hi + lo
+  int mpad = (n + 31) / 32 * 32;
+  std::vector<uint16_t> hi((size_t)mpad * mpad, 0), lo((size_t)mpad * mpad, 0);
+  const double nrm = std::sqrt(2.0 / M);
+  for (int j = 1; j <= n; ++j)
+    for (int k = 1; k <= n; ++k) {
+      double v = nrm * std::sin(pi * (double)j * (double)k / (double)M);
+      float vf = (float)v;
+      uint16_t h = bf16_rne(vf);
+      float r = (float)(v - (double)bf16_to_f(h));
+      hi[(size_t)(j - 1) * mpad + (k - 1)] = h;
+      lo[(size_t)(j - 1) * mpad + (k - 1)] = bf16_rne(r);
+    }
+  p->mpad = mpad;
+  DPM_TRY_HIP(hipMalloc(&p->tw_f, sizeof(C2<float>) * L));
+  DPM_TRY_HIP(hipMalloc(&p->tw_d, sizeof(C2<double>) * L));
+  DPM_TRY_HIP(hipMalloc(&p->lam, sizeof(double) * n));
+  DPM_TRY_HIP(hipMalloc(&p->s_hi, sizeof(uint16_t) * hi.size()));
+  DPM_TRY_HIP(hipMalloc(&p->s_lo, sizeof(uint16_t) * lo.size()));
+  DPM_TRY_HIP(hipMemcpy(p->tw_f, twf.data(), sizeof(C2<float>) * L, hipMemcpyHostToDevice));
+  DPM_TRY_HIP(hipMemcpy(p->tw_d, twd.data(), sizeof(C2<double>) * L, hipMemcpyHostToDevice));
+  DPM_TRY_HIP(hipMemcpy(p->lam, lam.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  DPM_TRY_HIP(hipMemcpy(p->s_hi, hi.data(), sizeof(uint16_t) * hi.size(), hipMemcpyHostToDevice));
+  DPM_TRY_HIP(hipMemcpy(p->s_lo, lo.data(), sizeof(uint16_t) * lo.size(), hipMemcpyHostToDevice));
+  return DPM_OK;
+}
+
+dpm_status get_plan(int n, const Plan** out) {
+  int dev = 0;
+  DPM_TRY_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  auto key = std::make_pair(dev, n);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second;
+    return DPM_OK;
+  }
+  Plan* p = new Plan();
+  dpm_status st = build_plan(n, p);
+  if (st != DPM_OK) {
+    (void)hipFree(p->tw_f);
+    (void)hipFree(p->tw_d);
+    (void)hipFree(p->lam);
+    (void)hipFree(p->s_hi);
+    (void)hipFree(p->s_lo);
+    delete p;
+    return st;
+  }
+  g_plans[key] = p;
+  *out = p;
+  return DPM_OK;
+}
+
+}  // namespace dpm

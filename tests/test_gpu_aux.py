@@ -1,0 +1,152 @@
+"""GPU parity of aux_solve / aux_solve_batched against the FP64 oracle.
+
+Tolerances (relative max-norm per right-hand side): FP64 transforms 1e-12, FP32 transforms
+1e-5, FP32 transforms + FP64 refinement 1e-10.
+"""
+import numpy as np
+import pytest
+
+import dpm_inputs as inp
+from oracle import aux as oaux
+from tests.gpu_util import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "refined": 1e-10}
+
+
+def _solve(b_np, sigma, h, dev, **kw):
+    import torch
+    from paper_1811_03557_amd import api
+    b = torch.from_numpy(np.ascontiguousarray(b_np)).to(dev)
+    u = api.aux_solve_batched(b, sigma, h, **kw)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+def _max_rel(u, ref):
+    return max(oaux.rel_err_inf(u[i], ref[i]) for i in range(ref.shape[0]))
+
+
+@pytest.mark.parametrize("n", [7, 15, 31, 63, 127])
+@pytest.mark.parametrize("sigma", [0.0, 1.0, 1e4])
+def test_fp64_parity(n, sigma):
+    dev = need_gpu()
+    say(f"fp64 parity n={n} sigma={sigma}")
+    h, _ = inp.grid(n)
+    nrhs = 3 if n <= 63 else 2
+    b = inp.rhs_normal(n, nrhs, seed=n)
+    ref = oaux.aux_solve(b, sigma, h)
+    u = _solve(b, sigma, h, dev, prec="fp64")
+    assert _max_rel(u, ref) < TOL["fp64"]
+
+
+@pytest.mark.parametrize("n", [7, 31, 127])
+def test_fp32_io_parity(n):
+    import torch
+    dev = need_gpu()
+    say(f"fp32 io parity n={n}")
+    h, _ = inp.grid(n)
+    b = inp.rhs_normal(n, 2, seed=1)
+    ref = oaux.aux_solve(b, 1.0, h)
+    bf = torch.from_numpy(b.astype(np.float32)).to(dev)
+    from paper_1811_03557_amd import api
+    u = api.aux_solve_batched(bf, 1.0, h, prec="fp32").cpu().numpy().astype(np.float64)
+    assert _max_rel(u, ref) < TOL["fp32"]
+
+
+@pytest.mark.parametrize("n", [15, 63, 127])
+@pytest.mark.parametrize("sigma", [1.0, 1e4])
+def test_fp32_refined_parity(n, sigma):
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    say(f"fp32+refinement parity n={n} sigma={sigma}")
+    h, _ = inp.grid(n)
+    b = inp.rhs_normal(n, 3, seed=2)
+    ref = oaux.aux_solve(b, sigma, h)
+    # without refinement: FP32 accuracy
+    u0 = _solve(b, sigma, h, dev, prec="fp32", max_refine=0)
+    assert _max_rel(u0, ref) < TOL["fp32"]
+    bt = torch.from_numpy(b).to(dev)
+    u, info = api.aux_solve_batched(bt, sigma, h, prec="fp32", max_refine=4, rtol=1e-10, info=True)
+    u = u.cpu().numpy()
+    assert _max_rel(u, ref) < TOL["refined"]
+    assert 1 <= info["refine_iters"] <= 3
+
+
+def test_eigenmode_closed_form_full_size():
+    """At N = 255 a single sine mode is solved exactly (property at any size)."""
+    dev = need_gpu()
+    n = 255
+    say("eigenmode n=255")
+    h, _ = inp.grid(n)
+    j = np.arange(1, n + 1)
+    sigma = 1.0
+    out = []
+    for (k1, k2, k3) in [(1, 1, 1), (255, 3, 128), (17, 200, 64)]:
+        s = [np.sin(np.pi * j * k / (n + 1)) for k in (k1, k2, k3)]
+        b = s[2][:, None, None] * s[1][None, :, None] * s[0][None, None, :]
+        lam = sum(4.0 / h**2 * np.sin(np.pi * k / (2 * (n + 1))) ** 2 for k in (k1, k2, k3))
+        out.append((b, b / (sigma + lam)))
+    b = np.stack([o[0] for o in out])
+    ref = np.stack([o[1] for o in out])
+    u = _solve(b, sigma, h, dev, prec="fp64")
+    assert _max_rel(u, ref) < TOL["fp64"]
+
+
+@pytest.mark.parametrize("prec,kw,tol", [("fp64", {}, 1e-12),
+                                         ("fp32", {"max_refine": 4, "rtol": 1e-10}, 1e-10)])
+def test_full_size_255_parity(prec, kw, tol):
+    """The benchmark's launch configuration (N = 255) against the oracle on 2 right-hand sides."""
+    dev = need_gpu()
+    n = 255
+    say(f"n=255 parity {prec}")
+    h, _ = inp.grid(n)
+    b = inp.rhs_normal(n, 2, seed=0)
+    ref = oaux.aux_solve(b, 1.0, h)
+    u = _solve(b, 1.0, h, dev, prec=prec, **kw)
+    assert _max_rel(u, ref) < tol
+
+
+def test_config1_manufactured():
+    dev = need_gpu()
+    n = 31
+    h, _ = inp.grid(n)
+    dt = h
+    sigma = 1.0 / dt + 1.0
+    ustar = inp.manufactured_c1(n, dt)
+    b = oaux.apply_operator(ustar, sigma, h) + inp.noise_uniform(n, seed=0)
+    ref = oaux.aux_solve(b, sigma, h)
+    u = _solve(b[None], sigma, h, dev, prec="fp64")[0]
+    assert oaux.rel_err_inf(u, ref) < TOL["fp64"]
+    # noise-free manufactured data come back exactly
+    u2 = _solve(oaux.apply_operator(ustar, sigma, h)[None], sigma, h, dev, prec="fp64")[0]
+    assert oaux.rel_err_inf(u2, ustar) < TOL["fp64"]
+
+
+def test_batch_chunks_and_ragged_count():
+    """Results do not depend on how the batch is chunked (chunk 1, 2, all) for 5 RHS."""
+    dev = need_gpu()
+    n = 63
+    h, _ = inp.grid(n)
+    b = inp.rhs_normal(n, 5, seed=9)
+    us = [_solve(b, 2.0, h, dev, prec="fp32", max_refine=2, rtol=1e-12, rhs_chunk=c)
+          for c in (1, 2, 0)]
+    assert np.array_equal(us[0], us[1]) and np.array_equal(us[0], us[2])
+    ref = oaux.aux_solve(b, 2.0, h)
+    assert _max_rel(us[0], ref) < TOL["refined"]
+
+
+def test_invalid_arguments_raise():
+    import torch
+    from paper_1811_03557_amd import api, _lib
+    dev = need_gpu()
+    b = torch.zeros((5, 5, 5), dtype=torch.float64, device=dev)   # n + 1 not a power of two
+    with pytest.raises(_lib.DPMError):
+        api.aux_solve(b, 1.0, 0.1)
+    b = torch.zeros((7, 7, 7), dtype=torch.float64, device=dev)
+    with pytest.raises(_lib.DPMError):
+        api.aux_solve(b, -1.0, 0.1)
+    with pytest.raises(_lib.DPMError):
+        api.aux_solve(b, 1.0, 0.0)
