@@ -19,9 +19,15 @@ import numpy as np
 
 
 def dst1_matrix(n: int) -> np.ndarray:
-    """Orthonormal DST-I matrix S[j-1,k-1] = sqrt(2/(n+1)) sin(pi j k/(n+1)), j,k = 1..n."""
-    j = np.arange(1, n + 1, dtype=np.float64)
-    return np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * np.outer(j, j) / (n + 1))
+    """Orthonormal DST-I matrix S[j-1,k-1] = sqrt(2/(n+1)) sin(pi j k/(n+1)), j,k = 1..n.
+
+    sin is 2 pi-periodic, so j k is first reduced modulo 2(n+1) in exact integer arithmetic;
+    the argument passed to sin then stays below 2 pi (unreduced arguments reach ~pi n and lose
+    up to ~1e-14 of accuracy at n = 255).
+    """
+    j = np.arange(1, n + 1, dtype=np.int64)
+    r = np.outer(j, j) % (2 * (n + 1))
+    return np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * r.astype(np.float64) / (n + 1))
 
 
 def eigenvalues(n: int, h: float) -> np.ndarray:

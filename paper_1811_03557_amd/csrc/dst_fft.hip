@@ -5,13 +5,21 @@
 // + lambda_kz.  One solve is five sweeps over the volume: forward x, forward y, a fused z sweep
 // (forward, eigenvalue scaling, inverse), inverse y, inverse x.
 //
-// A sweep moves tiles of W lines (W * sizeof(real) = 128 bytes of each row of the tile, so
-// every global access is a run of >= 128 contiguous bytes) into LDS.  Two real lines a, b are
-// transformed together by one complex FFT of length L = 2(N+1): the odd extensions of the two
-// lines form z = y_a + i y_b, and Z = FFT(z) gives DST(a)_k = -Im Z_k / 2 and
-// DST(b)_k = Re Z_k / 2 for k = 1..N.  The FFT is a Stockham radix-8 (last stage radix 2 or 4)
-// with every thread holding 8 complex values in registers and LDS between stages; twiddles come
-// from an FP64-computed table.
+// Sweep layout.  A block moves a tile of W whole lines (W * sizeof(real) = 128 bytes of every
+// row of the tile, so each global access is a run of 128 contiguous bytes) into LDS with a
+// pitch of M = N + 1 reals per line, transforms every line in place in its own LDS slot and
+// writes the tile back.  Line transforms are wave-local: the G threads of a line sit in one
+// wavefront and synchronise with wavefront barriers only; the two block barriers per tile
+// separate the cooperative load, the transforms and the store.
+//
+// Line transform (DST-I of length N = M - 1, M a power of two), through a real DFT of length M:
+//   y_j = sin(pi j/M)(x_j + x_{M-j}) + (x_j - x_{M-j})/2,  y_0 = 0,  F = DFT_M(y);
+//   then X_2k = -Im F_k and X_2k+1 = X_2k-1 + Re F_k (X_1 = Re F_0 / 2): the odd outputs are a
+//   prefix sum, evaluated as a tree scan across the threads of the line.
+// The real DFT is a complex FFT of length H = M/2 on w_q = y_2q + i y_2q+1 (Stockham radix-8,
+// last stage radix 2 or 4, 8 complex values per thread) followed by the even/odd split
+// F_k = (W_k + conj W_{H-k})/2 - i e^{-2 pi i k/M} (W_k - conj W_{H-k})/2.
+// All sines and twiddles come from one FP64-computed table e^{-i pi j/M}, j < 2M, held in LDS.
 //
 // The first x sweep of a refinement step computes the FP64 residual b - (sigma - Lap_h) u on the
 // fly; the last x sweep can add its result into u (u += c) and reduce max|c|, max|u|.
@@ -35,6 +43,13 @@ template <typename T>
 __device__ __forceinline__ C2<T> mul_minus_i(C2<T> a) { return {a.y, -a.x}; }
 template <typename T>
 __device__ __forceinline__ C2<T> mul_plus_i(C2<T> a) { return {-a.y, a.x}; }
+
+// Wavefront-scope barrier for LDS exchanges among the threads of one line.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // In-register DFTs of size 2, 4, 8 with omega = exp(-2 pi i / R).
 template <typename T>
@@ -71,33 +86,39 @@ __device__ __forceinline__ void dft8(C2<T>* a) {
   a[7] = csub(e3, o3);
 }
 
-template <typename T, int LOG2L>
+template <typename T, int LOGM>
 struct Cfg {
-  static constexpr int L = 1 << LOG2L;  // complex FFT length
-  static constexpr int M = L / 2;       // N + 1
+  static constexpr int M = 1 << LOGM;   // N + 1
   static constexpr int N = M - 1;       // line length
-  static constexpr int TPF = L / 8;     // threads per FFT (8 values each)
-  static constexpr int W = (sizeof(T) == 4) ? 32 : (L >= 2048 ? 8 : 16);  // lines per tile
-  static constexpr int NF0 = kBlock / TPF;
-  static constexpr int NF = (NF0 < W / 2) ? NF0 : W / 2;  // FFTs in flight per block
-  static constexpr int ROUNDS = (W / 2 + NF - 1) / NF;
+  static constexpr int H = M / 2;       // complex FFT length
+  static constexpr int V = H >= 8 ? 8 : H;  // complex values per thread
+  static constexpr int G = H / V;       // threads per line (divides 64)
+  static constexpr int W = sizeof(T) == 4 ? 32 : (M >= 1024 ? 8 : 16);  // lines per tile
+  static constexpr int LPR = kBlock / G;              // lines per round
+  static constexpr int ROUNDS = (W + LPR - 1) / LPR;
 };
 
-// One Stockham stage of radix R at stride NS on the 8 values a thread holds.  On entry a[s]
-// is element j + s*TPF; on exit a[s] is output element pos[s].
-template <typename T, int L, int R, int NS>
-__device__ __forceinline__ void stage(C2<T>* a, int* pos, int j, const C2<T>* __restrict__ tw) {
-  constexpr int TPF = L / 8;
-  constexpr int Q = 8 / R;
+template <int H, int NS>
+constexpr int radix_at() {
+  return (NS * 8 <= H) ? 8 : H / NS;
+}
+
+// One Stockham stage of radix R at stride NS over an FFT of length H with V values per
+// thread.  On entry a[s] is element g + s*G; on exit a[s] is output element pos[s].
+// tw: table e^{-i pi j/M}, j < 2M (M = 2H); the FFT twiddle e^{-2 pi i e/H} is tw[4e].
+template <typename T, int H, int V, int R, int NS>
+__device__ __forceinline__ void stage(C2<T>* a, int* pos, int g, const C2<T>* tw) {
+  constexpr int G = H / V;
+  constexpr int Q = V / R;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int v = j + q * TPF;
+    const int v = g + q * G;
     const int vm = v & (NS - 1);
     C2<T> x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       x[r] = a[q + r * Q];
-      if (NS > 1 && r > 0) x[r] = cmul(x[r], tw[(r * vm * (L / (NS * R))) & (L - 1)]);
+      if (NS > 1 && r > 0) x[r] = cmul(x[r], tw[4 * ((r * vm * (H / (NS * R))) & (H - 1))]);
     }
     if constexpr (R == 8) {
       dft8(x);
@@ -115,63 +136,133 @@ __device__ __forceinline__ void stage(C2<T>* a, int* pos, int j, const C2<T>* __
   }
 }
 
-template <int L, int NS>
-constexpr int radix_at() {
-  return (NS * 8 <= L) ? 8 : L / NS;
-}
-
-// Runs the stages from stride NS to the end.  The values for the stage at NS are in a[]
-// (element j + s*TPF).  Intermediate results go through buf (this FFT's slot of L values).
-// All threads of the block call this (barriers inside); `act` gates the arithmetic.
-template <typename T, int L, int NS>
-__device__ __forceinline__ void run_stages(C2<T>* a, int* pos, int j, bool act, C2<T>* buf,
-                                           const C2<T>* __restrict__ tw) {
-  constexpr int R = radix_at<L, NS>();
-  constexpr int TPF = L / 8;
-  if (act) stage<T, L, R, NS>(a, pos, j, tw);
-  if constexpr (NS * R < L) {
-    if (act) {
+// Stages from stride NS to the end, exchanging through `buf` (the line's own slot).  On return
+// the natural-order result is in buf (and the caller has passed a wave barrier).
+template <typename T, int H, int V, int NS>
+__device__ __forceinline__ void fft_stages(C2<T>* a, int g, C2<T>* buf, const C2<T>* tw) {
+  constexpr int R = radix_at<H, NS>();
+  constexpr int G = H / V;
+  int pos[V];
+  stage<T, H, V, R, NS>(a, pos, g, tw);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) buf[pos[s]] = a[s];
-    }
-    __syncthreads();
-    if (act) {
+  for (int s = 0; s < V; ++s) buf[pos[s]] = a[s];
+  wave_sync();
+  if constexpr (NS * R < H) {
 #pragma unroll
-      for (int s = 0; s < 8; ++s) a[s] = buf[j + s * TPF];
-    }
-    __syncthreads();
-    run_stages<T, L, NS * R>(a, pos, j, act, buf, tw);
+    for (int s = 0; s < V; ++s) a[s] = buf[g + s * G];
+    wave_sync();
+    fft_stages<T, H, V, NS * R>(a, g, buf, tw);
   }
 }
 
-// Odd extension of tile line `ln` (length N, pitch N) at index i of the length-2M sequence.
-template <typename T, int M>
-__device__ __forceinline__ T odd_ext(const T* __restrict__ line, int i) {
-  if (i == 0 || i == M) return (T)0;
-  if (i < M) return line[i - 1];
-  return -line[2 * M - i - 1];
+// In-place orthonormal DST-I of one line (N reals at `line`, slot of M reals) by the G threads
+// g = 0..G-1 of the line.  The result X_i (i = 1..N) is written to line[i-1] after
+// multiplication by scale(i) * sqrt(2/M).
+template <typename T, int LOGM, class Scale>
+__device__ __forceinline__ void dst1_line(T* line, int g, const C2<T>* tw, Scale scale) {
+  using K = Cfg<T, LOGM>;
+  constexpr int M = K::M, H = K::H, V = K::V, G = K::G;
+  C2<T>* buf = reinterpret_cast<C2<T>*>(line);
+  // ---- pre-processing into the first stage's registers: element q = g + s*G
+  C2<T> a[V];
+#pragma unroll
+  for (int s = 0; s < V; ++s) {
+    const int q = g + s * G;
+    const int j0 = 2 * q, j1 = 2 * q + 1;
+    // x_j at line[j-1]; x_0 = x_M = 0
+    const T xa0 = j0 > 0 ? line[j0 - 1] : (T)0;
+    const T xb0 = j0 > 0 ? line[M - j0 - 1] : (T)0;
+    const T xa1 = line[j1 - 1];
+    const T xb1 = line[M - j1 - 1];
+    const T s0 = -tw[j0].y;  // sin(pi j/M)
+    const T s1 = -tw[j1].y;
+    a[s].x = j0 > 0 ? s0 * (xa0 + xb0) + (T)0.5 * (xa0 - xb0) : (T)0;
+    a[s].y = s1 * (xa1 + xb1) + (T)0.5 * (xa1 - xb1);
+  }
+  wave_sync();  // all reads of x done before the slot is overwritten
+  fft_stages<T, H, V, 1>(a, g, buf, tw);
+  // ---- post-processing: thread g owns k = g*V .. g*V + V - 1
+  T re[V], im[V];
+#pragma unroll
+  for (int s = 0; s < V; ++s) {
+    const int k = g * V + s;
+    const C2<T> A = buf[k];
+    const C2<T> Bc = buf[(H - k) & (H - 1)];
+    const C2<T> B = {Bc.x, -Bc.y};
+    const C2<T> E = {(T)0.5 * (A.x + B.x), (T)0.5 * (A.y + B.y)};
+    const C2<T> D = {(T)0.5 * (A.x - B.x), (T)0.5 * (A.y - B.y)};
+    const C2<T> O = {D.y, -D.x};  // -i D
+    const C2<T> F = cadd(E, cmul(tw[2 * k], O));
+    re[s] = F.x;
+    im[s] = F.y;
+  }
+  // inclusive prefix of Re F over k: thread-local, then across the G threads of the line
+#pragma unroll
+  for (int s = 1; s < V; ++s) re[s] += re[s - 1];
+  T run = re[V - 1];
+  T incl = run;
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    const T o = __shfl_up(incl, off, G);
+    if (g >= off) incl += o;
+  }
+  const T excl = incl - run;
+  // Re F_0 (= re[0] of thread 0 before the prefix; unchanged by it) broadcast to the line
+  const T f0 = __shfl(re[0], 0, G);
+  wave_sync();  // all reads of W done before X overwrites the slot
+  const T c1 = (T)sqrt(2.0 / (double)M);
+#pragma unroll
+  for (int s = 0; s < V; ++s) {
+    const int k = g * V + s;
+    const T xodd = excl + re[s] - (T)0.5 * f0;  // X_{2k+1}
+    if (k > 0) line[2 * k - 1] = -im[s] * c1 * scale(2 * k);
+    line[2 * k] = xodd * c1 * scale(2 * k + 1);
+  }
+  wave_sync();
 }
 
-template <typename T, int LOG2L, int AX, bool ZPASS, int IN, int OUT>
-__global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p) {
-  using K = Cfg<T, LOG2L>;
-  constexpr int L = K::L, M = K::M, N = K::N, TPF = K::TPF, W = K::W, NF = K::NF;
+struct NoScale {
+  __device__ __forceinline__ float operator()(int) const { return 1.0f; }
+};
+
+template <typename T>
+struct EigScale {  // 1 / (base + inv_h2 * lam_hat[k-1])
+  double base, inv_h2;
+  const double* lam;
+  __device__ __forceinline__ T operator()(int k) const {
+    return (T)(1.0 / (base + inv_h2 * lam[k - 1]));
+  }
+};
+
+// blockIdx -> logical tile such that consecutive logical tiles run on the same XCD (blocks are
+// dispatched round-robin over the 8 XCDs), so neighbouring tiles that share cache lines and
+// stencil rows share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = b & 7, slot = b >> 3;
+  return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
+template <typename T, int LOGM, int AX, bool ZPASS, int IN, int OUT>
+__global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int nblocks) {
+  using K = Cfg<T, LOGM>;
+  constexpr int M = K::M, N = K::N, G = K::G, W = K::W;
   constexpr long long VOL = (long long)N * N * N;
-  // geometry of the tiles: X lines are rows (contiguous), Y/Z lines are columns of W x-values
   constexpr int LINES_PER_ROW = (AX == AX_X) ? N * N : N;
   constexpr int TILES_PER_ROW = (LINES_PER_ROW + W - 1) / W;
   constexpr long long S_OUTER = (AX == AX_X) ? 0 : (AX == AX_Y ? (long long)N * N : N);
   constexpr long long S_LINE = (AX == AX_X) ? N : 1;
   constexpr long long S_ELEM = (AX == AX_X) ? 1 : (AX == AX_Y ? N : (long long)N * N);
 
-  __shared__ T tile[W * N];
-  __shared__ C2<T> fbuf[NF * L];
+  __shared__ __align__(16) T tile[W * M];
+  __shared__ __align__(16) C2<T> tw[2 * M];
   __shared__ unsigned long long red[2][kBlock / 64];
 
-  const int rhs = blockIdx.y;
+  const int logical = xcd_remap(blockIdx.x, nblocks);
+  const int rhs = logical / tiles;
+  const int t = logical - rhs * tiles;
   if (p.done != nullptr && p.done[p.rhs0 + rhs] != 0) return;  // converged: uniform exit
 
-  const int t = blockIdx.x;
   const int row = t / TILES_PER_ROW;
   const int ti = t - row * TILES_PER_ROW;
   const int line0 = ti * W;
@@ -179,20 +270,22 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p) {
   const long long base = (long long)rhs * VOL + (long long)row * S_OUTER + (long long)line0 * S_LINE;
   const int tid = threadIdx.x;
 
+  const C2<T>* gtw = static_cast<const C2<T>*>(p.tw);
+  for (int i = tid; i < 2 * M; i += kBlock) tw[i] = gtw[i];
+
   // ------------------------------------------------------------------ load the tile
   if constexpr (AX == AX_X) {
     const int cnt = nlines * N;
     for (int e = tid; e < cnt; e += kBlock) {
+      const int w = e / N;
+      const int x = e - w * N;
       const long long g = base + e;
       T v;
       if constexpr (IN == IN_RESID) {
-        const int w = e / N;
-        const int x = e - w * N;
         const int ln = line0 + w;
         const int z = ln / N;
         const int y = ln - z * N;
         const double* __restrict__ u = p.u;
-        const double uc = u[g];
         double nb = 0.0;
         if (x > 0) nb += u[g - 1];
         if (x < N - 1) nb += u[g + 1];
@@ -200,19 +293,19 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p) {
         if (y < N - 1) nb += u[g + N];
         if (z > 0) nb += u[g - (long long)N * N];
         if (z < N - 1) nb += u[g + (long long)N * N];
-        const double r = p.b[g] - (p.sigma + 6.0 * p.inv_h2) * uc + p.inv_h2 * nb;
+        const double r = p.b[g] - (p.sigma + 6.0 * p.inv_h2) * u[g] + p.inv_h2 * nb;
         v = (T)r;
       } else if constexpr (IN == IN_F64) {
         v = (T)(static_cast<const double*>(p.in)[g]);
       } else {
         v = static_cast<const T*>(p.in)[g];
       }
-      tile[e] = v;  // (w, x) at w*N + x
+      tile[w * M + x] = v;
     }
   } else {
     const int cnt = N * W;
     for (int e = tid; e < cnt; e += kBlock) {
-      const int j = e / W;        // W is a power of two
+      const int j = e / W;  // W is a power of two
       const int w = e - j * W;
       if (w < nlines) {
         const long long g = base + w + (long long)j * S_ELEM;
@@ -222,87 +315,26 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p) {
         } else {
           v = static_cast<const T*>(p.in)[g];
         }
-        tile[w * N + j] = v;
+        tile[w * M + j] = v;
       }
     }
   }
   __syncthreads();
 
-  // ------------------------------------------------------------------ transform line pairs
-  const C2<T>* __restrict__ tw = static_cast<const C2<T>*>(p.tw);
-  const int f = tid / TPF;
-  const int j = tid - f * TPF;
-  C2<T>* buf = fbuf + (f < NF ? f : 0) * L;
-  const T c1 = (T)(1.0 / sqrt(2.0 * (double)M));  // orthonormal scale of one DST-I
-
+  // ------------------------------------------------------------------ transform the lines
+  const int g = tid % G;
 #pragma unroll 1
   for (int round = 0; round < K::ROUNDS; ++round) {
-    const int pair = round * NF + f;
-    const int la = 2 * pair;
-    const int lb = la + 1;
-    const bool act = (f < NF) && (la < nlines);
-    const bool hasb = lb < nlines;
-    const T* linea = tile + la * N;
-    const T* lineb = tile + (hasb ? lb : la) * N;
-    C2<T> a[8];
-    int pos[8];
-    if (act) {
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int i = j + s * TPF;
-        a[s].x = odd_ext<T, M>(linea, i);
-        a[s].y = hasb ? odd_ext<T, M>(lineb, i) : (T)0;
-      }
-    }
-    __syncthreads();  // every line of this round read before any write back into the tile
-    run_stages<T, L, 1>(a, pos, j, act, buf, tw);
-
-    if constexpr (ZPASS) {
-      // scale by 1/(sigma + lambda_kx + lambda_ky + lambda_kz) and restart from the odd
-      // extension of the scaled coefficients (S is its own inverse)
-      const int kx_a = line0 + la;      // x index of line a (0-based)
-      const int kx_b = line0 + lb;
-      const int ky = row;               // y index (0-based)
-      const double base_a = act ? p.sigma + p.inv_h2 * (p.lam_hat[kx_a] + p.lam_hat[ky]) : 1.0;
-      const double base_b = (act && hasb) ? p.sigma + p.inv_h2 * (p.lam_hat[kx_b] + p.lam_hat[ky]) : 1.0;
-      if (act) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int k = pos[s];
-          if (k == 0 || k == M) {
-            buf[k] = {(T)0, (T)0};
-          } else if (k < M) {
-            const double lz = p.inv_h2 * p.lam_hat[k - 1];
-            const T da = (T)(1.0 / (base_a + lz));
-            const T db = (T)(1.0 / (base_b + lz));
-            C2<T> w;
-            w.x = -a[s].y * c1 * da;
-            w.y = a[s].x * c1 * db;
-            buf[k] = w;
-            buf[2 * M - k] = {-w.x, -w.y};
-          }
-        }
-      }
-      __syncthreads();
-      if (act) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) a[s] = buf[j + s * TPF];
-      }
-      __syncthreads();
-      run_stages<T, L, 1>(a, pos, j, act, buf, tw);
-    }
-
-    // extract DST coefficients k = 1..N of both lines back into the tile
-    if (act) {
-      T* wa = tile + la * N;
-      T* wb = tile + lb * N;
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int k = pos[s];
-        if (k >= 1 && k < M) {
-          wa[k - 1] = -a[s].y * c1;
-          if (hasb) wb[k - 1] = a[s].x * c1;
-        }
+    const int l = round * K::LPR + tid / G;
+    if (l < nlines) {  // uniform across the G threads of a line (all in one wavefront)
+      T* line = tile + l * M;
+      if constexpr (ZPASS) {
+        EigScale<T> sc{p.sigma + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]), p.inv_h2,
+                       p.lam_hat};
+        dst1_line<T, LOGM>(line, g, tw, sc);
+        dst1_line<T, LOGM>(line, g, tw, NoScale{});
+      } else {
+        dst1_line<T, LOGM>(line, g, tw, NoScale{});
       }
     }
   }
@@ -313,35 +345,36 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p) {
   if constexpr (AX == AX_X) {
     const int cnt = nlines * N;
     for (int e = tid; e < cnt; e += kBlock) {
-      const long long g = base + e;
-      const T v = tile[e];
+      const int w = e / N;
+      const int x = e - w * N;
+      const long long gi = base + e;
+      const T v = tile[w * M + x];
       if constexpr (OUT == OUT_UPD) {
         double* uo = static_cast<double*>(p.out);
-        const double nu = uo[g] + (double)v;
-        uo[g] = nu;
+        const double nu = uo[gi] + (double)v;
+        uo[gi] = nu;
         cm = fmax(cm, fabs((double)v));
         um = fmax(um, fabs(nu));
       } else if constexpr (OUT == OUT_F64) {
-        static_cast<double*>(p.out)[g] = (double)v;
+        static_cast<double*>(p.out)[gi] = (double)v;
         cm = fmax(cm, fabs((double)v));
       } else {
-        static_cast<T*>(p.out)[g] = v;
-        if (p.cmax != nullptr) cm = fmax(cm, fabs((double)v));
+        static_cast<T*>(p.out)[gi] = v;
       }
     }
   } else {
     const int cnt = N * W;
     for (int e = tid; e < cnt; e += kBlock) {
-      const int j2 = e / W;
-      const int w = e - j2 * W;
+      const int j = e / W;
+      const int w = e - j * W;
       if (w < nlines) {
-        const long long g = base + w + (long long)j2 * S_ELEM;
-        static_cast<T*>(p.out)[g] = tile[w * N + j2];
+        const long long gi = base + w + (long long)j * S_ELEM;
+        static_cast<T*>(p.out)[gi] = tile[w * M + j];
       }
     }
   }
 
-  if constexpr (AX == AX_X) {
+  if constexpr (AX == AX_X && OUT != OUT_WS) {
     if (p.cmax != nullptr) {
       if constexpr (OUT != OUT_UPD) um = cm;  // the first solve's correction is u itself
       // block max of cm, um -> one atomicMax each (max is order independent: deterministic)
@@ -368,29 +401,32 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p) {
   }
 }
 
-template <typename T, int LOG2L>
+template <typename T, int LOGM>
 dpm_status launch_t(AxisKind ax, bool zpass, InKind in, OutKind out, const PassArgs& a,
                     int nrhs, hipStream_t s) {
-  using K = Cfg<T, LOG2L>;
+  using K = Cfg<T, LOGM>;
   constexpr int N = K::N, W = K::W;
-  const int lines_per_row = (ax == AX_X) ? N * N : N;
-  const int rows = (ax == AX_X) ? 1 : N;
-  const int tiles = rows * ((lines_per_row + W - 1) / W);
-  dim3 grid(tiles, nrhs), block(kBlock);
+  const long long lines_per_row = (ax == AX_X) ? (long long)N * N : N;
+  const long long rows = (ax == AX_X) ? 1 : N;
+  const long long tiles = rows * ((lines_per_row + W - 1) / W);
+  const long long nb = tiles * nrhs;
+  if (nb > 0x7fffffffLL) { set_error("launch too large"); return DPM_EINVAL; }
+  dim3 grid((unsigned)nb), block(kBlock);
+  const int ti = (int)tiles, nbi = (int)nb;
   if (ax == AX_X) {
     if (zpass) { set_error("z sweep requested on the x axis"); return DPM_EINVAL; }
-    if (in == IN_WS && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOG2L, AX_X, false, IN_WS, OUT_WS>), grid, block, 0, s, a);
-    else if (in == IN_F64 && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOG2L, AX_X, false, IN_F64, OUT_WS>), grid, block, 0, s, a);
-    else if (in == IN_RESID && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOG2L, AX_X, false, IN_RESID, OUT_WS>), grid, block, 0, s, a);
-    else if (in == IN_WS && out == OUT_F64) hipLaunchKernelGGL((k_dst_pass<T, LOG2L, AX_X, false, IN_WS, OUT_F64>), grid, block, 0, s, a);
-    else if (in == IN_WS && out == OUT_UPD) hipLaunchKernelGGL((k_dst_pass<T, LOG2L, AX_X, false, IN_WS, OUT_UPD>), grid, block, 0, s, a);
+    if (in == IN_WS && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, false, IN_WS, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+    else if (in == IN_F64 && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, false, IN_F64, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+    else if (in == IN_RESID && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, false, IN_RESID, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+    else if (in == IN_WS && out == OUT_F64) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, false, IN_WS, OUT_F64>), grid, block, 0, s, a, ti, nbi);
+    else if (in == IN_WS && out == OUT_UPD) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, false, IN_WS, OUT_UPD>), grid, block, 0, s, a, ti, nbi);
     else { set_error("unsupported x sweep kind (%d,%d)", (int)in, (int)out); return DPM_EINVAL; }
   } else if (ax == AX_Y) {
     if (zpass || in != IN_WS || out != OUT_WS) { set_error("unsupported y sweep kind"); return DPM_EINVAL; }
-    hipLaunchKernelGGL((k_dst_pass<T, LOG2L, AX_Y, false, IN_WS, OUT_WS>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_Y, false, IN_WS, OUT_WS>), grid, block, 0, s, a, ti, nbi);
   } else {
     if (!zpass || in != IN_WS || out != OUT_WS) { set_error("unsupported z sweep kind"); return DPM_EINVAL; }
-    hipLaunchKernelGGL((k_dst_pass<T, LOG2L, AX_Z, true, IN_WS, OUT_WS>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_Z, true, IN_WS, OUT_WS>), grid, block, 0, s, a, ti, nbi);
   }
   DPM_TRY_HIP(hipGetLastError());
   return DPM_OK;
@@ -400,14 +436,14 @@ template <typename T>
 dpm_status launch_size(int n, AxisKind ax, bool zpass, InKind in, OutKind out, const PassArgs& a,
                        int nrhs, hipStream_t s) {
   switch (n) {
-    case 7: return launch_t<T, 4>(ax, zpass, in, out, a, nrhs, s);
-    case 15: return launch_t<T, 5>(ax, zpass, in, out, a, nrhs, s);
-    case 31: return launch_t<T, 6>(ax, zpass, in, out, a, nrhs, s);
-    case 63: return launch_t<T, 7>(ax, zpass, in, out, a, nrhs, s);
-    case 127: return launch_t<T, 8>(ax, zpass, in, out, a, nrhs, s);
-    case 255: return launch_t<T, 9>(ax, zpass, in, out, a, nrhs, s);
-    case 511: return launch_t<T, 10>(ax, zpass, in, out, a, nrhs, s);
-    case 1023: return launch_t<T, 11>(ax, zpass, in, out, a, nrhs, s);
+    case 7: return launch_t<T, 3>(ax, zpass, in, out, a, nrhs, s);
+    case 15: return launch_t<T, 4>(ax, zpass, in, out, a, nrhs, s);
+    case 31: return launch_t<T, 5>(ax, zpass, in, out, a, nrhs, s);
+    case 63: return launch_t<T, 6>(ax, zpass, in, out, a, nrhs, s);
+    case 127: return launch_t<T, 7>(ax, zpass, in, out, a, nrhs, s);
+    case 255: return launch_t<T, 8>(ax, zpass, in, out, a, nrhs, s);
+    case 511: return launch_t<T, 9>(ax, zpass, in, out, a, nrhs, s);
+    case 1023: return launch_t<T, 10>(ax, zpass, in, out, a, nrhs, s);
     default: set_error("no FFT sweep for n = %d", n); return DPM_EINVAL;
   }
 }
@@ -417,14 +453,9 @@ dpm_status launch_size(int n, AxisKind ax, bool zpass, InKind in, OutKind out, c
 dpm_status launch_dst_pass(int real_bytes, int n, AxisKind ax, bool zpass, InKind in,
                            OutKind out, const PassArgs& a, int nrhs, hipStream_t s) {
   if (nrhs <= 0) return DPM_OK;
-  if (nrhs > 65535) { set_error("too many right-hand sides in one launch"); return DPM_EINVAL; }
   if (real_bytes == 4) return launch_size<float>(n, ax, zpass, in, out, a, nrhs, s);
-  // FP64 transforms: FP64 input/output is the native type
+  // FP64 transforms: FP64 input is the native type
   if (in == IN_F64) in = IN_WS;
-  if (out == OUT_F64) {
-    // storing FP64 from an FP64 tile: same as a plain store, keep the max tracking
-    return launch_size<double>(n, ax, zpass, in, OUT_F64, a, nrhs, s);
-  }
   return launch_size<double>(n, ax, zpass, in, out, a, nrhs, s);
 }
 

@@ -126,3 +126,14 @@ def test_batched_shapes():
     u = aux.aux_solve(b, 2.0, h)
     for i in range(3):
         assert np.max(np.abs(u[i] - aux.aux_solve(b[i], 2.0, h))) < 1e-14
+
+
+def test_dst_matrix_accuracy_against_high_precision():
+    """Entries of the sine matrix agree with a long-double evaluation to ~1 ulp at n = 255."""
+    n = 255
+    S = aux.dst1_matrix(n)
+    j = np.arange(1, n + 1)
+    r = (np.outer(j, j) % (2 * (n + 1))).astype(np.longdouble)
+    pi = np.longdouble("3.14159265358979323846264338327950288")
+    ref = np.sqrt(np.longdouble(2) / (n + 1)) * np.sin(pi * r / (n + 1))
+    assert float(np.max(np.abs(S - ref))) < 4e-16
