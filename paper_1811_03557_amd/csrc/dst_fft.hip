@@ -7,7 +7,7 @@
 //
 // Sweep layout.  A block moves a tile of W whole lines (W * sizeof(real) = 128 bytes of every
 // row of the tile, so each global access is a run of 128 contiguous bytes) into LDS with a
-// pitch of M = N + 1 reals per line, transforms every line in place in its own LDS slot and
+// padded pitch per line, transforms every line in place in its own LDS slot and
 // writes the tile back.  Line transforms are wave-local: the G threads of a line sit in one
 // wavefront and synchronise with wavefront barriers only; the two block barriers per tile
 // separate the cooperative load, the transforms and the store.
@@ -93,10 +93,17 @@ struct Cfg {
   static constexpr int H = M / 2;       // complex FFT length
   static constexpr int V = H >= 8 ? 8 : H;  // complex values per thread
   static constexpr int G = H / V;       // threads per line (divides 64)
-  static constexpr int W = sizeof(T) == 4 ? 32 : (M >= 1024 ? 8 : 16);  // lines per tile
+  static constexpr int W = (sizeof(T) == 4 ? 32 : 16) / (M >= 1024 ? 2 : 1);  // lines per tile
+  // LDS pitch of a line: room for the padded FFT buffer (H + H/8 complex), even so that a
+  // line starts on a complex boundary, and not a multiple of the bank count
+  static constexpr int P = ((M + M / 8 + 2) + 1) & ~1;
   static constexpr int LPR = kBlock / G;              // lines per round
   static constexpr int ROUNDS = (W + LPR - 1) / LPR;
 };
+
+// Padded position of complex element p in a line's FFT buffer: one pad slot every 8 elements
+// keeps the radix-8 stage writes (stride 8) and the post-processing reads conflict-free.
+__device__ __forceinline__ int pad8(int p) { return p + (p >> 3); }
 
 template <int H, int NS>
 constexpr int radix_at() {
@@ -136,8 +143,8 @@ __device__ __forceinline__ void stage(C2<T>* a, int* pos, int g, const C2<T>* tw
   }
 }
 
-// Stages from stride NS to the end, exchanging through `buf` (the line's own slot).  On return
-// the natural-order result is in buf (and the caller has passed a wave barrier).
+// Stages from stride NS to the end, exchanging through `buf` (the line's own slot, padded
+// positions).  On return the natural-order result is in buf[pad8(k)] behind a wave barrier.
 template <typename T, int H, int V, int NS>
 __device__ __forceinline__ void fft_stages(C2<T>* a, int g, C2<T>* buf, const C2<T>* tw) {
   constexpr int R = radix_at<H, NS>();
@@ -145,17 +152,17 @@ __device__ __forceinline__ void fft_stages(C2<T>* a, int g, C2<T>* buf, const C2
   int pos[V];
   stage<T, H, V, R, NS>(a, pos, g, tw);
 #pragma unroll
-  for (int s = 0; s < V; ++s) buf[pos[s]] = a[s];
+  for (int s = 0; s < V; ++s) buf[pad8(pos[s])] = a[s];
   wave_sync();
   if constexpr (NS * R < H) {
 #pragma unroll
-    for (int s = 0; s < V; ++s) a[s] = buf[g + s * G];
+    for (int s = 0; s < V; ++s) a[s] = buf[pad8(g + s * G)];
     wave_sync();
     fft_stages<T, H, V, NS * R>(a, g, buf, tw);
   }
 }
 
-// In-place orthonormal DST-I of one line (N reals at `line`, slot of M reals) by the G threads
+// In-place orthonormal DST-I of one line (N reals at `line`, slot of P reals) by the G threads
 // g = 0..G-1 of the line.  The result X_i (i = 1..N) is written to line[i-1] after
 // multiplication by scale(i) * sqrt(2/M).
 template <typename T, int LOGM, class Scale>
@@ -186,8 +193,8 @@ __device__ __forceinline__ void dst1_line(T* line, int g, const C2<T>* tw, Scale
 #pragma unroll
   for (int s = 0; s < V; ++s) {
     const int k = g * V + s;
-    const C2<T> A = buf[k];
-    const C2<T> Bc = buf[(H - k) & (H - 1)];
+    const C2<T> A = buf[pad8(k)];
+    const C2<T> Bc = buf[pad8((H - k) & (H - 1))];
     const C2<T> B = {Bc.x, -Bc.y};
     const C2<T> E = {(T)0.5 * (A.x + B.x), (T)0.5 * (A.y + B.y)};
     const C2<T> D = {(T)0.5 * (A.x - B.x), (T)0.5 * (A.y - B.y)};
@@ -246,7 +253,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 template <typename T, int LOGM, int AX, bool ZPASS, int IN, int OUT>
 __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int nblocks) {
   using K = Cfg<T, LOGM>;
-  constexpr int M = K::M, N = K::N, G = K::G, W = K::W;
+  constexpr int M = K::M, N = K::N, G = K::G, W = K::W, P = K::P;
   constexpr long long VOL = (long long)N * N * N;
   constexpr int LINES_PER_ROW = (AX == AX_X) ? N * N : N;
   constexpr int TILES_PER_ROW = (LINES_PER_ROW + W - 1) / W;
@@ -254,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
   constexpr long long S_LINE = (AX == AX_X) ? N : 1;
   constexpr long long S_ELEM = (AX == AX_X) ? 1 : (AX == AX_Y ? N : (long long)N * N);
 
-  __shared__ __align__(16) T tile[W * M];
+  __shared__ __align__(16) T tile[W * P];
   __shared__ __align__(16) C2<T> tw[2 * M];
   __shared__ unsigned long long red[2][kBlock / 64];
 
@@ -271,51 +278,97 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
   const int tid = threadIdx.x;
 
   const C2<T>* gtw = static_cast<const C2<T>*>(p.tw);
-  for (int i = tid; i < 2 * M; i += kBlock) tw[i] = gtw[i];
+  {
+    constexpr int TWP = (2 * M + kBlock - 1) / kBlock;
+    C2<T> tv[TWP];
+#pragma unroll
+    for (int i = 0; i < TWP; ++i) tv[i] = gtw[min(tid + i * kBlock, 2 * M - 1)];
+#pragma unroll
+    for (int i = 0; i < TWP; ++i)
+      if (tid + i * kBlock < 2 * M) tw[tid + i * kBlock] = tv[i];
+  }
 
   // ------------------------------------------------------------------ load the tile
+  // Each thread owns elements e = tid + i*kBlock of the tile; the loads of a chunk are all
+  // issued before the first use, so a block has CH loads per thread in flight.
+  constexpr int PER = (W * N + kBlock - 1) / kBlock;
+  // chunk of elements per thread whose loads are in flight together (a multiple of 4 or < 4)
+  constexpr int CHMAX = IN == IN_RESID ? 8 : (sizeof(T) == 4 ? 16 : 8);
+  constexpr int CH = PER < CHMAX ? PER : CHMAX;
+  // uniform (per block) base pointers; element offsets inside a tile fit in 32 bits
+  const T* __restrict__ in_t = static_cast<const T*>(p.in) + base;
+  const double* __restrict__ in_d = static_cast<const double*>(p.in) + base;
   if constexpr (AX == AX_X) {
     const int cnt = nlines * N;
-    for (int e = tid; e < cnt; e += kBlock) {
-      const int w = e / N;
-      const int x = e - w * N;
-      const long long g = base + e;
-      T v;
+#pragma unroll 1
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+      T v[CH];
       if constexpr (IN == IN_RESID) {
-        const int ln = line0 + w;
-        const int z = ln / N;
-        const int y = ln - z * N;
-        const double* __restrict__ u = p.u;
-        double nb = 0.0;
-        if (x > 0) nb += u[g - 1];
-        if (x < N - 1) nb += u[g + 1];
-        if (y > 0) nb += u[g - N];
-        if (y < N - 1) nb += u[g + N];
-        if (z > 0) nb += u[g - (long long)N * N];
-        if (z < N - 1) nb += u[g + (long long)N * N];
-        const double r = p.b[g] - (p.sigma + 6.0 * p.inv_h2) * u[g] + p.inv_h2 * nb;
-        v = (T)r;
-      } else if constexpr (IN == IN_F64) {
-        v = (T)(static_cast<const double*>(p.in)[g]);
+        // FP64 residual b - (sigma - Lap_h) u, four elements at a time
+#pragma unroll
+        for (int i0 = 0; i0 < CH; i0 += 4) {
+          constexpr int K4 = CH < 4 ? CH : 4;
+          double rb[K4], uc[K4], nb[K4];
+#pragma unroll
+          for (int k = 0; k < K4; ++k) {
+            const int e = min(tid + (c0 + i0 + k) * kBlock, cnt - 1);
+            const int w = e / N;
+            const int x = e - w * N;
+            const int ln = line0 + w;
+            const int z = ln / N;
+            const int y = ln - z * N;
+            const double* __restrict__ u = p.u + base;
+            uc[k] = u[e];
+            rb[k] = p.b[base + e];
+            double a0 = x > 0 ? u[e - 1] : 0.0;
+            double a1 = x < N - 1 ? u[e + 1] : 0.0;
+            double a2 = y > 0 ? u[e - N] : 0.0;
+            double a3 = y < N - 1 ? u[e + N] : 0.0;
+            double a4 = z > 0 ? u[e - N * N] : 0.0;
+            double a5 = z < N - 1 ? u[e + N * N] : 0.0;
+            nb[k] = (a0 + a1) + (a2 + a3) + (a4 + a5);
+          }
+#pragma unroll
+          for (int k = 0; k < K4; ++k)
+            v[i0 + k] = (T)(rb[k] - (p.sigma + 6.0 * p.inv_h2) * uc[k] + p.inv_h2 * nb[k]);
+        }
       } else {
-        v = static_cast<const T*>(p.in)[g];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const int e = min(tid + (c0 + i) * kBlock, cnt - 1);
+          if constexpr (IN == IN_F64) v[i] = (T)in_d[e];
+          else v[i] = in_t[e];
+        }
       }
-      tile[w * M + x] = v;
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int e = tid + (c0 + i) * kBlock;
+        if (e < cnt) {
+          const int w = e / N;
+          tile[w * P + (e - w * N)] = v[i];
+        }
+      }
     }
   } else {
-    const int cnt = N * W;
-    for (int e = tid; e < cnt; e += kBlock) {
-      const int j = e / W;  // W is a power of two
-      const int w = e - j * W;
-      if (w < nlines) {
-        const long long g = base + w + (long long)j * S_ELEM;
-        T v;
-        if constexpr (IN == IN_F64) {
-          v = (T)(static_cast<const double*>(p.in)[g]);
-        } else {
-          v = static_cast<const T*>(p.in)[g];
-        }
-        tile[w * M + j] = v;
+    constexpr int CNT = N * W;
+#pragma unroll 1
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+      T v[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int e = min(tid + (c0 + i) * kBlock, CNT - 1);
+        const int j = e / W;  // W is a power of two
+        const int w = min(e - j * W, nlines - 1);
+        const int off = w + j * (int)S_ELEM;
+        if constexpr (IN == IN_F64) v[i] = (T)in_d[off];
+        else v[i] = in_t[off];
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int e = tid + (c0 + i) * kBlock;
+        const int j = e / W;
+        const int w = e - j * W;
+        if (e < CNT && w < nlines) tile[w * P + j] = v[i];
       }
     }
   }
@@ -327,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
   for (int round = 0; round < K::ROUNDS; ++round) {
     const int l = round * K::LPR + tid / G;
     if (l < nlines) {  // uniform across the G threads of a line (all in one wavefront)
-      T* line = tile + l * M;
+      T* line = tile + l * P;
       if constexpr (ZPASS) {
         EigScale<T> sc{p.sigma + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]), p.inv_h2,
                        p.lam_hat};
@@ -344,32 +397,63 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
   double cm = 0.0, um = 0.0;
   if constexpr (AX == AX_X) {
     const int cnt = nlines * N;
-    for (int e = tid; e < cnt; e += kBlock) {
-      const int w = e / N;
-      const int x = e - w * N;
-      const long long gi = base + e;
-      const T v = tile[w * M + x];
+#pragma unroll 1
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+      T v[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int e = min(tid + (c0 + i) * kBlock, cnt - 1);
+        const int w = e / N;
+        v[i] = tile[w * P + (e - w * N)];
+      }
       if constexpr (OUT == OUT_UPD) {
-        double* uo = static_cast<double*>(p.out);
-        const double nu = uo[gi] + (double)v;
-        uo[gi] = nu;
-        cm = fmax(cm, fabs((double)v));
-        um = fmax(um, fabs(nu));
-      } else if constexpr (OUT == OUT_F64) {
-        static_cast<double*>(p.out)[gi] = (double)v;
-        cm = fmax(cm, fabs((double)v));
+        double* uo = static_cast<double*>(p.out) + base;
+        double old[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) old[i] = uo[min(tid + (c0 + i) * kBlock, cnt - 1)];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const int e = tid + (c0 + i) * kBlock;
+          if (e < cnt) {
+            const double nu = old[i] + (double)v[i];
+            uo[e] = nu;
+            cm = fmax(cm, fabs((double)v[i]));
+            um = fmax(um, fabs(nu));
+          }
+        }
       } else {
-        static_cast<T*>(p.out)[gi] = v;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const int e = tid + (c0 + i) * kBlock;
+          if (e < cnt) {
+            if constexpr (OUT == OUT_F64) {
+              (static_cast<double*>(p.out) + base)[e] = (double)v[i];
+              cm = fmax(cm, fabs((double)v[i]));
+            } else {
+              (static_cast<T*>(p.out) + base)[e] = v[i];
+            }
+          }
+        }
       }
     }
   } else {
-    const int cnt = N * W;
-    for (int e = tid; e < cnt; e += kBlock) {
-      const int j = e / W;
-      const int w = e - j * W;
-      if (w < nlines) {
-        const long long gi = base + w + (long long)j * S_ELEM;
-        static_cast<T*>(p.out)[gi] = tile[w * M + j];
+    constexpr int CNT = N * W;
+#pragma unroll 1
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+      T v[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int e = min(tid + (c0 + i) * kBlock, CNT - 1);
+        const int j = e / W;
+        const int w = e - j * W;
+        v[i] = tile[w * P + j];
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int e = tid + (c0 + i) * kBlock;
+        const int j = e / W;
+        const int w = e - j * W;
+        if (e < CNT && w < nlines) (static_cast<T*>(p.out) + base)[w + j * (int)S_ELEM] = v[i];
       }
     }
   }

@@ -85,7 +85,8 @@ def test_eigenmode_closed_form_full_size():
     sigma = 1.0
     out = []
     for (k1, k2, k3) in [(1, 1, 1), (255, 3, 128), (17, 200, 64)]:
-        s = [np.sin(np.pi * j * k / (n + 1)) for k in (k1, k2, k3)]
+        # exact integer reduction of j k keeps sin's argument below 2 pi
+        s = [np.sin(np.pi * ((j * k) % (2 * (n + 1))) / (n + 1)) for k in (k1, k2, k3)]
         b = s[2][:, None, None] * s[1][None, :, None] * s[0][None, None, :]
         lam = sum(4.0 / h**2 * np.sin(np.pi * k / (2 * (n + 1))) ** 2 for k in (k1, k2, k3))
         out.append((b, b / (sigma + lam)))
