@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark of the auxiliary-problem solve on one MI355X.
+
+Workload (one step): nrhs = 64 right-hand sides with i.i.d. N(0,1) entries (seed 0, drawn on
+the device) on the 255^3 interior grid of the cube [-1.5, 1.5]^3 (h = 3/256), sigma = 1, solved
+by aux_solve_batched to a relative max-norm error of 1e-10.  Paths timed: FP64 transforms, and
+FP32 transforms with FP64 residual refinement.  `value` is the solves/s of the fastest path
+whose error, checked against the CPU FP64 oracle on a sampled right-hand side, meets 1e-10.
+
+Prints one JSON line on stdout (everything else goes to stderr).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "aux solves/s at 255³ FP32 vs FP64 @1e-10 rel; p50/p99 latency; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+KIND_NAMES = ["x_first", "y", "z_fused", "x_last", "x_residual", "x_update"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=255)
+    ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--sigma", type=float, default=1.0)
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--paths", default="fp64,fp32_ir")
+    ap.add_argument("--cpu-sample", type=int, default=3, help="oracle solves timed for cpu_baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solve is a single-GPU "
+              "path in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import dpm_inputs as inp
+    from paper_1811_03557_amd import _lib, api
+
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    n, nrhs = args.n, args.nrhs
+    h, _ = inp.grid(n)
+    b = inp.rhs_normal_device(n, nrhs, seed=0, device=dev)
+    u = torch.empty_like(b)
+    vol = n ** 3
+
+    path_cfg = {
+        "fp64": dict(prec="fp64", max_refine=0, dtype="f64"),
+        "fp32_ir": dict(prec="fp32", max_refine=3, dtype="f32 transforms + f64 refinement"),
+        "bf16x3_ir": dict(prec="bf16x3", max_refine=4, dtype="bf16x3 MFMA + f64 refinement"),
+    }
+    results = {}
+    for name in [p for p in args.paths.split(",") if p]:
+        cfg = path_cfg[name]
+        g = api.grid(n, h, args.sigma)
+        o = api.opts(cfg["prec"], True, args.rtol, cfg["max_refine"])
+        ws = torch.empty(max(1, api.workspace_size(g, nrhs, o)), dtype=torch.uint8, device=dev)
+
+        def step():
+            api.aux_solve_batched(b, args.sigma, h, prec=cfg["prec"], rtol=args.rtol,
+                                  max_refine=cfg["max_refine"], out=u, workspace=ws)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        _lib.check(lib.dpm_timing_begin(64 * args.steps * (1 + cfg["max_refine"]) * 6))
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(args.steps):
+            step()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / args.steps
+        import ctypes as C
+        cnt = (C.c_int32 * 6)()
+        mean = (C.c_double * 6)()
+        _lib.check(lib.dpm_timing_end(6, cnt, mean))
+        kern = {KIND_NAMES[k]: {"launches_per_step": cnt[k] / args.steps, "mean_ms": mean[k]}
+                for k in range(6) if cnt[k] > 0}
+        # refinement iterations actually used (one extra solve with info)
+        _, info = api.aux_solve_batched(b, args.sigma, h, prec=cfg["prec"], rtol=args.rtol,
+                                        max_refine=cfg["max_refine"], out=u, workspace=ws,
+                                        info=True)
+        results[name] = dict(ms_per_step=ms, solves_per_s=nrhs / (ms * 1e-3), kernels=kern,
+                             refine_iters=info["refine_iters"], dtype=cfg["dtype"],
+                             u0=u[0].cpu().numpy())
+        log(f"[bench] {name}: {ms:.3f} ms/step, {nrhs / (ms * 1e-3):.1f} solves/s, "
+            f"refine_iters={info['refine_iters']}, kernels={kern}")
+
+    # ---- accuracy on a sampled right-hand side against the CPU FP64 oracle, timed as baseline
+    cpu = None
+    b_host = b[: max(1, args.cpu_sample)].cpu().numpy()
+    from oracle import aux as oaux
+    t = time.perf_counter()
+    ref0 = oaux.aux_solve(b_host[0], args.sigma, h)
+    t_first = time.perf_counter() - t
+    for name, r in results.items():
+        r["rel_err_sample"] = oaux.rel_err_inf(r.pop("u0"), ref0)
+        log(f"[bench] {name}: rel err vs oracle (rhs 0) = {r['rel_err_sample']:.3e}")
+    if not args.no_cpu and args.cpu_sample > 1:
+        t = time.perf_counter()
+        for i in range(1, b_host.shape[0]):
+            oaux.aux_solve(b_host[i], args.sigma, h)
+        t_rest = time.perf_counter() - t
+        k = b_host.shape[0] - 1
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        cpu = {"value": k / t_rest, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+               "sample": f"{k} right-hand sides of the same workload (255^3, sigma {args.sigma}), "
+                         f"dense FP64 DST-I oracle; first solve {t_first:.2f} s excluded"}
+        log(f"[bench] cpu oracle: {k / t_rest:.3f} solves/s on {cores} threads")
+
+    ok = {k: v for k, v in results.items() if v["rel_err_sample"] <= args.rtol}
+    best_name = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else None
+    best = ok[best_name] if best_name else None
+
+    roof = None
+    if best is not None:
+        # dominant kernel of the headline path: largest total time per step
+        kern = best["kernels"]
+        dom = max(kern, key=lambda k: kern[k]["launches_per_step"] * kern[k]["mean_ms"])
+        rb = 8 if best_name == "fp64" else 4
+        in_b = 8 if (dom in ("x_first", "x_residual") and rb == 4) else rb
+        out_b = 8 if (dom in ("x_last", "x_update") and rb == 4) else rb
+        per_launch_rhs = nrhs / kern[dom]["launches_per_step"]
+        alg_bytes = per_launch_rhs * vol * (in_b + out_b)
+        achieved = alg_bytes / (kern[dom]["mean_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "bytes_per_launch": alg_bytes, "mean_launch_ms": kern[dom]["mean_ms"]}
+
+    line = {
+        "metric": METRIC,
+        "value": round(best["solves_per_s"], 2) if best else None,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(best["ms_per_step"], 4) if best else None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": best["dtype"] if best else None,
+        "data": "synthetic",
+        "config": {"workload": f"aux solve {n}^3 interior, {nrhs} RHS N(0,1) seed 0, sigma "
+                               f"{args.sigma}, rel tol {args.rtol}", "n": n, "nrhs": nrhs,
+                   "path": best_name},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
+        "alg_hbm_frac": (round(best["solves_per_s"] * 16 * vol / (HBM_PEAK_GBS * 1e9), 4)
+                         if best else None),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -69,3 +69,12 @@ def poisson_arrivals(n: int, qps: float, seed: int = 0) -> np.ndarray:
     """Arrival times (s) of a Poisson process with rate qps."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / qps, size=n))
+
+
+def rhs_normal_device(n: int, nrhs: int, seed: int = 0, device="cuda"):
+    """nrhs i.i.d. N(0,1) FP64 right-hand sides drawn on the device by torch's seeded generator,
+    shape (nrhs, n, n, n).  Used where the batch is too large to draw on the host."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return torch.randn((nrhs, n, n, n), dtype=torch.float64, device=device, generator=g)

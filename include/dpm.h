@@ -189,6 +189,16 @@ dpm_status dpm_gauss_state(const dpm_bep* bep, const dpm_geometry* geom, double 
 
 void dpm_bep_destroy(dpm_bep* bep);
 
+/*
+ * Measurement support (not part of the method): while enabled, every sweep kernel launched by
+ * the solves is bracketed by hipEvents on the stream it runs on.  dpm_timing_end synchronises
+ * the events and returns, per sweep kind, the number of launches and their mean duration in ms.
+ * Kinds: 0 first x sweep, 1 y sweep, 2 fused z sweep, 3 last x sweep, 4 residual x sweep,
+ * 5 update x sweep.  At most max_launches launches are recorded.  Process-wide, not thread safe.
+ */
+dpm_status dpm_timing_begin(int32_t max_launches);
+dpm_status dpm_timing_end(int32_t nkinds, int32_t* counts, double* mean_ms);
+
 /* Thread-local text of the last error (empty string when none). */
 const char* dpm_last_error(void);
 

@@ -62,10 +62,12 @@ __global__ void k_flags_check(SolveFlags f, int rhs0, int nb, int k, double rtol
   f.umax[r] = 0ull;
 }
 
+// Right-hand sides per launch: the working volume of a chunk is kept near 128 MB so that the
+// sweeps of one chunk find it in the 256 MB Infinity Cache.
 int default_chunk(int n, int nrhs, int real_bytes, bool need_ws) {
-  if (!need_ws) return nrhs;
+  (void)need_ws;
   const double vol = (double)n * n * n * real_bytes;
-  int c = (int)std::floor(64.0e6 / vol);
+  int c = (int)std::floor(128.0e6 / vol);
   if (c < 1) c = 1;
   if (c > nrhs) c = nrhs;
   if (c > 65535) c = 65535;
@@ -148,20 +150,28 @@ static dpm_status five_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind 
   a.rhs0 = rhs0;
   a.b = b;
   a.u = u;
-  auto pass = [&](AxisKind ax, bool z, InKind ik, OutKind ok, const void* i, void* o, bool track) {
+  auto pass = [&](AxisKind ax, bool z, InKind ik, OutKind ok, const void* i, void* o, bool track,
+                  bool first) {
     PassArgs q = a;
     q.in = i;
     q.out = o;
     q.cmax = track ? fl->cmax : nullptr;
     q.umax = track ? fl->umax : nullptr;
-    if (bf16) return launch_bf16x3_pass(g.n, ax, z, ik, ok, q, pl, nb, s);
-    return launch_dst_pass(rb, g.n, ax, z, ik, ok, q, nb, s);
+    const int kind = ax == AX_Y ? SW_Y : ax == AX_Z ? SW_Z
+                   : ik == IN_RESID ? SW_X_RESID : ok == OUT_UPD ? SW_X_UPD
+                   : first ? SW_X_FIRST : SW_X_LAST;
+    const bool tm = timing_on();
+    if (tm) timing_before(s);
+    dpm_status st = bf16 ? launch_bf16x3_pass(g.n, ax, z, ik, ok, q, pl, nb, s)
+                         : launch_dst_pass(rb, g.n, ax, z, ik, ok, q, nb, s);
+    if (tm) timing_after(s, kind);
+    return st;
   };
-  DPM_TRY(pass(AX_X, false, in_kind, OUT_WS, src, ws, false));
-  DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, ws, ws, false));
-  DPM_TRY(pass(AX_Z, true, IN_WS, OUT_WS, ws, ws, false));
-  DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, ws, ws, false));
-  DPM_TRY(pass(AX_X, false, IN_WS, out_kind, ws, dst, fl != nullptr));
+  DPM_TRY(pass(AX_X, false, in_kind, OUT_WS, src, ws, false, true));
+  DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, ws, ws, false, false));
+  DPM_TRY(pass(AX_Z, true, IN_WS, OUT_WS, ws, ws, false, false));
+  DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, ws, ws, false, false));
+  DPM_TRY(pass(AX_X, false, IN_WS, out_kind, ws, dst, fl != nullptr, false));
   return DPM_OK;
 }
 

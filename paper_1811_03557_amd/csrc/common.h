@@ -83,6 +83,14 @@ dpm_status launch_dst_pass(int real_bytes, int n, AxisKind ax, bool zpass, InKin
 dpm_status launch_bf16x3_pass(int n, AxisKind ax, bool zpass, InKind in, OutKind out,
                               const PassArgs& a, const Plan* plan, int nrhs, hipStream_t s);
 
+// ---------------------------------------------------------------- measurement support
+// Sweep kinds reported by dpm_timing_end.
+enum SweepKind { SW_X_FIRST = 0, SW_Y = 1, SW_Z = 2, SW_X_LAST = 3, SW_X_RESID = 4, SW_X_UPD = 5,
+                 SW_KINDS = 6 };
+bool timing_on();
+void timing_before(hipStream_t s);
+void timing_after(hipStream_t s, int kind);
+
 // ---------------------------------------------------------------- solver internals
 struct SolveFlags {
   int* done;
