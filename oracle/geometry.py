@@ -91,7 +91,8 @@ def project_sphere(z, y, x, center=(0.0, 0.0, 0.0), radius=1.0):
     px, py, pz = x - cx, y - cy, z - cz
     rho = np.sqrt(px * px + py * py + pz * pz)
     d = rho - radius
-    theta = np.arccos(np.clip(pz / rho, -1.0, 1.0))
+    # polar angle as atan2(sin, cos): well conditioned at the poles (arccos loses sqrt(eps))
+    theta = np.arctan2(np.sqrt(px * px + py * py), pz)
     phi = np.arctan2(py, px)
     return d, theta, phi
 
@@ -124,8 +125,9 @@ def project_ellipsoid(z, y, x, center=(0.0, 0.0, 0.0), axes=(1.0, 0.8, 0.6)):
         outside = float(np.sum(p * p / a2)) > 1.0
         dist = float(np.linalg.norm(p - q))
         d[i] = dist if outside else -dist
-        th[i] = np.arccos(np.clip(q[2] / a[2], -1.0, 1.0))
-        ph[i] = np.arctan2(q[1] / a[1], q[0] / a[0])
+        u, v, w = q / a
+        th[i] = np.arctan2(np.hypot(u, v), w)
+        ph[i] = np.arctan2(v, u)
     shp = np.shape(x)
     return d.reshape(shp), th.reshape(shp), ph.reshape(shp)
 
