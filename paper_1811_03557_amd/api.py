@@ -142,3 +142,108 @@ def basis(n: int, h: float, x0: float, geo: L.Geometry, idx: torch.Tensor, lmax:
                                int(lmax), int(beta), C.c_void_p(B.data_ptr()),
                                C.c_void_p(d.data_ptr()), C.c_void_p(_stream(stream))))
     return B, d
+
+
+class BEP:
+    """Owner of a dpm_bep handle (boundary matrix, QR, point sets); released on close()."""
+
+    def __init__(self, ptr: int, n: int, h: float, sigma: float, x0: float, device):
+        self.ptr = ptr
+        self.n, self.h, self.sigma, self.x0 = n, h, sigma, x0
+        self.device = device
+        ng, ngi, nb = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        rmin, rmax = C.c_double(0), C.c_double(0)
+        L.check(L.load().dpm_bep_info(C.c_void_p(ptr), C.byref(ng), C.byref(ngi), C.byref(nb),
+                                      C.byref(rmin), C.byref(rmax)))
+        self.n_gamma, self.n_gamma_in, self.n_basis = ng.value, ngi.value, nb.value
+        self.rdiag = (rmin.value, rmax.value)
+
+    def close(self):
+        if self.ptr:
+            L.load().dpm_bep_destroy(C.c_void_p(self.ptr))
+            self.ptr = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_boundary_matrix(m_plus: torch.Tensor, basis_mat: torch.Tensor, n: int, h: float,
+                          sigma: float, x0: float = 0.0, prec: str = "fp64", rtol: float = 1e-10,
+                          max_refine: int = 0, rhs_chunk: int = 0, return_A: bool = False,
+                          stream=None):
+    """Step 2: the reduced-BEP matrix of the densities `basis_mat` (n_basis x n_gamma) and its QR.
+
+    Returns a BEP handle (and A, |gamma_in| x n_basis, when return_A)."""
+    lib = L.load()
+    g = grid(n, h, sigma, x0)
+    o = opts(prec, True, rtol, max_refine, rhs_chunk)
+    nb = int(basis_mat.shape[0])
+    out = C.c_void_p(0)
+    A = None
+    if return_A:
+        # |gamma_in| is known only after classification: count first
+        _, is_in = gamma_points(m_plus, h, x0, stream)
+        A = torch.empty((nb, int(is_in.sum().item())), dtype=torch.float64, device=m_plus.device)
+    L.check(lib.dpm_build_boundary_matrix(
+        C.byref(g), C.c_void_p(_dev(m_plus, "m_plus", torch.uint8)), nb,
+        C.c_void_p(_dev(basis_mat, "basis", torch.float64)), C.byref(o),
+        C.c_void_p(_stream(stream)), C.byref(out), C.c_void_p(A.data_ptr()) if A is not None else None))
+    bep = BEP(out.value, n, h, sigma, x0, m_plus.device)
+    if return_A:
+        return bep, A.t()   # column-major storage -> (|gamma_in|, n_basis) view
+    return bep
+
+
+def bep_solve(bep: BEP, g: torch.Tensor, stream=None) -> torch.Tensor:
+    """Least-squares coefficients for g of shape (nvec, |gamma_in|)."""
+    gg = g.unsqueeze(0) if g.dim() == 1 else g
+    Cc = torch.empty((gg.shape[0], bep.n_basis), dtype=torch.float64, device=gg.device)
+    L.check(L.load().dpm_bep_solve(C.c_void_p(bep.ptr), int(gg.shape[0]),
+                                   C.c_void_p(_dev(gg, "g", torch.float64)),
+                                   C.c_void_p(Cc.data_ptr()), C.c_void_p(_stream(stream))))
+    return Cc[0] if g.dim() == 1 else Cc
+
+
+def step_workspace_size(bep: BEP, o: L.Opts) -> int:
+    nb = C.c_size_t(0)
+    L.check(L.load().dpm_step_workspace_size(C.c_void_p(bep.ptr), C.byref(o), C.byref(nb)))
+    return int(nb.value)
+
+
+def dpm_step(bep: BEP, dt: float, chi: float, rho: torch.Tensor, c: torch.Tensor,
+             rho_out: torch.Tensor | None = None, c_out: torch.Tensor | None = None,
+             prec: str = "fp64", rtol: float = 1e-10, max_refine: int = 0,
+             workspace: torch.Tensor | None = None, stream=None, info: bool = False):
+    """Steps 4a-7 for (rho, c) on N+; returns (rho_new, c_new)."""
+    lib = L.load()
+    o = opts(prec, True, rtol, max_refine)
+    nbytes = step_workspace_size(bep, o)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=rho.device)
+    o.workspace = C.c_void_p(workspace.data_ptr())
+    o.workspace_bytes = workspace.numel()
+    rho_out = torch.empty_like(rho) if rho_out is None else rho_out
+    c_out = torch.empty_like(c) if c_out is None else c_out
+    inf = L.Info()
+    L.check(lib.dpm_step(C.c_void_p(bep.ptr), float(dt), float(chi),
+                         C.c_void_p(_dev(rho, "rho", torch.float64)),
+                         C.c_void_p(_dev(c, "c", torch.float64)),
+                         C.c_void_p(_dev(rho_out, "rho_out", torch.float64)),
+                         C.c_void_p(_dev(c_out, "c_out", torch.float64)), C.byref(o),
+                         C.c_void_p(_stream(stream)), C.byref(inf) if info else None))
+    if info:
+        return rho_out, c_out, {"refine_iters": inf.refine_iters, "est_rel_err": inf.est_rel_err}
+    return rho_out, c_out
+
+
+def gauss_state(bep: BEP, geo: L.Geometry, amp: float, rate: float, center=(0.0, 0.0, 0.0),
+                stream=None) -> torch.Tensor:
+    """amp exp(-rate |x - center|^2) on M+, and at the projection onto Gamma on gamma."""
+    out = torch.empty((bep.n, bep.n, bep.n), dtype=torch.float64, device=bep.device)
+    c3 = (C.c_double * 3)(*center)
+    L.check(L.load().dpm_gauss_state(C.c_void_p(bep.ptr), C.byref(geo), float(amp), float(rate),
+                                     c3, C.c_void_p(out.data_ptr()), C.c_void_p(_stream(stream))))
+    return out

@@ -2,7 +2,7 @@
 // Nothing is enqueued when validation fails.
 #include <cmath>
 
-#include "common.h"
+#include "bep.h"
 
 namespace dpm {
 const char* last_error_text();
@@ -13,6 +13,12 @@ dpm_status basis_impl(const dpm_grid& g, const dpm_geometry& geo, int32_t n_gamm
                       const int32_t* idx, int32_t lmax, int32_t beta, double* basis, double* d_out,
                       hipStream_t s);
 dpm_status validate_geometry(const dpm_geometry* geo);
+dpm_status step_workspace_impl(const dpm_bep* b, const dpm_opts& o, size_t* bytes);
+dpm_status step_impl(const dpm_bep* b, double dt, double chi, const double* rho_in,
+                     const double* c_in, double* rho_out, double* c_out, const dpm_opts& o,
+                     hipStream_t s, dpm_info* info);
+dpm_status gauss_state_impl(const dpm_bep* b, const dpm_geometry& geo, double amp, double rate,
+                            const double* c3, double* out, hipStream_t s);
 }  // namespace dpm
 
 using namespace dpm;
@@ -98,5 +104,79 @@ dpm_status dpm_basis(const dpm_grid* grid, const dpm_geometry* geom, int32_t n_g
   return basis_impl(*grid, *geom, n_gamma, idx, lmax, beta, basis, d_out,
                     static_cast<hipStream_t>(stream));
 }
+
+dpm_status dpm_build_boundary_matrix(const dpm_grid* grid, const uint8_t* m_plus,
+                                     int32_t n_basis, const double* basis, const dpm_opts* opts,
+                                     void* stream, dpm_bep** out, double* A_out) {
+  clear_error();
+  DPM_TRY(validate_grid(grid));
+  DPM_TRY(validate_opts(*grid, opts));
+  if (!m_plus || !basis || !out) { set_error("m_plus, basis or out is NULL"); return DPM_EINVAL; }
+  if (n_basis <= 0 || n_basis > 1024) { set_error("n_basis out of range [1, 1024]"); return DPM_EINVAL; }
+  if (!opts->io_fp64) { set_error("the boundary matrix needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
+  *out = nullptr;
+  return build_bep_impl(*grid, m_plus, n_basis, basis, *opts, static_cast<hipStream_t>(stream),
+                        out, A_out);
+}
+
+dpm_status dpm_bep_info(const dpm_bep* bep, int32_t* n_gamma, int32_t* n_gamma_in,
+                        int32_t* n_basis, double* min_abs_rdiag, double* max_abs_rdiag) {
+  clear_error();
+  if (!bep) { set_error("bep is NULL"); return DPM_EINVAL; }
+  if (n_gamma) *n_gamma = bep->n_gamma;
+  if (n_gamma_in) *n_gamma_in = bep->n_in;
+  if (n_basis) *n_basis = bep->n_basis;
+  if (min_abs_rdiag) *min_abs_rdiag = bep->rdiag_min;
+  if (max_abs_rdiag) *max_abs_rdiag = bep->rdiag_max;
+  return DPM_OK;
+}
+
+dpm_status dpm_bep_solve(const dpm_bep* bep, int32_t nvec, const double* g, double* C,
+                         void* stream) {
+  clear_error();
+  if (!bep || !g || !C) { set_error("bep, g or C is NULL"); return DPM_EINVAL; }
+  if (nvec <= 0 || nvec > 65535) { set_error("nvec out of range"); return DPM_EINVAL; }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* y = nullptr;
+  DPM_TRY_HIP(hipMallocAsync((void**)&y, sizeof(double) * (size_t)nvec * bep->n_in, s));
+  qr_solve(bep, nvec, g, y, C, s);
+  hipError_t e = hipGetLastError();
+  (void)hipFreeAsync(y, s);
+  if (e != hipSuccess) { set_error("dpm_bep_solve: %s", hipGetErrorString(e)); return DPM_EHIP; }
+  return DPM_OK;
+}
+
+dpm_status dpm_step_workspace_size(const dpm_bep* bep, const dpm_opts* opts, size_t* bytes) {
+  clear_error();
+  if (!bep || !bytes) { set_error("bep or bytes is NULL"); return DPM_EINVAL; }
+  DPM_TRY(validate_opts(bep->grid, opts));
+  return step_workspace_impl(bep, *opts, bytes);
+}
+
+dpm_status dpm_step(const dpm_bep* bep, double dt, double chi, const double* rho_in,
+                    const double* c_in, double* rho_out, double* c_out, const dpm_opts* opts,
+                    void* stream, dpm_info* info) {
+  clear_error();
+  if (!bep || !rho_in || !c_in || !rho_out || !c_out) { set_error("NULL argument"); return DPM_EINVAL; }
+  DPM_TRY(validate_opts(bep->grid, opts));
+  if (!opts->io_fp64) { set_error("dpm_step needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(chi)) { set_error("dt must be finite and > 0, chi finite"); return DPM_EINVAL; }
+  if (std::fabs(bep->grid.sigma * dt - 1.0) > 1e-12) {
+    set_error("the handle was built with sigma = %g but 1/dt = %g", bep->grid.sigma, 1.0 / dt);
+    return DPM_EINVAL;
+  }
+  return step_impl(bep, dt, chi, rho_in, c_in, rho_out, c_out, *opts,
+                   static_cast<hipStream_t>(stream), info);
+}
+
+dpm_status dpm_gauss_state(const dpm_bep* bep, const dpm_geometry* geom, double amp,
+                           double rate, const double center[3], double* out, void* stream) {
+  clear_error();
+  if (!bep || !out || !center) { set_error("NULL argument"); return DPM_EINVAL; }
+  DPM_TRY(validate_geometry(geom));
+  return gauss_state_impl(bep, *geom, amp, rate, center, out, static_cast<hipStream_t>(stream));
+}
+
+void dpm_bep_destroy(dpm_bep* bep) { destroy_bep(bep); }
 
 }  // extern "C"

@@ -1,0 +1,40 @@
+// Internal layout of the boundary-equation handle and the helpers shared by the DPM kernels.
+#pragma once
+
+#include "common.h"
+
+struct dpm_bep {
+  dpm_grid grid{};
+  dpm_opts opts{};          // precision of the AP solves (workspace fields unused)
+  int n_gamma = 0, n_in = 0, n_basis = 0;
+  uint8_t* m_plus = nullptr;  // N^3, 1 on M+
+  uint8_t* n_plus = nullptr;  // N^3, 1 on N+ = M+ and gamma_ex
+  int32_t* idx = nullptr;     // gamma, ascending linear index
+  uint8_t* is_in = nullptr;   // gamma_in flags
+  int32_t* idx_in = nullptr;  // linear indices of gamma_in (rows of A)
+  int32_t* pos_in = nullptr;  // position of each gamma_in node inside the gamma list
+  double* basis = nullptr;    // n_basis x n_gamma densities (row nu contiguous)
+  double* A = nullptr;        // n_in x n_basis, column-major: Householder vectors below R
+  double* tau = nullptr;      // n_basis reflector scalars
+  double rdiag_min = 0.0, rdiag_max = 0.0;
+};
+
+namespace dpm {
+
+void fill_zero(double* p, long long n, hipStream_t s);
+void scatter_density(const double* dens, int c0, int ncol, int ng, const int32_t* idx,
+                     double* vol, long long vsz, hipStream_t s);
+// out = M+ ? plus (or 0) : (sigma - Lap_h) w, for nvol volumes
+void minus_operator(const double* w, const uint8_t* mp, const double* plus, double* out, int n,
+                    double sigma, double inv_h2, int nvol, hipStream_t s);
+void gather(const double* vol, long long vsz, const int32_t* idx, int m, int nvec, double* out,
+            hipStream_t s);
+// C[r] = R^-1 Q^T g[r], r < nvec; y: device scratch nvec x n_in
+void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* y, double* C, hipStream_t s);
+
+dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
+                          const double* basis, const dpm_opts& o, hipStream_t s, dpm_bep** out,
+                          double* A_out);
+void destroy_bep(dpm_bep* b);
+
+}  // namespace dpm

@@ -1,0 +1,379 @@
+// Boundary equations of the DPM on the device (paper Sec. 2 and Algorithm "Main Steps",
+// Steps 2 and 5): right-hand sides of the difference potentials of the basis densities, the
+// reduced-BEP matrix A[:, nu] = Tr_gamma_in (I - P_gamma) phi_nu (eq BEP_recast), its FP64
+// Householder QR, and the least-squares solve C = R^-1 Q^T g.
+#include <cmath>
+#include <vector>
+
+#include "bep.h"
+
+namespace dpm {
+
+dpm_status gamma_points_impl(const dpm_grid& g, const uint8_t* m_plus, int32_t* n_gamma,
+                             int32_t* n_gamma_in, int32_t* idx, uint8_t* is_in, hipStream_t s);
+
+namespace {
+
+constexpr int kB = 256;
+
+__global__ void k_fill_zero(double* __restrict__ p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// vol[c][idx[i]] = dens[(c0 + c) * ng + i]: densities of columns c0.. extended by zero
+__global__ void k_scatter_density(const double* __restrict__ dens, int c0, int ncol, int ng,
+                                  const int32_t* __restrict__ idx, double* __restrict__ vol,
+                                  long long vsz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= ng || c >= ncol) return;
+  vol[(long long)c * vsz + idx[i]] = dens[(long long)(c0 + c) * ng + i];
+}
+
+// out = M- ? (sigma - Lap_h) w : keep (keep = 0, or the M+ part given in `plus`)
+__global__ void k_minus_operator(const double* __restrict__ w, const uint8_t* __restrict__ mp,
+                                 const double* __restrict__ plus, double* __restrict__ out, int n,
+                                 double sigma, double inv_h2, int nvol) {
+  const long long vsz = (long long)n * n * n;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= vsz || c >= nvol) return;
+  const long long o = (long long)c * vsz + i;
+  if (mp[i]) {
+    out[o] = plus ? plus[o] : 0.0;
+    return;
+  }
+  const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+  const double* wc = w + (long long)c * vsz;
+  double nb = 0.0;
+  if (x > 0) nb += wc[i - 1];
+  if (x < n - 1) nb += wc[i + 1];
+  if (y > 0) nb += wc[i - n];
+  if (y < n - 1) nb += wc[i + n];
+  if (z > 0) nb += wc[i - (long long)n * n];
+  if (z < n - 1) nb += wc[i + (long long)n * n];
+  out[o] = (sigma + 6.0 * inv_h2) * wc[i] - inv_h2 * nb;
+}
+
+// A[i + (c0+c)*n_in] = dens[(c0+c)][pos_in[i]] - u[c][idx_in[i]]
+__global__ void k_trace_columns(const double* __restrict__ dens, const double* __restrict__ u,
+                                const int32_t* __restrict__ idx_in,
+                                const int32_t* __restrict__ pos_in, int n_in, int ng, int c0,
+                                int ncol, long long vsz, double* __restrict__ A) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n_in || c >= ncol) return;
+  A[(long long)(c0 + c) * n_in + i] =
+      dens[(long long)(c0 + c) * ng + pos_in[i]] - u[(long long)c * vsz + idx_in[i]];
+}
+
+__global__ void k_gather(const double* __restrict__ vol, long long vsz,
+                         const int32_t* __restrict__ idx, int m, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < m) out[(long long)c * m + i] = vol[(long long)c * vsz + idx[i]];
+}
+
+__device__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int k = 0; k < nw; ++k) t += sh[k];  // fixed order: deterministic
+  return t;
+}
+
+// Householder reflector of column j (LAPACK dlarfg convention): on exit A[j,j] = beta (= R_jj),
+// A[j+1:, j] = v (v_0 = 1 implicit), tau[j].  One block.
+__global__ void k_house(double* __restrict__ A, int m, int j, double* __restrict__ tau) {
+  __shared__ double sh[16];
+  double* col = A + (long long)j * m;
+  double ss = 0.0;
+  for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) ss += col[i] * col[i];
+  const double sigma2 = block_sum(ss, sh);
+  const double alpha = col[j];
+  if (sigma2 == 0.0) {
+    if (threadIdx.x == 0) tau[j] = 0.0;
+    return;
+  }
+  const double nrm = sqrt(alpha * alpha + sigma2);
+  const double beta = alpha >= 0.0 ? -nrm : nrm;
+  const double scal = 1.0 / (alpha - beta);
+  for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) col[i] *= scal;
+  if (threadIdx.x == 0) {
+    tau[j] = (beta - alpha) / beta;
+    col[j] = beta;
+  }
+}
+
+// Apply H_j = I - tau v v^T to the trailing columns k > j; one block per column.
+__global__ void k_apply_house(double* __restrict__ A, int m, int ncols, int j,
+                              const double* __restrict__ tau) {
+  __shared__ double sh[16];
+  const int k = j + 1 + blockIdx.x;
+  if (k >= ncols) return;
+  const double t = tau[j];
+  if (t == 0.0) return;
+  const double* v = A + (long long)j * m;
+  double* a = A + (long long)k * m;
+  double d = 0.0;
+  for (int i = j + threadIdx.x; i < m; i += blockDim.x) d += (i == j ? 1.0 : v[i]) * a[i];
+  const double w = t * block_sum(d, sh);
+  for (int i = j + threadIdx.x; i < m; i += blockDim.x) a[i] -= w * (i == j ? 1.0 : v[i]);
+}
+
+// C = R^-1 (Q^T g) for nvec right-hand sides (one block each): reflectors applied in order,
+// then back substitution with the n x n upper triangle.
+__global__ void k_qr_solve(const double* __restrict__ A, const double* __restrict__ tau, int m,
+                           int n, const double* __restrict__ g, double* __restrict__ y,
+                           double* __restrict__ C) {
+  __shared__ double sh[16];
+  __shared__ double cs[1024];
+  const int r = blockIdx.x;
+  double* yv = y + (long long)r * m;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) yv[i] = g[(long long)r * m + i];
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double* v = A + (long long)j * m;
+    double d = 0.0;
+    for (int i = j + threadIdx.x; i < m; i += blockDim.x) d += (i == j ? 1.0 : v[i]) * yv[i];
+    const double w = tau[j] * block_sum(d, sh);
+    for (int i = j + threadIdx.x; i < m; i += blockDim.x) yv[i] -= w * (i == j ? 1.0 : v[i]);
+    __syncthreads();
+  }
+  // back substitution, n <= 1024
+  for (int i = n - 1; i >= 0; --i) {
+    double d = 0.0;
+    for (int k = i + 1 + threadIdx.x; k < n; k += blockDim.x) d += A[(long long)k * m + i] * cs[k];
+    const double s = block_sum(d, sh);
+    if (threadIdx.x == 0) cs[i] = (yv[i] - s) / A[(long long)i * m + i];
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) C[(long long)r * n + i] = cs[i];
+}
+
+__global__ void k_rdiag(const double* __restrict__ A, int m, int n, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = fabs(A[(long long)i * m + i]);
+}
+
+// positions of the gamma_in entries inside the gamma list, and their linear indices
+__global__ void k_in_lists(const int32_t* __restrict__ idx, const uint8_t* __restrict__ is_in,
+                           const int32_t* __restrict__ rank_in, int ng,
+                           int32_t* __restrict__ idx_in, int32_t* __restrict__ pos_in) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ng && is_in[i]) {
+    const int r = rank_in[i];
+    idx_in[r] = idx[i];
+    pos_in[r] = i;
+  }
+}
+
+// N+ = M+ plus gamma_ex
+__global__ void k_nplus(const uint8_t* __restrict__ mp, const int32_t* __restrict__ idx, int ng,
+                        uint8_t* __restrict__ np, long long vsz, int phase) {
+  if (phase == 0) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < vsz;
+         i += (long long)gridDim.x * blockDim.x)
+      np[i] = mp[i];
+  } else {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ng) np[idx[i]] = 1;
+  }
+}
+
+unsigned grid1(long long n, int b = kB) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void fill_zero(double* p, long long n, hipStream_t s) {
+  long long blocks = (n + kB - 1) / kB;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(kB), 0, s, p, n);
+}
+
+void scatter_density(const double* dens, int c0, int ncol, int ng, const int32_t* idx,
+                     double* vol, long long vsz, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_density, dim3(grid1(ng), ncol), dim3(kB), 0, s, dens, c0, ncol,
+                     ng, idx, vol, vsz);
+}
+
+void minus_operator(const double* w, const uint8_t* mp, const double* plus, double* out, int n,
+                    double sigma, double inv_h2, int nvol, hipStream_t s) {
+  const long long vsz = (long long)n * n * n;
+  hipLaunchKernelGGL(k_minus_operator, dim3(grid1(vsz), nvol), dim3(kB), 0, s, w, mp, plus, out,
+                     n, sigma, inv_h2, nvol);
+}
+
+void gather(const double* vol, long long vsz, const int32_t* idx, int m, int nvec, double* out,
+            hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(grid1(m), nvec), dim3(kB), 0, s, vol, vsz, idx, m, out);
+}
+
+void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* y, double* C, hipStream_t s) {
+  hipLaunchKernelGGL(k_qr_solve, dim3(nvec), dim3(1024), 0, s, bep->A, bep->tau, bep->n_in,
+                     bep->n_basis, g, y, C);
+}
+
+dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
+                          const double* basis, const dpm_opts& o, hipStream_t s, dpm_bep** out,
+                          double* A_out) {
+  int32_t ng = 0, nin = 0;
+  DPM_TRY(gamma_points_impl(g, m_plus, &ng, &nin, nullptr, nullptr, s));
+  if (n_basis > nin) {
+    set_error("n_basis = %d exceeds |gamma_in| = %d", n_basis, nin);
+    return DPM_ERANK;
+  }
+  const long long vsz = (long long)g.n * g.n * g.n;
+  dpm_bep* b = new dpm_bep();
+  b->grid = g;
+  b->n_gamma = ng;
+  b->n_in = nin;
+  b->n_basis = n_basis;
+  b->opts = o;
+  b->opts.workspace = nullptr;
+  b->opts.workspace_bytes = 0;
+  auto fail = [&](dpm_status st) {
+    destroy_bep(b);
+    return st;
+  };
+  auto al = [&](void** p, size_t bytes) { return hipMalloc(p, bytes > 0 ? bytes : 1) == hipSuccess; };
+  if (!al((void**)&b->m_plus, vsz) || !al((void**)&b->n_plus, vsz) ||
+      !al((void**)&b->idx, sizeof(int32_t) * ng) || !al((void**)&b->is_in, ng) ||
+      !al((void**)&b->idx_in, sizeof(int32_t) * nin) ||
+      !al((void**)&b->pos_in, sizeof(int32_t) * nin) ||
+      !al((void**)&b->basis, sizeof(double) * (size_t)n_basis * ng) ||
+      !al((void**)&b->A, sizeof(double) * (size_t)n_basis * nin) ||
+      !al((void**)&b->tau, sizeof(double) * n_basis)) {
+    set_error("dpm_build_boundary_matrix: device allocation failed");
+    return fail(DPM_ENOMEM);
+  }
+  if (hipMemcpyAsync(b->m_plus, m_plus, vsz, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(b->basis, basis, sizeof(double) * (size_t)n_basis * ng,
+                     hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    set_error("dpm_build_boundary_matrix: copy failed");
+    return fail(DPM_EHIP);
+  }
+  {
+    dpm_status st = gamma_points_impl(g, b->m_plus, &ng, &nin, b->idx, b->is_in, s);
+    if (st != DPM_OK) return fail(st);
+  }
+  // gamma_in lists: rank of each gamma_in entry via a host scan of the flags
+  {
+    std::vector<uint8_t> fl(ng);
+    std::vector<int32_t> rk(ng, 0);
+    if (hipMemcpy(fl.data(), b->is_in, ng, hipMemcpyDeviceToHost) != hipSuccess) {
+      set_error("dpm_build_boundary_matrix: copy failed");
+      return fail(DPM_EHIP);
+    }
+    int r = 0;
+    for (int i = 0; i < ng; ++i) { rk[i] = r; r += fl[i]; }
+    int32_t* drk = nullptr;
+    if (hipMalloc(&drk, sizeof(int32_t) * ng) != hipSuccess) {
+      set_error("dpm_build_boundary_matrix: device allocation failed");
+      return fail(DPM_ENOMEM);
+    }
+    hipError_t e = hipMemcpy(drk, rk.data(), sizeof(int32_t) * ng, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_in_lists, dim3(grid1(ng)), dim3(kB), 0, s, b->idx, b->is_in, drk, ng,
+                         b->idx_in, b->pos_in);
+      hipLaunchKernelGGL(k_nplus, dim3(4096), dim3(kB), 0, s, b->m_plus, b->idx, ng, b->n_plus, vsz, 0);
+      hipLaunchKernelGGL(k_nplus, dim3(grid1(ng)), dim3(kB), 0, s, b->m_plus, b->idx, ng, b->n_plus, vsz, 1);
+      e = hipStreamSynchronize(s);
+    }
+    (void)hipFree(drk);
+    if (e != hipSuccess) {
+      set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e));
+      return fail(DPM_EHIP);
+    }
+  }
+  // columns in chunks: scatter densities, M- operator, batched AP solve, trace on gamma_in
+  int chunk = o.rhs_chunk > 0 ? o.rhs_chunk : 16;
+  if (chunk > n_basis) chunk = n_basis;
+  dpm_opts so = o;
+  size_t wsb = 0;
+  DPM_TRY(workspace_size_impl(g, chunk, so, &wsb));
+  double *w = nullptr, *rhs = nullptr, *u = nullptr;
+  void* ws = nullptr;
+  if (!al((void**)&w, sizeof(double) * vsz * chunk) || !al((void**)&rhs, sizeof(double) * vsz * chunk) ||
+      !al((void**)&u, sizeof(double) * vsz * chunk) || !al(&ws, wsb)) {
+    (void)hipFree(w); (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
+    set_error("dpm_build_boundary_matrix: device allocation failed");
+    return fail(DPM_ENOMEM);
+  }
+  so.workspace = ws;
+  so.workspace_bytes = wsb;
+  so.rhs_chunk = 0;
+  dpm_status st = DPM_OK;
+  const double inv_h2 = 1.0 / (g.h * g.h);
+  for (int c0 = 0; c0 < n_basis && st == DPM_OK; c0 += chunk) {
+    const int nc = (n_basis - c0) < chunk ? (n_basis - c0) : chunk;
+    fill_zero(w, vsz * nc, s);
+    scatter_density(b->basis, c0, nc, ng, b->idx, w, vsz, s);
+    minus_operator(w, b->m_plus, nullptr, rhs, g.n, g.sigma, inv_h2, nc, s);
+    st = aux_solve_impl(g, nc, rhs, u, so, s, nullptr);
+    if (st != DPM_OK) break;
+    hipLaunchKernelGGL(k_trace_columns, dim3(grid1(nin), nc), dim3(kB), 0, s, b->basis, u,
+                       b->idx_in, b->pos_in, nin, ng, c0, nc, vsz, b->A);
+    if (hipGetLastError() != hipSuccess) { set_error("trace kernel launch failed"); st = DPM_EHIP; }
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(w); (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
+  if (st != DPM_OK) return fail(st);
+  if (A_out &&
+      hipMemcpyAsync(A_out, b->A, sizeof(double) * (size_t)n_basis * nin, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    set_error("dpm_build_boundary_matrix: copy of A failed");
+    return fail(DPM_EHIP);
+  }
+  // Householder QR in place
+  for (int j = 0; j < n_basis; ++j) {
+    hipLaunchKernelGGL(k_house, dim3(1), dim3(1024), 0, s, b->A, nin, j, b->tau);
+    if (j + 1 < n_basis)
+      hipLaunchKernelGGL(k_apply_house, dim3(n_basis - j - 1), dim3(512), 0, s, b->A, nin, n_basis, j, b->tau);
+  }
+  double* rd = nullptr;
+  std::vector<double> rdh(n_basis);
+  if (!al((void**)&rd, sizeof(double) * n_basis)) {
+    set_error("dpm_build_boundary_matrix: device allocation failed");
+    return fail(DPM_ENOMEM);
+  }
+  hipLaunchKernelGGL(k_rdiag, dim3(grid1(n_basis)), dim3(kB), 0, s, b->A, nin, n_basis, rd);
+  hipError_t e = hipMemcpyAsync(rdh.data(), rd, sizeof(double) * n_basis, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(rd);
+  if (e != hipSuccess) {
+    set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e));
+    return fail(DPM_EHIP);
+  }
+  double mn = INFINITY, mx = 0.0;
+  for (double v : rdh) { mn = std::fmin(mn, v); mx = std::fmax(mx, v); }
+  b->rdiag_min = mn;
+  b->rdiag_max = mx;
+  if (!(mn > 1e-12 * mx)) {
+    set_error("boundary matrix is rank deficient: min |R_ii| = %g, max |R_ii| = %g", mn, mx);
+    return fail(DPM_ERANK);
+  }
+  *out = b;
+  return DPM_OK;
+}
+
+void destroy_bep(dpm_bep* b) {
+  if (!b) return;
+  (void)hipFree(b->m_plus);
+  (void)hipFree(b->n_plus);
+  (void)hipFree(b->idx);
+  (void)hipFree(b->is_in);
+  (void)hipFree(b->idx_in);
+  (void)hipFree(b->pos_in);
+  (void)hipFree(b->basis);
+  (void)hipFree(b->A);
+  (void)hipFree(b->tau);
+  delete b;
+}
+
+}  // namespace dpm

@@ -1,0 +1,215 @@
+// One IMEX time step of the DPM for the chemotaxis system (paper Sec. 2, Algorithm "Main Steps",
+// Steps 4a, 5, 6, 7) on the device, and the Gaussian initial data of the paper's Tests A/B.
+//
+//   f_rho = rho - dt g, f_c = (1 - dt) c + dt rho on M+  (eqs discrete_chemotaxis,
+//     discrete_convective_term, c-central-difference, upwind_approximation,
+//     truncated_taylor_expansion, slope_limiter; alpha = gamma_rho = gamma_c = 1)
+//   G f = AP(sigma 1_{M+} f)  (two right-hand sides, one batched solve)
+//   C = least squares of the reduced BEP against Tr_gamma_in G f (QR kept in the handle)
+//   u_gamma = basis^T C
+//   u = P_{N+gamma} u_gamma + G f = AP(1_{M+} sigma f + 1_{M-} (sigma - Lap_h)[u_gamma])
+//     (Green's formula as one solve, by linearity of the AP), restricted to N+.
+// Readings: the limited slope is zero at gamma_ex nodes; a face gradient of exactly 0 takes the
+// right (downstream-cell) state, as the scheme is written.
+#include <cmath>
+
+#include "bep.h"
+#include "geom_dev.h"
+
+namespace dpm {
+
+namespace {
+
+constexpr int kB = 256;
+
+__device__ __forceinline__ double minmod3(double a, double b, double c) {
+  if (a > 0.0 && b > 0.0 && c > 0.0) return fmin(a, fmin(b, c));
+  if (a < 0.0 && b < 0.0 && c < 0.0) return fmax(a, fmax(b, c));
+  return 0.0;
+}
+
+// b2[0] = sigma 1_{M+} f_rho, b2[1] = sigma 1_{M+} f_c
+__global__ void k_pks_rhs(const double* __restrict__ rho, const double* __restrict__ c,
+                          const uint8_t* __restrict__ mp, int n, double h, double dt, double chi,
+                          double sigma, double* __restrict__ b2) {
+  const long long vsz = (long long)n * n * n;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= vsz) return;
+  if (!mp[i]) {
+    b2[i] = 0.0;
+    b2[vsz + i] = 0.0;
+    return;
+  }
+  const double r0 = rho[i], c0 = c[i];
+  const double ih = 1.0 / h, hh = 0.5 * h;
+  const long long st[3] = {(long long)n * n, (long long)n, 1};  // z, y, x
+  double g = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const long long s = st[a];
+    const double rp = rho[i + s], rm = rho[i - s];
+    const double cp = c[i + s], cm = c[i - s];
+    const double s0 = minmod3(2.0 * (rp - r0) * ih, (rp - rm) * (0.5 * ih), 2.0 * (r0 - rm) * ih);
+    double sp = 0.0, sm = 0.0;
+    if (mp[i + s]) {
+      const double rpp = rho[i + 2 * s];
+      sp = minmod3(2.0 * (rpp - rp) * ih, (rpp - r0) * (0.5 * ih), 2.0 * (rp - r0) * ih);
+    }
+    if (mp[i - s]) {
+      const double rmm = rho[i - 2 * s];
+      sm = minmod3(2.0 * (r0 - rm) * ih, (r0 - rmm) * (0.5 * ih), 2.0 * (rm - rmm) * ih);
+    }
+    const double gp = (cp - c0) * ih;  // face i + 1/2
+    const double gm = (c0 - cm) * ih;  // face i - 1/2
+    const double fp = chi * (gp > 0.0 ? r0 + hh * s0 : rp - hh * sp) * gp;
+    const double fm = chi * (gm > 0.0 ? rm + hh * sm : r0 - hh * s0) * gm;
+    g += (fp - fm) * ih;
+  }
+  b2[i] = sigma * (r0 - dt * g);
+  b2[vsz + i] = sigma * ((1.0 - dt) * c0 + dt * r0);
+}
+
+// u_gamma[r][i] = sum_nu basis[nu][i] C[r][nu]
+__global__ void k_density(const double* __restrict__ basis, const double* __restrict__ C,
+                          int nb, int ng, double* __restrict__ ug) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= ng) return;
+  double acc = 0.0;
+  for (int nu = 0; nu < nb; ++nu) acc += basis[(long long)nu * ng + i] * C[r * nb + nu];
+  ug[(long long)r * ng + i] = acc;
+}
+
+__global__ void k_restrict(const double* __restrict__ U, const uint8_t* __restrict__ np,
+                           long long vsz, double* __restrict__ o0, double* __restrict__ o1) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= vsz) return;
+  const bool in = np[i] != 0;
+  o0[i] = in ? U[i] : 0.0;
+  o1[i] = in ? U[vsz + i] : 0.0;
+}
+
+// amp exp(-rate |x - x_c|^2) at M+ nodes; phase 1 overwrites gamma nodes with the value at
+// their projection onto Gamma
+__global__ void k_gauss_nodes(const uint8_t* __restrict__ mp, int n, double h, double x0,
+                              double amp, double rate, double xc, double yc, double zc,
+                              double* __restrict__ out) {
+  const long long vsz = (long long)n * n * n;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= vsz) return;
+  if (!mp[i]) { out[i] = 0.0; return; }
+  const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+  const double dx = x0 + h * x - xc, dy = x0 + h * y - yc, dz = x0 + h * z - zc;
+  out[i] = amp * exp(-rate * (dx * dx + dy * dy + dz * dz));
+}
+
+__global__ void k_gauss_gamma(const int32_t* __restrict__ idx, int ng, int n, double h, double x0,
+                              GeoDev geo, double amp, double rate, double xc, double yc,
+                              double zc, double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ng) return;
+  const long long i = idx[k];
+  const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+  double d, th, ph, q[3];
+  project(geo, x0 + h * x - geo.cx, x0 + h * y - geo.cy, x0 + h * z - geo.cz, &d, &th, &ph, q);
+  const double dx = geo.cx + q[0] - xc, dy = geo.cy + q[1] - yc, dz = geo.cz + q[2] - zc;
+  out[i] = amp * exp(-rate * (dx * dx + dy * dy + dz * dz));
+}
+
+unsigned grid1(long long n) { return (unsigned)((n + kB - 1) / kB); }
+
+struct StepLayout {
+  size_t b2, X, w, g, y, C, ug, solve_ws, total;
+};
+
+StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
+  const size_t V = (size_t)b->grid.n * b->grid.n * b->grid.n * sizeof(double);
+  StepLayout L;
+  size_t o = 0;
+  L.b2 = o; o = align_up(o + 2 * V, 256);
+  L.X = o; o = align_up(o + 2 * V, 256);
+  L.w = o; o = align_up(o + 2 * V, 256);
+  L.g = o; o = align_up(o + 2 * sizeof(double) * b->n_in, 256);
+  L.y = o; o = align_up(o + 2 * sizeof(double) * b->n_in, 256);
+  L.C = o; o = align_up(o + 2 * sizeof(double) * b->n_basis, 256);
+  L.ug = o; o = align_up(o + 2 * sizeof(double) * b->n_gamma, 256);
+  L.solve_ws = o; o = align_up(o + solve_ws, 256);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+dpm_status step_workspace_impl(const dpm_bep* b, const dpm_opts& o, size_t* bytes) {
+  size_t sw = 0;
+  dpm_opts so = o;
+  so.rhs_chunk = 0;
+  DPM_TRY(workspace_size_impl(b->grid, 2, so, &sw));
+  *bytes = step_layout(b, sw).total;
+  return DPM_OK;
+}
+
+dpm_status step_impl(const dpm_bep* b, double dt, double chi, const double* rho_in,
+                     const double* c_in, double* rho_out, double* c_out, const dpm_opts& o,
+                     hipStream_t s, dpm_info* info) {
+  const dpm_grid& g = b->grid;
+  size_t sw = 0;
+  dpm_opts so = o;
+  so.rhs_chunk = 0;
+  DPM_TRY(workspace_size_impl(g, 2, so, &sw));
+  const StepLayout L = step_layout(b, sw);
+  if (o.workspace == nullptr || o.workspace_bytes < L.total) {
+    set_error("dpm_step: workspace too small: %zu bytes given, %zu needed", o.workspace_bytes, L.total);
+    return DPM_EINVAL;
+  }
+  char* ws = static_cast<char*>(o.workspace);
+  double* b2 = reinterpret_cast<double*>(ws + L.b2);
+  double* X = reinterpret_cast<double*>(ws + L.X);
+  double* w = reinterpret_cast<double*>(ws + L.w);
+  double* gv = reinterpret_cast<double*>(ws + L.g);
+  double* yv = reinterpret_cast<double*>(ws + L.y);
+  double* C = reinterpret_cast<double*>(ws + L.C);
+  double* ug = reinterpret_cast<double*>(ws + L.ug);
+  so.workspace = ws + L.solve_ws;
+  so.workspace_bytes = sw;
+  const long long vsz = (long long)g.n * g.n * g.n;
+  const double sigma = g.sigma;
+  // Step 4a: right-hand sides and particular solutions
+  hipLaunchKernelGGL(k_pks_rhs, dim3(grid1(vsz)), dim3(kB), 0, s, rho_in, c_in, b->m_plus, g.n,
+                     g.h, dt, chi, sigma, b2);
+  DPM_TRY_HIP(hipGetLastError());
+  dpm_info i1{};
+  DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, nullptr));
+  // Step 5: Tr_gamma_in G f, least squares, densities
+  gather(X, vsz, b->idx_in, b->n_in, 2, gv, s);
+  qr_solve(b, 2, gv, yv, C, s);
+  hipLaunchKernelGGL(k_density, dim3(grid1(b->n_gamma), 2), dim3(kB), 0, s, b->basis, C,
+                     b->n_basis, b->n_gamma, ug);
+  // Steps 6-7: Green's formula as one AP solve per species
+  fill_zero(w, 2 * vsz, s);
+  scatter_density(ug, 0, 2, b->n_gamma, b->idx, w, vsz, s);
+  minus_operator(w, b->m_plus, b2, b2, g.n, sigma, 1.0 / (g.h * g.h), 2, s);
+  DPM_TRY_HIP(hipGetLastError());
+  DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, info ? &i1 : nullptr));
+  hipLaunchKernelGGL(k_restrict, dim3(grid1(vsz)), dim3(kB), 0, s, X, b->n_plus, vsz, rho_out, c_out);
+  DPM_TRY_HIP(hipGetLastError());
+  if (info) {
+    DPM_TRY_HIP(hipStreamSynchronize(s));
+    *info = i1;
+  }
+  return DPM_OK;
+}
+
+dpm_status gauss_state_impl(const dpm_bep* b, const dpm_geometry& geo, double amp, double rate,
+                            const double* c3, double* out, hipStream_t s) {
+  const dpm_grid& g = b->grid;
+  const long long vsz = (long long)g.n * g.n * g.n;
+  hipLaunchKernelGGL(k_gauss_nodes, dim3(grid1(vsz)), dim3(kB), 0, s, b->m_plus, g.n, g.h, g.x0,
+                     amp, rate, c3[0], c3[1], c3[2], out);
+  hipLaunchKernelGGL(k_gauss_gamma, dim3(grid1(b->n_gamma)), dim3(kB), 0, s, b->idx, b->n_gamma,
+                     g.n, g.h, g.x0, to_dev(geo), amp, rate, c3[0], c3[1], c3[2], out);
+  DPM_TRY_HIP(hipGetLastError());
+  return DPM_OK;
+}
+
+}  // namespace dpm

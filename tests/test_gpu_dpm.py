@@ -1,0 +1,158 @@
+"""GPU parity of the DPM pieces against the FP64 oracle: point sets (bit-exact), spectral
+densities, reduced-BEP matrix, its least-squares solve and one time step."""
+import numpy as np
+import pytest
+
+import dpm_inputs as inp
+from oracle import basis as ob
+from oracle import dpm as odpm
+from oracle import geometry as og
+from oracle import pks as opks
+from tests.gpu_util import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n, shape):
+    h, x0 = inp.grid(n)
+    z, y, x = inp.mesh(n)
+    if shape == "sphere":
+        mp = og.inside_sphere(z, y, x)
+        proj = lambda gz, gy, gx: og.project_sphere(gz, gy, gx)
+        geo = dict(kind="sphere", axes=(1.0,))
+    else:
+        mp = og.inside_ellipsoid(z, y, x)
+        proj = lambda gz, gy, gx: og.project_ellipsoid(gz, gy, gx)
+        geo = dict(kind="ellipsoid", axes=(1.0, 0.8, 0.6))
+    return h, x0, mp, proj, geo
+
+
+@pytest.mark.parametrize("n,shape", [(15, "sphere"), (31, "sphere"), (31, "ellipsoid"), (127, "sphere")])
+def test_point_sets_exact(n, shape):
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    say(f"point sets n={n} {shape}")
+    h, x0, mp, _, geo = _case(n, shape)
+    m_gpu = api.classify(n, h, x0, api.geometry(**geo), device=dev)
+    assert np.array_equal(m_gpu.cpu().numpy().astype(bool), mp)
+    idx, is_in = api.gamma_points(m_gpu, h, x0)
+    ps = og.PointSets(mp)
+    assert np.array_equal(idx.cpu().numpy(), ps.idx)
+    assert np.array_equal(is_in.cpu().numpy().astype(bool), ps.is_in)
+
+
+@pytest.mark.parametrize("n,shape,lmax", [(31, "sphere", 4), (31, "ellipsoid", 4), (63, "sphere", 10)])
+def test_basis_parity(n, shape, lmax):
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    say(f"basis n={n} {shape} lmax={lmax}")
+    h, x0, mp, proj, geo = _case(n, shape)
+    m_gpu = api.classify(n, h, x0, api.geometry(**geo), device=dev)
+    idx, _ = api.gamma_points(m_gpu, h, x0)
+    B, d = api.basis(n, h, x0, api.geometry(**geo), idx, lmax, 1)
+    ps = og.PointSets(mp)
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    dd, th, ph = proj(gz, gy, gx)
+    Bref = ob.basis_matrix(dd, th, ph, lmax, 1)
+    assert np.max(np.abs(d.cpu().numpy() - dd)) < 1e-13
+    assert np.max(np.abs(B.cpu().numpy() - Bref)) < 1e-12 * np.max(np.abs(Bref))
+
+
+def test_geometry_without_margin_rejected():
+    from paper_1811_03557_amd import api, _lib
+    dev = need_gpu()
+    n = 15
+    h, x0 = inp.grid(n)
+    m = api.classify(n, h, x0, api.geometry("sphere", axes=(1.45,)), device=dev)
+    with pytest.raises(_lib.DPMError) as e:
+        api.gamma_points(m, h, x0)
+    assert e.value.status == _lib.DPM_EGEOM
+
+
+def _bep_case(n, shape, lmax, sigma, dev, prec="fp64", max_refine=0):
+    import torch
+    from paper_1811_03557_amd import api
+    h, x0, mp, proj, geo = _case(n, shape)
+    ps = og.PointSets(mp)
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    dd, th, ph = proj(gz, gy, gx)
+    Bref = ob.basis_matrix(dd, th, ph, lmax, 1)
+    m_gpu = torch.from_numpy(mp.astype(np.uint8)).to(dev)
+    bep, A = api.build_boundary_matrix(m_gpu, torch.from_numpy(Bref).to(dev), n, h, sigma, x0,
+                                       prec=prec, max_refine=max_refine, return_A=True)
+    return h, x0, mp, ps, Bref, bep, A.cpu().numpy(), geo
+
+
+@pytest.mark.parametrize("prec,max_refine,tol", [("fp64", 0, 1e-11), ("fp32", 3, 1e-9)])
+def test_boundary_matrix_config1(prec, max_refine, tol):
+    """50-column reduced-BEP matrix of the unit sphere at 31^3, sigma = 1/dt + 1 with dt = h."""
+    dev = need_gpu()
+    say(f"boundary matrix 31^3 {prec}")
+    n = 31
+    h, _ = inp.grid(n)
+    sigma = 1.0 / h + 1.0
+    h, x0, mp, ps, Bref, bep, A, _ = _bep_case(n, "sphere", 4, sigma, dev, prec, max_refine)
+    assert (bep.n_gamma, bep.n_gamma_in, bep.n_basis) == (ps.n_gamma, ps.n_gamma_in, 50)
+    Aref = odpm.bep_matrix(Bref, ps, sigma, h)
+    assert np.max(np.abs(A - Aref)) < tol * np.max(np.abs(Aref))
+    bep.close()
+
+
+def test_least_squares_against_lapack():
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    n = 31
+    h, _ = inp.grid(n)
+    sigma = 2.0 / h**2
+    h, x0, mp, ps, Bref, bep, A, _ = _bep_case(n, "ellipsoid", 3, sigma, dev)
+    g = np.random.default_rng(3).normal(size=(3, ps.n_gamma_in))
+    C = api.bep_solve(bep, torch.from_numpy(g).to(dev)).cpu().numpy()
+    for r in range(3):
+        Cref = odpm.least_squares(A, g[r])
+        assert np.max(np.abs(C[r] - Cref)) < 1e-9 * np.max(np.abs(Cref))
+    bep.close()
+
+
+@pytest.mark.parametrize("n,shape", [(15, "sphere"), (31, "ellipsoid")])
+def test_dpm_step_parity(n, shape):
+    """One step from the Test A data: the HIP step (one merged Green solve) against the oracle's
+    separate potential and particular solves."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    say(f"dpm step n={n} {shape}")
+    h, _ = inp.grid(n)
+    dt = 0.5 * h * h
+    h, x0, mp, ps, Bref, bep, A, geo = _bep_case(n, shape, 2, 1.0 / dt, dev)
+    z, y, x = inp.mesh(n)
+    r2 = x**2 + y**2 + z**2
+    rho = np.where(ps.n_plus, 10 * np.exp(-4 * r2), 0.0)
+    c = np.where(ps.n_plus, 5 * np.exp(-2 * r2), 0.0)
+    r1, c1, _ = opks.dpm_step(rho, c, ps, Bref, A, h, dt, 1.0)
+    rg, cg = api.dpm_step(bep, dt, 1.0, torch.from_numpy(rho).to(dev), torch.from_numpy(c).to(dev))
+    rg, cg = rg.cpu().numpy(), cg.cpu().numpy()
+    assert np.max(np.abs(rg - r1)) < 1e-10 * np.max(np.abs(r1))
+    assert np.max(np.abs(cg - c1)) < 1e-10 * np.max(np.abs(c1))
+    assert np.all(rg[~ps.n_plus] == 0)
+    bep.close()
+
+
+def test_gauss_state():
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    n = 31
+    h, _ = inp.grid(n)
+    h, x0, mp, ps, Bref, bep, A, geo = _bep_case(n, "ellipsoid", 0, 1.0 / h, dev)
+    st = api.gauss_state(bep, api.geometry(**geo), 1000.0, 100.0).cpu().numpy()
+    z, y, x = inp.mesh(n)
+    ref = np.where(ps.m_plus, 1000 * np.exp(-100 * (x**2 + y**2 + z**2)), 0.0).ravel()
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    a = np.array([1.0, 0.8, 0.6])
+    d, th, ph = og.project_ellipsoid(gz, gy, gx)
+    q = np.stack([a[0] * np.sin(th) * np.cos(ph), a[1] * np.sin(th) * np.sin(ph), a[2] * np.cos(th)], 1)
+    ref[ps.idx] = 1000 * np.exp(-100 * np.sum(q * q, 1))
+    assert np.max(np.abs(st.ravel() - ref)) < 1e-10
+    bep.close()
