@@ -40,8 +40,10 @@ struct C2 {
 struct Plan {
   int n = 0;
   int log2L = 0;             // complex FFT length L = 2(n+1) = 2^log2L
-  C2<float>* tw_f = nullptr;  // exp(-2 pi i e / L), e = 0..L-1
-  C2<double>* tw_d = nullptr;
+  // packed transform table (M = n + 1, H = M / 2), 3M reals:
+  //   [ sin(pi j/M), j < M | e^{-2 pi i e/H}, e < H (complex) | e^{-2 pi i k/M}, k < H (complex) ]
+  float* tw_f = nullptr;
+  double* tw_d = nullptr;
   double* lam = nullptr;     // lambda_k = (4/h^2) sin^2(pi k / (2(n+1))) * h^2, k = 1..n
                              // (stored without the 1/h^2 factor: lam_hat = 4 sin^2(...))
   // split-bf16 dense sine matrix for the MFMA path: [Mpad][Mpad] bf16 hi and lo

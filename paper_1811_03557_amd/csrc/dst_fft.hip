@@ -19,7 +19,7 @@
 // The real DFT is a complex FFT of length H = M/2 on w_q = y_2q + i y_2q+1 (Stockham radix-8,
 // last stage radix 2 or 4, 8 complex values per thread) followed by the even/odd split
 // F_k = (W_k + conj W_{H-k})/2 - i e^{-2 pi i k/M} (W_k - conj W_{H-k})/2.
-// All sines and twiddles come from one FP64-computed table e^{-i pi j/M}, j < 2M, held in LDS.
+// Sines and twiddles come from one FP64-computed table held in LDS.
 //
 // The first x sweep of a refinement step computes the FP64 residual b - (sigma - Lap_h) u on the
 // fly; the last x sweep can add its result into u (u += c) and reduce max|c|, max|u|.
@@ -112,7 +112,7 @@ constexpr int radix_at() {
 
 // One Stockham stage of radix R at stride NS over an FFT of length H with V values per
 // thread.  On entry a[s] is element g + s*G; on exit a[s] is output element pos[s].
-// tw: table e^{-i pi j/M}, j < 2M (M = 2H); the FFT twiddle e^{-2 pi i e/H} is tw[4e].
+// tw: e^{-2 pi i e/H}, e < H.
 template <typename T, int H, int V, int R, int NS>
 __device__ __forceinline__ void stage(C2<T>* a, int* pos, int g, const C2<T>* tw) {
   constexpr int G = H / V;
@@ -125,7 +125,7 @@ __device__ __forceinline__ void stage(C2<T>* a, int* pos, int g, const C2<T>* tw
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       x[r] = a[q + r * Q];
-      if (NS > 1 && r > 0) x[r] = cmul(x[r], tw[4 * ((r * vm * (H / (NS * R))) & (H - 1))]);
+      if (NS > 1 && r > 0) x[r] = cmul(x[r], tw[(r * vm * (H / (NS * R))) & (H - 1)]);
     }
     if constexpr (R == 8) {
       dft8(x);
@@ -162,68 +162,99 @@ __device__ __forceinline__ void fft_stages(C2<T>* a, int g, C2<T>* buf, const C2
   }
 }
 
-// In-place orthonormal DST-I of one line (N reals at `line`, slot of P reals) by the G threads
-// g = 0..G-1 of the line.  The result X_i (i = 1..N) is written to line[i-1] after
-// multiplication by scale(i) * sqrt(2/M).
+// Inclusive prefix sum across the G threads of a line (G divides 64; groups are aligned).
+// Within a 16-lane DPP row the shifts are row_shr moves; wider groups use lane shuffles.
+template <int N>
+__device__ __forceinline__ double dpp_shr(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x110 + N, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x110 + N, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int N>
+__device__ __forceinline__ float dpp_shr(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + N, 0xF, 0xF, false));
+}
+template <typename T, int G>
+__device__ __forceinline__ T group_scan(T v, int g) {
+  if constexpr (G <= 16) {
+    if constexpr (G > 1) { const T t = dpp_shr<1>(v); if (g >= 1) v += t; }
+    if constexpr (G > 2) { const T t = dpp_shr<2>(v); if (g >= 2) v += t; }
+    if constexpr (G > 4) { const T t = dpp_shr<4>(v); if (g >= 4) v += t; }
+    if constexpr (G > 8) { const T t = dpp_shr<8>(v); if (g >= 8) v += t; }
+  } else {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+      const T o = __shfl_up(v, off, G);
+      if (g >= off) v += o;
+    }
+  }
+  return v;
+}
+
+// In-place orthonormal DST-I of one line by the G threads g = 0..G-1 of the line.  Slot layout
+// (P reals): x_j at line[j], j = 1..N, line[0] = 0; on exit X_i (i = 1..N) is at line[i] after
+// multiplication by scale(i) * sqrt(2/M), and line[0] = 0 again.  The slot doubles as the
+// padded FFT buffer (pad8 positions).  Thread g owns the strided elements g + s*G, so that every
+// LDS access of a stage touches consecutive positions.
+// tab: [ sin(pi j/M), j < M | e^{-2 pi i e/H}, e < H | e^{-2 pi i k/M}, k < H ].
 template <typename T, int LOGM, class Scale>
-__device__ __forceinline__ void dst1_line(T* line, int g, const C2<T>* tw, Scale scale) {
+__device__ __forceinline__ void dst1_line(T* line, int g, const T* tab, Scale scale) {
   using K = Cfg<T, LOGM>;
   constexpr int M = K::M, H = K::H, V = K::V, G = K::G;
   C2<T>* buf = reinterpret_cast<C2<T>*>(line);
-  // ---- pre-processing into the first stage's registers: element q = g + s*G
+  const T* ts = tab;
+  const C2<T>* tw = reinterpret_cast<const C2<T>*>(tab + M);
+  const C2<T>* tp = reinterpret_cast<const C2<T>*>(tab + 2 * M);
+  // ---- pre-processing into the first stage's registers: element q = g + s*G holds
+  //      y_2q + i y_2q+1 with y_j = sin(pi j/M)(x_j + x_{M-j}) + (x_j - x_{M-j})/2, y_0 = 0
   C2<T> a[V];
 #pragma unroll
   for (int s = 0; s < V; ++s) {
     const int q = g + s * G;
-    const int j0 = 2 * q, j1 = 2 * q + 1;
-    // x_j at line[j-1]; x_0 = x_M = 0
-    const T xa0 = j0 > 0 ? line[j0 - 1] : (T)0;
-    const T xb0 = j0 > 0 ? line[M - j0 - 1] : (T)0;
-    const T xa1 = line[j1 - 1];
-    const T xb1 = line[M - j1 - 1];
-    const T s0 = -tw[j0].y;  // sin(pi j/M)
-    const T s1 = -tw[j1].y;
-    a[s].x = j0 > 0 ? s0 * (xa0 + xb0) + (T)0.5 * (xa0 - xb0) : (T)0;
-    a[s].y = s1 * (xa1 + xb1) + (T)0.5 * (xa1 - xb1);
+    const C2<T> xa = buf[q];                       // (x_2q, x_2q+1)
+    const C2<T> sn = reinterpret_cast<const C2<T>*>(ts)[q];  // (sin(pi 2q/M), sin(pi (2q+1)/M))
+    const T xb0 = q > 0 ? line[M - 2 * q] : (T)0;  // x_{M-2q}
+    const T xb1 = line[M - 2 * q - 1];             // x_{M-2q-1}
+    a[s].x = q > 0 ? sn.x * (xa.x + xb0) + (T)0.5 * (xa.x - xb0) : (T)0;
+    a[s].y = sn.y * (xa.y + xb1) + (T)0.5 * (xa.y - xb1);
   }
   wave_sync();  // all reads of x done before the slot is overwritten
   fft_stages<T, H, V, 1>(a, g, buf, tw);
-  // ---- post-processing: thread g owns k = g*V .. g*V + V - 1
+  // ---- post-processing: F_k = E_k + e^{-2 pi i k/M} O_k for k = g + s*G
   T re[V], im[V];
 #pragma unroll
   for (int s = 0; s < V; ++s) {
-    const int k = g * V + s;
+    const int k = g + s * G;
     const C2<T> A = buf[pad8(k)];
     const C2<T> Bc = buf[pad8((H - k) & (H - 1))];
     const C2<T> B = {Bc.x, -Bc.y};
     const C2<T> E = {(T)0.5 * (A.x + B.x), (T)0.5 * (A.y + B.y)};
     const C2<T> D = {(T)0.5 * (A.x - B.x), (T)0.5 * (A.y - B.y)};
     const C2<T> O = {D.y, -D.x};  // -i D
-    const C2<T> F = cadd(E, cmul(tw[2 * k], O));
+    const C2<T> F = cadd(E, cmul(tp[k], O));
     re[s] = F.x;
     im[s] = F.y;
   }
-  // inclusive prefix of Re F over k: thread-local, then across the G threads of the line
+  // ---- X_{2k+1} = sum_{k' <= k} Re F_k' - Re F_0 / 2: prefix in k = g + s*G order, i.e. a
+  //      scan across the line's threads for each s plus the totals of the rows before it
+  const T f0 = __shfl(re[0], 0, G);  // Re F_0 (element k = 0: s = 0, g = 0)
+  T carry = -(T)0.5 * f0;
 #pragma unroll
-  for (int s = 1; s < V; ++s) re[s] += re[s - 1];
-  T run = re[V - 1];
-  T incl = run;
-#pragma unroll
-  for (int off = 1; off < G; off <<= 1) {
-    const T o = __shfl_up(incl, off, G);
-    if (g >= off) incl += o;
+  for (int s = 0; s < V; ++s) {
+    const T incl = group_scan<T, G>(re[s], g);
+    const T tot = __shfl(incl, G - 1, G);
+    re[s] = carry + incl;
+    carry += tot;
   }
-  const T excl = incl - run;
-  // Re F_0 (= re[0] of thread 0 before the prefix; unchanged by it) broadcast to the line
-  const T f0 = __shfl(re[0], 0, G);
-  wave_sync();  // all reads of W done before X overwrites the slot
+  wave_sync();  // all reads of the FFT result done before X overwrites the slot
   const T c1 = (T)sqrt(2.0 / (double)M);
 #pragma unroll
   for (int s = 0; s < V; ++s) {
-    const int k = g * V + s;
-    const T xodd = excl + re[s] - (T)0.5 * f0;  // X_{2k+1}
-    if (k > 0) line[2 * k - 1] = -im[s] * c1 * scale(2 * k);
-    line[2 * k] = xodd * c1 * scale(2 * k + 1);
+    const int k = g + s * G;
+    C2<T> o;
+    o.x = k > 0 ? -im[s] * c1 * scale(2 * k) : (T)0;  // X_2k   (line[0] = 0 for k = 0)
+    o.y = re[s] * c1 * scale(2 * k + 1);              // X_2k+1
+    buf[k] = o;
   }
   wave_sync();
 }
@@ -262,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
   constexpr long long S_ELEM = (AX == AX_X) ? 1 : (AX == AX_Y ? N : (long long)N * N);
 
   __shared__ __align__(16) T tile[W * P];
-  __shared__ __align__(16) C2<T> tw[2 * M];
+  __shared__ __align__(16) T tab[3 * M];
   __shared__ unsigned long long red[2][kBlock / 64];
 
   const int logical = xcd_remap(blockIdx.x, nblocks);
@@ -277,15 +308,15 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
   const long long base = (long long)rhs * VOL + (long long)row * S_OUTER + (long long)line0 * S_LINE;
   const int tid = threadIdx.x;
 
-  const C2<T>* gtw = static_cast<const C2<T>*>(p.tw);
   {
-    constexpr int TWP = (2 * M + kBlock - 1) / kBlock;
-    C2<T> tv[TWP];
+    const T* gtab = static_cast<const T*>(p.tw);
+    constexpr int TP = (3 * M + kBlock - 1) / kBlock;
+    T tv[TP];
 #pragma unroll
-    for (int i = 0; i < TWP; ++i) tv[i] = gtw[min(tid + i * kBlock, 2 * M - 1)];
+    for (int i = 0; i < TP; ++i) tv[i] = gtab[min(tid + i * kBlock, 3 * M - 1)];
 #pragma unroll
-    for (int i = 0; i < TWP; ++i)
-      if (tid + i * kBlock < 2 * M) tw[tid + i * kBlock] = tv[i];
+    for (int i = 0; i < TP; ++i)
+      if (tid + i * kBlock < 3 * M) tab[tid + i * kBlock] = tv[i];
   }
 
   // ------------------------------------------------------------------ load the tile
@@ -345,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
         const int e = tid + (c0 + i) * kBlock;
         if (e < cnt) {
           const int w = e / N;
-          tile[w * P + (e - w * N)] = v[i];
+          tile[w * P + (e - w * N) + 1] = v[i];
         }
       }
     }
@@ -368,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
         const int e = tid + (c0 + i) * kBlock;
         const int j = e / W;
         const int w = e - j * W;
-        if (e < CNT && w < nlines) tile[w * P + j] = v[i];
+        if (e < CNT && w < nlines) tile[w * P + j + 1] = v[i];
       }
     }
   }
@@ -384,10 +415,10 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
       if constexpr (ZPASS) {
         EigScale<T> sc{p.sigma + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]), p.inv_h2,
                        p.lam_hat};
-        dst1_line<T, LOGM>(line, g, tw, sc);
-        dst1_line<T, LOGM>(line, g, tw, NoScale{});
+        dst1_line<T, LOGM>(line, g, tab, sc);
+        dst1_line<T, LOGM>(line, g, tab, NoScale{});
       } else {
-        dst1_line<T, LOGM>(line, g, tw, NoScale{});
+        dst1_line<T, LOGM>(line, g, tab, NoScale{});
       }
     }
   }
@@ -404,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
       for (int i = 0; i < CH; ++i) {
         const int e = min(tid + (c0 + i) * kBlock, cnt - 1);
         const int w = e / N;
-        v[i] = tile[w * P + (e - w * N)];
+        v[i] = tile[w * P + (e - w * N) + 1];
       }
       if constexpr (OUT == OUT_UPD) {
         double* uo = static_cast<double*>(p.out) + base;
@@ -446,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
         const int e = min(tid + (c0 + i) * kBlock, CNT - 1);
         const int j = e / W;
         const int w = e - j * W;
-        v[i] = tile[w * P + j];
+        v[i] = tile[w * P + j + 1];
       }
 #pragma unroll
       for (int i = 0; i < CH; ++i) {

@@ -1,5 +1,5 @@
-// Per-(device, n) tables of the sine transforms: FFT twiddles, the 1D Dirichlet eigenvalues
-// and the split-bf16 dense sine matrix.  Computed on the host in FP64 from their definitions
+// Per-(device, n) tables of the sine transforms: the packed sine/twiddle table of the real-FFT
+// DST-I, the 1D Dirichlet eigenvalues and the split-bf16 dense sine matrix.  Computed on the host in FP64 from their definitions
 // (std::sin / std::cos), uploaded once and kept until the process ends.
 #include <cmath>
 #include <cstdio>
@@ -58,13 +58,22 @@ static dpm_status build_plan(int n, Plan* p) {
   while ((1 << lg) < L) ++lg;
   p->log2L = lg;
   const double pi = std::acos(-1.0);
-  std::vector<C2<double>> twd(L);
-  std::vector<C2<float>> twf(L);
-  for (int e = 0; e < L; ++e) {
-    double a = -2.0 * pi * (double)e / (double)L;
-    twd[e] = {std::cos(a), std::sin(a)};
-    twf[e] = {(float)twd[e].x, (float)twd[e].y};
+  // packed transform table: [ sin(pi j/M), j < M | e^{-2 pi i e/H}, e < H | e^{-2 pi i k/M}, k < H ]
+  const int H = M / 2;
+  std::vector<double> tabd(3 * (size_t)M);
+  for (int j = 0; j < M; ++j) tabd[j] = std::sin(pi * (double)j / (double)M);
+  for (int e = 0; e < H; ++e) {
+    const double a = -2.0 * pi * (double)e / (double)H;
+    tabd[M + 2 * e] = std::cos(a);
+    tabd[M + 2 * e + 1] = std::sin(a);
   }
+  for (int k = 0; k < H; ++k) {
+    const double a = -2.0 * pi * (double)k / (double)M;
+    tabd[2 * M + 2 * k] = std::cos(a);
+    tabd[2 * M + 2 * k + 1] = std::sin(a);
+  }
+  std::vector<float> tabf(tabd.size());
+  for (size_t i = 0; i < tabd.size(); ++i) tabf[i] = (float)tabd[i];
   std::vector<double> lam(n);
   for (int k = 1; k <= n; ++k) {
     double s = std::sin(pi * k / (2.0 * M));
@@ -84,13 +93,13 @@ static dpm_status build_plan(int n, Plan* p) {
       lo[(size_t)(j - 1) * mpad + (k - 1)] = bf16_rne(r);
     }
   p->mpad = mpad;
-  DPM_TRY_HIP(hipMalloc(&p->tw_f, sizeof(C2<float>) * L));
-  DPM_TRY_HIP(hipMalloc(&p->tw_d, sizeof(C2<double>) * L));
+  DPM_TRY_HIP(hipMalloc(&p->tw_f, sizeof(float) * tabf.size()));
+  DPM_TRY_HIP(hipMalloc(&p->tw_d, sizeof(double) * tabd.size()));
   DPM_TRY_HIP(hipMalloc(&p->lam, sizeof(double) * n));
   DPM_TRY_HIP(hipMalloc(&p->s_hi, sizeof(uint16_t) * hi.size()));
   DPM_TRY_HIP(hipMalloc(&p->s_lo, sizeof(uint16_t) * lo.size()));
-  DPM_TRY_HIP(hipMemcpy(p->tw_f, twf.data(), sizeof(C2<float>) * L, hipMemcpyHostToDevice));
-  DPM_TRY_HIP(hipMemcpy(p->tw_d, twd.data(), sizeof(C2<double>) * L, hipMemcpyHostToDevice));
+  DPM_TRY_HIP(hipMemcpy(p->tw_f, tabf.data(), sizeof(float) * tabf.size(), hipMemcpyHostToDevice));
+  DPM_TRY_HIP(hipMemcpy(p->tw_d, tabd.data(), sizeof(double) * tabd.size(), hipMemcpyHostToDevice));
   DPM_TRY_HIP(hipMemcpy(p->lam, lam.data(), sizeof(double) * n, hipMemcpyHostToDevice));
   DPM_TRY_HIP(hipMemcpy(p->s_hi, hi.data(), sizeof(uint16_t) * hi.size(), hipMemcpyHostToDevice));
   DPM_TRY_HIP(hipMemcpy(p->s_lo, lo.data(), sizeof(uint16_t) * lo.size(), hipMemcpyHostToDevice));
