@@ -86,6 +86,17 @@ __device__ __forceinline__ void dft8(C2<T>* a) {
   a[7] = csub(e3, o3);
 }
 
+// Smallest even LDS pitch (reals) that holds a line's x_0..x_M and its padded FFT buffer and
+// is congruent to +-2 modulo 32, so the W lines of a strided load hit distinct banks.
+constexpr int pitch_for(int M) {
+  const int H = M / 2;
+  int need = 2 * ((H - 1) + (H - 1) / 8) + 2;
+  if (need < M + 1) need = M + 1;
+  int p = need + (need & 1);
+  while (p % 32 != 2 && p % 32 != 30) p += 2;
+  return p;
+}
+
 template <typename T, int LOGM>
 struct Cfg {
   static constexpr int M = 1 << LOGM;   // N + 1
@@ -96,7 +107,7 @@ struct Cfg {
   static constexpr int W = (sizeof(T) == 4 ? 32 : 16) / (M >= 1024 ? 2 : 1);  // lines per tile
   // LDS pitch of a line: room for the padded FFT buffer (H + H/8 complex), even so that a
   // line starts on a complex boundary, and not a multiple of the bank count
-  static constexpr int P = ((M + M / 8 + 2) + 1) & ~1;
+  static constexpr int P = pitch_for(M);
   static constexpr int LPR = kBlock / G;              // lines per round
   static constexpr int ROUNDS = (W + LPR - 1) / LPR;
 };
@@ -263,14 +274,6 @@ struct NoScale {
   __device__ __forceinline__ float operator()(int) const { return 1.0f; }
 };
 
-template <typename T>
-struct EigScale {  // 1 / (base + inv_h2 * lam_hat[k-1])
-  double base, inv_h2;
-  const double* lam;
-  __device__ __forceinline__ T operator()(int k) const {
-    return (T)(1.0 / (base + inv_h2 * lam[k - 1]));
-  }
-};
 
 // blockIdx -> logical tile such that consecutive logical tiles run on the same XCD (blocks are
 // dispatched round-robin over the 8 XCDs), so neighbouring tiles that share cache lines and
@@ -413,10 +416,19 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
     if (l < nlines) {  // uniform across the G threads of a line (all in one wavefront)
       T* line = tile + l * P;
       if constexpr (ZPASS) {
-        EigScale<T> sc{p.sigma + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]), p.inv_h2,
-                       p.lam_hat};
-        dst1_line<T, LOGM>(line, g, tab, sc);
-        dst1_line<T, LOGM>(line, g, tab, NoScale{});
+        // forward DST scaled by 1/(sigma + lambda), then the inverse DST: one code path run
+        // twice keeps the register footprint of a single transform
+        const double bxy = p.sigma + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]);
+#pragma unroll 1
+        for (int rep = 0; rep < 2; ++rep) {
+          dst1_line<T, LOGM>(line, g, tab, NoScale{});
+          if (rep == 0) {
+#pragma unroll 4
+            for (int i = 1 + g; i <= N; i += G)
+              line[i] *= (T)(1.0 / (bxy + p.inv_h2 * p.lam_hat[i - 1]));
+            wave_sync();
+          }
+        }
       } else {
         dst1_line<T, LOGM>(line, g, tab, NoScale{});
       }
