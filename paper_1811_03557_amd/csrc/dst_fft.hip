@@ -187,7 +187,13 @@ __device__ __forceinline__ float dpp_shr(float v) {
 }
 template <typename T, int G>
 __device__ __forceinline__ T group_scan(T v, int g) {
-  if constexpr (G <= 16) {
+  if constexpr (G == 16) {
+    // the group is exactly one DPP row: shifted-in lanes read 0, no guard needed
+    v += dpp_shr<1>(v);
+    v += dpp_shr<2>(v);
+    v += dpp_shr<4>(v);
+    v += dpp_shr<8>(v);
+  } else if constexpr (G < 16) {
     if constexpr (G > 1) { const T t = dpp_shr<1>(v); if (g >= 1) v += t; }
     if constexpr (G > 2) { const T t = dpp_shr<2>(v); if (g >= 2) v += t; }
     if constexpr (G > 4) { const T t = dpp_shr<4>(v); if (g >= 4) v += t; }
@@ -202,14 +208,15 @@ __device__ __forceinline__ T group_scan(T v, int g) {
   return v;
 }
 
-// In-place orthonormal DST-I of one line by the G threads g = 0..G-1 of the line.  Slot layout
-// (P reals): x_j at line[j], j = 1..N, line[0] = 0; on exit X_i (i = 1..N) is at line[i] after
-// multiplication by scale(i) * sqrt(2/M), and line[0] = 0 again.  The slot doubles as the
+// In-place DST-I of one line by the G threads g = 0..G-1 of the line, unnormalised: on exit
+// line[i] = 2 X_i with X_i = sum_j x_j sin(pi i j/M) (the orthonormal transform is
+// sqrt(2/M) X; the factors of all six transforms of a solve are applied once, in the z sweep).
+// Slot layout (P reals): x_j at line[j], j = 1..N, line[0] = 0, and again line[0] = 0 on exit.  The slot doubles as the
 // padded FFT buffer (pad8 positions).  Thread g owns the strided elements g + s*G, so that every
 // LDS access of a stage touches consecutive positions.
 // tab: [ sin(pi j/M), j < M | e^{-2 pi i e/H}, e < H | e^{-2 pi i k/M}, k < H ].
-template <typename T, int LOGM, class Scale>
-__device__ __forceinline__ void dst1_line(T* line, int g, const T* tab, Scale scale) {
+template <typename T, int LOGM>
+__device__ __forceinline__ void dst1_line(T* line, int g, const T* tab) {
   using K = Cfg<T, LOGM>;
   constexpr int M = K::M, H = K::H, V = K::V, G = K::G;
   C2<T>* buf = reinterpret_cast<C2<T>*>(line);
@@ -239,14 +246,14 @@ __device__ __forceinline__ void dst1_line(T* line, int g, const T* tab, Scale sc
     const C2<T> A = buf[pad8(k)];
     const C2<T> Bc = buf[pad8((H - k) & (H - 1))];
     const C2<T> B = {Bc.x, -Bc.y};
-    const C2<T> E = {(T)0.5 * (A.x + B.x), (T)0.5 * (A.y + B.y)};
-    const C2<T> D = {(T)0.5 * (A.x - B.x), (T)0.5 * (A.y - B.y)};
-    const C2<T> O = {D.y, -D.x};  // -i D
-    const C2<T> F = cadd(E, cmul(tp[k], O));
+    const C2<T> E = {A.x + B.x, A.y + B.y};  // 2 E_k
+    const C2<T> D = {A.x - B.x, A.y - B.y};  // 2 i O_k
+    const C2<T> O = {D.y, -D.x};             // -i D = 2 O_k
+    const C2<T> F = cadd(E, cmul(tp[k], O));  // 2 F_k
     re[s] = F.x;
     im[s] = F.y;
   }
-  // ---- X_{2k+1} = sum_{k' <= k} Re F_k' - Re F_0 / 2: prefix in k = g + s*G order, i.e. a
+  // ---- X_{2k+1} = sum_{k' <= k} Re F_k' - Re F_0 / 2 (here all doubled): prefix in k = g + s*G order, i.e. a
   //      scan across the line's threads for each s plus the totals of the rows before it
   const T f0 = __shfl(re[0], 0, G);  // Re F_0 (element k = 0: s = 0, g = 0)
   T carry = -(T)0.5 * f0;
@@ -258,21 +265,17 @@ __device__ __forceinline__ void dst1_line(T* line, int g, const T* tab, Scale sc
     carry += tot;
   }
   wave_sync();  // all reads of the FFT result done before X overwrites the slot
-  const T c1 = (T)sqrt(2.0 / (double)M);
 #pragma unroll
   for (int s = 0; s < V; ++s) {
     const int k = g + s * G;
     C2<T> o;
-    o.x = k > 0 ? -im[s] * c1 * scale(2 * k) : (T)0;  // X_2k   (line[0] = 0 for k = 0)
-    o.y = re[s] * c1 * scale(2 * k + 1);              // X_2k+1
+    o.x = k > 0 ? -im[s] : (T)0;  // 2 X_2k   (line[0] = 0 for k = 0)
+    o.y = re[s];                  // 2 X_2k+1
     buf[k] = o;
   }
   wave_sync();
 }
 
-struct NoScale {
-  __device__ __forceinline__ float operator()(int) const { return 1.0f; }
-};
 
 
 // blockIdx -> logical tile such that consecutive logical tiles run on the same XCD (blocks are
@@ -419,18 +422,20 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
         // forward DST scaled by 1/(sigma + lambda), then the inverse DST: one code path run
         // twice keeps the register footprint of a single transform
         const double bxy = p.sigma + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]);
+        // (sqrt(2/M) / 2)^6: normalisation of the six unnormalised transforms of the solve
+        constexpr double kNorm = 1.0 / (8.0 * (double)M * (double)M * (double)M);
 #pragma unroll 1
         for (int rep = 0; rep < 2; ++rep) {
-          dst1_line<T, LOGM>(line, g, tab, NoScale{});
+          dst1_line<T, LOGM>(line, g, tab);
           if (rep == 0) {
 #pragma unroll 4
             for (int i = 1 + g; i <= N; i += G)
-              line[i] *= (T)(1.0 / (bxy + p.inv_h2 * p.lam_hat[i - 1]));
+              line[i] *= (T)(kNorm / (bxy + p.inv_h2 * p.lam_hat[i - 1]));
             wave_sync();
           }
         }
       } else {
-        dst1_line<T, LOGM>(line, g, tab, NoScale{});
+        dst1_line<T, LOGM>(line, g, tab);
       }
     }
   }
