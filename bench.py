@@ -40,7 +40,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--sigma", type=float, default=1.0)
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--paths", default="fp64,fp32_ir")
+    ap.add_argument("--paths", default="fp64,fp32_ir,bf16x3_ir")
     ap.add_argument("--cpu-sample", type=int, default=3, help="oracle solves timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -65,7 +65,7 @@ def main():
     path_cfg = {
         "fp64": dict(prec="fp64", max_refine=0, dtype="f64"),
         "fp32_ir": dict(prec="fp32", max_refine=3, dtype="f32 transforms + f64 refinement"),
-        "bf16x3_ir": dict(prec="bf16x3", max_refine=4, dtype="bf16x3 MFMA + f64 refinement"),
+        "bf16x3_ir": dict(prec="bf16x3", max_refine=5, dtype="bf16x3 MFMA + f64 refinement"),
     }
     results = {}
     for name in [p for p in args.paths.split(",") if p]:

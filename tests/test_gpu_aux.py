@@ -151,3 +151,22 @@ def test_invalid_arguments_raise():
         api.aux_solve(b, -1.0, 0.1)
     with pytest.raises(_lib.DPMError):
         api.aux_solve(b, 1.0, 0.0)
+
+
+@pytest.mark.parametrize("n", [15, 63, 127, 255])
+def test_bf16x3_parity(n):
+    """Split-bf16 MFMA sweeps: ~1e-5 per transform unrefined (the dropped lo*lo product is
+    ~2^-16 relative; six transforms -> tolerance 1e-4), 1e-10 after FP64 refinement."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    say(f"bf16x3 parity n={n}")
+    h, _ = inp.grid(n)
+    b = inp.rhs_normal(n, 2, seed=4)
+    ref = oaux.aux_solve(b, 1.0, h)
+    u0 = _solve(b, 1.0, h, dev, prec="bf16x3", max_refine=0)
+    assert _max_rel(u0, ref) < 1e-4
+    bt = torch.from_numpy(b).to(dev)
+    u, info = api.aux_solve_batched(bt, 1.0, h, prec="bf16x3", max_refine=6, rtol=1e-10, info=True)
+    assert _max_rel(u.cpu().numpy(), ref) < TOL["refined"]
+    assert info["refine_iters"] >= 1
