@@ -71,6 +71,23 @@ def poisson_arrivals(n: int, qps: float, seed: int = 0) -> np.ndarray:
     return np.cumsum(rng.exponential(1.0 / qps, size=n))
 
 
+def serving_workload(n_sims: int = 64, n_requests: int = 2000, qps: float = 1000.0, seed: int = 0,
+                     sizes=(31, 63, 127, 255), step_fraction: float = 0.5,
+                     closed_loop: bool = False):
+    """Request mix of a serving run: simulations from `serving_mix`, the first
+    step_fraction of them advancing DPM steps and the rest issuing aux solves; each request
+    picks a simulation uniformly and, for aux solves, its own log-uniform sigma on [1, 1e4];
+    Poisson arrivals at qps (all at time 0 when closed_loop).
+    Returns (sim_n, sim_sigma, sim_is_step, req_sim, req_sigma, req_arrival)."""
+    ns, sig = serving_mix(n_sims, seed=seed, sizes=sizes)
+    is_step = np.arange(n_sims) < int(step_fraction * n_sims)
+    rng = np.random.default_rng(seed + 1)
+    req_sim = rng.integers(0, n_sims, size=n_requests)
+    req_sig = np.exp(rng.uniform(0.0, np.log(1e4), size=n_requests))
+    arr = np.zeros(n_requests) if closed_loop else poisson_arrivals(n_requests, qps, seed=seed + 2)
+    return ns, sig, is_step, req_sim, req_sig, arr
+
+
 def rhs_normal_device(n: int, nrhs: int, seed: int = 0, device="cuda"):
     """nrhs i.i.d. N(0,1) FP64 right-hand sides drawn on the device by torch's seeded generator,
     shape (nrhs, n, n, n).  Used where the batch is too large to draw on the host."""

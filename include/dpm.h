@@ -9,7 +9,8 @@
  *    zero Dirichlet data.  Volumes are C-ordered [z][y][x] (x fastest) over M0 only; batches are
  *    [nrhs][z][y][x].
  *  - Every pointer argument named "device" is device memory owned by the caller (for example a
- *    torch tensor); the library never frees it.  Pointers must be 16-byte aligned.
+ *    torch tensor); the library never frees it.  Arrays must be aligned to their element size
+ *    (a view into a batch at any right-hand side is fine); workspaces to 16 bytes.
  *  - stream: a hipStream_t passed as void* (NULL = the default stream).  Work is enqueued
  *    asynchronously; results are valid after the stream is synchronised, unless the call says
  *    it synchronises.
@@ -93,6 +94,14 @@ dpm_status aux_solve(const dpm_grid* grid, const void* b, void* u, const dpm_opt
 /* nrhs independent auxiliary problems with the same grid and sigma: b, u are [nrhs][N^3]. */
 dpm_status aux_solve_batched(const dpm_grid* grid, int32_t nrhs, const void* b, void* u,
                              const dpm_opts* opts, void* stream, dpm_info* info);
+
+/* aux_solve_batched with one shift per right-hand side: right-hand side r is solved with
+ * sigma[r] (host array of nrhs finite values >= 0; grid->sigma is ignored).  The shifts are
+ * copied to the workspace on the stream before the call returns, so the host array may be
+ * reused at once.  Lets requests with different time steps share one batched launch. */
+dpm_status aux_solve_batched_sigma(const dpm_grid* grid, int32_t nrhs, const double* sigma,
+                                   const void* b, void* u, const dpm_opts* opts, void* stream,
+                                   dpm_info* info);
 
 /* Geometry of the domain Omega inside the cube: a sphere (axes[0] = radius) or an ellipsoid
  * with semi-axes (axes[0], axes[1], axes[2]) along (x, y, z). */

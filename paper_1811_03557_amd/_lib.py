@@ -44,6 +44,8 @@ SIGNATURES = {
     "dpm_prepare": (C.c_int, [_I]),
     "aux_solve": (C.c_int, [C.POINTER(Grid), _P, _P, C.POINTER(Opts), _P, C.POINTER(Info)]),
     "aux_solve_batched": (C.c_int, [C.POINTER(Grid), _I, _P, _P, C.POINTER(Opts), _P, C.POINTER(Info)]),
+    "aux_solve_batched_sigma": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(_D), _P, _P,
+                                          C.POINTER(Opts), _P, C.POINTER(Info)]),
     "dpm_classify": (C.c_int, [C.POINTER(Grid), C.POINTER(Geometry), _P, _P]),
     "dpm_gamma_points": (C.c_int, [C.POINTER(Grid), _P, C.POINTER(_I), C.POINTER(_I), _P, _P, _P]),
     "dpm_basis": (C.c_int, [C.POINTER(Grid), C.POINTER(Geometry), _I, _P, _I, _I, _P, _P, _P]),

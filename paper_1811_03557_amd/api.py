@@ -89,6 +89,32 @@ def aux_solve_batched(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64
     return res
 
 
+def aux_solve_batched_sigma(b: torch.Tensor, sigmas, h: float, prec: str = "fp64",
+                            rtol: float = 1e-10, max_refine: int = 0,
+                            out: torch.Tensor | None = None,
+                            workspace: torch.Tensor | None = None, stream=None,
+                            rhs_chunk: int = 0):
+    """Batched solve with one shift per right-hand side: b (nrhs, n, n, n), sigmas (nrhs,)."""
+    lib = L.load()
+    nrhs, n = int(b.shape[0]), int(b.shape[1])
+    sig = (C.c_double * nrhs)(*[float(x) for x in sigmas])
+    if len(sig) != nrhs:
+        raise ValueError("one sigma per right-hand side")
+    io_fp64 = b.dtype == torch.float64
+    out = torch.empty_like(b) if out is None else out
+    g = grid(n, h, 0.0)
+    o = opts(prec, io_fp64, rtol, max_refine, rhs_chunk)
+    nbytes = workspace_size(g, nrhs, o)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=b.device)
+    o.workspace = C.c_void_p(workspace.data_ptr())
+    o.workspace_bytes = workspace.numel()
+    L.check(lib.aux_solve_batched_sigma(C.byref(g), nrhs, sig, C.c_void_p(_dev(b, "b")),
+                                        C.c_void_p(_dev(out, "u", b.dtype)), C.byref(o),
+                                        C.c_void_p(_stream(stream)), None))
+    return out
+
+
 def aux_solve(b: torch.Tensor, sigma: float, h: float, **kw):
     """Single right-hand side (n, n, n); see aux_solve_batched."""
     if b.dim() != 3:

@@ -23,7 +23,8 @@ dpm_status gauss_state_impl(const dpm_bep* b, const dpm_geometry& geo, double am
 
 using namespace dpm;
 
-static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+static bool aligned_to(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+static bool aligned16(const void* p) { return aligned_to(p, 16); }
 
 extern "C" {
 
@@ -56,8 +57,9 @@ dpm_status aux_solve_batched(const dpm_grid* grid, int32_t nrhs, const void* b, 
   DPM_TRY(validate_opts(*grid, opts));
   if (nrhs <= 0) { set_error("nrhs must be > 0"); return DPM_EINVAL; }
   if (!b || !u) { set_error("b or u is NULL"); return DPM_EINVAL; }
-  if (!aligned16(b) || !aligned16(u) || !aligned16(opts->workspace)) {
-    set_error("b, u and workspace must be 16-byte aligned");
+  if (!aligned_to(b, opts->io_fp64 ? 8 : 4) || !aligned_to(u, opts->io_fp64 ? 8 : 4) ||
+      !aligned16(opts->workspace)) {
+    set_error("b and u must be aligned to their element size, the workspace to 16 bytes");
     return DPM_EINVAL;
   }
   const size_t bytes = (size_t)nrhs * grid->n * grid->n * grid->n * (opts->io_fp64 ? 8 : 4);
@@ -65,6 +67,32 @@ dpm_status aux_solve_batched(const dpm_grid* grid, int32_t nrhs, const void* b, 
   const char* ub = static_cast<const char*>(u);
   if (bb < ub + bytes && ub < bb + bytes) { set_error("b and u overlap"); return DPM_EINVAL; }
   return aux_solve_impl(*grid, nrhs, b, u, *opts, static_cast<hipStream_t>(stream), info);
+}
+
+dpm_status aux_solve_batched_sigma(const dpm_grid* grid, int32_t nrhs, const double* sigma,
+                                   const void* b, void* u, const dpm_opts* opts, void* stream,
+                                   dpm_info* info) {
+  clear_error();
+  if (!sigma) { set_error("sigma is NULL"); return DPM_EINVAL; }
+  if (nrhs <= 0) { set_error("nrhs must be > 0"); return DPM_EINVAL; }
+  for (int i = 0; i < nrhs; ++i)
+    if (!(sigma[i] >= 0.0) || !std::isfinite(sigma[i])) {
+      set_error("sigma[%d] must be finite and >= 0", i);
+      return DPM_EINVAL;
+    }
+  DPM_TRY(validate_grid(grid));
+  DPM_TRY(validate_opts(*grid, opts));
+  if (!b || !u) { set_error("b or u is NULL"); return DPM_EINVAL; }
+  if (!aligned_to(b, opts->io_fp64 ? 8 : 4) || !aligned_to(u, opts->io_fp64 ? 8 : 4) ||
+      !aligned16(opts->workspace)) {
+    set_error("b and u must be aligned to their element size, the workspace to 16 bytes");
+    return DPM_EINVAL;
+  }
+  const size_t bytes = (size_t)nrhs * grid->n * grid->n * grid->n * (opts->io_fp64 ? 8 : 4);
+  const char* bb = static_cast<const char*>(b);
+  const char* ub = static_cast<const char*>(u);
+  if (bb < ub + bytes && ub < bb + bytes) { set_error("b and u overlap"); return DPM_EINVAL; }
+  return aux_solve_impl(*grid, nrhs, b, u, *opts, static_cast<hipStream_t>(stream), info, sigma);
 }
 
 dpm_status aux_solve(const dpm_grid* grid, const void* b, void* u, const dpm_opts* opts,

@@ -10,7 +10,7 @@ namespace {
 
 // Per right-hand-side refinement state lives at the start of the workspace.
 struct FlagLayout {
-  size_t done, iters, cmax, umax, prev, est, total;
+  size_t done, iters, cmax, umax, prev, est, sig, total;
 };
 FlagLayout flag_layout(int nrhs) {
   FlagLayout f;
@@ -21,6 +21,7 @@ FlagLayout flag_layout(int nrhs) {
   f.umax = o; o = align_up(o + 8 * nrhs, 256);
   f.prev = o; o = align_up(o + 8 * nrhs, 256);
   f.est = o; o = align_up(o + 8 * nrhs, 256);
+  f.sig = o; o = align_up(o + 8 * nrhs, 256);
   f.total = o;
   return f;
 }
@@ -140,8 +141,10 @@ dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, s
 static dpm_status five_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind in_kind,
                               const void* src, OutKind out_kind, void* dst, void* ws,
                               const double* b, const double* u, const SolveFlags* fl, int rhs0,
-                              int nb, bool gated, bool bf16, hipStream_t s) {
+                              int nb, bool gated, bool bf16, const double* sig_rhs,
+                              hipStream_t s) {
   PassArgs a{};
+  a.sigma_rhs = sig_rhs;
   a.tw = rb == 4 ? (const void*)pl->tw_f : (const void*)pl->tw_d;
   a.lam_hat = pl->lam;
   a.sigma = g.sigma;
@@ -176,7 +179,7 @@ static dpm_status five_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind 
 }
 
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, const dpm_opts& o,
-                          hipStream_t s, dpm_info* info) {
+                          hipStream_t s, dpm_info* info, const double* sigma_host) {
   const Plan* pl = nullptr;
   DPM_TRY(get_plan(g.n, &pl));
   const int rb = real_bytes_of(o);
@@ -200,6 +203,11 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
   fl.prev = reinterpret_cast<double*>(wsb + fo.prev);
   fl.est = reinterpret_cast<double*>(wsb + fo.est);
   void* vol_ws = ws_needed ? (void*)(wsb + fo.total) : nullptr;
+  double* sig_dev = nullptr;
+  if (sigma_host != nullptr) {
+    sig_dev = reinterpret_cast<double*>(wsb + fo.sig);
+    DPM_TRY_HIP(hipMemcpyAsync(sig_dev, sigma_host, sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+  }
 
   hipLaunchKernelGGL(k_flags_reset, dim3((nrhs + 255) / 256), dim3(256), 0, s, fl, nrhs);
   DPM_TRY_HIP(hipGetLastError());
@@ -214,21 +222,21 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
     if (o.prec == DPM_FP64 && !refine) {
       // FP64 transforms in place in u: no workspace traffic beyond u itself
       DPM_TRY(five_sweeps(pl, 8, g, IN_WS, bc, OUT_F64, uc, uc, nullptr, nullptr, &fl, c0, nb,
-                          false, false, s));
+                          false, false, sig_dev, s));
     } else if (o.prec == DPM_FP32 && !o.io_fp64) {
       DPM_TRY(five_sweeps(pl, 4, g, IN_WS, bc, OUT_WS, uc, uc, nullptr, nullptr, nullptr, c0, nb,
-                          false, false, s));
+                          false, false, sig_dev, s));
     } else {
       // reduced-precision (or FP64) transforms on the workspace, FP64 iterate in u
       const double* bd = reinterpret_cast<const double*>(bc);
       double* ud = reinterpret_cast<double*>(uc);
       DPM_TRY(five_sweeps(pl, rb, g, IN_F64, bc, OUT_F64, uc, vol_ws, nullptr, nullptr, &fl, c0,
-                          nb, false, bf16, s));
+                          nb, false, bf16, sig_dev, s));
       hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, 0, o.rtol);
       DPM_TRY_HIP(hipGetLastError());
       for (int k = 1; k <= o.max_refine; ++k) {
         DPM_TRY(five_sweeps(pl, rb, g, IN_RESID, nullptr, OUT_UPD, uc, vol_ws, bd, ud, &fl, c0,
-                            nb, true, bf16, s));
+                            nb, true, bf16, sig_dev, s));
         hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, k, o.rtol);
         DPM_TRY_HIP(hipGetLastError());
       }

@@ -92,6 +92,7 @@ __global__ __launch_bounds__(kB) void k_bf16x3_pass(PassArgs p, const __bf16* __
 
   const int rhs = blockIdx.y;
   if (p.done != nullptr && p.done[p.rhs0 + rhs] != 0) return;
+  const double sig = p.sigma_rhs != nullptr ? p.sigma_rhs[p.rhs0 + rhs] : p.sigma;
   const int t = blockIdx.x;
   const int row = t / TILES_PER_ROW;
   const int ti = t - row * TILES_PER_ROW;
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(kB) void k_bf16x3_pass(PassArgs p, const __bf16* __
         const double a3 = y < N - 1 ? u[gi + N] : 0.0;
         const double a4 = z > 0 ? u[gi - (long long)N * N] : 0.0;
         const double a5 = z < N - 1 ? u[gi + (long long)N * N] : 0.0;
-        const double r = p.b[gi] - (p.sigma + 6.0 * p.inv_h2) * u[gi] +
+        const double r = p.b[gi] - (sig + 6.0 * p.inv_h2) * u[gi] +
                          p.inv_h2 * ((a0 + a1) + (a2 + a3) + (a4 + a5));
         v[i] = ok ? (float)r : 0.f;
       } else {
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(kB) void k_bf16x3_pass(PassArgs p, const __bf16* __
       if (tile >= C::KB * WB) break;
       const int kb = tile / WB, wb = tile - kb * WB;
       const int w = wb * 16 + r;
-      const double bxy = (w < nlines) ? p.sigma + p.inv_h2 * (p.lam_hat[line0 + w] + p.lam_hat[row]) : 1.0;
+      const double bxy = (w < nlines) ? sig + p.inv_h2 * (p.lam_hat[line0 + w] + p.lam_hat[row]) : 1.0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int k = kb * 16 + 4 * g + v;

@@ -70,6 +70,7 @@ struct PassArgs {
   const void* tw;            // twiddles of the transform precision
   const double* lam_hat;     // 4 sin^2(pi k/(2(n+1))), k = 1..n
   double sigma;
+  const double* sigma_rhs;   // per right-hand side sigma (device, nullable: use sigma)
   double inv_h2;
   const int* done;           // per right-hand side: skip the whole pass when set (nullable)
   unsigned long long* cmax;  // per rhs: max |correction| (update/store passes, nullable)
@@ -105,7 +106,8 @@ struct SolveFlags {
 
 size_t flags_bytes(int nrhs);
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u,
-                          const dpm_opts& o, hipStream_t s, dpm_info* info);
+                          const dpm_opts& o, hipStream_t s, dpm_info* info,
+                          const double* sigma_host = nullptr);
 dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes);
 dpm_status validate_grid(const dpm_grid* g);
 dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o);

@@ -306,6 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
   const int rhs = logical / tiles;
   const int t = logical - rhs * tiles;
   if (p.done != nullptr && p.done[p.rhs0 + rhs] != 0) return;  // converged: uniform exit
+  const double sig = p.sigma_rhs != nullptr ? p.sigma_rhs[p.rhs0 + rhs] : p.sigma;
 
   const int row = t / TILES_PER_ROW;
   const int ti = t - row * TILES_PER_ROW;
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
           }
 #pragma unroll
           for (int k = 0; k < K4; ++k)
-            v[i0 + k] = (T)(rb[k] - (p.sigma + 6.0 * p.inv_h2) * uc[k] + p.inv_h2 * nb[k]);
+            v[i0 + k] = (T)(rb[k] - (sig + 6.0 * p.inv_h2) * uc[k] + p.inv_h2 * nb[k]);
         }
       } else {
 #pragma unroll
@@ -421,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
       if constexpr (ZPASS) {
         // forward DST scaled by 1/(sigma + lambda), then the inverse DST: one code path run
         // twice keeps the register footprint of a single transform
-        const double bxy = p.sigma + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]);
+        const double bxy = sig + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]);
         // (sqrt(2/M) / 2)^6: normalisation of the six unnormalised transforms of the solve
         constexpr double kNorm = 1.0 / (8.0 * (double)M * (double)M * (double)M);
 #pragma unroll 1

@@ -1,0 +1,241 @@
+"""Continuous-batching server for auxiliary-problem and DPM-step requests on one GPU.
+
+Many simulations issue requests of uneven grid sizes.  Each grid size N is a size class with
+its own HIP stream, so work of different classes overlaps on the device.  An aux request owns
+a slot of its class's ring of device-resident right-hand-side/solution buffers; ready requests
+in consecutive slots are launched together as one `aux_solve_batched_sigma` (each keeps its
+own sigma), so requests that arrive while others run join the next launch instead of waiting
+for a fixed batch.  A DPM-step request advances its simulation's resident state with its
+resident boundary matrix (`dpm_step`); the class stream orders the steps of a simulation.
+Admission is by HBM footprint: a class's ring holds as many slots as its share of the budget
+allows, and a request is admitted when a slot is free (first come, first served).  Completion
+times come from GPU events, latencies are arrival -> completion.
+
+Host orchestration only: every arithmetic step runs in libdpm's kernels.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+import torch
+
+from . import api
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    sim: int
+    kind: str            # "aux" or "step"
+    n: int
+    sigma: float
+    arrival: float       # seconds after the start of the run
+    slot: int = -1
+    t_done: float = float("nan")
+    batch: int = 0
+    out: object = None   # copy of the solution, when the server keeps results
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+@dataclasses.dataclass
+class Simulation:
+    sid: int
+    n: int
+    sigma: float
+    kind: str            # "aux" or "step"
+
+
+class SizeClass:
+    def __init__(self, n: int, slots: int, max_batch: int, device, prec: str, rtol: float,
+                 max_refine: int, seed: int):
+        self.n = n
+        self.h = 3.0 / (n + 1)
+        self.x0 = -1.5 + self.h
+        self.stream = torch.cuda.Stream(device=device)
+        self.slots = slots
+        self.max_batch = max_batch
+        self.prec, self.rtol, self.max_refine = prec, rtol, max_refine
+        g = torch.Generator(device=device)
+        g.manual_seed(seed)
+        self.b = torch.randn((slots, n, n, n), dtype=torch.float64, device=device, generator=g)
+        self.u = torch.zeros_like(self.b)
+        gr = api.grid(n, self.h, 1.0)
+        o = api.opts(prec, True, rtol, max_refine)
+        self.ws = torch.empty(max(1, api.workspace_size(gr, max_batch, o)), dtype=torch.uint8,
+                              device=device)
+        self.free = collections.deque(range(slots))
+        self.ready: collections.deque = collections.deque()   # admitted aux requests, slot order
+        self.steps: collections.deque = collections.deque()   # admitted step requests
+        self.step_ws = None
+
+    def footprint(self) -> int:
+        return 2 * self.b.numel() * 8 + self.ws.numel()
+
+
+class Server:
+    def __init__(self, sims, device="cuda:0", hbm_budget: float = 64e9, max_batch: int = 8,
+                 prec: str = "fp64", rtol: float = 1e-10, max_refine: int = 0, lmax: int = 4,
+                 chi: float = 1.0, keep_results: bool = False, seed: int = 0):
+        self.device = torch.device(device)
+        self.chi = chi
+        self.keep = keep_results
+        self.sims = {s.sid: s for s in sims}
+        sizes = sorted({s.n for s in sims})
+        # HBM admission: each class gets a share of the budget proportional to its volume
+        per_slot = {n: 2 * 8 * n ** 3 for n in sizes}
+        share = hbm_budget / max(1, len(sizes))
+        self.classes = {}
+        for i, n in enumerate(sizes):
+            slots = int(max(1, min(4 * max_batch, share // per_slot[n])))
+            self.classes[n] = SizeClass(n, slots, min(max_batch, slots), self.device, prec, rtol,
+                                        max_refine, seed + i)
+        # resident DPM state: boundary matrix (sigma = 1/dt) and (rho, c) per step simulation
+        self.bep, self.state = {}, {}
+        for s in sims:
+            if s.kind != "step":
+                continue
+            c = self.classes[s.n]
+            geo = api.geometry("sphere", axes=(1.0,))
+            m = api.classify(s.n, c.h, c.x0, geo, device=self.device)
+            idx, _ = api.gamma_points(m, c.h, c.x0)
+            B, _ = api.basis(s.n, c.h, c.x0, geo, idx, lmax, 1)
+            bep = api.build_boundary_matrix(m, B, s.n, c.h, s.sigma, c.x0)
+            rho = api.gauss_state(bep, geo, 1000.0, 100.0)
+            cc = api.gauss_state(bep, geo, 500.0, 50.0)
+            self.bep[s.sid], self.state[s.sid] = bep, (rho, cc)
+            if c.step_ws is None:
+                o = api.opts("fp64", True, rtol, 0)
+                c.step_ws = torch.empty(api.step_workspace_size(bep, o), dtype=torch.uint8,
+                                        device=self.device)
+            elif c.step_ws.numel() < api.step_workspace_size(bep, api.opts("fp64", True, rtol, 0)):
+                c.step_ws = torch.empty(api.step_workspace_size(bep, api.opts("fp64", True, rtol, 0)),
+                                        dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize()
+
+    def footprint(self) -> int:
+        return sum(c.footprint() for c in self.classes.values())
+
+    # ------------------------------------------------------------------ launches
+    def _launch_aux(self, c: SizeClass, reqs, inflight):
+        first = reqs[0].slot
+        k = len(reqs)
+        sig = [r.sigma for r in reqs]
+        api.aux_solve_batched_sigma(c.b[first:first + k], sig, c.h, prec=c.prec, rtol=c.rtol,
+                                    max_refine=c.max_refine, out=c.u[first:first + k],
+                                    workspace=c.ws, stream=c.stream)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(c.stream)
+        for i, r in enumerate(reqs):
+            r.batch = k
+            if self.keep:
+                with torch.cuda.stream(c.stream):
+                    r.out = c.u[first + i].clone()
+        inflight.append((ev, reqs, c))
+
+    def _launch_step(self, c: SizeClass, r: Request, inflight):
+        bep = self.bep[r.sim]
+        rho, cc = self.state[r.sim]
+        api.dpm_step(bep, 1.0 / bep.sigma, self.chi, rho, cc, rho, cc, workspace=c.step_ws,
+                     stream=c.stream)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(c.stream)
+        r.batch = 1
+        if self.keep:
+            with torch.cuda.stream(c.stream):
+                r.out = (rho.clone(), cc.clone())
+        inflight.append((ev, [r], c))
+
+    # ------------------------------------------------------------------ the loop
+    def run(self, requests, max_inflight_per_class: int = 2):
+        """Serve `requests` (arrival times relative to the start); returns the requests with
+        their completion times filled in."""
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        pending = collections.deque(reqs)
+        inflight = []
+        done = 0
+        e0 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        e0.synchronize()
+        t0 = time.perf_counter()
+        nfl = collections.Counter()
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            # admission: first come, first served, while the head request fits
+            while pending and pending[0].arrival <= now:
+                r = pending[0]
+                c = self.classes[r.n]
+                if r.kind == "aux":
+                    if not c.free:
+                        break
+                    r.slot = c.free.popleft()
+                    c.ready.append(r)
+                else:
+                    c.steps.append(r)
+                pending.popleft()
+            # launches: continuous batching per class
+            for n, c in self.classes.items():
+                while nfl[n] < max_inflight_per_class and (c.ready or c.steps):
+                    if c.ready:
+                        batch = [c.ready.popleft()]
+                        while (c.ready and len(batch) < c.max_batch
+                               and c.ready[0].slot == batch[-1].slot + 1):
+                            batch.append(c.ready.popleft())
+                        self._launch_aux(c, batch, inflight)
+                    else:
+                        self._launch_step(c, c.steps.popleft(), inflight)
+                    nfl[n] += 1
+            # completions
+            still = []
+            for ev, rs, c in inflight:
+                if ev.query():
+                    t = e0.elapsed_time(ev) * 1e-3
+                    for r in rs:
+                        r.t_done = t
+                        if r.kind == "aux":
+                            c.free.append(r.slot)
+                    done += len(rs)
+                    nfl[c.n] -= 1
+                else:
+                    still.append((ev, rs, c))
+            inflight = still
+            if not inflight and pending and pending[0].arrival > now:
+                time.sleep(min(1e-4, pending[0].arrival - now))
+        torch.cuda.synchronize()
+        return reqs
+
+
+def build_requests(sim_n, sim_sigma, sim_is_step, req_sim, req_sigma, req_arrival):
+    """Simulations and requests from plain arrays: per simulation its grid size, sigma and
+    whether it advances DPM steps; per request its simulation, sigma and arrival time (s).
+    A step request takes its simulation's sigma."""
+    sims = [Simulation(i, int(sim_n[i]), float(sim_sigma[i]), "step" if sim_is_step[i] else "aux")
+            for i in range(len(sim_n))]
+    reqs = []
+    for k in range(len(req_sim)):
+        s = sims[int(req_sim[k])]
+        sg = s.sigma if s.kind == "step" else float(req_sigma[k])
+        reqs.append(Request(k, s.sid, s.kind, s.n, sg, float(req_arrival[k])))
+    return sims, reqs
+
+
+def summarize(reqs, makespan: float | None = None):
+    lat = np.array([r.latency for r in reqs]) * 1e3
+    t_end = max(r.t_done for r in reqs)
+    t_beg = min(r.arrival for r in reqs)
+    span = makespan if makespan is not None else t_end - t_beg
+    solves = sum(1 if r.kind == "aux" else 4 for r in reqs)
+    per_n = {}
+    for n in sorted({r.n for r in reqs}):
+        l = np.array([r.latency for r in reqs if r.n == n]) * 1e3
+        per_n[str(n)] = {"count": int(l.size), "p50_ms": float(np.percentile(l, 50)),
+                         "p99_ms": float(np.percentile(l, 99))}
+    return {"requests": len(reqs), "requests_per_s": len(reqs) / span,
+            "solves_per_s": solves / span, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_batch": float(np.mean([r.batch for r in reqs])),
+            "per_n": per_n}

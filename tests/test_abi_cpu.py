@@ -55,3 +55,13 @@ def test_host_validation_without_device():
     assert nb.value >= 255**3 * 4
     # null pointers are rejected before any launch
     assert lib.aux_solve(C.byref(g), None, None, C.byref(o), None, None) == _lib.DPM_EINVAL
+    # misaligned volumes and bad per-right-hand-side sigmas are rejected before any launch
+    fake = C.c_void_p(0x10000)
+    odd = C.c_void_p(0x10004)
+    assert lib.aux_solve(C.byref(g), odd, fake, C.byref(o), None, None) == _lib.DPM_EINVAL
+    assert "aligned" in lib.dpm_last_error().decode()
+    for bad_sig in ([1.0, -1.0], [float("nan"), 1.0], [1.0, float("inf")]):
+        sg = (C.c_double * 2)(*bad_sig)
+        assert lib.aux_solve_batched_sigma(C.byref(g), 2, sg, fake, C.c_void_p(0x90000000),
+                                           C.byref(o), None, None) == _lib.DPM_EINVAL
+        assert "sigma" in lib.dpm_last_error().decode()
