@@ -7,6 +7,12 @@ by aux_solve_batched to a relative max-norm error of 1e-10.  Paths timed: FP64 t
 FP32 transforms with FP64 residual refinement.  `value` is the solves/s of the fastest path
 whose error, checked against the CPU FP64 oracle on a sampled right-hand side, meets 1e-10.
 
+Serving (the "serving" object): a continuous-batching server over 64 simulations of mixed grid
+sizes; a closed-loop run gives the saturation rate and an open-loop run with Poisson arrivals
+at 0.7x that rate gives p50/p99 request latency.
+
+Time loop (the "pks_time_loop" object): 200 graph-replayed DPM steps on an ellipsoid at 127^3.
+
 Prints one JSON line on stdout (everything else goes to stderr).
 """
 from __future__ import annotations
@@ -31,6 +37,92 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def run_serving(args, dev):
+    """Continuous batching over a mixed request stream: a closed-loop run (every request
+    queued at t = 0) measures the saturation rate, then Poisson arrivals at 0.7x that rate give
+    the latency percentiles."""
+    import torch
+    import dpm_inputs as inp
+    from paper_1811_03557_amd import serve
+
+    def one(closed, qps, nreq, seed):
+        arrays = inp.serving_workload(n_sims=args.serve_sims, n_requests=nreq, qps=qps,
+                                      seed=seed, closed_loop=closed)
+        sims, reqs = serve.build_requests(*arrays)
+        srv = serve.Server(sims, device=dev, prec="fp64", rtol=args.rtol)
+        srv.run(reqs[: min(64, nreq)])        # warm-up: plans, allocator, first launches
+        sims, reqs = serve.build_requests(*arrays)
+        t = time.perf_counter()
+        out = srv.run(reqs)
+        wall = time.perf_counter() - t
+        summ = serve.summarize(out)
+        summ["wall_s"] = wall
+        summ["hbm_footprint_gb"] = srv.footprint() / 1e9
+        del srv
+        torch.cuda.synchronize()
+        return summ
+
+    sat = one(True, 0.0, args.serve_requests, 11)
+    log(f"[bench] serving closed loop: {sat['requests_per_s']:.1f} req/s, "
+        f"{sat['solves_per_s']:.1f} solves/s, mean batch {sat['mean_batch']:.2f}")
+    qps = 0.7 * sat["requests_per_s"]
+    opn = one(False, qps, args.serve_requests, 12)
+    log(f"[bench] serving open loop at {qps:.1f} req/s: p50 {opn['p50_ms']:.2f} ms, "
+        f"p99 {opn['p99_ms']:.2f} ms, {opn['requests_per_s']:.1f} req/s")
+    return {"workload": f"{args.serve_sims} simulations, N uniform over 31/63/127/255, sigma "
+                        f"log-uniform [1, 1e4]; half advance DPM steps (4 solves each), half "
+                        f"issue aux solves with their own sigma; {args.serve_requests} requests",
+            "saturation_requests_per_s": round(sat["requests_per_s"], 1),
+            "saturation_solves_per_s": round(sat["solves_per_s"], 1),
+            "offered_requests_per_s": round(qps, 1),
+            "requests_per_s": round(opn["requests_per_s"], 1),
+            "solves_per_s": round(opn["solves_per_s"], 1),
+            "p50_ms": round(opn["p50_ms"], 3), "p99_ms": round(opn["p99_ms"], 3),
+            "mean_batch": round(opn["mean_batch"], 2), "per_n": opn["per_n"],
+            "hbm_footprint_gb": round(opn["hbm_footprint_gb"], 2)}
+
+
+def run_pks(args, dev):
+    """Time loop of the chemotaxis system: ellipsoid (1, 0.8, 0.6) in the cube, N = 127,
+    dt = h/4, chi = 1, Test A initial data, l <= 4 with beta = 1 (50 densities); each step is
+    one replay of the captured dpm_step (4 aux solves).  Returns steps/s per precision."""
+    import torch
+    from paper_1811_03557_amd import api
+    n = args.pks_n
+    h = 3.0 / (n + 1)
+    x0 = -1.5 + h
+    dt = h / 4
+    geo = api.geometry("ellipsoid", axes=(1.0, 0.8, 0.6))
+    m = api.classify(n, h, x0, geo, device=dev)
+    idx, _ = api.gamma_points(m, h, x0)
+    B, _ = api.basis(n, h, x0, geo, idx, 4, 1)
+    out = {"workload": f"ellipsoid (1, 0.8, 0.6), N = {n}, dt = h/4, chi = 1, Test A data, "
+                       f"50 densities, {args.pks_steps} steps, one graph replay per step"}
+    for prec in ("fp32", "fp64"):
+        bep = api.build_boundary_matrix(m, B, n, h, 1.0 / dt, x0, prec=prec)
+        rho = api.gauss_state(bep, geo, 1000.0, 100.0)
+        c = api.gauss_state(bep, geo, 500.0, 50.0)
+        st = api.Stepper(bep, dt, 1.0, rho, c, prec=prec)
+        st.run(2)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        st.run(args.pks_steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.pks_steps
+        bad = st.first_nonfinite()
+        out[prec] = {"steps_per_s": round(1e3 / ms, 2), "ms_per_step": round(ms, 4),
+                     "aux_solves_per_s": round(4e3 / ms, 1),
+                     "first_nonfinite_step": bad,
+                     "alg_hbm_frac": round(32 * n**3 / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 5)}
+        log(f"[bench] pks {prec}: {ms:.3f} ms/step, first non-finite step {bad}")
+        st.close()
+        bep.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,6 +135,11 @@ def main():
     ap.add_argument("--paths", default="fp64,fp32_ir,bf16x3_ir")
     ap.add_argument("--cpu-sample", type=int, default=3, help="oracle solves timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=600,
+                    help="requests of the serving run (0 = skip)")
+    ap.add_argument("--serve-sims", type=int, default=64)
+    ap.add_argument("--pks-steps", type=int, default=200, help="time-loop steps (0 = skip)")
+    ap.add_argument("--pks-n", type=int, default=127)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -133,6 +230,11 @@ def main():
                          f"dense FP64 DST-I oracle; first solve {t_first:.2f} s excluded"}
         log(f"[bench] cpu oracle: {k / t_rest:.3f} solves/s on {cores} threads")
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = run_serving(args, dev)
+    pks = run_pks(args, dev) if args.pks_steps > 0 else None
+
     ok = {k: v for k, v in results.items() if v["rel_err_sample"] <= args.rtol}
     best_name = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else None
     best = ok[best_name] if best_name else None
@@ -170,6 +272,8 @@ def main():
                    "path": best_name},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
+        "pks_time_loop": pks,
         "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
         "alg_hbm_frac": (round(best["solves_per_s"] * 16 * vol / (HBM_PEAK_GBS * 1e9), 4)
                          if best else None),

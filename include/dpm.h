@@ -189,6 +189,26 @@ dpm_status dpm_step(const dpm_bep* bep, double dt, double chi, const double* rho
                     void* stream, dpm_info* info);
 
 /*
+ * dpm_stepper -- the time loop of the paper's Algorithm "Main Steps" (Steps 4a-7 repeated) on
+ * fixed buffers: dpm_stepper_create captures one dpm_step that updates (rho, c) in place into a
+ * HIP graph; dpm_stepper_run replays it nsteps times on `stream`.  Each replay also checks the
+ * step's outputs for non-finite values on the device; dpm_stepper_first_nonfinite returns the
+ * number (from 1, counted since create) of the first step whose output held one, or 0.
+ * rho, c: device N^3 FP64 state, updated in place by every replay; opts->workspace: at least
+ * dpm_step_workspace_size bytes.  Both must stay valid, and must not be used by other work
+ * while replays run, until dpm_stepper_destroy.  The handle keeps a pointer to bep: destroy the
+ * stepper first.  create enqueues the guard's reset on `stream`; it fails with DPM_EINVAL while
+ * sweep timing is enabled.  first_nonfinite synchronises `stream`; destroy synchronises the
+ * device.  Replays of one stepper on different streams race.
+ */
+typedef struct dpm_stepper dpm_stepper;
+dpm_status dpm_stepper_create(const dpm_bep* bep, double dt, double chi, double* rho, double* c,
+                              const dpm_opts* opts, void* stream, dpm_stepper** out);
+dpm_status dpm_stepper_run(dpm_stepper* st, int32_t nsteps, void* stream);
+dpm_status dpm_stepper_first_nonfinite(const dpm_stepper* st, void* stream, int32_t* step);
+void dpm_stepper_destroy(dpm_stepper* st);
+
+/*
  * dpm_gauss_state -- initial data amp * exp(-rate |x - center|^2) (paper Sec. 4, Tests A and B)
  * at the nodes of M+ and, on gamma, at the projection of each node onto Gamma (paper eq
  * boundary_approx); zero elsewhere.  out: device N^3 FP64.

@@ -56,6 +56,10 @@ SIGNATURES = {
     "dpm_bep_solve": (C.c_int, [_P, _I, _P, _P, _P]),
     "dpm_step_workspace_size": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
     "dpm_step": (C.c_int, [_P, _D, _D, _P, _P, _P, _P, C.POINTER(Opts), _P, C.POINTER(Info)]),
+    "dpm_stepper_create": (C.c_int, [_P, _D, _D, _P, _P, C.POINTER(Opts), _P, C.POINTER(_P)]),
+    "dpm_stepper_run": (C.c_int, [_P, C.c_int32, _P]),
+    "dpm_stepper_first_nonfinite": (C.c_int, [_P, _P, C.POINTER(C.c_int32)]),
+    "dpm_stepper_destroy": (None, [_P]),
     "dpm_gauss_state": (C.c_int, [_P, C.POINTER(Geometry), _D, _D, C.POINTER(_D), _P, _P]),
     "dpm_bep_destroy": (None, [_P]),
     "dpm_last_error": (C.c_char_p, []),

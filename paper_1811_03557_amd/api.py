@@ -265,6 +265,50 @@ def dpm_step(bep: BEP, dt: float, chi: float, rho: torch.Tensor, c: torch.Tensor
     return rho_out, c_out
 
 
+class Stepper:
+    """Graph-captured time loop: dpm_step on (rho, c) in place, replayed on demand."""
+
+    def __init__(self, bep: BEP, dt: float, chi: float, rho: torch.Tensor, c: torch.Tensor,
+                 prec: str = "fp64", rtol: float = 1e-10, max_refine: int = 0,
+                 workspace: torch.Tensor | None = None, stream=None):
+        lib = L.load()
+        o = opts(prec, True, rtol, max_refine)
+        nbytes = step_workspace_size(bep, o)
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=rho.device)
+        o.workspace = C.c_void_p(workspace.data_ptr())
+        o.workspace_bytes = workspace.numel()
+        # the handle keeps raw pointers: hold the tensors for its lifetime
+        self.bep, self.rho, self.c, self.workspace = bep, rho, c, workspace
+        out = C.c_void_p(0)
+        L.check(lib.dpm_stepper_create(C.c_void_p(bep.ptr), float(dt), float(chi),
+                                       C.c_void_p(_dev(rho, "rho", torch.float64)),
+                                       C.c_void_p(_dev(c, "c", torch.float64)), C.byref(o),
+                                       C.c_void_p(_stream(stream)), C.byref(out)))
+        self.ptr = out.value
+
+    def run(self, nsteps: int, stream=None) -> None:
+        L.check(L.load().dpm_stepper_run(C.c_void_p(self.ptr), int(nsteps),
+                                         C.c_void_p(_stream(stream))))
+
+    def first_nonfinite(self, stream=None) -> int:
+        v = C.c_int32(0)
+        L.check(L.load().dpm_stepper_first_nonfinite(C.c_void_p(self.ptr),
+                                                     C.c_void_p(_stream(stream)), C.byref(v)))
+        return int(v.value)
+
+    def close(self):
+        if self.ptr:
+            L.load().dpm_stepper_destroy(C.c_void_p(self.ptr))
+            self.ptr = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def gauss_state(bep: BEP, geo: L.Geometry, amp: float, rate: float, center=(0.0, 0.0, 0.0),
                 stream=None) -> torch.Tensor:
     """amp exp(-rate |x - center|^2) on M+, and at the projection onto Gamma on gamma."""

@@ -17,6 +17,11 @@ dpm_status step_workspace_impl(const dpm_bep* b, const dpm_opts& o, size_t* byte
 dpm_status step_impl(const dpm_bep* b, double dt, double chi, const double* rho_in,
                      const double* c_in, double* rho_out, double* c_out, const dpm_opts& o,
                      hipStream_t s, dpm_info* info);
+dpm_status stepper_create_impl(const dpm_bep* b, double dt, double chi, double* rho, double* c,
+                               const dpm_opts& o, hipStream_t s, dpm_stepper** out);
+dpm_status stepper_run_impl(dpm_stepper* p, int nsteps, hipStream_t s);
+dpm_status stepper_first_nonfinite_impl(const dpm_stepper* p, hipStream_t s, int32_t* step);
+void stepper_destroy_impl(dpm_stepper* p);
 dpm_status gauss_state_impl(const dpm_bep* b, const dpm_geometry& geo, double amp, double rate,
                             const double* c3, double* out, hipStream_t s);
 }  // namespace dpm
@@ -196,6 +201,41 @@ dpm_status dpm_step(const dpm_bep* bep, double dt, double chi, const double* rho
   return step_impl(bep, dt, chi, rho_in, c_in, rho_out, c_out, *opts,
                    static_cast<hipStream_t>(stream), info);
 }
+
+dpm_status dpm_stepper_create(const dpm_bep* bep, double dt, double chi, double* rho, double* c,
+                              const dpm_opts* opts, void* stream, dpm_stepper** out) {
+  clear_error();
+  if (!bep || !rho || !c || !out) { set_error("NULL argument"); return DPM_EINVAL; }
+  *out = nullptr;
+  DPM_TRY(validate_opts(bep->grid, opts));
+  if (!opts->io_fp64) { set_error("dpm_stepper_create needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
+  if (!aligned_to(rho, 8) || !aligned_to(c, 8) || !aligned16(opts->workspace)) {
+    set_error("rho and c must be 8-byte aligned, the workspace 16-byte aligned");
+    return DPM_EINVAL;
+  }
+  if (rho == c) { set_error("rho and c must be different buffers"); return DPM_EINVAL; }
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(chi)) { set_error("dt must be finite and > 0, chi finite"); return DPM_EINVAL; }
+  if (std::fabs(bep->grid.sigma * dt - 1.0) > 1e-12) {
+    set_error("the handle was built with sigma = %g but 1/dt = %g", bep->grid.sigma, 1.0 / dt);
+    return DPM_EINVAL;
+  }
+  return stepper_create_impl(bep, dt, chi, rho, c, *opts, static_cast<hipStream_t>(stream), out);
+}
+
+dpm_status dpm_stepper_run(dpm_stepper* st, int32_t nsteps, void* stream) {
+  clear_error();
+  if (!st) { set_error("stepper is NULL"); return DPM_EINVAL; }
+  if (nsteps < 0) { set_error("nsteps must be >= 0"); return DPM_EINVAL; }
+  return stepper_run_impl(st, nsteps, static_cast<hipStream_t>(stream));
+}
+
+dpm_status dpm_stepper_first_nonfinite(const dpm_stepper* st, void* stream, int32_t* step) {
+  clear_error();
+  if (!st || !step) { set_error("stepper or step is NULL"); return DPM_EINVAL; }
+  return stepper_first_nonfinite_impl(st, static_cast<hipStream_t>(stream), step);
+}
+
+void dpm_stepper_destroy(dpm_stepper* st) { stepper_destroy_impl(st); }
 
 dpm_status dpm_gauss_state(const dpm_bep* bep, const dpm_geometry* geom, double amp,
                            double rate, const double center[3], double* out, void* stream) {

@@ -19,6 +19,15 @@ struct dpm_bep {
   double rdiag_min = 0.0, rdiag_max = 0.0;
 };
 
+// A captured time step (dpm_step in place on fixed buffers) replayed as a HIP graph.
+struct dpm_stepper {
+  const dpm_bep* bep = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int* guard = nullptr;  // inside the caller's workspace: step counter, first non-finite step
+  long long steps_run = 0;
+};
+
 namespace dpm {
 
 void fill_zero(double* p, long long n, hipStream_t s);

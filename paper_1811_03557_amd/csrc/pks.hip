@@ -11,6 +11,7 @@
 //     (Green's formula as one solve, by linearity of the AP), restricted to N+.
 // Readings: the limited slope is zero at gamma_ex nodes; a face gradient of exactly 0 takes the
 // right (downstream-cell) state, as the scheme is written.
+#include <climits>
 #include <cmath>
 
 #include "bep.h"
@@ -80,13 +81,30 @@ __global__ void k_density(const double* __restrict__ basis, const double* __rest
   ug[(long long)r * ng + i] = acc;
 }
 
+// Restriction to N+; with a guard, a non-finite output records the current step number
+// (guard[0]) into guard[1] by atomic minimum.
 __global__ void k_restrict(const double* __restrict__ U, const uint8_t* __restrict__ np,
-                           long long vsz, double* __restrict__ o0, double* __restrict__ o1) {
+                           long long vsz, double* __restrict__ o0, double* __restrict__ o1,
+                           int* __restrict__ guard) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= vsz) return;
   const bool in = np[i] != 0;
-  o0[i] = in ? U[i] : 0.0;
-  o1[i] = in ? U[vsz + i] : 0.0;
+  const double v0 = in ? U[i] : 0.0, v1 = in ? U[vsz + i] : 0.0;
+  o0[i] = v0;
+  o1[i] = v1;
+  if (guard != nullptr && !(isfinite(v0) && isfinite(v1))) atomicMin(&guard[1], guard[0]);
+}
+
+// guard[0] = step number (from 1), guard[1] = first step with a non-finite output
+__global__ void k_guard_init(int* guard) {
+  if (threadIdx.x == 0) {
+    guard[0] = 1;
+    guard[1] = INT_MAX;
+  }
+}
+
+__global__ void k_guard_tick(int* guard) {
+  if (threadIdx.x == 0) guard[0] += 1;
 }
 
 // amp exp(-rate |x - x_c|^2) at M+ nodes; phase 1 overwrites gamma nodes with the value at
@@ -119,7 +137,7 @@ __global__ void k_gauss_gamma(const int32_t* __restrict__ idx, int ng, int n, do
 unsigned grid1(long long n) { return (unsigned)((n + kB - 1) / kB); }
 
 struct StepLayout {
-  size_t b2, X, w, g, y, C, ug, solve_ws, total;
+  size_t b2, X, w, g, y, C, ug, guard, solve_ws, total;
 };
 
 StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
@@ -133,6 +151,7 @@ StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
   L.y = o; o = align_up(o + 2 * sizeof(double) * b->n_in, 256);
   L.C = o; o = align_up(o + 2 * sizeof(double) * b->n_basis, 256);
   L.ug = o; o = align_up(o + 2 * sizeof(double) * b->n_gamma, 256);
+  L.guard = o; o = align_up(o + 2 * sizeof(int), 256);
   L.solve_ws = o; o = align_up(o + solve_ws, 256);
   L.total = o;
   return L;
@@ -149,9 +168,12 @@ dpm_status step_workspace_impl(const dpm_bep* b, const dpm_opts& o, size_t* byte
   return DPM_OK;
 }
 
-dpm_status step_impl(const dpm_bep* b, double dt, double chi, const double* rho_in,
-                     const double* c_in, double* rho_out, double* c_out, const dpm_opts& o,
-                     hipStream_t s, dpm_info* info) {
+namespace {
+
+// Steps 4a-7 enqueued on s; no host synchronisation, so the sequence can be captured.
+dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* rho_in,
+                        const double* c_in, double* rho_out, double* c_out, const dpm_opts& o,
+                        hipStream_t s, dpm_info* info, bool guard) {
   const dpm_grid& g = b->grid;
   size_t sw = 0;
   dpm_opts so = o;
@@ -170,6 +192,7 @@ dpm_status step_impl(const dpm_bep* b, double dt, double chi, const double* rho_
   double* yv = reinterpret_cast<double*>(ws + L.y);
   double* C = reinterpret_cast<double*>(ws + L.C);
   double* ug = reinterpret_cast<double*>(ws + L.ug);
+  int* gd = guard ? reinterpret_cast<int*>(ws + L.guard) : nullptr;
   so.workspace = ws + L.solve_ws;
   so.workspace_bytes = sw;
   const long long vsz = (long long)g.n * g.n * g.n;
@@ -178,7 +201,6 @@ dpm_status step_impl(const dpm_bep* b, double dt, double chi, const double* rho_
   hipLaunchKernelGGL(k_pks_rhs, dim3(grid1(vsz)), dim3(kB), 0, s, rho_in, c_in, b->m_plus, g.n,
                      g.h, dt, chi, sigma, b2);
   DPM_TRY_HIP(hipGetLastError());
-  dpm_info i1{};
   DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, nullptr));
   // Step 5: Tr_gamma_in G f, least squares, densities
   gather(X, vsz, b->idx_in, b->n_in, 2, gv, s);
@@ -190,14 +212,103 @@ dpm_status step_impl(const dpm_bep* b, double dt, double chi, const double* rho_
   scatter_density(ug, 0, 2, b->n_gamma, b->idx, w, vsz, s);
   minus_operator(w, b->m_plus, b2, b2, g.n, sigma, 1.0 / (g.h * g.h), 2, s);
   DPM_TRY_HIP(hipGetLastError());
-  DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, info ? &i1 : nullptr));
-  hipLaunchKernelGGL(k_restrict, dim3(grid1(vsz)), dim3(kB), 0, s, X, b->n_plus, vsz, rho_out, c_out);
+  DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, info));
+  hipLaunchKernelGGL(k_restrict, dim3(grid1(vsz)), dim3(kB), 0, s, X, b->n_plus, vsz, rho_out,
+                     c_out, gd);
+  if (gd != nullptr) hipLaunchKernelGGL(k_guard_tick, dim3(1), dim3(64), 0, s, gd);
   DPM_TRY_HIP(hipGetLastError());
-  if (info) {
-    DPM_TRY_HIP(hipStreamSynchronize(s));
-    *info = i1;
-  }
   return DPM_OK;
+}
+
+}  // namespace
+
+dpm_status step_impl(const dpm_bep* b, double dt, double chi, const double* rho_in,
+                     const double* c_in, double* rho_out, double* c_out, const dpm_opts& o,
+                     hipStream_t s, dpm_info* info) {
+  return step_enqueue(b, dt, chi, rho_in, c_in, rho_out, c_out, o, s, info, false);
+}
+
+dpm_status stepper_create_impl(const dpm_bep* b, double dt, double chi, double* rho, double* c,
+                               const dpm_opts& o, hipStream_t s, dpm_stepper** out) {
+  size_t need = 0;
+  DPM_TRY(step_workspace_impl(b, o, &need));
+  if (o.workspace == nullptr || o.workspace_bytes < need) {
+    set_error("dpm_stepper_create: workspace too small: %zu bytes given, %zu needed",
+              o.workspace_bytes, need);
+    return DPM_EINVAL;
+  }
+  size_t sw = 0;
+  dpm_opts so = o;
+  so.rhs_chunk = 0;
+  DPM_TRY(workspace_size_impl(b->grid, 2, so, &sw));
+  int* gd = reinterpret_cast<int*>(static_cast<char*>(o.workspace) + step_layout(b, sw).guard);
+  if (timing_on()) {
+    set_error("dpm_stepper_create: sweep timing is enabled; end it before capturing a step");
+    return DPM_EINVAL;
+  }
+  const Plan* pl = nullptr;
+  DPM_TRY(get_plan(b->grid.n, &pl));  // tables exist before capture: no allocation inside it
+
+  hipStream_t cs = nullptr;
+  DPM_TRY_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    set_error("dpm_stepper_create: hipStreamBeginCapture: %s", hipGetErrorString(e));
+    return DPM_EHIP;
+  }
+  const dpm_status st = step_enqueue(b, dt, chi, rho, c, rho, c, o, cs, nullptr, true);
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (st != DPM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    set_error("dpm_stepper_create: graph capture: %s", hipGetErrorString(e));
+    return DPM_EHIP;
+  }
+  hipLaunchKernelGGL(k_guard_init, dim3(1), dim3(64), 0, s, gd);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    set_error("dpm_stepper_create: %s", hipGetErrorString(e));
+    return DPM_EHIP;
+  }
+  auto* p = new dpm_stepper;
+  p->bep = b;
+  p->graph = graph;
+  p->exec = exec;
+  p->guard = gd;
+  *out = p;
+  return DPM_OK;
+}
+
+dpm_status stepper_run_impl(dpm_stepper* p, int nsteps, hipStream_t s) {
+  for (int k = 0; k < nsteps; ++k) DPM_TRY_HIP(hipGraphLaunch(p->exec, s));
+  p->steps_run += nsteps;
+  return DPM_OK;
+}
+
+dpm_status stepper_first_nonfinite_impl(const dpm_stepper* p, hipStream_t s, int32_t* step) {
+  int v = 0;
+  DPM_TRY_HIP(hipMemcpyAsync(&v, p->guard + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  DPM_TRY_HIP(hipStreamSynchronize(s));
+  *step = v == INT_MAX ? 0 : v;
+  return DPM_OK;
+}
+
+void stepper_destroy_impl(dpm_stepper* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();  // replays still in flight finish before the graph goes
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  delete p;
 }
 
 dpm_status gauss_state_impl(const dpm_bep* b, const dpm_geometry& geo, double amp, double rate,
