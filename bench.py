@@ -12,6 +12,7 @@ sizes; a closed-loop run gives the saturation rate and an open-loop run with Poi
 at 0.7x that rate gives p50/p99 request latency.
 
 Time loop (the "pks_time_loop" object): 200 graph-replayed DPM steps on an ellipsoid at 127^3.
+Boundary matrix (the "boundary_matrix" object): the 242-column build at 127^3 per precision.
 
 Prints one JSON line on stdout (everything else goes to stderr).
 """
@@ -123,6 +124,35 @@ def run_pks(args, dev):
     return out
 
 
+def run_boundary_matrix(args, dev):
+    """Step 2 of the method at 127^3: the 242-column reduced-BEP matrix of the unit sphere
+    (real Y_lm, l <= 10, beta = 1), sigma = 2/h^2, built and QR-factored by one
+    dpm_build_boundary_matrix call per precision; wall time of the whole call."""
+    import torch
+    from paper_1811_03557_amd import api
+    n = 127
+    h = 3.0 / (n + 1)
+    x0 = -1.5 + h
+    sigma = 2.0 / h**2
+    geo = api.geometry("sphere", axes=(1.0,))
+    m = api.classify(n, h, x0, geo, device=dev)
+    idx, _ = api.gamma_points(m, h, x0)
+    B, _ = api.basis(n, h, x0, geo, idx, 10, 1)
+    out = {"workload": f"unit sphere, N = {n}, sigma = 2/h^2, 242 columns (l <= 10, beta = 1), "
+                       "solves + traces + Householder QR"}
+    for name, prec, mr in (("fp32", "fp32", 0), ("fp32_ir", "fp32", 3), ("fp64", "fp64", 0)):
+        api.build_boundary_matrix(m, B, n, h, sigma, x0, prec=prec, max_refine=mr).close()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bep = api.build_boundary_matrix(m, B, n, h, sigma, x0, prec=prec, max_refine=mr)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out[name] = {"build_s": round(dt, 4), "columns_per_s": round(bep.n_basis / dt, 1)}
+        log(f"[bench] boundary matrix {name}: {dt * 1e3:.1f} ms for {bep.n_basis} columns")
+        bep.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +170,7 @@ def main():
     ap.add_argument("--serve-sims", type=int, default=64)
     ap.add_argument("--pks-steps", type=int, default=200, help="time-loop steps (0 = skip)")
     ap.add_argument("--pks-n", type=int, default=127)
+    ap.add_argument("--no-bmat", action="store_true", help="skip the boundary-matrix build")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -234,6 +265,7 @@ def main():
     if args.serve_requests > 0:
         serving = run_serving(args, dev)
     pks = run_pks(args, dev) if args.pks_steps > 0 else None
+    bmat = run_boundary_matrix(args, dev) if not args.no_bmat else None
 
     ok = {k: v for k, v in results.items() if v["rel_err_sample"] <= args.rtol}
     best_name = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else None
@@ -274,6 +306,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "pks_time_loop": pks,
+        "boundary_matrix": bmat,
         "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
         "alg_hbm_frac": (round(best["solves_per_s"] * 16 * vol / (HBM_PEAK_GBS * 1e9), 4)
                          if best else None),

@@ -99,6 +99,26 @@ def test_boundary_matrix_config1(prec, max_refine, tol):
     bep.close()
 
 
+@pytest.mark.parametrize("prec,max_refine,tol", [("fp32", 0, 1e-5), ("fp32", 3, 1e-10),
+                                                  ("fp64", 0, 1e-11)])
+def test_boundary_matrix_config2(prec, max_refine, tol):
+    """242-column reduced-BEP matrix of the unit sphere at 127^3 (l <= 10, beta = 1),
+    sigma = 2/h^2; sampled columns against the oracle's, relative max-norm per column."""
+    dev = need_gpu()
+    say(f"boundary matrix 127^3 242 columns {prec} refine {max_refine}")
+    n = 127
+    h, _ = inp.grid(n)
+    sigma = 2.0 / h**2
+    h, x0, mp, ps, Bref, bep, A, _ = _bep_case(n, "sphere", 10, sigma, dev, prec, max_refine)
+    assert (bep.n_gamma_in, bep.n_basis) == (ps.n_gamma_in, 242)
+    cols = [0, 1, 37, 120, 121, 200, 241]
+    Aref = odpm.bep_matrix(Bref[cols], ps, sigma, h)
+    for j, nu in enumerate(cols):
+        e = np.max(np.abs(A[:, nu] - Aref[:, j])) / np.max(np.abs(Aref[:, j]))
+        assert e < tol, (nu, e)
+    bep.close()
+
+
 def test_least_squares_against_lapack():
     import torch
     from paper_1811_03557_amd import api
