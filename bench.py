@@ -34,6 +34,29 @@ HBM_PEAK_GBS = 8000.0
 KIND_NAMES = ["x_first", "y", "z_fused", "x_last", "x_residual", "x_update"]
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dst_sweeps_fp64_aux255_64rhs_hbm_traffic.txt")
+KERNEL_SOURCES = ["paper_1811_03557_amd/csrc/dst_fft.hip", "paper_1811_03557_amd/csrc/common.h"]
+
+
+def counted_traffic(kind, path_name, n, rhs_per_launch):
+    """HBM bytes per launch of a sweep kind from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy of known size), or None when the summary does not cover
+    this configuration or the kernel source has changed since the counters were taken."""
+    import hashlib
+    if path_name != "fp64" or n != 255 or rhs_per_launch != 1 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
+                                     for f in KERNEL_SOURCES)).hexdigest()
+    taken, val = None, None
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("kernel source sha256"):
+            taken = line.rsplit(":", 1)[1].strip()
+        parts = line.split()
+        if len(parts) == 3 and parts[0] == "traffic_bytes_per_launch" and parts[1] == kind:
+            val = float(parts[2])
+    return val if (taken == digest and val is not None) else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -163,7 +186,10 @@ def main():
     ap.add_argument("--sigma", type=float, default=1.0)
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--paths", default="fp64,fp32_ir,bf16x3_ir")
-    ap.add_argument("--cpu-sample", type=int, default=3, help="oracle solves timed for cpu_baseline")
+    ap.add_argument("--cpu-sample", type=int, default=3,
+                    help="right-hand sides copied to the host for the oracle")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall time of the oracle sample timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="requests of the serving run (0 = skip)")
@@ -171,6 +197,9 @@ def main():
     ap.add_argument("--pks-steps", type=int, default=200, help="time-loop steps (0 = skip)")
     ap.add_argument("--pks-n", type=int, default=127)
     ap.add_argument("--no-bmat", action="store_true", help="skip the boundary-matrix build")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run 3 plain device copies of this many bytes (calibrates the "
+                         "HBM traffic counters against a kernel of known traffic)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -189,6 +218,14 @@ def main():
     b = inp.rhs_normal_device(n, nrhs, seed=0, device=dev)
     u = torch.empty_like(b)
     vol = n ** 3
+
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     path_cfg = {
         "fp64": dict(prec="fp64", max_refine=0, dtype="f64"),
@@ -246,19 +283,22 @@ def main():
         r["rel_err_sample"] = oaux.rel_err_inf(r.pop("u0"), ref0)
         log(f"[bench] {name}: rel err vs oracle (rhs 0) = {r['rel_err_sample']:.3e}")
     if not args.no_cpu and args.cpu_sample > 1:
+        # bounded sample: oracle solves of right-hand sides 1.. (cycled) for about cpu_seconds
         t = time.perf_counter()
-        for i in range(1, b_host.shape[0]):
-            oaux.aux_solve(b_host[i], args.sigma, h)
+        k = 0
+        while k < 3 or (time.perf_counter() - t < args.cpu_seconds and k < 400):
+            oaux.aux_solve(b_host[1 + k % (b_host.shape[0] - 1)], args.sigma, h)
+            k += 1
         t_rest = time.perf_counter() - t
-        k = b_host.shape[0] - 1
         try:
             from threadpoolctl import threadpool_info
             cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
         except Exception:
             cores = os.cpu_count()
         cpu = {"value": k / t_rest, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-               "sample": f"{k} right-hand sides of the same workload (255^3, sigma {args.sigma}), "
-                         f"dense FP64 DST-I oracle; first solve {t_first:.2f} s excluded"}
+               "sample": f"{k} solves ({t_rest:.1f} s) of right-hand sides 1-{b_host.shape[0] - 1} "
+                         f"of the same workload (255^3, sigma {args.sigma}), dense FP64 DST-I "
+                         f"oracle; the first solve ({t_first:.2f} s) excluded"}
         log(f"[bench] cpu oracle: {k / t_rest:.3f} solves/s on {cores} threads")
 
     serving = None
@@ -279,11 +319,14 @@ def main():
         rb = 8 if best_name == "fp64" else 4
         in_b = 8 if (dom in ("x_first", "x_residual") and rb == 4) else rb
         out_b = 8 if (dom in ("x_last", "x_update") and rb == 4) else rb
-        per_launch_rhs = nrhs / kern[dom]["launches_per_step"]
+        # every sweep launch covers one chunk of right-hand sides; the first x sweep runs once
+        # per chunk, so its launch count gives the chunk (the y kind runs twice per solve)
+        per_launch_rhs = nrhs / kern["x_first"]["launches_per_step"]
         alg_bytes = per_launch_rhs * vol * (in_b + out_b)
         achieved = alg_bytes / (kern[dom]["mean_ms"] * 1e-3) / 1e9
+        traffic = counted_traffic(dom, best_name, n, per_launch_rhs)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "bytes_per_launch": alg_bytes, "mean_launch_ms": kern[dom]["mean_ms"]}
 
     line = {
