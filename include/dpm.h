@@ -74,6 +74,10 @@ typedef struct {
 dpm_status dpm_workspace_size(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts,
                               size_t* bytes);
 
+/* Right-hand sides per sweep launch that aux_solve_batched uses for nrhs right-hand sides with
+ * these options (opts->rhs_chunk if set, else the library's choice for the grid size). */
+dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, int32_t* chunk);
+
 /* Builds the per-(device, n) tables (sine/twiddle and eigenvalue tables) ahead of time.  The
  * first solve of a size does this by itself; call it first when that solve is captured into a
  * HIP graph, since building uploads with synchronous copies. */
@@ -219,13 +223,16 @@ dpm_status dpm_gauss_state(const dpm_bep* bep, const dpm_geometry* geom, double 
 void dpm_bep_destroy(dpm_bep* bep);
 
 /*
- * Measurement support (not part of the method): while enabled, every sweep kernel launched by
- * the solves is bracketed by hipEvents on the stream it runs on.  dpm_timing_end synchronises
- * the events and returns, per sweep kind, the number of launches and their mean duration in ms.
- * Kinds: 0 first x sweep, 1 y sweep, 2 fused z sweep, 3 last x sweep, 4 residual x sweep,
- * 5 update x sweep.  At most max_launches launches are recorded.  Process-wide, not thread safe.
+ * Measurement support (not part of the method): while enabled, the sweep kernels launched for a
+ * sampled chunk of right-hand sides are bracketed by hipEvents on the stream they run on.  A
+ * chunk [rhs0, rhs0 + nb) of a solve call is sampled when it holds an index that is a multiple of
+ * rhs_stride (1 = every launch; a larger stride keeps the events' own cost out of the timed
+ * work).  dpm_timing_end synchronises the events and returns, per sweep kind, the number of timed
+ * launches and their mean duration in ms.  Kinds: 0 first x sweep, 1 y sweep, 2 fused z sweep,
+ * 3 last x sweep, 4 residual x sweep, 5 update x sweep.  At most max_launches launches are
+ * recorded.  Process-wide, not thread safe.
  */
-dpm_status dpm_timing_begin(int32_t max_launches);
+dpm_status dpm_timing_begin(int32_t max_launches, int32_t rhs_stride);
 dpm_status dpm_timing_end(int32_t nkinds, int32_t* counts, double* mean_ms);
 
 /* Thread-local text of the last error (empty string when none). */

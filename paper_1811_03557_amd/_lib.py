@@ -63,7 +63,8 @@ SIGNATURES = {
     "dpm_gauss_state": (C.c_int, [_P, C.POINTER(Geometry), _D, _D, C.POINTER(_D), _P, _P]),
     "dpm_bep_destroy": (None, [_P]),
     "dpm_last_error": (C.c_char_p, []),
-    "dpm_timing_begin": (C.c_int, [_I]),
+    "dpm_timing_begin": (C.c_int, [_I, _I]),
+    "dpm_rhs_chunk": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(Opts), C.POINTER(_I)]),
     "dpm_timing_end": (C.c_int, [_I, C.POINTER(_I), C.POINTER(_D)]),
 }
 

@@ -47,6 +47,13 @@ def workspace_size(g: L.Grid, nrhs: int, o: L.Opts) -> int:
     return int(nb.value)
 
 
+def rhs_chunk(g: L.Grid, nrhs: int, o: L.Opts) -> int:
+    """Right-hand sides per sweep launch for a solve of nrhs right-hand sides."""
+    c = C.c_int32(0)
+    L.check(L.load().dpm_rhs_chunk(C.byref(g), int(nrhs), C.byref(o), C.byref(c)))
+    return int(c.value)
+
+
 def prepare(n: int) -> None:
     L.check(L.load().dpm_prepare(int(n)))
 

@@ -55,6 +55,16 @@ dpm_status dpm_workspace_size(const dpm_grid* grid, int32_t nrhs, const dpm_opts
   return workspace_size_impl(*grid, nrhs, *opts, bytes);
 }
 
+dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, int32_t* chunk) {
+  clear_error();
+  DPM_TRY(validate_grid(grid));
+  DPM_TRY(validate_opts(*grid, opts));
+  if (nrhs <= 0) { set_error("nrhs must be > 0"); return DPM_EINVAL; }
+  if (!chunk) { set_error("chunk is NULL"); return DPM_EINVAL; }
+  *chunk = rhs_chunk_of(*grid, nrhs, *opts);
+  return DPM_OK;
+}
+
 dpm_status aux_solve_batched(const dpm_grid* grid, int32_t nrhs, const void* b, void* u,
                              const dpm_opts* opts, void* stream, dpm_info* info) {
   clear_error();

@@ -87,6 +87,11 @@ int real_bytes_of(const dpm_opts& o) { return o.prec == DPM_FP64 ? 8 : 4; }
 
 size_t flags_bytes(int nrhs) { return flag_layout(nrhs).total; }
 
+int rhs_chunk_of(const dpm_grid& g, int nrhs, const dpm_opts& o) {
+  return o.rhs_chunk > 0 ? (o.rhs_chunk < nrhs ? o.rhs_chunk : nrhs)
+                         : default_chunk(g.n, nrhs, real_bytes_of(o), needs_ws(o));
+}
+
 dpm_status validate_grid(const dpm_grid* g) {
   if (!g) { set_error("grid is NULL"); return DPM_EINVAL; }
   if (g->n < 1 || g->n > 1023) { set_error("n = %d out of range [1, 1023]", g->n); return DPM_EINVAL; }
@@ -163,7 +168,7 @@ static dpm_status five_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind 
     const int kind = ax == AX_Y ? SW_Y : ax == AX_Z ? SW_Z
                    : ik == IN_RESID ? SW_X_RESID : ok == OUT_UPD ? SW_X_UPD
                    : first ? SW_X_FIRST : SW_X_LAST;
-    const bool tm = timing_on();
+    const bool tm = timing_on(rhs0, nb);
     if (tm) timing_before(s);
     dpm_status st = bf16 ? launch_bf16x3_pass(g.n, ax, z, ik, ok, q, pl, nb, s)
                          : launch_dst_pass(rb, g.n, ax, z, ik, ok, q, nb, s);

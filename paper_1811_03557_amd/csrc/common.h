@@ -90,7 +90,8 @@ dpm_status launch_bf16x3_pass(int n, AxisKind ax, bool zpass, InKind in, OutKind
 // Sweep kinds reported by dpm_timing_end.
 enum SweepKind { SW_X_FIRST = 0, SW_Y = 1, SW_Z = 2, SW_X_LAST = 3, SW_X_RESID = 4, SW_X_UPD = 5,
                  SW_KINDS = 6 };
-bool timing_on();
+bool timing_enabled();
+bool timing_on(int rhs0, int nb);
 void timing_before(hipStream_t s);
 void timing_after(hipStream_t s, int kind);
 
@@ -108,6 +109,8 @@ size_t flags_bytes(int nrhs);
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u,
                           const dpm_opts& o, hipStream_t s, dpm_info* info,
                           const double* sigma_host = nullptr);
+// Right-hand sides per sweep launch that a solve of nrhs right-hand sides uses.
+int rhs_chunk_of(const dpm_grid& g, int nrhs, const dpm_opts& o);
 dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes);
 dpm_status validate_grid(const dpm_grid* g);
 dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o);

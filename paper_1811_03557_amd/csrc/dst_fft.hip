@@ -278,6 +278,29 @@ __device__ __forceinline__ void dst1_line(T* line, int g, const T* tab) {
 
 
 
+// Loads and stores at a uniform base plus a 32-bit byte offset (the global saddr form).  The
+// base is passed through readfirstlane so that it stays in scalar registers: the compiler then
+// moves a step's base with scalar adds instead of a 64-bit vector add per element.  Callers pass
+// pointers that are uniform across the wavefront.
+template <typename T>
+__device__ __forceinline__ T* sbase(T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+  return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
+}
+#define DPM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T ld(const T* base, unsigned byte_off) {
+  const DPM_GLOBAL char* b = (const DPM_GLOBAL char*)sbase(base);
+  return *(const DPM_GLOBAL T*)(b + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, unsigned byte_off, T v) {
+  DPM_GLOBAL char* b = (DPM_GLOBAL char*)sbase(base);
+  *(DPM_GLOBAL T*)(b + byte_off) = v;
+}
+
 // blockIdx -> logical tile such that consecutive logical tiles run on the same XCD (blocks are
 // dispatched round-robin over the 8 XCDs), so neighbouring tiles that share cache lines and
 // stencil rows share an L2.
@@ -327,22 +350,83 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
   }
 
   // ------------------------------------------------------------------ load the tile
-  // Each thread owns elements e = tid + i*kBlock of the tile; the loads of a chunk are all
-  // issued before the first use, so a block has CH loads per thread in flight.
+  // Thread -> (line w of the tile, first element j0); its i-th element is j = j0 + JPI*i.  Along
+  // x the JPI lanes of a line read consecutive elements; along y and z the W lanes of an
+  // element index read W adjacent lines.  Either way a wavefront reads runs of >= 128 bytes.
+  // Each thread forms one 32-bit byte offset; the step i moves a uniform base pointer, so the
+  // loop carries no per-element address arithmetic.  Only steps that can reach j >= N clamp.
+  constexpr int JPI = kBlock / W;                       // element stride between steps
+  constexpr bool LINEMAJOR = AX == AX_X;
+  constexpr bool STEPMAP = !LINEMAJOR || JPI * (int)sizeof(T) >= 128;
+  constexpr int NSTEP = (N + JPI - 1) / JPI;            // steps per thread
+  constexpr int IFULL = N / JPI;                        // steps with every j < N
+  const int w = LINEMAJOR ? tid / JPI : tid % W;
+  const int j0 = LINEMAJOR ? tid % JPI : tid / W;
+  const int wl = min(w, nlines - 1);                    // lines past the tile's end reload one
+  const unsigned off0 = (unsigned)(wl * (int)S_LINE + j0 * (int)S_ELEM) * (unsigned)sizeof(T);
+  const unsigned offl = (unsigned)(wl * (int)S_LINE + min(j0 + JPI * (NSTEP - 1), N - 1) *
+                                   (int)S_ELEM) * (unsigned)sizeof(T);  // last step, clamped
+  T* const lds0 = tile + w * P + j0 + 1;                // slot of step 0; step i adds JPI*i
+  const int jl = min(j0 + JPI * (NSTEP - 1), N);        // last step's slot (N: unused line[M])
+  // per-thread line coordinates (x sweep, residual mode)
+  const int lny = (line0 + wl) % N, lnz = (line0 + wl) / N;
+  (void)lny; (void)lnz;
+
+  // PER / CH of the flat mapping (FP32 x sweeps)
   constexpr int PER = (W * N + kBlock - 1) / kBlock;
-  // chunk of elements per thread whose loads are in flight together (a multiple of 4 or < 4)
   constexpr int CHMAX = IN == IN_RESID ? 8 : (sizeof(T) == 4 ? 16 : 8);
   constexpr int CH = PER < CHMAX ? PER : CHMAX;
-  // uniform (per block) base pointers; element offsets inside a tile fit in 32 bits
   const T* __restrict__ in_t = static_cast<const T*>(p.in) + base;
   const double* __restrict__ in_d = static_cast<const double*>(p.in) + base;
-  if constexpr (AX == AX_X) {
+
+  if constexpr (STEPMAP) {
+    constexpr int SCHMAX = IN == IN_RESID ? 4 : 8;
+    constexpr int SCH = NSTEP < SCHMAX ? NSTEP : SCHMAX;  // steps in flight per chunk
+#pragma unroll
+    for (int c0 = 0; c0 < NSTEP; c0 += SCH) {
+      T v[SCH];
+#pragma unroll
+      for (int k = 0; k < SCH; ++k) {
+        const int i = c0 + k;
+        if (i >= NSTEP) break;
+        const unsigned off = i < IFULL ? off0 : offl;
+        const long long step = i < IFULL ? (long long)i * JPI * S_ELEM : 0;
+        if constexpr (IN == IN_RESID) {
+          // FP64 residual b - (sigma - Lap_h) u at (x, y, z) = (j, lny, lnz)
+          const double* __restrict__ ub = p.u + base + step;
+          const double* __restrict__ bb = p.b + base + step;
+          const int x = i < IFULL ? j0 + JPI * i : min(j0 + JPI * i, N - 1);
+          const double uc = ld(ub, off), rb = ld(bb, off);
+          // neighbours move the (uniform) pointer, never the unsigned offset below zero
+          const double a0 = x > 0 ? ld(ub - 1, off) : 0.0;
+          const double a1 = x < N - 1 ? ld(ub + 1, off) : 0.0;
+          const double a2 = lny > 0 ? ld(ub - N, off) : 0.0;
+          const double a3 = lny < N - 1 ? ld(ub + N, off) : 0.0;
+          const double a4 = lnz > 0 ? ld(ub - (long long)N * N, off) : 0.0;
+          const double a5 = lnz < N - 1 ? ld(ub + (long long)N * N, off) : 0.0;
+          v[k] = (T)(rb - (sig + 6.0 * p.inv_h2) * uc +
+                     p.inv_h2 * ((a0 + a1) + (a2 + a3) + (a4 + a5)));
+        } else if constexpr (IN == IN_F64) {
+          v[k] = (T)ld(in_d + step, off);
+        } else {
+          v[k] = ld(in_t + step, off);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < SCH; ++k) {
+        const int i = c0 + k;
+        if (i >= NSTEP) break;
+        if (i < IFULL) lds0[JPI * i] = v[k];
+        else tile[w * P + jl + 1] = v[k];
+      }
+    }
+  } else {
+    // flat mapping: thread owns tile elements e = tid + i*kBlock (x lines, narrow reals)
     const int cnt = nlines * N;
 #pragma unroll 1
     for (int c0 = 0; c0 < PER; c0 += CH) {
       T v[CH];
       if constexpr (IN == IN_RESID) {
-        // FP64 residual b - (sigma - Lap_h) u, four elements at a time
 #pragma unroll
         for (int i0 = 0; i0 < CH; i0 += 4) {
           constexpr int K4 = CH < 4 ? CH : 4;
@@ -350,9 +434,9 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
 #pragma unroll
           for (int k = 0; k < K4; ++k) {
             const int e = min(tid + (c0 + i0 + k) * kBlock, cnt - 1);
-            const int w = e / N;
-            const int x = e - w * N;
-            const int ln = line0 + w;
+            const int ww = e / N;
+            const int x = e - ww * N;
+            const int ln = line0 + ww;
             const int z = ln / N;
             const int y = ln - z * N;
             const double* __restrict__ u = p.u + base;
@@ -382,31 +466,9 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
       for (int i = 0; i < CH; ++i) {
         const int e = tid + (c0 + i) * kBlock;
         if (e < cnt) {
-          const int w = e / N;
-          tile[w * P + (e - w * N) + 1] = v[i];
+          const int ww = e / N;
+          tile[ww * P + (e - ww * N) + 1] = v[i];
         }
-      }
-    }
-  } else {
-    constexpr int CNT = N * W;
-#pragma unroll 1
-    for (int c0 = 0; c0 < PER; c0 += CH) {
-      T v[CH];
-#pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        const int e = min(tid + (c0 + i) * kBlock, CNT - 1);
-        const int j = e / W;  // W is a power of two
-        const int w = min(e - j * W, nlines - 1);
-        const int off = w + j * (int)S_ELEM;
-        if constexpr (IN == IN_F64) v[i] = (T)in_d[off];
-        else v[i] = in_t[off];
-      }
-#pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        const int e = tid + (c0 + i) * kBlock;
-        const int j = e / W;
-        const int w = e - j * W;
-        if (e < CNT && w < nlines) tile[w * P + j + 1] = v[i];
       }
     }
   }
@@ -444,7 +506,39 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
 
   // ------------------------------------------------------------------ store the tile
   double cm = 0.0, um = 0.0;
-  if constexpr (AX == AX_X) {
+  if constexpr (STEPMAP) {
+    if (w < nlines) {
+      T v[NSTEP];
+#pragma unroll
+      for (int i = 0; i < NSTEP; ++i) v[i] = i < IFULL ? lds0[JPI * i] : tile[w * P + jl + 1];
+      double old[OUT == OUT_UPD ? NSTEP : 1];
+      if constexpr (OUT == OUT_UPD) {
+        // all reads of u before its first write (the stores may alias the reads)
+#pragma unroll
+        for (int i = 0; i < NSTEP; ++i)
+          old[i] = ld(static_cast<const double*>(p.out) + base +
+                          (i < IFULL ? (long long)i * JPI * S_ELEM : 0),
+                      i < IFULL ? off0 : offl);
+      }
+#pragma unroll
+      for (int i = 0; i < NSTEP; ++i) {
+        if (i >= IFULL && j0 + JPI * i >= N) break;
+        const unsigned off = i < IFULL ? off0 : offl;
+        const long long step = i < IFULL ? (long long)i * JPI * S_ELEM : 0;
+        if constexpr (OUT == OUT_UPD) {
+          const double nu = old[i] + (double)v[i];
+          st(static_cast<double*>(p.out) + base + step, off, nu);
+          cm = fmax(cm, fabs((double)v[i]));
+          um = fmax(um, fabs(nu));
+        } else if constexpr (OUT == OUT_F64) {
+          st(static_cast<double*>(p.out) + base + step, off, (double)v[i]);
+          cm = fmax(cm, fabs((double)v[i]));
+        } else {
+          st(static_cast<T*>(p.out) + base + step, off, v[i]);
+        }
+      }
+    }
+  } else if constexpr (AX == AX_X) {
     const int cnt = nlines * N;
 #pragma unroll 1
     for (int c0 = 0; c0 < PER; c0 += CH) {
@@ -452,8 +546,8 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
 #pragma unroll
       for (int i = 0; i < CH; ++i) {
         const int e = min(tid + (c0 + i) * kBlock, cnt - 1);
-        const int w = e / N;
-        v[i] = tile[w * P + (e - w * N) + 1];
+        const int ww = e / N;
+        v[i] = tile[ww * P + (e - ww * N) + 1];
       }
       if constexpr (OUT == OUT_UPD) {
         double* uo = static_cast<double*>(p.out) + base;
@@ -483,26 +577,6 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
             }
           }
         }
-      }
-    }
-  } else {
-    constexpr int CNT = N * W;
-#pragma unroll 1
-    for (int c0 = 0; c0 < PER; c0 += CH) {
-      T v[CH];
-#pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        const int e = min(tid + (c0 + i) * kBlock, CNT - 1);
-        const int j = e / W;
-        const int w = e - j * W;
-        v[i] = tile[w * P + j + 1];
-      }
-#pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        const int e = tid + (c0 + i) * kBlock;
-        const int j = e / W;
-        const int w = e - j * W;
-        if (e < CNT && w < nlines) (static_cast<T*>(p.out) + base)[w + j * (int)S_ELEM] = v[i];
       }
     }
   }

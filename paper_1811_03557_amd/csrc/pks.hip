@@ -242,7 +242,7 @@ dpm_status stepper_create_impl(const dpm_bep* b, double dt, double chi, double* 
   so.rhs_chunk = 0;
   DPM_TRY(workspace_size_impl(b->grid, 2, so, &sw));
   int* gd = reinterpret_cast<int*>(static_cast<char*>(o.workspace) + step_layout(b, sw).guard);
-  if (timing_on()) {
+  if (timing_enabled()) {
     set_error("dpm_stepper_create: sweep timing is enabled; end it before capturing a step");
     return DPM_EINVAL;
   }

@@ -75,6 +75,41 @@ def test_fp32_refined_parity(n, sigma):
     assert 1 <= info["refine_iters"] <= 3
 
 
+@pytest.mark.parametrize("n", [31, 255])
+def test_fp64_refined_parity(n):
+    """FP64 transforms with FP64 refinement (residual and update sweeps in double)."""
+    dev = need_gpu()
+    say(f"fp64 refined n={n}")
+    h, _ = inp.grid(n)
+    b = inp.rhs_normal(n, 2, seed=11)
+    ref = oaux.aux_solve(b, 1.0, h)
+    u = _solve(b, 1.0, h, dev, prec="fp64", max_refine=2, rtol=1e-14)
+    assert _max_rel(u, ref) < TOL["fp64"]
+
+
+@pytest.mark.parametrize("prec,kw,modes,tol", [
+    ("fp64", {}, [(1, 2, 3), (511, 300, 77)], 1e-12),
+    ("fp32", {"max_refine": 4, "rtol": 1e-10}, [(1, 2, 3), (511, 300, 77)], 1e-10),
+    ("fp32", {}, [(1, 2, 3), (5, 9, 2)], 1e-5)])
+def test_eigenmode_closed_form_511(prec, kw, modes, tol):
+    """N = 511 (a 256-point complex FFT per line): sine modes are solved exactly.  Plain FP32 is
+    held to 1e-5 on low modes only: for a high mode the transforms' rounding (~eps32 log2 M of
+    |b|) lands in low-frequency coefficients, divided by sigma + lambda_min = 4.3 while the
+    solution is divided by sigma + lambda_mode = 2e5, so its relative error grows with that
+    ratio (5e-5 measured for (511, 300, 77)); refinement brings it to 1e-10."""
+    dev = need_gpu()
+    n = 511
+    say(f"eigenmode n=511 {prec} {kw}")
+    h, _ = inp.grid(n)
+    j = np.arange(1, n + 1)
+    for (k1, k2, k3) in modes:
+        s = [np.sin(np.pi * ((j * k) % (2 * (n + 1))) / (n + 1)) for k in (k1, k2, k3)]
+        b = s[2][:, None, None] * s[1][None, :, None] * s[0][None, None, :]
+        lam = sum(4.0 / h**2 * np.sin(np.pi * k / (2 * (n + 1))) ** 2 for k in (k1, k2, k3))
+        u = _solve(b[None], 1.0, h, dev, prec=prec, **kw)[0]
+        assert oaux.rel_err_inf(u, b / (1.0 + lam)) < tol, (k1, k2, k3)
+
+
 def test_eigenmode_closed_form_full_size():
     """At N = 255 a single sine mode is solved exactly (property at any size)."""
     dev = need_gpu()
