@@ -278,6 +278,162 @@ __device__ __forceinline__ void dst1_line(T* line, int g, const T* tab) {
 
 
 
+// ---------------------------------------------------------------------------------------
+// Line transform with explicit LDS addressing, for G a multiple of 8 (N >= 127).  Every
+// position a thread touches is a per-thread part a plus a compile-time part c, where c is a
+// multiple of 8 or a + c has c's low three bits on top of a multiple of 8; in both cases
+// pad8(a + c) = pad8(a) + c + c/8, so each LDS access is a per-thread base plus an immediate.
+
+// One Stockham stage (radix R, stride NS) writing its outputs to their padded positions.
+// On entry a[s] holds element g + s*G.
+template <typename T, int H, int V, int R, int NS>
+__device__ __forceinline__ void stage_w(const C2<T>* a, int g, C2<T>* buf, const C2<T>* tw) {
+  constexpr int G = H / V;
+  constexpr int Q = V / R;
+  constexpr int KT = H / (NS * R);  // twiddle index stride
+  static_assert(G % 8 == 0, "explicit addressing needs G % 8 == 0");
+  int a_thr, vmk;
+  if constexpr (NS <= G) {
+    const int gm = g & (NS - 1);
+    a_thr = (g - gm) * R + gm;  // (v - vm) R + vm with vm = g mod NS
+    vmk = gm * KT;
+  } else {
+    a_thr = g;                  // vm = g + (q G mod NS)
+    vmk = g * KT;
+  }
+  C2<T>* wb = buf + (a_thr + (a_thr >> 3));
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int cq = NS <= G ? 0 : (q * G) % NS;
+    C2<T> x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      x[r] = a[q + r * Q];
+      if (NS > 1 && r > 0) x[r] = cmul(x[r], tw[r * (vmk + cq * KT)]);
+    }
+    if constexpr (R == 8) {
+      dft8(x);
+    } else if constexpr (R == 4) {
+      dft4(x[0], x[1], x[2], x[3]);
+    } else {
+      dft2(x[0], x[1]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int c = NS <= G ? q * G * R + r * NS : (q * G - cq) * R + cq + r * NS;
+      wb[c + c / 8] = x[r];
+    }
+  }
+}
+
+template <typename T, int H, int V, int NS>
+__device__ __forceinline__ void fft_stages_w(C2<T>* a, int g, C2<T>* buf, const C2<T>* tw) {
+  constexpr int R = radix_at<H, NS>();
+  constexpr int G = H / V;
+  stage_w<T, H, V, R, NS>(a, g, buf, tw);
+  wave_sync();
+  if constexpr (NS * R < H) {
+    const C2<T>* rb = buf + (g + (g >> 3));
+#pragma unroll
+    for (int s = 0; s < V; ++s) a[s] = rb[s * (G + G / 8)];
+    wave_sync();
+    fft_stages_w<T, H, V, NS * R>(a, g, buf, tw);
+  }
+}
+
+// Broadcast of lane n of each 16-lane DPP row to the whole row.
+template <int L>
+__device__ __forceinline__ double row_bcast(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + L, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + L, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int L>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + L, 0xF, 0xF, false));
+}
+template <typename T, int G>
+__device__ __forceinline__ T group_bcast_first(T v) {
+  if constexpr (G == 16) return row_bcast<0>(v);
+  else return __shfl(v, 0, G);
+}
+template <typename T, int G>
+__device__ __forceinline__ T group_bcast_last(T v) {
+  if constexpr (G == 16) return row_bcast<15>(v);
+  else return __shfl(v, G - 1, G);
+}
+
+// Unnormalised DST-I of one line (as dst1_line) into registers: on exit o[s] = (2 X_2k,
+// 2 X_2k+1) for k = g + s*G, and the slot may be overwritten.  FROMREG: the pairs
+// (x_2q, x_2q+1), q = g + s*G, are taken from o[] instead of the slot (the slot must still
+// hold the line in natural layout for the mirrored reads).
+template <typename T, int LOGM, bool FROMREG>
+__device__ __forceinline__ void dst1_regs(T* line, int g, const T* tab, C2<T>* o) {
+  using K = Cfg<T, LOGM>;
+  constexpr int M = K::M, H = K::H, V = K::V, G = K::G;
+  constexpr int G9 = G + G / 8;
+  C2<T>* buf = reinterpret_cast<C2<T>*>(line);
+  const C2<T>* sn = reinterpret_cast<const C2<T>*>(tab) + g;
+  const C2<T>* tw = reinterpret_cast<const C2<T>*>(tab + M);
+  const C2<T>* tp = reinterpret_cast<const C2<T>*>(tab + 2 * M) + g;
+  const T* lb = line + (M - 2 * g - 2 * (V - 1) * G);  // lb[2 (V-1-s) G] = x_{M-2q}
+  const C2<T>* xb = buf + g;
+  C2<T> a[V];
+#pragma unroll
+  for (int s = 0; s < V; ++s) {
+    const C2<T> xa = FROMREG ? o[s] : xb[s * G];
+    const C2<T> w = sn[s * G];
+    const T xb0 = lb[2 * (V - 1 - s) * G];      // for q = 0: line[M], not used
+    const T xb1 = lb[2 * (V - 1 - s) * G - 1];
+    const T ax = w.x * (xa.x + xb0) + (T)0.5 * (xa.x - xb0);
+    a[s].x = (s == 0 && g == 0) ? (T)0 : ax;
+    a[s].y = w.y * (xa.y + xb1) + (T)0.5 * (xa.y - xb1);
+  }
+  wave_sync();
+  fft_stages_w<T, H, V, 1>(a, g, buf, tw);
+  // F_k = E_k + e^{-2 pi i k/M} O_k; the mirror (H - k) mod H is pad8(G - g) + (V-1-s) G9,
+  // except k = 0, whose mirror is 0
+  const C2<T>* pa = buf + (g + (g >> 3));
+  const C2<T>* pm = buf + (g > 0 ? (G - g) + ((G - g) >> 3) : G9);
+  const C2<T>* pm0 = g > 0 ? pm + (V - 1) * G9 : buf;
+  T re[V], im[V];
+#pragma unroll
+  for (int s = 0; s < V; ++s) {
+    const C2<T> A = pa[s * G9];
+    const C2<T> Bc = s == 0 ? *pm0 : pm[(V - 1 - s) * G9];
+    const C2<T> B = {Bc.x, -Bc.y};
+    const C2<T> E = {A.x + B.x, A.y + B.y};
+    const C2<T> D = {A.x - B.x, A.y - B.y};
+    const C2<T> O = {D.y, -D.x};
+    const C2<T> F = cadd(E, cmul(tp[s * G], O));
+    re[s] = F.x;
+    im[s] = F.y;
+  }
+  const T f0 = group_bcast_first<T, G>(re[0]);
+  T carry = -(T)0.5 * f0;
+#pragma unroll
+  for (int s = 0; s < V; ++s) {
+    const T incl = group_scan<T, G>(re[s], g);
+    const T tot = group_bcast_last<T, G>(incl);
+    re[s] = carry + incl;
+    carry += tot;
+  }
+#pragma unroll
+  for (int s = 0; s < V; ++s) {
+    o[s].x = (s == 0 && g == 0) ? (T)0 : -im[s];
+    o[s].y = re[s];
+  }
+  wave_sync();  // all reads of the FFT result done before the slot is overwritten
+}
+
+// 1/d to FP64 accuracy: hardware reciprocal and two Newton steps.
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  r = fma(fma(-d, r, 1.0), r, r);
+  return r;
+}
+
 // Loads and stores at a uniform base plus a 32-bit byte offset (the global saddr form).  The
 // base is passed through readfirstlane so that it stays in scalar registers: the compiler then
 // moves a step's base with scalar adds instead of a 64-bit vector add per element.  Callers pass
@@ -323,6 +479,8 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
 
   __shared__ __align__(16) T tile[W * P];
   __shared__ __align__(16) T tab[3 * M];
+  // eigenvalue table of the z sweep: lamt[0] = 0, lamt[i] = lam_hat_i (i = 1..N)
+  __shared__ double lamt[ZPASS ? M : 1];
   __shared__ unsigned long long red[2][kBlock / 64];
 
   const int logical = xcd_remap(blockIdx.x, nblocks);
@@ -347,6 +505,9 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
 #pragma unroll
     for (int i = 0; i < TP; ++i)
       if (tid + i * kBlock < 3 * M) tab[tid + i * kBlock] = tv[i];
+    if constexpr (ZPASS) {
+      for (int i = tid; i < M; i += kBlock) lamt[i] = i == 0 ? 0.0 : p.lam_hat[i - 1];
+    }
   }
 
   // ------------------------------------------------------------------ load the tile
@@ -481,7 +642,30 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
     const int l = round * K::LPR + tid / G;
     if (l < nlines) {  // uniform across the G threads of a line (all in one wavefront)
       T* line = tile + l * P;
-      if constexpr (ZPASS) {
+      if constexpr (K::G % 8 == 0) {
+        C2<T> o[K::V];
+        C2<T>* ob = reinterpret_cast<C2<T>*>(line) + g;
+        dst1_regs<T, LOGM, false>(line, g, tab, o);
+        if constexpr (ZPASS) {
+          // scale X_i by (sqrt(2/M)/2)^6 / (sigma + lambda_x + lambda_y + lambda_z), i = 2k, 2k+1
+          const double bxy = sig + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]);
+          constexpr double kNorm = 1.0 / (8.0 * (double)M * (double)M * (double)M);
+          const double* lp = lamt + 2 * g;
+#pragma unroll
+          for (int s2 = 0; s2 < K::V; ++s2) {
+            const double d0 = kNorm * recip(bxy + p.inv_h2 * lp[2 * s2 * G]);
+            const double d1 = kNorm * recip(bxy + p.inv_h2 * lp[2 * s2 * G + 1]);
+            o[s2].x = (T)((double)o[s2].x * d0);
+            o[s2].y = (T)((double)o[s2].y * d1);
+            ob[s2 * G] = o[s2];
+          }
+          wave_sync();
+          dst1_regs<T, LOGM, true>(line, g, tab, o);
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < K::V; ++s2) ob[s2 * G] = o[s2];
+        wave_sync();
+      } else if constexpr (ZPASS) {
         // forward DST scaled by 1/(sigma + lambda), then the inverse DST: one code path run
         // twice keeps the register footprint of a single transform
         const double bxy = sig + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]);
