@@ -35,7 +35,8 @@ KIND_NAMES = ["x_first", "y", "z_fused", "x_last", "x_residual", "x_update"]
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dst_sweeps_fp64_aux255_64rhs_hbm_traffic.txt")
-KERNEL_SOURCES = ["paper_1811_03557_amd/csrc/dst_fft.hip", "paper_1811_03557_amd/csrc/common.h"]
+KERNEL_SOURCES = ["paper_1811_03557_amd/csrc/dst_fft.hip", "paper_1811_03557_amd/csrc/common.h",
+                  "paper_1811_03557_amd/csrc/aux_solve.hip"]
 
 
 def counted_traffic(kind, path_name, n, rhs_per_launch):
@@ -43,18 +44,21 @@ def counted_traffic(kind, path_name, n, rhs_per_launch):
     WRITE_SIZE scaled by a plain copy of known size), or None when the summary does not cover
     this configuration or the kernel source has changed since the counters were taken."""
     import hashlib
-    if path_name != "fp64" or n != 255 or rhs_per_launch != 1 or not os.path.exists(TRAFFIC_FILE):
+    if path_name != "fp64" or n != 255 or not os.path.exists(TRAFFIC_FILE):
         return None
     digest = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
                                      for f in KERNEL_SOURCES)).hexdigest()
-    taken, val = None, None
+    taken, val, rpl = None, None, None
     for line in open(TRAFFIC_FILE):
         if line.startswith("kernel source sha256"):
             taken = line.rsplit(":", 1)[1].strip()
         parts = line.split()
+        if len(parts) == 2 and parts[0] == "rhs_per_launch":
+            rpl = int(parts[1])
         if len(parts) == 3 and parts[0] == "traffic_bytes_per_launch" and parts[1] == kind:
             val = float(parts[2])
-    return val if (taken == digest and val is not None) else None
+    ok = taken == digest and val is not None and rpl == int(rhs_per_launch)
+    return val if ok else None
 
 
 def log(*a):

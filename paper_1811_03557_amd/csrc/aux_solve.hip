@@ -63,12 +63,13 @@ __global__ void k_flags_check(SolveFlags f, int rhs0, int nb, int k, double rtol
   f.umax[r] = 0ull;
 }
 
-// Right-hand sides per launch: the working volume of a chunk is kept near 128 MB so that the
-// sweeps of one chunk find it in the 256 MB Infinity Cache.
+// Right-hand sides per launch: the chunk's transform volumes total about the 256 MB Infinity
+// Cache (rounded to the nearest count; measured at 255^3: 2 FP64 or 4 FP32 volumes per launch
+// beat 1 and 3).
 int default_chunk(int n, int nrhs, int real_bytes, bool need_ws) {
   (void)need_ws;
   const double vol = (double)n * n * n * real_bytes;
-  int c = (int)std::floor(128.0e6 / vol);
+  int c = (int)std::lround(256.0e6 / vol);
   if (c < 1) c = 1;
   if (c > nrhs) c = nrhs;
   if (c > 65535) c = 65535;
