@@ -227,7 +227,8 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
     char* uc = static_cast<char*>(u) + (size_t)c0 * vol * io_bytes;
     if (o.prec == DPM_FP64 && !refine) {
       // FP64 transforms in place in u: no workspace traffic beyond u itself
-      DPM_TRY(five_sweeps(pl, 8, g, IN_WS, bc, OUT_F64, uc, uc, nullptr, nullptr, &fl, c0, nb,
+      // (no max-norm tracking: only refinement uses it)
+      DPM_TRY(five_sweeps(pl, 8, g, IN_WS, bc, OUT_F64, uc, uc, nullptr, nullptr, nullptr, c0, nb,
                           false, false, sig_dev, s));
     } else if (o.prec == DPM_FP32 && !o.io_fp64) {
       DPM_TRY(five_sweeps(pl, 4, g, IN_WS, bc, OUT_WS, uc, uc, nullptr, nullptr, nullptr, c0, nb,

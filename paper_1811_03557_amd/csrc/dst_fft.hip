@@ -307,9 +307,28 @@ __device__ __forceinline__ void stage_w(const C2<T>* a, int g, C2<T>* buf, const
     const int cq = NS <= G ? 0 : (q * G) % NS;
     C2<T> x[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      x[r] = a[q + r * Q];
-      if (NS > 1 && r > 0) x[r] = cmul(x[r], tw[r * (vmk + cq * KT)]);
+    for (int r = 0; r < R; ++r) x[r] = a[q + r * Q];
+    if constexpr (NS > 1 && sizeof(T) == 4) {
+      // FP32: twiddles as read from the table (each rounded once from FP64)
+#pragma unroll
+      for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r * (vmk + cq * KT)]);
+    } else if constexpr (NS > 1) {
+      // FP64: twiddle w^r for r < R from one table read: w^2 = w w, w^3 = w^2 w, w^4 = w^2 w^2,
+      // ... (at most four roundings deep, a few ulp)
+      C2<T> wr[R];
+      wr[1] = tw[vmk + cq * KT];
+      if constexpr (R > 2) {
+        wr[2] = cmul(wr[1], wr[1]);
+        wr[3] = cmul(wr[2], wr[1]);
+      }
+      if constexpr (R > 4) {
+        wr[4] = cmul(wr[2], wr[2]);
+        wr[5] = cmul(wr[4], wr[1]);
+        wr[6] = cmul(wr[3], wr[3]);
+        wr[7] = cmul(wr[6], wr[1]);
+      }
+#pragma unroll
+      for (int r = 1; r < R; ++r) x[r] = cmul(x[r], wr[r]);
     }
     if constexpr (R == 8) {
       dft8(x);
@@ -368,26 +387,41 @@ __device__ __forceinline__ T group_bcast_last(T v) {
 // (x_2q, x_2q+1), q = g + s*G, are taken from o[] instead of the slot (the slot must still
 // hold the line in natural layout for the mirrored reads).
 template <typename T, int LOGM, bool FROMREG>
-__device__ __forceinline__ void dst1_regs(T* line, int g, const T* tab, C2<T>* o) {
+__device__ __forceinline__ void dst1_regs(T* line, int g, const T* tab, const T* gtab, C2<T>* o) {
   using K = Cfg<T, LOGM>;
   constexpr int M = K::M, H = K::H, V = K::V, G = K::G;
   constexpr int G9 = G + G / 8;
   C2<T>* buf = reinterpret_cast<C2<T>*>(line);
-  const C2<T>* sn = reinterpret_cast<const C2<T>*>(tab) + g;
   const C2<T>* tw = reinterpret_cast<const C2<T>*>(tab + M);
-  const C2<T>* tp = reinterpret_cast<const C2<T>*>(tab + 2 * M) + g;
   const T* lb = line + (M - 2 * g - 2 * (V - 1) * G);  // lb[2 (V-1-s) G] = x_{M-2q}
   const C2<T>* xb = buf + g;
+  // E_s = e^{-2 pi i k/M} for the lane's indices k = g + s*G (pre-processing uses q = k):
+  // E_0 from the LDS table, E_s = E_0 rho_s with rho_s = e^{-2 pi i s G/M} read uniformly
+  // from the global table (scalar loads)
+  // (FP64 only; FP32 reads every value from the table, each rounded once from FP64)
+  constexpr bool REG = sizeof(T) == 8;
+  const C2<T>* gtp = reinterpret_cast<const C2<T>*>(gtab + 2 * M);
+  const C2<T>* ltp = reinterpret_cast<const C2<T>*>(tab + 2 * M) + g;
+  const C2<T>* lsn = reinterpret_cast<const C2<T>*>(tab) + g;
+  C2<T> E[V];
+  E[0] = ltp[0];
+#pragma unroll
+  for (int s = 1; s < V; ++s) E[s] = REG ? cmul(E[0], gtp[s * G]) : ltp[s * G];
+  // sin(pi 2q/M) = -Im E, sin(pi (2q+1)/M) = sin(2 pi q/M) cos(pi/M) + cos(2 pi q/M) sin(pi/M)
+  const T s1 = gtab[1];          // sin(pi/M)
+  const T c1 = gtab[M / 2 - 1];  // cos(pi/M) = sin(pi (M/2 - 1)/M)
   C2<T> a[V];
 #pragma unroll
   for (int s = 0; s < V; ++s) {
     const C2<T> xa = FROMREG ? o[s] : xb[s * G];
-    const C2<T> w = sn[s * G];
+    const C2<T> snt = REG ? C2<T>{-E[s].y, -E[s].y * c1 + E[s].x * s1} : lsn[s * G];
+    const T sn0 = snt.x;
+    const T sn1 = snt.y;
     const T xb0 = lb[2 * (V - 1 - s) * G];      // for q = 0: line[M], not used
     const T xb1 = lb[2 * (V - 1 - s) * G - 1];
-    const T ax = w.x * (xa.x + xb0) + (T)0.5 * (xa.x - xb0);
+    const T ax = sn0 * (xa.x + xb0) + (T)0.5 * (xa.x - xb0);
     a[s].x = (s == 0 && g == 0) ? (T)0 : ax;
-    a[s].y = w.y * (xa.y + xb1) + (T)0.5 * (xa.y - xb1);
+    a[s].y = sn1 * (xa.y + xb1) + (T)0.5 * (xa.y - xb1);
   }
   wave_sync();
   fft_stages_w<T, H, V, 1>(a, g, buf, tw);
@@ -402,10 +436,10 @@ __device__ __forceinline__ void dst1_regs(T* line, int g, const T* tab, C2<T>* o
     const C2<T> A = pa[s * G9];
     const C2<T> Bc = s == 0 ? *pm0 : pm[(V - 1 - s) * G9];
     const C2<T> B = {Bc.x, -Bc.y};
-    const C2<T> E = {A.x + B.x, A.y + B.y};
+    const C2<T> Ev = {A.x + B.x, A.y + B.y};
     const C2<T> D = {A.x - B.x, A.y - B.y};
     const C2<T> O = {D.y, -D.x};
-    const C2<T> F = cadd(E, cmul(tp[s * G], O));
+    const C2<T> F = cadd(Ev, cmul(E[s], O));
     re[s] = F.x;
     im[s] = F.y;
   }
@@ -643,9 +677,10 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
     if (l < nlines) {  // uniform across the G threads of a line (all in one wavefront)
       T* line = tile + l * P;
       if constexpr (K::G % 8 == 0) {
+        const T* gtab_k = static_cast<const T*>(p.tw);
         C2<T> o[K::V];
         C2<T>* ob = reinterpret_cast<C2<T>*>(line) + g;
-        dst1_regs<T, LOGM, false>(line, g, tab, o);
+        dst1_regs<T, LOGM, false>(line, g, tab, gtab_k, o);
         if constexpr (ZPASS) {
           // scale X_i by (sqrt(2/M)/2)^6 / (sigma + lambda_x + lambda_y + lambda_z), i = 2k, 2k+1
           const double bxy = sig + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]);
@@ -660,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
             ob[s2 * G] = o[s2];
           }
           wave_sync();
-          dst1_regs<T, LOGM, true>(line, g, tab, o);
+          dst1_regs<T, LOGM, true>(line, g, tab, gtab_k, o);
         }
 #pragma unroll
         for (int s2 = 0; s2 < K::V; ++s2) ob[s2 * G] = o[s2];
