@@ -500,9 +500,20 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
+// The FP64 fused z sweep (two transforms per line, latency-bound) reads its tables from global
+// memory and is compiled for 4 waves per SIMD: with 38.7 KB of LDS per block, 4 blocks share
+// a CU.  The other sweeps keep the tables in LDS.
+template <typename T, int LOGM, bool ZPASS>
+struct ZOcc {
+  static constexpr bool gtab = ZPASS && sizeof(T) == 8 && Cfg<T, LOGM>::G % 8 == 0;
+  static constexpr int waves = gtab ? 4 : 1;
+};
+
 template <typename T, int LOGM, int AX, bool ZPASS, int IN, int OUT>
-__global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int nblocks) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ZOcc<T, LOGM, ZPASS>::waves)))
+void k_dst_pass(PassArgs p, int tiles, int nblocks) {
   using K = Cfg<T, LOGM>;
+  constexpr bool GTAB = ZOcc<T, LOGM, ZPASS>::gtab;
   constexpr int M = K::M, N = K::N, G = K::G, W = K::W, P = K::P;
   constexpr long long VOL = (long long)N * N * N;
   constexpr int LINES_PER_ROW = (AX == AX_X) ? N * N : N;
@@ -512,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
   constexpr long long S_ELEM = (AX == AX_X) ? 1 : (AX == AX_Y ? N : (long long)N * N);
 
   __shared__ __align__(16) T tile[W * P];
-  __shared__ __align__(16) T tab[3 * M];
+  __shared__ __align__(16) T tab[GTAB ? 2 : 3 * M];
   // eigenvalue table of the z sweep: lamt[0] = 0, lamt[i] = lam_hat_i (i = 1..N)
   __shared__ double lamt[ZPASS ? M : 1];
   __shared__ unsigned long long red[2][kBlock / 64];
@@ -532,13 +543,15 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
 
   {
     const T* gtab = static_cast<const T*>(p.tw);
-    constexpr int TP = (3 * M + kBlock - 1) / kBlock;
-    T tv[TP];
+    if constexpr (!GTAB) {
+      constexpr int TP = (3 * M + kBlock - 1) / kBlock;
+      T tv[TP];
 #pragma unroll
-    for (int i = 0; i < TP; ++i) tv[i] = gtab[min(tid + i * kBlock, 3 * M - 1)];
+      for (int i = 0; i < TP; ++i) tv[i] = gtab[min(tid + i * kBlock, 3 * M - 1)];
 #pragma unroll
-    for (int i = 0; i < TP; ++i)
-      if (tid + i * kBlock < 3 * M) tab[tid + i * kBlock] = tv[i];
+      for (int i = 0; i < TP; ++i)
+        if (tid + i * kBlock < 3 * M) tab[tid + i * kBlock] = tv[i];
+    }
     if constexpr (ZPASS) {
       for (int i = tid; i < M; i += kBlock) lamt[i] = i == 0 ? 0.0 : p.lam_hat[i - 1];
     }
@@ -678,9 +691,10 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
       T* line = tile + l * P;
       if constexpr (K::G % 8 == 0) {
         const T* gtab_k = static_cast<const T*>(p.tw);
+        const T* ttab = GTAB ? gtab_k : tab;
         C2<T> o[K::V];
         C2<T>* ob = reinterpret_cast<C2<T>*>(line) + g;
-        dst1_regs<T, LOGM, false>(line, g, tab, gtab_k, o);
+        dst1_regs<T, LOGM, false>(line, g, ttab, gtab_k, o);
         if constexpr (ZPASS) {
           // scale X_i by (sqrt(2/M)/2)^6 / (sigma + lambda_x + lambda_y + lambda_z), i = 2k, 2k+1
           const double bxy = sig + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]);
@@ -695,7 +709,7 @@ __global__ __launch_bounds__(kBlock) void k_dst_pass(PassArgs p, int tiles, int 
             ob[s2 * G] = o[s2];
           }
           wave_sync();
-          dst1_regs<T, LOGM, true>(line, g, tab, gtab_k, o);
+          dst1_regs<T, LOGM, true>(line, g, ttab, gtab_k, o);
         }
 #pragma unroll
         for (int s2 = 0; s2 < K::V; ++s2) ob[s2 * G] = o[s2];
