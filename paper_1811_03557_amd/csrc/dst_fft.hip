@@ -505,7 +505,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // a CU.  The other sweeps keep the tables in LDS.
 template <typename T, int LOGM, bool ZPASS>
 struct ZOcc {
-  static constexpr bool gtab = ZPASS && sizeof(T) == 8 && Cfg<T, LOGM>::G % 8 == 0;
+  static constexpr bool gtab = sizeof(T) == 8 && Cfg<T, LOGM>::G % 8 == 0;
   static constexpr int waves = gtab ? 4 : 1;
 };
 
