@@ -151,7 +151,8 @@ typedef struct dpm_bep dpm_bep; /* library-owned: mask, gamma lists, basis, BEP 
  * dpm_build_boundary_matrix -- paper Algorithm "Main Steps", Step 2: the reduced-BEP matrix
  * (eq BEP_recast) A[:, nu] = Tr_gamma_in (I - P_gamma) basis_nu, one AP solve per column with
  * right-hand side 1_{M-} (sigma - Lap_h)[basis_nu extended by zero] (Def. "DP" in sigma-form),
- * followed by an FP64 Householder QR of A kept in the handle.
+ * followed by an FP64 Householder QR A = Q R and the least-squares operator P = R^-1 Q1^T
+ * (Q1: the first n_basis columns of Q), both kept in the handle.
  * m_plus: device N^3 uint8; basis: device n_basis x n_gamma FP64 in the order of
  * dpm_gamma_points.  opts selects the precision of the solves (refinement applies).
  * A_out: nullable device |gamma_in| x n_basis FP64, column-major.  Allocates the handle's
@@ -167,8 +168,9 @@ dpm_status dpm_bep_info(const dpm_bep* bep, int32_t* n_gamma, int32_t* n_gamma_i
 
 /*
  * dpm_bep_solve -- paper Step 5: least-squares coefficients C = argmin ||A C - g||_2 of the
- * reduced BEP (eq BEP_recast) from the QR kept in the handle.  g: device nvec x |gamma_in| FP64;
- * C: device nvec x n_basis FP64.  Asynchronous.
+ * reduced BEP (eq BEP_recast), as C = P g with the operator P = R^-1 Q1^T formed from the QR at
+ * build time.  g: device nvec x |gamma_in| FP64; C: device nvec x n_basis FP64.  Asynchronous;
+ * allocates nothing.
  */
 dpm_status dpm_bep_solve(const dpm_bep* bep, int32_t nvec, const double* g, double* C,
                          void* stream);

@@ -180,11 +180,8 @@ dpm_status dpm_bep_solve(const dpm_bep* bep, int32_t nvec, const double* g, doub
   if (!bep || !g || !C) { set_error("bep, g or C is NULL"); return DPM_EINVAL; }
   if (nvec <= 0 || nvec > 65535) { set_error("nvec out of range"); return DPM_EINVAL; }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  double* y = nullptr;
-  DPM_TRY_HIP(hipMallocAsync((void**)&y, sizeof(double) * (size_t)nvec * bep->n_in, s));
-  qr_solve(bep, nvec, g, y, C, s);
+  qr_solve(bep, nvec, g, C, s);
   hipError_t e = hipGetLastError();
-  (void)hipFreeAsync(y, s);
   if (e != hipSuccess) { set_error("dpm_bep_solve: %s", hipGetErrorString(e)); return DPM_EHIP; }
   return DPM_OK;
 }

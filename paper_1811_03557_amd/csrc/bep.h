@@ -16,6 +16,7 @@ struct dpm_bep {
   double* basis = nullptr;    // n_basis x n_gamma densities (row nu contiguous)
   double* A = nullptr;        // n_in x n_basis, column-major: Householder vectors below R
   double* tau = nullptr;      // n_basis reflector scalars
+  double* P = nullptr;        // n_basis x n_in least-squares operator R^-1 Q1^T (row nu contiguous)
   double rdiag_min = 0.0, rdiag_max = 0.0;
 };
 
@@ -38,8 +39,8 @@ void minus_operator(const double* w, const uint8_t* mp, const double* plus, doub
                     double sigma, double inv_h2, int nvol, hipStream_t s);
 void gather(const double* vol, long long vsz, const int32_t* idx, int m, int nvec, double* out,
             hipStream_t s);
-// C[r] = R^-1 Q^T g[r], r < nvec; y: device scratch nvec x n_in
-void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* y, double* C, hipStream_t s);
+// C[r] = R^-1 Q1^T g[r], r < nvec, as one product with the precomputed operator P
+void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* C, hipStream_t s);
 
 dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
                           const double* basis, const dpm_opts& o, hipStream_t s, dpm_bep** out,

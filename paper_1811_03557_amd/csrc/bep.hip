@@ -127,34 +127,56 @@ __global__ void k_apply_house(double* __restrict__ A, int m, int ncols, int j,
   for (int i = j + threadIdx.x; i < m; i += blockDim.x) a[i] -= w * (i == j ? 1.0 : v[i]);
 }
 
-// C = R^-1 (Q^T g) for nvec right-hand sides (one block each): reflectors applied in order,
-// then back substitution with the n x n upper triangle.
-__global__ void k_qr_solve(const double* __restrict__ A, const double* __restrict__ tau, int m,
-                           int n, const double* __restrict__ g, double* __restrict__ y,
-                           double* __restrict__ C) {
+// Q1 = Q[:, 0:n] = H_0 H_1 ... H_{n-1} [I_n; 0], formed in place in E (m x n, column-major),
+// one reflector per launch from the last to the first; H_j changes only the columns c >= j
+// (the columns c < j are still e_c, which has no entry in rows >= j).  One block per column.
+__global__ void k_apply_house_q(const double* __restrict__ A, int m, int n, int j,
+                                const double* __restrict__ tau, double* __restrict__ E) {
   __shared__ double sh[16];
-  __shared__ double cs[1024];
-  const int r = blockIdx.x;
-  double* yv = y + (long long)r * m;
-  for (int i = threadIdx.x; i < m; i += blockDim.x) yv[i] = g[(long long)r * m + i];
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const double* v = A + (long long)j * m;
-    double d = 0.0;
-    for (int i = j + threadIdx.x; i < m; i += blockDim.x) d += (i == j ? 1.0 : v[i]) * yv[i];
-    const double w = tau[j] * block_sum(d, sh);
-    for (int i = j + threadIdx.x; i < m; i += blockDim.x) yv[i] -= w * (i == j ? 1.0 : v[i]);
-    __syncthreads();
+  const int c = j + blockIdx.x;
+  if (c >= n) return;
+  const double t = tau[j];
+  if (t == 0.0) return;
+  const double* v = A + (long long)j * m;
+  double* e = E + (long long)c * m;
+  double d = 0.0;
+  for (int i = j + threadIdx.x; i < m; i += blockDim.x) d += (i == j ? 1.0 : v[i]) * e[i];
+  const double w = t * block_sum(d, sh);
+  for (int i = j + threadIdx.x; i < m; i += blockDim.x) e[i] -= w * (i == j ? 1.0 : v[i]);
+}
+
+__global__ void k_identity_cols(double* __restrict__ E, int m, int n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)m * n) return;
+  const long long c = i / m, r = i - c * m;
+  E[i] = r == c ? 1.0 : 0.0;
+}
+
+// P = R^-1 Q1^T (n x m, row nu contiguous): for each row i of Q1 (one thread), back
+// substitution x R^T ... i.e. R x = Q1[i, :]^T with R the upper triangle of A.
+__global__ void k_form_p(const double* __restrict__ A, const double* __restrict__ E, int m,
+                         int n, double* __restrict__ P) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  for (int nu = n - 1; nu >= 0; --nu) {
+    double acc = E[(long long)nu * m + i];
+    for (int k = nu + 1; k < n; ++k) acc -= A[(long long)k * m + nu] * P[(long long)k * m + i];
+    P[(long long)nu * m + i] = acc / A[(long long)nu * m + nu];
   }
-  // back substitution, n <= 1024
-  for (int i = n - 1; i >= 0; --i) {
-    double d = 0.0;
-    for (int k = i + 1 + threadIdx.x; k < n; k += blockDim.x) d += A[(long long)k * m + i] * cs[k];
-    const double s = block_sum(d, sh);
-    if (threadIdx.x == 0) cs[i] = (yv[i] - s) / A[(long long)i * m + i];
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) C[(long long)r * n + i] = cs[i];
+}
+
+// C[r][nu] = sum_i P[nu][i] g[r][i]: the least-squares coefficients of right-hand side r.
+// One block per (nu, r).
+__global__ void k_lsq_apply(const double* __restrict__ P, int m, int n,
+                            const double* __restrict__ g, double* __restrict__ C) {
+  __shared__ double sh[16];
+  const int nu = blockIdx.x, r = blockIdx.y;
+  const double* pr = P + (long long)nu * m;
+  const double* gr = g + (long long)r * m;
+  double d = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) d += pr[i] * gr[i];
+  const double t = block_sum(d, sh);
+  if (threadIdx.x == 0) C[(long long)r * n + nu] = t;
 }
 
 __global__ void k_rdiag(const double* __restrict__ A, int m, int n, double* __restrict__ out) {
@@ -215,9 +237,9 @@ void gather(const double* vol, long long vsz, const int32_t* idx, int m, int nve
   hipLaunchKernelGGL(k_gather, dim3(grid1(m), nvec), dim3(kB), 0, s, vol, vsz, idx, m, out);
 }
 
-void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* y, double* C, hipStream_t s) {
-  hipLaunchKernelGGL(k_qr_solve, dim3(nvec), dim3(1024), 0, s, bep->A, bep->tau, bep->n_in,
-                     bep->n_basis, g, y, C);
+void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* C, hipStream_t s) {
+  hipLaunchKernelGGL(k_lsq_apply, dim3(bep->n_basis, nvec), dim3(256), 0, s, bep->P, bep->n_in,
+                     bep->n_basis, g, C);
 }
 
 dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
@@ -358,6 +380,29 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
     set_error("boundary matrix is rank deficient: min |R_ii| = %g, max |R_ii| = %g", mn, mx);
     return fail(DPM_ERANK);
   }
+  // least-squares operator P = R^-1 Q1^T, so that every later solve is one product C = P g
+  {
+    double* E = nullptr;
+    if (!al((void**)&b->P, sizeof(double) * (size_t)n_basis * nin) ||
+        !al((void**)&E, sizeof(double) * (size_t)n_basis * nin)) {
+      (void)hipFree(E);
+      set_error("dpm_build_boundary_matrix: device allocation failed");
+      return fail(DPM_ENOMEM);
+    }
+    hipLaunchKernelGGL(k_identity_cols, dim3(grid1((long long)nin * n_basis)), dim3(kB), 0, s, E,
+                       nin, n_basis);
+    for (int j = n_basis - 1; j >= 0; --j)
+      hipLaunchKernelGGL(k_apply_house_q, dim3(n_basis - j), dim3(512), 0, s, b->A, nin, n_basis,
+                         j, b->tau, E);
+    hipLaunchKernelGGL(k_form_p, dim3(grid1(nin)), dim3(kB), 0, s, b->A, E, nin, n_basis, b->P);
+    hipError_t e2 = hipGetLastError();
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    (void)hipFree(E);
+    if (e2 != hipSuccess) {
+      set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e2));
+      return fail(DPM_EHIP);
+    }
+  }
   *out = b;
   return DPM_OK;
 }
@@ -373,6 +418,7 @@ void destroy_bep(dpm_bep* b) {
   (void)hipFree(b->basis);
   (void)hipFree(b->A);
   (void)hipFree(b->tau);
+  (void)hipFree(b->P);
   delete b;
 }
 

@@ -500,12 +500,13 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
-// The FP64 fused z sweep (two transforms per line, latency-bound) reads its tables from global
-// memory and is compiled for 4 waves per SIMD: with 38.7 KB of LDS per block, 4 blocks share
-// a CU.  The other sweeps keep the tables in LDS.
+// FP64 sweeps at N = 127 and 255 read their tables from global memory (L1/L2 resident) and are
+// compiled for 4 waves per SIMD: with at most 38.7 KB of LDS per block, 4 blocks share a CU
+// (the fused z sweep, two transforms per line, is bound by LDS latency at 3).  FP32 sweeps and
+// N >= 511 (two blocks per CU at most) keep the tables in LDS.
 template <typename T, int LOGM, bool ZPASS>
 struct ZOcc {
-  static constexpr bool gtab = sizeof(T) == 8 && Cfg<T, LOGM>::G % 8 == 0;
+  static constexpr bool gtab = sizeof(T) == 8 && Cfg<T, LOGM>::G % 8 == 0 && LOGM <= 8;
   static constexpr int waves = gtab ? 4 : 1;
 };
 

@@ -137,7 +137,7 @@ __global__ void k_gauss_gamma(const int32_t* __restrict__ idx, int ng, int n, do
 unsigned grid1(long long n) { return (unsigned)((n + kB - 1) / kB); }
 
 struct StepLayout {
-  size_t b2, X, w, g, y, C, ug, guard, solve_ws, total;
+  size_t b2, X, w, g, C, ug, guard, solve_ws, total;
 };
 
 StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
@@ -148,7 +148,6 @@ StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
   L.X = o; o = align_up(o + 2 * V, 256);
   L.w = o; o = align_up(o + 2 * V, 256);
   L.g = o; o = align_up(o + 2 * sizeof(double) * b->n_in, 256);
-  L.y = o; o = align_up(o + 2 * sizeof(double) * b->n_in, 256);
   L.C = o; o = align_up(o + 2 * sizeof(double) * b->n_basis, 256);
   L.ug = o; o = align_up(o + 2 * sizeof(double) * b->n_gamma, 256);
   L.guard = o; o = align_up(o + 2 * sizeof(int), 256);
@@ -189,7 +188,6 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   double* X = reinterpret_cast<double*>(ws + L.X);
   double* w = reinterpret_cast<double*>(ws + L.w);
   double* gv = reinterpret_cast<double*>(ws + L.g);
-  double* yv = reinterpret_cast<double*>(ws + L.y);
   double* C = reinterpret_cast<double*>(ws + L.C);
   double* ug = reinterpret_cast<double*>(ws + L.ug);
   int* gd = guard ? reinterpret_cast<int*>(ws + L.guard) : nullptr;
@@ -204,7 +202,7 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, nullptr));
   // Step 5: Tr_gamma_in G f, least squares, densities
   gather(X, vsz, b->idx_in, b->n_in, 2, gv, s);
-  qr_solve(b, 2, gv, yv, C, s);
+  qr_solve(b, 2, gv, C, s);
   hipLaunchKernelGGL(k_density, dim3(grid1(b->n_gamma), 2), dim3(kB), 0, s, b->basis, C,
                      b->n_basis, b->n_gamma, ug);
   // Steps 6-7: Green's formula as one AP solve per species
