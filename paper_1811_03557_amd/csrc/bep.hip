@@ -152,17 +152,49 @@ __global__ void k_identity_cols(double* __restrict__ E, int m, int n) {
   E[i] = r == c ? 1.0 : 0.0;
 }
 
-// P = R^-1 Q1^T (n x m, row nu contiguous): for each row i of Q1 (one thread), back
-// substitution x R^T ... i.e. R x = Q1[i, :]^T with R the upper triangle of A.
-__global__ void k_form_p(const double* __restrict__ A, const double* __restrict__ E, int m,
+// Rinv = R^-1 (n x n, row-major, upper triangular) with R the upper triangle of A: one block
+// per column c, back substitution R x = e_c with the dot products reduced across the block.
+__global__ void k_rinv(const double* __restrict__ A, int m, int n, double* __restrict__ Rinv) {
+  __shared__ double sh[16];
+  __shared__ double x[1024];
+  const int c = blockIdx.x;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) x[k] = 0.0;
+  __syncthreads();
+  for (int nu = c; nu >= 0; --nu) {
+    double d = 0.0;
+    for (int k = nu + 1 + threadIdx.x; k <= c; k += blockDim.x) d += A[(long long)k * m + nu] * x[k];
+    const double s = block_sum(d, sh);
+    if (threadIdx.x == 0) x[nu] = ((nu == c ? 1.0 : 0.0) - s) / A[(long long)nu * m + nu];
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < n; k += blockDim.x) Rinv[(long long)k * n + c] = x[k];
+}
+
+// P[nu][i] = sum_k Rinv[nu][k] Q1[i][k] for a tile of PT rows nu (Rinv rows in LDS) and one row
+// i of Q1 per thread (E column-major: Q1[i][k] = E[k m + i], coalesced across threads).
+constexpr int PT = 8;
+__global__ void k_form_p(const double* __restrict__ Rinv, const double* __restrict__ E, int m,
                          int n, double* __restrict__ P) {
+  extern __shared__ double rt[];  // PT x n
+  const int nu0 = blockIdx.y * PT;
+  for (int t = threadIdx.x; t < PT * n; t += blockDim.x) {
+    const int r = t / n, k = t - r * n;
+    rt[t] = nu0 + r < n ? Rinv[(long long)(nu0 + r) * n + k] : 0.0;
+  }
+  __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  for (int nu = n - 1; nu >= 0; --nu) {
-    double acc = E[(long long)nu * m + i];
-    for (int k = nu + 1; k < n; ++k) acc -= A[(long long)k * m + nu] * P[(long long)k * m + i];
-    P[(long long)nu * m + i] = acc / A[(long long)nu * m + nu];
+  double acc[PT];
+#pragma unroll
+  for (int t = 0; t < PT; ++t) acc[t] = 0.0;
+  for (int k = nu0; k < n; ++k) {  // Rinv[nu][k] = 0 for k < nu
+    const double e = E[(long long)k * m + i];
+#pragma unroll
+    for (int t = 0; t < PT; ++t) acc[t] += rt[t * n + k] * e;
   }
+#pragma unroll
+  for (int t = 0; t < PT; ++t)
+    if (nu0 + t < n) P[(long long)(nu0 + t) * m + i] = acc[t];
 }
 
 // C[r][nu] = sum_i P[nu][i] g[r][i]: the least-squares coefficients of right-hand side r.
@@ -394,10 +426,19 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
     for (int j = n_basis - 1; j >= 0; --j)
       hipLaunchKernelGGL(k_apply_house_q, dim3(n_basis - j), dim3(512), 0, s, b->A, nin, n_basis,
                          j, b->tau, E);
-    hipLaunchKernelGGL(k_form_p, dim3(grid1(nin)), dim3(kB), 0, s, b->A, E, nin, n_basis, b->P);
+    double* Rinv = nullptr;
+    if (!al((void**)&Rinv, sizeof(double) * (size_t)n_basis * n_basis)) {
+      (void)hipFree(E);
+      set_error("dpm_build_boundary_matrix: device allocation failed");
+      return fail(DPM_ENOMEM);
+    }
+    hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, b->A, nin, n_basis, Rinv);
+    hipLaunchKernelGGL(k_form_p, dim3(grid1(nin), (n_basis + PT - 1) / PT), dim3(kB),
+                       sizeof(double) * PT * n_basis, s, Rinv, E, nin, n_basis, b->P);
     hipError_t e2 = hipGetLastError();
     if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
     (void)hipFree(E);
+    (void)hipFree(Rinv);
     if (e2 != hipSuccess) {
       set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e2));
       return fail(DPM_EHIP);
