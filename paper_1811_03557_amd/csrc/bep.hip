@@ -32,30 +32,36 @@ __global__ void k_scatter_density(const double* __restrict__ dens, int c0, int n
   vol[(long long)c * vsz + idx[i]] = dens[(long long)(c0 + c) * ng + i];
 }
 
-// out = M- ? (sigma - Lap_h) w : keep (keep = 0, or the M+ part given in `plus`)
+// out = M- ? (sigma - Lap_h) w : keep (keep = 0, or the M+ part given in `plus`).  One block per
+// x-line (blockIdx.x = y + n z) and volume (blockIdx.y); the line's coordinates come from one
+// 32-bit division, x is the loop index.
 __global__ void k_minus_operator(const double* __restrict__ w, const uint8_t* __restrict__ mp,
                                  const double* __restrict__ plus, double* __restrict__ out, int n,
                                  double sigma, double inv_h2, int nvol) {
-  const long long vsz = (long long)n * n * n;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned line = blockIdx.x;
   const int c = blockIdx.y;
-  if (i >= vsz || c >= nvol) return;
-  const long long o = (long long)c * vsz + i;
-  if (mp[i]) {
-    out[o] = plus ? plus[o] : 0.0;
-    return;
-  }
-  const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+  const int z = (int)(line / (unsigned)n), y = (int)(line - (unsigned)z * (unsigned)n);
+  const long long vsz = (long long)n * n * n;
+  const long long l0 = (long long)line * n;
   const double* wc = w + (long long)c * vsz;
-  double nb = 0.0;
-  if (x > 0) nb += wc[i - 1];
-  if (x < n - 1) nb += wc[i + 1];
-  if (y > 0) nb += wc[i - n];
-  if (y < n - 1) nb += wc[i + n];
-  if (z > 0) nb += wc[i - (long long)n * n];
-  if (z < n - 1) nb += wc[i + (long long)n * n];
-  out[o] = (sigma + 6.0 * inv_h2) * wc[i] - inv_h2 * nb;
+  for (int x = threadIdx.x; x < n; x += blockDim.x) {
+    const long long i = l0 + x;
+    const long long o = (long long)c * vsz + i;
+    if (mp[i]) {
+      out[o] = plus ? plus[o] : 0.0;
+      continue;
+    }
+    double nb = 0.0;
+    if (x > 0) nb += wc[i - 1];
+    if (x < n - 1) nb += wc[i + 1];
+    if (y > 0) nb += wc[i - n];
+    if (y < n - 1) nb += wc[i + n];
+    if (z > 0) nb += wc[i - (long long)n * n];
+    if (z < n - 1) nb += wc[i + (long long)n * n];
+    out[o] = (sigma + 6.0 * inv_h2) * wc[i] - inv_h2 * nb;
+  }
 }
+
 
 // A[i + (c0+c)*n_in] = dens[(c0+c)][pos_in[i]] - u[c][idx_in[i]]
 __global__ void k_trace_columns(const double* __restrict__ dens, const double* __restrict__ u,
@@ -88,13 +94,62 @@ __device__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Rows j..m-1 in chunks of 4 rows per thread, the loads of a chunk in flight together.
+constexpr int RU = 4;
+
+// sum_{i >= j} v_i a_i with v_j = 1 (the reflector's implicit unit entry)
+__device__ double refl_dot(const double* __restrict__ v, const double* __restrict__ a, int m,
+                           int j, double* sh) {
+  double d = 0.0;
+  for (int b = j; b < m; b += RU * (int)blockDim.x) {
+    double vv[RU], aa[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int i = b + threadIdx.x + u * blockDim.x;
+      vv[u] = i < m ? (i == j ? 1.0 : v[i]) : 0.0;
+      aa[u] = i < m ? a[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) d += vv[u] * aa[u];
+  }
+  return block_sum(d, sh);
+}
+
+// a_i -= w v_i for i >= j (v_j = 1)
+__device__ void refl_update(const double* __restrict__ v, double* __restrict__ a, int m, int j,
+                            double w) {
+  for (int b = j; b < m; b += RU * (int)blockDim.x) {
+    double vv[RU], aa[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int i = b + threadIdx.x + u * blockDim.x;
+      vv[u] = i < m ? (i == j ? 1.0 : v[i]) : 0.0;
+      aa[u] = i < m ? a[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int i = b + threadIdx.x + u * blockDim.x;
+      if (i < m) a[i] = aa[u] - w * vv[u];
+    }
+  }
+}
+
 // Householder reflector of column j (LAPACK dlarfg convention): on exit A[j,j] = beta (= R_jj),
 // A[j+1:, j] = v (v_0 = 1 implicit), tau[j].  One block.
 __global__ void k_house(double* __restrict__ A, int m, int j, double* __restrict__ tau) {
   __shared__ double sh[16];
   double* col = A + (long long)j * m;
   double ss = 0.0;
-  for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) ss += col[i] * col[i];
+  for (int b = j + 1; b < m; b += RU * (int)blockDim.x) {
+    double cv[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int i = b + threadIdx.x + u * blockDim.x;
+      cv[u] = i < m ? col[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) ss += cv[u] * cv[u];
+  }
   const double sigma2 = block_sum(ss, sh);
   const double alpha = col[j];
   if (sigma2 == 0.0) {
@@ -121,10 +176,8 @@ __global__ void k_apply_house(double* __restrict__ A, int m, int ncols, int j,
   if (t == 0.0) return;
   const double* v = A + (long long)j * m;
   double* a = A + (long long)k * m;
-  double d = 0.0;
-  for (int i = j + threadIdx.x; i < m; i += blockDim.x) d += (i == j ? 1.0 : v[i]) * a[i];
-  const double w = t * block_sum(d, sh);
-  for (int i = j + threadIdx.x; i < m; i += blockDim.x) a[i] -= w * (i == j ? 1.0 : v[i]);
+  const double w = t * refl_dot(v, a, m, j, sh);
+  refl_update(v, a, m, j, w);
 }
 
 // Q1 = Q[:, 0:n] = H_0 H_1 ... H_{n-1} [I_n; 0], formed in place in E (m x n, column-major),
@@ -139,10 +192,8 @@ __global__ void k_apply_house_q(const double* __restrict__ A, int m, int n, int 
   if (t == 0.0) return;
   const double* v = A + (long long)j * m;
   double* e = E + (long long)c * m;
-  double d = 0.0;
-  for (int i = j + threadIdx.x; i < m; i += blockDim.x) d += (i == j ? 1.0 : v[i]) * e[i];
-  const double w = t * block_sum(d, sh);
-  for (int i = j + threadIdx.x; i < m; i += blockDim.x) e[i] -= w * (i == j ? 1.0 : v[i]);
+  const double w = t * refl_dot(v, e, m, j, sh);
+  refl_update(v, e, m, j, w);
 }
 
 __global__ void k_identity_cols(double* __restrict__ E, int m, int n) {
@@ -259,9 +310,8 @@ void scatter_density(const double* dens, int c0, int ncol, int ng, const int32_t
 
 void minus_operator(const double* w, const uint8_t* mp, const double* plus, double* out, int n,
                     double sigma, double inv_h2, int nvol, hipStream_t s) {
-  const long long vsz = (long long)n * n * n;
-  hipLaunchKernelGGL(k_minus_operator, dim3(grid1(vsz), nvol), dim3(kB), 0, s, w, mp, plus, out,
-                     n, sigma, inv_h2, nvol);
+  hipLaunchKernelGGL(k_minus_operator, dim3((unsigned)(n * n), nvol), dim3(n < 128 ? 128 : 256), 0,
+                     s, w, mp, plus, out, n, sigma, inv_h2, nvol);
 }
 
 void gather(const double* vol, long long vsz, const int32_t* idx, int m, int nvec, double* out,
