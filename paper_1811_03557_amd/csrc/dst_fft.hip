@@ -573,8 +573,11 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
   const int j0 = LINEMAJOR ? tid % JPI : tid / W;
   const int wl = min(w, nlines - 1);                    // lines past the tile's end reload one
   const unsigned off0 = (unsigned)(wl * (int)S_LINE + j0 * (int)S_ELEM) * (unsigned)sizeof(T);
-  const unsigned offl = (unsigned)(wl * (int)S_LINE + min(j0 + JPI * (NSTEP - 1), N - 1) *
-                                   (int)S_ELEM) * (unsigned)sizeof(T);  // last step, clamped
+  // last step, clamped to j <= N - 1, relative to that step's base like every other step (an
+  // absolute element offset overflows 32 bits along z at N = 1023)
+  constexpr int JLAST = JPI * (NSTEP - 1);
+  const unsigned offl = (unsigned)(wl * (int)S_LINE + min(j0, N - 1 - JLAST) * (int)S_ELEM) *
+                        (unsigned)sizeof(T);
   T* const lds0 = tile + w * P + j0 + 1;                // slot of step 0; step i adds JPI*i
   const int jl = min(j0 + JPI * (NSTEP - 1), N);        // last step's slot (N: unused line[M])
   // per-thread line coordinates (x sweep, residual mode)
@@ -599,7 +602,7 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
         const int i = c0 + k;
         if (i >= NSTEP) break;
         const unsigned off = i < IFULL ? off0 : offl;
-        const long long step = i < IFULL ? (long long)i * JPI * S_ELEM : 0;
+        const long long step = (long long)i * JPI * S_ELEM;
         if constexpr (IN == IN_RESID) {
           // FP64 residual b - (sigma - Lap_h) u at (x, y, z) = (j, lny, lnz)
           const double* __restrict__ ub = p.u + base + step;
@@ -750,15 +753,14 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
         // all reads of u before its first write (the stores may alias the reads)
 #pragma unroll
         for (int i = 0; i < NSTEP; ++i)
-          old[i] = ld(static_cast<const double*>(p.out) + base +
-                          (i < IFULL ? (long long)i * JPI * S_ELEM : 0),
+          old[i] = ld(static_cast<const double*>(p.out) + base + (long long)i * JPI * S_ELEM,
                       i < IFULL ? off0 : offl);
       }
 #pragma unroll
       for (int i = 0; i < NSTEP; ++i) {
         if (i >= IFULL && j0 + JPI * i >= N) break;
         const unsigned off = i < IFULL ? off0 : offl;
-        const long long step = i < IFULL ? (long long)i * JPI * S_ELEM : 0;
+        const long long step = (long long)i * JPI * S_ELEM;
         if constexpr (OUT == OUT_UPD) {
           const double nu = old[i] + (double)v[i];
           st(static_cast<double*>(p.out) + base + step, off, nu);

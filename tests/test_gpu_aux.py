@@ -110,6 +110,29 @@ def test_eigenmode_closed_form_511(prec, kw, modes, tol):
         assert oaux.rel_err_inf(u, b / (1.0 + lam)) < tol, (k1, k2, k3)
 
 
+def test_eigenmode_closed_form_1023():
+    """N = 1023, the largest grid the solver takes (8.6 GB per FP64 volume, 8-line tiles, a
+    512-point complex FFT per line): a sine mode is solved exactly.  The separable right-hand
+    side and its closed-form solution are formed on the device from FP64 sine vectors."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    n = 1023
+    say("eigenmode n=1023")
+    h, _ = inp.grid(n)
+    j = np.arange(1, n + 1)
+    k1, k2, k3 = 5, 1000, 333
+    s = [torch.from_numpy(np.sin(np.pi * ((j * k) % (2 * (n + 1))) / (n + 1))).to(dev)
+         for k in (k1, k2, k3)]
+    lam = sum(4.0 / h**2 * np.sin(np.pi * k / (2 * (n + 1))) ** 2 for k in (k1, k2, k3))
+    b = (s[2][:, None, None] * s[1][None, :, None]) * s[0][None, None, :]
+    u = api.aux_solve_batched(b[None], 1.0, h)[0]
+    b.div_(1.0 + lam)  # the exact solution, in place
+    err = (u - b).abs().max().item() / b.abs().max().item()
+    say(f"n=1023 rel err {err:.2e}")
+    assert err < 1e-12
+
+
 def test_eigenmode_closed_form_full_size():
     """At N = 255 a single sine mode is solved exactly (property at any size)."""
     dev = need_gpu()
