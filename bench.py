@@ -67,47 +67,54 @@ def log(*a):
 
 def run_serving(args, dev):
     """Continuous batching over a mixed request stream: a closed-loop run (every request
-    queued at t = 0) measures the saturation rate, then Poisson arrivals at 0.7x that rate give
-    the latency percentiles."""
+    queued at t = 0) measures the saturation rate, then Poisson arrivals at 0.3, 0.5, 0.7 and
+    0.9 times that rate give the latency percentiles (0.7 is the reported operating point)."""
     import torch
     import dpm_inputs as inp
     from paper_1811_03557_amd import serve
 
-    def one(closed, qps, nreq, seed):
-        arrays = inp.serving_workload(n_sims=args.serve_sims, n_requests=nreq, qps=qps,
-                                      seed=seed, closed_loop=closed)
-        sims, reqs = serve.build_requests(*arrays)
-        srv = serve.Server(sims, device=dev, prec="fp64", rtol=args.rtol)
-        srv.run(reqs[: min(64, nreq)])        # warm-up: plans, allocator, first launches
-        sims, reqs = serve.build_requests(*arrays)
-        t = time.perf_counter()
-        out = srv.run(reqs)
-        wall = time.perf_counter() - t
-        summ = serve.summarize(out)
-        summ["wall_s"] = wall
-        summ["hbm_footprint_gb"] = srv.footprint() / 1e9
-        del srv
-        torch.cuda.synchronize()
-        return summ
+    nreq = args.serve_requests
+    base = inp.serving_workload(n_sims=args.serve_sims, n_requests=nreq, seed=11,
+                                closed_loop=True)
+    sims, reqs = serve.build_requests(*base)
+    srv = serve.Server(sims, device=dev, prec="fp64", rtol=args.rtol)
+    srv.run(reqs[: min(64, nreq)])            # warm-up: plans, allocator, first launches
 
-    sat = one(True, 0.0, args.serve_requests, 11)
+    def one(arrays):
+        _, rq = serve.build_requests(*arrays)
+        return serve.summarize(srv.run(rq))
+
+    sat = one(base)
     log(f"[bench] serving closed loop: {sat['requests_per_s']:.1f} req/s, "
         f"{sat['solves_per_s']:.1f} solves/s, mean batch {sat['mean_batch']:.2f}")
-    qps = 0.7 * sat["requests_per_s"]
-    opn = one(False, qps, args.serve_requests, 12)
-    log(f"[bench] serving open loop at {qps:.1f} req/s: p50 {opn['p50_ms']:.2f} ms, "
-        f"p99 {opn['p99_ms']:.2f} ms, {opn['requests_per_s']:.1f} req/s")
-    return {"workload": f"{args.serve_sims} simulations, N uniform over 31/63/127/255, sigma "
-                        f"log-uniform [1, 1e4]; half advance DPM steps (4 solves each), half "
-                        f"issue aux solves with their own sigma; {args.serve_requests} requests",
-            "saturation_requests_per_s": round(sat["requests_per_s"], 1),
-            "saturation_solves_per_s": round(sat["solves_per_s"], 1),
-            "offered_requests_per_s": round(qps, 1),
-            "requests_per_s": round(opn["requests_per_s"], 1),
-            "solves_per_s": round(opn["solves_per_s"], 1),
-            "p50_ms": round(opn["p50_ms"], 3), "p99_ms": round(opn["p99_ms"], 3),
-            "mean_batch": round(opn["mean_batch"], 2), "per_n": opn["per_n"],
-            "hbm_footprint_gb": round(opn["hbm_footprint_gb"], 2)}
+    sweep = {}
+    for f in (0.3, 0.5, 0.7, 0.9):
+        qps = f * sat["requests_per_s"]
+        arrays = inp.serving_workload(n_sims=args.serve_sims, n_requests=nreq, qps=qps,
+                                      seed=11, closed_loop=False)
+        r = one(arrays)
+        sweep[f] = dict(r, offered=qps)
+        log(f"[bench] serving open loop at {f:.1f}x = {qps:.1f} req/s: p50 {r['p50_ms']:.2f} ms, "
+            f"p99 {r['p99_ms']:.2f} ms, {r['requests_per_s']:.1f} req/s")
+    opn = sweep[0.7]
+    out = {"workload": f"{args.serve_sims} simulations, N uniform over 31/63/127/255, sigma "
+                       f"log-uniform [1, 1e4]; half advance DPM steps (4 solves each), half "
+                       f"issue aux solves with their own sigma; {nreq} requests per run",
+           "saturation_requests_per_s": round(sat["requests_per_s"], 1),
+           "saturation_solves_per_s": round(sat["solves_per_s"], 1),
+           "offered_requests_per_s": round(opn["offered"], 1),
+           "requests_per_s": round(opn["requests_per_s"], 1),
+           "solves_per_s": round(opn["solves_per_s"], 1),
+           "p50_ms": round(opn["p50_ms"], 3), "p99_ms": round(opn["p99_ms"], 3),
+           "mean_batch": round(opn["mean_batch"], 2), "per_n": opn["per_n"],
+           "load_sweep": {str(f): {"offered_requests_per_s": round(v["offered"], 1),
+                                   "p50_ms": round(v["p50_ms"], 3), "p99_ms": round(v["p99_ms"], 3),
+                                   "requests_per_s": round(v["requests_per_s"], 1)}
+                          for f, v in sweep.items()},
+           "hbm_footprint_gb": round(srv.footprint() / 1e9, 2)}
+    del srv
+    torch.cuda.synchronize()
+    return out
 
 
 def run_pks(args, dev):
@@ -195,7 +202,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall time of the oracle sample timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=600,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving run (0 = skip)")
     ap.add_argument("--serve-sims", type=int, default=64)
     ap.add_argument("--pks-steps", type=int, default=200, help="time-loop steps (0 = skip)")

@@ -1,15 +1,17 @@
 """Continuous-batching server for auxiliary-problem and DPM-step requests on one GPU.
 
-Many simulations issue requests of uneven grid sizes.  Each grid size N is a size class with
-its own HIP stream, so work of different classes overlaps on the device.  An aux request owns
-a slot of its class's ring of device-resident right-hand-side/solution buffers; ready requests
-in consecutive slots are launched together as one `aux_solve_batched_sigma` (each keeps its
-own sigma), so requests that arrive while others run join the next launch instead of waiting
-for a fixed batch.  A DPM-step request advances its simulation's resident state with its
-resident boundary matrix (`dpm_step`); the class stream orders the steps of a simulation.
-Admission is by HBM footprint: a class's ring holds as many slots as its share of the budget
-allows, and a request is admitted when a slot is free (first come, first served).  Completion
-times come from GPU events, latencies are arrival -> completion.
+Many simulations issue requests of uneven grid sizes.  Each grid size N is a size class with its
+own HIP stream(s), so work of different classes overlaps on the device (one stream per class by
+default: a second stream let two large requests of one class slow each other down, measured).  An aux
+request owns a slot of its class's ring of device-resident right-hand-side/solution buffers;
+ready requests in consecutive slots are launched together as one `aux_solve_batched_sigma` (each
+keeps its own sigma), so requests that arrive while others run join the next launch instead of
+waiting for a fixed batch.  A DPM-step request advances its simulation's resident state with its
+resident boundary matrix (`dpm_step`); every simulation is pinned to one stream of its class, so
+its steps run in arrival order.  Each stream has its own workspaces.  Admission is per class and
+first come, first served: a class's ring holds as many slots as its share of the HBM budget
+allows, and an aux request is admitted when a slot of its class is free (a full class does not
+hold up the others).  Completion times come from GPU events; latency is arrival -> completion.
 
 Host orchestration only: every arithmetic step runs in libdpm's kernels.
 """
@@ -51,13 +53,23 @@ class Simulation:
     kind: str            # "aux" or "step"
 
 
+class Lane:
+    """One stream of a size class with its own solve and step workspaces."""
+
+    def __init__(self, device, aux_ws_bytes: int):
+        self.stream = torch.cuda.Stream(device=device)
+        self.ws = torch.empty(max(1, aux_ws_bytes), dtype=torch.uint8, device=device)
+        self.step_ws = None
+        self.steps: collections.deque = collections.deque()  # step requests pinned here
+        self.inflight = 0
+
+
 class SizeClass:
     def __init__(self, n: int, slots: int, max_batch: int, device, prec: str, rtol: float,
-                 max_refine: int, seed: int):
+                 max_refine: int, seed: int, lanes: int):
         self.n = n
         self.h = 3.0 / (n + 1)
         self.x0 = -1.5 + self.h
-        self.stream = torch.cuda.Stream(device=device)
         self.slots = slots
         self.max_batch = max_batch
         self.prec, self.rtol, self.max_refine = prec, rtol, max_refine
@@ -67,36 +79,39 @@ class SizeClass:
         self.u = torch.zeros_like(self.b)
         gr = api.grid(n, self.h, 1.0)
         o = api.opts(prec, True, rtol, max_refine)
-        self.ws = torch.empty(max(1, api.workspace_size(gr, max_batch, o)), dtype=torch.uint8,
-                              device=device)
+        wsb = api.workspace_size(gr, max_batch, o)
+        self.lanes = [Lane(device, wsb) for _ in range(lanes)]
         self.free = collections.deque(range(slots))
-        self.ready: collections.deque = collections.deque()   # admitted aux requests, slot order
-        self.steps: collections.deque = collections.deque()   # admitted step requests
-        self.step_ws = None
+        self.pending: collections.deque = collections.deque()  # arrived, not yet admitted
+        self.ready: collections.deque = collections.deque()    # admitted aux requests
 
     def footprint(self) -> int:
-        return 2 * self.b.numel() * 8 + self.ws.numel()
+        ws = sum(l.ws.numel() + (l.step_ws.numel() if l.step_ws is not None else 0)
+                 for l in self.lanes)
+        return 2 * self.b.numel() * 8 + ws
 
 
 class Server:
     def __init__(self, sims, device="cuda:0", hbm_budget: float = 64e9, max_batch: int = 8,
                  prec: str = "fp64", rtol: float = 1e-10, max_refine: int = 0, lmax: int = 4,
-                 chi: float = 1.0, keep_results: bool = False, seed: int = 0):
+                 chi: float = 1.0, keep_results: bool = False, lanes: int = 1, seed: int = 0):
         self.device = torch.device(device)
         self.chi = chi
         self.keep = keep_results
         self.sims = {s.sid: s for s in sims}
         sizes = sorted({s.n for s in sims})
-        # HBM admission: each class gets a share of the budget proportional to its volume
+        # HBM admission: each class gets an equal share of the budget for its slot ring
         per_slot = {n: 2 * 8 * n ** 3 for n in sizes}
         share = hbm_budget / max(1, len(sizes))
         self.classes = {}
         for i, n in enumerate(sizes):
             slots = int(max(1, min(4 * max_batch, share // per_slot[n])))
             self.classes[n] = SizeClass(n, slots, min(max_batch, slots), self.device, prec, rtol,
-                                        max_refine, seed + i)
-        # resident DPM state: boundary matrix (sigma = 1/dt) and (rho, c) per step simulation
-        self.bep, self.state = {}, {}
+                                        max_refine, seed + i, lanes)
+        # resident DPM state: boundary matrix (sigma = 1/dt) and (rho, c) per step simulation,
+        # each simulation pinned to one lane of its class
+        self.bep, self.state, self.lane_of = {}, {}, {}
+        o64 = api.opts("fp64", True, rtol, 0)
         for s in sims:
             if s.kind != "step":
                 continue
@@ -109,90 +124,93 @@ class Server:
             rho = api.gauss_state(bep, geo, 1000.0, 100.0)
             cc = api.gauss_state(bep, geo, 500.0, 50.0)
             self.bep[s.sid], self.state[s.sid] = bep, (rho, cc)
-            if c.step_ws is None:
-                o = api.opts("fp64", True, rtol, 0)
-                c.step_ws = torch.empty(api.step_workspace_size(bep, o), dtype=torch.uint8,
-                                        device=self.device)
-            elif c.step_ws.numel() < api.step_workspace_size(bep, api.opts("fp64", True, rtol, 0)):
-                c.step_ws = torch.empty(api.step_workspace_size(bep, api.opts("fp64", True, rtol, 0)),
-                                        dtype=torch.uint8, device=self.device)
+            lane = c.lanes[s.sid % len(c.lanes)]
+            self.lane_of[s.sid] = lane
+            need = api.step_workspace_size(bep, o64)
+            if lane.step_ws is None or lane.step_ws.numel() < need:
+                lane.step_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         torch.cuda.synchronize()
 
     def footprint(self) -> int:
         return sum(c.footprint() for c in self.classes.values())
 
     # ------------------------------------------------------------------ launches
-    def _launch_aux(self, c: SizeClass, reqs, inflight):
+    def _launch_aux(self, c: SizeClass, lane: Lane, reqs, inflight):
         first = reqs[0].slot
         k = len(reqs)
         sig = [r.sigma for r in reqs]
         api.aux_solve_batched_sigma(c.b[first:first + k], sig, c.h, prec=c.prec, rtol=c.rtol,
                                     max_refine=c.max_refine, out=c.u[first:first + k],
-                                    workspace=c.ws, stream=c.stream)
+                                    workspace=lane.ws, stream=lane.stream)
         ev = torch.cuda.Event(enable_timing=True)
-        ev.record(c.stream)
+        ev.record(lane.stream)
         for i, r in enumerate(reqs):
             r.batch = k
             if self.keep:
-                with torch.cuda.stream(c.stream):
+                with torch.cuda.stream(lane.stream):
                     r.out = c.u[first + i].clone()
-        inflight.append((ev, reqs, c))
+        inflight.append((ev, reqs, c, lane))
 
-    def _launch_step(self, c: SizeClass, r: Request, inflight):
+    def _launch_step(self, c: SizeClass, lane: Lane, r: Request, inflight):
         bep = self.bep[r.sim]
         rho, cc = self.state[r.sim]
-        api.dpm_step(bep, 1.0 / bep.sigma, self.chi, rho, cc, rho, cc, workspace=c.step_ws,
-                     stream=c.stream)
+        api.dpm_step(bep, 1.0 / bep.sigma, self.chi, rho, cc, rho, cc, workspace=lane.step_ws,
+                     stream=lane.stream)
         ev = torch.cuda.Event(enable_timing=True)
-        ev.record(c.stream)
+        ev.record(lane.stream)
         r.batch = 1
         if self.keep:
-            with torch.cuda.stream(c.stream):
+            with torch.cuda.stream(lane.stream):
                 r.out = (rho.clone(), cc.clone())
-        inflight.append((ev, [r], c))
+        inflight.append((ev, [r], c, lane))
 
     # ------------------------------------------------------------------ the loop
-    def run(self, requests, max_inflight_per_class: int = 2):
+    def run(self, requests, max_inflight_per_lane: int = 2):
         """Serve `requests` (arrival times relative to the start); returns the requests with
         their completion times filled in."""
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
-        pending = collections.deque(reqs)
+        arriving = collections.deque(reqs)
         inflight = []
         done = 0
         e0 = torch.cuda.Event(enable_timing=True)
         e0.record()
         e0.synchronize()
         t0 = time.perf_counter()
-        nfl = collections.Counter()
         while done < len(reqs):
             now = time.perf_counter() - t0
-            # admission: first come, first served, while the head request fits
-            while pending and pending[0].arrival <= now:
-                r = pending[0]
-                c = self.classes[r.n]
-                if r.kind == "aux":
-                    if not c.free:
-                        break
-                    r.slot = c.free.popleft()
-                    c.ready.append(r)
-                else:
-                    c.steps.append(r)
-                pending.popleft()
-            # launches: continuous batching per class
-            for n, c in self.classes.items():
-                while nfl[n] < max_inflight_per_class and (c.ready or c.steps):
-                    if c.ready:
-                        batch = [c.ready.popleft()]
-                        while (c.ready and len(batch) < c.max_batch
-                               and c.ready[0].slot == batch[-1].slot + 1):
-                            batch.append(c.ready.popleft())
-                        self._launch_aux(c, batch, inflight)
+            while arriving and arriving[0].arrival <= now:
+                r = arriving.popleft()
+                self.classes[r.n].pending.append(r)
+            for c in self.classes.values():
+                # admission, first come first served within the class
+                while c.pending:
+                    r = c.pending[0]
+                    if r.kind == "aux":
+                        if not c.free:
+                            break
+                        r.slot = c.free.popleft()
+                        c.ready.append(r)
                     else:
-                        self._launch_step(c, c.steps.popleft(), inflight)
-                    nfl[n] += 1
+                        self.lane_of[r.sim].steps.append(r)
+                    c.pending.popleft()
+                # launches: each lane takes the older of its next step and the class's next
+                # aux batch (consecutive slots, up to max_batch)
+                for lane in c.lanes:
+                    while lane.inflight < max_inflight_per_lane and (c.ready or lane.steps):
+                        take_step = bool(lane.steps) and (
+                            not c.ready or lane.steps[0].arrival <= c.ready[0].arrival)
+                        if take_step:
+                            self._launch_step(c, lane, lane.steps.popleft(), inflight)
+                        else:
+                            batch = [c.ready.popleft()]
+                            while (c.ready and len(batch) < c.max_batch
+                                   and c.ready[0].slot == batch[-1].slot + 1):
+                                batch.append(c.ready.popleft())
+                            self._launch_aux(c, lane, batch, inflight)
+                        lane.inflight += 1
             # completions
             still = []
-            for ev, rs, c in inflight:
+            for ev, rs, c, lane in inflight:
                 if ev.query():
                     t = e0.elapsed_time(ev) * 1e-3
                     for r in rs:
@@ -200,12 +218,12 @@ class Server:
                         if r.kind == "aux":
                             c.free.append(r.slot)
                     done += len(rs)
-                    nfl[c.n] -= 1
+                    lane.inflight -= 1
                 else:
-                    still.append((ev, rs, c))
+                    still.append((ev, rs, c, lane))
             inflight = still
-            if not inflight and pending and pending[0].arrival > now:
-                time.sleep(min(1e-4, pending[0].arrival - now))
+            if not inflight and arriving and arriving[0].arrival > now:
+                time.sleep(min(1e-4, arriving[0].arrival - now))
         torch.cuda.synchronize()
         return reqs
 
