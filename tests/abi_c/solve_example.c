@@ -1,0 +1,139 @@
+/*
+ * A C program that drives libdpm through its C ABI alone (no Python): one auxiliary-problem solve
+ * of a sine mode checked against its closed form, the argument checks, and a short DPM time loop
+ * on the unit sphere (classification, discrete boundary, densities, boundary matrix, captured
+ * steps).  Prints "ok" and returns 0 on success.
+ */
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <hip/hip_runtime_api.h>
+
+#include "dpm.h"
+
+#define CHECK(call)                                                                   \
+  do {                                                                                \
+    dpm_status st_ = (call);                                                          \
+    if (st_ != DPM_OK) {                                                              \
+      fprintf(stderr, "%s failed (%d): %s\n", #call, (int)st_, dpm_last_error());     \
+      return 1;                                                                       \
+    }                                                                                 \
+  } while (0)
+#define HCHECK(call)                                                                  \
+  do {                                                                                \
+    if ((call) != hipSuccess) {                                                       \
+      fprintf(stderr, "%s failed\n", #call);                                          \
+      return 1;                                                                       \
+    }                                                                                 \
+  } while (0)
+
+static const double kPi = 3.14159265358979323846;
+
+int main(void) {
+  const int n = 31;
+  const double h = 3.0 / (n + 1), x0 = -1.5 + h, sigma = 2.0;
+  const size_t vol = (size_t)n * n * n;
+
+  /* ---- 1. sine mode (k1, k2, k3): u = b / (sigma + lambda_k1 + lambda_k2 + lambda_k3) */
+  const int k1 = 3, k2 = 17, k3 = 31;
+  double* b = (double*)malloc(sizeof(double) * vol);
+  double* u = (double*)malloc(sizeof(double) * vol);
+  if (!b || !u) return 1;
+  double lam = 0.0;
+  const int ks[3] = {k1, k2, k3};
+  for (int a = 0; a < 3; ++a) {
+    const double s = sin(kPi * ks[a] / (2.0 * (n + 1)));
+    lam += 4.0 / (h * h) * s * s;
+  }
+  for (int z = 0; z < n; ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x)
+        b[((size_t)z * n + y) * n + x] = sin(kPi * (double)((x + 1) * k1 % (2 * (n + 1))) / (n + 1)) *
+                                         sin(kPi * (double)((y + 1) * k2 % (2 * (n + 1))) / (n + 1)) *
+                                         sin(kPi * (double)((z + 1) * k3 % (2 * (n + 1))) / (n + 1));
+  double *db = NULL, *du = NULL;
+  HCHECK(hipMalloc((void**)&db, sizeof(double) * vol));
+  HCHECK(hipMalloc((void**)&du, sizeof(double) * vol));
+  HCHECK(hipMemcpy(db, b, sizeof(double) * vol, hipMemcpyHostToDevice));
+  dpm_grid g = {n, h, sigma, x0};
+  dpm_opts o = {DPM_FP64, 1, 1e-10, 0, 0, NULL, 0};
+  size_t wsb = 0;
+  CHECK(dpm_workspace_size(&g, 1, &o, &wsb));
+  void* ws = NULL;
+  HCHECK(hipMalloc(&ws, wsb > 0 ? wsb : 1));
+  o.workspace = ws;
+  o.workspace_bytes = wsb;
+  CHECK(aux_solve(&g, db, du, &o, NULL, NULL));
+  HCHECK(hipMemcpy(u, du, sizeof(double) * vol, hipMemcpyDeviceToHost));
+  double err = 0.0, mx = 0.0;
+  for (size_t i = 0; i < vol; ++i) {
+    const double ref = b[i] / (sigma + lam);
+    err = fmax(err, fabs(u[i] - ref));
+    mx = fmax(mx, fabs(ref));
+  }
+  printf("sine mode n=%d rel err %.2e\n", n, err / mx);
+  if (!(err <= 1e-12 * mx)) return 1;
+
+  /* ---- 2. argument checks: nothing is launched, the error text names the problem */
+  dpm_grid bad = {30, h, sigma, x0};
+  if (aux_solve(&bad, db, du, &o, NULL, NULL) != DPM_EINVAL) return 1;
+  printf("n = 30 rejected: %s\n", dpm_last_error());
+  dpm_grid negs = {n, h, -1.0, x0};
+  if (aux_solve(&negs, db, du, &o, NULL, NULL) != DPM_EINVAL) return 1;
+
+  /* ---- 3. DPM time loop on the unit sphere (l <= 2, beta = 1: 18 densities) */
+  const double dt = 0.5 * h * h;
+  dpm_grid gs = {n, h, 1.0 / dt, x0};
+  dpm_geometry geo = {0, {0.0, 0.0, 0.0}, {1.0, 1.0, 1.0}};
+  uint8_t* mp = NULL;
+  HCHECK(hipMalloc((void**)&mp, vol));
+  CHECK(dpm_classify(&gs, &geo, mp, NULL));
+  int32_t ng = 0, ngi = 0;
+  CHECK(dpm_gamma_points(&gs, mp, &ng, &ngi, NULL, NULL, NULL));
+  int32_t* idx = NULL;
+  uint8_t* is_in = NULL;
+  HCHECK(hipMalloc((void**)&idx, sizeof(int32_t) * ng));
+  HCHECK(hipMalloc((void**)&is_in, (size_t)ng));
+  CHECK(dpm_gamma_points(&gs, mp, &ng, &ngi, idx, is_in, NULL));
+  const int lmax = 2, nb = 2 * (lmax + 1) * (lmax + 1);
+  double *basis = NULL, *dist = NULL;
+  HCHECK(hipMalloc((void**)&basis, sizeof(double) * (size_t)nb * ng));
+  HCHECK(hipMalloc((void**)&dist, sizeof(double) * ng));
+  CHECK(dpm_basis(&gs, &geo, ng, idx, lmax, 1, basis, dist, NULL));
+  dpm_bep* bep = NULL;
+  CHECK(dpm_build_boundary_matrix(&gs, mp, nb, basis, &o, NULL, &bep, NULL));
+  double *rho = NULL, *c = NULL;
+  HCHECK(hipMalloc((void**)&rho, sizeof(double) * vol));
+  HCHECK(hipMalloc((void**)&c, sizeof(double) * vol));
+  const double c3[3] = {0.0, 0.0, 0.0};
+  CHECK(dpm_gauss_state(bep, &geo, 10.0, 4.0, c3, rho, NULL));
+  CHECK(dpm_gauss_state(bep, &geo, 5.0, 2.0, c3, c, NULL));
+  dpm_opts so = {DPM_FP64, 1, 1e-10, 0, 0, NULL, 0};
+  size_t swb = 0;
+  CHECK(dpm_step_workspace_size(bep, &so, &swb));
+  void* sws = NULL;
+  HCHECK(hipMalloc(&sws, swb));
+  so.workspace = sws;
+  so.workspace_bytes = swb;
+  dpm_stepper* st = NULL;
+  CHECK(dpm_stepper_create(bep, dt, 1.0, rho, c, &so, NULL, &st));
+  CHECK(dpm_stepper_run(st, 3, NULL));
+  int32_t bad_step = -1;
+  CHECK(dpm_stepper_first_nonfinite(st, NULL, &bad_step));
+  HCHECK(hipMemcpy(u, rho, sizeof(double) * vol, hipMemcpyDeviceToHost));
+  double mass = 0.0;
+  for (size_t i = 0; i < vol; ++i) mass += u[i];
+  printf("dpm: |gamma| = %d, |gamma_in| = %d, 3 captured steps, first non-finite step %d, "
+         "sum rho %.6e\n", ng, ngi, bad_step, mass);
+  if (bad_step != 0 || !(mass > 0.0) || !isfinite(mass)) return 1;
+  dpm_stepper_destroy(st);
+  dpm_bep_destroy(bep);
+  (void)hipFree(sws); (void)hipFree(rho); (void)hipFree(c); (void)hipFree(basis);
+  (void)hipFree(dist); (void)hipFree(idx); (void)hipFree(is_in); (void)hipFree(mp);
+  (void)hipFree(ws); (void)hipFree(db); (void)hipFree(du);
+  free(b);
+  free(u);
+  printf("ok\n");
+  return 0;
+}

@@ -8,14 +8,16 @@ from gpu_util import need_gpu, say
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_equal_standalone_runs():
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_served_results_equal_standalone_runs(lanes):
     import torch
     from paper_1811_03557_amd import api, serve
     dev = need_gpu()
     sims, reqs = serve.build_requests(*inp.serving_workload(
         n_sims=8, n_requests=48, seed=3, sizes=(15, 31, 63), closed_loop=True))
     say(f"serve: {len(sims)} simulations, {len(reqs)} requests")
-    srv = serve.Server(sims, device=dev, hbm_budget=2e8, max_batch=4, lmax=2, keep_results=True)
+    srv = serve.Server(sims, device=dev, hbm_budget=2e8, max_batch=4, lmax=2, keep_results=True,
+                       lanes=lanes)
     # initial states, before any step runs
     init = {sid: (r.clone(), c.clone()) for sid, (r, c) in srv.state.items()}
     out = srv.run(reqs)
