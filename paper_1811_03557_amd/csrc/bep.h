@@ -17,6 +17,7 @@ struct dpm_bep {
   double* A = nullptr;        // n_in x n_basis, column-major: Householder vectors below R
   double* tau = nullptr;      // n_basis reflector scalars
   double* P = nullptr;        // n_basis x n_in least-squares operator R^-1 Q1^T (row nu contiguous)
+  int32_t* gpos = nullptr;    // N^3: position of each node in the gamma list, -1 off gamma
   double rdiag_min = 0.0, rdiag_max = 0.0;
 };
 
@@ -32,11 +33,9 @@ struct dpm_stepper {
 namespace dpm {
 
 void fill_zero(double* p, long long n, hipStream_t s);
-void scatter_density(const double* dens, int c0, int ncol, int ng, const int32_t* idx,
-                     double* vol, long long vsz, hipStream_t s);
-// out = M+ ? plus (or 0) : (sigma - Lap_h) w, for nvol volumes
-void minus_operator(const double* w, const uint8_t* mp, const double* plus, double* out, int n,
-                    double sigma, double inv_h2, int nvol, hipStream_t s);
+// out[c] = (sigma - Lap_h)[dens[c0 + c] on gamma, extended by zero] at the M- nodes where it can
+// be nonzero (gamma_ex and their M- neighbours); other entries of out are left as they are.
+void minus_rhs(const dpm_bep* b, const double* dens, int c0, int ncol, double* out, hipStream_t s);
 void gather(const double* vol, long long vsz, const int32_t* idx, int m, int nvec, double* out,
             hipStream_t s);
 // C[r] = R^-1 Q1^T g[r], r < nvec, as one product with the precomputed operator P

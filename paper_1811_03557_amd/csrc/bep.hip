@@ -22,45 +22,59 @@ __global__ void k_fill_zero(double* __restrict__ p, long long n) {
     p[i] = 0.0;
 }
 
-// vol[c][idx[i]] = dens[(c0 + c) * ng + i]: densities of columns c0.. extended by zero
-__global__ void k_scatter_density(const double* __restrict__ dens, int c0, int ncol, int ng,
-                                  const int32_t* __restrict__ idx, double* __restrict__ vol,
-                                  long long vsz) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (i >= ng || c >= ncol) return;
-  vol[(long long)c * vsz + idx[i]] = dens[(long long)(c0 + c) * ng + i];
-}
-
-// out = M- ? (sigma - Lap_h) w : keep (keep = 0, or the M+ part given in `plus`).  One block per
-// x-line (blockIdx.x = y + n z) and volume (blockIdx.y); the line's coordinates come from one
-// 32-bit division, x is the loop index.
-__global__ void k_minus_operator(const double* __restrict__ w, const uint8_t* __restrict__ mp,
-                                 const double* __restrict__ plus, double* __restrict__ out, int n,
-                                 double sigma, double inv_h2, int nvol) {
-  const unsigned line = blockIdx.x;
-  const int c = blockIdx.y;
-  const int z = (int)(line / (unsigned)n), y = (int)(line - (unsigned)z * (unsigned)n);
-  const long long vsz = (long long)n * n * n;
-  const long long l0 = (long long)line * n;
-  const double* wc = w + (long long)c * vsz;
-  for (int x = threadIdx.x; x < n; x += blockDim.x) {
-    const long long i = l0 + x;
-    const long long o = (long long)c * vsz + i;
-    if (mp[i]) {
-      out[o] = plus ? plus[o] : 0.0;
-      continue;
-    }
-    double nb = 0.0;
-    if (x > 0) nb += wc[i - 1];
-    if (x < n - 1) nb += wc[i + 1];
-    if (y > 0) nb += wc[i - n];
-    if (y < n - 1) nb += wc[i + n];
-    if (z > 0) nb += wc[i - (long long)n * n];
-    if (z < n - 1) nb += wc[i + (long long)n * n];
-    out[o] = (sigma + 6.0 * inv_h2) * wc[i] - inv_h2 * nb;
+// gpos[i] = position of node i in the gamma list, or -1.
+__global__ void k_gpos(const int32_t* __restrict__ idx, int ng, int32_t* __restrict__ gpos,
+                       long long vsz, int phase) {
+  if (phase == 0) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < vsz;
+         i += (long long)gridDim.x * blockDim.x)
+      gpos[i] = -1;
+  } else {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < ng) gpos[idx[k]] = k;
   }
 }
+
+// out[c][q] = (sigma - Lap_h)[v_c] at the M- nodes q where it can be nonzero, v_c the density
+// dens[c0 + c] on gamma extended by zero (zero Dirichlet data outside the cube).  Those nodes are
+// gamma_ex and the M- neighbours of gamma_ex (an M- neighbour of a gamma_in node is in
+// gamma_ex): thread (e, k) takes gamma node e, if it is in gamma_ex, and its k-th node of
+// {itself, 6 neighbours}; a node reached from two gamma_ex nodes gets the same value twice.
+// Other entries of out are left as they are (the caller has them at zero on M-).
+__device__ __forceinline__ double dens_at(const double* __restrict__ dr,
+                                          const int32_t* __restrict__ gpos, long long q) {
+  const int gi = gpos[q];
+  return gi >= 0 ? dr[gi] : 0.0;
+}
+
+__global__ void k_minus_rhs(const double* __restrict__ dens, int c0, int ng,
+                            const int32_t* __restrict__ idx, const uint8_t* __restrict__ is_in,
+                            const int32_t* __restrict__ gpos, const uint8_t* __restrict__ mp,
+                            int n, double sigma, double inv_h2, double* __restrict__ out,
+                            long long vsz) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  const int e = t / 7, k = t - 7 * (t / 7);
+  if (e >= ng || is_in[e]) return;
+  const unsigned p = (unsigned)idx[e], un = (unsigned)n;
+  int x = (int)(p % un), y = (int)((p / un) % un), z = (int)(p / (un * un));
+  // k: 0 self, 1/2 x-+, 3/4 y-+, 5/6 z-+
+  if (k == 1) --x; else if (k == 2) ++x; else if (k == 3) --y; else if (k == 4) ++y;
+  else if (k == 5) --z; else if (k == 6) ++z;
+  if (x < 0 || x >= n || y < 0 || y >= n || z < 0 || z >= n) return;
+  const long long q = ((long long)z * n + y) * n + x;
+  if (mp[q]) return;
+  const double* dr = dens + (long long)(c0 + c) * ng;
+  double nb = 0.0;
+  if (x > 0) nb += dens_at(dr, gpos, q - 1);
+  if (x < n - 1) nb += dens_at(dr, gpos, q + 1);
+  if (y > 0) nb += dens_at(dr, gpos, q - n);
+  if (y < n - 1) nb += dens_at(dr, gpos, q + n);
+  if (z > 0) nb += dens_at(dr, gpos, q - (long long)n * n);
+  if (z < n - 1) nb += dens_at(dr, gpos, q + (long long)n * n);
+  out[(long long)c * vsz + q] = (sigma + 6.0 * inv_h2) * dens_at(dr, gpos, q) - inv_h2 * nb;
+}
+
 
 
 // A[i + (c0+c)*n_in] = dens[(c0+c)][pos_in[i]] - u[c][idx_in[i]]
@@ -94,8 +108,8 @@ __device__ double block_sum(double v, double* sh) {
   return t;
 }
 
-// Rows j..m-1 in chunks of 4 rows per thread, the loads of a chunk in flight together.
-constexpr int RU = 4;
+// Rows j..m-1 in chunks of RU rows per thread, the loads of a chunk in flight together.
+constexpr int RU = 8;
 
 // sum_{i >= j} v_i a_i with v_j = 1 (the reflector's implicit unit entry)
 __device__ double refl_dot(const double* __restrict__ v, const double* __restrict__ a, int m,
@@ -180,27 +194,75 @@ __global__ void k_apply_house(double* __restrict__ A, int m, int ncols, int j,
   refl_update(v, a, m, j, w);
 }
 
-// Q1 = Q[:, 0:n] = H_0 H_1 ... H_{n-1} [I_n; 0], formed in place in E (m x n, column-major),
-// one reflector per launch from the last to the first; H_j changes only the columns c >= j
-// (the columns c < j are still e_c, which has no entry in rows >= j).  One block per column.
-__global__ void k_apply_house_q(const double* __restrict__ A, int m, int n, int j,
-                                const double* __restrict__ tau, double* __restrict__ E) {
-  __shared__ double sh[16];
-  const int c = j + blockIdx.x;
-  if (c >= n) return;
-  const double t = tau[j];
-  if (t == 0.0) return;
-  const double* v = A + (long long)j * m;
-  double* e = E + (long long)c * m;
-  const double w = t * refl_dot(v, e, m, j, sh);
-  refl_update(v, e, m, j, w);
+// Compact WY form of the reflectors (Schreiber-Van Loan): Q = H_0 ... H_{n-1} = I - V T V^T,
+// V (m x n) unit lower trapezoidal (the Householder vectors below R in A, with the implicit
+// unit diagonal), T (n x n) upper triangular.
+__device__ __forceinline__ double vval(const double* __restrict__ A, int m, int i, int k) {
+  return i == k ? 1.0 : (i > k ? A[(long long)k * m + i] : 0.0);
 }
 
-__global__ void k_identity_cols(double* __restrict__ E, int m, int n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)m * n) return;
-  const long long c = i / m, r = i - c * m;
-  E[i] = r == c ? 1.0 : 0.0;
+// G = V^T V (n x n, row-major), 16 x 16 output tiles, rows of V staged through LDS.
+__global__ void k_gram(const double* __restrict__ A, int m, int n, double* __restrict__ G) {
+  __shared__ double va[16][17], vb[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
+  const int lo = a0 > b0 ? a0 : b0;  // V[i][k] = 0 for i < k: rows i < max(a0, b0) add nothing
+  double acc = 0.0;
+  for (int i0 = lo; i0 < m; i0 += 16) {
+    // thread (ty, tx) loads row i0 + tx of columns a0 + ty and b0 + ty (consecutive rows)
+    const int i = i0 + tx;
+    va[tx][ty] = (i < m && a0 + ty < n) ? vval(A, m, i, a0 + ty) : 0.0;
+    vb[tx][ty] = (i < m && b0 + ty < n) ? vval(A, m, i, b0 + ty) : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc += va[r][tx] * vb[r][ty];
+    __syncthreads();
+  }
+  if (a0 + tx < n && b0 + ty < n) G[(long long)(a0 + tx) * n + b0 + ty] = acc;
+}
+
+// T (row-major, upper triangular).  With tau_j = 2 / (v_j^T v_j) (every reflector here, or
+// tau_j = 0), T^-1 is the upper triangle of G with 1/tau_j on the diagonal, so column c of T
+// solves that triangle against e_c: x_j = tau_j (delta_jc - sum_{j < k <= c} G[j][k] x_k),
+// which also gives a zero column for tau_j = 0.  One block per column.
+__global__ void k_tinv(const double* __restrict__ G, const double* __restrict__ tau, int n,
+                       double* __restrict__ T) {
+  __shared__ double sh[16];
+  __shared__ double x[1024];
+  const int c = blockIdx.x;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) x[k] = 0.0;
+  __syncthreads();
+  for (int j = c; j >= 0; --j) {
+    double d = 0.0;
+    for (int k = j + 1 + threadIdx.x; k <= c; k += blockDim.x) d += G[(long long)j * n + k] * x[k];
+    const double s = block_sum(d, sh);
+    if (threadIdx.x == 0) x[j] = tau[j] * ((j == c ? 1.0 : 0.0) - s);
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < n; k += blockDim.x) T[(long long)k * n + c] = x[k];
+}
+
+// W = V1 T^T with V1 = V[0:n, 0:n] (unit lower triangular): W[a][b] = sum_k V1[a][k] T[b][k],
+// nonzero terms for b <= k <= a.  One thread per entry.
+__global__ void k_v1tt(const double* __restrict__ A, int m, int n, const double* __restrict__ T,
+                       double* __restrict__ W) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int a = e / n, bcol = e - a * n;
+  double d = 0.0;
+  for (int k = bcol; k <= a; ++k) d += vval(A, m, a, k) * T[(long long)bcol * n + k];
+  W[e] = d;
+}
+
+// K = Rinv W (Rinv upper triangular: terms a >= nu).  One thread per entry.
+__global__ void k_kmat(const double* __restrict__ Rinv, const double* __restrict__ W, int n,
+                       double* __restrict__ K) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int nu = e / n, bcol = e - nu * n;
+  double d = 0.0;
+  for (int a = nu; a < n; ++a) d += Rinv[(long long)nu * n + a] * W[(long long)a * n + bcol];
+  K[e] = d;
 }
 
 // Rinv = R^-1 (n x n, row-major, upper triangular) with R the upper triangle of A: one block
@@ -221,16 +283,17 @@ __global__ void k_rinv(const double* __restrict__ A, int m, int n, double* __res
   for (int k = threadIdx.x; k < n; k += blockDim.x) Rinv[(long long)k * n + c] = x[k];
 }
 
-// P[nu][i] = sum_k Rinv[nu][k] Q1[i][k] for a tile of PT rows nu (Rinv rows in LDS) and one row
-// i of Q1 per thread (E column-major: Q1[i][k] = E[k m + i], coalesced across threads).
+// P = R^-1 Q1^T = [Rinv 0] - K V^T (Q1 = [I; 0] - V T V1^T): P[nu][i] = Rinv[nu][i] (i < n)
+// - sum_{k <= min(i, n-1)} K[nu][k] V[i][k], for a tile of PT rows nu (K rows in LDS) and one
+// row i of V per thread (V[i][k] = A[k m + i], coalesced across threads).
 constexpr int PT = 8;
-__global__ void k_form_p(const double* __restrict__ Rinv, const double* __restrict__ E, int m,
-                         int n, double* __restrict__ P) {
-  extern __shared__ double rt[];  // PT x n
+__global__ void k_form_p(const double* __restrict__ Rinv, const double* __restrict__ K,
+                         const double* __restrict__ A, int m, int n, double* __restrict__ P) {
+  extern __shared__ double kt[];  // PT x n
   const int nu0 = blockIdx.y * PT;
   for (int t = threadIdx.x; t < PT * n; t += blockDim.x) {
     const int r = t / n, k = t - r * n;
-    rt[t] = nu0 + r < n ? Rinv[(long long)(nu0 + r) * n + k] : 0.0;
+    kt[t] = nu0 + r < n ? K[(long long)(nu0 + r) * n + k] : 0.0;
   }
   __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -238,14 +301,16 @@ __global__ void k_form_p(const double* __restrict__ Rinv, const double* __restri
   double acc[PT];
 #pragma unroll
   for (int t = 0; t < PT; ++t) acc[t] = 0.0;
-  for (int k = nu0; k < n; ++k) {  // Rinv[nu][k] = 0 for k < nu
-    const double e = E[(long long)k * m + i];
+  const int kend = i < n - 1 ? i : n - 1;
+  for (int k = 0; k <= kend; ++k) {
+    const double v = vval(A, m, i, k);
 #pragma unroll
-    for (int t = 0; t < PT; ++t) acc[t] += rt[t * n + k] * e;
+    for (int t = 0; t < PT; ++t) acc[t] += kt[t * n + k] * v;
   }
 #pragma unroll
   for (int t = 0; t < PT; ++t)
-    if (nu0 + t < n) P[(long long)(nu0 + t) * m + i] = acc[t];
+    if (nu0 + t < n)
+      P[(long long)(nu0 + t) * m + i] = (i < n ? Rinv[(long long)(nu0 + t) * n + i] : 0.0) - acc[t];
 }
 
 // C[r][nu] = sum_i P[nu][i] g[r][i]: the least-squares coefficients of right-hand side r.
@@ -302,16 +367,13 @@ void fill_zero(double* p, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(kB), 0, s, p, n);
 }
 
-void scatter_density(const double* dens, int c0, int ncol, int ng, const int32_t* idx,
-                     double* vol, long long vsz, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter_density, dim3(grid1(ng), ncol), dim3(kB), 0, s, dens, c0, ncol,
-                     ng, idx, vol, vsz);
-}
-
-void minus_operator(const double* w, const uint8_t* mp, const double* plus, double* out, int n,
-                    double sigma, double inv_h2, int nvol, hipStream_t s) {
-  hipLaunchKernelGGL(k_minus_operator, dim3((unsigned)(n * n), nvol), dim3(n < 128 ? 128 : 256), 0,
-                     s, w, mp, plus, out, n, sigma, inv_h2, nvol);
+void minus_rhs(const dpm_bep* b, const double* dens, int c0, int ncol, double* out,
+               hipStream_t s) {
+  const dpm_grid& g = b->grid;
+  const long long vsz = (long long)g.n * g.n * g.n;
+  hipLaunchKernelGGL(k_minus_rhs, dim3(grid1(7LL * b->n_gamma), ncol), dim3(kB), 0, s, dens, c0,
+                     b->n_gamma, b->idx, b->is_in, b->gpos, b->m_plus, g.n, g.sigma,
+                     1.0 / (g.h * g.h), out, vsz);
 }
 
 void gather(const double* vol, long long vsz, const int32_t* idx, int m, int nvec, double* out,
@@ -353,7 +415,8 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
       !al((void**)&b->pos_in, sizeof(int32_t) * nin) ||
       !al((void**)&b->basis, sizeof(double) * (size_t)n_basis * ng) ||
       !al((void**)&b->A, sizeof(double) * (size_t)n_basis * nin) ||
-      !al((void**)&b->tau, sizeof(double) * n_basis)) {
+      !al((void**)&b->tau, sizeof(double) * n_basis) ||
+      !al((void**)&b->gpos, sizeof(int32_t) * vsz)) {
     set_error("dpm_build_boundary_matrix: device allocation failed");
     return fail(DPM_ENOMEM);
   }
@@ -388,6 +451,8 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
                          b->idx_in, b->pos_in);
       hipLaunchKernelGGL(k_nplus, dim3(4096), dim3(kB), 0, s, b->m_plus, b->idx, ng, b->n_plus, vsz, 0);
       hipLaunchKernelGGL(k_nplus, dim3(grid1(ng)), dim3(kB), 0, s, b->m_plus, b->idx, ng, b->n_plus, vsz, 1);
+      hipLaunchKernelGGL(k_gpos, dim3(4096), dim3(kB), 0, s, b->idx, ng, b->gpos, vsz, 0);
+      hipLaunchKernelGGL(k_gpos, dim3(grid1(ng)), dim3(kB), 0, s, b->idx, ng, b->gpos, vsz, 1);
       e = hipStreamSynchronize(s);
     }
     (void)hipFree(drk);
@@ -396,17 +461,18 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
       return fail(DPM_EHIP);
     }
   }
-  // columns in chunks: scatter densities, M- operator, batched AP solve, trace on gamma_in
+  // columns in chunks: M- operator on the densities (sparse), batched AP solve, trace on
+  // gamma_in
   int chunk = o.rhs_chunk > 0 ? o.rhs_chunk : 16;
   if (chunk > n_basis) chunk = n_basis;
   dpm_opts so = o;
   size_t wsb = 0;
   DPM_TRY(workspace_size_impl(g, chunk, so, &wsb));
-  double *w = nullptr, *rhs = nullptr, *u = nullptr;
+  double *rhs = nullptr, *u = nullptr;
   void* ws = nullptr;
-  if (!al((void**)&w, sizeof(double) * vsz * chunk) || !al((void**)&rhs, sizeof(double) * vsz * chunk) ||
+  if (!al((void**)&rhs, sizeof(double) * vsz * chunk) ||
       !al((void**)&u, sizeof(double) * vsz * chunk) || !al(&ws, wsb)) {
-    (void)hipFree(w); (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
+    (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
     set_error("dpm_build_boundary_matrix: device allocation failed");
     return fail(DPM_ENOMEM);
   }
@@ -414,12 +480,10 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
   so.workspace_bytes = wsb;
   so.rhs_chunk = 0;
   dpm_status st = DPM_OK;
-  const double inv_h2 = 1.0 / (g.h * g.h);
   for (int c0 = 0; c0 < n_basis && st == DPM_OK; c0 += chunk) {
     const int nc = (n_basis - c0) < chunk ? (n_basis - c0) : chunk;
-    fill_zero(w, vsz * nc, s);
-    scatter_density(b->basis, c0, nc, ng, b->idx, w, vsz, s);
-    minus_operator(w, b->m_plus, nullptr, rhs, g.n, g.sigma, inv_h2, nc, s);
+    fill_zero(rhs, vsz * nc, s);
+    minus_rhs(b, b->basis, c0, nc, rhs, s);
     st = aux_solve_impl(g, nc, rhs, u, so, s, nullptr);
     if (st != DPM_OK) break;
     hipLaunchKernelGGL(k_trace_columns, dim3(grid1(nin), nc), dim3(kB), 0, s, b->basis, u,
@@ -427,7 +491,7 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
     if (hipGetLastError() != hipSuccess) { set_error("trace kernel launch failed"); st = DPM_EHIP; }
   }
   (void)hipStreamSynchronize(s);
-  (void)hipFree(w); (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
+  (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
   if (st != DPM_OK) return fail(st);
   if (A_out &&
       hipMemcpyAsync(A_out, b->A, sizeof(double) * (size_t)n_basis * nin, hipMemcpyDeviceToDevice, s) != hipSuccess) {
@@ -438,7 +502,7 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
   for (int j = 0; j < n_basis; ++j) {
     hipLaunchKernelGGL(k_house, dim3(1), dim3(1024), 0, s, b->A, nin, j, b->tau);
     if (j + 1 < n_basis)
-      hipLaunchKernelGGL(k_apply_house, dim3(n_basis - j - 1), dim3(512), 0, s, b->A, nin, n_basis, j, b->tau);
+      hipLaunchKernelGGL(k_apply_house, dim3(n_basis - j - 1), dim3(1024), 0, s, b->A, nin, n_basis, j, b->tau);
   }
   double* rd = nullptr;
   std::vector<double> rdh(n_basis);
@@ -464,31 +528,30 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
   }
   // least-squares operator P = R^-1 Q1^T, so that every later solve is one product C = P g
   {
-    double* E = nullptr;
+    const size_t nn = (size_t)n_basis * n_basis;
+    double *G = nullptr, *T = nullptr, *W = nullptr, *K = nullptr, *Rinv = nullptr;
+    auto free_all = [&]() {
+      (void)hipFree(G); (void)hipFree(T); (void)hipFree(W); (void)hipFree(K); (void)hipFree(Rinv);
+    };
     if (!al((void**)&b->P, sizeof(double) * (size_t)n_basis * nin) ||
-        !al((void**)&E, sizeof(double) * (size_t)n_basis * nin)) {
-      (void)hipFree(E);
+        !al((void**)&G, sizeof(double) * nn) || !al((void**)&T, sizeof(double) * nn) ||
+        !al((void**)&W, sizeof(double) * nn) || !al((void**)&K, sizeof(double) * nn) ||
+        !al((void**)&Rinv, sizeof(double) * nn)) {
+      free_all();
       set_error("dpm_build_boundary_matrix: device allocation failed");
       return fail(DPM_ENOMEM);
     }
-    hipLaunchKernelGGL(k_identity_cols, dim3(grid1((long long)nin * n_basis)), dim3(kB), 0, s, E,
-                       nin, n_basis);
-    for (int j = n_basis - 1; j >= 0; --j)
-      hipLaunchKernelGGL(k_apply_house_q, dim3(n_basis - j), dim3(512), 0, s, b->A, nin, n_basis,
-                         j, b->tau, E);
-    double* Rinv = nullptr;
-    if (!al((void**)&Rinv, sizeof(double) * (size_t)n_basis * n_basis)) {
-      (void)hipFree(E);
-      set_error("dpm_build_boundary_matrix: device allocation failed");
-      return fail(DPM_ENOMEM);
-    }
+    const unsigned nt = (unsigned)((n_basis + 15) / 16);
+    hipLaunchKernelGGL(k_gram, dim3(nt, nt), dim3(256), 0, s, b->A, nin, n_basis, G);
+    hipLaunchKernelGGL(k_tinv, dim3(n_basis), dim3(256), 0, s, G, b->tau, n_basis, T);
     hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, b->A, nin, n_basis, Rinv);
+    hipLaunchKernelGGL(k_v1tt, dim3(grid1((long long)nn)), dim3(kB), 0, s, b->A, nin, n_basis, T, W);
+    hipLaunchKernelGGL(k_kmat, dim3(grid1((long long)nn)), dim3(kB), 0, s, Rinv, W, n_basis, K);
     hipLaunchKernelGGL(k_form_p, dim3(grid1(nin), (n_basis + PT - 1) / PT), dim3(kB),
-                       sizeof(double) * PT * n_basis, s, Rinv, E, nin, n_basis, b->P);
+                       sizeof(double) * PT * n_basis, s, Rinv, K, b->A, nin, n_basis, b->P);
     hipError_t e2 = hipGetLastError();
     if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
-    (void)hipFree(E);
-    (void)hipFree(Rinv);
+    free_all();
     if (e2 != hipSuccess) {
       set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e2));
       return fail(DPM_EHIP);
@@ -510,6 +573,7 @@ void destroy_bep(dpm_bep* b) {
   (void)hipFree(b->A);
   (void)hipFree(b->tau);
   (void)hipFree(b->P);
+  (void)hipFree(b->gpos);
   delete b;
 }
 

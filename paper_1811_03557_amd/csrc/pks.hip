@@ -137,7 +137,7 @@ __global__ void k_gauss_gamma(const int32_t* __restrict__ idx, int ng, int n, do
 unsigned grid1(long long n) { return (unsigned)((n + kB - 1) / kB); }
 
 struct StepLayout {
-  size_t b2, X, w, g, C, ug, guard, solve_ws, total;
+  size_t b2, X, g, C, ug, guard, solve_ws, total;
 };
 
 StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
@@ -146,7 +146,6 @@ StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
   size_t o = 0;
   L.b2 = o; o = align_up(o + 2 * V, 256);
   L.X = o; o = align_up(o + 2 * V, 256);
-  L.w = o; o = align_up(o + 2 * V, 256);
   L.g = o; o = align_up(o + 2 * sizeof(double) * b->n_in, 256);
   L.C = o; o = align_up(o + 2 * sizeof(double) * b->n_basis, 256);
   L.ug = o; o = align_up(o + 2 * sizeof(double) * b->n_gamma, 256);
@@ -186,7 +185,6 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   char* ws = static_cast<char*>(o.workspace);
   double* b2 = reinterpret_cast<double*>(ws + L.b2);
   double* X = reinterpret_cast<double*>(ws + L.X);
-  double* w = reinterpret_cast<double*>(ws + L.w);
   double* gv = reinterpret_cast<double*>(ws + L.g);
   double* C = reinterpret_cast<double*>(ws + L.C);
   double* ug = reinterpret_cast<double*>(ws + L.ug);
@@ -206,9 +204,8 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   hipLaunchKernelGGL(k_density, dim3(grid1(b->n_gamma), 2), dim3(kB), 0, s, b->basis, C,
                      b->n_basis, b->n_gamma, ug);
   // Steps 6-7: Green's formula as one AP solve per species
-  fill_zero(w, 2 * vsz, s);
-  scatter_density(ug, 0, 2, b->n_gamma, b->idx, w, vsz, s);
-  minus_operator(w, b->m_plus, b2, b2, g.n, sigma, 1.0 / (g.h * g.h), 2, s);
+  // b2 holds sigma 1_{M+} f, zero on M-: add the M- part (sigma - Lap_h)[u_gamma] in place
+  minus_rhs(b, ug, 0, 2, b2, s);
   DPM_TRY_HIP(hipGetLastError());
   DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, info));
   hipLaunchKernelGGL(k_restrict, dim3(grid1(vsz)), dim3(kB), 0, s, X, b->n_plus, vsz, rho_out,
