@@ -111,48 +111,12 @@ __device__ double block_sum(double v, double* sh) {
 // Rows j..m-1 in chunks of RU rows per thread, the loads of a chunk in flight together.
 constexpr int RU = 8;
 
-// sum_{i >= j} v_i a_i with v_j = 1 (the reflector's implicit unit entry)
-__device__ double refl_dot(const double* __restrict__ v, const double* __restrict__ a, int m,
-                           int j, double* sh) {
-  double d = 0.0;
-  for (int b = j; b < m; b += RU * (int)blockDim.x) {
-    double vv[RU], aa[RU];
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int i = b + threadIdx.x + u * blockDim.x;
-      vv[u] = i < m ? (i == j ? 1.0 : v[i]) : 0.0;
-      aa[u] = i < m ? a[i] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) d += vv[u] * aa[u];
-  }
-  return block_sum(d, sh);
-}
-
-// a_i -= w v_i for i >= j (v_j = 1)
-__device__ void refl_update(const double* __restrict__ v, double* __restrict__ a, int m, int j,
-                            double w) {
-  for (int b = j; b < m; b += RU * (int)blockDim.x) {
-    double vv[RU], aa[RU];
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int i = b + threadIdx.x + u * blockDim.x;
-      vv[u] = i < m ? (i == j ? 1.0 : v[i]) : 0.0;
-      aa[u] = i < m ? a[i] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int i = b + threadIdx.x + u * blockDim.x;
-      if (i < m) a[i] = aa[u] - w * vv[u];
-    }
-  }
-}
-
-// Householder reflector of column j (LAPACK dlarfg convention): on exit A[j,j] = beta (= R_jj),
-// A[j+1:, j] = v (v_0 = 1 implicit), tau[j].  One block.
-__global__ void k_house(double* __restrict__ A, int m, int j, double* __restrict__ tau) {
-  __shared__ double sh[16];
-  double* col = A + (long long)j * m;
+// Householder reflector (LAPACK dlarfg convention) of the raw column col at pivot j:
+// beta = -sign(alpha) ||col[j:]||, v_i = col_i / (alpha - beta) (i > j), v_j = 1,
+// tau = (beta - alpha) / beta; returns false (tau = 0, H = I) when col[j+1:] = 0.  Every block
+// of a launch computes it in the same order, so all get the same values.
+__device__ bool reflector(const double* __restrict__ col, int m, int j, double* sh,
+                          double* beta, double* scal, double* tau) {
   double ss = 0.0;
   for (int b = j + 1; b < m; b += RU * (int)blockDim.x) {
     double cv[RU];
@@ -165,33 +129,69 @@ __global__ void k_house(double* __restrict__ A, int m, int j, double* __restrict
     for (int u = 0; u < RU; ++u) ss += cv[u] * cv[u];
   }
   const double sigma2 = block_sum(ss, sh);
+  if (sigma2 == 0.0) { *tau = 0.0; return false; }
   const double alpha = col[j];
-  if (sigma2 == 0.0) {
-    if (threadIdx.x == 0) tau[j] = 0.0;
-    return;
-  }
   const double nrm = sqrt(alpha * alpha + sigma2);
-  const double beta = alpha >= 0.0 ? -nrm : nrm;
-  const double scal = 1.0 / (alpha - beta);
-  for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) col[i] *= scal;
-  if (threadIdx.x == 0) {
-    tau[j] = (beta - alpha) / beta;
-    col[j] = beta;
-  }
+  *beta = alpha >= 0.0 ? -nrm : nrm;
+  *scal = 1.0 / (alpha - *beta);
+  *tau = (*beta - alpha) / *beta;
+  return true;
 }
 
-// Apply H_j = I - tau v v^T to the trailing columns k > j; one block per column.
-__global__ void k_apply_house(double* __restrict__ A, int m, int ncols, int j,
-                              const double* __restrict__ tau) {
+// One step j of the Householder QR in place.  Blocks 1.. apply H_j, formed from the raw column
+// j, to the trailing columns k = j + blockIdx.x (v_i = col_i * scal on the fly); block 0 stores
+// the reflector of the previous step (column j - 1, which no other block of this launch reads):
+// A[j-1, j-1] = beta (= R), A[j:, j-1] = v, tau[j-1].  Launched for j = 0..n (the last launch
+// only stores step n - 1).
+__global__ void k_house_step(double* __restrict__ A, int m, int ncols, int j,
+                             double* __restrict__ tau) {
   __shared__ double sh[16];
-  const int k = j + 1 + blockIdx.x;
-  if (k >= ncols) return;
-  const double t = tau[j];
-  if (t == 0.0) return;
-  const double* v = A + (long long)j * m;
+  double beta = 0.0, scal = 0.0, t = 0.0;
+  if (blockIdx.x == 0) {
+    if (j == 0) return;
+    double* col = A + (long long)(j - 1) * m;
+    const bool nz = reflector(col, m, j - 1, sh, &beta, &scal, &t);
+    __syncthreads();  // all reads of the raw column before it is scaled
+    if (nz) {
+      for (int i = j + threadIdx.x; i < m; i += blockDim.x) col[i] *= scal;
+      if (threadIdx.x == 0) col[j - 1] = beta;
+    }
+    if (threadIdx.x == 0) tau[j - 1] = t;
+    return;
+  }
+  const int k = j + blockIdx.x;
+  if (j >= ncols || k >= ncols) return;
+  const double* c = A + (long long)j * m;
+  if (!reflector(c, m, j, sh, &beta, &scal, &t)) return;
   double* a = A + (long long)k * m;
-  const double w = t * refl_dot(v, a, m, j, sh);
-  refl_update(v, a, m, j, w);
+  // d = v^T a with v_j = 1, v_i = c_i scal
+  double d = 0.0;
+  for (int b = j; b < m; b += RU * (int)blockDim.x) {
+    double vv[RU], aa[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int i = b + threadIdx.x + u * blockDim.x;
+      vv[u] = i < m ? (i == j ? 1.0 : c[i] * scal) : 0.0;
+      aa[u] = i < m ? a[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) d += vv[u] * aa[u];
+  }
+  const double w = t * block_sum(d, sh);
+  for (int b = j; b < m; b += RU * (int)blockDim.x) {
+    double vv[RU], aa[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int i = b + threadIdx.x + u * blockDim.x;
+      vv[u] = i < m ? (i == j ? 1.0 : c[i] * scal) : 0.0;
+      aa[u] = i < m ? a[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int i = b + threadIdx.x + u * blockDim.x;
+      if (i < m) a[i] = aa[u] - w * vv[u];
+    }
+  }
 }
 
 // Compact WY form of the reflectors (Schreiber-Van Loan): Q = H_0 ... H_{n-1} = I - V T V^T,
@@ -498,12 +498,11 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
     set_error("dpm_build_boundary_matrix: copy of A failed");
     return fail(DPM_EHIP);
   }
-  // Householder QR in place
-  for (int j = 0; j < n_basis; ++j) {
-    hipLaunchKernelGGL(k_house, dim3(1), dim3(1024), 0, s, b->A, nin, j, b->tau);
-    if (j + 1 < n_basis)
-      hipLaunchKernelGGL(k_apply_house, dim3(n_basis - j - 1), dim3(1024), 0, s, b->A, nin, n_basis, j, b->tau);
-  }
+  // Householder QR in place: one launch per step (the step-j reflector is applied by the
+  // trailing-column blocks and stored by block 0 of the next launch)
+  for (int j = 0; j <= n_basis; ++j)
+    hipLaunchKernelGGL(k_house_step, dim3(j < n_basis ? n_basis - j : 1), dim3(1024), 0, s, b->A,
+                       nin, n_basis, j, b->tau);
   double* rd = nullptr;
   std::vector<double> rdh(n_basis);
   if (!al((void**)&rd, sizeof(double) * n_basis)) {
