@@ -108,89 +108,126 @@ __device__ double block_sum(double v, double* sh) {
   return t;
 }
 
-// Rows j..m-1 in chunks of RU rows per thread, the loads of a chunk in flight together.
-constexpr int RU = 8;
-
-// Householder reflector (LAPACK dlarfg convention) of the raw column col at pivot j:
-// beta = -sign(alpha) ||col[j:]||, v_i = col_i / (alpha - beta) (i > j), v_j = 1,
-// tau = (beta - alpha) / beta; returns false (tau = 0, H = I) when col[j+1:] = 0.  Every block
-// of a launch computes it in the same order, so all get the same values.
-__device__ bool reflector(const double* __restrict__ col, int m, int j, double* sh,
-                          double* beta, double* scal, double* tau) {
-  double ss = 0.0;
-  for (int b = j + 1; b < m; b += RU * (int)blockDim.x) {
-    double cv[RU];
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int i = b + threadIdx.x + u * blockDim.x;
-      cv[u] = i < m ? col[i] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) ss += cv[u] * cv[u];
+// Sums of two values over the block, in a fixed order (deterministic).
+__device__ void block_sum2(double& a, double& b, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
   }
-  const double sigma2 = block_sum(ss, sh);
-  if (sigma2 == 0.0) { *tau = 0.0; return false; }
-  const double alpha = col[j];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) { sh[2 * w] = a; sh[2 * w + 1] = b; }
+  __syncthreads();
+  double s = 0.0, t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int k = 0; k < nw; ++k) { s += sh[2 * k]; t += sh[2 * k + 1]; }
+  a = s;
+  b = t;
+}
+
+// Threads of a Householder step; each holds R rows of a column in registers (rows p + 1 + t +
+// u * kQT for the pivot p), and rows beyond R * kQT are streamed in a second loop.
+constexpr int kQT = 1024;
+
+// Householder reflector (LAPACK dlarfg convention) of a column x at pivot p, from alpha = x_p
+// and sigma2 = ||x[p+1:]||^2: beta = -sign(alpha) sqrt(alpha^2 + sigma2), v_p = 1,
+// v_i = x_i / (alpha - beta) (i > p), tau = (beta - alpha) / beta; sigma2 = 0 means H = I
+// (tau = 0, v not stored).
+struct Refl {
+  double beta, scal, tau;
+};
+__device__ __forceinline__ Refl make_refl(double alpha, double sigma2) {
   const double nrm = sqrt(alpha * alpha + sigma2);
-  *beta = alpha >= 0.0 ? -nrm : nrm;
-  *scal = 1.0 / (alpha - *beta);
-  *tau = (*beta - alpha) / *beta;
-  return true;
+  Refl r;
+  r.beta = alpha >= 0.0 ? -nrm : nrm;
+  r.scal = 1.0 / (alpha - r.beta);
+  r.tau = (r.beta - alpha) / r.beta;
+  return r;
 }
 
 // One step j of the Householder QR in place.  Blocks 1.. apply H_j, formed from the raw column
-// j, to the trailing columns k = j + blockIdx.x (v_i = col_i * scal on the fly); block 0 stores
-// the reflector of the previous step (column j - 1, which no other block of this launch reads):
-// A[j-1, j-1] = beta (= R), A[j:, j-1] = v, tau[j-1].  Launched for j = 0..n (the last launch
-// only stores step n - 1).
-__global__ void k_house_step(double* __restrict__ A, int m, int ncols, int j,
-                             double* __restrict__ tau) {
-  __shared__ double sh[16];
-  double beta = 0.0, scal = 0.0, t = 0.0;
-  if (blockIdx.x == 0) {
-    if (j == 0) return;
-    double* col = A + (long long)(j - 1) * m;
-    const bool nz = reflector(col, m, j - 1, sh, &beta, &scal, &t);
-    __syncthreads();  // all reads of the raw column before it is scaled
-    if (nz) {
-      for (int i = j + threadIdx.x; i < m; i += blockDim.x) col[i] *= scal;
-      if (threadIdx.x == 0) col[j - 1] = beta;
-    }
-    if (threadIdx.x == 0) tau[j - 1] = t;
+// j, to the trailing columns k = j + blockIdx.x: one pass loads x = A[j+1:, j] and a =
+// A[j+1:, k] and reduces ||x||^2 and x^T a together, so that v^T a = a_j + scal x^T a.
+// Block 0 stores the reflector of the previous step (column j - 1, which no other block of
+// this launch reads): A[j-1, j-1] = beta (= R), A[j:, j-1] = v, tau[j-1].  Launched for
+// j = 0..n (the last launch only stores step n - 1).  Every block forms the reflector from the
+// same values in the same order, so the stored v is the one that was applied.
+template <int R>
+__global__ __launch_bounds__(kQT) void k_house_step(double* __restrict__ A, int m, int ncols,
+                                                    int j, double* __restrict__ tau) {
+  __shared__ double sh[2 * (kQT / 64)];
+  const int t = threadIdx.x;
+  const bool store = blockIdx.x == 0;
+  const int p = store ? j - 1 : j;  // pivot of the reflector this block forms
+  const int k = j + blockIdx.x;
+  if (store ? j == 0 : (j >= ncols || k >= ncols)) return;
+  double* c = A + (long long)p * m;
+  double* a = A + (long long)k * m;  // block 0: unused
+  const int r0 = p + 1;
+  double x[R], y[R];
+  double ss = 0.0, xa = 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int i = r0 + t + u * kQT;
+    x[u] = i < m ? c[i] : 0.0;
+    y[u] = (!store && i < m) ? a[i] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < R; ++u) { ss += x[u] * x[u]; xa += x[u] * y[u]; }
+  for (int i = r0 + R * kQT + t; i < m; i += kQT) {  // rows beyond the register tile
+    const double xi = c[i];
+    ss += xi * xi;
+    if (!store) xa += xi * a[i];
+  }
+  block_sum2(ss, xa, sh);
+  const double alpha = c[p];
+  if (ss == 0.0) {  // H = I
+    if (store && t == 0) tau[p] = 0.0;
     return;
   }
-  const int k = j + blockIdx.x;
-  if (j >= ncols || k >= ncols) return;
-  const double* c = A + (long long)j * m;
-  if (!reflector(c, m, j, sh, &beta, &scal, &t)) return;
-  double* a = A + (long long)k * m;
-  // d = v^T a with v_j = 1, v_i = c_i scal
-  double d = 0.0;
-  for (int b = j; b < m; b += RU * (int)blockDim.x) {
-    double vv[RU], aa[RU];
+  const Refl h = make_refl(alpha, ss);
+  if (store) {
 #pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int i = b + threadIdx.x + u * blockDim.x;
-      vv[u] = i < m ? (i == j ? 1.0 : c[i] * scal) : 0.0;
-      aa[u] = i < m ? a[i] : 0.0;
+    for (int u = 0; u < R; ++u) {
+      const int i = r0 + t + u * kQT;
+      if (i < m) c[i] = x[u] * h.scal;
     }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) d += vv[u] * aa[u];
+    for (int i = r0 + R * kQT + t; i < m; i += kQT) c[i] *= h.scal;
+    if (t == 0) {
+      c[p] = h.beta;
+      tau[p] = h.tau;
+    }
+    return;
   }
-  const double w = t * block_sum(d, sh);
-  for (int b = j; b < m; b += RU * (int)blockDim.x) {
-    double vv[RU], aa[RU];
+  const double aj = a[j];
+  const double w = h.tau * (aj + h.scal * xa);
+  if (t == 0) a[j] = aj - w;
 #pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int i = b + threadIdx.x + u * blockDim.x;
-      vv[u] = i < m ? (i == j ? 1.0 : c[i] * scal) : 0.0;
-      aa[u] = i < m ? a[i] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int i = b + threadIdx.x + u * blockDim.x;
-      if (i < m) a[i] = aa[u] - w * vv[u];
-    }
+  for (int u = 0; u < R; ++u) {
+    const int i = r0 + t + u * kQT;
+    if (i < m) a[i] = y[u] - w * (x[u] * h.scal);
+  }
+  for (int i = r0 + R * kQT + t; i < m; i += kQT) a[i] -= w * (c[i] * h.scal);
+}
+
+// Rows per thread of the register tile for the rows below pivot j.
+int qr_rows_per_thread(int m, int j) {
+  const int rows = m - j;
+  for (int r : {1, 2, 4, 8, 12, 16})
+    if (r * kQT >= rows) return r;
+  return 20;  // the largest tile without spills at kQT threads
+}
+
+void launch_house_step(double* A, int m, int ncols, int j, double* tau, hipStream_t s) {
+  const dim3 grid(j < ncols ? ncols - j : 1), block(kQT);
+  switch (qr_rows_per_thread(m, j > 0 ? j - 1 : 0)) {
+    case 1: hipLaunchKernelGGL(k_house_step<1>, grid, block, 0, s, A, m, ncols, j, tau); break;
+    case 2: hipLaunchKernelGGL(k_house_step<2>, grid, block, 0, s, A, m, ncols, j, tau); break;
+    case 4: hipLaunchKernelGGL(k_house_step<4>, grid, block, 0, s, A, m, ncols, j, tau); break;
+    case 8: hipLaunchKernelGGL(k_house_step<8>, grid, block, 0, s, A, m, ncols, j, tau); break;
+    case 12: hipLaunchKernelGGL(k_house_step<12>, grid, block, 0, s, A, m, ncols, j, tau); break;
+    case 16: hipLaunchKernelGGL(k_house_step<16>, grid, block, 0, s, A, m, ncols, j, tau); break;
+    default: hipLaunchKernelGGL(k_house_step<20>, grid, block, 0, s, A, m, ncols, j, tau); break;
   }
 }
 
@@ -201,24 +238,66 @@ __device__ __forceinline__ double vval(const double* __restrict__ A, int m, int 
   return i == k ? 1.0 : (i > k ? A[(long long)k * m + i] : 0.0);
 }
 
-// G = V^T V (n x n, row-major), 16 x 16 output tiles, rows of V staged through LDS.
-__global__ void k_gram(const double* __restrict__ A, int m, int n, double* __restrict__ G) {
-  __shared__ double va[16][17], vb[16][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
-  const int lo = a0 > b0 ? a0 : b0;  // V[i][k] = 0 for i < k: rows i < max(a0, b0) add nothing
-  double acc = 0.0;
-  for (int i0 = lo; i0 < m; i0 += 16) {
-    // thread (ty, tx) loads row i0 + tx of columns a0 + ty and b0 + ty (consecutive rows)
-    const int i = i0 + tx;
-    va[tx][ty] = (i < m && a0 + ty < n) ? vval(A, m, i, a0 + ty) : 0.0;
-    vb[tx][ty] = (i < m && b0 + ty < n) ? vval(A, m, i, b0 + ty) : 0.0;
-    __syncthreads();
+// G = V^T V (n x n, row-major), upper triangle of 32 x 32 tiles (tile row <= tile column), the
+// rows of V split into chunks of kGC rows over blockIdx.y: block (tile, chunk) writes its
+// partial sum to Gp[chunk], k_gram_reduce adds the chunks in order (deterministic).  Rows of a
+// chunk are staged through LDS 32 at a time; each thread owns a 2 x 2 block of the tile.
+constexpr int kGT = 32, kGC = 1024;
+__global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ A, int m, int n,
+                                                   double* __restrict__ Gp) {
+  __shared__ double va[kGT][kGT + 1], vb[kGT][kGT + 1];  // [row][column]
+  const int nt = (n + kGT - 1) / kGT;
+  // tile index -> (ta, tb), ta <= tb, row-major over the upper triangle
+  int tile = blockIdx.x, ta = 0;
+  while (tile >= nt - ta) { tile -= nt - ta; ++ta; }
+  const int tb = ta + tile;
+  const int a0 = ta * kGT, b0 = tb * kGT;
+  const int i_lo = blockIdx.y * kGC, i_hi = min(m, i_lo + kGC);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;  // outputs (a0+2tx+{0,1}, b0+2ty+{0,1})
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  const int start = max(i_lo, b0);  // V[i][k] = 0 for i < k, and b0 >= a0
+  const int lr = threadIdx.x & 31, lc = threadIdx.x >> 5;  // loader: row lr, columns lc + 8q
+  for (int i0 = start; i0 < i_hi; i0 += kGT) {
+    const int i = i0 + lr;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc += va[r][tx] * vb[r][ty];
+    for (int q = 0; q < 4; ++q) {
+      const int ca = a0 + lc + 8 * q, cb = b0 + lc + 8 * q;
+      va[lr][lc + 8 * q] = (i < i_hi && ca < n) ? vval(A, m, i, ca) : 0.0;
+      vb[lr][lc + 8 * q] = (i < i_hi && cb < n) ? vval(A, m, i, cb) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int r = 0; r < kGT; ++r) {
+      const double x0 = va[r][2 * tx], x1 = va[r][2 * tx + 1];
+      const double y0 = vb[r][2 * ty], y1 = vb[r][2 * ty + 1];
+      acc[0][0] += x0 * y0;
+      acc[0][1] += x0 * y1;
+      acc[1][0] += x1 * y0;
+      acc[1][1] += x1 * y1;
+    }
     __syncthreads();
   }
-  if (a0 + tx < n && b0 + ty < n) G[(long long)(a0 + tx) * n + b0 + ty] = acc;
+  double* g = Gp + (long long)blockIdx.y * n * n;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int ra = a0 + 2 * tx + u, cb = b0 + 2 * ty + v;
+      if (ra < n && cb < n) g[(long long)ra * n + cb] = acc[u][v];
+    }
+}
+
+// G[a][b] = sum over chunks of Gp[chunk][a][b], for a <= b (the part k_tinv reads).
+__global__ void k_gram_reduce(const double* __restrict__ Gp, int nchunk, int n,
+                              double* __restrict__ G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int ra = e / n, cb = e - ra * n;
+  // entries with a > b are not written by k_gram_part (and not read)
+  if (ra > cb) { G[e] = 0.0; return; }
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += Gp[(long long)c * n * n + e];
+  G[e] = s;
 }
 
 // T (row-major, upper triangular).  With tau_j = 2 / (v_j^T v_j) (every reflector here, or
@@ -500,9 +579,7 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
   }
   // Householder QR in place: one launch per step (the step-j reflector is applied by the
   // trailing-column blocks and stored by block 0 of the next launch)
-  for (int j = 0; j <= n_basis; ++j)
-    hipLaunchKernelGGL(k_house_step, dim3(j < n_basis ? n_basis - j : 1), dim3(1024), 0, s, b->A,
-                       nin, n_basis, j, b->tau);
+  for (int j = 0; j <= n_basis; ++j) launch_house_step(b->A, nin, n_basis, j, b->tau, s);
   double* rd = nullptr;
   std::vector<double> rdh(n_basis);
   if (!al((void**)&rd, sizeof(double) * n_basis)) {
@@ -528,20 +605,25 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
   // least-squares operator P = R^-1 Q1^T, so that every later solve is one product C = P g
   {
     const size_t nn = (size_t)n_basis * n_basis;
-    double *G = nullptr, *T = nullptr, *W = nullptr, *K = nullptr, *Rinv = nullptr;
+    double *G = nullptr, *T = nullptr, *W = nullptr, *K = nullptr, *Rinv = nullptr, *Gp = nullptr;
     auto free_all = [&]() {
       (void)hipFree(G); (void)hipFree(T); (void)hipFree(W); (void)hipFree(K); (void)hipFree(Rinv);
+      (void)hipFree(Gp);
     };
     if (!al((void**)&b->P, sizeof(double) * (size_t)n_basis * nin) ||
         !al((void**)&G, sizeof(double) * nn) || !al((void**)&T, sizeof(double) * nn) ||
         !al((void**)&W, sizeof(double) * nn) || !al((void**)&K, sizeof(double) * nn) ||
-        !al((void**)&Rinv, sizeof(double) * nn)) {
+        !al((void**)&Rinv, sizeof(double) * nn) ||
+        !al((void**)&Gp, sizeof(double) * nn * (size_t)((nin + kGC - 1) / kGC))) {
       free_all();
       set_error("dpm_build_boundary_matrix: device allocation failed");
       return fail(DPM_ENOMEM);
     }
-    const unsigned nt = (unsigned)((n_basis + 15) / 16);
-    hipLaunchKernelGGL(k_gram, dim3(nt, nt), dim3(256), 0, s, b->A, nin, n_basis, G);
+    const int nt = (n_basis + kGT - 1) / kGT, nchunk = (nin + kGC - 1) / kGC;
+    hipLaunchKernelGGL(k_gram_part, dim3(nt * (nt + 1) / 2, nchunk), dim3(256), 0, s, b->A, nin,
+                       n_basis, Gp);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(grid1((long long)nn)), dim3(kB), 0, s, Gp, nchunk,
+                       n_basis, G);
     hipLaunchKernelGGL(k_tinv, dim3(n_basis), dim3(256), 0, s, G, b->tau, n_basis, T);
     hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, b->A, nin, n_basis, Rinv);
     hipLaunchKernelGGL(k_v1tt, dim3(grid1((long long)nn)), dim3(kB), 0, s, b->A, nin, n_basis, T, W);
