@@ -13,6 +13,8 @@ at 0.7x that rate gives p50/p99 request latency.
 
 Time loop (the "pks_time_loop" object): 200 graph-replayed DPM steps on an ellipsoid at 127^3.
 Boundary matrix (the "boundary_matrix" object): the 242-column build at 127^3 per precision.
+Adaptive loop (the "adaptive_time_loop" object): dt from the CFL-type bound with Step 4b
+rebuilds of the boundary matrix, on the same ellipsoid at 127^3.
 
 Prints one JSON line on stdout (everything else goes to stderr).
 """
@@ -158,6 +160,50 @@ def run_pks(args, dev):
     return out
 
 
+def run_adaptive(args, dev):
+    """Adaptive time loop (Steps 3-8, dpm_run) on the ellipsoid (1, 0.8, 0.6) at N = 127 with
+    50 densities (l <= 4, beta = 1), FP64 transforms, from dt0 = h/4: Test A data with chi = 1
+    (the CFL bound cuts dt at step 1, one rebuild), and rho0 of Test A with c0 = 0 and
+    chi = 1000 (c steepens every step, so every step after the first shrinks dt and rebuilds the
+    matrix, the regime near blow-up).  Wall time of the whole run, and of one rebuild alone."""
+    import torch
+    from paper_1811_03557_amd import api
+    n = args.pks_n
+    h = 3.0 / (n + 1)
+    x0 = -1.5 + h
+    dt0 = h / 4
+    k = args.adaptive_steps
+    geo = api.geometry("ellipsoid", axes=(1.0, 0.8, 0.6))
+    m = api.classify(n, h, x0, geo, device=dev)
+    idx, _ = api.gamma_points(m, h, x0)
+    B, _ = api.basis(n, h, x0, geo, idx, 4, 1)
+    out = {"workload": f"ellipsoid (1, 0.8, 0.6), N = {n}, 50 densities, FP64, dt0 = h/4, "
+                       f"{k} steps of dt = min(CFL bound, previous dt) with Step 4b rebuilds"}
+    bep = api.build_boundary_matrix(m, B, n, h, 1.0 / dt0, x0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bep.rebuild(1.0 / dt0)
+    torch.cuda.synchronize()
+    out["rebuild_ms"] = round((time.perf_counter() - t) * 1e3, 2)
+    for name, chi, c_amp in (("test_a_chi1", 1.0, 500.0), ("c0_zero_chi1000", 1000.0, 0.0)):
+        bep.rebuild(1.0 / dt0)
+        rho = api.gauss_state(bep, geo, 1000.0, 100.0)
+        c = api.gauss_state(bep, geo, c_amp, 50.0) if c_amp else torch.zeros_like(rho)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = api.run(bep, chi, rho, c, t_final=1.0, max_steps=k)
+        torch.cuda.synchronize()
+        s = time.perf_counter() - t
+        out[name] = {"steps": res["steps"], "rebuilds": res["rebuilds"], "stop": res["stop"],
+                     "run_s": round(s, 4), "steps_per_s": round(res["steps"] / s, 1),
+                     "dt_first": res["dt_hist"][0] if res["steps"] else None, "dt_last": res["dt"],
+                     "rho_max": res["rho_max"]}
+        log(f"[bench] adaptive {name}: {res['steps']} steps, {res['rebuilds']} rebuilds, "
+            f"{s * 1e3:.1f} ms ({res['stop']})")
+    bep.close()
+    return out
+
+
 def run_boundary_matrix(args, dev):
     """Step 2 of the method at 127^3: the 242-column reduced-BEP matrix of the unit sphere
     (real Y_lm, l <= 10, beta = 1), sigma = 2/h^2, built and QR-factored by one
@@ -208,6 +254,8 @@ def main():
     ap.add_argument("--pks-steps", type=int, default=200, help="time-loop steps (0 = skip)")
     ap.add_argument("--pks-n", type=int, default=127)
     ap.add_argument("--no-bmat", action="store_true", help="skip the boundary-matrix build")
+    ap.add_argument("--adaptive-steps", type=int, default=20,
+                    help="steps of each adaptive-loop run (0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run 3 plain device copies of this many bytes (calibrates the "
                          "HBM traffic counters against a kernel of known traffic)")
@@ -322,6 +370,7 @@ def main():
         serving = run_serving(args, dev)
     pks = run_pks(args, dev) if args.pks_steps > 0 else None
     bmat = run_boundary_matrix(args, dev) if not args.no_bmat else None
+    adaptive = run_adaptive(args, dev) if args.adaptive_steps > 0 else None
 
     ok = {k: v for k, v in results.items() if v["rel_err_sample"] <= args.rtol}
     best_name = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else None
@@ -364,6 +413,7 @@ def main():
         "serving": serving,
         "pks_time_loop": pks,
         "boundary_matrix": bmat,
+        "adaptive_time_loop": adaptive,
         "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
         "alg_hbm_frac": (round(best["solves_per_s"] * 16 * vol / (HBM_PEAK_GBS * 1e9), 4)
                          if best else None),

@@ -215,6 +215,60 @@ dpm_status dpm_stepper_first_nonfinite(const dpm_stepper* st, void* stream, int3
 void dpm_stepper_destroy(dpm_stepper* st);
 
 /*
+ * dpm_cfl_scan -- paper Algorithm "Main Steps", Steps 3 and 8: the quantities the adaptive time
+ * loop decides on.  out2[0] = max |grad_h c| over the six faces of every M+ node (the face
+ * differences (c_nb - c) / h of eq cfl_condition, neighbours in N+), out2[1] = max |rho| over
+ * M+.  The CFL-type bound of the positivity theorem is then dt <= h / (6 chi out2[0]).  A
+ * non-finite value anywhere in the scanned entries makes the corresponding output NaN.
+ * rho, c: device N^3 FP64; out2: device, 2 FP64.  Asynchronous; allocates nothing.
+ */
+dpm_status dpm_cfl_scan(const dpm_bep* bep, const double* rho, const double* c, double* out2,
+                        void* stream);
+
+/*
+ * dpm_bep_rebuild -- paper Step 4b: recompute the reduced-BEP matrix (the same densities and
+ * geometry), its Householder QR and the least-squares operator in place for a new sigma
+ * (= 1/dt), with the transform options given at build time.  Synchronises `stream`; allocates
+ * temporaries for the column solves.  Errors as dpm_build_boundary_matrix; after a failure the
+ * handle must only be destroyed.  A stepper built on this handle keeps replaying its own dt:
+ * create a new one after a rebuild.
+ */
+dpm_status dpm_bep_rebuild(dpm_bep* bep, double sigma, void* stream);
+
+/*
+ * dpm_run -- the adaptive time loop of the paper's Algorithm "Main Steps" (Steps 3-8) on (rho, c)
+ * in place, starting at t = 0 with the dt of the handle (dt_0 = 1/sigma: Step 2 builds with the
+ * largest step, 0.5 h^2 in the paper).  Each step: scan (dpm_cfl_scan); stop if max |rho| over
+ * M+ exceeds rho_cap (Step 8) or a scanned value is not finite; dt = min(h / (6 chi max|grad c|),
+ * dt_prev) (Step 3; dt never grows, so the matrix of the last rebuild always belongs to the
+ * current dt); if dt < dt_prev rebuild the matrix at sigma = 1/dt (Step 4b); one dpm_step
+ * (Steps 4a-7); t += dt.  The loop ends when t >= t_final, after max_steps steps, or at a stop.
+ * One 16-byte device-to-host copy and one synchronisation per step.
+ * opts->workspace: at least dpm_step_workspace_size + 256 bytes.  dt_hist and rebuilt_hist
+ * (host, nullable, max_steps entries) receive each step's dt and whether it rebuilt (1/0).
+ * On return the handle holds the matrix of the last dt.
+ */
+typedef struct {
+  double chi;       /* chemotactic sensitivity */
+  double t_final;   /* final time */
+  double rho_cap;   /* Step 8 threshold on max |rho| over M+ */
+  int32_t max_steps;
+} dpm_run_params;
+typedef enum { DPM_RUN_TFINAL = 0, DPM_RUN_MAXSTEPS = 1, DPM_RUN_RHOCAP = 2, DPM_RUN_NONFINITE = 3 } dpm_run_stop;
+typedef struct {
+  int32_t steps;     /* steps taken */
+  int32_t rebuilds;  /* Step 4b rebuilds */
+  int32_t stop;      /* dpm_run_stop */
+  double t;          /* time reached */
+  double dt;         /* dt of the last step (1/sigma of the handle) */
+  double rho_max;    /* max |rho| over M+ at the last scan */
+  double grad_max;   /* max |grad_h c| at the last scan */
+} dpm_run_info;
+dpm_status dpm_run(dpm_bep* bep, const dpm_run_params* params, double* rho, double* c,
+                   const dpm_opts* opts, void* stream, dpm_run_info* info, double* dt_hist,
+                   uint8_t* rebuilt_hist);
+
+/*
  * dpm_gauss_state -- initial data amp * exp(-rate |x - center|^2) (paper Sec. 4, Tests A and B)
  * at the nodes of M+ and, on gamma, at the projection of each node onto Gamma (paper eq
  * boundary_approx); zero elsewhere.  out: device N^3 FP64.

@@ -16,13 +16,19 @@ One DPM step (Algorithm "Main Steps", Steps 4a, 5, 6, 7; sigma = 1/dt for both s
 particular solutions, Tr_gamma_in G f, least squares against the precomputed BEP matrix,
 density, difference potential, Green's formula, restricted to N+.
 
+The adaptive loop (Steps 3-8): each step takes dt = min(CFL-type bound of the positivity
+theorem, previous dt), rebuilds the BEP matrix at sigma = 1/dt when dt shrank (Step 4b), and
+stops at the final time, after a step budget, or when max |rho| over M+ passes a threshold
+(Step 8).  Reading: dt never grows once reduced, so the matrix always belongs to the step's dt
+(the algorithm rebuilds only on a decrease and is silent on increases).
+
 TEST INFRASTRUCTURE: imported only by tests/, smoke() and bench.py's cpu_baseline.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .dpm import difference_potential, least_squares, particular_solution, trace
+from .dpm import bep_matrix, difference_potential, least_squares, particular_solution, trace
 from .geometry import PointSets
 
 
@@ -81,14 +87,20 @@ def pks_rhs(rho, c, m_plus, h, dt, chi):
     return f_rho, f_c
 
 
-def cfl_dt(c: np.ndarray, m_plus: np.ndarray, h: float, chi: float) -> float:
-    """Largest dt allowed by the CFL-type condition of the positivity theorem."""
+def face_gradient_max(c: np.ndarray, m_plus: np.ndarray, h: float) -> float:
+    """max |grad_h c| over the six faces of every M+ node (eq cfl_condition)."""
     gmax = 0.0
     for ax in range(3):
         for k in (1, -1):
             gr = np.abs(_shift(c, ax, k) - c) / h
             gmax = max(gmax, float(np.max(np.where(m_plus, gr, 0.0))))
-    return np.inf if gmax == 0.0 else h / (6.0 * chi * gmax)
+    return gmax
+
+
+def cfl_dt(c: np.ndarray, m_plus: np.ndarray, h: float, chi: float) -> float:
+    """Largest dt allowed by the CFL-type condition of the positivity theorem."""
+    gmax = face_gradient_max(c, m_plus, h)
+    return np.inf if gmax == 0.0 or chi == 0.0 else h / (6.0 * chi * gmax)
 
 
 def dpm_step(rho, c, ps: PointSets, basis: np.ndarray, A: np.ndarray, h: float, dt: float,
@@ -106,3 +118,42 @@ def dpm_step(rho, c, ps: PointSets, basis: np.ndarray, A: np.ndarray, h: float, 
         out.append(u)
         coefs.append(C)
     return out[0], out[1], coefs
+
+
+def adaptive_run(rho, c, ps: PointSets, basis: np.ndarray, h: float, sigma0: float, chi: float,
+                 t_final: float, rho_cap: float = np.inf, max_steps: int = 1000):
+    """Steps 3-8 from dt_0 = 1/sigma0 (the step of Step 2's matrix).
+
+    Returns (rho, c, summary) with summary keys steps, rebuilds, stop, t, dt, rho_max,
+    grad_max, dt_hist, rebuilt."""
+    dt_prev = 1.0 / sigma0
+    A = bep_matrix(basis, ps, sigma0, h)                               # Step 2
+    t, dts, rebuilt, stop = 0.0, [], [], "max_steps"
+    gmax = rmax = 0.0
+    while True:
+        if t >= t_final:
+            stop = "t_final"
+            break
+        if len(dts) >= max_steps:
+            stop = "max_steps"
+            break
+        gmax = face_gradient_max(c, ps.m_plus, h)                      # Step 3
+        rmax = float(np.max(np.where(ps.m_plus, np.abs(rho), 0.0)))    # Step 8
+        if not (np.isfinite(gmax) and np.isfinite(rmax)):
+            stop = "nonfinite"
+            break
+        if rmax > rho_cap:
+            stop = "rho_cap"
+            break
+        dt = min(cfl_dt(c, ps.m_plus, h, chi), dt_prev)
+        rb = dt < dt_prev
+        if rb:                                                         # Step 4b
+            A = bep_matrix(basis, ps, 1.0 / dt, h)
+        rho, c, _ = dpm_step(rho, c, ps, basis, A, h, dt, chi)         # Steps 4a-7
+        dts.append(dt)
+        rebuilt.append(rb)
+        t += dt
+        dt_prev = dt
+    return rho, c, {"steps": len(dts), "rebuilds": int(sum(rebuilt)), "stop": stop, "t": t,
+                    "dt": dt_prev, "rho_max": rmax, "grad_max": gmax, "dt_hist": dts,
+                    "rebuilt": rebuilt}

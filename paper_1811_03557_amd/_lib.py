@@ -31,6 +31,20 @@ class Info(C.Structure):
     _fields_ = [("refine_iters", C.c_int32), ("est_rel_err", C.c_double)]
 
 
+class RunParams(C.Structure):
+    _fields_ = [("chi", C.c_double), ("t_final", C.c_double), ("rho_cap", C.c_double),
+                ("max_steps", C.c_int32)]
+
+
+class RunInfo(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("rebuilds", C.c_int32), ("stop", C.c_int32),
+                ("t", C.c_double), ("dt", C.c_double), ("rho_max", C.c_double),
+                ("grad_max", C.c_double)]
+
+
+RUN_STOPS = {0: "t_final", 1: "max_steps", 2: "rho_cap", 3: "nonfinite"}
+
+
 class Geometry(C.Structure):
     _fields_ = [("kind", C.c_int32), ("center", C.c_double * 3), ("axes", C.c_double * 3)]
 
@@ -60,6 +74,10 @@ SIGNATURES = {
     "dpm_stepper_run": (C.c_int, [_P, C.c_int32, _P]),
     "dpm_stepper_first_nonfinite": (C.c_int, [_P, _P, C.POINTER(C.c_int32)]),
     "dpm_stepper_destroy": (None, [_P]),
+    "dpm_cfl_scan": (C.c_int, [_P, _P, _P, _P, _P]),
+    "dpm_bep_rebuild": (C.c_int, [_P, _D, _P]),
+    "dpm_run": (C.c_int, [_P, C.POINTER(RunParams), _P, _P, C.POINTER(Opts), _P,
+                          C.POINTER(RunInfo), _P, _P]),
     "dpm_gauss_state": (C.c_int, [_P, C.POINTER(Geometry), _D, _D, C.POINTER(_D), _P, _P]),
     "dpm_bep_destroy": (None, [_P]),
     "dpm_last_error": (C.c_char_p, []),

@@ -191,6 +191,19 @@ class BEP:
         self.n_gamma, self.n_gamma_in, self.n_basis = ng.value, ngi.value, nb.value
         self.rdiag = (rmin.value, rmax.value)
 
+    def rebuild(self, sigma: float, stream=None) -> None:
+        """Step 4b: the matrix, its QR and the least-squares operator again at a new sigma."""
+        L.check(L.load().dpm_bep_rebuild(C.c_void_p(self.ptr), float(sigma),
+                                         C.c_void_p(_stream(stream))))
+        self.sigma = float(sigma)
+        self._refresh_rdiag()
+
+    def _refresh_rdiag(self):
+        rmin, rmax = C.c_double(0), C.c_double(0)
+        L.check(L.load().dpm_bep_info(C.c_void_p(self.ptr), None, None, None, C.byref(rmin),
+                                      C.byref(rmax)))
+        self.rdiag = (rmin.value, rmax.value)
+
     def close(self):
         if self.ptr:
             L.load().dpm_bep_destroy(C.c_void_p(self.ptr))
@@ -314,6 +327,45 @@ class Stepper:
             self.close()
         except Exception:
             pass
+
+
+def cfl_scan(bep: BEP, rho: torch.Tensor, c: torch.Tensor, stream=None) -> torch.Tensor:
+    """Device tensor [max |grad_h c| over the faces of M+ nodes, max |rho| over M+]."""
+    out = torch.empty(2, dtype=torch.float64, device=rho.device)
+    L.check(L.load().dpm_cfl_scan(C.c_void_p(bep.ptr), C.c_void_p(_dev(rho, "rho", torch.float64)),
+                                  C.c_void_p(_dev(c, "c", torch.float64)),
+                                  C.c_void_p(out.data_ptr()), C.c_void_p(_stream(stream))))
+    return out
+
+
+def run(bep: BEP, chi: float, rho: torch.Tensor, c: torch.Tensor, t_final: float,
+        rho_cap: float = float("inf"), max_steps: int = 1000, prec: str = "fp64",
+        rtol: float = 1e-10, max_refine: int = 0, workspace: torch.Tensor | None = None,
+        stream=None) -> dict:
+    """Steps 3-8: the adaptive time loop on (rho, c) in place, from dt = 1/bep.sigma.
+
+    Returns the run summary with the per-step dt and rebuild flags; the handle then holds the
+    matrix of the last dt (bep.sigma is updated)."""
+    lib = L.load()
+    o = opts(prec, True, rtol, max_refine)
+    nbytes = step_workspace_size(bep, o) + 256
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=rho.device)
+    o.workspace = C.c_void_p(workspace.data_ptr())
+    o.workspace_bytes = workspace.numel()
+    p = L.RunParams(float(chi), float(t_final), float(rho_cap), int(max_steps))
+    info = L.RunInfo()
+    dts = (C.c_double * max(int(max_steps), 1))()
+    rbs = (C.c_uint8 * max(int(max_steps), 1))()
+    L.check(lib.dpm_run(C.c_void_p(bep.ptr), C.byref(p), C.c_void_p(_dev(rho, "rho", torch.float64)),
+                        C.c_void_p(_dev(c, "c", torch.float64)), C.byref(o),
+                        C.c_void_p(_stream(stream)), C.byref(info), dts, rbs))
+    k = info.steps
+    bep.sigma = 1.0 / info.dt
+    bep._refresh_rdiag()
+    return {"steps": k, "rebuilds": info.rebuilds, "stop": L.RUN_STOPS[info.stop], "t": info.t,
+            "dt": info.dt, "rho_max": info.rho_max, "grad_max": info.grad_max,
+            "dt_hist": [dts[i] for i in range(k)], "rebuilt": [bool(rbs[i]) for i in range(k)]}
 
 
 def gauss_state(bep: BEP, geo: L.Geometry, amp: float, rate: float, center=(0.0, 0.0, 0.0),

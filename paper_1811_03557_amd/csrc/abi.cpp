@@ -244,6 +244,44 @@ dpm_status dpm_stepper_first_nonfinite(const dpm_stepper* st, void* stream, int3
 
 void dpm_stepper_destroy(dpm_stepper* st) { stepper_destroy_impl(st); }
 
+dpm_status dpm_cfl_scan(const dpm_bep* bep, const double* rho, const double* c, double* out2,
+                        void* stream) {
+  clear_error();
+  if (!bep || !rho || !c || !out2) { set_error("NULL argument"); return DPM_EINVAL; }
+  if (!aligned_to(rho, 8) || !aligned_to(c, 8) || !aligned_to(out2, 8)) {
+    set_error("rho, c and out2 must be 8-byte aligned");
+    return DPM_EINVAL;
+  }
+  return cfl_scan_impl(bep, rho, c, out2, static_cast<hipStream_t>(stream));
+}
+
+dpm_status dpm_bep_rebuild(dpm_bep* bep, double sigma, void* stream) {
+  clear_error();
+  if (!bep) { set_error("bep is NULL"); return DPM_EINVAL; }
+  if (!(sigma >= 0.0) || !std::isfinite(sigma)) { set_error("sigma must be finite and >= 0"); return DPM_EINVAL; }
+  return rebuild_bep_impl(bep, sigma, static_cast<hipStream_t>(stream));
+}
+
+dpm_status dpm_run(dpm_bep* bep, const dpm_run_params* params, double* rho, double* c,
+                   const dpm_opts* opts, void* stream, dpm_run_info* info, double* dt_hist,
+                   uint8_t* rebuilt_hist) {
+  clear_error();
+  if (!bep || !params || !rho || !c) { set_error("NULL argument"); return DPM_EINVAL; }
+  DPM_TRY(validate_opts(bep->grid, opts));
+  if (!opts->io_fp64) { set_error("dpm_run needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
+  if (!aligned_to(rho, 8) || !aligned_to(c, 8) || !aligned16(opts->workspace)) {
+    set_error("rho and c must be 8-byte aligned, the workspace 16-byte aligned");
+    return DPM_EINVAL;
+  }
+  if (rho == c) { set_error("rho and c must be different buffers"); return DPM_EINVAL; }
+  if (!(params->chi >= 0.0) || !std::isfinite(params->chi)) { set_error("chi must be finite and >= 0"); return DPM_EINVAL; }
+  if (std::isnan(params->t_final) || std::isnan(params->rho_cap)) { set_error("t_final and rho_cap must not be NaN"); return DPM_EINVAL; }
+  if (params->max_steps < 0) { set_error("max_steps must be >= 0"); return DPM_EINVAL; }
+  if (!(bep->grid.sigma > 0.0)) { set_error("the handle's sigma must be > 0 (sigma = 1/dt)"); return DPM_EINVAL; }
+  return run_impl(bep, *params, rho, c, *opts, static_cast<hipStream_t>(stream), info, dt_hist,
+                  rebuilt_hist);
+}
+
 dpm_status dpm_gauss_state(const dpm_bep* bep, const dpm_geometry* geom, double amp,
                            double rate, const double center[3], double* out, void* stream) {
   clear_error();

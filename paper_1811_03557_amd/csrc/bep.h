@@ -44,6 +44,12 @@ void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* C, hipStrea
 dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
                           const double* basis, const dpm_opts& o, hipStream_t s, dpm_bep** out,
                           double* A_out);
+dpm_status rebuild_bep_impl(dpm_bep* b, double sigma, hipStream_t s);
+dpm_status cfl_scan_impl(const dpm_bep* b, const double* rho, const double* c, double* out2,
+                         hipStream_t s);
+dpm_status run_impl(dpm_bep* b, const dpm_run_params& p, double* rho, double* c,
+                    const dpm_opts& o, hipStream_t s, dpm_run_info* info, double* dt_hist,
+                    uint8_t* rebuilt_hist);
 void destroy_bep(dpm_bep* b);
 
 }  // namespace dpm

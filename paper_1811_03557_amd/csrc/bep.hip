@@ -465,6 +465,115 @@ void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* C, hipStrea
                      bep->n_basis, g, C);
 }
 
+// Columns of the reduced-BEP matrix at the handle's sigma (M- operator on the densities, batched
+// AP solves, traces on gamma_in), the Householder QR, the rank test and the least-squares
+// operator P, into the handle's buffers.
+dpm_status factor_bep(dpm_bep* b, hipStream_t s, double* A_out) {
+  const dpm_grid& g = b->grid;
+  const dpm_opts& o = b->opts;
+  const int n_basis = b->n_basis, nin = b->n_in, ng = b->n_gamma;
+  const long long vsz = (long long)g.n * g.n * g.n;
+  auto al = [&](void** p, size_t bytes) { return hipMalloc(p, bytes > 0 ? bytes : 1) == hipSuccess; };
+  // columns in chunks: M- operator on the densities (sparse), batched AP solve, trace on
+  // gamma_in
+  int chunk = o.rhs_chunk > 0 ? o.rhs_chunk : 16;
+  if (chunk > n_basis) chunk = n_basis;
+  dpm_opts so = o;
+  size_t wsb = 0;
+  DPM_TRY(workspace_size_impl(g, chunk, so, &wsb));
+  double *rhs = nullptr, *u = nullptr;
+  void* ws = nullptr;
+  if (!al((void**)&rhs, sizeof(double) * vsz * chunk) ||
+      !al((void**)&u, sizeof(double) * vsz * chunk) || !al(&ws, wsb)) {
+    (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
+    set_error("dpm_build_boundary_matrix: device allocation failed");
+    return DPM_ENOMEM;
+  }
+  so.workspace = ws;
+  so.workspace_bytes = wsb;
+  so.rhs_chunk = 0;
+  dpm_status st = DPM_OK;
+  for (int c0 = 0; c0 < n_basis && st == DPM_OK; c0 += chunk) {
+    const int nc = (n_basis - c0) < chunk ? (n_basis - c0) : chunk;
+    fill_zero(rhs, vsz * nc, s);
+    minus_rhs(b, b->basis, c0, nc, rhs, s);
+    st = aux_solve_impl(g, nc, rhs, u, so, s, nullptr);
+    if (st != DPM_OK) break;
+    hipLaunchKernelGGL(k_trace_columns, dim3(grid1(nin), nc), dim3(kB), 0, s, b->basis, u,
+                       b->idx_in, b->pos_in, nin, ng, c0, nc, vsz, b->A);
+    if (hipGetLastError() != hipSuccess) { set_error("trace kernel launch failed"); st = DPM_EHIP; }
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
+  if (st != DPM_OK) return st;
+  if (A_out &&
+      hipMemcpyAsync(A_out, b->A, sizeof(double) * (size_t)n_basis * nin, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    set_error("dpm_build_boundary_matrix: copy of A failed");
+    return DPM_EHIP;
+  }
+  // Householder QR in place: one launch per step (the step-j reflector is applied by the
+  // trailing-column blocks and stored by block 0 of the next launch)
+  for (int j = 0; j <= n_basis; ++j) launch_house_step(b->A, nin, n_basis, j, b->tau, s);
+  double* rd = nullptr;
+  std::vector<double> rdh(n_basis);
+  if (!al((void**)&rd, sizeof(double) * n_basis)) {
+    set_error("dpm_build_boundary_matrix: device allocation failed");
+    return DPM_ENOMEM;
+  }
+  hipLaunchKernelGGL(k_rdiag, dim3(grid1(n_basis)), dim3(kB), 0, s, b->A, nin, n_basis, rd);
+  hipError_t e = hipMemcpyAsync(rdh.data(), rd, sizeof(double) * n_basis, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(rd);
+  if (e != hipSuccess) {
+    set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e));
+    return DPM_EHIP;
+  }
+  double mn = INFINITY, mx = 0.0;
+  for (double v : rdh) { mn = std::fmin(mn, v); mx = std::fmax(mx, v); }
+  b->rdiag_min = mn;
+  b->rdiag_max = mx;
+  if (!(mn > 1e-12 * mx)) {
+    set_error("boundary matrix is rank deficient: min |R_ii| = %g, max |R_ii| = %g", mn, mx);
+    return DPM_ERANK;
+  }
+  // least-squares operator P = R^-1 Q1^T, so that every later solve is one product C = P g
+  {
+    const size_t nn = (size_t)n_basis * n_basis;
+    double *G = nullptr, *T = nullptr, *W = nullptr, *K = nullptr, *Rinv = nullptr, *Gp = nullptr;
+    auto free_all = [&]() {
+      (void)hipFree(G); (void)hipFree(T); (void)hipFree(W); (void)hipFree(K); (void)hipFree(Rinv);
+      (void)hipFree(Gp);
+    };
+    if (!al((void**)&G, sizeof(double) * nn) || !al((void**)&T, sizeof(double) * nn) ||
+        !al((void**)&W, sizeof(double) * nn) || !al((void**)&K, sizeof(double) * nn) ||
+        !al((void**)&Rinv, sizeof(double) * nn) ||
+        !al((void**)&Gp, sizeof(double) * nn * (size_t)((nin + kGC - 1) / kGC))) {
+      free_all();
+      set_error("dpm_build_boundary_matrix: device allocation failed");
+      return DPM_ENOMEM;
+    }
+    const int nt = (n_basis + kGT - 1) / kGT, nchunk = (nin + kGC - 1) / kGC;
+    hipLaunchKernelGGL(k_gram_part, dim3(nt * (nt + 1) / 2, nchunk), dim3(256), 0, s, b->A, nin,
+                       n_basis, Gp);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(grid1((long long)nn)), dim3(kB), 0, s, Gp, nchunk,
+                       n_basis, G);
+    hipLaunchKernelGGL(k_tinv, dim3(n_basis), dim3(256), 0, s, G, b->tau, n_basis, T);
+    hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, b->A, nin, n_basis, Rinv);
+    hipLaunchKernelGGL(k_v1tt, dim3(grid1((long long)nn)), dim3(kB), 0, s, b->A, nin, n_basis, T, W);
+    hipLaunchKernelGGL(k_kmat, dim3(grid1((long long)nn)), dim3(kB), 0, s, Rinv, W, n_basis, K);
+    hipLaunchKernelGGL(k_form_p, dim3(grid1(nin), (n_basis + PT - 1) / PT), dim3(kB),
+                       sizeof(double) * PT * n_basis, s, Rinv, K, b->A, nin, n_basis, b->P);
+    hipError_t e2 = hipGetLastError();
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    free_all();
+    if (e2 != hipSuccess) {
+      set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e2));
+      return DPM_EHIP;
+    }
+  }
+  return DPM_OK;
+}
+
 dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
                           const double* basis, const dpm_opts& o, hipStream_t s, dpm_bep** out,
                           double* A_out) {
@@ -495,6 +604,7 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
       !al((void**)&b->basis, sizeof(double) * (size_t)n_basis * ng) ||
       !al((void**)&b->A, sizeof(double) * (size_t)n_basis * nin) ||
       !al((void**)&b->tau, sizeof(double) * n_basis) ||
+      !al((void**)&b->P, sizeof(double) * (size_t)n_basis * nin) ||
       !al((void**)&b->gpos, sizeof(int32_t) * vsz)) {
     set_error("dpm_build_boundary_matrix: device allocation failed");
     return fail(DPM_ENOMEM);
@@ -540,106 +650,17 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
       return fail(DPM_EHIP);
     }
   }
-  // columns in chunks: M- operator on the densities (sparse), batched AP solve, trace on
-  // gamma_in
-  int chunk = o.rhs_chunk > 0 ? o.rhs_chunk : 16;
-  if (chunk > n_basis) chunk = n_basis;
-  dpm_opts so = o;
-  size_t wsb = 0;
-  DPM_TRY(workspace_size_impl(g, chunk, so, &wsb));
-  double *rhs = nullptr, *u = nullptr;
-  void* ws = nullptr;
-  if (!al((void**)&rhs, sizeof(double) * vsz * chunk) ||
-      !al((void**)&u, sizeof(double) * vsz * chunk) || !al(&ws, wsb)) {
-    (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
-    set_error("dpm_build_boundary_matrix: device allocation failed");
-    return fail(DPM_ENOMEM);
-  }
-  so.workspace = ws;
-  so.workspace_bytes = wsb;
-  so.rhs_chunk = 0;
-  dpm_status st = DPM_OK;
-  for (int c0 = 0; c0 < n_basis && st == DPM_OK; c0 += chunk) {
-    const int nc = (n_basis - c0) < chunk ? (n_basis - c0) : chunk;
-    fill_zero(rhs, vsz * nc, s);
-    minus_rhs(b, b->basis, c0, nc, rhs, s);
-    st = aux_solve_impl(g, nc, rhs, u, so, s, nullptr);
-    if (st != DPM_OK) break;
-    hipLaunchKernelGGL(k_trace_columns, dim3(grid1(nin), nc), dim3(kB), 0, s, b->basis, u,
-                       b->idx_in, b->pos_in, nin, ng, c0, nc, vsz, b->A);
-    if (hipGetLastError() != hipSuccess) { set_error("trace kernel launch failed"); st = DPM_EHIP; }
-  }
-  (void)hipStreamSynchronize(s);
-  (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
-  if (st != DPM_OK) return fail(st);
-  if (A_out &&
-      hipMemcpyAsync(A_out, b->A, sizeof(double) * (size_t)n_basis * nin, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-    set_error("dpm_build_boundary_matrix: copy of A failed");
-    return fail(DPM_EHIP);
-  }
-  // Householder QR in place: one launch per step (the step-j reflector is applied by the
-  // trailing-column blocks and stored by block 0 of the next launch)
-  for (int j = 0; j <= n_basis; ++j) launch_house_step(b->A, nin, n_basis, j, b->tau, s);
-  double* rd = nullptr;
-  std::vector<double> rdh(n_basis);
-  if (!al((void**)&rd, sizeof(double) * n_basis)) {
-    set_error("dpm_build_boundary_matrix: device allocation failed");
-    return fail(DPM_ENOMEM);
-  }
-  hipLaunchKernelGGL(k_rdiag, dim3(grid1(n_basis)), dim3(kB), 0, s, b->A, nin, n_basis, rd);
-  hipError_t e = hipMemcpyAsync(rdh.data(), rd, sizeof(double) * n_basis, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(rd);
-  if (e != hipSuccess) {
-    set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e));
-    return fail(DPM_EHIP);
-  }
-  double mn = INFINITY, mx = 0.0;
-  for (double v : rdh) { mn = std::fmin(mn, v); mx = std::fmax(mx, v); }
-  b->rdiag_min = mn;
-  b->rdiag_max = mx;
-  if (!(mn > 1e-12 * mx)) {
-    set_error("boundary matrix is rank deficient: min |R_ii| = %g, max |R_ii| = %g", mn, mx);
-    return fail(DPM_ERANK);
-  }
-  // least-squares operator P = R^-1 Q1^T, so that every later solve is one product C = P g
   {
-    const size_t nn = (size_t)n_basis * n_basis;
-    double *G = nullptr, *T = nullptr, *W = nullptr, *K = nullptr, *Rinv = nullptr, *Gp = nullptr;
-    auto free_all = [&]() {
-      (void)hipFree(G); (void)hipFree(T); (void)hipFree(W); (void)hipFree(K); (void)hipFree(Rinv);
-      (void)hipFree(Gp);
-    };
-    if (!al((void**)&b->P, sizeof(double) * (size_t)n_basis * nin) ||
-        !al((void**)&G, sizeof(double) * nn) || !al((void**)&T, sizeof(double) * nn) ||
-        !al((void**)&W, sizeof(double) * nn) || !al((void**)&K, sizeof(double) * nn) ||
-        !al((void**)&Rinv, sizeof(double) * nn) ||
-        !al((void**)&Gp, sizeof(double) * nn * (size_t)((nin + kGC - 1) / kGC))) {
-      free_all();
-      set_error("dpm_build_boundary_matrix: device allocation failed");
-      return fail(DPM_ENOMEM);
-    }
-    const int nt = (n_basis + kGT - 1) / kGT, nchunk = (nin + kGC - 1) / kGC;
-    hipLaunchKernelGGL(k_gram_part, dim3(nt * (nt + 1) / 2, nchunk), dim3(256), 0, s, b->A, nin,
-                       n_basis, Gp);
-    hipLaunchKernelGGL(k_gram_reduce, dim3(grid1((long long)nn)), dim3(kB), 0, s, Gp, nchunk,
-                       n_basis, G);
-    hipLaunchKernelGGL(k_tinv, dim3(n_basis), dim3(256), 0, s, G, b->tau, n_basis, T);
-    hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, b->A, nin, n_basis, Rinv);
-    hipLaunchKernelGGL(k_v1tt, dim3(grid1((long long)nn)), dim3(kB), 0, s, b->A, nin, n_basis, T, W);
-    hipLaunchKernelGGL(k_kmat, dim3(grid1((long long)nn)), dim3(kB), 0, s, Rinv, W, n_basis, K);
-    hipLaunchKernelGGL(k_form_p, dim3(grid1(nin), (n_basis + PT - 1) / PT), dim3(kB),
-                       sizeof(double) * PT * n_basis, s, Rinv, K, b->A, nin, n_basis, b->P);
-    hipError_t e2 = hipGetLastError();
-    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
-    free_all();
-    if (e2 != hipSuccess) {
-      set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e2));
-      return fail(DPM_EHIP);
-    }
+    const dpm_status st = factor_bep(b, s, A_out);
+    if (st != DPM_OK) return fail(st);
   }
   *out = b;
   return DPM_OK;
+}
+
+dpm_status rebuild_bep_impl(dpm_bep* b, double sigma, hipStream_t s) {
+  b->grid.sigma = sigma;
+  return factor_bep(b, s, nullptr);
 }
 
 void destroy_bep(dpm_bep* b) {

@@ -134,6 +134,48 @@ __global__ void k_gauss_gamma(const int32_t* __restrict__ idx, int ng, int n, do
   out[i] = amp * exp(-rate * (dx * dx + dy * dy + dz * dz));
 }
 
+// Maxima of non-negative doubles as atomic maxima of their bit patterns: non-negative doubles
+// order as unsigned integers, and a NaN (its sign cleared by fabs) orders above +inf, so any NaN
+// in the scanned entries makes the result NaN.  Order-independent, hence deterministic.
+__device__ __forceinline__ unsigned long long mag_bits(double v) {
+  return (unsigned long long)__double_as_longlong(fabs(v));
+}
+
+__global__ void k_scan_init(unsigned long long* __restrict__ out2) {
+  if (threadIdx.x < 2) out2[threadIdx.x] = 0ull;
+}
+
+// out2[0] = max over M+ nodes and their six faces of |c_nb - c| / h (eq cfl_condition),
+// out2[1] = max over M+ of |rho|.  M+ nodes are interior to the cube, so every neighbour exists.
+__global__ void k_cfl_scan(const double* __restrict__ rho, const double* __restrict__ c,
+                           const uint8_t* __restrict__ mp, int n, double h,
+                           unsigned long long* __restrict__ out2) {
+  const long long vsz = (long long)n * n * n;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long gb = 0ull, rb = 0ull;
+  if (i < vsz && mp[i]) {
+    const double c0 = c[i];
+    const long long st[3] = {(long long)n * n, (long long)n, 1};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const unsigned long long up = mag_bits((c[i + st[a]] - c0) / h);
+      const unsigned long long dn = mag_bits((c[i - st[a]] - c0) / h);
+      gb = up > gb ? up : gb;
+      gb = dn > gb ? dn : gb;
+    }
+    rb = mag_bits(rho[i]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long go = __shfl_xor(gb, off), ro = __shfl_xor(rb, off);
+    gb = go > gb ? go : gb;
+    rb = ro > rb ? ro : rb;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (gb) atomicMax(&out2[0], gb);
+    if (rb) atomicMax(&out2[1], rb);
+  }
+}
+
 unsigned grid1(long long n) { return (unsigned)((n + kB - 1) / kB); }
 
 struct StepLayout {
@@ -304,6 +346,70 @@ void stepper_destroy_impl(dpm_stepper* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   delete p;
+}
+
+dpm_status cfl_scan_impl(const dpm_bep* b, const double* rho, const double* c, double* out2,
+                         hipStream_t s) {
+  const dpm_grid& g = b->grid;
+  const long long vsz = (long long)g.n * g.n * g.n;
+  auto* o = reinterpret_cast<unsigned long long*>(out2);
+  hipLaunchKernelGGL(k_scan_init, dim3(1), dim3(64), 0, s, o);
+  hipLaunchKernelGGL(k_cfl_scan, dim3(grid1(vsz)), dim3(kB), 0, s, rho, c, b->m_plus, g.n, g.h, o);
+  DPM_TRY_HIP(hipGetLastError());
+  return DPM_OK;
+}
+
+dpm_status run_impl(dpm_bep* b, const dpm_run_params& p, double* rho, double* c,
+                    const dpm_opts& o, hipStream_t s, dpm_run_info* info, double* dt_hist,
+                    uint8_t* rebuilt_hist) {
+  size_t need = 0;
+  DPM_TRY(step_workspace_impl(b, o, &need));
+  const size_t scan_off = align_up(need, 256);
+  if (o.workspace == nullptr || o.workspace_bytes < scan_off + 2 * sizeof(double)) {
+    set_error("dpm_run: workspace too small: %zu bytes given, %zu needed", o.workspace_bytes,
+              scan_off + 2 * sizeof(double));
+    return DPM_EINVAL;
+  }
+  double* scan = reinterpret_cast<double*>(static_cast<char*>(o.workspace) + scan_off);
+  dpm_run_info r{};
+  r.stop = DPM_RUN_MAXSTEPS;
+  double t = 0.0, dt_prev = 1.0 / b->grid.sigma;
+  for (;;) {
+    if (t >= p.t_final) { r.stop = DPM_RUN_TFINAL; break; }
+    if (r.steps >= p.max_steps) { r.stop = DPM_RUN_MAXSTEPS; break; }
+    // Steps 3 and 8: the CFL-type bound and the size of rho, from the current state
+    double v[2] = {0.0, 0.0};
+    DPM_TRY(cfl_scan_impl(b, rho, c, scan, s));
+    DPM_TRY_HIP(hipMemcpyAsync(v, scan, sizeof(v), hipMemcpyDeviceToHost, s));
+    DPM_TRY_HIP(hipStreamSynchronize(s));
+    r.grad_max = v[0];
+    r.rho_max = v[1];
+    if (!(std::isfinite(v[0]) && std::isfinite(v[1]))) { r.stop = DPM_RUN_NONFINITE; break; }
+    if (v[1] > p.rho_cap) { r.stop = DPM_RUN_RHOCAP; break; }
+    double dt = dt_prev;
+    if (v[0] > 0.0) {
+      const double dt_cfl = b->grid.h / (6.0 * p.chi * v[0]);
+      if (dt_cfl < dt) dt = dt_cfl;
+    }
+    // Step 4b: a smaller step needs the matrix (and its QR) at the new sigma
+    const bool rebuild = dt < dt_prev;
+    if (rebuild) {
+      DPM_TRY(rebuild_bep_impl(b, 1.0 / dt, s));
+      ++r.rebuilds;
+    }
+    // Steps 4a-7 in place
+    DPM_TRY(step_enqueue(b, dt, p.chi, rho, c, rho, c, o, s, nullptr, false));
+    if (dt_hist) dt_hist[r.steps] = dt;
+    if (rebuilt_hist) rebuilt_hist[r.steps] = rebuild ? 1 : 0;
+    ++r.steps;
+    t += dt;
+    dt_prev = dt;
+  }
+  DPM_TRY_HIP(hipStreamSynchronize(s));
+  r.t = t;
+  r.dt = dt_prev;
+  if (info) *info = r;
+  return DPM_OK;
 }
 
 dpm_status gauss_state_impl(const dpm_bep* b, const dpm_geometry& geo, double amp, double rate,

@@ -18,7 +18,8 @@ def _declared():
 def test_header_declares_abi():
     names = _declared()
     for must in ["aux_solve", "aux_solve_batched", "dpm_build_boundary_matrix", "dpm_step",
-                 "dpm_gamma_points", "dpm_last_error", "dpm_workspace_size"]:
+                 "dpm_gamma_points", "dpm_last_error", "dpm_workspace_size", "dpm_cfl_scan",
+                 "dpm_bep_rebuild", "dpm_run"]:
         assert must in names
 
 
@@ -65,3 +66,8 @@ def test_host_validation_without_device():
         assert lib.aux_solve_batched_sigma(C.byref(g), 2, sg, fake, C.c_void_p(0x90000000),
                                            C.byref(o), None, None) == _lib.DPM_EINVAL
         assert "sigma" in lib.dpm_last_error().decode()
+    # the adaptive loop's entry points reject a missing handle before any launch
+    prm = _lib.RunParams(1.0, 1.0, float("inf"), 10)
+    assert lib.dpm_run(None, C.byref(prm), fake, odd, C.byref(o), None, None, None, None) == _lib.DPM_EINVAL
+    assert lib.dpm_bep_rebuild(None, 1.0, None) == _lib.DPM_EINVAL
+    assert lib.dpm_cfl_scan(None, fake, fake, fake, None) == _lib.DPM_EINVAL

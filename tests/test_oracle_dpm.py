@@ -197,3 +197,72 @@ def test_dpm_step_symmetry_and_positivity():
     for f in (r1, c1):
         assert np.allclose(f, f[::-1], atol=1e-10) and np.allclose(f, np.transpose(f, (1, 2, 0)), atol=1e-10)
         assert f[ps.n_plus].min() >= -1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_cfl_scan_linear_field(axis):
+    """eq cfl_condition on a field linear along one axis (values on N+, zero beyond): every face of
+    an M+ node sees the slope s, so max |grad_h c| = |s| and the bound is h / (6 chi |s|); faces
+    of nodes outside M+ (which reach the zeros beyond N+) must not count."""
+    h, _, mesh, ps = _sphere_case(15)
+    s, chi = -3.25, 0.8
+    c = np.where(ps.n_plus, s * mesh[axis], 0.0)
+    g = pks.face_gradient_max(c, ps.m_plus, h)
+    assert abs(g - abs(s)) < 1e-12 * abs(s)
+    assert abs(pks.cfl_dt(c, ps.m_plus, h, chi) - h / (6 * chi * abs(s))) < 1e-12 * h
+    # a field constant on N+ gives no bound
+    assert pks.cfl_dt(np.where(ps.n_plus, 2.0, 0.0), ps.m_plus, h, chi) == np.inf
+
+
+def _adaptive_case(n, lmax):
+    h, x0, (z, y, x), ps = _sphere_case(n)
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    d, th, ph = og.project_sphere(gz, gy, gx)
+    B = ob.basis_matrix(d, th, ph, lmax=lmax, beta=1)
+    return h, (z, y, x), ps, B
+
+
+def test_adaptive_constant_state():
+    """Constant data: no CFL bound, so dt stays 1/sigma0 with no rebuild; the state is the exact
+    discrete solution (rho constant, c_{k+1} = (1 - dt) c_k + dt rho) and the loop ends at the
+    first t >= t_final."""
+    h, _, ps, B = _adaptive_case(15, 1)
+    dt0 = 0.5 * h * h
+    rho = np.where(ps.n_plus, 3.0, 0.0)
+    c = np.where(ps.n_plus, 5.0, 0.0)
+    r, cc, s = pks.adaptive_run(rho, c, ps, B, h, 1.0 / dt0, 1.0, t_final=3.5 * dt0)
+    assert s["stop"] == "t_final" and s["steps"] == 4 and s["rebuilds"] == 0
+    assert s["dt_hist"] == [1.0 / (1.0 / dt0)] * 4
+    assert abs(s["t"] - 4 * (1.0 / (1.0 / dt0))) < 1e-15
+    ck = 5.0
+    for _ in range(4):
+        ck = (1 - s["dt"]) * ck + s["dt"] * 3.0
+    assert np.allclose(r[ps.n_plus], 3.0, rtol=1e-11)
+    assert np.allclose(cc[ps.n_plus], ck, rtol=1e-11)
+
+
+def test_adaptive_rules_test_a():
+    """Test A data on a centred sphere: the CFL bound is far below 0.5 h^2, so step 1 takes
+    exactly that bound and rebuilds; dt never grows; rebuilds happen exactly when dt shrinks;
+    the state keeps the sphere's symmetries; max_steps and rho_cap stop the loop."""
+    h, (z, y, x), ps, B = _adaptive_case(15, 1)
+    r2 = x**2 + y**2 + z**2
+    rho = np.where(ps.n_plus, 1000 * np.exp(-100 * r2), 0.0)
+    c = np.where(ps.n_plus, 500 * np.exp(-50 * r2), 0.0)
+    sigma0 = 1.0 / (0.5 * h * h)
+    r, cc, s = pks.adaptive_run(rho, c, ps, B, h, sigma0, 1.0, t_final=1.0, max_steps=4)
+    assert s["stop"] == "max_steps" and s["steps"] == 4
+    assert s["dt_hist"][0] == pks.cfl_dt(c, ps.m_plus, h, 1.0) < 1.0 / sigma0
+    assert s["rebuilt"][0]
+    prev = 1.0 / sigma0
+    for dt, rb in zip(s["dt_hist"], s["rebuilt"]):
+        assert dt <= prev and rb == (dt < prev)
+        prev = dt
+    assert s["rebuilds"] == sum(s["rebuilt"])
+    assert abs(s["t"] - sum(s["dt_hist"])) < 1e-15
+    for f in (r, cc):
+        assert np.allclose(f, f[::-1], atol=1e-9 * np.abs(f).max())
+        assert np.allclose(f, np.transpose(f, (1, 2, 0)), atol=1e-9 * np.abs(f).max())
+    # Step 8: a threshold below the initial max |rho| stops before the first step
+    _, _, s2 = pks.adaptive_run(rho, c, ps, B, h, sigma0, 1.0, t_final=1.0, rho_cap=100.0)
+    assert s2["stop"] == "rho_cap" and s2["steps"] == 0 and s2["rho_max"] == np.max(rho[ps.m_plus])
