@@ -9,7 +9,8 @@ whose error, checked against the CPU FP64 oracle on a sampled right-hand side, m
 
 Serving (the "serving" object): a continuous-batching server over 64 simulations of mixed grid
 sizes; a closed-loop run gives the saturation rate and an open-loop run with Poisson arrivals
-at 0.7x that rate gives p50/p99 request latency.
+at 0.7x that rate (10^4 requests) gives p50/p99 request latency; 0.3x, 0.5x and 0.9x are swept
+with fewer requests.
 
 Time loop (the "pks_time_loop" object): 200 graph-replayed DPM steps on an ellipsoid at 127^3.
 Boundary matrix (the "boundary_matrix" object): the 242-column build at 127^3 per precision.
@@ -92,7 +93,8 @@ def run_serving(args, dev):
     sweep = {}
     for f in (0.3, 0.5, 0.7, 0.9):
         qps = f * sat["requests_per_s"]
-        arrays = inp.serving_workload(n_sims=args.serve_sims, n_requests=nreq, qps=qps,
+        k = max(nreq, args.serve_main_requests) if f == 0.7 else nreq
+        arrays = inp.serving_workload(n_sims=args.serve_sims, n_requests=k, qps=qps,
                                       seed=11, closed_loop=False)
         r = one(arrays)
         sweep[f] = dict(r, offered=qps)
@@ -101,7 +103,8 @@ def run_serving(args, dev):
     opn = sweep[0.7]
     out = {"workload": f"{args.serve_sims} simulations, N uniform over 31/63/127/255, sigma "
                        f"log-uniform [1, 1e4]; half advance DPM steps (4 solves each), half "
-                       f"issue aux solves with their own sigma; {nreq} requests per run",
+                       f"issue aux solves with their own sigma; {args.serve_main_requests} "
+                       f"requests at the 0.7x operating point, {nreq} per other run",
            "saturation_requests_per_s": round(sat["requests_per_s"], 1),
            "saturation_solves_per_s": round(sat["solves_per_s"], 1),
            "offered_requests_per_s": round(opn["offered"], 1),
@@ -109,6 +112,7 @@ def run_serving(args, dev):
            "solves_per_s": round(opn["solves_per_s"], 1),
            "p50_ms": round(opn["p50_ms"], 3), "p99_ms": round(opn["p99_ms"], 3),
            "mean_batch": round(opn["mean_batch"], 2), "per_n": opn["per_n"],
+           "requests_at_operating_point": opn["requests"],
            "load_sweep": {str(f): {"offered_requests_per_s": round(v["offered"], 1),
                                    "p50_ms": round(v["p50_ms"], 3), "p99_ms": round(v["p99_ms"], 3),
                                    "requests_per_s": round(v["requests_per_s"], 1)}
@@ -250,6 +254,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving run (0 = skip)")
+    ap.add_argument("--serve-main-requests", type=int, default=10000,
+                    help="requests of the open-loop run at 0.7x saturation")
     ap.add_argument("--serve-sims", type=int, default=64)
     ap.add_argument("--pks-steps", type=int, default=200, help="time-loop steps (0 = skip)")
     ap.add_argument("--pks-n", type=int, default=127)

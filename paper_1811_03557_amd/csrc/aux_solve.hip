@@ -215,12 +215,16 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
     DPM_TRY_HIP(hipMemcpyAsync(sig_dev, sigma_host, sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
   }
 
-  hipLaunchKernelGGL(k_flags_reset, dim3((nrhs + 255) / 256), dim3(256), 0, s, fl, nrhs);
-  DPM_TRY_HIP(hipGetLastError());
-
   const size_t vol = (size_t)g.n * g.n * g.n;
   const size_t io_bytes = o.io_fp64 ? 8 : 4;
   const bool refine = o.max_refine > 0;
+  // the flags serve the paths that track max-norms (FP64 iterate with workspace transforms)
+  const bool plain = (o.prec == DPM_FP64 && !refine) || (o.prec == DPM_FP32 && !o.io_fp64);
+  if (!plain) {
+    hipLaunchKernelGGL(k_flags_reset, dim3((nrhs + 255) / 256), dim3(256), 0, s, fl, nrhs);
+    DPM_TRY_HIP(hipGetLastError());
+  }
+
   for (int c0 = 0; c0 < nrhs; c0 += chunk) {
     const int nb = (nrhs - c0) < chunk ? (nrhs - c0) : chunk;
     const char* bc = static_cast<const char*>(b) + (size_t)c0 * vol * io_bytes;
@@ -250,7 +254,11 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
     }
   }
 
-  if (info) {
+  if (info && plain) {
+    DPM_TRY_HIP(hipStreamSynchronize(s));
+    info->refine_iters = 0;
+    info->est_rel_err = 0.0;
+  } else if (info) {
     DPM_TRY_HIP(hipStreamSynchronize(s));
     std::vector<int> it(nrhs), dn(nrhs);
     std::vector<double> est(nrhs);

@@ -36,10 +36,11 @@ void fill_zero(double* p, long long n, hipStream_t s);
 // out[c] = (sigma - Lap_h)[dens[c0 + c] on gamma, extended by zero] at the M- nodes where it can
 // be nonzero (gamma_ex and their M- neighbours); other entries of out are left as they are.
 void minus_rhs(const dpm_bep* b, const double* dens, int c0, int ncol, double* out, hipStream_t s);
-void gather(const double* vol, long long vsz, const int32_t* idx, int m, int nvec, double* out,
-            hipStream_t s);
 // C[r] = R^-1 Q1^T g[r], r < nvec, as one product with the precomputed operator P
 void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* C, hipStream_t s);
+// C = P Tr_gamma_in vol for nvec volumes (the traces gathered on the fly)
+void qr_solve_traces(const dpm_bep* bep, int nvec, const double* vol, long long vsz, double* C,
+                     hipStream_t s);
 
 dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
                           const double* basis, const dpm_opts& o, hipStream_t s, dpm_bep** out,

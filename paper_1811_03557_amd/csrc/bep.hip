@@ -89,13 +89,6 @@ __global__ void k_trace_columns(const double* __restrict__ dens, const double* _
       dens[(long long)(c0 + c) * ng + pos_in[i]] - u[(long long)c * vsz + idx_in[i]];
 }
 
-__global__ void k_gather(const double* __restrict__ vol, long long vsz,
-                         const int32_t* __restrict__ idx, int m, double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (i < m) out[(long long)c * m + i] = vol[(long long)c * vsz + idx[i]];
-}
-
 __device__ double block_sum(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -392,16 +385,34 @@ __global__ void k_form_p(const double* __restrict__ Rinv, const double* __restri
       P[(long long)(nu0 + t) * m + i] = (i < n ? Rinv[(long long)(nu0 + t) * n + i] : 0.0) - acc[t];
 }
 
-// C[r][nu] = sum_i P[nu][i] g[r][i]: the least-squares coefficients of right-hand side r.
-// One block per (nu, r).
-__global__ void k_lsq_apply(const double* __restrict__ P, int m, int n,
-                            const double* __restrict__ g, double* __restrict__ C) {
-  __shared__ double sh[16];
+// C[r][nu] = sum_i P[nu][i] g_r[i]: the least-squares coefficients of right-hand side r, with
+// g_r[i] = g[r m + i], or, gathering, g_r[i] = vol[r vsz + idx[i]] (the trace of solution r on
+// gamma_in read straight from its volume).  One block of kLT threads per (nu, r); each thread
+// loads kLU rows at a time, all in flight together, then one fixed-order block reduction.
+constexpr int kLT = 1024, kLU = 16;
+template <bool GATHER>
+__global__ __launch_bounds__(kLT) void k_lsq_apply(const double* __restrict__ P, int m, int n,
+                                                   const double* __restrict__ g, long long vsz,
+                                                   const int32_t* __restrict__ idx,
+                                                   double* __restrict__ C) {
+  __shared__ double sh[kLT / 64];
   const int nu = blockIdx.x, r = blockIdx.y;
   const double* pr = P + (long long)nu * m;
-  const double* gr = g + (long long)r * m;
   double d = 0.0;
-  for (int i = threadIdx.x; i < m; i += blockDim.x) d += pr[i] * gr[i];
+  for (int b0 = 0; b0 < m; b0 += kLU * kLT) {
+    double pv[kLU], gv[kLU];
+#pragma unroll
+    for (int u = 0; u < kLU; ++u) {
+      const int i = b0 + threadIdx.x + u * kLT;
+      pv[u] = i < m ? pr[i] : 0.0;
+      if (GATHER)
+        gv[u] = i < m ? g[(long long)r * vsz + idx[i]] : 0.0;
+      else
+        gv[u] = i < m ? g[(long long)r * m + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLU; ++u) d += pv[u] * gv[u];
+  }
   const double t = block_sum(d, sh);
   if (threadIdx.x == 0) C[(long long)r * n + nu] = t;
 }
@@ -455,14 +466,15 @@ void minus_rhs(const dpm_bep* b, const double* dens, int c0, int ncol, double* o
                      1.0 / (g.h * g.h), out, vsz);
 }
 
-void gather(const double* vol, long long vsz, const int32_t* idx, int m, int nvec, double* out,
-            hipStream_t s) {
-  hipLaunchKernelGGL(k_gather, dim3(grid1(m), nvec), dim3(kB), 0, s, vol, vsz, idx, m, out);
+void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* C, hipStream_t s) {
+  hipLaunchKernelGGL(k_lsq_apply<false>, dim3(bep->n_basis, nvec), dim3(kLT), 0, s, bep->P,
+                     bep->n_in, bep->n_basis, g, 0LL, nullptr, C);
 }
 
-void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* C, hipStream_t s) {
-  hipLaunchKernelGGL(k_lsq_apply, dim3(bep->n_basis, nvec), dim3(256), 0, s, bep->P, bep->n_in,
-                     bep->n_basis, g, C);
+void qr_solve_traces(const dpm_bep* bep, int nvec, const double* vol, long long vsz, double* C,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_lsq_apply<true>, dim3(bep->n_basis, nvec), dim3(kLT), 0, s, bep->P,
+                     bep->n_in, bep->n_basis, vol, vsz, bep->idx_in, C);
 }
 
 // Columns of the reduced-BEP matrix at the handle's sigma (M- operator on the densities, batched

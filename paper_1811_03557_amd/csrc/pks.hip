@@ -70,29 +70,55 @@ __global__ void k_pks_rhs(const double* __restrict__ rho, const double* __restri
   b2[vsz + i] = sigma * ((1.0 - dt) * c0 + dt * r0);
 }
 
-// u_gamma[r][i] = sum_nu basis[nu][i] C[r][nu]
+// u_gamma[r][i] = sum_nu basis[nu][i] C[r][nu] for the two species r = 0, 1: one thread per
+// gamma node reads its basis column once, kDU densities in flight at a time.
+constexpr int kDU = 10;
 __global__ void k_density(const double* __restrict__ basis, const double* __restrict__ C,
                           int nb, int ng, double* __restrict__ ug) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
   if (i >= ng) return;
-  double acc = 0.0;
-  for (int nu = 0; nu < nb; ++nu) acc += basis[(long long)nu * ng + i] * C[r * nb + nu];
-  ug[(long long)r * ng + i] = acc;
+  double a0 = 0.0, a1 = 0.0;
+  int nu = 0;
+  for (; nu + kDU <= nb; nu += kDU) {
+    double v[kDU];
+#pragma unroll
+    for (int u = 0; u < kDU; ++u) v[u] = basis[(long long)(nu + u) * ng + i];
+#pragma unroll
+    for (int u = 0; u < kDU; ++u) {
+      a0 += v[u] * C[nu + u];
+      a1 += v[u] * C[nb + nu + u];
+    }
+  }
+  for (; nu < nb; ++nu) {
+    const double v = basis[(long long)nu * ng + i];
+    a0 += v * C[nu];
+    a1 += v * C[nb + nu];
+  }
+  ug[i] = a0;
+  ug[(long long)ng + i] = a1;
 }
 
 // Restriction to N+; with a guard, a non-finite output records the current step number
-// (guard[0]) into guard[1] by atomic minimum.
+// (guard[0]) into guard[1] by atomic minimum: one atomic per block that holds one, skipped once
+// the step is recorded (a state that is non-finite everywhere would otherwise serialise
+// thousands of atomics on one address).
 __global__ void k_restrict(const double* __restrict__ U, const uint8_t* __restrict__ np,
                            long long vsz, double* __restrict__ o0, double* __restrict__ o1,
                            int* __restrict__ guard) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= vsz) return;
-  const bool in = np[i] != 0;
-  const double v0 = in ? U[i] : 0.0, v1 = in ? U[vsz + i] : 0.0;
-  o0[i] = v0;
-  o1[i] = v1;
-  if (guard != nullptr && !(isfinite(v0) && isfinite(v1))) atomicMin(&guard[1], guard[0]);
+  bool bad = false;
+  if (i < vsz) {
+    const bool in = np[i] != 0;
+    const double v0 = in ? U[i] : 0.0, v1 = in ? U[vsz + i] : 0.0;
+    o0[i] = v0;
+    o1[i] = v1;
+    bad = !(isfinite(v0) && isfinite(v1));
+  }
+  if (guard == nullptr) return;
+  if (__syncthreads_or(bad) && threadIdx.x == 0) {
+    const int step = guard[0];
+    if (guard[1] > step) atomicMin(&guard[1], step);
+  }
 }
 
 // guard[0] = step number (from 1), guard[1] = first step with a non-finite output
@@ -147,15 +173,21 @@ __global__ void k_scan_init(unsigned long long* __restrict__ out2) {
 
 // out2[0] = max over M+ nodes and their six faces of |c_nb - c| / h (eq cfl_condition),
 // out2[1] = max over M+ of |rho|.  M+ nodes are interior to the cube, so every neighbour exists.
-__global__ void k_cfl_scan(const double* __restrict__ rho, const double* __restrict__ c,
-                           const uint8_t* __restrict__ mp, int n, double h,
-                           unsigned long long* __restrict__ out2) {
+// A fixed grid strides over the nodes; each block reduces its maxima (waves, then LDS) and
+// issues one atomic per output.
+constexpr int kScanBlocks = 512;
+__global__ __launch_bounds__(256) void k_cfl_scan(const double* __restrict__ rho,
+                                                  const double* __restrict__ c,
+                                                  const uint8_t* __restrict__ mp, int n, double h,
+                                                  unsigned long long* __restrict__ out2) {
+  __shared__ unsigned long long sg[4], sr[4];
   const long long vsz = (long long)n * n * n;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long st[3] = {(long long)n * n, (long long)n, 1};
   unsigned long long gb = 0ull, rb = 0ull;
-  if (i < vsz && mp[i]) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < vsz;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (!mp[i]) continue;
     const double c0 = c[i];
-    const long long st[3] = {(long long)n * n, (long long)n, 1};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const unsigned long long up = mag_bits((c[i + st[a]] - c0) / h);
@@ -163,14 +195,22 @@ __global__ void k_cfl_scan(const double* __restrict__ rho, const double* __restr
       gb = up > gb ? up : gb;
       gb = dn > gb ? dn : gb;
     }
-    rb = mag_bits(rho[i]);
+    const unsigned long long r = mag_bits(rho[i]);
+    rb = r > rb ? r : rb;
   }
   for (int off = 32; off > 0; off >>= 1) {
     const unsigned long long go = __shfl_xor(gb, off), ro = __shfl_xor(rb, off);
     gb = go > gb ? go : gb;
     rb = ro > rb ? ro : rb;
   }
-  if ((threadIdx.x & 63) == 0) {
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sg[w] = gb; sr[w] = rb; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+      gb = sg[k] > gb ? sg[k] : gb;
+      rb = sr[k] > rb ? sr[k] : rb;
+    }
     if (gb) atomicMax(&out2[0], gb);
     if (rb) atomicMax(&out2[1], rb);
   }
@@ -179,7 +219,7 @@ __global__ void k_cfl_scan(const double* __restrict__ rho, const double* __restr
 unsigned grid1(long long n) { return (unsigned)((n + kB - 1) / kB); }
 
 struct StepLayout {
-  size_t b2, X, g, C, ug, guard, solve_ws, total;
+  size_t b2, X, C, ug, guard, solve_ws, total;
 };
 
 StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
@@ -188,7 +228,6 @@ StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
   size_t o = 0;
   L.b2 = o; o = align_up(o + 2 * V, 256);
   L.X = o; o = align_up(o + 2 * V, 256);
-  L.g = o; o = align_up(o + 2 * sizeof(double) * b->n_in, 256);
   L.C = o; o = align_up(o + 2 * sizeof(double) * b->n_basis, 256);
   L.ug = o; o = align_up(o + 2 * sizeof(double) * b->n_gamma, 256);
   L.guard = o; o = align_up(o + 2 * sizeof(int), 256);
@@ -227,7 +266,6 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   char* ws = static_cast<char*>(o.workspace);
   double* b2 = reinterpret_cast<double*>(ws + L.b2);
   double* X = reinterpret_cast<double*>(ws + L.X);
-  double* gv = reinterpret_cast<double*>(ws + L.g);
   double* C = reinterpret_cast<double*>(ws + L.C);
   double* ug = reinterpret_cast<double*>(ws + L.ug);
   int* gd = guard ? reinterpret_cast<int*>(ws + L.guard) : nullptr;
@@ -241,9 +279,8 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   DPM_TRY_HIP(hipGetLastError());
   DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, nullptr));
   // Step 5: Tr_gamma_in G f, least squares, densities
-  gather(X, vsz, b->idx_in, b->n_in, 2, gv, s);
-  qr_solve(b, 2, gv, C, s);
-  hipLaunchKernelGGL(k_density, dim3(grid1(b->n_gamma), 2), dim3(kB), 0, s, b->basis, C,
+  qr_solve_traces(b, 2, X, vsz, C, s);
+  hipLaunchKernelGGL(k_density, dim3(grid1(b->n_gamma)), dim3(kB), 0, s, b->basis, C,
                      b->n_basis, b->n_gamma, ug);
   // Steps 6-7: Green's formula as one AP solve per species
   // b2 holds sigma 1_{M+} f, zero on M-: add the M- part (sigma - Lap_h)[u_gamma] in place
@@ -354,7 +391,8 @@ dpm_status cfl_scan_impl(const dpm_bep* b, const double* rho, const double* c, d
   const long long vsz = (long long)g.n * g.n * g.n;
   auto* o = reinterpret_cast<unsigned long long*>(out2);
   hipLaunchKernelGGL(k_scan_init, dim3(1), dim3(64), 0, s, o);
-  hipLaunchKernelGGL(k_cfl_scan, dim3(grid1(vsz)), dim3(kB), 0, s, rho, c, b->m_plus, g.n, g.h, o);
+  const unsigned nblk = grid1(vsz) < (unsigned)kScanBlocks ? grid1(vsz) : (unsigned)kScanBlocks;
+  hipLaunchKernelGGL(k_cfl_scan, dim3(nblk), dim3(kB), 0, s, rho, c, b->m_plus, g.n, g.h, o);
   DPM_TRY_HIP(hipGetLastError());
   return DPM_OK;
 }
