@@ -526,7 +526,7 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
   __shared__ __align__(16) T tile[W * P];
   __shared__ __align__(16) T tab[GTAB ? 2 : 3 * M];
   // eigenvalue table of the z sweep: lamt[0] = 0, lamt[i] = lam_hat_i (i = 1..N)
-  __shared__ double lamt[ZPASS ? M : 1];
+  __shared__ __align__(16) double lamt[ZPASS ? M : 2];
   __shared__ unsigned long long red[2][kBlock / 64];
 
   const int logical = xcd_remap(blockIdx.x, nblocks);
@@ -569,8 +569,16 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
   constexpr bool STEPMAP = !LINEMAJOR || JPI * (int)sizeof(T) >= 128;
   constexpr int NSTEP = (N + JPI - 1) / JPI;            // steps per thread
   constexpr int IFULL = N / JPI;                        // steps with every j < N
-  const int w = LINEMAJOR ? tid / JPI : tid % W;
-  const int j0 = LINEMAJOR ? tid % JPI : tid / W;
+  // Along y and z (FP64, 16 lines of 16 elements per step) the lanes of each wavefront are
+  // permuted so that every 16-lane LDS pass covers 8 lines x 2 adjacent elements: with the line
+  // pitch even, 16 lines of one element would be an even lane stride, which the LDS serves
+  // slower than odd strides (measured 12% per instruction).  A wavefront still reads and
+  // writes the same 128-byte runs.
+  constexpr bool PERM = !LINEMAJOR && W == 16 && JPI == 16;
+  const int lq = tid & 63, wq = tid >> 6;
+  const int w = LINEMAJOR ? tid / JPI : (PERM ? ((lq & 7) | (((lq >> 4) & 1) << 3)) : tid % W);
+  const int j0 = LINEMAJOR ? tid % JPI
+                           : (PERM ? ((((lq >> 3) & 1) | ((lq >> 5) << 1)) + 4 * wq) : tid / W);
   const int wl = min(w, nlines - 1);                    // lines past the tile's end reload one
   const unsigned off0 = (unsigned)(wl * (int)S_LINE + j0 * (int)S_ELEM) * (unsigned)sizeof(T);
   // last step, clamped to j <= N - 1, relative to that step's base like every other step (an
@@ -703,11 +711,13 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
           // scale X_i by (sqrt(2/M)/2)^6 / (sigma + lambda_x + lambda_y + lambda_z), i = 2k, 2k+1
           const double bxy = sig + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]);
           constexpr double kNorm = 1.0 / (8.0 * (double)M * (double)M * (double)M);
-          const double* lp = lamt + 2 * g;
+          // (lambda_2k, lambda_2k+1) as one aligned 16-byte read
+          const C2<double>* lp = reinterpret_cast<const C2<double>*>(lamt) + g;
 #pragma unroll
           for (int s2 = 0; s2 < K::V; ++s2) {
-            const double d0 = kNorm * recip(bxy + p.inv_h2 * lp[2 * s2 * G]);
-            const double d1 = kNorm * recip(bxy + p.inv_h2 * lp[2 * s2 * G + 1]);
+            const C2<double> lv = lp[s2 * G];
+            const double d0 = kNorm * recip(bxy + p.inv_h2 * lv.x);
+            const double d1 = kNorm * recip(bxy + p.inv_h2 * lv.y);
             o[s2].x = (T)((double)o[s2].x * d0);
             o[s2].y = (T)((double)o[s2].y * d1);
             ob[s2 * G] = o[s2];
