@@ -3,8 +3,10 @@
 
 Workload (one step): nrhs = 64 right-hand sides with i.i.d. N(0,1) entries (seed 0, drawn on
 the device) on the 255^3 interior grid of the cube [-1.5, 1.5]^3 (h = 3/256), sigma = 1, solved
-by aux_solve_batched to a relative max-norm error of 1e-10.  Paths timed: FP64 transforms, and
-FP32 transforms with FP64 residual refinement.  `value` is the solves/s of the fastest path
+by aux_solve_batched to a relative max-norm error of 1e-10.  Paths timed: FP64 FFT-form
+transforms, FP32 transforms with FP64 residual refinement, split-bf16 dense transforms on the
+matrix cores with FP64 refinement, and FP64 dense transforms on the FP64 matrix cores (the GEMM
+form).  `value` is the solves/s of the fastest path
 whose error, checked against the CPU FP64 oracle on a sampled right-hand side, meets 1e-10.
 
 Serving (the "serving" object): a continuous-batching server over 64 simulations of mixed grid
@@ -246,7 +248,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--sigma", type=float, default=1.0)
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--paths", default="fp64,fp32_ir,bf16x3_ir")
+    ap.add_argument("--paths", default="fp64,fp32_ir,bf16x3_ir,fp64_gemm")
     ap.add_argument("--cpu-sample", type=int, default=3,
                     help="right-hand sides copied to the host for the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -296,6 +298,7 @@ def main():
         "fp64": dict(prec="fp64", max_refine=0, dtype="f64"),
         "fp32_ir": dict(prec="fp32", max_refine=3, dtype="f32 transforms + f64 refinement"),
         "bf16x3_ir": dict(prec="bf16x3", max_refine=5, dtype="bf16x3 MFMA + f64 refinement"),
+        "fp64_gemm": dict(prec="fp64_gemm", max_refine=0, dtype="f64 dense DST on FP64 MFMA"),
     }
     results = {}
     for name in [p for p in args.paths.split(",") if p]:
@@ -339,6 +342,15 @@ def main():
                              rhs_per_launch=chunk,
                              refine_iters=info["refine_iters"], dtype=cfg["dtype"],
                              u0=u[0].cpu().numpy())
+        if cfg["prec"] == "fp64_gemm":
+            # the dense form is bound by the FP64 matrix cores: 2 MP^2 flop per line and product
+            # (MP = 256, the padded matrix), one product per x/y sweep line, two per z line
+            mp = (n + 31) // 32 * 32
+            fl = {k: chunk * n * n * 2 * mp * mp * (2 if k == "z_fused" else 1) for k in kern}
+            results[name]["mfma"] = {
+                k: {"tflops": round(fl[k] / (kern[k]["mean_ms"] * 1e-3) / 1e12, 1),
+                    "frac_of_fp64_peak": round(fl[k] / (kern[k]["mean_ms"] * 1e-3) / 78.6e12, 3)}
+                for k in kern}
         log(f"[bench] {name}: {ms:.3f} ms/step, {nrhs / (ms * 1e-3):.1f} solves/s, "
             f"refine_iters={info['refine_iters']}, kernels={kern}")
 
@@ -387,7 +399,7 @@ def main():
         # dominant kernel of the headline path: largest total time per step
         kern = best["kernels"]
         dom = max(kern, key=lambda k: kern[k]["timed_launches_per_step"] * kern[k]["mean_ms"])
-        rb = 8 if best_name == "fp64" else 4
+        rb = 8 if best_name in ("fp64", "fp64_gemm") else 4
         in_b = 8 if (dom in ("x_first", "x_residual") and rb == 4) else rb
         out_b = 8 if (dom in ("x_last", "x_update") and rb == 4) else rb
         per_launch_rhs = best["rhs_per_launch"]

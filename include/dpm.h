@@ -45,7 +45,9 @@ typedef enum {
 typedef enum {
   DPM_FP64 = 0,   /* FP64 transforms */
   DPM_FP32 = 1,   /* FP32 transforms (FP64 residual refinement when io_fp64 and max_refine > 0) */
-  DPM_BF16X3 = 2  /* split bf16 hi/lo dense-DST on MFMA, FP32 accumulation (N <= 256) */
+  DPM_BF16X3 = 2,  /* split bf16 hi/lo dense-DST on MFMA, FP32 accumulation (N <= 256) */
+  DPM_FP64_GEMM = 3 /* FP64 transforms as dense DST-I products on the FP64 matrix cores (N <= 255;
+                       FP64 I/O, no refinement): the dense counterpart of DPM_FP64 */
 } dpm_precision;
 
 typedef struct {

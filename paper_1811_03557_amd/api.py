@@ -12,7 +12,8 @@ import torch
 
 from . import _lib as L
 
-PRECISIONS = {"fp64": L.DPM_FP64, "fp32": L.DPM_FP32, "bf16x3": L.DPM_BF16X3}
+PRECISIONS = {"fp64": L.DPM_FP64, "fp32": L.DPM_FP32, "bf16x3": L.DPM_BF16X3,
+              "fp64_gemm": L.DPM_FP64_GEMM}
 
 
 def _stream(stream) -> int:

@@ -79,10 +79,13 @@ int default_chunk(int n, int nrhs, int real_bytes, bool need_ws) {
 bool needs_ws(const dpm_opts& o) {
   if (o.prec == DPM_FP32) return o.io_fp64 != 0;
   if (o.prec == DPM_FP64) return o.max_refine > 0;
+  if (o.prec == DPM_FP64_GEMM) return false;  // in place in u, like plain FP64
   return true;  // BF16X3: FP32 tile workspace
 }
 
-int real_bytes_of(const dpm_opts& o) { return o.prec == DPM_FP64 ? 8 : 4; }
+int real_bytes_of(const dpm_opts& o) {
+  return (o.prec == DPM_FP64 || o.prec == DPM_FP64_GEMM) ? 8 : 4;
+}
 
 }  // namespace
 
@@ -111,7 +114,8 @@ dpm_status validate_grid(const dpm_grid* g) {
 
 dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o) {
   if (!o) { set_error("opts is NULL"); return DPM_EINVAL; }
-  if (o->prec != DPM_FP64 && o->prec != DPM_FP32 && o->prec != DPM_BF16X3) {
+  if (o->prec != DPM_FP64 && o->prec != DPM_FP32 && o->prec != DPM_BF16X3 &&
+      o->prec != DPM_FP64_GEMM) {
     set_error("unknown precision %d", o->prec);
     return DPM_EINVAL;
   }
@@ -127,6 +131,10 @@ dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o) {
   }
   if (o->rhs_chunk < 0) { set_error("rhs_chunk must be >= 0"); return DPM_EINVAL; }
   if (o->prec == DPM_BF16X3 && g.n > 255) { set_error("DPM_BF16X3 supports n <= 255"); return DPM_EINVAL; }
+  if (o->prec == DPM_FP64_GEMM && (g.n > 255 || o->max_refine != 0)) {
+    set_error("DPM_FP64_GEMM supports n <= 255 without refinement");
+    return DPM_EINVAL;
+  }
   return DPM_OK;
 }
 
@@ -141,13 +149,17 @@ dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, s
   return DPM_OK;
 }
 
+// Transform forms of the sweeps: real FFT (dst_fft.hip), split-bf16 dense products on the
+// bf16 matrix cores, FP64 dense products on the FP64 matrix cores.
+enum { FORM_FFT = 0, FORM_BF16X3 = 1, FORM_F64MM = 2 };
+
 // One solve (five sweeps) of nb right-hand sides.  in_kind/out_kind select the first and last
 // sweeps; vol_in/vol_out are the first sweep's source and the last sweep's destination, ws the
 // volume the middle sweeps work on.
 static dpm_status five_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind in_kind,
                               const void* src, OutKind out_kind, void* dst, void* ws,
                               const double* b, const double* u, const SolveFlags* fl, int rhs0,
-                              int nb, bool gated, bool bf16, const double* sig_rhs,
+                              int nb, bool gated, int form, const double* sig_rhs,
                               hipStream_t s) {
   PassArgs a{};
   a.sigma_rhs = sig_rhs;
@@ -171,8 +183,9 @@ static dpm_status five_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind 
                    : first ? SW_X_FIRST : SW_X_LAST;
     const bool tm = timing_on(rhs0, nb);
     if (tm) timing_before(s);
-    dpm_status st = bf16 ? launch_bf16x3_pass(g.n, ax, z, ik, ok, q, pl, nb, s)
-                         : launch_dst_pass(rb, g.n, ax, z, ik, ok, q, nb, s);
+    dpm_status st = form == FORM_BF16X3 ? launch_bf16x3_pass(g.n, ax, z, ik, ok, q, pl, nb, s)
+                  : form == FORM_F64MM  ? launch_f64mm_pass(g.n, ax, z, q, pl, nb, s)
+                                        : launch_dst_pass(rb, g.n, ax, z, ik, ok, q, nb, s);
     if (tm) timing_after(s, kind);
     return st;
   };
@@ -189,7 +202,7 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
   const Plan* pl = nullptr;
   DPM_TRY(get_plan(g.n, &pl));
   const int rb = real_bytes_of(o);
-  const bool bf16 = o.prec == DPM_BF16X3;
+  const int form = o.prec == DPM_BF16X3 ? FORM_BF16X3 : o.prec == DPM_FP64_GEMM ? FORM_F64MM : FORM_FFT;
   const bool ws_needed = needs_ws(o);
   const int chunk = o.rhs_chunk > 0 ? (o.rhs_chunk < nrhs ? o.rhs_chunk : nrhs)
                                     : default_chunk(g.n, nrhs, rb, ws_needed);
@@ -219,7 +232,8 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
   const size_t io_bytes = o.io_fp64 ? 8 : 4;
   const bool refine = o.max_refine > 0;
   // the flags serve the paths that track max-norms (FP64 iterate with workspace transforms)
-  const bool plain = (o.prec == DPM_FP64 && !refine) || (o.prec == DPM_FP32 && !o.io_fp64);
+  const bool plain = (o.prec == DPM_FP64 && !refine) || (o.prec == DPM_FP32 && !o.io_fp64) ||
+                     o.prec == DPM_FP64_GEMM;
   if (!plain) {
     hipLaunchKernelGGL(k_flags_reset, dim3((nrhs + 255) / 256), dim3(256), 0, s, fl, nrhs);
     DPM_TRY_HIP(hipGetLastError());
@@ -229,25 +243,25 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
     const int nb = (nrhs - c0) < chunk ? (nrhs - c0) : chunk;
     const char* bc = static_cast<const char*>(b) + (size_t)c0 * vol * io_bytes;
     char* uc = static_cast<char*>(u) + (size_t)c0 * vol * io_bytes;
-    if (o.prec == DPM_FP64 && !refine) {
+    if ((o.prec == DPM_FP64 && !refine) || o.prec == DPM_FP64_GEMM) {
       // FP64 transforms in place in u: no workspace traffic beyond u itself
       // (no max-norm tracking: only refinement uses it)
       DPM_TRY(five_sweeps(pl, 8, g, IN_WS, bc, OUT_F64, uc, uc, nullptr, nullptr, nullptr, c0, nb,
-                          false, false, sig_dev, s));
+                          false, form, sig_dev, s));
     } else if (o.prec == DPM_FP32 && !o.io_fp64) {
       DPM_TRY(five_sweeps(pl, 4, g, IN_WS, bc, OUT_WS, uc, uc, nullptr, nullptr, nullptr, c0, nb,
-                          false, false, sig_dev, s));
+                          false, form, sig_dev, s));
     } else {
       // reduced-precision (or FP64) transforms on the workspace, FP64 iterate in u
       const double* bd = reinterpret_cast<const double*>(bc);
       double* ud = reinterpret_cast<double*>(uc);
       DPM_TRY(five_sweeps(pl, rb, g, IN_F64, bc, OUT_F64, uc, vol_ws, nullptr, nullptr, &fl, c0,
-                          nb, false, bf16, sig_dev, s));
+                          nb, false, form, sig_dev, s));
       hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, 0, o.rtol);
       DPM_TRY_HIP(hipGetLastError());
       for (int k = 1; k <= o.max_refine; ++k) {
         DPM_TRY(five_sweeps(pl, rb, g, IN_RESID, nullptr, OUT_UPD, uc, vol_ws, bd, ud, &fl, c0,
-                            nb, true, bf16, sig_dev, s));
+                            nb, true, form, sig_dev, s));
         hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, k, o.rtol);
         DPM_TRY_HIP(hipGetLastError());
       }

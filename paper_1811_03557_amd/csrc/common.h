@@ -50,6 +50,8 @@ struct Plan {
   uint16_t* s_hi = nullptr;
   uint16_t* s_lo = nullptr;
   int mpad = 0;
+  // the same matrix in FP64 for the FP64 matrix-core path (n <= 255 only, else null)
+  double* s_d = nullptr;
 };
 
 // Returns the plan of the current device for size n (creating it on first use).
@@ -85,6 +87,10 @@ dpm_status launch_dst_pass(int real_bytes, int n, AxisKind ax, bool zpass, InKin
 // ---------------------------------------------------------------- BF16x3 MFMA dense DST
 dpm_status launch_bf16x3_pass(int n, AxisKind ax, bool zpass, InKind in, OutKind out,
                               const PassArgs& a, const Plan* plan, int nrhs, hipStream_t s);
+
+// ---------------------------------------------------------------- FP64 matrix-core dense DST
+dpm_status launch_f64mm_pass(int n, AxisKind ax, bool zpass, const PassArgs& a, const Plan* plan,
+                             int nrhs, hipStream_t s);
 
 // ---------------------------------------------------------------- measurement support
 // Sweep kinds reported by dpm_timing_end.

@@ -82,6 +82,8 @@ static dpm_status build_plan(int n, Plan* p) {
   // dense orthonormal DST-I matrix padded to a multiple of 32, split into bf16 hi + lo
   int mpad = (n + 31) / 32 * 32;
   std::vector<uint16_t> hi((size_t)mpad * mpad, 0), lo((size_t)mpad * mpad, 0);
+  const bool dense64 = mpad <= 256;
+  std::vector<double> sd(dense64 ? (size_t)mpad * mpad : 0, 0.0);
   const double nrm = std::sqrt(2.0 / M);
   for (int j = 1; j <= n; ++j)
     for (int k = 1; k <= n; ++k) {
@@ -91,6 +93,7 @@ static dpm_status build_plan(int n, Plan* p) {
       float r = (float)(v - (double)bf16_to_f(h));
       hi[(size_t)(j - 1) * mpad + (k - 1)] = h;
       lo[(size_t)(j - 1) * mpad + (k - 1)] = bf16_rne(r);
+      if (dense64) sd[(size_t)(j - 1) * mpad + (k - 1)] = v;
     }
   p->mpad = mpad;
   DPM_TRY_HIP(hipMalloc(&p->tw_f, sizeof(float) * tabf.size()));
@@ -103,6 +106,10 @@ static dpm_status build_plan(int n, Plan* p) {
   DPM_TRY_HIP(hipMemcpy(p->lam, lam.data(), sizeof(double) * n, hipMemcpyHostToDevice));
   DPM_TRY_HIP(hipMemcpy(p->s_hi, hi.data(), sizeof(uint16_t) * hi.size(), hipMemcpyHostToDevice));
   DPM_TRY_HIP(hipMemcpy(p->s_lo, lo.data(), sizeof(uint16_t) * lo.size(), hipMemcpyHostToDevice));
+  if (dense64) {
+    DPM_TRY_HIP(hipMalloc(&p->s_d, sizeof(double) * sd.size()));
+    DPM_TRY_HIP(hipMemcpy(p->s_d, sd.data(), sizeof(double) * sd.size(), hipMemcpyHostToDevice));
+  }
   return DPM_OK;
 }
 
@@ -124,6 +131,7 @@ dpm_status get_plan(int n, const Plan** out) {
     (void)hipFree(p->lam);
     (void)hipFree(p->s_hi);
     (void)hipFree(p->s_lo);
+    (void)hipFree(p->s_d);
     delete p;
     return st;
   }

@@ -247,3 +247,44 @@ def test_per_rhs_sigma_matches_single_solves():
                                        rtol=1e-10).cpu().numpy()[0]
             assert np.array_equal(ub[i], ui), (prec, i)
             assert oaux.rel_err_inf(ub[i], oaux.aux_solve(b[i], s, h)) < 1e-10
+
+
+@pytest.mark.parametrize("n", [7, 15, 31, 63, 127, 255])
+def test_fp64_gemm_parity(n):
+    """FP64 dense-DST sweeps on the FP64 matrix cores (the GEMM form): the FP64 bar, 1e-12,
+    against the oracle on a ragged batch of 3 (chunk 2 at 255^3: a full and a partial launch)
+    and on sine modes in closed form."""
+    dev = need_gpu()
+    say(f"fp64 gemm parity n={n}")
+    h, _ = inp.grid(n)
+    nrhs = 3 if n <= 127 else 2
+    b = inp.rhs_normal(n, nrhs, seed=n + 1)
+    ref = oaux.aux_solve(b, 1.0, h)
+    u = _solve(b, 1.0, h, dev, prec="fp64_gemm")
+    assert _max_rel(u, ref) < TOL["fp64"]
+    if n >= 127:
+        u2 = _solve(b, 1.0, h, dev, prec="fp64_gemm", rhs_chunk=1)
+        assert np.array_equal(u, u2)  # the chunking does not change the arithmetic
+    j = np.arange(1, n + 1)
+    ks = [(1, 1, 1), (n, 2, (n + 1) // 2)]
+    bs, refs = [], []
+    for (k1, k2, k3) in ks:
+        s = [np.sin(np.pi * ((j * k) % (2 * (n + 1))) / (n + 1)) for k in (k1, k2, k3)]
+        bm = s[2][:, None, None] * s[1][None, :, None] * s[0][None, None, :]
+        lam = sum(4.0 / h**2 * np.sin(np.pi * k / (2 * (n + 1))) ** 2 for k in (k1, k2, k3))
+        bs.append(bm)
+        refs.append(bm / (1e4 + lam))
+    um = _solve(np.stack(bs), 1e4, h, dev, prec="fp64_gemm")
+    assert _max_rel(um, np.stack(refs)) < TOL["fp64"]
+
+
+def test_fp64_gemm_rejects_refinement_and_large_n():
+    import torch
+    from paper_1811_03557_amd import api, _lib
+    dev = need_gpu()
+    b = torch.zeros((2, 7, 7, 7), dtype=torch.float64, device=dev)
+    with pytest.raises(_lib.DPMError):
+        api.aux_solve_batched(b, 1.0, 0.1, prec="fp64_gemm", max_refine=1)
+    b = torch.zeros((1, 511, 511, 511), dtype=torch.float64, device=dev)
+    with pytest.raises(_lib.DPMError):
+        api.aux_solve_batched(b, 1.0, 3.0 / 512, prec="fp64_gemm")
