@@ -232,12 +232,12 @@ __device__ __forceinline__ double vval(const double* __restrict__ A, int m, int 
 }
 
 // G = V^T V (n x n, row-major), upper triangle of 32 x 32 tiles (tile row <= tile column), the
-// rows of V split into chunks of kGC rows over blockIdx.y: block (tile, chunk) writes its
+// rows of V split into chunks of rc rows over blockIdx.y: block (tile, chunk) writes its
 // partial sum to Gp[chunk], k_gram_reduce adds the chunks in order (deterministic).  Rows of a
 // chunk are staged through LDS 32 at a time; each thread owns a 2 x 2 block of the tile.
-constexpr int kGT = 32, kGC = 1024;
+constexpr int kGT = 32;
 __global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ A, int m, int n,
-                                                   double* __restrict__ Gp) {
+                                                   int rc, double* __restrict__ Gp) {
   __shared__ double va[kGT][kGT + 1], vb[kGT][kGT + 1];  // [row][column]
   const int nt = (n + kGT - 1) / kGT;
   // tile index -> (ta, tb), ta <= tb, row-major over the upper triangle
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ A,
   while (tile >= nt - ta) { tile -= nt - ta; ++ta; }
   const int tb = ta + tile;
   const int a0 = ta * kGT, b0 = tb * kGT;
-  const int i_lo = blockIdx.y * kGC, i_hi = min(m, i_lo + kGC);
+  const int i_lo = blockIdx.y * rc, i_hi = min(m, i_lo + rc);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;  // outputs (a0+2tx+{0,1}, b0+2ty+{0,1})
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   const int start = max(i_lo, b0);  // V[i][k] = 0 for i < k, and b0 >= a0
@@ -280,17 +280,24 @@ __global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ A,
     }
 }
 
-// G[a][b] = sum over chunks of Gp[chunk][a][b], for a <= b (the part k_tinv reads).
-__global__ void k_gram_reduce(const double* __restrict__ Gp, int nchunk, int n,
-                              double* __restrict__ G) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * n) return;
-  const int ra = e / n, cb = e - ra * n;
+// G[a][b] = sum over chunks of Gp[chunk][a][b], for a <= b (the part k_tinv reads): one
+// wavefront per entry, lane l adding chunks l, l + 64, ..., then a fixed butterfly across the
+// lanes (the same order every run).
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ Gp, int nchunk,
+                                                     int n, double* __restrict__ G) {
+  const long long e = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (e >= (long long)n * n) return;  // uniform across the wavefront
+  const int ra = (int)(e / n), cb = (int)(e - (long long)ra * n);
   // entries with a > b are not written by k_gram_part (and not read)
-  if (ra > cb) { G[e] = 0.0; return; }
+  if (ra > cb) {
+    if (lane == 0) G[e] = 0.0;
+    return;
+  }
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += Gp[(long long)c * n * n + e];
-  G[e] = s;
+  for (int c = lane; c < nchunk; c += 64) s += Gp[(long long)c * n * n + e];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) G[e] = s;
 }
 
 // T (row-major, upper triangular).  With tau_j = 2 / (v_j^T v_j) (every reflector here, or
@@ -477,6 +484,15 @@ void qr_solve_traces(const dpm_bep* bep, int nvec, const double* vol, long long 
                      bep->n_in, bep->n_basis, vol, vsz, bep->idx_in, C);
 }
 
+// Row chunks of the Gram product: about 2,048 blocks over the upper-triangle tiles, chunks of
+// 32 to 1,024 rows.
+int gram_chunks(int m, int n) {
+  const int nt = (n + kGT - 1) / kGT, tiles = nt * (nt + 1) / 2;
+  int rc = (int)(((long long)m * tiles + 2047) / 2048);
+  rc = rc < 32 ? 32 : (rc > 1024 ? 1024 : rc);
+  return (m + rc - 1) / rc;
+}
+
 // Columns of the reduced-BEP matrix at the handle's sigma (M- operator on the densities, batched
 // AP solves, traces on gamma_in), the Householder QR, the rank test and the least-squares
 // operator P, into the handle's buffers.
@@ -559,16 +575,17 @@ dpm_status factor_bep(dpm_bep* b, hipStream_t s, double* A_out) {
     if (!al((void**)&G, sizeof(double) * nn) || !al((void**)&T, sizeof(double) * nn) ||
         !al((void**)&W, sizeof(double) * nn) || !al((void**)&K, sizeof(double) * nn) ||
         !al((void**)&Rinv, sizeof(double) * nn) ||
-        !al((void**)&Gp, sizeof(double) * nn * (size_t)((nin + kGC - 1) / kGC))) {
+        !al((void**)&Gp, sizeof(double) * nn * (size_t)gram_chunks(nin, n_basis))) {
       free_all();
       set_error("dpm_build_boundary_matrix: device allocation failed");
       return DPM_ENOMEM;
     }
-    const int nt = (n_basis + kGT - 1) / kGT, nchunk = (nin + kGC - 1) / kGC;
+    const int nt = (n_basis + kGT - 1) / kGT, nchunk = gram_chunks(nin, n_basis);
+    const int rc = (nin + nchunk - 1) / nchunk;
     hipLaunchKernelGGL(k_gram_part, dim3(nt * (nt + 1) / 2, nchunk), dim3(256), 0, s, b->A, nin,
-                       n_basis, Gp);
-    hipLaunchKernelGGL(k_gram_reduce, dim3(grid1((long long)nn)), dim3(kB), 0, s, Gp, nchunk,
-                       n_basis, G);
+                       n_basis, rc, Gp);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((nn + 3) / 4)), dim3(256), 0, s, Gp,
+                       nchunk, n_basis, G);
     hipLaunchKernelGGL(k_tinv, dim3(n_basis), dim3(256), 0, s, G, b->tau, n_basis, T);
     hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, b->A, nin, n_basis, Rinv);
     hipLaunchKernelGGL(k_v1tt, dim3(grid1((long long)nn)), dim3(kB), 0, s, b->A, nin, n_basis, T, W);
