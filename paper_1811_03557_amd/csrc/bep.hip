@@ -36,24 +36,19 @@ __global__ void k_gpos(const int32_t* __restrict__ idx, int ng, int32_t* __restr
 }
 
 // out[c][q] = (sigma - Lap_h)[v_c] at the M- nodes q where it can be nonzero, v_c the density
-// dens[c0 + c] on gamma extended by zero (zero Dirichlet data outside the cube).  Those nodes are
-// gamma_ex and the M- neighbours of gamma_ex (an M- neighbour of a gamma_in node is in
-// gamma_ex): thread (e, k) takes gamma node e, if it is in gamma_ex, and its k-th node of
-// {itself, 6 neighbours}; a node reached from two gamma_ex nodes gets the same value twice.
-// Other entries of out are left as they are (the caller has them at zero on M-).
-__device__ __forceinline__ double dens_at(const double* __restrict__ dr,
-                                          const int32_t* __restrict__ gpos, long long q) {
-  const int gi = gpos[q];
-  return gi >= 0 ? dr[gi] : 0.0;
-}
-
-__global__ void k_minus_rhs(const double* __restrict__ dens, int c0, int ng,
+// dens[c0 + c] on gamma extended by zero (zero Dirichlet data outside the cube), c < ncol.
+// Those nodes are gamma_ex and the M- neighbours of gamma_ex (an M- neighbour of a gamma_in node
+// is in gamma_ex): thread (e, k) takes gamma node e, if it is in gamma_ex, and its k-th node of
+// {itself, 6 neighbours}, finds the gamma positions of that node's stencil once and then
+// writes every column; a node reached from two gamma_ex nodes gets the same value twice.  The
+// set of nodes written depends only on the geometry.  Other entries of out are left as they
+// are (the caller has them at zero on M-).
+__global__ void k_minus_rhs(const double* __restrict__ dens, int c0, int ncol, int ng,
                             const int32_t* __restrict__ idx, const uint8_t* __restrict__ is_in,
                             const int32_t* __restrict__ gpos, const uint8_t* __restrict__ mp,
                             int n, double sigma, double inv_h2, double* __restrict__ out,
                             long long vsz) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
   const int e = t / 7, k = t - 7 * (t / 7);
   if (e >= ng || is_in[e]) return;
   const unsigned p = (unsigned)idx[e], un = (unsigned)n;
@@ -64,18 +59,20 @@ __global__ void k_minus_rhs(const double* __restrict__ dens, int c0, int ng,
   if (x < 0 || x >= n || y < 0 || y >= n || z < 0 || z >= n) return;
   const long long q = ((long long)z * n + y) * n + x;
   if (mp[q]) return;
-  const double* dr = dens + (long long)(c0 + c) * ng;
-  double nb = 0.0;
-  if (x > 0) nb += dens_at(dr, gpos, q - 1);
-  if (x < n - 1) nb += dens_at(dr, gpos, q + 1);
-  if (y > 0) nb += dens_at(dr, gpos, q - n);
-  if (y < n - 1) nb += dens_at(dr, gpos, q + n);
-  if (z > 0) nb += dens_at(dr, gpos, q - (long long)n * n);
-  if (z < n - 1) nb += dens_at(dr, gpos, q + (long long)n * n);
-  out[(long long)c * vsz + q] = (sigma + 6.0 * inv_h2) * dens_at(dr, gpos, q) - inv_h2 * nb;
+  // gamma positions of the node and its in-cube neighbours (-1: not on gamma or outside)
+  const long long nn = (long long)n * n;
+  const int g0 = gpos[q];
+  const int gx0 = x > 0 ? gpos[q - 1] : -1, gx1 = x < n - 1 ? gpos[q + 1] : -1;
+  const int gy0 = y > 0 ? gpos[q - n] : -1, gy1 = y < n - 1 ? gpos[q + n] : -1;
+  const int gz0 = z > 0 ? gpos[q - nn] : -1, gz1 = z < n - 1 ? gpos[q + nn] : -1;
+  const double diag = sigma + 6.0 * inv_h2;
+  for (int c = 0; c < ncol; ++c) {
+    const double* dr = dens + (long long)(c0 + c) * ng;
+    auto at = [&](int gi) { return gi >= 0 ? dr[gi] : 0.0; };
+    const double nb = at(gx0) + at(gx1) + at(gy0) + at(gy1) + at(gz0) + at(gz1);
+    out[(long long)c * vsz + q] = diag * at(g0) - inv_h2 * nb;
+  }
 }
-
-
 
 // A[i + (c0+c)*n_in] = dens[(c0+c)][pos_in[i]] - u[c][idx_in[i]]
 __global__ void k_trace_columns(const double* __restrict__ dens, const double* __restrict__ u,
@@ -468,7 +465,7 @@ void minus_rhs(const dpm_bep* b, const double* dens, int c0, int ncol, double* o
                hipStream_t s) {
   const dpm_grid& g = b->grid;
   const long long vsz = (long long)g.n * g.n * g.n;
-  hipLaunchKernelGGL(k_minus_rhs, dim3(grid1(7LL * b->n_gamma), ncol), dim3(kB), 0, s, dens, c0,
+  hipLaunchKernelGGL(k_minus_rhs, dim3(grid1(7LL * b->n_gamma)), dim3(kB), 0, s, dens, c0, ncol,
                      b->n_gamma, b->idx, b->is_in, b->gpos, b->m_plus, g.n, g.sigma,
                      1.0 / (g.h * g.h), out, vsz);
 }
@@ -523,7 +520,9 @@ dpm_status factor_bep(dpm_bep* b, hipStream_t s, double* A_out) {
   dpm_status st = DPM_OK;
   for (int c0 = 0; c0 < n_basis && st == DPM_OK; c0 += chunk) {
     const int nc = (n_basis - c0) < chunk ? (n_basis - c0) : chunk;
-    fill_zero(rhs, vsz * nc, s);
+    // zeros once: every chunk writes the same nodes (the set depends on the geometry only) and
+    // the solves leave their right-hand sides unchanged
+    if (c0 == 0) fill_zero(rhs, vsz * nc, s);
     minus_rhs(b, b->basis, c0, nc, rhs, s);
     st = aux_solve_impl(g, nc, rhs, u, so, s, nullptr);
     if (st != DPM_OK) break;
