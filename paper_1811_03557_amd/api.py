@@ -362,8 +362,9 @@ def run(bep: BEP, chi: float, rho: torch.Tensor, c: torch.Tensor, t_final: float
                         C.c_void_p(_dev(c, "c", torch.float64)), C.byref(o),
                         C.c_void_p(_stream(stream)), C.byref(info), dts, rbs))
     k = info.steps
-    bep.sigma = 1.0 / info.dt
-    bep._refresh_rdiag()
+    if info.rebuilds > 0:  # the library rebuilt at sigma = 1/dt (the same division)
+        bep.sigma = 1.0 / info.dt
+        bep._refresh_rdiag()
     return {"steps": k, "rebuilds": info.rebuilds, "stop": L.RUN_STOPS[info.stop], "t": info.t,
             "dt": info.dt, "rho_max": info.rho_max, "grad_max": info.grad_max,
             "dt_hist": [dts[i] for i in range(k)], "rebuilt": [bool(rbs[i]) for i in range(k)]}

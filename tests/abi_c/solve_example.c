@@ -128,7 +128,28 @@ int main(void) {
          "sum rho %.6e\n", ng, ngi, bad_step, mass);
   if (bad_step != 0 || !(mass > 0.0) || !isfinite(mass)) return 1;
   dpm_stepper_destroy(st);
+
+  /* ---- 4. adaptive loop (Steps 3-8) from Test A data: the CFL-type bound cuts dt below
+   *         0.5 h^2 at the first step, which rebuilds the boundary matrix in place */
+  void* rws = NULL;
+  HCHECK(hipMalloc(&rws, swb + 256));
+  dpm_opts ro = so;
+  ro.workspace = rws;
+  ro.workspace_bytes = swb + 256;
+  CHECK(dpm_gauss_state(bep, &geo, 1000.0, 100.0, c3, rho, NULL));
+  CHECK(dpm_gauss_state(bep, &geo, 500.0, 50.0, c3, c, NULL));
+  const dpm_run_params rp = {1.0, 1.0, 1e30, 4};
+  dpm_run_info ri;
+  double dts[4];
+  uint8_t rbs[4];
+  CHECK(dpm_run(bep, &rp, rho, c, &ro, NULL, &ri, dts, rbs));
+  printf("adaptive: %d steps, %d rebuilds, dt %.3e -> %.3e (0.5 h^2 = %.3e), stop %d, max rho %.3e\n",
+         ri.steps, ri.rebuilds, dts[0], ri.dt, dt, ri.stop, ri.rho_max);
+  if (ri.steps != 4 || ri.rebuilds < 1 || !rbs[0] || !(dts[0] < dt) || ri.stop != DPM_RUN_MAXSTEPS ||
+      !isfinite(ri.rho_max))
+    return 1;
   dpm_bep_destroy(bep);
+  (void)hipFree(rws);
   (void)hipFree(sws); (void)hipFree(rho); (void)hipFree(c); (void)hipFree(basis);
   (void)hipFree(dist); (void)hipFree(idx); (void)hipFree(is_in); (void)hipFree(mp);
   (void)hipFree(ws); (void)hipFree(db); (void)hipFree(du);

@@ -119,3 +119,24 @@ def test_adaptive_run_stops():
         _compare(res, ref, rg, cg, ro, co)
         assert abs(res["rho_max"] - ref["rho_max"]) <= 1e-10 * ref["rho_max"]
     bep.close()
+
+
+def test_adaptive_run_stops_on_nonfinite_state():
+    """Step 8's guard: a NaN planted at one M+ node stops the loop before any step, the handle
+    keeps its matrix (no rebuild), and the state is left as it was."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    n = 31
+    h = inp.grid(n)[0]
+    sigma0 = 1.0 / (0.5 * h * h)
+    h, ps, B, rho, c, m, Bd, bep = _case(n, 1, 500.0, dev, sigma0)
+    i = int(np.flatnonzero(ps.m_plus.ravel())[11])
+    rho.ravel()[i] = np.nan
+    rg, cg = torch.from_numpy(rho).to(dev), torch.from_numpy(c).to(dev)
+    res = api.run(bep, 1.0, rg, cg, t_final=1.0, max_steps=5)
+    say(f"nonfinite stop: {res['stop']} after {res['steps']} steps")
+    assert res["stop"] == "nonfinite" and res["steps"] == 0 and res["rebuilds"] == 0
+    assert np.isnan(res["rho_max"]) and bep.sigma == sigma0
+    assert np.array_equal(cg.cpu().numpy(), c)
+    bep.close()
