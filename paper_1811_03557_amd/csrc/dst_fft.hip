@@ -285,9 +285,10 @@ __device__ __forceinline__ void dst1_line(T* line, int g, const T* tab) {
 // pad8(a + c) = pad8(a) + c + c/8, so each LDS access is a per-thread base plus an immediate.
 
 // One Stockham stage (radix R, stride NS) writing its outputs to their padded positions.
-// On entry a[s] holds element g + s*G.
-template <typename T, int H, int V, int R, int NS>
-__device__ __forceinline__ void stage_w(const C2<T>* a, int g, C2<T>* buf, const C2<T>* tw) {
+// On entry a[s] holds element g + s*G.  KEEP (the last stage): the outputs also stay in a[],
+// output r of butterfly q in slot q + r*Q, which is the lane's own element g + (q + r*Q)*G.
+template <typename T, int H, int V, int R, int NS, bool KEEP>
+__device__ __forceinline__ void stage_w(C2<T>* a, int g, C2<T>* buf, const C2<T>* tw) {
   constexpr int G = H / V;
   constexpr int Q = V / R;
   constexpr int KT = H / (NS * R);  // twiddle index stride
@@ -342,6 +343,10 @@ __device__ __forceinline__ void stage_w(const C2<T>* a, int g, C2<T>* buf, const
       const int c = NS <= G ? q * G * R + r * NS : (q * G - cq) * R + cq + r * NS;
       wb[c + c / 8] = x[r];
     }
+    if constexpr (KEEP) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[q + r * Q] = x[r];
+    }
   }
 }
 
@@ -349,7 +354,7 @@ template <typename T, int H, int V, int NS>
 __device__ __forceinline__ void fft_stages_w(C2<T>* a, int g, C2<T>* buf, const C2<T>* tw) {
   constexpr int R = radix_at<H, NS>();
   constexpr int G = H / V;
-  stage_w<T, H, V, R, NS>(a, g, buf, tw);
+  stage_w<T, H, V, R, NS, (NS * R >= H)>(a, g, buf, tw);
   wave_sync();
   if constexpr (NS * R < H) {
     const C2<T>* rb = buf + (g + (g >> 3));
@@ -425,15 +430,15 @@ __device__ __forceinline__ void dst1_regs(T* line, int g, const T* tab, const T*
   }
   wave_sync();
   fft_stages_w<T, H, V, 1>(a, g, buf, tw);
-  // F_k = E_k + e^{-2 pi i k/M} O_k; the mirror (H - k) mod H is pad8(G - g) + (V-1-s) G9,
-  // except k = 0, whose mirror is 0
-  const C2<T>* pa = buf + (g + (g >> 3));
+  // F_k = E_k + e^{-2 pi i k/M} O_k.  The lane's own FFT outputs k = g + s*G are still in a[s]
+  // (the last stage keeps them); the mirror (H - k) mod H, another lane's, is read from LDS at
+  // pad8(G - g) + (V-1-s) G9, except k = 0, whose mirror is 0
   const C2<T>* pm = buf + (g > 0 ? (G - g) + ((G - g) >> 3) : G9);
   const C2<T>* pm0 = g > 0 ? pm + (V - 1) * G9 : buf;
   T re[V], im[V];
 #pragma unroll
   for (int s = 0; s < V; ++s) {
-    const C2<T> A = pa[s * G9];
+    const C2<T> A = a[s];
     const C2<T> Bc = s == 0 ? *pm0 : pm[(V - 1 - s) * G9];
     const C2<T> B = {Bc.x, -Bc.y};
     const C2<T> Ev = {A.x + B.x, A.y + B.y};
