@@ -46,12 +46,14 @@ typedef enum {
   DPM_FP64 = 0,   /* FP64 transforms */
   DPM_FP32 = 1,   /* FP32 transforms (FP64 residual refinement when io_fp64 and max_refine > 0) */
   DPM_BF16X3 = 2,  /* split bf16 hi/lo dense-DST on MFMA, FP32 accumulation (N <= 256) */
-  DPM_FP64_GEMM = 3 /* FP64 transforms as dense DST-I products on the FP64 matrix cores (N <= 255;
-                       FP64 I/O, no refinement): the dense counterpart of DPM_FP64 */
+  DPM_FP64_GEMM = 3 /* FP64 transforms as dense DST-I products on the FP64 matrix cores (any
+                       7 <= N <= 543, N + 1 need not be a power of two; FP64 I/O, no
+                       refinement): the dense counterpart of DPM_FP64 */
 } dpm_precision;
 
 typedef struct {
-  int32_t n;     /* interior nodes per axis, 1 <= n <= 1023 */
+  int32_t n;     /* interior nodes per axis, 7 <= n <= 1023; the FFT-form and split-bf16
+                    transforms need n + 1 a power of two, DPM_FP64_GEMM takes any n <= 543 */
   double h;      /* mesh spacing, > 0 */
   double sigma;  /* shift of the operator sigma I - Lap_h, >= 0 and finite */
   double x0;     /* coordinate of the first interior node (geometry calls only) */

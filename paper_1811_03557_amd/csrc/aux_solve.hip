@@ -98,11 +98,7 @@ int rhs_chunk_of(const dpm_grid& g, int nrhs, const dpm_opts& o) {
 
 dpm_status validate_grid(const dpm_grid* g) {
   if (!g) { set_error("grid is NULL"); return DPM_EINVAL; }
-  if (g->n < 1 || g->n > 1023) { set_error("n = %d out of range [1, 1023]", g->n); return DPM_EINVAL; }
-  if (!fft_size_supported(g->n)) {
-    set_error("n = %d: n + 1 must be a power of two with 7 <= n <= 1023", g->n);
-    return DPM_EINVAL;
-  }
+  if (g->n < 7 || g->n > 1023) { set_error("n = %d out of range [7, 1023]", g->n); return DPM_EINVAL; }
   if (!(g->h > 0.0) || !std::isfinite(g->h)) { set_error("h must be finite and > 0"); return DPM_EINVAL; }
   if (!(g->sigma >= 0.0) || !std::isfinite(g->sigma)) {
     set_error("sigma must be finite and >= 0");
@@ -130,11 +126,17 @@ dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o) {
     return DPM_EINVAL;
   }
   if (o->rhs_chunk < 0) { set_error("rhs_chunk must be >= 0"); return DPM_EINVAL; }
-  if (o->prec == DPM_BF16X3 && g.n > 255) { set_error("DPM_BF16X3 supports n <= 255"); return DPM_EINVAL; }
-  if (o->prec == DPM_FP64_GEMM && (g.n > 255 || o->max_refine != 0)) {
-    set_error("DPM_FP64_GEMM supports n <= 255 without refinement");
+  if (o->prec == DPM_FP64_GEMM) {
+    if (!dense_size_supported(g.n) || o->max_refine != 0) {
+      set_error("DPM_FP64_GEMM supports 7 <= n <= %d without refinement", kDenseMaxN);
+      return DPM_EINVAL;
+    }
+  } else if (!fft_size_supported(g.n)) {
+    set_error("n = %d: the FFT-form and split-bf16 transforms need n + 1 a power of two "
+              "(DPM_FP64_GEMM takes any 7 <= n <= %d)", g.n, kDenseMaxN);
     return DPM_EINVAL;
   }
+  if (o->prec == DPM_BF16X3 && g.n > 255) { set_error("DPM_BF16X3 supports n <= 255"); return DPM_EINVAL; }
   return DPM_OK;
 }
 

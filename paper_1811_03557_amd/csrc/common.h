@@ -50,7 +50,7 @@ struct Plan {
   uint16_t* s_hi = nullptr;
   uint16_t* s_lo = nullptr;
   int mpad = 0;
-  // the same matrix in FP64 for the FP64 matrix-core path (n <= 255 only, else null)
+  // the same matrix in FP64 for the FP64 matrix-core path (n <= kDenseMaxN, else null)
   double* s_d = nullptr;
 };
 
@@ -58,6 +58,10 @@ struct Plan {
 dpm_status get_plan(int n, const Plan** out);
 
 bool fft_size_supported(int n);  // n + 1 a power of two and 7 <= n <= 1023
+// Sizes of the dense (GEMM-form) FP64 sweeps: any 7 <= n <= kDenseMaxN (matrix padded to a
+// multiple of 32, at most 544)
+constexpr int kDenseMaxN = 543;
+bool dense_size_supported(int n);
 
 // ---------------------------------------------------------------- DST pass kernels
 enum InKind { IN_WS = 0, IN_F64 = 1, IN_RESID = 2 };

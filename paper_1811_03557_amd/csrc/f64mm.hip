@@ -1,8 +1,9 @@
 // Per-axis DST-I sweeps as dense FP64 products on the matrix cores (the "GEMM form" of the
 // auxiliary-problem solve, the comparison to the FFT form of dst_fft.hip).
 //
-// A line x (N values, zero-padded to K = MP, a multiple of 32) is transformed as X = S x with S
-// the orthonormal DST-I matrix (symmetric, S S = I).  A block owns a tile of W = 32 lines, kept
+// A line x (N values, any 7 <= N <= 543, zero-padded to K = MP, a multiple of 32) is transformed
+// as X = S x with S the orthonormal DST-I matrix (symmetric, S S = I); unlike the FFT form, N + 1
+// need not be a power of two.  A block owns a tile of W = 32 lines, kept
 // in LDS as [line][k] FP64 with an odd pitch (MP + 1), so that 16 consecutive lines of one k fall
 // in distinct banks.  D[k][w] = sum_j S[k][j] In[w][j] with v_mfma_f64_16x16x4f64: A = S (16 rows
 // k by 4 columns j, read from the plan's matrix, L2 resident), B = In^T (4 rows j by 16 lines,
@@ -21,11 +22,9 @@ constexpr int kWL = 32;   // lines per tile
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <int LOGM>
+template <int MPAD>
 struct CfgD {
-  static constexpr int M = 1 << LOGM;
-  static constexpr int N = M - 1;
-  static constexpr int MP = (N + 31) / 32 * 32;    // padded K: the plan's matrix pitch
+  static constexpr int MP = MPAD;                  // padded K: the plan's matrix pitch
   static constexpr int PB = MP + 1;                // LDS pitch of a line (odd)
   static constexpr int KB = MP / 16;               // 16-row blocks of the output
   static constexpr int WB = kWL / 16;              // 16-line blocks of the output
@@ -35,10 +34,10 @@ struct CfgD {
 
 // acc[t] = (S In^T) on the tiles of this wave: line block wb = wave % WB, row blocks
 // kb = wave / WB + WPB t.
-template <int LOGM>
+template <int MPAD>
 __device__ __forceinline__ void tile_gemm_d(const double* __restrict__ S, const double* in,
                                             f64x4* acc, int wave, int lane) {
-  using C = CfgD<LOGM>;
+  using C = CfgD<MPAD>;
   constexpr int MP = C::MP, PB = C::PB, TPW = C::TPW, WB = C::WB, WPB = C::WPB;
   const int r = lane & 15, q = lane >> 4;
   const int wb = wave % WB, kb0 = wave / WB;
@@ -59,12 +58,12 @@ __device__ __forceinline__ void tile_gemm_d(const double* __restrict__ S, const 
 
 // Writes the tiles of this wave to LDS as [line][k]; scaled by 1/(bxy_w + inv_h2 lam_hat[k])
 // (zero for k >= N or lines past the tile) when SCALE.
-template <int LOGM, bool SCALE>
+template <int MPAD, bool SCALE>
 __device__ __forceinline__ void tile_stage_d(const f64x4* acc, double* in, int wave, int lane,
-                                             int nlines, double bxy, double inv_h2,
+                                             int N, int nlines, double bxy, double inv_h2,
                                              const double* __restrict__ lam_hat) {
-  using C = CfgD<LOGM>;
-  constexpr int N = C::N, PB = C::PB, TPW = C::TPW, WB = C::WB, WPB = C::WPB;
+  using C = CfgD<MPAD>;
+  constexpr int PB = C::PB, TPW = C::TPW, WB = C::WB, WPB = C::WPB;
   const int r = lane & 15, q = lane >> 4;
   const int wb = wave % WB, kb0 = wave / WB;
   const int w = wb * 16 + r;
@@ -82,18 +81,18 @@ __device__ __forceinline__ void tile_stage_d(const f64x4* acc, double* in, int w
   }
 }
 
-template <int LOGM, int AX, bool ZPASS>
+template <int MPAD, int AX, bool ZPASS>
 __global__ __launch_bounds__(kT) void k_f64mm_pass(PassArgs p, const double* __restrict__ S,
-                                                   int tiles) {
-  using C = CfgD<LOGM>;
-  constexpr int N = C::N, MP = C::MP, PB = C::PB, TPW = C::TPW;
+                                                   int N, int tiles) {
+  using C = CfgD<MPAD>;
+  constexpr int MP = C::MP, PB = C::PB, TPW = C::TPW;
   constexpr int W = kWL;
-  constexpr long long VOL = (long long)N * N * N;
-  constexpr int LINES_PER_ROW = (AX == AX_X) ? N * N : N;
-  constexpr int TILES_PER_ROW = (LINES_PER_ROW + W - 1) / W;
-  constexpr long long S_OUTER = (AX == AX_X) ? 0 : (AX == AX_Y ? (long long)N * N : N);
-  constexpr long long S_LINE = (AX == AX_X) ? N : 1;
-  constexpr long long S_ELEM = (AX == AX_X) ? 1 : (AX == AX_Y ? N : (long long)N * N);
+  const long long VOL = (long long)N * N * N;
+  const int LINES_PER_ROW = (AX == AX_X) ? N * N : N;
+  const int TILES_PER_ROW = (LINES_PER_ROW + W - 1) / W;
+  const long long S_OUTER = (AX == AX_X) ? 0 : (AX == AX_Y ? (long long)N * N : N);
+  const long long S_LINE = (AX == AX_X) ? N : 1;
+  const long long S_ELEM = (AX == AX_X) ? 1 : (AX == AX_Y ? N : (long long)N * N);
   __shared__ __align__(16) double in[W * PB];
 
   const int rhs = blockIdx.y;
@@ -140,21 +139,21 @@ __global__ __launch_bounds__(kT) void k_f64mm_pass(PassArgs p, const double* __r
   __syncthreads();
 
   f64x4 acc[TPW];
-  tile_gemm_d<LOGM>(S, in, acc, wave, lane);
+  tile_gemm_d<MPAD>(S, in, acc, wave, lane);
   __syncthreads();  // every wave has read the tile
   if constexpr (ZPASS) {
     const int w = (wave % C::WB) * 16 + (lane & 15);
     const double bxy = w < nlines ? sig + p.inv_h2 * (p.lam_hat[line0 + w] + p.lam_hat[row]) : 1.0;
-    tile_stage_d<LOGM, true>(acc, in, wave, lane, nlines, bxy, p.inv_h2, p.lam_hat);
+    tile_stage_d<MPAD, true>(acc, in, wave, lane, N, nlines, bxy, p.inv_h2, p.lam_hat);
     __syncthreads();
-    tile_gemm_d<LOGM>(S, in, acc, wave, lane);
+    tile_gemm_d<MPAD>(S, in, acc, wave, lane);
     __syncthreads();
   }
-  tile_stage_d<LOGM, false>(acc, in, wave, lane, nlines, 0.0, 0.0, nullptr);
+  tile_stage_d<MPAD, false>(acc, in, wave, lane, N, nlines, 0.0, 0.0, nullptr);
   __syncthreads();
 
   // ---- store the tile with the load's mapping
-  constexpr int TOTO = W * N;
+  const int TOTO = W * N;
 #pragma unroll 4
   for (int e = tid; e < TOTO; e += kT) {
     int w, j;
@@ -164,27 +163,24 @@ __global__ __launch_bounds__(kT) void k_f64mm_pass(PassArgs p, const double* __r
   }
 }
 
-template <int LOGM>
-dpm_status launch_d(AxisKind ax, bool zpass, const PassArgs& a, const Plan* pl, int nrhs,
+template <int MPAD>
+dpm_status launch_d(int n, AxisKind ax, const PassArgs& a, const Plan* pl, int nrhs,
                     hipStream_t s) {
-  using C = CfgD<LOGM>;
-  constexpr int N = C::N;
-  if (pl->mpad != C::MP || pl->s_d == nullptr) {
-    set_error("FP64 sine matrix missing or with pad %d, expected %d", pl->mpad, C::MP);
+  if (pl->mpad != MPAD || pl->s_d == nullptr) {
+    set_error("FP64 sine matrix missing or with pad %d, expected %d", pl->mpad, MPAD);
     return DPM_EINVAL;
   }
-  const long long lines_per_row = (ax == AX_X) ? (long long)N * N : N;
-  const long long rows = (ax == AX_X) ? 1 : N;
+  const long long lines_per_row = (ax == AX_X) ? (long long)n * n : n;
+  const long long rows = (ax == AX_X) ? 1 : n;
   const long long tiles = rows * ((lines_per_row + kWL - 1) / kWL);
   dim3 grid((unsigned)tiles, nrhs), block(kT);
   const int ti = (int)tiles;
   if (ax == AX_X)
-    hipLaunchKernelGGL((k_f64mm_pass<LOGM, AX_X, false>), grid, block, 0, s, a, pl->s_d, ti);
+    hipLaunchKernelGGL((k_f64mm_pass<MPAD, AX_X, false>), grid, block, 0, s, a, pl->s_d, n, ti);
   else if (ax == AX_Y)
-    hipLaunchKernelGGL((k_f64mm_pass<LOGM, AX_Y, false>), grid, block, 0, s, a, pl->s_d, ti);
+    hipLaunchKernelGGL((k_f64mm_pass<MPAD, AX_Y, false>), grid, block, 0, s, a, pl->s_d, n, ti);
   else
-    hipLaunchKernelGGL((k_f64mm_pass<LOGM, AX_Z, true>), grid, block, 0, s, a, pl->s_d, ti);
-  (void)zpass;
+    hipLaunchKernelGGL((k_f64mm_pass<MPAD, AX_Z, true>), grid, block, 0, s, a, pl->s_d, n, ti);
   DPM_TRY_HIP(hipGetLastError());
   return DPM_OK;
 }
@@ -200,14 +196,28 @@ dpm_status launch_f64mm_pass(int n, AxisKind ax, bool zpass, const PassArgs& a, 
     set_error("the FP64 GEMM sweeps serve the plain solve (no refinement)");
     return DPM_EINVAL;
   }
-  switch (n) {
-    case 7: return launch_d<3>(ax, zpass, a, pl, nrhs, s);
-    case 15: return launch_d<4>(ax, zpass, a, pl, nrhs, s);
-    case 31: return launch_d<5>(ax, zpass, a, pl, nrhs, s);
-    case 63: return launch_d<6>(ax, zpass, a, pl, nrhs, s);
-    case 127: return launch_d<7>(ax, zpass, a, pl, nrhs, s);
-    case 255: return launch_d<8>(ax, zpass, a, pl, nrhs, s);
-    default: set_error("DPM_FP64_GEMM supports n = 7, 15, 31, 63, 127, 255"); return DPM_EINVAL;
+  if (!dense_size_supported(n)) {
+    set_error("DPM_FP64_GEMM supports 7 <= n <= %d", kDenseMaxN);
+    return DPM_EINVAL;
+  }
+  switch ((n + 31) / 32) {
+    case 1: return launch_d<32>(n, ax, a, pl, nrhs, s);
+    case 2: return launch_d<64>(n, ax, a, pl, nrhs, s);
+    case 3: return launch_d<96>(n, ax, a, pl, nrhs, s);
+    case 4: return launch_d<128>(n, ax, a, pl, nrhs, s);
+    case 5: return launch_d<160>(n, ax, a, pl, nrhs, s);
+    case 6: return launch_d<192>(n, ax, a, pl, nrhs, s);
+    case 7: return launch_d<224>(n, ax, a, pl, nrhs, s);
+    case 8: return launch_d<256>(n, ax, a, pl, nrhs, s);
+    case 9: return launch_d<288>(n, ax, a, pl, nrhs, s);
+    case 10: return launch_d<320>(n, ax, a, pl, nrhs, s);
+    case 11: return launch_d<352>(n, ax, a, pl, nrhs, s);
+    case 12: return launch_d<384>(n, ax, a, pl, nrhs, s);
+    case 13: return launch_d<416>(n, ax, a, pl, nrhs, s);
+    case 14: return launch_d<448>(n, ax, a, pl, nrhs, s);
+    case 15: return launch_d<480>(n, ax, a, pl, nrhs, s);
+    case 16: return launch_d<512>(n, ax, a, pl, nrhs, s);
+    default: return launch_d<544>(n, ax, a, pl, nrhs, s);
   }
 }
 

@@ -50,6 +50,8 @@ bool fft_size_supported(int n) {
   return (m & (m - 1)) == 0;
 }
 
+bool dense_size_supported(int n) { return n >= 7 && n <= kDenseMaxN; }
+
 static dpm_status build_plan(int n, Plan* p) {
   p->n = n;
   const int M = n + 1;
@@ -82,7 +84,7 @@ static dpm_status build_plan(int n, Plan* p) {
   // dense orthonormal DST-I matrix padded to a multiple of 32, split into bf16 hi + lo
   int mpad = (n + 31) / 32 * 32;
   std::vector<uint16_t> hi((size_t)mpad * mpad, 0), lo((size_t)mpad * mpad, 0);
-  const bool dense64 = mpad <= 256;
+  const bool dense64 = dense_size_supported(n);
   std::vector<double> sd(dense64 ? (size_t)mpad * mpad : 0, 0.0);
   const double nrm = std::sqrt(2.0 / M);
   for (int j = 1; j <= n; ++j)

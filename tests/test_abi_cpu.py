@@ -54,6 +54,14 @@ def test_host_validation_without_device():
     o3 = _lib.Opts(_lib.DPM_FP32, 1, 1e-10, 2, 1, None, 0)
     assert lib.dpm_workspace_size(C.byref(g), 4, C.byref(o3), C.byref(nb)) == _lib.DPM_OK
     assert nb.value >= 255**3 * 4
+    # N + 1 not a power of two: only the dense FP64 form takes it (N = 36, a mesh of the paper)
+    g36 = _lib.Grid(36, 3.0 / 37, 1.0, 0.0)
+    assert lib.dpm_workspace_size(C.byref(g36), 1, C.byref(o), C.byref(nb)) == _lib.DPM_EINVAL
+    assert "DPM_FP64_GEMM" in lib.dpm_last_error().decode()
+    og = _lib.Opts(_lib.DPM_FP64_GEMM, 1, 1e-10, 0, 0, None, 0)
+    assert lib.dpm_workspace_size(C.byref(g36), 1, C.byref(og), C.byref(nb)) == _lib.DPM_OK
+    g600 = _lib.Grid(600, 3.0 / 601, 1.0, 0.0)
+    assert lib.dpm_workspace_size(C.byref(g600), 1, C.byref(og), C.byref(nb)) == _lib.DPM_EINVAL
     # null pointers are rejected before any launch
     assert lib.aux_solve(C.byref(g), None, None, C.byref(o), None, None) == _lib.DPM_EINVAL
     # misaligned volumes and bad per-right-hand-side sigmas are rejected before any launch

@@ -201,7 +201,7 @@ def test_invalid_arguments_raise():
     import torch
     from paper_1811_03557_amd import api, _lib
     dev = need_gpu()
-    b = torch.zeros((5, 5, 5), dtype=torch.float64, device=dev)   # n + 1 not a power of two
+    b = torch.zeros((5, 5, 5), dtype=torch.float64, device=dev)   # n below the smallest size
     with pytest.raises(_lib.DPMError):
         api.aux_solve(b, 1.0, 0.1)
     b = torch.zeros((7, 7, 7), dtype=torch.float64, device=dev)
@@ -249,11 +249,12 @@ def test_per_rhs_sigma_matches_single_solves():
             assert oaux.rel_err_inf(ub[i], oaux.aux_solve(b[i], s, h)) < 1e-10
 
 
-@pytest.mark.parametrize("n", [7, 15, 31, 63, 127, 255])
+@pytest.mark.parametrize("n", [7, 15, 31, 63, 127, 255, 36, 68, 132, 260])
 def test_fp64_gemm_parity(n):
     """FP64 dense-DST sweeps on the FP64 matrix cores (the GEMM form): the FP64 bar, 1e-12,
     against the oracle on a ragged batch of 3 (chunk 2 at 255^3: a full and a partial launch)
-    and on sine modes in closed form."""
+    and on sine modes in closed form.  36, 68, 132 and 260 are meshes of the paper's tables,
+    N + 1 not a power of two (matrix padded to 64, 96, 160 and 288)."""
     dev = need_gpu()
     say(f"fp64 gemm parity n={n}")
     h, _ = inp.grid(n)
@@ -285,6 +286,13 @@ def test_fp64_gemm_rejects_refinement_and_large_n():
     b = torch.zeros((2, 7, 7, 7), dtype=torch.float64, device=dev)
     with pytest.raises(_lib.DPMError):
         api.aux_solve_batched(b, 1.0, 0.1, prec="fp64_gemm", max_refine=1)
-    b = torch.zeros((1, 511, 511, 511), dtype=torch.float64, device=dev)
-    with pytest.raises(_lib.DPMError):
-        api.aux_solve_batched(b, 1.0, 3.0 / 512, prec="fp64_gemm")
+    b = torch.zeros((1, 600, 600, 600), dtype=torch.float64, device=dev)
+    with pytest.raises(_lib.DPMError) as e:  # beyond the dense sizes
+        api.aux_solve_batched(b, 1.0, 3.0 / 601, prec="fp64_gemm")
+    assert "n <= 543" in str(e.value)
+    del b
+    # the FFT form needs N + 1 a power of two, and says where to go otherwise
+    b = torch.zeros((1, 36, 36, 36), dtype=torch.float64, device=dev)
+    with pytest.raises(_lib.DPMError) as e:
+        api.aux_solve_batched(b, 1.0, 3.0 / 37, prec="fp64")
+    assert "DPM_FP64_GEMM" in str(e.value)

@@ -144,23 +144,26 @@ def test_least_squares_against_lapack(n, shape, lmax):
     bep.close()
 
 
-@pytest.mark.parametrize("n,shape", [(15, "sphere"), (31, "ellipsoid")])
-def test_dpm_step_parity(n, shape):
+@pytest.mark.parametrize("n,shape,prec", [(15, "sphere", "fp64"), (31, "ellipsoid", "fp64"),
+                                          (36, "sphere", "fp64_gemm"), (68, "ellipsoid", "fp64_gemm")])
+def test_dpm_step_parity(n, shape, prec):
     """One step from the Test A data: the HIP step (one merged Green solve) against the oracle's
-    separate potential and particular solves."""
+    separate potential and particular solves.  N = 36 and 68 are meshes of the paper's tables
+    (N + 1 not a power of two): boundary matrix and step run on the dense FP64 transforms."""
     import torch
     from paper_1811_03557_amd import api
     dev = need_gpu()
-    say(f"dpm step n={n} {shape}")
+    say(f"dpm step n={n} {shape} {prec}")
     h, _ = inp.grid(n)
     dt = 0.5 * h * h
-    h, x0, mp, ps, Bref, bep, A, geo = _bep_case(n, shape, 2, 1.0 / dt, dev)
+    h, x0, mp, ps, Bref, bep, A, geo = _bep_case(n, shape, 2, 1.0 / dt, dev, prec=prec)
     z, y, x = inp.mesh(n)
     r2 = x**2 + y**2 + z**2
     rho = np.where(ps.n_plus, 10 * np.exp(-4 * r2), 0.0)
     c = np.where(ps.n_plus, 5 * np.exp(-2 * r2), 0.0)
     r1, c1, _ = opks.dpm_step(rho, c, ps, Bref, A, h, dt, 1.0)
-    rg, cg = api.dpm_step(bep, dt, 1.0, torch.from_numpy(rho).to(dev), torch.from_numpy(c).to(dev))
+    rg, cg = api.dpm_step(bep, dt, 1.0, torch.from_numpy(rho).to(dev), torch.from_numpy(c).to(dev),
+                          prec=prec)
     rg, cg = rg.cpu().numpy(), cg.cpu().numpy()
     assert np.max(np.abs(rg - r1)) < 1e-10 * np.max(np.abs(r1))
     assert np.max(np.abs(cg - c1)) < 1e-10 * np.max(np.abs(c1))
