@@ -18,6 +18,8 @@ Time loop (the "pks_time_loop" object): 200 graph-replayed DPM steps on an ellip
 Boundary matrix (the "boundary_matrix" object): the 242-column build at 127^3 per precision.
 Adaptive loop (the "adaptive_time_loop" object): dt from the CFL-type bound with Step 4b
 rebuilds of the boundary matrix, on the same ellipsoid at 127^3.
+Test B (the "test_b" object): the 500-column zonal boundary matrix at 255^3 and the adaptive
+loop from the paper's Test B data with 150 zonal harmonics at 127^3.
 
 Prints one JSON line on stdout (everything else goes to stderr).
 """
@@ -210,6 +212,60 @@ def run_adaptive(args, dev):
     return out
 
 
+def run_test_b(args, dev):
+    """The paper's Test B workload (blow-up at the boundary) in the single-domain approach:
+    zonal 2-term extension (P_nu(cos theta), beta = 0).  (i) Step 2 with the largest column count
+    the paper uses, 500 zonal harmonics on the unit sphere at N = 255, sigma = 2/h^2; (ii) the
+    adaptive loop from rho0 = 2000 exp(-100 (x^2 + y^2 + (z - 0.25)^2)), c0 = 0 at N = 127 with
+    150 harmonics, dt0 = 0.5 h^2, FP64, args.adaptive_steps steps.  Wall times."""
+    import torch
+    from paper_1811_03557_amd import api
+    geo = api.geometry("sphere", axes=(1.0,))
+    out = {"workload": "unit sphere, zonal 2-term extension; build: N = 255, 500 harmonics, "
+                       "sigma = 2/h^2; adaptive: N = 127, 150 harmonics, Test B data, dt0 = 0.5 h^2"}
+    n = 255
+    h = 3.0 / (n + 1)
+    x0 = -1.5 + h
+    m = api.classify(n, h, x0, geo, device=dev)
+    idx, _ = api.gamma_points(m, h, x0)
+    B, _ = api.basis_zonal(n, h, x0, geo, idx, 499, 0)
+    api.build_boundary_matrix(m, B, n, h, 2.0 / h**2, x0).close()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bep = api.build_boundary_matrix(m, B, n, h, 2.0 / h**2, x0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    out["build_500"] = {"n": n, "columns": bep.n_basis, "gamma_in": bep.n_gamma_in,
+                        "build_s": round(dt, 4), "columns_per_s": round(bep.n_basis / dt, 1),
+                        "rdiag_min_over_max": round(bep.rdiag[0] / bep.rdiag[1], 4)}
+    log(f"[bench] test B build: {bep.n_basis} zonal columns at {n}^3 in {dt * 1e3:.1f} ms")
+    bep.close()
+    del m, idx, B
+    n = args.pks_n
+    h = 3.0 / (n + 1)
+    x0 = -1.5 + h
+    m = api.classify(n, h, x0, geo, device=dev)
+    idx, _ = api.gamma_points(m, h, x0)
+    B, _ = api.basis_zonal(n, h, x0, geo, idx, 149, 0)
+    dt0 = 0.5 * h * h
+    bep = api.build_boundary_matrix(m, B, n, h, 1.0 / dt0, x0)
+    rho = api.gauss_state(bep, geo, 2000.0, 100.0, center=(0.0, 0.0, 0.25))
+    c = torch.zeros_like(rho)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = api.run(bep, 1.0, rho, c, t_final=1.0, max_steps=args.adaptive_steps)
+    torch.cuda.synchronize()
+    s = time.perf_counter() - t
+    out["adaptive"] = {"n": n, "columns": bep.n_basis, "steps": res["steps"],
+                       "rebuilds": res["rebuilds"], "stop": res["stop"], "run_s": round(s, 4),
+                       "steps_per_s": round(res["steps"] / s, 1), "dt_first": res["dt_hist"][0],
+                       "dt_last": res["dt"], "rho_max": res["rho_max"]}
+    log(f"[bench] test B adaptive: {res['steps']} steps, {res['rebuilds']} rebuilds, "
+        f"{s * 1e3:.1f} ms")
+    bep.close()
+    return out
+
+
 def run_boundary_matrix(args, dev):
     """Step 2 of the method at 127^3: the 242-column reduced-BEP matrix of the unit sphere
     (real Y_lm, l <= 10, beta = 1), sigma = 2/h^2, built and QR-factored by one
@@ -389,6 +445,7 @@ def main():
     pks = run_pks(args, dev) if args.pks_steps > 0 else None
     bmat = run_boundary_matrix(args, dev) if not args.no_bmat else None
     adaptive = run_adaptive(args, dev) if args.adaptive_steps > 0 else None
+    test_b = run_test_b(args, dev) if args.adaptive_steps > 0 and not args.no_bmat else None
 
     ok = {k: v for k, v in results.items() if v["rel_err_sample"] <= args.rtol}
     best_name = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else None
@@ -432,6 +489,7 @@ def main():
         "pks_time_loop": pks,
         "boundary_matrix": bmat,
         "adaptive_time_loop": adaptive,
+        "test_b": test_b,
         "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
         "alg_hbm_frac": (round(best["solves_per_s"] * 16 * vol / (HBM_PEAK_GBS * 1e9), 4)
                          if best else None),

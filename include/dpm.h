@@ -152,6 +152,19 @@ dpm_status dpm_basis(const dpm_grid* grid, const dpm_geometry* geom, int32_t n_g
 typedef struct dpm_bep dpm_bep; /* library-owned: mask, gamma lists, basis, BEP matrix, QR */
 
 /*
+ * dpm_basis_zonal -- zonal densities of the extension operator, the paper's basis for initial
+ * data symmetric about the z axis ("Basis functions, extension operators and BEPs"; remark (i)
+ * of the spectral approach): P_nu(cos theta), the unnormalised Legendre polynomials of degree
+ * nu = 0..mmax of the polar angle of each gamma node's projection onto Gamma.  basis: device,
+ * n_basis x n_gamma FP64 (row nu contiguous), n_basis = (beta + 1)(mmax + 1); rows mmax + 1 ..
+ * carry (d^2/2) P_nu when beta = 1 (the 3-term extension), none when beta = 0 (the 2-term
+ * extension with zero Neumann data).  d_out (nullable, device n_gamma FP64) receives d.
+ */
+dpm_status dpm_basis_zonal(const dpm_grid* grid, const dpm_geometry* geom, int32_t n_gamma,
+                           const int32_t* idx, int32_t mmax, int32_t beta, double* basis,
+                           double* d_out, void* stream);
+
+/*
  * dpm_build_boundary_matrix -- paper Algorithm "Main Steps", Step 2: the reduced-BEP matrix
  * (eq BEP_recast) A[:, nu] = Tr_gamma_in (I - P_gamma) basis_nu, one AP solve per column with
  * right-hand side 1_{M-} (sigma - Lap_h)[basis_nu extended by zero] (Def. "DP" in sigma-form),

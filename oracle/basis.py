@@ -14,12 +14,17 @@ tests; the fitted solution does not depend on the scaling of the columns.
 Evaluated here through scipy.special.sph_harm_y (complex, with the Condon-Shortley phase),
 converted to the real form.
 
+Zonal basis (the paper's choice for initial data symmetric about the z axis, "Basis functions,
+extension operators and BEPs" and remark (i) of the spectral approach): phi_nu = P_nu(cos theta),
+the Legendre polynomial of degree nu (unnormalised, as in the paper), nu = 0..M, evaluated here
+through scipy.special.eval_legendre.
+
 TEST INFRASTRUCTURE: imported only by tests/, smoke() and bench.py's cpu_baseline.
 """
 from __future__ import annotations
 
 import numpy as np
-from scipy.special import sph_harm_y
+from scipy.special import eval_legendre, sph_harm_y
 
 
 def real_sph_harm(l: int, m: int, theta, phi):
@@ -45,3 +50,13 @@ def basis_matrix(d, theta, phi, lmax: int, beta: int = 1) -> np.ndarray:
     if beta:
         return np.concatenate([Y, 0.5 * np.asarray(d)[None, :] ** 2 * Y], axis=0)
     return Y
+
+
+def zonal_basis_matrix(d, theta, mmax: int, beta: int = 0) -> np.ndarray:
+    """Zonal densities on gamma, shape ((beta + 1)(mmax + 1), n_gamma): rows P_nu(cos theta),
+    nu = 0..mmax, then (if beta) (d^2/2) P_nu(cos theta)."""
+    x = np.cos(np.asarray(theta, dtype=np.float64))
+    P = np.array([eval_legendre(nu, x) for nu in range(mmax + 1)], dtype=np.float64)
+    if beta:
+        return np.concatenate([P, 0.5 * np.asarray(d)[None, :] ** 2 * P], axis=0)
+    return P

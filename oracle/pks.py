@@ -125,10 +125,10 @@ def adaptive_run(rho, c, ps: PointSets, basis: np.ndarray, h: float, sigma0: flo
     """Steps 3-8 from dt_0 = 1/sigma0 (the step of Step 2's matrix).
 
     Returns (rho, c, summary) with summary keys steps, rebuilds, stop, t, dt, rho_max,
-    grad_max, dt_hist, rebuilt."""
+    grad_max, dt_hist, rebuilt and cfl_hist (the CFL-type bound of each step's state)."""
     dt_prev = 1.0 / sigma0
     A = bep_matrix(basis, ps, sigma0, h)                               # Step 2
-    t, dts, rebuilt, stop = 0.0, [], [], "max_steps"
+    t, dts, rebuilt, cfls, stop = 0.0, [], [], [], "max_steps"
     gmax = rmax = 0.0
     while True:
         if t >= t_final:
@@ -145,15 +145,17 @@ def adaptive_run(rho, c, ps: PointSets, basis: np.ndarray, h: float, sigma0: flo
         if rmax > rho_cap:
             stop = "rho_cap"
             break
-        dt = min(cfl_dt(c, ps.m_plus, h, chi), dt_prev)
+        cfl = cfl_dt(c, ps.m_plus, h, chi)
+        dt = min(cfl, dt_prev)
         rb = dt < dt_prev
         if rb:                                                         # Step 4b
             A = bep_matrix(basis, ps, 1.0 / dt, h)
         rho, c, _ = dpm_step(rho, c, ps, basis, A, h, dt, chi)         # Steps 4a-7
         dts.append(dt)
         rebuilt.append(rb)
+        cfls.append(cfl)
         t += dt
         dt_prev = dt
     return rho, c, {"steps": len(dts), "rebuilds": int(sum(rebuilt)), "stop": stop, "t": t,
                     "dt": dt_prev, "rho_max": rmax, "grad_max": gmax, "dt_hist": dts,
-                    "rebuilt": rebuilt}
+                    "rebuilt": rebuilt, "cfl_hist": cfls}

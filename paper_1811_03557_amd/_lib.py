@@ -63,6 +63,8 @@ SIGNATURES = {
     "dpm_classify": (C.c_int, [C.POINTER(Grid), C.POINTER(Geometry), _P, _P]),
     "dpm_gamma_points": (C.c_int, [C.POINTER(Grid), _P, C.POINTER(_I), C.POINTER(_I), _P, _P, _P]),
     "dpm_basis": (C.c_int, [C.POINTER(Grid), C.POINTER(Geometry), _I, _P, _I, _I, _P, _P, _P]),
+    "dpm_basis_zonal": (C.c_int, [C.POINTER(Grid), C.POINTER(Geometry), _I, _P, _I, _I, _P, _P,
+                                  _P]),
     "dpm_build_boundary_matrix": (C.c_int, [C.POINTER(Grid), _P, _I, _P, C.POINTER(Opts), _P,
                                             C.POINTER(_P), _P]),
     "dpm_bep_info": (C.c_int, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I), C.POINTER(_D),

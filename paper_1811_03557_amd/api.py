@@ -178,6 +178,21 @@ def basis(n: int, h: float, x0: float, geo: L.Geometry, idx: torch.Tensor, lmax:
     return B, d
 
 
+def basis_zonal(n: int, h: float, x0: float, geo: L.Geometry, idx: torch.Tensor, mmax: int,
+                beta: int = 0, stream=None):
+    """(basis ((beta + 1)(mmax + 1), n_gamma) FP64, d (n_gamma) FP64): Legendre P_nu(cos theta)."""
+    ng = int(idx.numel())
+    nb = (beta + 1) * (mmax + 1)
+    B = torch.empty((nb, ng), dtype=torch.float64, device=idx.device)
+    d = torch.empty(ng, dtype=torch.float64, device=idx.device)
+    g = grid(n, h, 0.0, x0)
+    L.check(L.load().dpm_basis_zonal(C.byref(g), C.byref(geo), ng,
+                                     C.c_void_p(_dev(idx, "idx", torch.int32)), int(mmax),
+                                     int(beta), C.c_void_p(B.data_ptr()),
+                                     C.c_void_p(d.data_ptr()), C.c_void_p(_stream(stream))))
+    return B, d
+
+
 class BEP:
     """Owner of a dpm_bep handle (boundary matrix, QR, point sets); released on close()."""
 

@@ -12,6 +12,9 @@ dpm_status gamma_points_impl(const dpm_grid& g, const uint8_t* m_plus, int32_t* 
 dpm_status basis_impl(const dpm_grid& g, const dpm_geometry& geo, int32_t n_gamma,
                       const int32_t* idx, int32_t lmax, int32_t beta, double* basis, double* d_out,
                       hipStream_t s);
+dpm_status basis_zonal_impl(const dpm_grid& g, const dpm_geometry& geo, int32_t n_gamma,
+                            const int32_t* idx, int32_t mmax, int32_t beta, double* basis,
+                            double* d_out, hipStream_t s);
 dpm_status validate_geometry(const dpm_geometry* geo);
 dpm_status step_workspace_impl(const dpm_bep* b, const dpm_opts& o, size_t* bytes);
 dpm_status step_impl(const dpm_bep* b, double dt, double chi, const double* rho_in,
@@ -147,6 +150,23 @@ dpm_status dpm_basis(const dpm_grid* grid, const dpm_geometry* geom, int32_t n_g
   if (!aligned16(basis)) { set_error("basis must be 16-byte aligned"); return DPM_EINVAL; }
   return basis_impl(*grid, *geom, n_gamma, idx, lmax, beta, basis, d_out,
                     static_cast<hipStream_t>(stream));
+}
+
+dpm_status dpm_basis_zonal(const dpm_grid* grid, const dpm_geometry* geom, int32_t n_gamma,
+                           const int32_t* idx, int32_t mmax, int32_t beta, double* basis,
+                           double* d_out, void* stream) {
+  clear_error();
+  DPM_TRY(validate_grid(grid));
+  DPM_TRY(validate_geometry(geom));
+  if (n_gamma <= 0 || !idx || !basis) { set_error("empty gamma or NULL pointer"); return DPM_EINVAL; }
+  if (mmax < 0 || mmax > 1023) { set_error("mmax out of range [0, 1023]"); return DPM_EINVAL; }
+  if (beta != 0 && beta != 1) { set_error("beta must be 0 or 1"); return DPM_EINVAL; }
+  if (!aligned_to(basis, 8) || (d_out && !aligned_to(d_out, 8))) {
+    set_error("basis and d_out must be 8-byte aligned");
+    return DPM_EINVAL;
+  }
+  return basis_zonal_impl(*grid, *geom, n_gamma, idx, mmax, beta, basis, d_out,
+                          static_cast<hipStream_t>(stream));
 }
 
 dpm_status dpm_build_boundary_matrix(const dpm_grid* grid, const uint8_t* m_plus,

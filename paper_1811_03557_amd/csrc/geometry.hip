@@ -174,6 +174,33 @@ __global__ void k_basis(int n, double h, double x0, GeoDev g, int ng,
   }
 }
 
+// Zonal densities: P_nu(cos theta) (Legendre, unnormalised), nu = 0..mmax, by the three-term
+// recurrence (nu + 1) P_{nu+1} = (2 nu + 1) x P_nu - nu P_{nu-1}, stable for |x| <= 1; rows
+// mmax + 1 .. carry (d^2/2) P_nu when beta = 1.
+__global__ void k_basis_zonal(int n, double h, double x0, GeoDev g, int ng,
+                              const int32_t* __restrict__ idx, int mmax, int beta,
+                              double* __restrict__ basis, double* __restrict__ d_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ng) return;
+  const long long li = idx[i];
+  const int ix = (int)(li % n);
+  const int iy = (int)((li / n) % n);
+  const int iz = (int)(li / ((long long)n * n));
+  double d, th, ph;
+  project(g, x0 + h * ix - g.cx, x0 + h * iy - g.cy, x0 + h * iz - g.cz, &d, &th, &ph);
+  if (d_out) d_out[i] = d;
+  const double x = cos(th), half_d2 = 0.5 * d * d;
+  const long long off2 = (long long)(mmax + 1) * ng;
+  double pm1 = 0.0, p = 1.0;  // P_{nu-1}, P_nu
+  for (int nu = 0; nu <= mmax; ++nu) {
+    basis[(long long)nu * ng + i] = p;
+    if (beta) basis[off2 + (long long)nu * ng + i] = half_d2 * p;
+    const double pn = ((2.0 * nu + 1.0) * x * p - nu * pm1) / (nu + 1.0);
+    pm1 = p;
+    p = pn;
+  }
+}
+
 }  // namespace
 
 dpm_status classify_impl(const dpm_grid& g, const dpm_geometry& geo, uint8_t* m_plus, hipStream_t s) {
@@ -261,6 +288,15 @@ dpm_status basis_impl(const dpm_grid& g, const dpm_geometry& geo, int32_t n_gamm
                       hipStream_t s) {
   hipLaunchKernelGGL(k_basis, dim3((n_gamma + 127) / 128), dim3(128), 0, s, g.n, g.h, g.x0,
                      to_dev(geo), n_gamma, idx, lmax, beta, basis, d_out);
+  DPM_TRY_HIP(hipGetLastError());
+  return DPM_OK;
+}
+
+dpm_status basis_zonal_impl(const dpm_grid& g, const dpm_geometry& geo, int32_t n_gamma,
+                            const int32_t* idx, int32_t mmax, int32_t beta, double* basis,
+                            double* d_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_basis_zonal, dim3((n_gamma + 127) / 128), dim3(128), 0, s, g.n, g.h, g.x0,
+                     to_dev(geo), n_gamma, idx, mmax, beta, basis, d_out);
   DPM_TRY_HIP(hipGetLastError());
   return DPM_OK;
 }

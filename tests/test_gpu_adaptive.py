@@ -140,3 +140,36 @@ def test_adaptive_run_stops_on_nonfinite_state():
     assert np.isnan(res["rho_max"]) and bep.sigma == sigma0
     assert np.array_equal(cg.cpu().numpy(), c)
     bep.close()
+
+
+def test_adaptive_run_test_b():
+    """Test B data (rho0 = 2000 exp(-100 (x^2 + y^2 + (z - 0.25)^2)), c0 = 0: blow-up at the
+    boundary) with the zonal 2-term extension (M = 10, beta = 0) from dt0 = 0.5 h^2 at 31^3: the
+    oracle's decisions (a rebuild at step 2, when c has grown) and states, step by step."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    n, steps = 31, 6
+    h, x0 = inp.grid(n)
+    z, y, x = inp.mesh(n)
+    ps = og.PointSets(og.inside_sphere(z, y, x))
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    d, th, ph = og.project_sphere(gz, gy, gx)
+    B = ob.zonal_basis_matrix(d, th, 10, beta=0)
+    rho = np.where(ps.n_plus, 2000.0 * np.exp(-100.0 * (x**2 + y**2 + (z - 0.25) ** 2)), 0.0)
+    c = np.zeros_like(rho)
+    sigma0 = 1.0 / (0.5 * h * h)
+    say(f"adaptive run n={n} Test B zonal M=10")
+    ro, co, ref = opks.adaptive_run(rho, c, ps, B, h, sigma0, 1.0, 1.0, max_steps=steps)
+    assert ref["rebuilt"][1] and ref["rebuilds"] >= 1
+    prev = 1.0 / sigma0
+    for cfl, dt in zip(ref["cfl_hist"], ref["dt_hist"]):
+        assert abs(cfl / prev - 1.0) > 1e-6  # every decision far from a rounding tie
+        prev = dt
+    m = torch.from_numpy(ps.m_plus.astype(np.uint8)).to(dev)
+    bep = api.build_boundary_matrix(m, torch.from_numpy(B).to(dev), n, h, sigma0, x0)
+    rg, cg = torch.from_numpy(rho).to(dev), torch.from_numpy(c).to(dev)
+    res = api.run(bep, 1.0, rg, cg, t_final=1.0, max_steps=steps)
+    say(f"  {res['steps']} steps, rebuilt {res['rebuilt']}, max rho {res['rho_max']:.4e}")
+    _compare(res, ref, rg, cg, ro, co)
+    bep.close()

@@ -188,3 +188,47 @@ def test_gauss_state():
     ref[ps.idx] = 1000 * np.exp(-100 * np.sum(q * q, 1))
     assert np.max(np.abs(st.ravel() - ref)) < 1e-10
     bep.close()
+
+
+@pytest.mark.parametrize("n,mmax,beta", [(63, 40, 1), (127, 499, 0)])
+def test_zonal_basis_parity(n, mmax, beta):
+    """Legendre densities P_nu(cos theta) on gamma (the paper's zonal basis) against the oracle's
+    library evaluation, up to degree 499 (Test B's largest count).  The device recurrence and the
+    oracle's projection angles agree to rounding; P_499 amplifies an angle difference by up to
+    nu^2, hence the absolute bound 1e-10 at that degree (|P_nu| <= 1)."""
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    say(f"zonal basis n={n} mmax={mmax} beta={beta}")
+    h, x0, mp, proj, geo = _case(n, "sphere")
+    m_gpu = api.classify(n, h, x0, api.geometry(**geo), device=dev)
+    idx, _ = api.gamma_points(m_gpu, h, x0)
+    B, d = api.basis_zonal(n, h, x0, api.geometry(**geo), idx, mmax, beta)
+    ps = og.PointSets(mp)
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    dd, th, ph = proj(gz, gy, gx)
+    Bref = ob.zonal_basis_matrix(dd, th, mmax, beta)
+    assert B.shape == Bref.shape
+    assert np.max(np.abs(B.cpu().numpy() - Bref)) < (1e-12 if mmax < 100 else 1e-10)
+
+
+def test_boundary_matrix_zonal_two_term():
+    """Reduced-BEP matrix of the zonal 2-term extension (beta = 0, M = 10: Test B's form) at 31^3
+    against the oracle, column by column."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    n = 31
+    h, x0, mp, proj, geo = _case(n, "sphere")
+    sigma = 2.0 / h**2
+    ps = og.PointSets(mp)
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    dd, th, ph = proj(gz, gy, gx)
+    Bref = ob.zonal_basis_matrix(dd, th, 10, 0)
+    m_gpu = torch.from_numpy(mp.astype(np.uint8)).to(dev)
+    bep, A = api.build_boundary_matrix(m_gpu, torch.from_numpy(Bref).to(dev), n, h, sigma, x0,
+                                       return_A=True)
+    Aref = odpm.bep_matrix(Bref, ps, sigma, h)
+    A = A.cpu().numpy()
+    for nu in range(Bref.shape[0]):
+        assert np.max(np.abs(A[:, nu] - Aref[:, nu])) < 1e-11 * np.max(np.abs(Aref[:, nu])), nu
+    bep.close()

@@ -162,3 +162,34 @@ def test_basis_matrix_layout():
     assert B.shape == (18, 3)
     assert np.allclose(B[9:], 0.5 * d**2 * B[:9])
     assert np.allclose(B[4], ob.real_sph_harm(2, -2, th, ph))
+
+
+def test_zonal_basis_closed_forms_and_endpoints():
+    th = np.array([0.0, 0.4, 1.3, 2.2, np.pi])
+    x = np.cos(th)
+    d = np.array([0.1, -0.05, 0.2, 0.0, -0.3])
+    B = ob.zonal_basis_matrix(d, th, 3, beta=1)
+    ref = [np.ones_like(x), x, 0.5 * (3 * x**2 - 1), 0.5 * (5 * x**3 - 3 * x)]
+    assert B.shape == (8, 5)
+    for nu in range(4):
+        assert np.allclose(B[nu], ref[nu], atol=1e-15)
+        assert np.allclose(B[4 + nu], 0.5 * d**2 * ref[nu], atol=1e-15)
+    # P_nu(1) = 1 and P_nu(-1) = (-1)^nu up to the degrees of the paper's Test B
+    P = ob.zonal_basis_matrix(np.zeros(2), np.array([0.0, np.pi]), 499, beta=0)
+    assert np.allclose(P[:, 0], 1.0, atol=1e-12)
+    assert np.allclose(P[:, 1], (-1.0) ** np.arange(500), atol=1e-12)
+
+
+def test_zonal_basis_orthogonal_and_matches_real_harmonics():
+    """int_{-1}^{1} P_l P_m dx = 2/(2l+1) delta_lm (Gauss-Legendre, exact for these degrees), and
+    P_l(cos theta) = sqrt(4 pi/(2l+1)) Y_l0 from the independent spherical-harmonic routine."""
+    L = 300
+    xg, wg = np.polynomial.legendre.leggauss(L + 2)
+    P = ob.zonal_basis_matrix(np.zeros_like(xg), np.arccos(xg), L, beta=0)
+    G = (P * wg) @ P.T
+    assert np.max(np.abs(G - np.diag(2.0 / (2 * np.arange(L + 1) + 1)))) < 1e-12
+    th = np.linspace(0.05, 3.1, 9)
+    Z = ob.zonal_basis_matrix(np.zeros_like(th), th, 10, beta=0)
+    for l in range(11):
+        y = ob.real_sph_harm(l, 0, th, np.zeros_like(th))
+        assert np.allclose(Z[l], np.sqrt(4 * np.pi / (2 * l + 1)) * y, atol=1e-13), l
