@@ -20,6 +20,9 @@ Adaptive loop (the "adaptive_time_loop" object): dt from the CFL-type bound with
 rebuilds of the boundary matrix, on the same ellipsoid at 127^3.
 Test B (the "test_b" object): the 500-column zonal boundary matrix at 255^3 and the adaptive
 loop from the paper's Test B data with 150 zonal harmonics at 127^3.
+Domain decomposition (the "domain_decomposition" object): Case 1 on the Test A setup, the
+ball on a 127^3 mesh and the shell on a 63^3 mesh, against the single domain at 255^3 with the
+same fine spacing: build and per-step times and their ratio.
 
 Prints one JSON line on stdout (everything else goes to stderr).
 """
@@ -27,6 +30,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -266,6 +270,88 @@ def run_test_b(args, dev):
     return out
 
 
+def run_dd(args, dev):
+    """Domain decomposition, Case 1, on the paper's Test A setup (blow-up at the centre): the
+    ball r < 0.5 on a fine mesh (N1 = 127 on [-0.75, 0.75]^3, h1 = 3/256) and the shell
+    0.5 < r < 1 on a coarse one (N2 = 63 on [-1.5, 1.5]^3, h2 = 4 h1), one zonal harmonic per
+    term (3-term extensions on Gamma and on Z: 5 columns), dt = h1 / (6 max|grad c0|) (the
+    CFL-type bound of the positivity theorem at the initial data, max|grad c0| from the formula,
+    which bounds the face differences; far below 0.5 h1^2 for these data).  Against the single
+    domain at the same fine spacing everywhere (N = 255, 2 columns): Step 2 wall time and the
+    per-step time (eager steps, FP64), whose ratio is the per-step R_S = T_SD / T_DD."""
+    import torch
+    from paper_1811_03557_amd import api
+    n1, n2 = 127, 63
+    h1, h2 = 1.5 / (n1 + 1), 3.0 / (n2 + 1)
+    # c0 = 500 exp(-50 r^2): |grad c0| = 5e4 r exp(-50 r^2), largest at r = 0.1
+    dt = min(0.5 * h1 * h1, h1 / (6.0 * 5e4 * 0.1 * math.exp(-0.5)))
+    prm = api.dd_params(n1, h1, -0.75 + h1, n2, h2, -1.5 + h2, 1.0 / dt, 0.5, 1.0, 0.75, 0, 1, 0)
+    api.dd_build(prm, device=dev).close()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    dd = api.dd_build(prm, device=dev)
+    torch.cuda.synchronize()
+    build_dd = time.perf_counter() - t
+    state = [dd.gauss_state(l, a, r) for l in (0, 1) for a, r in ((1000.0, 100.0), (500.0, 50.0))]
+    ws = torch.empty(dd.workspace_size(api.opts("fp64")), dtype=torch.uint8, device=dev)
+    steps = args.dd_steps
+    for _ in range(2):
+        api.dd_step(dd, dt, 1.0, state, out=state, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        api.dd_step(dd, dt, 1.0, state, out=state, workspace=ws)
+    torch.cuda.synchronize()
+    t_dd = (time.perf_counter() - t) / steps
+    finite = all(bool(torch.isfinite(v).all()) for v in state)
+    out = {"workload": "Test A data, ball r < 0.5 at N1 = 127 (h1 = 3/256) + shell 0.5 < r < 1 "
+                       "at N2 = 63 (h2 = 3/64), one zonal harmonic per term, dt at the CFL "
+                       "bound of the initial data; "
+                       "single domain at N = 255 (h = 3/256) for comparison",
+           "dd_127_63": {"columns": dd.n_cols, "rows": sum(dd.n_gamma_in),
+                         "build_s": round(build_dd, 4), "ms_per_step": round(t_dd * 1e3, 3),
+                         "steps_per_s": round(1.0 / t_dd, 1), "finite": finite}}
+    log(f"[bench] DD 127/63: build {build_dd * 1e3:.1f} ms, {t_dd * 1e3:.3f} ms/step")
+    dd.close()
+    del state, ws
+    # the single domain at the fine spacing everywhere
+    n = 255
+    h = 3.0 / (n + 1)
+    x0 = -1.5 + h
+    geo = api.geometry("sphere", axes=(1.0,))
+    m = api.classify(n, h, x0, geo, device=dev)
+    idx, _ = api.gamma_points(m, h, x0)
+    B, _ = api.basis_zonal(n, h, x0, geo, idx, 0, 1)
+    api.build_boundary_matrix(m, B, n, h, 1.0 / dt, x0).close()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bep = api.build_boundary_matrix(m, B, n, h, 1.0 / dt, x0)
+    torch.cuda.synchronize()
+    build_sd = time.perf_counter() - t
+    rho = api.gauss_state(bep, geo, 1000.0, 100.0)
+    c = api.gauss_state(bep, geo, 500.0, 50.0)
+    o = api.opts("fp64")
+    ws = torch.empty(api.step_workspace_size(bep, o), dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        api.dpm_step(bep, dt, 1.0, rho, c, rho, c, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        api.dpm_step(bep, dt, 1.0, rho, c, rho, c, workspace=ws)
+    torch.cuda.synchronize()
+    t_sd = (time.perf_counter() - t) / steps
+    out["sd_255"] = {"columns": bep.n_basis, "rows": bep.n_gamma_in, "build_s": round(build_sd, 4),
+                     "ms_per_step": round(t_sd * 1e3, 3), "steps_per_s": round(1.0 / t_sd, 1)}
+    out["sd_255"]["finite"] = bool(torch.isfinite(rho).all() and torch.isfinite(c).all())
+    out["dt"] = dt
+    out["R_S_per_step"] = round(t_sd / t_dd, 2)
+    out["R_S_build"] = round(build_sd / build_dd, 2)
+    log(f"[bench] SD 255: build {build_sd * 1e3:.1f} ms, {t_sd * 1e3:.3f} ms/step; "
+        f"R_S per step {t_sd / t_dd:.2f}")
+    bep.close()
+    return out
+
+
 def run_boundary_matrix(args, dev):
     """Step 2 of the method at 127^3: the 242-column reduced-BEP matrix of the unit sphere
     (real Y_lm, l <= 10, beta = 1), sigma = 2/h^2, built and QR-factored by one
@@ -320,6 +406,8 @@ def main():
     ap.add_argument("--no-bmat", action="store_true", help="skip the boundary-matrix build")
     ap.add_argument("--adaptive-steps", type=int, default=20,
                     help="steps of each adaptive-loop run (0 = skip)")
+    ap.add_argument("--dd-steps", type=int, default=50,
+                    help="domain-decomposition steps timed (0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run 3 plain device copies of this many bytes (calibrates the "
                          "HBM traffic counters against a kernel of known traffic)")
@@ -446,6 +534,7 @@ def main():
     bmat = run_boundary_matrix(args, dev) if not args.no_bmat else None
     adaptive = run_adaptive(args, dev) if args.adaptive_steps > 0 else None
     test_b = run_test_b(args, dev) if args.adaptive_steps > 0 and not args.no_bmat else None
+    dd = run_dd(args, dev) if args.dd_steps > 0 else None
 
     ok = {k: v for k, v in results.items() if v["rel_err_sample"] <= args.rtol}
     best_name = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else None
@@ -490,6 +579,7 @@ def main():
         "boundary_matrix": bmat,
         "adaptive_time_loop": adaptive,
         "test_b": test_b,
+        "domain_decomposition": dd,
         "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
         "alg_hbm_frac": (round(best["solves_per_s"] * 16 * vol / (HBM_PEAK_GBS * 1e9), 4)
                          if best else None),

@@ -296,6 +296,79 @@ dpm_status dpm_gauss_state(const dpm_bep* bep, const dpm_geometry* geom, double 
 void dpm_bep_destroy(dpm_bep* bep);
 
 /*
+ * Domain decomposition, Case 1 (paper Sec. 3: "Case 1" and "BEPs for Case 1", eqs
+ * interface_condition, DD1_BEP1, DD1_BEP2, reduced_DD1_BEP1, reduced_DD1_BEP2).  Omega, the ball
+ * |x - center| < r_gamma, is split by the interface sphere Z, |x - center| = r_z, into Omega_1
+ * (the inner ball) and Omega_2 (the shell); each is embedded in its own cube with its own mesh
+ * (grid1, grid2: n, h, x0 per subdomain; nodes exactly on Z belong to neither M+).  zeta_1 is
+ * Omega_1's discrete grid boundary; Omega_2's is the union of gamma near Gamma and zeta_2 near Z,
+ * split at |x - center| = r_split.  Densities (zonal, P_nu(cos theta) of the polar angle about
+ * center): near Gamma P_nu and, when beta = 1, (d^2/2) P_nu with d = |x - center| - r_gamma
+ * (nu <= m_gamma); near Z P_nu, d P_nu and (d^2/2) P_nu with d = |x - center| - r_z (nu <= m_z),
+ * the same coefficients on both sides of Z, which imposes the continuity of u and of its first
+ * two normal derivatives.  Columns: [Gamma part, (beta + 1)(m_gamma + 1) ; Z part,
+ * 3 (m_z + 1)].  The two reduced BEPs are solved together as one least-squares problem,
+ * rows [zeta_1,in ; gamma_in of Omega_2], with the FP64 Householder QR of the single domain.
+ */
+typedef struct dpm_dd dpm_dd; /* library-owned: both subdomains' point sets, densities, QR */
+typedef struct {
+  dpm_grid grid1;     /* mesh of Omega_1's cube; sigma = 1/dt, the same in grid2 */
+  dpm_grid grid2;     /* mesh of Omega_2's cube */
+  double center[3];   /* (x, y, z) */
+  double r_z;         /* radius of the interface Z, 0 < r_z < r_split < r_gamma */
+  double r_gamma;     /* radius of Gamma */
+  double r_split;     /* gamma nodes of Omega_2 with |x - center| > r_split take the Gamma part */
+  int32_t m_gamma;    /* highest degree on Gamma, >= 0 */
+  int32_t beta;       /* 1: 3-term extension on Gamma, 0: 2-term (zero Neumann data both) */
+  int32_t m_z;        /* highest degree on Z, >= 0 */
+} dpm_dd_params;
+
+/*
+ * dpm_dd_build -- Step 2 of the paper's algorithm for both subdomains: point sets, densities,
+ * one AP solve per density on each mesh, the stacked matrix [[0, A_1], [A_2]] (A_1 carries the
+ * Z columns only) and its QR and least-squares operator.  opts selects the precision of the
+ * solves (both grids must suit it).  A_out: nullable device (|zeta_1,in| + |gamma_2,in|) x
+ * n_cols FP64, column-major, the matrix before factorisation.  Allocates the handle's device
+ * memory and synchronises the stream.  DPM_EGEOM when a subdomain's N+ leaves its cube,
+ * DPM_ERANK when the stacked matrix is rank deficient.  Release with dpm_dd_destroy.
+ */
+dpm_status dpm_dd_build(const dpm_dd_params* params, const dpm_opts* opts, void* stream,
+                        dpm_dd** out, double* A_out);
+
+/* Counts of a built handle (host values; arrays of two entries, subdomain 1 first). */
+dpm_status dpm_dd_info(const dpm_dd* dd, int32_t n_gamma[2], int32_t n_gamma_in[2],
+                       int32_t* n_cols, double* min_abs_rdiag, double* max_abs_rdiag);
+
+/* Copies of subdomain l's (0 or 1) M+ and N+ masks (device, its N^3 uint8; each nullable). */
+dpm_status dpm_dd_masks(const dpm_dd* dd, int32_t l, uint8_t* m_plus, uint8_t* n_plus,
+                        void* stream);
+
+/* Scratch bytes needed by dpm_dd_step with these options. */
+dpm_status dpm_dd_step_workspace_size(const dpm_dd* dd, const dpm_opts* opts, size_t* bytes);
+
+/*
+ * dpm_dd_step -- one IMEX time step on both subdomains (paper Algorithm "Main Steps", Steps
+ * 4a-7, with the coupled BEP of Case 1 in Step 5): forcing and particular solutions on each mesh,
+ * coefficients from the stacked traces by one least squares, each subdomain's densities and its
+ * discrete generalized Green's formula.  The handle must have been built with sigma = 1/dt.
+ * in = {rho_1, c_1, rho_2, c_2}: device FP64 volumes of the subdomains' meshes (values on N+
+ * used); out: the same four, zero off N+ (they may alias the inputs).  opts->workspace: at least
+ * dpm_dd_step_workspace_size bytes.  Asynchronous; allocates nothing.  Omega_2's share runs on a
+ * stream owned by the handle, forked from `stream` and joined back to it by events, so the two
+ * meshes' solves overlap; work enqueued on `stream` afterwards sees all four outputs.  Calls on
+ * one handle must not overlap (they share that stream's events).
+ */
+dpm_status dpm_dd_step(const dpm_dd* dd, double dt, double chi, const double* const in[4],
+                       double* const out[4], const dpm_opts* opts, void* stream);
+
+/* amp exp(-rate |x - c0|^2) at the nodes of subdomain l's N+, zero elsewhere: the initial data
+ * of the paper's Tests A and B on one mesh.  out: device FP64 volume of that mesh. */
+dpm_status dpm_dd_gauss_state(const dpm_dd* dd, int32_t l, double amp, double rate,
+                              const double c0[3], double* out, void* stream);
+
+void dpm_dd_destroy(dpm_dd* dd);
+
+/*
  * Measurement support (not part of the method): while enabled, the sweep kernels launched for a
  * sampled chunk of right-hand sides are bracketed by hipEvents on the stream they run on.  A
  * chunk [rhs0, rhs0 + nb) of a solve call is sampled when it holds an index that is a multiple of

@@ -49,6 +49,12 @@ class Geometry(C.Structure):
     _fields_ = [("kind", C.c_int32), ("center", C.c_double * 3), ("axes", C.c_double * 3)]
 
 
+class DDParams(C.Structure):
+    _fields_ = [("grid1", Grid), ("grid2", Grid), ("center", C.c_double * 3), ("r_z", C.c_double),
+                ("r_gamma", C.c_double), ("r_split", C.c_double), ("m_gamma", C.c_int32),
+                ("beta", C.c_int32), ("m_z", C.c_int32)]
+
+
 # exported symbol -> (restype, argtypes)
 _P = C.c_void_p
 _I = C.c_int32
@@ -82,6 +88,14 @@ SIGNATURES = {
                           C.POINTER(RunInfo), _P, _P]),
     "dpm_gauss_state": (C.c_int, [_P, C.POINTER(Geometry), _D, _D, C.POINTER(_D), _P, _P]),
     "dpm_bep_destroy": (None, [_P]),
+    "dpm_dd_build": (C.c_int, [C.POINTER(DDParams), C.POINTER(Opts), _P, C.POINTER(_P), _P]),
+    "dpm_dd_info": (C.c_int, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I), C.POINTER(_D),
+                              C.POINTER(_D)]),
+    "dpm_dd_masks": (C.c_int, [_P, _I, _P, _P, _P]),
+    "dpm_dd_step_workspace_size": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
+    "dpm_dd_step": (C.c_int, [_P, _D, _D, C.POINTER(_P), C.POINTER(_P), C.POINTER(Opts), _P]),
+    "dpm_dd_gauss_state": (C.c_int, [_P, _I, _D, _D, C.POINTER(_D), _P, _P]),
+    "dpm_dd_destroy": (None, [_P]),
     "dpm_last_error": (C.c_char_p, []),
     "dpm_timing_begin": (C.c_int, [_I, _I]),
     "dpm_rhs_chunk": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(Opts), C.POINTER(_I)]),

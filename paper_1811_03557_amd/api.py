@@ -259,6 +259,111 @@ def build_boundary_matrix(m_plus: torch.Tensor, basis_mat: torch.Tensor, n: int,
     return bep
 
 
+class DD:
+    """Owner of a dpm_dd handle: the two subdomains of the domain decomposition (Case 1), their
+    point sets and densities, and the QR of the coupled reduced BEPs; released on close()."""
+
+    def __init__(self, ptr: int, params: L.DDParams, device):
+        self.ptr = ptr
+        self.params = params
+        self.device = device
+        self.sigma = params.grid1.sigma
+        self.n = (params.grid1.n, params.grid2.n)
+        ng, ngi = (C.c_int32 * 2)(), (C.c_int32 * 2)()
+        nc, rmin, rmax = C.c_int32(0), C.c_double(0), C.c_double(0)
+        L.check(L.load().dpm_dd_info(C.c_void_p(ptr), ng, ngi, C.byref(nc), C.byref(rmin),
+                                     C.byref(rmax)))
+        self.n_gamma, self.n_gamma_in = tuple(ng), tuple(ngi)
+        self.n_cols = nc.value
+        self.rdiag = (rmin.value, rmax.value)
+
+    def masks(self, l: int, stream=None):
+        """(M+, N+) of subdomain l as uint8 volumes."""
+        n = self.n[l]
+        mp = torch.empty((n, n, n), dtype=torch.uint8, device=self.device)
+        np_ = torch.empty_like(mp)
+        L.check(L.load().dpm_dd_masks(C.c_void_p(self.ptr), l, C.c_void_p(mp.data_ptr()),
+                                      C.c_void_p(np_.data_ptr()), C.c_void_p(_stream(stream))))
+        return mp, np_
+
+    def gauss_state(self, l: int, amp: float, rate: float, center=(0.0, 0.0, 0.0), stream=None):
+        n = self.n[l]
+        out = torch.empty((n, n, n), dtype=torch.float64, device=self.device)
+        L.check(L.load().dpm_dd_gauss_state(C.c_void_p(self.ptr), l, float(amp), float(rate),
+                                            (C.c_double * 3)(*center), C.c_void_p(out.data_ptr()),
+                                            C.c_void_p(_stream(stream))))
+        return out
+
+    def workspace_size(self, o: L.Opts) -> int:
+        nb = C.c_size_t(0)
+        L.check(L.load().dpm_dd_step_workspace_size(C.c_void_p(self.ptr), C.byref(o), C.byref(nb)))
+        return int(nb.value)
+
+    def close(self):
+        if self.ptr:
+            L.load().dpm_dd_destroy(C.c_void_p(self.ptr))
+            self.ptr = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dd_params(n1: int, h1: float, x01: float, n2: int, h2: float, x02: float, sigma: float,
+              r_z: float, r_gamma: float, r_split: float, m_gamma: int, beta: int, m_z: int,
+              center=(0.0, 0.0, 0.0)) -> L.DDParams:
+    return L.DDParams(grid(n1, h1, sigma, x01), grid(n2, h2, sigma, x02), (C.c_double * 3)(*center),
+                      float(r_z), float(r_gamma), float(r_split), int(m_gamma), int(beta), int(m_z))
+
+
+def dd_build(params: L.DDParams, prec: str = "fp64", device="cuda", return_A: bool = False,
+             stream=None):
+    """Step 2 of the domain decomposition (Case 1): both subdomains' columns, the stacked matrix
+    and its QR.  Returns a DD handle (and the stacked matrix, rows x n_cols, when return_A: the
+    row count is known only after a first build, so that case builds twice)."""
+    lib = L.load()
+    o = opts(prec, True)
+    out = C.c_void_p(0)
+    L.check(lib.dpm_dd_build(C.byref(params), C.byref(o), C.c_void_p(_stream(stream)),
+                             C.byref(out), None))
+    dd = DD(out.value, params, torch.device(device))
+    if not return_A:
+        return dd
+    rows = sum(dd.n_gamma_in)
+    dd.close()
+    A = torch.empty((dd.n_cols, rows), dtype=torch.float64, device=device)
+    out = C.c_void_p(0)
+    L.check(lib.dpm_dd_build(C.byref(params), C.byref(o), C.c_void_p(_stream(stream)),
+                             C.byref(out), C.c_void_p(A.data_ptr())))
+    return DD(out.value, params, torch.device(device)), A.t()
+
+
+def dd_step(dd: DD, dt: float, chi: float, state, out=None, prec: str = "fp64",
+            workspace: torch.Tensor | None = None, stream=None):
+    """One step on both subdomains; state = (rho_1, c_1, rho_2, c_2); returns the new four."""
+    for v, n in zip(state, (dd.n[0], dd.n[0], dd.n[1], dd.n[1])):
+        if v.numel() != n ** 3:
+            raise ValueError(f"state volumes must hold {dd.n[0]}^3, {dd.n[0]}^3, {dd.n[1]}^3, "
+                             f"{dd.n[1]}^3 values")
+    if out is not None and any(a.numel() != b.numel() for a, b in zip(out, state)):
+        raise ValueError("out volumes must match the state volumes")
+    o = opts(prec, True)
+    nbytes = dd.workspace_size(o)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=state[0].device)
+    o.workspace = C.c_void_p(workspace.data_ptr())
+    o.workspace_bytes = workspace.numel()
+    out = [torch.empty_like(v) for v in state] if out is None else out
+    names = ("rho_1", "c_1", "rho_2", "c_2")
+    pin = (C.c_void_p * 4)(*[_dev(v, k, torch.float64) for v, k in zip(state, names)])
+    pout = (C.c_void_p * 4)(*[_dev(v, k + "_out", torch.float64) for v, k in zip(out, names)])
+    L.check(L.load().dpm_dd_step(C.c_void_p(dd.ptr), float(dt), float(chi), pin, pout,
+                                 C.byref(o), C.c_void_p(_stream(stream))))
+    return tuple(out)
+
+
 def bep_solve(bep: BEP, g: torch.Tensor, stream=None) -> torch.Tensor:
     """Least-squares coefficients for g of shape (nvec, |gamma_in|)."""
     gg = g.unsqueeze(0) if g.dim() == 1 else g

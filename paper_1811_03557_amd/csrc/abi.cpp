@@ -27,6 +27,18 @@ dpm_status stepper_first_nonfinite_impl(const dpm_stepper* p, hipStream_t s, int
 void stepper_destroy_impl(dpm_stepper* p);
 dpm_status gauss_state_impl(const dpm_bep* b, const dpm_geometry& geo, double amp, double rate,
                             const double* c3, double* out, hipStream_t s);
+dpm_status dd_build_impl(const dpm_dd_params& prm, const dpm_opts& o, hipStream_t s,
+                         dpm_dd** out, double* A_out);
+dpm_status dd_step_workspace_impl(const dpm_dd* d, const dpm_opts& o, size_t* bytes);
+dpm_status dd_step_impl(const dpm_dd* d, double dt, double chi, const double* const in[4],
+                        double* const out[4], const dpm_opts& o, hipStream_t s);
+dpm_status dd_masks_impl(const dpm_dd* d, int l, uint8_t* m_plus, uint8_t* n_plus, hipStream_t s);
+dpm_status dd_gauss_impl(const dpm_dd* d, int l, double amp, double rate, const double c0[3],
+                         double* out, hipStream_t s);
+void dd_destroy(dpm_dd* d);
+double dd_sigma(const dpm_dd* d);
+dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], int32_t* n_cols,
+                        double* rmin, double* rmax);
 }  // namespace dpm
 
 using namespace dpm;
@@ -312,5 +324,86 @@ dpm_status dpm_gauss_state(const dpm_bep* bep, const dpm_geometry* geom, double 
 }
 
 void dpm_bep_destroy(dpm_bep* bep) { destroy_bep(bep); }
+
+dpm_status dpm_dd_build(const dpm_dd_params* params, const dpm_opts* opts, void* stream,
+                        dpm_dd** out, double* A_out) {
+  clear_error();
+  if (!params || !out) { set_error("NULL argument"); return DPM_EINVAL; }
+  *out = nullptr;
+  const dpm_dd_params& p = *params;
+  for (const dpm_grid* g : {&p.grid1, &p.grid2}) {
+    DPM_TRY(validate_grid(g));
+    DPM_TRY(validate_opts(*g, opts));
+  }
+  if (!opts->io_fp64) { set_error("the boundary matrix needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
+  if (p.grid1.sigma != p.grid2.sigma) { set_error("both meshes need the same sigma (= 1/dt)"); return DPM_EINVAL; }
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(p.center[i])) { set_error("center must be finite"); return DPM_EINVAL; }
+  if (!(p.r_z > 0.0) || !(p.r_split > p.r_z) || !(p.r_gamma > p.r_split) || !std::isfinite(p.r_gamma)) {
+    set_error("the radii must satisfy 0 < r_z < r_split < r_gamma (finite)");
+    return DPM_EINVAL;
+  }
+  if (p.m_gamma < 0 || p.m_z < 0 || (p.beta != 0 && p.beta != 1)) {
+    set_error("m_gamma, m_z must be >= 0 and beta 0 or 1");
+    return DPM_EINVAL;
+  }
+  if ((p.beta + 1) * (p.m_gamma + 1) + 3 * (p.m_z + 1) > 1024) {
+    set_error("more than 1024 columns");
+    return DPM_EINVAL;
+  }
+  return dd_build_impl(p, *opts, static_cast<hipStream_t>(stream), out, A_out);
+}
+
+dpm_status dpm_dd_info(const dpm_dd* dd, int32_t n_gamma[2], int32_t n_gamma_in[2],
+                       int32_t* n_cols, double* min_abs_rdiag, double* max_abs_rdiag) {
+  clear_error();
+  if (!dd) { set_error("dd is NULL"); return DPM_EINVAL; }
+  return dd_info_impl(dd, n_gamma, n_gamma_in, n_cols, min_abs_rdiag, max_abs_rdiag);
+}
+
+dpm_status dpm_dd_masks(const dpm_dd* dd, int32_t l, uint8_t* m_plus, uint8_t* n_plus,
+                        void* stream) {
+  clear_error();
+  if (!dd) { set_error("dd is NULL"); return DPM_EINVAL; }
+  if (l != 0 && l != 1) { set_error("subdomain index must be 0 or 1"); return DPM_EINVAL; }
+  return dd_masks_impl(dd, l, m_plus, n_plus, static_cast<hipStream_t>(stream));
+}
+
+dpm_status dpm_dd_step_workspace_size(const dpm_dd* dd, const dpm_opts* opts, size_t* bytes) {
+  clear_error();
+  if (!dd || !opts || !bytes) { set_error("NULL argument"); return DPM_EINVAL; }
+  return dd_step_workspace_impl(dd, *opts, bytes);
+}
+
+dpm_status dpm_dd_step(const dpm_dd* dd, double dt, double chi, const double* const in[4],
+                       double* const out[4], const dpm_opts* opts, void* stream) {
+  clear_error();
+  if (!dd || !in || !out) { set_error("NULL argument"); return DPM_EINVAL; }
+  for (int i = 0; i < 4; ++i)
+    if (!in[i] || !out[i] || !aligned_to(in[i], 8) || !aligned_to(out[i], 8)) {
+      set_error("volume %d is NULL or not 8-byte aligned", i);
+      return DPM_EINVAL;
+    }
+  if (out[0] == out[1] || out[2] == out[3]) { set_error("rho and c outputs must be different buffers"); return DPM_EINVAL; }
+  if (!opts) { set_error("opts is NULL"); return DPM_EINVAL; }
+  if (!opts->io_fp64) { set_error("dpm_dd_step needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
+  if (!aligned16(opts->workspace)) { set_error("the workspace must be 16-byte aligned"); return DPM_EINVAL; }
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(chi)) { set_error("dt must be finite and > 0, chi finite"); return DPM_EINVAL; }
+  if (std::fabs(dd_sigma(dd) * dt - 1.0) > 1e-12) {
+    set_error("the handle was built with sigma = %g but 1/dt = %g", dd_sigma(dd), 1.0 / dt);
+    return DPM_EINVAL;
+  }
+  return dd_step_impl(dd, dt, chi, in, out, *opts, static_cast<hipStream_t>(stream));
+}
+
+dpm_status dpm_dd_gauss_state(const dpm_dd* dd, int32_t l, double amp, double rate,
+                              const double c0[3], double* out, void* stream) {
+  clear_error();
+  if (!dd || !c0 || !out) { set_error("NULL argument"); return DPM_EINVAL; }
+  if (l != 0 && l != 1) { set_error("subdomain index must be 0 or 1"); return DPM_EINVAL; }
+  return dd_gauss_impl(dd, l, amp, rate, c0, out, static_cast<hipStream_t>(stream));
+}
+
+void dpm_dd_destroy(dpm_dd* dd) { dd_destroy(dd); }
 
 }  // extern "C"

@@ -42,9 +42,26 @@ void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* C, hipStrea
 void qr_solve_traces(const dpm_bep* bep, int nvec, const double* vol, long long vsz, double* C,
                      hipStream_t s);
 
+// factor = false stops after the columns (b->A unfactored, b->P unset): the handle then serves
+// as one subdomain of a coupled problem that factors the stacked matrix itself.
+// Step kernels on one handle's grid and point sets (the coupled subdomain step reuses them):
+// b2 = sigma 1_{M+} (f_rho, f_c); u_gamma of both species from coefficient rows C, C + ldc;
+// (o0, o1) = the two volumes of U restricted to N+.
+void launch_pks_rhs(const dpm_bep* b, const double* rho, const double* c, double dt, double chi,
+                    double* b2, hipStream_t s);
+void launch_density(const dpm_bep* b, const double* C, int ldc, double* ug, hipStream_t s);
+void launch_restrict(const dpm_bep* b, const double* U, double* o0, double* o1, hipStream_t s);
+
 dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
                           const double* basis, const dpm_opts& o, hipStream_t s, dpm_bep** out,
-                          double* A_out);
+                          double* A_out, bool factor = true);
+dpm_status bep_columns(dpm_bep* b, hipStream_t s);
+// Householder QR of A (m x n column-major, in place), rank test, P = R^-1 Q1^T (n x m)
+dpm_status lsq_factor(double* A, int m, int n, double* tau, double* P, hipStream_t s,
+                      double* rdiag_min, double* rdiag_max);
+// C[r] = P g[r] for nvec vectors g (m entries each), C rows of n entries
+void lsq_apply(const double* P, int m, int n, int nvec, const double* g, double* C,
+               hipStream_t s);
 dpm_status rebuild_bep_impl(dpm_bep* b, double sigma, hipStream_t s);
 dpm_status cfl_scan_impl(const dpm_bep* b, const double* rho, const double* c, double* out2,
                          hipStream_t s);

@@ -475,6 +475,12 @@ void qr_solve(const dpm_bep* bep, int nvec, const double* g, double* C, hipStrea
                      bep->n_in, bep->n_basis, g, 0LL, nullptr, C);
 }
 
+void lsq_apply(const double* P, int m, int n, int nvec, const double* g, double* C,
+               hipStream_t s) {
+  hipLaunchKernelGGL(k_lsq_apply<false>, dim3(n, nvec), dim3(kLT), 0, s, P, m, n, g, 0LL,
+                     nullptr, C);
+}
+
 void qr_solve_traces(const dpm_bep* bep, int nvec, const double* vol, long long vsz, double* C,
                      hipStream_t s) {
   hipLaunchKernelGGL(k_lsq_apply<true>, dim3(bep->n_basis, nvec), dim3(kLT), 0, s, bep->P,
@@ -491,9 +497,8 @@ int gram_chunks(int m, int n) {
 }
 
 // Columns of the reduced-BEP matrix at the handle's sigma (M- operator on the densities, batched
-// AP solves, traces on gamma_in), the Householder QR, the rank test and the least-squares
-// operator P, into the handle's buffers.
-dpm_status factor_bep(dpm_bep* b, hipStream_t s, double* A_out) {
+// AP solves, traces on gamma_in) into b->A.  Synchronises the stream.
+dpm_status bep_columns(dpm_bep* b, hipStream_t s) {
   const dpm_grid& g = b->grid;
   const dpm_opts& o = b->opts;
   const int n_basis = b->n_basis, nin = b->n_in, ng = b->n_gamma;
@@ -532,22 +537,26 @@ dpm_status factor_bep(dpm_bep* b, hipStream_t s, double* A_out) {
   }
   (void)hipStreamSynchronize(s);
   (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
-  if (st != DPM_OK) return st;
-  if (A_out &&
-      hipMemcpyAsync(A_out, b->A, sizeof(double) * (size_t)n_basis * nin, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-    set_error("dpm_build_boundary_matrix: copy of A failed");
-    return DPM_EHIP;
-  }
-  // Householder QR in place: one launch per step (the step-j reflector is applied by the
-  // trailing-column blocks and stored by block 0 of the next launch)
-  for (int j = 0; j <= n_basis; ++j) launch_house_step(b->A, nin, n_basis, j, b->tau, s);
+  return st;
+}
+
+// Householder QR of A (m x n, column-major, overwritten by the reflectors below R), the rank
+// test on the diagonal of R and the least-squares operator P = R^-1 Q1^T (n x m, row nu
+// contiguous).  Synchronises the stream.
+dpm_status lsq_factor(double* A, int m, int n_basis, double* tau, double* P, hipStream_t s,
+                      double* rdiag_min, double* rdiag_max) {
+  const int nin = m;
+  auto al = [&](void** p, size_t bytes) { return hipMalloc(p, bytes > 0 ? bytes : 1) == hipSuccess; };
+  // one launch per step (the step-j reflector is applied by the trailing-column blocks and
+  // stored by block 0 of the next launch)
+  for (int j = 0; j <= n_basis; ++j) launch_house_step(A, nin, n_basis, j, tau, s);
   double* rd = nullptr;
   std::vector<double> rdh(n_basis);
   if (!al((void**)&rd, sizeof(double) * n_basis)) {
     set_error("dpm_build_boundary_matrix: device allocation failed");
     return DPM_ENOMEM;
   }
-  hipLaunchKernelGGL(k_rdiag, dim3(grid1(n_basis)), dim3(kB), 0, s, b->A, nin, n_basis, rd);
+  hipLaunchKernelGGL(k_rdiag, dim3(grid1(n_basis)), dim3(kB), 0, s, A, nin, n_basis, rd);
   hipError_t e = hipMemcpyAsync(rdh.data(), rd, sizeof(double) * n_basis, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(rd);
@@ -557,8 +566,8 @@ dpm_status factor_bep(dpm_bep* b, hipStream_t s, double* A_out) {
   }
   double mn = INFINITY, mx = 0.0;
   for (double v : rdh) { mn = std::fmin(mn, v); mx = std::fmax(mx, v); }
-  b->rdiag_min = mn;
-  b->rdiag_max = mx;
+  *rdiag_min = mn;
+  *rdiag_max = mx;
   if (!(mn > 1e-12 * mx)) {
     set_error("boundary matrix is rank deficient: min |R_ii| = %g, max |R_ii| = %g", mn, mx);
     return DPM_ERANK;
@@ -581,16 +590,16 @@ dpm_status factor_bep(dpm_bep* b, hipStream_t s, double* A_out) {
     }
     const int nt = (n_basis + kGT - 1) / kGT, nchunk = gram_chunks(nin, n_basis);
     const int rc = (nin + nchunk - 1) / nchunk;
-    hipLaunchKernelGGL(k_gram_part, dim3(nt * (nt + 1) / 2, nchunk), dim3(256), 0, s, b->A, nin,
+    hipLaunchKernelGGL(k_gram_part, dim3(nt * (nt + 1) / 2, nchunk), dim3(256), 0, s, A, nin,
                        n_basis, rc, Gp);
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((nn + 3) / 4)), dim3(256), 0, s, Gp,
                        nchunk, n_basis, G);
-    hipLaunchKernelGGL(k_tinv, dim3(n_basis), dim3(256), 0, s, G, b->tau, n_basis, T);
-    hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, b->A, nin, n_basis, Rinv);
-    hipLaunchKernelGGL(k_v1tt, dim3(grid1((long long)nn)), dim3(kB), 0, s, b->A, nin, n_basis, T, W);
+    hipLaunchKernelGGL(k_tinv, dim3(n_basis), dim3(256), 0, s, G, tau, n_basis, T);
+    hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, A, nin, n_basis, Rinv);
+    hipLaunchKernelGGL(k_v1tt, dim3(grid1((long long)nn)), dim3(kB), 0, s, A, nin, n_basis, T, W);
     hipLaunchKernelGGL(k_kmat, dim3(grid1((long long)nn)), dim3(kB), 0, s, Rinv, W, n_basis, K);
     hipLaunchKernelGGL(k_form_p, dim3(grid1(nin), (n_basis + PT - 1) / PT), dim3(kB),
-                       sizeof(double) * PT * n_basis, s, Rinv, K, b->A, nin, n_basis, b->P);
+                       sizeof(double) * PT * n_basis, s, Rinv, K, A, nin, n_basis, P);
     hipError_t e2 = hipGetLastError();
     if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
     free_all();
@@ -602,9 +611,20 @@ dpm_status factor_bep(dpm_bep* b, hipStream_t s, double* A_out) {
   return DPM_OK;
 }
 
+// Columns, QR, rank test and least-squares operator of the handle's matrix.
+dpm_status factor_bep(dpm_bep* b, hipStream_t s, double* A_out) {
+  DPM_TRY(bep_columns(b, s));
+  if (A_out && hipMemcpyAsync(A_out, b->A, sizeof(double) * (size_t)b->n_basis * b->n_in,
+                              hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    set_error("dpm_build_boundary_matrix: copy of A failed");
+    return DPM_EHIP;
+  }
+  return lsq_factor(b->A, b->n_in, b->n_basis, b->tau, b->P, s, &b->rdiag_min, &b->rdiag_max);
+}
+
 dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
                           const double* basis, const dpm_opts& o, hipStream_t s, dpm_bep** out,
-                          double* A_out) {
+                          double* A_out, bool factor) {
   int32_t ng = 0, nin = 0;
   DPM_TRY(gamma_points_impl(g, m_plus, &ng, &nin, nullptr, nullptr, s));
   if (n_basis > nin) {
@@ -679,7 +699,7 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
     }
   }
   {
-    const dpm_status st = factor_bep(b, s, A_out);
+    const dpm_status st = factor ? factor_bep(b, s, A_out) : bep_columns(b, s);
     if (st != DPM_OK) return fail(st);
   }
   *out = b;

@@ -1,0 +1,409 @@
+// Domain decomposition of the DPM, Case 1 (paper Sec. 3: "Case 1" and "BEPs for Case 1", eqs
+// interface_condition, DD1_BEP1, DD1_BEP2, reduced_DD1_BEP1, reduced_DD1_BEP2).
+//
+// Omega_1 = {|x - c| < r_z} (the ball inside the interface sphere Z) and Omega_2 = {r_z < |x - c|
+// < r_gamma} (the shell between Z and Gamma), each on its own cube and mesh.  zeta_1 (the discrete
+// grid interface of Omega_1) is Omega_1's gamma; Omega_2's gamma is the union of the discrete grid
+// boundary near Gamma and zeta_2 near Z, split at the radius r_split.  The densities are zonal
+// spectral extensions: near Gamma P_nu and beta (d_G^2/2) P_nu (d_G = |x - c| - r_gamma, zero
+// Neumann data); near Z P_nu, d_Z P_nu and (d_Z^2/2) P_nu (d_Z = |x - c| - r_z along the radial
+// normal from both sides), whose coefficients are shared by the two subdomains: one coefficient
+// set carries the continuity of u and of its first two normal derivatives across Z.  The two
+// reduced BEPs are stacked into one least-squares problem, columns [Gamma part ; Z part]:
+//
+//        [ 0    A_1 ] [C]   [Tr_zeta_1,in G_1 f_1   ]
+//        [ A_2^G A_2^Z] [A] = [Tr_gamma_2,in G_2 f_2 ]
+//
+// (A_l: the reduced-BEP matrix of subdomain l on its own densities), factored once by the FP64
+// Householder QR of the single-domain path.  A step solves the particular solutions on both
+// meshes, the coupled least squares, and each subdomain's Green's formula.
+#include <cmath>
+#include <vector>
+
+#include "bep.h"
+
+struct dpm_dd {
+  dpm_dd_params prm{};
+  dpm_bep* sub[2] = {nullptr, nullptr};  // per subdomain: masks, gamma lists, densities, A_l
+  int n_gamma_cols = 0, n_z_cols = 0, n_cols = 0;
+  int rows = 0;           // |zeta_1,in| + |gamma_2,in|
+  double* A = nullptr;    // rows x n_cols, column-major; Householder vectors below R
+  double* tau = nullptr;  // n_cols
+  double* P = nullptr;    // n_cols x rows least-squares operator (row nu contiguous)
+  double rdiag_min = 0.0, rdiag_max = 0.0;
+  // Omega_2's share of a step runs on a second stream of the handle, forked from and joined to
+  // the caller's stream by events, so that the two meshes' solves overlap
+  hipStream_t side = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace dpm {
+
+dpm_status gamma_points_impl(const dpm_grid& g, const uint8_t* m_plus, int32_t* n_gamma,
+                             int32_t* n_gamma_in, int32_t* idx, uint8_t* is_in, hipStream_t s);
+dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes);
+
+namespace {
+
+constexpr int kB = 256;
+
+unsigned blocks_for(long long n) {
+  long long b = (n + kB - 1) / kB;
+  return (unsigned)(b > 65536 ? 65536 : (b < 1 ? 1 : b));
+}
+
+// M+ of Omega_1 (shell == 0: |x - c|^2 < r_in2) or of Omega_2 (shell == 1: r_in2 < |x - c|^2 <
+// r_out2); nodes exactly on Z belong to neither.
+__global__ void k_dd_classify(int n, double h, double x0, double cx, double cy, double cz,
+                              double r_in2, double r_out2, int shell, uint8_t* __restrict__ m) {
+  const long long vol = (long long)n * n * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < vol;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i % n);
+    const int iy = (int)((i / n) % n);
+    const int iz = (int)(i / ((long long)n * n));
+    const double px = x0 + h * ix - cx, py = x0 + h * iy - cy, pz = x0 + h * iz - cz;
+    const double r2 = px * px + py * py + pz * pz;
+    m[i] = (shell ? (r2 < r_out2 && r2 > r_in2) : (r2 < r_in2)) ? 1 : 0;
+  }
+}
+
+// Densities of one subdomain's gamma list (rows contiguous, n_gamma entries each).  Omega_2
+// (shell): rows [0, G) the Gamma part, G = (beta + 1)(m_gamma + 1), nonzero at nodes with
+// |x - c| > r_split; then the Z part, 3 (m_z + 1) rows, nonzero at the other nodes.  Omega_1: the
+// Z part only, at every node.  P_nu(cos theta) by the three-term recurrence, theta the polar
+// angle of the node about c.
+__global__ void k_dd_basis(int n, double h, double x0, double cx, double cy, double cz, int ng,
+                           const int32_t* __restrict__ idx, int shell, double r_gamma,
+                           int m_gamma, int beta, double r_z, int m_z, double r_split,
+                           double* __restrict__ basis) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ng) return;
+  const long long li = idx[i];
+  const int ix = (int)(li % n);
+  const int iy = (int)((li / n) % n);
+  const int iz = (int)(li / ((long long)n * n));
+  const double px = x0 + h * ix - cx, py = x0 + h * iy - cy, pz = x0 + h * iz - cz;
+  const double r = sqrt(px * px + py * py + pz * pz);
+  const double x = cos(atan2(sqrt(px * px + py * py), pz));
+  const bool on_g = shell && r > r_split;
+  const long long ngl = ng;
+  int row = 0;
+  if (shell) {
+    const int nz = m_gamma + 1;
+    const double dg = r - r_gamma, hd2 = 0.5 * dg * dg;
+    double pm1 = 0.0, p = 1.0;
+    for (int nu = 0; nu <= m_gamma; ++nu) {
+      basis[(row + nu) * ngl + i] = on_g ? p : 0.0;
+      if (beta) basis[(row + nz + nu) * ngl + i] = on_g ? hd2 * p : 0.0;
+      const double pn = ((2.0 * nu + 1.0) * x * p - nu * pm1) / (nu + 1.0);
+      pm1 = p;
+      p = pn;
+    }
+    row += (beta + 1) * nz;
+  }
+  const int nz = m_z + 1;
+  const double dz = r - r_z, hd2 = 0.5 * dz * dz;
+  double pm1 = 0.0, p = 1.0;
+  for (int nu = 0; nu <= m_z; ++nu) {
+    basis[(row + nu) * ngl + i] = on_g ? 0.0 : p;
+    basis[(row + nz + nu) * ngl + i] = on_g ? 0.0 : dz * p;
+    basis[(row + 2 * nz + nu) * ngl + i] = on_g ? 0.0 : hd2 * p;
+    const double pn = ((2.0 * nu + 1.0) * x * p - nu * pm1) / (nu + 1.0);
+    pm1 = p;
+    p = pn;
+  }
+}
+
+// The stacked matrix: rows [0, m0) = [0 | A_1] (Omega_1 carries only the Z columns), rows
+// [m0, m0 + m1) = A_2; all column-major.
+__global__ void k_dd_stack(const double* __restrict__ A0, int m0, const double* __restrict__ A1,
+                           int m1, int ng_cols, int n_cols, double* __restrict__ A) {
+  const long long M = (long long)m0 + m1, tot = M * n_cols;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / M);
+    const int i = (int)(e - (long long)j * M);
+    double v;
+    if (i < m0)
+      v = j >= ng_cols ? A0[(long long)(j - ng_cols) * m0 + i] : 0.0;
+    else
+      v = A1[(long long)j * m1 + (i - m0)];
+    A[e] = v;
+  }
+}
+
+// g[r] = [Tr_zeta_1,in X_1[r] ; Tr_gamma_2,in X_2[r]] for the two species r = blockIdx.y
+__global__ void k_dd_gather(const double* __restrict__ X0, long long v0,
+                            const int32_t* __restrict__ idx0, int m0,
+                            const double* __restrict__ X1, long long v1,
+                            const int32_t* __restrict__ idx1, int m1, double* __restrict__ g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  const int M = m0 + m1;
+  if (i >= M) return;
+  g[(long long)r * M + i] = i < m0 ? X0[r * v0 + idx0[i]] : X1[r * v1 + idx1[i - m0]];
+}
+
+// amp exp(-rate |x - c0|^2) at the nodes of N+, zero elsewhere
+__global__ void k_dd_gauss(const uint8_t* __restrict__ np, int n, double h, double x0, double amp,
+                           double rate, double cx, double cy, double cz, double* __restrict__ out) {
+  const long long vol = (long long)n * n * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < vol;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i % n);
+    const int iy = (int)((i / n) % n);
+    const int iz = (int)(i / ((long long)n * n));
+    const double px = x0 + h * ix - cx, py = x0 + h * iy - cy, pz = x0 + h * iz - cz;
+    out[i] = np[i] ? amp * exp(-rate * (px * px + py * py + pz * pz)) : 0.0;
+  }
+}
+
+struct DDLayout {
+  size_t b2[2], X[2], ug[2], g, C, solve_ws[2], total;
+};
+
+DDLayout dd_layout(const dpm_dd* d, size_t solve_ws) {
+  DDLayout L;
+  size_t o = 0;
+  for (int l = 0; l < 2; ++l) {
+    const dpm_grid& g = d->sub[l]->grid;
+    const size_t V = (size_t)g.n * g.n * g.n * sizeof(double);
+    L.b2[l] = o; o = align_up(o + 2 * V, 256);
+    L.X[l] = o; o = align_up(o + 2 * V, 256);
+    L.ug[l] = o; o = align_up(o + 2 * sizeof(double) * d->sub[l]->n_gamma, 256);
+  }
+  L.g = o; o = align_up(o + 2 * sizeof(double) * d->rows, 256);
+  L.C = o; o = align_up(o + 2 * sizeof(double) * d->n_cols, 256);
+  for (int l = 0; l < 2; ++l) { L.solve_ws[l] = o; o = align_up(o + solve_ws, 256); }
+  L.total = o;
+  return L;
+}
+
+dpm_status dd_solve_ws(const dpm_dd* d, const dpm_opts& o, size_t* bytes) {
+  size_t mx = 0;
+  dpm_opts so = o;
+  so.rhs_chunk = 0;
+  for (int l = 0; l < 2; ++l) {
+    size_t w = 0;
+    DPM_TRY(workspace_size_impl(d->sub[l]->grid, 2, so, &w));
+    if (w > mx) mx = w;
+  }
+  *bytes = mx;
+  return DPM_OK;
+}
+
+}  // namespace
+
+void dd_destroy(dpm_dd* d) {
+  if (!d) return;
+  for (hipEvent_t e : d->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (d->side) (void)hipStreamDestroy(d->side);
+  destroy_bep(d->sub[0]);
+  destroy_bep(d->sub[1]);
+  (void)hipFree(d->A);
+  (void)hipFree(d->tau);
+  (void)hipFree(d->P);
+  delete d;
+}
+
+dpm_status dd_build_impl(const dpm_dd_params& prm, const dpm_opts& o, hipStream_t s,
+                         dpm_dd** out, double* A_out) {
+  dpm_dd* d = new dpm_dd();
+  d->prm = prm;
+  d->n_gamma_cols = (prm.beta + 1) * (prm.m_gamma + 1);
+  d->n_z_cols = 3 * (prm.m_z + 1);
+  d->n_cols = d->n_gamma_cols + d->n_z_cols;
+  auto fail = [&](dpm_status st) {
+    dd_destroy(d);
+    return st;
+  };
+  if (hipStreamCreateWithFlags(&d->side, hipStreamNonBlocking) != hipSuccess) {
+    set_error("dpm_dd_build: stream creation failed");
+    return fail(DPM_EHIP);
+  }
+  for (hipEvent_t& e : d->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      set_error("dpm_dd_build: event creation failed");
+      return fail(DPM_EHIP);
+    }
+  const double* c = prm.center;
+  for (int l = 0; l < 2; ++l) {
+    const dpm_grid& g = l == 0 ? prm.grid1 : prm.grid2;
+    const long long vsz = (long long)g.n * g.n * g.n;
+    uint8_t* m = nullptr;
+    int32_t* idx = nullptr;
+    uint8_t* is_in = nullptr;
+    double* basis = nullptr;
+    auto release = [&]() {
+      (void)hipFree(m); (void)hipFree(idx); (void)hipFree(is_in); (void)hipFree(basis);
+    };
+    if (hipMalloc(&m, vsz) != hipSuccess) {
+      set_error("dpm_dd_build: device allocation failed");
+      return fail(DPM_ENOMEM);
+    }
+    hipLaunchKernelGGL(k_dd_classify, dim3(blocks_for(vsz)), dim3(kB), 0, s, g.n, g.h, g.x0, c[0],
+                       c[1], c[2], prm.r_z * prm.r_z, prm.r_gamma * prm.r_gamma, l, m);
+    int32_t ng = 0, nin = 0;
+    dpm_status st = gamma_points_impl(g, m, &ng, &nin, nullptr, nullptr, s);
+    if (st != DPM_OK) { release(); return fail(st); }
+    const int nb = l == 0 ? d->n_z_cols : d->n_cols;
+    if (hipMalloc(&idx, sizeof(int32_t) * ng) != hipSuccess || hipMalloc(&is_in, ng) != hipSuccess ||
+        hipMalloc(&basis, sizeof(double) * (size_t)nb * ng) != hipSuccess) {
+      release();
+      set_error("dpm_dd_build: device allocation failed");
+      return fail(DPM_ENOMEM);
+    }
+    st = gamma_points_impl(g, m, &ng, &nin, idx, is_in, s);
+    if (st != DPM_OK) { release(); return fail(st); }
+    hipLaunchKernelGGL(k_dd_basis, dim3((ng + 127) / 128), dim3(128), 0, s, g.n, g.h, g.x0, c[0],
+                       c[1], c[2], ng, idx, l, prm.r_gamma, prm.m_gamma, prm.beta, prm.r_z,
+                       prm.m_z, prm.r_split, basis);
+    if (hipGetLastError() != hipSuccess) {
+      release();
+      set_error("dpm_dd_build: kernel launch failed");
+      return fail(DPM_EHIP);
+    }
+    // point sets, densities and the unfactored columns A_l of this subdomain
+    st = build_bep_impl(g, m, nb, basis, o, s, &d->sub[l], nullptr, false);
+    (void)hipStreamSynchronize(s);
+    release();
+    if (st != DPM_OK) return fail(st);
+  }
+  const int m0 = d->sub[0]->n_in, m1 = d->sub[1]->n_in;
+  d->rows = m0 + m1;
+  if (d->n_cols > d->rows) {
+    set_error("dpm_dd_build: %d columns exceed the %d rows of the coupled BEP", d->n_cols, d->rows);
+    return fail(DPM_ERANK);
+  }
+  const size_t na = (size_t)d->rows * d->n_cols;
+  if (hipMalloc(&d->A, sizeof(double) * na) != hipSuccess ||
+      hipMalloc(&d->tau, sizeof(double) * d->n_cols) != hipSuccess ||
+      hipMalloc(&d->P, sizeof(double) * na) != hipSuccess) {
+    set_error("dpm_dd_build: device allocation failed");
+    return fail(DPM_ENOMEM);
+  }
+  hipLaunchKernelGGL(k_dd_stack, dim3(blocks_for((long long)na)), dim3(kB), 0, s, d->sub[0]->A,
+                     m0, d->sub[1]->A, m1, d->n_gamma_cols, d->n_cols, d->A);
+  if (hipGetLastError() != hipSuccess) {
+    set_error("dpm_dd_build: kernel launch failed");
+    return fail(DPM_EHIP);
+  }
+  if (A_out && hipMemcpyAsync(A_out, d->A, sizeof(double) * na, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    set_error("dpm_dd_build: copy of A failed");
+    return fail(DPM_EHIP);
+  }
+  {
+    const dpm_status st = lsq_factor(d->A, d->rows, d->n_cols, d->tau, d->P, s, &d->rdiag_min,
+                                     &d->rdiag_max);
+    if (st != DPM_OK) return fail(st);
+  }
+  *out = d;
+  return DPM_OK;
+}
+
+double dd_sigma(const dpm_dd* d) { return d->prm.grid1.sigma; }
+
+dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], int32_t* n_cols,
+                        double* rmin, double* rmax) {
+  for (int l = 0; l < 2; ++l) {
+    if (n_gamma) n_gamma[l] = d->sub[l]->n_gamma;
+    if (n_in) n_in[l] = d->sub[l]->n_in;
+  }
+  if (n_cols) *n_cols = d->n_cols;
+  if (rmin) *rmin = d->rdiag_min;
+  if (rmax) *rmax = d->rdiag_max;
+  return DPM_OK;
+}
+
+dpm_status dd_step_workspace_impl(const dpm_dd* d, const dpm_opts& o, size_t* bytes) {
+  size_t sw = 0;
+  DPM_TRY(dd_solve_ws(d, o, &sw));
+  *bytes = dd_layout(d, sw).total;
+  return DPM_OK;
+}
+
+dpm_status dd_step_impl(const dpm_dd* d, double dt, double chi, const double* const in[4],
+                        double* const out[4], const dpm_opts& o, hipStream_t s) {
+  size_t sw = 0;
+  DPM_TRY(dd_solve_ws(d, o, &sw));
+  const DDLayout L = dd_layout(d, sw);
+  if (o.workspace == nullptr || o.workspace_bytes < L.total) {
+    set_error("dpm_dd_step: workspace too small: %zu bytes given, %zu needed", o.workspace_bytes,
+              L.total);
+    return DPM_EINVAL;
+  }
+  char* ws = static_cast<char*>(o.workspace);
+  dpm_opts so[2] = {o, o};
+  double* b2[2];
+  double* X[2];
+  double* ug[2];
+  for (int l = 0; l < 2; ++l) {
+    so[l].rhs_chunk = 0;
+    so[l].workspace = ws + L.solve_ws[l];
+    so[l].workspace_bytes = sw;
+    b2[l] = reinterpret_cast<double*>(ws + L.b2[l]);
+    X[l] = reinterpret_cast<double*>(ws + L.X[l]);
+    ug[l] = reinterpret_cast<double*>(ws + L.ug[l]);
+  }
+  double* g = reinterpret_cast<double*>(ws + L.g);
+  double* C = reinterpret_cast<double*>(ws + L.C);
+  hipStream_t st[2] = {s, d->side};
+  // Step 4a on both meshes (Omega_2 on the side stream): forcing and particular solutions
+  DPM_TRY_HIP(hipEventRecord(d->ev[0], s));
+  DPM_TRY_HIP(hipStreamWaitEvent(d->side, d->ev[0], 0));
+  for (int l = 0; l < 2; ++l) {
+    launch_pks_rhs(d->sub[l], in[2 * l], in[2 * l + 1], dt, chi, b2[l], st[l]);
+    DPM_TRY_HIP(hipGetLastError());
+    DPM_TRY(aux_solve_impl(d->sub[l]->grid, 2, b2[l], X[l], so[l], st[l], nullptr));
+  }
+  DPM_TRY_HIP(hipEventRecord(d->ev[1], d->side));
+  DPM_TRY_HIP(hipStreamWaitEvent(s, d->ev[1], 0));
+  // Step 5: the coupled least squares on the stacked traces
+  const dpm_bep* s0 = d->sub[0];
+  const dpm_bep* s1 = d->sub[1];
+  const long long v0 = (long long)s0->grid.n * s0->grid.n * s0->grid.n;
+  const long long v1 = (long long)s1->grid.n * s1->grid.n * s1->grid.n;
+  hipLaunchKernelGGL(k_dd_gather, dim3((d->rows + kB - 1) / kB, 2), dim3(kB), 0, s, X[0], v0,
+                     s0->idx_in, s0->n_in, X[1], v1, s1->idx_in, s1->n_in, g);
+  lsq_apply(d->P, d->rows, d->n_cols, 2, g, C, s);
+  // densities: Omega_1 from the Z coefficients, Omega_2 from all of them
+  launch_density(s0, C + d->n_gamma_cols, d->n_cols, ug[0], s);
+  launch_density(s1, C, d->n_cols, ug[1], s);
+  DPM_TRY_HIP(hipGetLastError());
+  // Steps 6-7 per subdomain: Green's formula as one AP solve per species, restriction to N+
+  DPM_TRY_HIP(hipEventRecord(d->ev[2], s));
+  DPM_TRY_HIP(hipStreamWaitEvent(d->side, d->ev[2], 0));
+  for (int l = 0; l < 2; ++l) {
+    minus_rhs(d->sub[l], ug[l], 0, 2, b2[l], st[l]);
+    DPM_TRY_HIP(hipGetLastError());
+    DPM_TRY(aux_solve_impl(d->sub[l]->grid, 2, b2[l], X[l], so[l], st[l], nullptr));
+    launch_restrict(d->sub[l], X[l], out[2 * l], out[2 * l + 1], st[l]);
+    DPM_TRY_HIP(hipGetLastError());
+  }
+  DPM_TRY_HIP(hipEventRecord(d->ev[3], d->side));
+  DPM_TRY_HIP(hipStreamWaitEvent(s, d->ev[3], 0));
+  return DPM_OK;
+}
+
+dpm_status dd_masks_impl(const dpm_dd* d, int l, uint8_t* m_plus, uint8_t* n_plus, hipStream_t s) {
+  const dpm_bep* b = d->sub[l];
+  const size_t vsz = (size_t)b->grid.n * b->grid.n * b->grid.n;
+  if (m_plus) DPM_TRY_HIP(hipMemcpyAsync(m_plus, b->m_plus, vsz, hipMemcpyDeviceToDevice, s));
+  if (n_plus) DPM_TRY_HIP(hipMemcpyAsync(n_plus, b->n_plus, vsz, hipMemcpyDeviceToDevice, s));
+  return DPM_OK;
+}
+
+dpm_status dd_gauss_impl(const dpm_dd* d, int l, double amp, double rate, const double c0[3],
+                         double* out, hipStream_t s) {
+  const dpm_bep* b = d->sub[l];
+  const dpm_grid& g = b->grid;
+  const long long vsz = (long long)g.n * g.n * g.n;
+  hipLaunchKernelGGL(k_dd_gauss, dim3(blocks_for(vsz)), dim3(kB), 0, s, b->n_plus, g.n, g.h, g.x0,
+                     amp, rate, c0[0], c0[1], c0[2], out);
+  DPM_TRY_HIP(hipGetLastError());
+  return DPM_OK;
+}
+
+}  // namespace dpm

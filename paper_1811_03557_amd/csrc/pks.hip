@@ -70,11 +70,11 @@ __global__ void k_pks_rhs(const double* __restrict__ rho, const double* __restri
   b2[vsz + i] = sigma * ((1.0 - dt) * c0 + dt * r0);
 }
 
-// u_gamma[r][i] = sum_nu basis[nu][i] C[r][nu] for the two species r = 0, 1: one thread per
+// u_gamma[r][i] = sum_nu basis[nu][i] C[r ldc + nu] for the two species r = 0, 1: one thread per
 // gamma node reads its basis column once, kDU densities in flight at a time.
 constexpr int kDU = 10;
 __global__ void k_density(const double* __restrict__ basis, const double* __restrict__ C,
-                          int nb, int ng, double* __restrict__ ug) {
+                          int nb, int ldc, int ng, double* __restrict__ ug) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ng) return;
   double a0 = 0.0, a1 = 0.0;
@@ -86,13 +86,13 @@ __global__ void k_density(const double* __restrict__ basis, const double* __rest
 #pragma unroll
     for (int u = 0; u < kDU; ++u) {
       a0 += v[u] * C[nu + u];
-      a1 += v[u] * C[nb + nu + u];
+      a1 += v[u] * C[ldc + nu + u];
     }
   }
   for (; nu < nb; ++nu) {
     const double v = basis[(long long)nu * ng + i];
     a0 += v * C[nu];
-    a1 += v * C[nb + nu];
+    a1 += v * C[ldc + nu];
   }
   ug[i] = a0;
   ug[(long long)ng + i] = a1;
@@ -238,6 +238,25 @@ StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
 
 }  // namespace
 
+void launch_pks_rhs(const dpm_bep* b, const double* rho, const double* c, double dt, double chi,
+                    double* b2, hipStream_t s) {
+  const dpm_grid& g = b->grid;
+  const long long vsz = (long long)g.n * g.n * g.n;
+  hipLaunchKernelGGL(k_pks_rhs, dim3(grid1(vsz)), dim3(kB), 0, s, rho, c, b->m_plus, g.n, g.h,
+                     dt, chi, g.sigma, b2);
+}
+
+void launch_density(const dpm_bep* b, const double* C, int ldc, double* ug, hipStream_t s) {
+  hipLaunchKernelGGL(k_density, dim3(grid1(b->n_gamma)), dim3(kB), 0, s, b->basis, C,
+                     b->n_basis, ldc, b->n_gamma, ug);
+}
+
+void launch_restrict(const dpm_bep* b, const double* U, double* o0, double* o1, hipStream_t s) {
+  const long long vsz = (long long)b->grid.n * b->grid.n * b->grid.n;
+  hipLaunchKernelGGL(k_restrict, dim3(grid1(vsz)), dim3(kB), 0, s, U, b->n_plus, vsz, o0, o1,
+                     nullptr);
+}
+
 dpm_status step_workspace_impl(const dpm_bep* b, const dpm_opts& o, size_t* bytes) {
   size_t sw = 0;
   dpm_opts so = o;
@@ -281,7 +300,7 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   // Step 5: Tr_gamma_in G f, least squares, densities
   qr_solve_traces(b, 2, X, vsz, C, s);
   hipLaunchKernelGGL(k_density, dim3(grid1(b->n_gamma)), dim3(kB), 0, s, b->basis, C,
-                     b->n_basis, b->n_gamma, ug);
+                     b->n_basis, b->n_basis, b->n_gamma, ug);
   // Steps 6-7: Green's formula as one AP solve per species
   // b2 holds sigma 1_{M+} f, zero on M-: add the M- part (sigma - Lap_h)[u_gamma] in place
   minus_rhs(b, ug, 0, 2, b2, s);

@@ -79,3 +79,36 @@ def test_host_validation_without_device():
     assert lib.dpm_run(None, C.byref(prm), fake, odd, C.byref(o), None, None, None, None) == _lib.DPM_EINVAL
     assert lib.dpm_bep_rebuild(None, 1.0, None) == _lib.DPM_EINVAL
     assert lib.dpm_cfl_scan(None, fake, fake, fake, None) == _lib.DPM_EINVAL
+
+
+def test_dd_validation_without_device():
+    """The domain-decomposition entry points reject bad radii, degrees, meshes and handles before
+    any launch."""
+    from paper_1811_03557_amd import _lib
+    lib = _lib.load()
+    g1 = _lib.Grid(15, 0.09375, 1000.0, -0.75 + 0.09375)
+    g2 = _lib.Grid(31, 0.09375, 1000.0, -1.5 + 0.09375)
+    o = _lib.Opts(_lib.DPM_FP64, 1, 1e-10, 0, 0, None, 0)
+    out = C.c_void_p(0)
+
+    def build(**kw):
+        p = dict(grid1=g1, grid2=g2, center=(C.c_double * 3)(0, 0, 0), r_z=0.5, r_gamma=1.0,
+                 r_split=0.75, m_gamma=2, beta=1, m_z=2)
+        p.update(kw)
+        prm = _lib.DDParams(**p)
+        return lib.dpm_dd_build(C.byref(prm), C.byref(o), None, C.byref(out), None)
+
+    for kw, word in [({"r_split": 0.4}, "radii"), ({"r_gamma": 0.7}, "radii"),
+                     ({"r_z": 0.0}, "radii"), ({"beta": 2}, "beta"), ({"m_z": -1}, "m_gamma"),
+                     ({"m_gamma": 600}, "columns"),
+                     ({"grid2": _lib.Grid(31, 0.09375, 999.0, -1.5 + 0.09375)}, "sigma"),
+                     ({"grid1": _lib.Grid(36, 0.09375, 1000.0, -0.75)}, "n + 1")]:
+        assert build(**kw) == _lib.DPM_EINVAL, kw
+        assert word in lib.dpm_last_error().decode(), (kw, lib.dpm_last_error())
+    assert out.value is None
+    fake = C.c_void_p(256)
+    vols = (C.c_void_p * 4)(256, 512, 768, 1024)
+    assert lib.dpm_dd_step(None, 1e-3, 1.0, vols, vols, C.byref(o), None) == _lib.DPM_EINVAL
+    assert lib.dpm_dd_masks(None, 0, fake, fake, None) == _lib.DPM_EINVAL
+    assert lib.dpm_dd_gauss_state(None, 0, 1.0, 1.0, (C.c_double * 3)(0, 0, 0), fake, None) == _lib.DPM_EINVAL
+    assert lib.dpm_dd_info(None, None, None, None, None, None) == _lib.DPM_EINVAL

@@ -1,0 +1,142 @@
+"""Domain decomposition, Case 1 (Sec. 3, eqs interface_condition, reduced_DD1_BEP1,
+reduced_DD1_BEP2) through the C ABI, against the oracle (oracle/dd.py) on the same data:
+
+- the point sets of both subdomains (bit-exact) and the stacked coupled-BEP matrix;
+- one step on both subdomains (forcing, particular solutions, the coupled least squares, the
+  Green's formula of each subdomain), also in place and on meshes of different spacing;
+- the exact constant state and the node-sampled Gaussian initial data.
+
+Tolerance: the matrix and the states come from FP64 AP solves (FFT form, relative error ~1e-14
+per solve) and an FP64 QR, so 1e-10 relative to the largest entry leaves four orders of margin.
+"""
+import numpy as np
+import pytest
+
+from oracle import dd as odd
+from oracle import geometry as og
+from tests.gpu_util import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _params(case, sigma, m_gamma, beta, m_z):
+    from paper_1811_03557_amd import api
+    return api.dd_params(case.n1, case.h1, case.x01, case.n2, case.h2, case.x02, sigma,
+                         case.r_z, 1.0, 0.5 * (case.r_z + 1.0), m_gamma, beta, m_z)
+
+
+def _data(mesh, ps):
+    z, y, x = mesh
+    r2 = x * x + y * y + z * z
+    return (np.where(ps.n_plus, 10 * np.exp(-2 * r2), 0.0),
+            np.where(ps.n_plus, 5 * np.exp(-r2), 0.0))
+
+
+CASES = [
+    # n1, half-width of Omega_1's cube, n2, r_z, m_gamma, m_z, beta
+    (15, 0.75, 31, 0.5, 2, 2, 1),    # the same spacing on both meshes
+    (31, 0.75, 31, 0.5, 3, 2, 1),    # Omega_1's mesh twice as fine
+    (63, 0.75, 31, 0.5, 0, 0, 1),    # Omega_1's mesh four times as fine, one harmonic per term
+]
+
+
+@pytest.mark.parametrize("n1,half1,n2,r_z,mg,mz,beta", CASES)
+def test_dd_matrix_and_point_sets(n1, half1, n2, r_z, mg, mz, beta):
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case = odd.DDCase(n1, half1, n2, r_z, mg, mz, beta)
+    assert case.ps1.margin_ok and case.ps2.margin_ok
+    dt = 1e-3
+    say(f"dd matrix n1={n1} half1={half1} n2={n2} mg={mg} mz={mz} beta={beta}")
+    dd, A = api.dd_build(_params(case, 1.0 / dt, mg, beta, mz), return_A=True, device=dev)
+    for l, ps in enumerate((case.ps1, case.ps2)):
+        mp, np_ = dd.masks(l)
+        assert np.array_equal(mp.cpu().numpy().astype(bool), ps.m_plus)
+        assert np.array_equal(np_.cpu().numpy().astype(bool), ps.n_plus)
+        assert dd.n_gamma[l] == ps.n_gamma and dd.n_gamma_in[l] == ps.n_gamma_in
+    # no gamma node of Omega_2 near the Gamma/Z split radius: the split is a clean decision
+    gz, gy, gx = og.gamma_coords(case.ps2, case.x02, case.h2)
+    rr = np.sqrt(gx * gx + gy * gy + gz * gz)
+    assert np.min(np.abs(rr - 0.5 * (r_z + 1.0))) > 0.5 * case.h2
+    ref = odd.dd_matrix(case, 1.0 / dt)
+    assert A.shape == ref.shape and dd.n_cols == case.n_cols
+    err = np.max(np.abs(A.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    say(f"  rows {ref.shape[0]}, cols {ref.shape[1]}, rel err {err:.2e}")
+    assert err <= TOL
+    dd.close()
+
+
+@pytest.mark.parametrize("n1,half1,n2,r_z,mg,mz,beta", CASES)
+def test_dd_step_matches_oracle(n1, half1, n2, r_z, mg, mz, beta):
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case = odd.DDCase(n1, half1, n2, r_z, mg, mz, beta)
+    dt, chi = 1e-3, 1.0
+    say(f"dd step n1={n1} half1={half1} n2={n2} mg={mg} mz={mz} beta={beta}")
+    A = odd.dd_matrix(case, 1.0 / dt)
+    r1, c1 = _data(case.mesh1, case.ps1)
+    r2, c2 = _data(case.mesh2, case.ps2)
+    ref = odd.dd_step(r1, c1, r2, c2, case, A, dt, chi)[:4]
+    dd = api.dd_build(_params(case, 1.0 / dt, mg, beta, mz), device=dev)
+    state = [torch.from_numpy(v).to(dev) for v in (r1, c1, r2, c2)]
+    out = api.dd_step(dd, dt, chi, state)
+    for k, (g, o) in enumerate(zip(out, ref)):
+        err = np.max(np.abs(g.cpu().numpy() - o)) / np.max(np.abs(o))
+        say(f"  output {k}: rel err {err:.2e}")
+        assert err <= TOL, (k, err)
+    # a second step in place against the oracle's second step
+    ref2 = odd.dd_step(*ref, case, A, dt, chi)[:4]
+    api.dd_step(dd, dt, chi, out, out=list(out))
+    for k, (g, o) in enumerate(zip(out, ref2)):
+        err = np.max(np.abs(g.cpu().numpy() - o)) / np.max(np.abs(o))
+        assert err <= TOL, ("second step", k, err)
+    dd.close()
+
+
+def test_dd_constant_state_and_gauss_data():
+    """A constant state is an exact discrete solution of the coupled problem (P_0 represents it
+    on both surfaces): rho stays 3, c moves to (1 - dt) 5 + 3 dt, on both N+; the node-sampled
+    Gaussian data equal the formula at the N+ nodes and zero elsewhere."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case = odd.DDCase(15, 0.75, 31, 0.5, 2, 2, 1)
+    dt = 0.5 * case.h2 ** 2
+    dd = api.dd_build(_params(case, 1.0 / dt, 2, 1, 2), device=dev)
+    say("dd constant state 15/31")
+    state = []
+    for ps in (case.ps1, case.ps2):
+        state += [torch.from_numpy(np.where(ps.n_plus, 3.0, 0.0)).to(dev),
+                  torch.from_numpy(np.where(ps.n_plus, 5.0, 0.0)).to(dev)]
+    out = [v.cpu().numpy() for v in api.dd_step(dd, dt, 1.0, state)]
+    cn = (1 - dt) * 5.0 + dt * 3.0
+    for (r, c), ps in ((out[:2], case.ps1), (out[2:], case.ps2)):
+        assert np.allclose(r[ps.n_plus], 3.0, rtol=1e-12, atol=0)
+        assert np.allclose(c[ps.n_plus], cn, rtol=1e-12, atol=0)
+        assert np.all(r[~ps.n_plus] == 0) and np.all(c[~ps.n_plus] == 0)
+    for l, (mesh, ps) in enumerate(((case.mesh1, case.ps1), (case.mesh2, case.ps2))):
+        z, y, x = mesh
+        ref = np.where(ps.n_plus, 7.0 * np.exp(-3.0 * ((x - 0.1) ** 2 + y * y + z * z)), 0.0)
+        g = dd.gauss_state(l, 7.0, 3.0, (0.1, 0.0, 0.0)).cpu().numpy()
+        assert np.max(np.abs(g - ref)) <= 1e-14 * 7.0
+    dd.close()
+
+
+def test_dd_rejects_wrong_dt_and_shapes():
+    import torch
+    from paper_1811_03557_amd import api
+    from paper_1811_03557_amd._lib import DPMError
+    dev = need_gpu()
+    case = odd.DDCase(15, 0.75, 31, 0.5, 0, 0, 1)
+    dd = api.dd_build(_params(case, 1000.0, 0, 1, 0), device=dev)
+    say("dd rejections")
+    state = [torch.zeros((n,) * 3, dtype=torch.float64, device=dev) for n in (15, 15, 31, 31)]
+    with pytest.raises(DPMError, match="sigma"):
+        api.dd_step(dd, 2e-3, 1.0, state)
+    with pytest.raises(ValueError, match="hold"):
+        api.dd_step(dd, 1e-3, 1.0, state[::-1])
+    dd.close()
