@@ -95,3 +95,104 @@ def test_dd_converges_to_single_domain():
     fine = _dd_minus_sd(31, 63, 0.0)
     for a, b in zip(coarse, fine):
         assert a < 1e-4 and a / b > 2.5, (a, b)
+
+
+# ---- Case 2: Z (radius 0.5 about the north pole q = (0, 0, 1)) meets Gamma -------------------
+
+def _data2(mesh, ps):
+    z, y, x = mesh
+    r2 = x * x + y * y + (z - 0.5) ** 2
+    return np.where(ps.n_plus, 10 * np.exp(-2 * r2), 0.0), np.where(ps.n_plus, 5 * np.exp(-r2), 0.0)
+
+
+@pytest.fixture(scope="module")
+def small2():
+    case = dd.DDCase2(15, 0.75, 0.75, 31, 1.0, 0.5, 4, 2, beta=0)
+    assert all(s["ps"].margin_ok for s in case.sub)
+    return case
+
+
+def test_dd2_parts_cover_the_discrete_boundaries(small2):
+    """The wedge angles follow from the two radii, every node of each subdomain's discrete
+    boundary falls in gamma_l or zeta_l, the wedge carries nodes in both, and the part decisions
+    are far from rounding ties."""
+    case = small2
+    assert np.isclose(np.cos(case.theta_star), 0.875) and np.isclose(np.cos(case.psi_star), 0.25)
+    assert case.covered
+    for l, s in enumerate(case.sub):
+        both = s["in_g"] & s["in_z"]
+        assert 0 < both.sum() < 0.5 * s["cover"].sum()
+        edge = case.theta_star + (s["eps_g"] if l == 0 else -s["eps_g"])
+        assert np.min(np.abs(s["theta"] - edge)) > 1e-4
+        assert np.min(np.abs(s["psi"] - (case.psi_star + s["eps_z"]))) > 1e-4
+        # effective densities: the average of the two at the wedge nodes
+        j = np.flatnonzero(both)[0]
+        assert np.allclose(s["B_eff"][: case.n_gamma_cols, j], 0.5 * s["bg"][:, j])
+        assert np.allclose(s["B_eff"][case.n_gamma_cols:, j], 0.5 * s["bz"][:, j])
+        # one BEP row per part: wedge nodes of gamma_in carry two
+        n_in_both = int((both & s["ps"].is_in).sum())
+        assert len(s["rows"]) == s["ps"].n_gamma_in + n_in_both
+
+
+def test_dd2_constant_state(small2):
+    case = small2
+    dt = 0.5 * case.sub[1]["h"] ** 2
+    A = dd.dd2_matrix(case, 1.0 / dt)
+    st = []
+    for s in case.sub:
+        st += [np.where(s["ps"].n_plus, 3.0, 0.0), np.where(s["ps"].n_plus, 5.0, 0.0)]
+    out = dd.dd2_step(*st, case, A, dt, 1.0)
+    cn = (1 - dt) * 5.0 + dt * 3.0
+    for (r, c), s in ((out[:2], case.sub[0]), (out[2:4], case.sub[1])):
+        assert np.allclose(r[s["ps"].n_plus], 3.0, rtol=1e-11)
+        assert np.allclose(c[s["ps"].n_plus], cn, rtol=1e-11)
+
+
+def test_dd2_axial_symmetry(small2):
+    case = small2
+    dt = 1e-3
+    A = dd.dd2_matrix(case, 1.0 / dt)
+    st = []
+    for s in case.sub:
+        st += list(_data2(s["mesh"], s["ps"]))
+    out = dd.dd2_step(*st, case, A, dt, 1.0)
+    for f in out[:4]:
+        tol = 1e-11 * np.abs(f).max()
+        assert np.max(np.abs(f - f[:, :, ::-1])) < tol
+        assert np.max(np.abs(f - f[:, ::-1, :])) < tol
+        assert np.max(np.abs(f - np.transpose(f, (0, 2, 1)))) < tol
+
+
+def _dd2_minus_sd(n1, n2, chi):
+    case = dd.DDCase2(n1, 0.75, 0.75, n2, 1.0, 0.5, 4, 4, beta=0)
+    dt = 1e-3
+    A = dd.dd2_matrix(case, 1.0 / dt)
+    s1, s2 = case.sub
+    st = list(_data2(s1["mesh"], s1["ps"])) + list(_data2(s2["mesh"], s2["ps"]))
+    o = dd.dd2_step(*st, case, A, dt, chi)
+    h, x0 = inp.grid(n2)
+    z, y, x = inp.mesh(n2)
+    ps = og.PointSets(og.inside_sphere(z, y, x))
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    d, th, _ = og.project_sphere(gz, gy, gx)
+    B = ob.zonal_basis_matrix(d, th, 4, 0)
+    rs, cs = _data2((z, y, x), ps)
+    rsd, csd, _ = pks.dpm_step(rs, cs, ps, B, dpm.bep_matrix(B, ps, 1 / dt, h), h, dt, chi)
+    # Omega_1's cube [-0.75, 0.75]^2 x [0, 1.5]: its nodes are Omega_2's, shifted
+    kz, kx = int(round(1.5 / h)), (n2 - n1) // 2
+    sl = (slice(kz, kz + n1), slice(kx, kx + n1), slice(kx, kx + n1))
+    m1, m2 = s1["ps"].m_plus, s2["ps"].m_plus
+    assert np.array_equal(s1["mesh"][0][m1], z[sl][m1])
+    return [np.max(np.abs(o[0][m1] - rsd[sl][m1])) / np.abs(rsd).max(),
+            np.max(np.abs(o[2][m2] - rsd[m2])) / np.abs(rsd).max(),
+            np.max(np.abs(o[1][m1] - csd[sl][m1])) / np.abs(csd).max(),
+            np.max(np.abs(o[3][m2] - csd[m2])) / np.abs(csd).max()]
+
+
+def test_dd2_converges_to_single_domain():
+    """The decomposed and single-domain steps approximate the same problem: their difference,
+    dominated by the wedge, falls by more than 3.5x per halving of h (with convection)."""
+    coarse = _dd2_minus_sd(15, 31, 1.0)
+    fine = _dd2_minus_sd(31, 63, 1.0)
+    for a, b in zip(coarse, fine):
+        assert b < 2e-3 and a / b > 3.5, (a, b)
