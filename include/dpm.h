@@ -327,17 +327,54 @@ typedef struct {
  * dpm_dd_build -- Step 2 of the paper's algorithm for both subdomains: point sets, densities,
  * one AP solve per density on each mesh, the stacked matrix [[0, A_1], [A_2]] (A_1 carries the
  * Z columns only) and its QR and least-squares operator.  opts selects the precision of the
- * solves (both grids must suit it).  A_out: nullable device (|zeta_1,in| + |gamma_2,in|) x
- * n_cols FP64, column-major, the matrix before factorisation.  Allocates the handle's device
+ * solves (both grids must suit it).  A_out: nullable device rows x n_cols FP64 (rows =
+ * |zeta_1,in| + |gamma_2,in|, see dpm_dd_info), column-major, the matrix before factorisation.  Allocates the handle's device
  * memory and synchronises the stream.  DPM_EGEOM when a subdomain's N+ leaves its cube,
  * DPM_ERANK when the stacked matrix is rank deficient.  Release with dpm_dd_destroy.
  */
 dpm_status dpm_dd_build(const dpm_dd_params* params, const dpm_opts* opts, void* stream,
                         dpm_dd** out, double* A_out);
 
-/* Counts of a built handle (host values; arrays of two entries, subdomain 1 first). */
+/*
+ * dpm_dd2_build -- the same for Case 2 (paper Sec. 3: "Case 2" and "BEPs for Case 2", eqs
+ * DD2_BEP and reduced_DD2_BEP, and the remark on effective densities): Omega is the ball
+ * |x| < r_gamma about the origin, Z the sphere of radius r_z about q = (0, 0, q_z) with q_z - r_z
+ * < r_gamma < q_z + r_z, so Z meets Gamma on a circle (polar angle theta* about the origin,
+ * angle psi* at q from the direction towards the origin); Omega_1 = Omega cap {|x - q| < r_z},
+ * Omega_2 = Omega cap {|x - q| > r_z}.  On subdomain l's mesh, gamma_l = the nodes of the ball's
+ * discrete grid boundary whose polar angle is at most theta* + eps (l = 1) or at least
+ * theta* - eps (l = 2), zeta_l = the nodes of the discrete grid boundary of Z's side whose angle
+ * psi is at most psi* + eps_z, with eps = eps_layers h_l / r_gamma and eps_z = eps_layers h_l /
+ * r_z.  Densities: one zonal expansion on Gamma (P_nu(cos theta) and, beta = 1, (d^2/2) P_nu,
+ * nu <= m_gamma) shared by gamma_1 and gamma_2, one 3-term expansion on Z (P_nu(cos psi), d P_nu,
+ * (d^2/2) P_nu, nu <= m_z) shared by zeta_1 and zeta_2.  A node in gamma_l and zeta_l carries
+ * the average of its two densities in the difference potential and two reduced-BEP equations
+ * (Gamma row first).  Rows follow each subdomain's gamma_in in ascending index, subdomain 1 first.
+ * Node coordinates of mesh l are (x0 + h i) + origin_l per axis.  DPM_EGEOM also when a node of
+ * a subdomain's discrete grid boundary falls in neither part (eps_layers too small).  The handle
+ * is used with dpm_dd_info, dpm_dd_masks, dpm_dd_step, dpm_dd_gauss_state and dpm_dd_destroy.
+ */
+typedef struct {
+  dpm_grid grid1;      /* mesh of Omega_1's cube; sigma = 1/dt, the same in grid2 */
+  dpm_grid grid2;      /* mesh of Omega_2's cube */
+  double origin1[3];   /* (x, y, z) offset of mesh 1's node coordinates */
+  double origin2[3];
+  double r_gamma;      /* radius of Gamma */
+  double q_z;          /* centre of Z on the z axis */
+  double r_z;          /* radius of Z */
+  double eps_layers;   /* angular tolerance of the parts, in mesh widths, > 0 */
+  int32_t m_gamma;     /* highest degree on Gamma, >= 0 */
+  int32_t beta;        /* 1: 3-term extension on Gamma, 0: 2-term */
+  int32_t m_z;         /* highest degree on Z, >= 0 */
+} dpm_dd2_params;
+dpm_status dpm_dd2_build(const dpm_dd2_params* params, const dpm_opts* opts, void* stream,
+                         dpm_dd** out, double* A_out);
+
+/* Counts of a built handle (host values; arrays of two entries, subdomain 1 first): gamma and
+ * gamma_in sizes, reduced-BEP rows (gamma_in, plus the wedge nodes' second rows in Case 2). */
 dpm_status dpm_dd_info(const dpm_dd* dd, int32_t n_gamma[2], int32_t n_gamma_in[2],
-                       int32_t* n_cols, double* min_abs_rdiag, double* max_abs_rdiag);
+                       int32_t n_rows[2], int32_t* n_cols, double* min_abs_rdiag,
+                       double* max_abs_rdiag);
 
 /* Copies of subdomain l's (0 or 1) M+ and N+ masks (device, its N^3 uint8; each nullable). */
 dpm_status dpm_dd_masks(const dpm_dd* dd, int32_t l, uint8_t* m_plus, uint8_t* n_plus,

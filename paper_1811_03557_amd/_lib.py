@@ -55,6 +55,13 @@ class DDParams(C.Structure):
                 ("beta", C.c_int32), ("m_z", C.c_int32)]
 
 
+class DD2Params(C.Structure):
+    _fields_ = [("grid1", Grid), ("grid2", Grid), ("origin1", C.c_double * 3),
+                ("origin2", C.c_double * 3), ("r_gamma", C.c_double), ("q_z", C.c_double),
+                ("r_z", C.c_double), ("eps_layers", C.c_double), ("m_gamma", C.c_int32),
+                ("beta", C.c_int32), ("m_z", C.c_int32)]
+
+
 # exported symbol -> (restype, argtypes)
 _P = C.c_void_p
 _I = C.c_int32
@@ -89,8 +96,9 @@ SIGNATURES = {
     "dpm_gauss_state": (C.c_int, [_P, C.POINTER(Geometry), _D, _D, C.POINTER(_D), _P, _P]),
     "dpm_bep_destroy": (None, [_P]),
     "dpm_dd_build": (C.c_int, [C.POINTER(DDParams), C.POINTER(Opts), _P, C.POINTER(_P), _P]),
-    "dpm_dd_info": (C.c_int, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I), C.POINTER(_D),
-                              C.POINTER(_D)]),
+    "dpm_dd2_build": (C.c_int, [C.POINTER(DD2Params), C.POINTER(Opts), _P, C.POINTER(_P), _P]),
+    "dpm_dd_info": (C.c_int, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I), C.POINTER(_I),
+                              C.POINTER(_D), C.POINTER(_D)]),
     "dpm_dd_masks": (C.c_int, [_P, _I, _P, _P, _P]),
     "dpm_dd_step_workspace_size": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
     "dpm_dd_step": (C.c_int, [_P, _D, _D, C.POINTER(_P), C.POINTER(_P), C.POINTER(Opts), _P]),

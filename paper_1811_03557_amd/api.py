@@ -269,11 +269,11 @@ class DD:
         self.device = device
         self.sigma = params.grid1.sigma
         self.n = (params.grid1.n, params.grid2.n)
-        ng, ngi = (C.c_int32 * 2)(), (C.c_int32 * 2)()
+        ng, ngi, nr = (C.c_int32 * 2)(), (C.c_int32 * 2)(), (C.c_int32 * 2)()
         nc, rmin, rmax = C.c_int32(0), C.c_double(0), C.c_double(0)
-        L.check(L.load().dpm_dd_info(C.c_void_p(ptr), ng, ngi, C.byref(nc), C.byref(rmin),
+        L.check(L.load().dpm_dd_info(C.c_void_p(ptr), ng, ngi, nr, C.byref(nc), C.byref(rmin),
                                      C.byref(rmax)))
-        self.n_gamma, self.n_gamma_in = tuple(ng), tuple(ngi)
+        self.n_gamma, self.n_gamma_in, self.n_rows = tuple(ng), tuple(ngi), tuple(nr)
         self.n_cols = nc.value
         self.rdiag = (rmin.value, rmax.value)
 
@@ -318,25 +318,33 @@ def dd_params(n1: int, h1: float, x01: float, n2: int, h2: float, x02: float, si
                       float(r_z), float(r_gamma), float(r_split), int(m_gamma), int(beta), int(m_z))
 
 
-def dd_build(params: L.DDParams, prec: str = "fp64", device="cuda", return_A: bool = False,
-             stream=None):
-    """Step 2 of the domain decomposition (Case 1): both subdomains' columns, the stacked matrix
-    and its QR.  Returns a DD handle (and the stacked matrix, rows x n_cols, when return_A: the
-    row count is known only after a first build, so that case builds twice)."""
+def dd2_params(n1: int, h1: float, x01: float, origin1, n2: int, h2: float, x02: float, origin2,
+               sigma: float, r_gamma: float, q_z: float, r_z: float, eps_layers: float,
+               m_gamma: int, beta: int, m_z: int) -> L.DD2Params:
+    return L.DD2Params(grid(n1, h1, sigma, x01), grid(n2, h2, sigma, x02),
+                       (C.c_double * 3)(*origin1), (C.c_double * 3)(*origin2), float(r_gamma),
+                       float(q_z), float(r_z), float(eps_layers), int(m_gamma), int(beta), int(m_z))
+
+
+def dd_build(params, prec: str = "fp64", device="cuda", return_A: bool = False, stream=None):
+    """Step 2 of the domain decomposition (Case 1 for DDParams, Case 2 for DD2Params): both
+    subdomains' columns, the stacked matrix and its QR.  Returns a DD handle (and the stacked
+    matrix, rows x n_cols, when return_A: the row count is known only after a first build, so
+    that case builds twice)."""
     lib = L.load()
+    fn = lib.dpm_dd2_build if isinstance(params, L.DD2Params) else lib.dpm_dd_build
     o = opts(prec, True)
     out = C.c_void_p(0)
-    L.check(lib.dpm_dd_build(C.byref(params), C.byref(o), C.c_void_p(_stream(stream)),
-                             C.byref(out), None))
+    L.check(fn(C.byref(params), C.byref(o), C.c_void_p(_stream(stream)), C.byref(out), None))
     dd = DD(out.value, params, torch.device(device))
     if not return_A:
         return dd
-    rows = sum(dd.n_gamma_in)
+    rows = sum(dd.n_rows)
     dd.close()
     A = torch.empty((dd.n_cols, rows), dtype=torch.float64, device=device)
     out = C.c_void_p(0)
-    L.check(lib.dpm_dd_build(C.byref(params), C.byref(o), C.c_void_p(_stream(stream)),
-                             C.byref(out), C.c_void_p(A.data_ptr())))
+    L.check(fn(C.byref(params), C.byref(o), C.c_void_p(_stream(stream)), C.byref(out),
+               C.c_void_p(A.data_ptr())))
     return DD(out.value, params, torch.device(device)), A.t()
 
 

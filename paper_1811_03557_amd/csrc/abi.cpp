@@ -37,8 +37,10 @@ dpm_status dd_gauss_impl(const dpm_dd* d, int l, double amp, double rate, const 
                          double* out, hipStream_t s);
 void dd_destroy(dpm_dd* d);
 double dd_sigma(const dpm_dd* d);
-dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], int32_t* n_cols,
-                        double* rmin, double* rmax);
+dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], int32_t n_rows[2],
+                        int32_t* n_cols, double* rmin, double* rmax);
+dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStream_t s,
+                          dpm_dd** out, double* A_out);
 }  // namespace dpm
 
 using namespace dpm;
@@ -354,11 +356,44 @@ dpm_status dpm_dd_build(const dpm_dd_params* params, const dpm_opts* opts, void*
   return dd_build_impl(p, *opts, static_cast<hipStream_t>(stream), out, A_out);
 }
 
+dpm_status dpm_dd2_build(const dpm_dd2_params* params, const dpm_opts* opts, void* stream,
+                         dpm_dd** out, double* A_out) {
+  clear_error();
+  if (!params || !out) { set_error("NULL argument"); return DPM_EINVAL; }
+  *out = nullptr;
+  const dpm_dd2_params& p = *params;
+  for (const dpm_grid* g : {&p.grid1, &p.grid2}) {
+    DPM_TRY(validate_grid(g));
+    DPM_TRY(validate_opts(*g, opts));
+  }
+  if (!opts->io_fp64) { set_error("the boundary matrix needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
+  if (p.grid1.sigma != p.grid2.sigma) { set_error("both meshes need the same sigma (= 1/dt)"); return DPM_EINVAL; }
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(p.origin1[i]) || !std::isfinite(p.origin2[i])) { set_error("origins must be finite"); return DPM_EINVAL; }
+  if (!(p.r_gamma > 0.0) || !(p.r_z > 0.0) || !std::isfinite(p.r_gamma) || !std::isfinite(p.r_z) ||
+      !std::isfinite(p.q_z) || !(std::fabs(p.q_z) - p.r_z < p.r_gamma) || !(p.r_gamma < std::fabs(p.q_z) + p.r_z) ||
+      !(p.q_z > 0.0)) {
+    set_error("the radii must satisfy q_z > 0 and q_z - r_z < r_gamma < q_z + r_z (Z meets Gamma)");
+    return DPM_EINVAL;
+  }
+  if (!(p.eps_layers > 0.0) || !std::isfinite(p.eps_layers)) { set_error("eps_layers must be finite and > 0"); return DPM_EINVAL; }
+  if (p.m_gamma < 0 || p.m_z < 0 || (p.beta != 0 && p.beta != 1)) {
+    set_error("m_gamma, m_z must be >= 0 and beta 0 or 1");
+    return DPM_EINVAL;
+  }
+  if ((p.beta + 1) * (p.m_gamma + 1) + 3 * (p.m_z + 1) > 1024) {
+    set_error("more than 1024 columns");
+    return DPM_EINVAL;
+  }
+  return dd2_build_impl(p, *opts, static_cast<hipStream_t>(stream), out, A_out);
+}
+
 dpm_status dpm_dd_info(const dpm_dd* dd, int32_t n_gamma[2], int32_t n_gamma_in[2],
-                       int32_t* n_cols, double* min_abs_rdiag, double* max_abs_rdiag) {
+                       int32_t n_rows[2], int32_t* n_cols, double* min_abs_rdiag,
+                       double* max_abs_rdiag) {
   clear_error();
   if (!dd) { set_error("dd is NULL"); return DPM_EINVAL; }
-  return dd_info_impl(dd, n_gamma, n_gamma_in, n_cols, min_abs_rdiag, max_abs_rdiag);
+  return dd_info_impl(dd, n_gamma, n_gamma_in, n_rows, n_cols, min_abs_rdiag, max_abs_rdiag);
 }
 
 dpm_status dpm_dd_masks(const dpm_dd* dd, int32_t l, uint8_t* m_plus, uint8_t* n_plus,

@@ -31,6 +31,11 @@ struct dpm_dd {
   double* tau = nullptr;  // n_cols
   double* P = nullptr;    // n_cols x rows least-squares operator (row nu contiguous)
   double rdiag_min = 0.0, rdiag_max = 0.0;
+  int kind = 1;                       // 1: Z inside Omega; 2: Z meets Gamma
+  int c_off[2] = {0, 0};              // first coefficient of each subdomain's densities
+  int m_rows[2] = {0, 0};             // reduced-BEP rows of each subdomain
+  int32_t* row_idx[2] = {nullptr, nullptr};  // linear node index of each row (Case 2: owned)
+  double origin[2][3] = {{0, 0, 0}, {0, 0, 0}};  // added to the node coordinates of each mesh
   // Omega_2's share of a step runs on a second stream of the handle, forked from and joined to
   // the caller's stream by events, so that the two meshes' solves overlap
   hipStream_t side = nullptr;
@@ -133,7 +138,8 @@ __global__ void k_dd_stack(const double* __restrict__ A0, int m0, const double* 
   }
 }
 
-// g[r] = [Tr_zeta_1,in X_1[r] ; Tr_gamma_2,in X_2[r]] for the two species r = blockIdx.y
+// g[r] = [X_1[r] at Omega_1's rows ; X_2[r] at Omega_2's rows] for the two species r =
+// blockIdx.y (the rows are the reduced-BEP equations: gamma_in nodes, twice at wedge nodes)
 __global__ void k_dd_gather(const double* __restrict__ X0, long long v0,
                             const int32_t* __restrict__ idx0, int m0,
                             const double* __restrict__ X1, long long v1,
@@ -146,16 +152,159 @@ __global__ void k_dd_gather(const double* __restrict__ X0, long long v0,
 }
 
 // amp exp(-rate |x - c0|^2) at the nodes of N+, zero elsewhere
-__global__ void k_dd_gauss(const uint8_t* __restrict__ np, int n, double h, double x0, double amp,
-                           double rate, double cx, double cy, double cz, double* __restrict__ out) {
+__global__ void k_dd_gauss(const uint8_t* __restrict__ np, int n, double h, double x0, double ox,
+                           double oy, double oz, double amp, double rate, double cx, double cy,
+                           double cz, double* __restrict__ out) {
   const long long vol = (long long)n * n * n;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < vol;
        i += (long long)gridDim.x * blockDim.x) {
     const int ix = (int)(i % n);
     const int iy = (int)((i / n) % n);
     const int iz = (int)(i / ((long long)n * n));
-    const double px = x0 + h * ix - cx, py = x0 + h * iy - cy, pz = x0 + h * iz - cz;
+    const double px = x0 + h * ix + ox - cx, py = x0 + h * iy + oy - cy, pz = x0 + h * iz + oz - cz;
     out[i] = np[i] ? amp * exp(-rate * (px * px + py * py + pz * pz)) : 0.0;
+  }
+}
+
+// ---- Case 2: Z, the sphere |x - q| = r_z about q = (0, 0, q_z), meets Gamma = {|x| = r_g} ----
+
+struct Case2Geo {
+  double r_g2;            // r_gamma^2
+  double qz, rz, rz2;
+  double ox, oy, oz;      // origin of the mesh
+  int l;                  // subdomain: 0 the cap |x - q| < r_z, 1 the rest
+};
+
+__device__ __forceinline__ bool c2_ball(const Case2Geo& G, double X, double Y, double Z) {
+  return X * X + Y * Y + Z * Z < G.r_g2;
+}
+__device__ __forceinline__ bool c2_zset(const Case2Geo& G, double X, double Y, double Z) {
+  const double q2 = X * X + Y * Y + (Z - G.qz) * (Z - G.qz);
+  return G.l == 0 ? q2 < G.rz2 : q2 > G.rz2;
+}
+
+// M+ of subdomain l: inside Gamma and on its side of Z (nodes exactly on Z in neither)
+__global__ void k_dd2_classify(int n, double h, double x0, Case2Geo G, uint8_t* __restrict__ m) {
+  const long long vol = (long long)n * n * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < vol;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i % n);
+    const int iy = (int)((i / n) % n);
+    const int iz = (int)(i / ((long long)n * n));
+    const double X = x0 + h * ix + G.ox, Y = x0 + h * iy + G.oy, Z = x0 + h * iz + G.oz;
+    m[i] = (c2_ball(G, X, Y, Z) && c2_zset(G, X, Y, Z)) ? 1 : 0;
+  }
+}
+
+// Whether node (ix, iy, iz) lies on the discrete grid boundary of the set given by the predicate
+// (a node of the set with a neighbour in the cube outside it, or the converse)
+template <bool ZSET>
+__device__ bool c2_on_boundary(const Case2Geo& G, int n, double h, double x0, int ix, int iy,
+                               int iz) {
+  auto in = [&](int a, int b, int c) {
+    const double X = x0 + h * a + G.ox, Y = x0 + h * b + G.oy, Z = x0 + h * c + G.oz;
+    return ZSET ? c2_zset(G, X, Y, Z) : c2_ball(G, X, Y, Z);
+  };
+  const bool self = in(ix, iy, iz);
+  const int d[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+  for (int k = 0; k < 6; ++k) {
+    const int a = ix + d[k][0], b = iy + d[k][1], c = iz + d[k][2];
+    if (a < 0 || a >= n || b < 0 || b >= n || c < 0 || c >= n) continue;
+    if (in(a, b, c) != self) return true;
+  }
+  return false;
+}
+
+// Parts and effective densities of subdomain l's gamma nodes.  part bit 0: gamma_l (on the
+// discrete boundary of the ball and the polar angle theta of the projection onto Gamma in the
+// subdomain's window), bit 1: zeta_l (on the discrete boundary of the Z side and the angle psi of
+// the projection onto Z, measured at q from the direction towards the origin, at most
+// psi* + eps_z).  Rows of basis: Gamma part P_nu(cos theta), beta (d_G^2/2) P_nu, then Z part
+// P_nu(cos psi), d_Z P_nu, (d_Z^2/2) P_nu, each scaled by 1/(number of parts) where the node is
+// in that part, zero where it is not.  *uncovered counts nodes in no part.
+__global__ void k_dd2_basis(int n, double h, double x0, Case2Geo G, int ng,
+                            const int32_t* __restrict__ idx, double r_g, int m_gamma, int beta,
+                            int m_z, double theta_win, double psi_win,
+                            double* __restrict__ basis, uint8_t* __restrict__ part,
+                            int* __restrict__ uncovered) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ng) return;
+  const long long li = idx[i];
+  const int ix = (int)(li % n);
+  const int iy = (int)((li / n) % n);
+  const int iz = (int)(li / ((long long)n * n));
+  const double X = x0 + h * ix + G.ox, Y = x0 + h * iy + G.oy, Z = x0 + h * iz + G.oz;
+  const double rho = sqrt(X * X + Y * Y);
+  const double rr = sqrt(X * X + Y * Y + Z * Z);
+  const double rq = sqrt(X * X + Y * Y + (Z - G.qz) * (Z - G.qz));
+  const double theta = atan2(rho, Z), psi = atan2(rho, G.qz - Z);
+  const bool win_g = G.l == 0 ? theta <= theta_win : theta >= theta_win;
+  const bool in_g = win_g && c2_on_boundary<false>(G, n, h, x0, ix, iy, iz);
+  const bool in_z = psi <= psi_win && c2_on_boundary<true>(G, n, h, x0, ix, iy, iz);
+  const int k = (int)in_g + (int)in_z;
+  part[i] = (uint8_t)((in_g ? 1 : 0) | (in_z ? 2 : 0));
+  if (k == 0) atomicAdd(uncovered, 1);
+  const double w = k == 2 ? 0.5 : 1.0;
+  const double wg = in_g ? w : 0.0, wz = in_z ? w : 0.0;
+  const long long ngl = ng;
+  {
+    const int nz = m_gamma + 1;
+    const double x = cos(theta);
+    const double dg = rr - r_g, hd2 = 0.5 * dg * dg;
+    double pm1 = 0.0, p = 1.0;
+    for (int nu = 0; nu <= m_gamma; ++nu) {
+      basis[nu * ngl + i] = p * wg;
+      if (beta) basis[(nz + nu) * ngl + i] = hd2 * p * wg;
+      const double pn = ((2.0 * nu + 1.0) * x * p - nu * pm1) / (nu + 1.0);
+      pm1 = p;
+      p = pn;
+    }
+  }
+  {
+    const int row = (beta + 1) * (m_gamma + 1);
+    const int nz = m_z + 1;
+    const double x = cos(psi);
+    const double dz = rq - G.rz, hd2 = 0.5 * dz * dz;
+    double pm1 = 0.0, p = 1.0;
+    for (int nu = 0; nu <= m_z; ++nu) {
+      basis[(row + nu) * ngl + i] = p * wz;
+      basis[(row + nz + nu) * ngl + i] = dz * p * wz;
+      basis[(row + 2 * nz + nu) * ngl + i] = hd2 * p * wz;
+      const double pn = ((2.0 * nu + 1.0) * x * p - nu * pm1) / (nu + 1.0);
+      pm1 = p;
+      p = pn;
+    }
+  }
+}
+
+// Rows [r0, r0 + nr) of the stacked matrix from subdomain l's columns A_l = B_eff|gamma_in -
+// Tr P B_eff (n_in x n_cols, column-major) and effective densities B_eff (n_cols x n_gamma): a
+// row of part Gamma (Z) at gamma_in node i (gamma position j) is -Tr_i P B_eff plus the node's
+// own, unscaled Gamma (Z) densities.  row_node: i | part << 30.
+__global__ void k_dd2_stack(const double* __restrict__ Al, int n_in, const double* __restrict__ B,
+                            int ng, const int32_t* __restrict__ pos_in,
+                            const uint8_t* __restrict__ part, const int32_t* __restrict__ row_node,
+                            int nr, int ng_cols, int n_cols, int r0, int M,
+                            double* __restrict__ A) {
+  const long long tot = (long long)nr * n_cols;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int nu = (int)(e / nr);
+    const int r = (int)(e - (long long)nu * nr);
+    const int code = row_node[r];
+    const int i = code & 0x3fffffff, zpart = code >> 30;
+    const int j = pos_in[i];
+    const int k = (part[j] & 1) + ((part[j] >> 1) & 1);
+    const bool own = zpart ? nu >= ng_cols : nu < ng_cols;
+    const double a = Al[(long long)nu * n_in + i];
+    double v;
+    if (own && k == 1)
+      v = a;  // the effective density is the node's own: A_l's row as it is
+    else {
+      const double b = B[(long long)nu * ng + j];
+      v = a - b + (own ? k * b : 0.0);
+    }
+    A[(long long)nu * M + r0 + r] = v;
   }
 }
 
@@ -197,6 +346,8 @@ dpm_status dd_solve_ws(const dpm_dd* d, const dpm_opts& o, size_t* bytes) {
 
 void dd_destroy(dpm_dd* d) {
   if (!d) return;
+  if (d->kind == 2)
+    for (int32_t* p : d->row_idx) (void)hipFree(p);
   for (hipEvent_t e : d->ev)
     if (e) (void)hipEventDestroy(e);
   if (d->side) (void)hipStreamDestroy(d->side);
@@ -273,6 +424,12 @@ dpm_status dd_build_impl(const dpm_dd_params& prm, const dpm_opts& o, hipStream_
   }
   const int m0 = d->sub[0]->n_in, m1 = d->sub[1]->n_in;
   d->rows = m0 + m1;
+  d->kind = 1;
+  d->c_off[0] = d->n_gamma_cols;
+  for (int l = 0; l < 2; ++l) {
+    d->m_rows[l] = d->sub[l]->n_in;
+    d->row_idx[l] = d->sub[l]->idx_in;  // every gamma_in node once, owned by the subdomain
+  }
   if (d->n_cols > d->rows) {
     set_error("dpm_dd_build: %d columns exceed the %d rows of the coupled BEP", d->n_cols, d->rows);
     return fail(DPM_ERANK);
@@ -303,13 +460,181 @@ dpm_status dd_build_impl(const dpm_dd_params& prm, const dpm_opts& o, hipStream_
   return DPM_OK;
 }
 
+dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStream_t s,
+                          dpm_dd** out, double* A_out) {
+  dpm_dd* d = new dpm_dd();
+  d->kind = 2;
+  d->n_gamma_cols = (prm.beta + 1) * (prm.m_gamma + 1);
+  d->n_z_cols = 3 * (prm.m_z + 1);
+  d->n_cols = d->n_gamma_cols + d->n_z_cols;
+  d->prm.grid1 = prm.grid1;
+  d->prm.grid2 = prm.grid2;
+  auto fail = [&](dpm_status st) {
+    dd_destroy(d);
+    return st;
+  };
+  if (hipStreamCreateWithFlags(&d->side, hipStreamNonBlocking) != hipSuccess) {
+    set_error("dpm_dd2_build: stream creation failed");
+    return fail(DPM_EHIP);
+  }
+  for (hipEvent_t& e : d->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      set_error("dpm_dd2_build: event creation failed");
+      return fail(DPM_EHIP);
+    }
+  // the circle where Z meets Gamma
+  const double rg = prm.r_gamma, qz = prm.q_z, rz = prm.r_z;
+  const double z_star = (rg * rg + qz * qz - rz * rz) / (2.0 * qz);
+  const double theta_star = std::acos(z_star / rg), psi_star = std::acos((qz - z_star) / rz);
+  uint8_t* parts[2] = {nullptr, nullptr};
+  auto free_parts = [&]() { (void)hipFree(parts[0]); (void)hipFree(parts[1]); };
+  for (int l = 0; l < 2; ++l) {
+    const dpm_grid& g = l == 0 ? prm.grid1 : prm.grid2;
+    const double* org = l == 0 ? prm.origin1 : prm.origin2;
+    for (int a = 0; a < 3; ++a) d->origin[l][a] = org[a];
+    Case2Geo G{rg * rg, qz, rz, rz * rz, org[0], org[1], org[2], l};
+    const long long vsz = (long long)g.n * g.n * g.n;
+    uint8_t* m = nullptr;
+    int32_t* idx = nullptr;
+    uint8_t* is_in = nullptr;
+    double* basis = nullptr;
+    int* unc = nullptr;
+    auto release = [&]() {
+      (void)hipFree(m); (void)hipFree(idx); (void)hipFree(is_in); (void)hipFree(basis);
+      (void)hipFree(unc);
+    };
+    if (hipMalloc(&m, vsz) != hipSuccess || hipMalloc(&unc, sizeof(int)) != hipSuccess) {
+      release(); free_parts();
+      set_error("dpm_dd2_build: device allocation failed");
+      return fail(DPM_ENOMEM);
+    }
+    hipLaunchKernelGGL(k_dd2_classify, dim3(blocks_for(vsz)), dim3(kB), 0, s, g.n, g.h, g.x0, G, m);
+    int32_t ng = 0, nin = 0;
+    dpm_status st = gamma_points_impl(g, m, &ng, &nin, nullptr, nullptr, s);
+    if (st != DPM_OK) { release(); free_parts(); return fail(st); }
+    const int nb = d->n_cols;
+    if (hipMalloc(&idx, sizeof(int32_t) * ng) != hipSuccess || hipMalloc(&is_in, ng) != hipSuccess ||
+        hipMalloc(&basis, sizeof(double) * (size_t)nb * ng) != hipSuccess ||
+        hipMalloc(&parts[l], ng) != hipSuccess) {
+      release(); free_parts();
+      set_error("dpm_dd2_build: device allocation failed");
+      return fail(DPM_ENOMEM);
+    }
+    st = gamma_points_impl(g, m, &ng, &nin, idx, is_in, s);
+    if (st != DPM_OK) { release(); free_parts(); return fail(st); }
+    const double eps = prm.eps_layers * g.h;
+    const double theta_win = l == 0 ? theta_star + eps / rg : theta_star - eps / rg;
+    const double psi_win = psi_star + eps / rz;
+    int uncovered = 0;
+    hipError_t e = hipMemsetAsync(unc, 0, sizeof(int), s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_dd2_basis, dim3((ng + 127) / 128), dim3(128), 0, s, g.n, g.h, g.x0, G,
+                         ng, idx, rg, prm.m_gamma, prm.beta, prm.m_z, theta_win, psi_win, basis,
+                         parts[l], unc);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&uncovered, unc, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      release(); free_parts();
+      set_error("dpm_dd2_build: %s", hipGetErrorString(e));
+      return fail(DPM_EHIP);
+    }
+    if (uncovered > 0) {
+      release(); free_parts();
+      set_error("dpm_dd2_build: %d nodes of subdomain %d's discrete boundary lie in neither gamma_l "
+                "nor zeta_l: raise eps_layers", uncovered, l + 1);
+      return fail(DPM_EGEOM);
+    }
+    st = build_bep_impl(g, m, nb, basis, o, s, &d->sub[l], nullptr, false);
+    (void)hipStreamSynchronize(s);
+    release();
+    if (st != DPM_OK) { free_parts(); return fail(st); }
+  }
+  // rows: gamma_in nodes in ascending index, a Gamma row and then a Z row at wedge nodes
+  std::vector<int32_t> rn[2];
+  for (int l = 0; l < 2; ++l) {
+    const dpm_bep* b = d->sub[l];
+    std::vector<uint8_t> pt(b->n_gamma);
+    std::vector<int32_t> pos(b->n_in), idx_in(b->n_in);
+    hipError_t e = hipMemcpy(pt.data(), parts[l], b->n_gamma, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(pos.data(), b->pos_in, sizeof(int32_t) * b->n_in, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(idx_in.data(), b->idx_in, sizeof(int32_t) * b->n_in, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      free_parts();
+      set_error("dpm_dd2_build: %s", hipGetErrorString(e));
+      return fail(DPM_EHIP);
+    }
+    std::vector<int32_t> ridx;
+    for (int i = 0; i < b->n_in; ++i) {
+      const uint8_t p = pt[pos[i]];
+      if (p & 1) { rn[l].push_back(i); ridx.push_back(idx_in[i]); }
+      if (p & 2) { rn[l].push_back(i | (1 << 30)); ridx.push_back(idx_in[i]); }
+    }
+    d->m_rows[l] = (int)ridx.size();
+    if (hipMalloc(&d->row_idx[l], sizeof(int32_t) * (ridx.size() + 1)) != hipSuccess ||
+        hipMemcpy(d->row_idx[l], ridx.data(), sizeof(int32_t) * ridx.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      free_parts();
+      set_error("dpm_dd2_build: device allocation or copy failed");
+      return fail(DPM_ENOMEM);
+    }
+  }
+  d->rows = d->m_rows[0] + d->m_rows[1];
+  if (d->n_cols > d->rows) {
+    free_parts();
+    set_error("dpm_dd2_build: %d columns exceed the %d rows of the coupled BEP", d->n_cols, d->rows);
+    return fail(DPM_ERANK);
+  }
+  const size_t na = (size_t)d->rows * d->n_cols;
+  int32_t* drn = nullptr;
+  if (hipMalloc(&d->A, sizeof(double) * na) != hipSuccess ||
+      hipMalloc(&d->tau, sizeof(double) * d->n_cols) != hipSuccess ||
+      hipMalloc(&d->P, sizeof(double) * na) != hipSuccess ||
+      hipMalloc(&drn, sizeof(int32_t) * (size_t)d->rows) != hipSuccess) {
+    free_parts();
+    (void)hipFree(drn);
+    set_error("dpm_dd2_build: device allocation failed");
+    return fail(DPM_ENOMEM);
+  }
+  hipError_t e = hipMemcpy(drn, rn[0].data(), sizeof(int32_t) * rn[0].size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(drn + rn[0].size(), rn[1].data(), sizeof(int32_t) * rn[1].size(), hipMemcpyHostToDevice);
+  for (int l = 0; l < 2 && e == hipSuccess; ++l) {
+    const dpm_bep* b = d->sub[l];
+    const int r0 = l == 0 ? 0 : d->m_rows[0];
+    hipLaunchKernelGGL(k_dd2_stack, dim3(blocks_for((long long)d->m_rows[l] * d->n_cols)), dim3(kB),
+                       0, s, b->A, b->n_in, b->basis, b->n_gamma, b->pos_in, parts[l], drn + r0,
+                       d->m_rows[l], d->n_gamma_cols, d->n_cols, r0, d->rows, d->A);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(drn);
+  free_parts();
+  if (e != hipSuccess) {
+    set_error("dpm_dd2_build: %s", hipGetErrorString(e));
+    return fail(DPM_EHIP);
+  }
+  if (A_out && hipMemcpyAsync(A_out, d->A, sizeof(double) * na, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    set_error("dpm_dd2_build: copy of A failed");
+    return fail(DPM_EHIP);
+  }
+  {
+    const dpm_status st = lsq_factor(d->A, d->rows, d->n_cols, d->tau, d->P, s, &d->rdiag_min,
+                                     &d->rdiag_max);
+    if (st != DPM_OK) return fail(st);
+  }
+  *out = d;
+  return DPM_OK;
+}
+
 double dd_sigma(const dpm_dd* d) { return d->prm.grid1.sigma; }
 
-dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], int32_t* n_cols,
-                        double* rmin, double* rmax) {
+dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], int32_t n_rows[2],
+                        int32_t* n_cols, double* rmin, double* rmax) {
   for (int l = 0; l < 2; ++l) {
     if (n_gamma) n_gamma[l] = d->sub[l]->n_gamma;
     if (n_in) n_in[l] = d->sub[l]->n_in;
+    if (n_rows) n_rows[l] = d->m_rows[l];
   }
   if (n_cols) *n_cols = d->n_cols;
   if (rmin) *rmin = d->rdiag_min;
@@ -366,11 +691,11 @@ dpm_status dd_step_impl(const dpm_dd* d, double dt, double chi, const double* co
   const long long v0 = (long long)s0->grid.n * s0->grid.n * s0->grid.n;
   const long long v1 = (long long)s1->grid.n * s1->grid.n * s1->grid.n;
   hipLaunchKernelGGL(k_dd_gather, dim3((d->rows + kB - 1) / kB, 2), dim3(kB), 0, s, X[0], v0,
-                     s0->idx_in, s0->n_in, X[1], v1, s1->idx_in, s1->n_in, g);
+                     d->row_idx[0], d->m_rows[0], X[1], v1, d->row_idx[1], d->m_rows[1], g);
   lsq_apply(d->P, d->rows, d->n_cols, 2, g, C, s);
-  // densities: Omega_1 from the Z coefficients, Omega_2 from all of them
-  launch_density(s0, C + d->n_gamma_cols, d->n_cols, ug[0], s);
-  launch_density(s1, C, d->n_cols, ug[1], s);
+  // densities (Case 1: Omega_1 from the Z coefficients only)
+  launch_density(s0, C + d->c_off[0], d->n_cols, ug[0], s);
+  launch_density(s1, C + d->c_off[1], d->n_cols, ug[1], s);
   DPM_TRY_HIP(hipGetLastError());
   // Steps 6-7 per subdomain: Green's formula as one AP solve per species, restriction to N+
   DPM_TRY_HIP(hipEventRecord(d->ev[2], s));
@@ -400,8 +725,9 @@ dpm_status dd_gauss_impl(const dpm_dd* d, int l, double amp, double rate, const 
   const dpm_bep* b = d->sub[l];
   const dpm_grid& g = b->grid;
   const long long vsz = (long long)g.n * g.n * g.n;
+  const double* o = d->origin[l];
   hipLaunchKernelGGL(k_dd_gauss, dim3(blocks_for(vsz)), dim3(kB), 0, s, b->n_plus, g.n, g.h, g.x0,
-                     amp, rate, c0[0], c0[1], c0[2], out);
+                     o[0], o[1], o[2], amp, rate, c0[0], c0[1], c0[2], out);
   DPM_TRY_HIP(hipGetLastError());
   return DPM_OK;
 }

@@ -111,4 +111,19 @@ def test_dd_validation_without_device():
     assert lib.dpm_dd_step(None, 1e-3, 1.0, vols, vols, C.byref(o), None) == _lib.DPM_EINVAL
     assert lib.dpm_dd_masks(None, 0, fake, fake, None) == _lib.DPM_EINVAL
     assert lib.dpm_dd_gauss_state(None, 0, 1.0, 1.0, (C.c_double * 3)(0, 0, 0), fake, None) == _lib.DPM_EINVAL
-    assert lib.dpm_dd_info(None, None, None, None, None, None) == _lib.DPM_EINVAL
+    assert lib.dpm_dd_info(None, None, None, None, None, None, None) == _lib.DPM_EINVAL
+    # Case 2: Z must meet Gamma
+    g1b = _lib.Grid(15, 0.09375, 1000.0, -0.75 + 0.09375)
+
+    def build2(**kw):
+        p = dict(grid1=g1b, grid2=g2, origin1=(C.c_double * 3)(0, 0, 0.75),
+                 origin2=(C.c_double * 3)(0, 0, 0), r_gamma=1.0, q_z=1.0, r_z=0.5, eps_layers=2.0,
+                 m_gamma=4, beta=0, m_z=2)
+        p.update(kw)
+        prm = _lib.DD2Params(**p)
+        return lib.dpm_dd2_build(C.byref(prm), C.byref(o), None, C.byref(out), None)
+
+    for kw, word in [({"q_z": 2.0}, "meets"), ({"q_z": 0.3}, "meets"), ({"eps_layers": 0.0}, "eps"),
+                     ({"beta": 3}, "beta"), ({"origin1": (C.c_double * 3)(0, float("nan"), 0)}, "origins")]:
+        assert build2(**kw) == _lib.DPM_EINVAL, kw
+        assert word in lib.dpm_last_error().decode(), (kw, lib.dpm_last_error())

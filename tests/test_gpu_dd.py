@@ -1,5 +1,6 @@
 """Domain decomposition, Case 1 (Sec. 3, eqs interface_condition, reduced_DD1_BEP1,
-reduced_DD1_BEP2) through the C ABI, against the oracle (oracle/dd.py) on the same data:
+reduced_DD1_BEP2) and Case 2 (eqs DD2_BEP, reduced_DD2_BEP, effective densities) through the C
+ABI, against the oracle (oracle/dd.py) on the same data:
 
 - the point sets of both subdomains (bit-exact) and the stacked coupled-BEP matrix;
 - one step on both subdomains (forcing, particular solutions, the coupled least squares, the
@@ -139,4 +140,101 @@ def test_dd_rejects_wrong_dt_and_shapes():
         api.dd_step(dd, 2e-3, 1.0, state)
     with pytest.raises(ValueError, match="hold"):
         api.dd_step(dd, 1e-3, 1.0, state[::-1])
+    dd.close()
+
+
+# ---- Case 2: Z (radius 0.5 about the north pole) meets Gamma ---------------------------------
+# The coupled matrices here have condition numbers up to 1e6 (zonal densities on both surfaces
+# meet at the wedge), so the least-squares coefficients carry relative errors up to ~1e6 x 1e-16
+# from either side's rounding: the steps are compared at 1e-9, the matrices (no solve) at 1e-10.
+
+CASES2 = [
+    # n1, n2, m_gamma, m_z, beta (Omega_1's cube [-0.75, 0.75]^2 x [0, 1.5])
+    (15, 31, 4, 2, 0),    # the same spacing on both meshes, 2-term extension on Gamma
+    (31, 31, 6, 3, 1),    # Omega_1's mesh twice as fine, 3-term extension on Gamma
+    (63, 31, 2, 2, 0),    # four times as fine
+]
+
+
+def _params2(case, sigma):
+    from paper_1811_03557_amd import api
+    s1, s2 = case.sub
+    return api.dd2_params(case.n1, s1["h"], s1["x0"], (0.0, 0.0, s1["zc"]), case.n2, s2["h"],
+                          s2["x0"], (0.0, 0.0, 0.0), sigma, 1.0, case.q_z, case.r_z, 2.0,
+                          case.m_gamma, case.beta, case.m_z)
+
+
+def _data2(mesh, ps):
+    z, y, x = mesh
+    r2 = x * x + y * y + (z - 0.5) ** 2
+    return (np.where(ps.n_plus, 10 * np.exp(-2 * r2), 0.0),
+            np.where(ps.n_plus, 5 * np.exp(-r2), 0.0))
+
+
+@pytest.mark.parametrize("n1,n2,mg,mz,beta", CASES2)
+def test_dd2_matrix_and_point_sets(n1, n2, mg, mz, beta):
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case = odd.DDCase2(n1, 0.75, 0.75, n2, 1.0, 0.5, mg, mz, beta=beta)
+    assert case.covered
+    dt = 1e-3
+    say(f"dd2 matrix n1={n1} n2={n2} mg={mg} mz={mz} beta={beta}")
+    dd, A = api.dd_build(_params2(case, 1.0 / dt), return_A=True, device=dev)
+    for l, s in enumerate(case.sub):
+        mp, np_ = dd.masks(l)
+        assert np.array_equal(mp.cpu().numpy().astype(bool), s["ps"].m_plus)
+        assert np.array_equal(np_.cpu().numpy().astype(bool), s["ps"].n_plus)
+        assert dd.n_gamma_in[l] == s["ps"].n_gamma_in and dd.n_rows[l] == len(s["rows"])
+    ref = odd.dd2_matrix(case, 1.0 / dt)
+    assert A.shape == ref.shape
+    err = np.max(np.abs(A.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    say(f"  rows {ref.shape[0]}, cols {ref.shape[1]}, rel err {err:.2e}")
+    assert err <= 1e-10
+    dd.close()
+
+
+@pytest.mark.parametrize("n1,n2,mg,mz,beta", CASES2)
+def test_dd2_step_matches_oracle(n1, n2, mg, mz, beta):
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case = odd.DDCase2(n1, 0.75, 0.75, n2, 1.0, 0.5, mg, mz, beta=beta)
+    dt, chi = 1e-3, 1.0
+    say(f"dd2 step n1={n1} n2={n2} mg={mg} mz={mz} beta={beta}")
+    A = odd.dd2_matrix(case, 1.0 / dt)
+    s1, s2 = case.sub
+    st = list(_data2(s1["mesh"], s1["ps"])) + list(_data2(s2["mesh"], s2["ps"]))
+    ref = odd.dd2_step(*st, case, A, dt, chi)[:4]
+    dd = api.dd_build(_params2(case, 1.0 / dt), device=dev)
+    state = [torch.from_numpy(v).to(dev) for v in st]
+    out = api.dd_step(dd, dt, chi, state)
+    for k, (g, o) in enumerate(zip(out, ref)):
+        err = np.max(np.abs(g.cpu().numpy() - o)) / np.max(np.abs(o))
+        say(f"  output {k}: rel err {err:.2e}")
+        assert err <= 1e-9, (k, err)
+    for l, s in enumerate(case.sub):
+        z, y, x = s["mesh"]
+        g0 = np.where(s["ps"].n_plus, 7.0 * np.exp(-3.0 * (x * x + y * y + (z - 0.4) ** 2)), 0.0)
+        g = dd.gauss_state(l, 7.0, 3.0, (0.0, 0.0, 0.4)).cpu().numpy()
+        assert np.max(np.abs(g - g0)) <= 1e-14 * 7.0
+    dd.close()
+
+
+def test_dd2_constant_state():
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case = odd.DDCase2(15, 0.75, 0.75, 31, 1.0, 0.5, 4, 2, beta=0)
+    dt = 0.5 * case.sub[1]["h"] ** 2
+    dd = api.dd_build(_params2(case, 1.0 / dt), device=dev)
+    say("dd2 constant state 15/31")
+    state = []
+    for s in case.sub:
+        state += [torch.from_numpy(np.where(s["ps"].n_plus, 3.0, 0.0)).to(dev),
+                  torch.from_numpy(np.where(s["ps"].n_plus, 5.0, 0.0)).to(dev)]
+    out = [v.cpu().numpy() for v in api.dd_step(dd, dt, 1.0, state)]
+    cn = (1 - dt) * 5.0 + dt * 3.0
+    for (r, c), s in ((out[:2], case.sub[0]), (out[2:], case.sub[1])):
+        assert np.allclose(r[s["ps"].n_plus], 3.0, rtol=1e-11, atol=0)
+        assert np.allclose(c[s["ps"].n_plus], cn, rtol=1e-11, atol=0)
     dd.close()
