@@ -22,7 +22,9 @@ Test B (the "test_b" object): the 500-column zonal boundary matrix at 255^3 and 
 loop from the paper's Test B data with 150 zonal harmonics at 127^3.
 Domain decomposition (the "domain_decomposition" object): Case 1 on the Test A setup, the
 ball on a 127^3 mesh and the shell on a 63^3 mesh, against the single domain at 255^3 with the
-same fine spacing: build and per-step times and their ratio.
+same fine spacing: build and per-step times and their ratio.  The "domain_decomposition_case2"
+object: Case 2 (Z meets Gamma) on the Test B setup at 127/63 (50 harmonics on Gamma, 10 on Z),
+against the single domain at 255^3.
 
 Prints one JSON line on stdout (everything else goes to stderr).
 """
@@ -352,6 +354,91 @@ def run_dd(args, dev):
     return out
 
 
+def run_dd2(args, dev):
+    """Domain decomposition, Case 2, on the paper's Test B setup (blow-up at the boundary): the
+    cap of the unit ball within 0.5 of the north pole (Z: the sphere of radius 0.5 about (0, 0, 1))
+    on a fine mesh (N1 = 127 on [-0.75, 0.75]^2 x [0, 1.5], h1 = 3/256) and the rest on a coarse
+    one (N2 = 63 on [-1.5, 1.5]^3, h2 = 4 h1); 50 zonal harmonics with the 2-term extension on
+    Gamma and 10 with the 3-term extension on Z (80 columns; the paper's 20 on Z leave the
+    coupled matrix numerically rank deficient, as Legendre polynomials of high degree are nearly
+    dependent on the arc of Z inside the ball, psi <= psi* = 75.5 degrees), parts with a
+    tolerance of 2 mesh widths; Test B data, dt = 0.5 h1^2 (c0 = 0: no CFL bound at the
+    start).  Against the single domain at N = 255 with the same 50 harmonics: Step 2 wall time
+    and the per-step time (eager steps, FP64)."""
+    import torch
+    from paper_1811_03557_amd import api
+    n1, n2 = 127, 63
+    h1, h2 = 1.5 / (n1 + 1), 3.0 / (n2 + 1)
+    dt = 0.5 * h1 * h1
+    prm = api.dd2_params(n1, h1, -0.75 + h1, (0.0, 0.0, 0.75), n2, h2, -1.5 + h2, (0.0, 0.0, 0.0),
+                         1.0 / dt, 1.0, 1.0, 0.5, 2.0, 49, 0, 9)
+    api.dd_build(prm, device=dev).close()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    dd = api.dd_build(prm, device=dev)
+    torch.cuda.synchronize()
+    build_dd = time.perf_counter() - t
+    state = []
+    for l in (0, 1):
+        state += [dd.gauss_state(l, 2000.0, 100.0, (0.0, 0.0, 0.25)),
+                  torch.zeros((dd.n[l],) * 3, dtype=torch.float64, device=dev)]
+    ws = torch.empty(dd.workspace_size(api.opts("fp64")), dtype=torch.uint8, device=dev)
+    steps = args.dd_steps
+    for _ in range(2):
+        api.dd_step(dd, dt, 1.0, state, out=state, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        api.dd_step(dd, dt, 1.0, state, out=state, workspace=ws)
+    torch.cuda.synchronize()
+    t_dd = (time.perf_counter() - t) / steps
+    finite = all(bool(torch.isfinite(v).all()) for v in state)
+    out = {"workload": "Test B data; cap |x - (0,0,1)| < 0.5 of the unit ball at N1 = 127 "
+                       "(h1 = 3/256) + the rest at N2 = 63 (h2 = 3/64); 50 zonal harmonics "
+                       "(2-term) on Gamma, 10 (3-term) on Z; dt = 0.5 h1^2; single domain at "
+                       "N = 255 with 50 harmonics for comparison",
+           "dd2_127_63": {"columns": dd.n_cols, "rows": sum(dd.n_rows),
+                          "build_s": round(build_dd, 4), "ms_per_step": round(t_dd * 1e3, 3),
+                          "steps_per_s": round(1.0 / t_dd, 1), "finite": finite,
+                          "rdiag_min_over_max": float(f"{dd.rdiag[0] / dd.rdiag[1]:.3e}")}}
+    log(f"[bench] DD2 127/63: build {build_dd * 1e3:.1f} ms, {t_dd * 1e3:.3f} ms/step")
+    dd.close()
+    del state, ws
+    n = 255
+    h = 3.0 / (n + 1)
+    x0 = -1.5 + h
+    geo = api.geometry("sphere", axes=(1.0,))
+    m = api.classify(n, h, x0, geo, device=dev)
+    idx, _ = api.gamma_points(m, h, x0)
+    B, _ = api.basis_zonal(n, h, x0, geo, idx, 49, 0)
+    api.build_boundary_matrix(m, B, n, h, 1.0 / dt, x0).close()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bep = api.build_boundary_matrix(m, B, n, h, 1.0 / dt, x0)
+    torch.cuda.synchronize()
+    build_sd = time.perf_counter() - t
+    rho = api.gauss_state(bep, geo, 2000.0, 100.0, center=(0.0, 0.0, 0.25))
+    c = torch.zeros_like(rho)
+    ws = torch.empty(api.step_workspace_size(bep, api.opts("fp64")), dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        api.dpm_step(bep, dt, 1.0, rho, c, rho, c, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        api.dpm_step(bep, dt, 1.0, rho, c, rho, c, workspace=ws)
+    torch.cuda.synchronize()
+    t_sd = (time.perf_counter() - t) / steps
+    out["sd_255"] = {"columns": bep.n_basis, "rows": bep.n_gamma_in, "build_s": round(build_sd, 4),
+                     "ms_per_step": round(t_sd * 1e3, 3), "steps_per_s": round(1.0 / t_sd, 1),
+                     "finite": bool(torch.isfinite(rho).all() and torch.isfinite(c).all())}
+    out["dt"] = dt
+    out["R_S_per_step"] = round(t_sd / t_dd, 2)
+    out["R_S_build"] = round(build_sd / build_dd, 2)
+    log(f"[bench] SD 255 (50 harmonics): build {build_sd * 1e3:.1f} ms, {t_sd * 1e3:.3f} ms/step")
+    bep.close()
+    return out
+
+
 def run_boundary_matrix(args, dev):
     """Step 2 of the method at 127^3: the 242-column reduced-BEP matrix of the unit sphere
     (real Y_lm, l <= 10, beta = 1), sigma = 2/h^2, built and QR-factored by one
@@ -535,6 +622,7 @@ def main():
     adaptive = run_adaptive(args, dev) if args.adaptive_steps > 0 else None
     test_b = run_test_b(args, dev) if args.adaptive_steps > 0 and not args.no_bmat else None
     dd = run_dd(args, dev) if args.dd_steps > 0 else None
+    dd2 = run_dd2(args, dev) if args.dd_steps > 0 and not args.no_bmat else None
 
     ok = {k: v for k, v in results.items() if v["rel_err_sample"] <= args.rtol}
     best_name = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else None
@@ -580,6 +668,7 @@ def main():
         "adaptive_time_loop": adaptive,
         "test_b": test_b,
         "domain_decomposition": dd,
+        "domain_decomposition_case2": dd2,
         "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
         "alg_hbm_frac": (round(best["solves_per_s"] * 16 * vol / (HBM_PEAK_GBS * 1e9), 4)
                          if best else None),
