@@ -403,6 +403,28 @@ dpm_status dpm_dd_step(const dpm_dd* dd, double dt, double chi, const double* co
 dpm_status dpm_dd_gauss_state(const dpm_dd* dd, int32_t l, double amp, double rate,
                               const double c0[3], double* out, void* stream);
 
+/*
+ * dpm_dd_rebuild -- Step 4b on the decomposed domain: both subdomains' columns, the stacked
+ * matrix, its QR and least-squares operator again at a new sigma (= 1/dt), in place.
+ * Synchronises `stream`; allocates temporaries for the column solves.  After a failure the
+ * handle must only be destroyed.
+ */
+dpm_status dpm_dd_rebuild(dpm_dd* dd, double sigma, void* stream);
+
+/*
+ * dpm_dd_run -- the adaptive time loop (paper Algorithm "Main Steps", Steps 3-8) on the
+ * decomposed domain, state = {rho_1, c_1, rho_2, c_2} in place, from t = 0 with the handle's dt
+ * (1/sigma).  Each step: scan both subdomains (max |grad_h c_l| over M+_l, max |rho_l| over
+ * M+_l, as dpm_cfl_scan); stop if a scanned value is not finite or max |rho| over both exceeds
+ * rho_cap; dt = min(dt_prev, h_l / (6 chi max|grad_h c_l|) for l = 1, 2) (each subdomain's
+ * CFL-type bound on its own mesh); if dt < dt_prev dpm_dd_rebuild at 1/dt; one dpm_dd_step.
+ * Ends as dpm_run.  opts->workspace: at least dpm_dd_step_workspace_size + 256 bytes.  info,
+ * dt_hist, rebuilt_hist as for dpm_run (grad_max and rho_max: the larger of the two subdomains).
+ */
+dpm_status dpm_dd_run(dpm_dd* dd, const dpm_run_params* params, double* const state[4],
+                      const dpm_opts* opts, void* stream, dpm_run_info* info, double* dt_hist,
+                      uint8_t* rebuilt_hist);
+
 void dpm_dd_destroy(dpm_dd* dd);
 
 /*

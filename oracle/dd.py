@@ -243,3 +243,51 @@ def dd2_step(rho1, c1, rho2, c2, case: DDCase2, A: np.ndarray, dt: float, chi: f
         coefs.append(C)
     (r1, r2), (cc1, cc2) = out
     return r1, cc1, r2, cc2, coefs
+
+
+def dd_adaptive_run(state, case, sigma0: float, chi: float, t_final: float,
+                    rho_cap: float = np.inf, max_steps: int = 1000):
+    """Steps 3-8 on the decomposed domain (either case) from dt_0 = 1/sigma0: each subdomain's
+    CFL-type bound on its own mesh, dt the smallest of them and of the previous dt, Step 4b (a new
+    coupled matrix) when dt shrinks, Step 8 on max |rho| over both M+.  state = (rho_1, c_1,
+    rho_2, c_2).  Returns (state, summary) with the keys of pks.adaptive_run."""
+    from .pks import cfl_dt
+    if isinstance(case, DDCase2):
+        subs = [(s["ps"], s["h"]) for s in case.sub]
+        matrix, step = dd2_matrix, dd2_step
+    else:
+        subs = [(case.ps1, case.h1), (case.ps2, case.h2)]
+        matrix, step = dd_matrix, dd_step
+    state = list(state)
+    dt_prev = 1.0 / sigma0
+    A = matrix(case, sigma0)                                               # Step 2
+    t, dts, rebuilt, stop = 0.0, [], [], "max_steps"
+    rmax = 0.0
+    while True:
+        if t >= t_final:
+            stop = "t_final"
+            break
+        if len(dts) >= max_steps:
+            stop = "max_steps"
+            break
+        vals = [float(np.max(np.where(ps.m_plus, np.abs(state[2 * l]), 0.0)))
+                for l, (ps, h) in enumerate(subs)]
+        cfls = [cfl_dt(state[2 * l + 1], ps.m_plus, h, chi) for l, (ps, h) in enumerate(subs)]
+        rmax = max(vals)
+        if not all(np.isfinite(v) for v in vals) or any(np.isnan(x) for x in cfls):
+            stop = "nonfinite"
+            break
+        if rmax > rho_cap:
+            stop = "rho_cap"
+            break
+        dt = min(min(cfls), dt_prev)                                       # Step 3
+        rb = dt < dt_prev
+        if rb:                                                             # Step 4b
+            A = matrix(case, 1.0 / dt)
+        state = list(step(*state, case, A, dt, chi)[:4])                   # Steps 4a-7
+        dts.append(dt)
+        rebuilt.append(rb)
+        t += dt
+        dt_prev = dt
+    return state, {"steps": len(dts), "rebuilds": int(sum(rebuilt)), "stop": stop, "t": t,
+                   "dt": dt_prev, "rho_max": rmax, "dt_hist": dts, "rebuilt": rebuilt}

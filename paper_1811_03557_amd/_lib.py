@@ -103,6 +103,9 @@ SIGNATURES = {
     "dpm_dd_step_workspace_size": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
     "dpm_dd_step": (C.c_int, [_P, _D, _D, C.POINTER(_P), C.POINTER(_P), C.POINTER(Opts), _P]),
     "dpm_dd_gauss_state": (C.c_int, [_P, _I, _D, _D, C.POINTER(_D), _P, _P]),
+    "dpm_dd_rebuild": (C.c_int, [_P, _D, _P]),
+    "dpm_dd_run": (C.c_int, [_P, C.POINTER(RunParams), C.POINTER(_P), C.POINTER(Opts), _P,
+                             C.POINTER(RunInfo), _P, _P]),
     "dpm_dd_destroy": (None, [_P]),
     "dpm_last_error": (C.c_char_p, []),
     "dpm_timing_begin": (C.c_int, [_I, _I]),

@@ -299,6 +299,19 @@ class DD:
         L.check(L.load().dpm_dd_step_workspace_size(C.c_void_p(self.ptr), C.byref(o), C.byref(nb)))
         return int(nb.value)
 
+    def rebuild(self, sigma: float, stream=None) -> None:
+        """Step 4b: both subdomains' columns and the coupled QR again at a new sigma."""
+        L.check(L.load().dpm_dd_rebuild(C.c_void_p(self.ptr), float(sigma),
+                                        C.c_void_p(_stream(stream))))
+        self.sigma = float(sigma)
+        self._refresh()
+
+    def _refresh(self):
+        rmin, rmax = C.c_double(0), C.c_double(0)
+        L.check(L.load().dpm_dd_info(C.c_void_p(self.ptr), None, None, None, None, C.byref(rmin),
+                                     C.byref(rmax)))
+        self.rdiag = (rmin.value, rmax.value)
+
     def close(self):
         if self.ptr:
             L.load().dpm_dd_destroy(C.c_void_p(self.ptr))
@@ -370,6 +383,38 @@ def dd_step(dd: DD, dt: float, chi: float, state, out=None, prec: str = "fp64",
     L.check(L.load().dpm_dd_step(C.c_void_p(dd.ptr), float(dt), float(chi), pin, pout,
                                  C.byref(o), C.c_void_p(_stream(stream))))
     return tuple(out)
+
+
+def dd_run(dd: DD, chi: float, state, t_final: float, rho_cap: float = float("inf"),
+           max_steps: int = 1000, prec: str = "fp64", workspace: torch.Tensor | None = None,
+           stream=None) -> dict:
+    """Steps 3-8 on the decomposed domain, state = (rho_1, c_1, rho_2, c_2) in place, from
+    dt = 1/dd.sigma; the run summary as for run()."""
+    for v, n in zip(state, (dd.n[0], dd.n[0], dd.n[1], dd.n[1])):
+        if v.numel() != n ** 3:
+            raise ValueError(f"state volumes must hold {dd.n[0]}^3, {dd.n[0]}^3, {dd.n[1]}^3, "
+                             f"{dd.n[1]}^3 values")
+    o = opts(prec, True)
+    nbytes = dd.workspace_size(o) + 256
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=state[0].device)
+    o.workspace = C.c_void_p(workspace.data_ptr())
+    o.workspace_bytes = workspace.numel()
+    p = L.RunParams(float(chi), float(t_final), float(rho_cap), int(max_steps))
+    info = L.RunInfo()
+    dts = (C.c_double * max(int(max_steps), 1))()
+    rbs = (C.c_uint8 * max(int(max_steps), 1))()
+    names = ("rho_1", "c_1", "rho_2", "c_2")
+    pst = (C.c_void_p * 4)(*[_dev(v, k, torch.float64) for v, k in zip(state, names)])
+    L.check(L.load().dpm_dd_run(C.c_void_p(dd.ptr), C.byref(p), pst, C.byref(o),
+                                C.c_void_p(_stream(stream)), C.byref(info), dts, rbs))
+    k = info.steps
+    if info.rebuilds > 0:
+        dd.sigma = 1.0 / info.dt
+        dd._refresh()
+    return {"steps": k, "rebuilds": info.rebuilds, "stop": L.RUN_STOPS[info.stop], "t": info.t,
+            "dt": info.dt, "rho_max": info.rho_max, "grad_max": info.grad_max,
+            "dt_hist": [dts[i] for i in range(k)], "rebuilt": [bool(rbs[i]) for i in range(k)]}
 
 
 def bep_solve(bep: BEP, g: torch.Tensor, stream=None) -> torch.Tensor:

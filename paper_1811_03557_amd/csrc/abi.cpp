@@ -41,6 +41,10 @@ dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], in
                         int32_t* n_cols, double* rmin, double* rmax);
 dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStream_t s,
                           dpm_dd** out, double* A_out);
+dpm_status dd_rebuild_impl(dpm_dd* d, double sigma, hipStream_t s);
+dpm_status dd_run_impl(dpm_dd* d, const dpm_run_params& p, double* const state[4],
+                       const dpm_opts& o, hipStream_t s, dpm_run_info* info, double* dt_hist,
+                       uint8_t* rebuilt_hist);
 }  // namespace dpm
 
 using namespace dpm;
@@ -437,6 +441,31 @@ dpm_status dpm_dd_gauss_state(const dpm_dd* dd, int32_t l, double amp, double ra
   if (!dd || !c0 || !out) { set_error("NULL argument"); return DPM_EINVAL; }
   if (l != 0 && l != 1) { set_error("subdomain index must be 0 or 1"); return DPM_EINVAL; }
   return dd_gauss_impl(dd, l, amp, rate, c0, out, static_cast<hipStream_t>(stream));
+}
+
+dpm_status dpm_dd_rebuild(dpm_dd* dd, double sigma, void* stream) {
+  clear_error();
+  if (!dd) { set_error("dd is NULL"); return DPM_EINVAL; }
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) { set_error("sigma must be finite and > 0"); return DPM_EINVAL; }
+  return dd_rebuild_impl(dd, sigma, static_cast<hipStream_t>(stream));
+}
+
+dpm_status dpm_dd_run(dpm_dd* dd, const dpm_run_params* params, double* const state[4],
+                      const dpm_opts* opts, void* stream, dpm_run_info* info, double* dt_hist,
+                      uint8_t* rebuilt_hist) {
+  clear_error();
+  if (!dd || !params || !state || !opts) { set_error("NULL argument"); return DPM_EINVAL; }
+  for (int i = 0; i < 4; ++i)
+    if (!state[i] || !aligned_to(state[i], 8)) { set_error("volume %d is NULL or not 8-byte aligned", i); return DPM_EINVAL; }
+  if (state[0] == state[1] || state[2] == state[3]) { set_error("rho and c must be different buffers"); return DPM_EINVAL; }
+  if (!opts->io_fp64) { set_error("dpm_dd_run needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
+  if (!aligned16(opts->workspace)) { set_error("the workspace must be 16-byte aligned"); return DPM_EINVAL; }
+  if (!(params->chi >= 0.0) || !std::isfinite(params->chi)) { set_error("chi must be finite and >= 0"); return DPM_EINVAL; }
+  if (std::isnan(params->t_final) || std::isnan(params->rho_cap)) { set_error("t_final and rho_cap must not be NaN"); return DPM_EINVAL; }
+  if (params->max_steps < 0) { set_error("max_steps must be >= 0"); return DPM_EINVAL; }
+  if (!(dd_sigma(dd) > 0.0)) { set_error("the handle's sigma must be > 0 (sigma = 1/dt)"); return DPM_EINVAL; }
+  return dd_run_impl(dd, *params, state, *opts, static_cast<hipStream_t>(stream), info, dt_hist,
+                     rebuilt_hist);
 }
 
 void dpm_dd_destroy(dpm_dd* dd) { dd_destroy(dd); }

@@ -35,6 +35,8 @@ struct dpm_dd {
   int c_off[2] = {0, 0};              // first coefficient of each subdomain's densities
   int m_rows[2] = {0, 0};             // reduced-BEP rows of each subdomain
   int32_t* row_idx[2] = {nullptr, nullptr};  // linear node index of each row (Case 2: owned)
+  uint8_t* parts[2] = {nullptr, nullptr};    // Case 2: part bits of each gamma node
+  int32_t* row_code = nullptr;               // Case 2: gamma_in position | part << 30 per row
   double origin[2][3] = {{0, 0, 0}, {0, 0, 0}};  // added to the node coordinates of each mesh
   // Omega_2's share of a step runs on a second stream of the handle, forked from and joined to
   // the caller's stream by events, so that the two meshes' solves overlap
@@ -346,8 +348,11 @@ dpm_status dd_solve_ws(const dpm_dd* d, const dpm_opts& o, size_t* bytes) {
 
 void dd_destroy(dpm_dd* d) {
   if (!d) return;
-  if (d->kind == 2)
+  if (d->kind == 2) {
     for (int32_t* p : d->row_idx) (void)hipFree(p);
+    for (uint8_t* p : d->parts) (void)hipFree(p);
+    (void)hipFree(d->row_code);
+  }
   for (hipEvent_t e : d->ev)
     if (e) (void)hipEventDestroy(e);
   if (d->side) (void)hipStreamDestroy(d->side);
@@ -357,6 +362,29 @@ void dd_destroy(dpm_dd* d) {
   (void)hipFree(d->tau);
   (void)hipFree(d->P);
   delete d;
+}
+
+// The stacked matrix from the subdomains' columns (Case 1: [[0, A_1], [A_2]]; Case 2: the rows
+// of both parts), A_out (nullable) a copy before factorisation, then QR, rank test and P.
+dpm_status dd_stack_factor(dpm_dd* d, hipStream_t s, double* A_out) {
+  const size_t na = (size_t)d->rows * d->n_cols;
+  if (d->kind == 1) {
+    hipLaunchKernelGGL(k_dd_stack, dim3(blocks_for((long long)na)), dim3(kB), 0, s, d->sub[0]->A,
+                       d->sub[0]->n_in, d->sub[1]->A, d->sub[1]->n_in, d->n_gamma_cols, d->n_cols,
+                       d->A);
+  } else {
+    for (int l = 0; l < 2; ++l) {
+      const dpm_bep* b = d->sub[l];
+      const int r0 = l == 0 ? 0 : d->m_rows[0];
+      hipLaunchKernelGGL(k_dd2_stack, dim3(blocks_for((long long)d->m_rows[l] * d->n_cols)),
+                         dim3(kB), 0, s, b->A, b->n_in, b->basis, b->n_gamma, b->pos_in,
+                         d->parts[l], d->row_code + r0, d->m_rows[l], d->n_gamma_cols, d->n_cols,
+                         r0, d->rows, d->A);
+    }
+  }
+  DPM_TRY_HIP(hipGetLastError());
+  if (A_out) DPM_TRY_HIP(hipMemcpyAsync(A_out, d->A, sizeof(double) * na, hipMemcpyDeviceToDevice, s));
+  return lsq_factor(d->A, d->rows, d->n_cols, d->tau, d->P, s, &d->rdiag_min, &d->rdiag_max);
 }
 
 dpm_status dd_build_impl(const dpm_dd_params& prm, const dpm_opts& o, hipStream_t s,
@@ -441,19 +469,8 @@ dpm_status dd_build_impl(const dpm_dd_params& prm, const dpm_opts& o, hipStream_
     set_error("dpm_dd_build: device allocation failed");
     return fail(DPM_ENOMEM);
   }
-  hipLaunchKernelGGL(k_dd_stack, dim3(blocks_for((long long)na)), dim3(kB), 0, s, d->sub[0]->A,
-                     m0, d->sub[1]->A, m1, d->n_gamma_cols, d->n_cols, d->A);
-  if (hipGetLastError() != hipSuccess) {
-    set_error("dpm_dd_build: kernel launch failed");
-    return fail(DPM_EHIP);
-  }
-  if (A_out && hipMemcpyAsync(A_out, d->A, sizeof(double) * na, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-    set_error("dpm_dd_build: copy of A failed");
-    return fail(DPM_EHIP);
-  }
   {
-    const dpm_status st = lsq_factor(d->A, d->rows, d->n_cols, d->tau, d->P, s, &d->rdiag_min,
-                                     &d->rdiag_max);
+    const dpm_status st = dd_stack_factor(d, s, A_out);
     if (st != DPM_OK) return fail(st);
   }
   *out = d;
@@ -486,8 +503,8 @@ dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStrea
   const double rg = prm.r_gamma, qz = prm.q_z, rz = prm.r_z;
   const double z_star = (rg * rg + qz * qz - rz * rz) / (2.0 * qz);
   const double theta_star = std::acos(z_star / rg), psi_star = std::acos((qz - z_star) / rz);
-  uint8_t* parts[2] = {nullptr, nullptr};
-  auto free_parts = [&]() { (void)hipFree(parts[0]); (void)hipFree(parts[1]); };
+  uint8_t** parts = d->parts;  // kept for rebuilds; freed with the handle
+  auto free_parts = [&]() {};
   for (int l = 0; l < 2; ++l) {
     const dpm_grid& g = l == 0 ? prm.grid1 : prm.grid2;
     const double* org = l == 0 ? prm.origin1 : prm.origin2;
@@ -586,45 +603,38 @@ dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStrea
     return fail(DPM_ERANK);
   }
   const size_t na = (size_t)d->rows * d->n_cols;
-  int32_t* drn = nullptr;
   if (hipMalloc(&d->A, sizeof(double) * na) != hipSuccess ||
       hipMalloc(&d->tau, sizeof(double) * d->n_cols) != hipSuccess ||
       hipMalloc(&d->P, sizeof(double) * na) != hipSuccess ||
-      hipMalloc(&drn, sizeof(int32_t) * (size_t)d->rows) != hipSuccess) {
-    free_parts();
-    (void)hipFree(drn);
+      hipMalloc(&d->row_code, sizeof(int32_t) * (size_t)d->rows) != hipSuccess) {
     set_error("dpm_dd2_build: device allocation failed");
     return fail(DPM_ENOMEM);
   }
+  int32_t* drn = d->row_code;
   hipError_t e = hipMemcpy(drn, rn[0].data(), sizeof(int32_t) * rn[0].size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(drn + rn[0].size(), rn[1].data(), sizeof(int32_t) * rn[1].size(), hipMemcpyHostToDevice);
-  for (int l = 0; l < 2 && e == hipSuccess; ++l) {
-    const dpm_bep* b = d->sub[l];
-    const int r0 = l == 0 ? 0 : d->m_rows[0];
-    hipLaunchKernelGGL(k_dd2_stack, dim3(blocks_for((long long)d->m_rows[l] * d->n_cols)), dim3(kB),
-                       0, s, b->A, b->n_in, b->basis, b->n_gamma, b->pos_in, parts[l], drn + r0,
-                       d->m_rows[l], d->n_gamma_cols, d->n_cols, r0, d->rows, d->A);
-    e = hipGetLastError();
-  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(drn);
-  free_parts();
   if (e != hipSuccess) {
     set_error("dpm_dd2_build: %s", hipGetErrorString(e));
     return fail(DPM_EHIP);
   }
-  if (A_out && hipMemcpyAsync(A_out, d->A, sizeof(double) * na, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-    set_error("dpm_dd2_build: copy of A failed");
-    return fail(DPM_EHIP);
-  }
   {
-    const dpm_status st = lsq_factor(d->A, d->rows, d->n_cols, d->tau, d->P, s, &d->rdiag_min,
-                                     &d->rdiag_max);
+    const dpm_status st = dd_stack_factor(d, s, A_out);
     if (st != DPM_OK) return fail(st);
   }
   *out = d;
   return DPM_OK;
+}
+
+dpm_status dd_rebuild_impl(dpm_dd* d, double sigma, hipStream_t s) {
+  d->prm.grid1.sigma = sigma;
+  d->prm.grid2.sigma = sigma;
+  for (int l = 0; l < 2; ++l) {
+    d->sub[l]->grid.sigma = sigma;
+    DPM_TRY(bep_columns(d->sub[l], s));
+  }
+  return dd_stack_factor(d, s, nullptr);
 }
 
 double dd_sigma(const dpm_dd* d) { return d->prm.grid1.sigma; }
@@ -709,6 +719,68 @@ dpm_status dd_step_impl(const dpm_dd* d, double dt, double chi, const double* co
   }
   DPM_TRY_HIP(hipEventRecord(d->ev[3], d->side));
   DPM_TRY_HIP(hipStreamWaitEvent(s, d->ev[3], 0));
+  return DPM_OK;
+}
+
+// The adaptive loop of the paper's algorithm on the decomposed domain: the CFL-type bound of
+// each subdomain on its own mesh (h_l / (6 chi max|grad_h c_l|)), the smaller of the two, Step 4b
+// rebuilds of both subdomains' columns and of the coupled QR when dt shrinks, Step 8 on
+// max |rho| over both M+.
+dpm_status dd_run_impl(dpm_dd* d, const dpm_run_params& p, double* const state[4],
+                       const dpm_opts& o, hipStream_t s, dpm_run_info* info, double* dt_hist,
+                       uint8_t* rebuilt_hist) {
+  size_t need = 0;
+  DPM_TRY(dd_step_workspace_impl(d, o, &need));
+  const size_t scan_off = align_up(need, 256);
+  if (o.workspace == nullptr || o.workspace_bytes < scan_off + 4 * sizeof(double)) {
+    set_error("dpm_dd_run: workspace too small: %zu bytes given, %zu needed", o.workspace_bytes,
+              scan_off + 4 * sizeof(double));
+    return DPM_EINVAL;
+  }
+  double* scan = reinterpret_cast<double*>(static_cast<char*>(o.workspace) + scan_off);
+  dpm_run_info r{};
+  r.stop = DPM_RUN_MAXSTEPS;
+  double t = 0.0, dt_prev = 1.0 / d->prm.grid1.sigma;
+  const double* in[4] = {state[0], state[1], state[2], state[3]};
+  for (;;) {
+    if (t >= p.t_final) { r.stop = DPM_RUN_TFINAL; break; }
+    if (r.steps >= p.max_steps) { r.stop = DPM_RUN_MAXSTEPS; break; }
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int l = 0; l < 2; ++l) DPM_TRY(cfl_scan_impl(d->sub[l], state[2 * l], state[2 * l + 1], scan + 2 * l, s));
+    DPM_TRY_HIP(hipMemcpyAsync(v, scan, sizeof(v), hipMemcpyDeviceToHost, s));
+    DPM_TRY_HIP(hipStreamSynchronize(s));
+    r.grad_max = std::fmax(v[0], v[2]);
+    r.rho_max = std::fmax(v[1], v[3]);
+    bool finite = true;
+    for (double x : v) finite = finite && std::isfinite(x);
+    if (!finite) {
+      r.grad_max = r.rho_max = NAN;
+      r.stop = DPM_RUN_NONFINITE;
+      break;
+    }
+    if (r.rho_max > p.rho_cap) { r.stop = DPM_RUN_RHOCAP; break; }
+    double dt = dt_prev;
+    for (int l = 0; l < 2; ++l)
+      if (v[2 * l] > 0.0) {
+        const double dt_cfl = d->sub[l]->grid.h / (6.0 * p.chi * v[2 * l]);
+        if (dt_cfl < dt) dt = dt_cfl;
+      }
+    const bool rebuild = dt < dt_prev;
+    if (rebuild) {
+      DPM_TRY(dd_rebuild_impl(d, 1.0 / dt, s));
+      ++r.rebuilds;
+    }
+    DPM_TRY(dd_step_impl(d, dt, p.chi, in, state, o, s));
+    if (dt_hist) dt_hist[r.steps] = dt;
+    if (rebuilt_hist) rebuilt_hist[r.steps] = rebuild ? 1 : 0;
+    ++r.steps;
+    t += dt;
+    dt_prev = dt;
+  }
+  DPM_TRY_HIP(hipStreamSynchronize(s));
+  r.t = t;
+  r.dt = dt_prev;
+  if (info) *info = r;
   return DPM_OK;
 }
 

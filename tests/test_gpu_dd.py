@@ -238,3 +238,74 @@ def test_dd2_constant_state():
         assert np.allclose(r[s["ps"].n_plus], 3.0, rtol=1e-11, atol=0)
         assert np.allclose(c[s["ps"].n_plus], cn, rtol=1e-11, atol=0)
     dd.close()
+
+
+def _adaptive_compare(res, ref, out, ref_state):
+    assert res["stop"] == ref["stop"] and res["steps"] == ref["steps"]
+    assert res["rebuilt"] == ref["rebuilt"]
+    for a, b in zip(res["dt_hist"], ref["dt_hist"]):
+        assert abs(a - b) <= 1e-10 * b, (a, b)
+    for k, (g, o) in enumerate(zip(out, ref_state)):
+        # scale by the largest entry (a state left at zero must come back exactly zero)
+        err = np.max(np.abs(g.cpu().numpy() - o)) / max(np.max(np.abs(o)), 1e-300)
+        assert err <= 1e-9, (k, err)
+
+
+def test_dd_adaptive_run_rebuilds():
+    """Case 1, rho of Test A with c0 = 0 and chi = 1000 from dt0 = 1e-3: the gradient of c grows
+    every step, each subdomain's CFL-type bound shrinks dt and the coupled matrix is rebuilt;
+    the same decisions and states as the oracle's loop."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case = odd.DDCase(15, 0.75, 31, 0.5, 1, 1, 1)
+    dt0, chi, steps = 1e-3, 1000.0, 5
+    st = []
+    for mesh, ps in ((case.mesh1, case.ps1), (case.mesh2, case.ps2)):
+        z, y, x = mesh
+        st += [np.where(ps.n_plus, 1000.0 * np.exp(-100.0 * (x * x + y * y + z * z)), 0.0),
+               np.zeros_like(x)]
+    say(f"dd adaptive run 15/31 chi={chi} steps={steps}")
+    ref_state, ref = odd.dd_adaptive_run(st, case, 1.0 / dt0, chi, 1.0, max_steps=steps)
+    assert ref["rebuilt"][1:] == [True] * (steps - 1)
+    for a, b in zip(ref["dt_hist"][1:], ref["dt_hist"][2:]):
+        assert b < a * (1 - 1e-3)
+    dd = api.dd_build(_params(case, 1.0 / dt0, 1, 1, 1), device=dev)
+    state = [torch.from_numpy(v).to(dev) for v in st]
+    res = api.dd_run(dd, chi, state, t_final=1.0, max_steps=steps)
+    say(f"  rebuilds {res['rebuilds']}, dt {res['dt_hist'][0]:.3e} .. {res['dt']:.3e}")
+    _adaptive_compare(res, ref, state, ref_state)
+    # the handle holds the last dt's matrix: a step with it matches a fresh build's
+    fresh = api.dd_build(_params(case, dd.sigma, 1, 1, 1), device=dev)
+    a = api.dd_step(dd, 1.0 / dd.sigma, chi, state)
+    b = api.dd_step(fresh, 1.0 / dd.sigma, chi, state)
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+    dd.close()
+    fresh.close()
+
+
+def test_dd2_adaptive_run_test_b():
+    """Case 2 with Test B data (rho0 = 2000 exp(-100 (x^2 + y^2 + (z - 0.25)^2)), c0 = 0) from
+    dt0 = 0.5 h^2 against the oracle's loop (a rebuild at step 2, when c has grown), and the
+    Step 8 stop at a threshold below the initial max |rho| (1814 at these nodes)."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case = odd.DDCase2(15, 0.75, 0.75, 31, 1.0, 0.5, 4, 2, beta=0)
+    dt0 = 0.5 * case.sub[1]["h"] ** 2
+    st = []
+    for s in case.sub:
+        z, y, x = s["mesh"]
+        st += [np.where(s["ps"].n_plus, 2000.0 * np.exp(-100.0 * (x * x + y * y + (z - 0.25) ** 2)), 0.0),
+               np.zeros_like(x)]
+    for kw in ({"t_final": 1.0, "max_steps": 4}, {"t_final": 1.0, "max_steps": 10, "rho_cap": 1500.0}):
+        say(f"dd2 adaptive run 15/31 Test B {kw}")
+        ref_state, ref = odd.dd_adaptive_run(st, case, 1.0 / dt0, 1.0, **kw)
+        dd = api.dd_build(_params2(case, 1.0 / dt0), device=dev)
+        state = [torch.from_numpy(v).to(dev) for v in st]
+        res = api.dd_run(dd, 1.0, state, **kw)
+        say(f"  {res['stop']} after {res['steps']} steps, rebuilt {res['rebuilt']}")
+        _adaptive_compare(res, ref, state, ref_state)
+        assert abs(res["rho_max"] - ref["rho_max"]) <= 1e-9 * ref["rho_max"]
+        assert res["stop"] == ("max_steps" if "rho_cap" not in kw else "rho_cap")
+        dd.close()
