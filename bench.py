@@ -622,7 +622,7 @@ def main():
     adaptive = run_adaptive(args, dev) if args.adaptive_steps > 0 else None
     test_b = run_test_b(args, dev) if args.adaptive_steps > 0 and not args.no_bmat else None
     dd = run_dd(args, dev) if args.dd_steps > 0 else None
-    dd2 = run_dd2(args, dev) if args.dd_steps > 0 and not args.no_bmat else None
+    dd2 = run_dd2(args, dev) if args.dd_steps > 0 else None
 
     ok = {k: v for k, v in results.items() if v["rel_err_sample"] <= args.rtol}
     best_name = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else None

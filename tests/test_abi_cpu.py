@@ -127,3 +127,6 @@ def test_dd_validation_without_device():
                      ({"beta": 3}, "beta"), ({"origin1": (C.c_double * 3)(0, float("nan"), 0)}, "origins")]:
         assert build2(**kw) == _lib.DPM_EINVAL, kw
         assert word in lib.dpm_last_error().decode(), (kw, lib.dpm_last_error())
+    prm = _lib.RunParams(1.0, 1.0, float("inf"), 10)
+    assert lib.dpm_dd_rebuild(None, 1.0, None) == _lib.DPM_EINVAL
+    assert lib.dpm_dd_run(None, C.byref(prm), vols, C.byref(o), None, None, None, None) == _lib.DPM_EINVAL
