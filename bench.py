@@ -439,6 +439,61 @@ def run_dd2(args, dev):
     return out
 
 
+def oracle_by_n(args, dev, oaux, cores):
+    """The oracle's time per solve at N = 31, 63, 127, 255 on the host's cores (one warm-up, then
+    the median of 3; single-threaded too for N <= 127), beside the GPU's FP64 rate at the same N
+    (64 right-hand sides per batched call).  N(0,1) right-hand sides, sigma = args.sigma."""
+    import torch
+    from paper_1811_03557_amd import api
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:
+        threadpool_limits = None
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {"cpu_model": model, "threads": cores, "sigma": args.sigma, "rows": []}
+    for n in (31, 63, 127, 255):
+        h = 3.0 / (n + 1)
+        rng = np.random.default_rng(n)
+        bh = rng.standard_normal((4, n, n, n))
+
+        def median_solve():
+            oaux.aux_solve(bh[0], args.sigma, h)
+            ts = []
+            for i in range(1, 4):
+                t = time.perf_counter()
+                oaux.aux_solve(bh[i], args.sigma, h)
+                ts.append(time.perf_counter() - t)
+            return sorted(ts)[1]
+        row = {"n": n, "oracle_s_per_solve": round(median_solve(), 5)}
+        if n <= 127 and threadpool_limits is not None:
+            with threadpool_limits(1):
+                row["oracle_1thread_s_per_solve"] = round(median_solve(), 5)
+        b = torch.from_numpy(np.broadcast_to(bh[0], (64, n, n, n)).copy()).to(dev)
+        u = torch.empty_like(b)
+        for _ in range(2):
+            api.aux_solve_batched(b, args.sigma, h, out=u)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            api.aux_solve_batched(b, args.sigma, h, out=u)
+        torch.cuda.synchronize()
+        row["gpu_fp64_solves_per_s"] = round(64 * reps / (time.perf_counter() - t), 1)
+        row["gpu_over_oracle"] = round(row["gpu_fp64_solves_per_s"] * row["oracle_s_per_solve"], 1)
+        out["rows"].append(row)
+        log(f"[bench] N = {n}: oracle {row['oracle_s_per_solve'] * 1e3:.2f} ms/solve, GPU FP64 "
+            f"{row['gpu_fp64_solves_per_s']:.0f} solves/s")
+        del b, u
+    return out
+
+
 def run_boundary_matrix(args, dev):
     """Step 2 of the method at 127^3: the 242-column reduced-BEP matrix of the unit sphere
     (real Y_lm, l <= 10, beta = 1), sigma = 2/h^2, built and QR-factored by one
@@ -613,6 +668,7 @@ def main():
                          f"of the same workload (255^3, sigma {args.sigma}), dense FP64 DST-I "
                          f"oracle; the first solve ({t_first:.2f} s) excluded"}
         log(f"[bench] cpu oracle: {k / t_rest:.3f} solves/s on {cores} threads")
+        cpu["by_n"] = oracle_by_n(args, dev, oaux, int(cores))
 
     serving = None
     if args.serve_requests > 0:
