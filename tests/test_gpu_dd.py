@@ -309,3 +309,33 @@ def test_dd2_adaptive_run_test_b():
         assert abs(res["rho_max"] - ref["rho_max"]) <= 1e-9 * ref["rho_max"]
         assert res["stop"] == ("max_steps" if "rho_cap" not in kw else "rho_cap")
         dd.close()
+
+
+def test_dd_meshes_off_powers_of_two_dense_form():
+    """Both cases on meshes with N + 1 not a power of two (N1/N2 = 20/36: h1 = 1.5/21, h2 = 3/37,
+    so the meshes do not align), solved by the dense FP64 transform form: one step against the
+    oracle (no node lies within 1e-3 of a classification radius, so the masks are decided
+    identically whatever the rounding)."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    dt, chi = 1e-3, 1.0
+    case = odd.DDCase(20, 0.75, 36, 0.5, 2, 2, 1)
+    case2 = odd.DDCase2(20, 0.75, 0.75, 36, 1.0, 0.5, 4, 2, beta=0)
+    runs = [("case 1", _params(case, 1.0 / dt, 2, 1, 2), odd.dd_matrix(case, 1.0 / dt),
+             list(_data(case.mesh1, case.ps1)) + list(_data(case.mesh2, case.ps2)),
+             lambda st, A: odd.dd_step(*st, case, A, dt, chi)[:4]),
+            ("case 2", _params2(case2, 1.0 / dt), odd.dd2_matrix(case2, 1.0 / dt),
+             list(_data2(case2.sub[0]["mesh"], case2.sub[0]["ps"]))
+             + list(_data2(case2.sub[1]["mesh"], case2.sub[1]["ps"])),
+             lambda st, A: odd.dd2_step(*st, case2, A, dt, chi)[:4])]
+    for label, prm, A, st, step in runs:
+        say(f"dd {label} 20/36 fp64_gemm")
+        ref = step(st, A)
+        dd = api.dd_build(prm, prec="fp64_gemm", device=dev)
+        out = api.dd_step(dd, dt, chi, [torch.from_numpy(v).to(dev) for v in st], prec="fp64_gemm")
+        for k, (g, o) in enumerate(zip(out, ref)):
+            err = np.max(np.abs(g.cpu().numpy() - o)) / np.max(np.abs(o))
+            say(f"  output {k}: rel err {err:.2e}")
+            assert err <= 1e-9, (label, k, err)
+        dd.close()
