@@ -389,7 +389,8 @@ dpm_status dpm_dd_step_workspace_size(const dpm_dd* dd, const dpm_opts* opts, si
  * coefficients from the stacked traces by one least squares, each subdomain's densities and its
  * discrete generalized Green's formula.  The handle must have been built with sigma = 1/dt.
  * in = {rho_1, c_1, rho_2, c_2}: device FP64 volumes of the subdomains' meshes (values on N+
- * used); out: the same four, zero off N+ (they may alias the inputs).  opts->workspace: at least
+ * used); out: the same four, zero off N+, four different buffers (each may alias its own
+ * input).  opts->workspace: at least
  * dpm_dd_step_workspace_size bytes.  Asynchronous; allocates nothing.  Omega_2's share runs on a
  * stream owned by the handle, forked from `stream` and joined back to it by events, so the two
  * meshes' solves overlap; work enqueued on `stream` afterwards sees all four outputs.  Calls on

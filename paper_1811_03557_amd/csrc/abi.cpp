@@ -423,7 +423,9 @@ dpm_status dpm_dd_step(const dpm_dd* dd, double dt, double chi, const double* co
       set_error("volume %d is NULL or not 8-byte aligned", i);
       return DPM_EINVAL;
     }
-  if (out[0] == out[1] || out[2] == out[3]) { set_error("rho and c outputs must be different buffers"); return DPM_EINVAL; }
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (out[i] == out[j]) { set_error("the four outputs must be different buffers"); return DPM_EINVAL; }
   if (!opts) { set_error("opts is NULL"); return DPM_EINVAL; }
   if (!opts->io_fp64) { set_error("dpm_dd_step needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
   if (!aligned16(opts->workspace)) { set_error("the workspace must be 16-byte aligned"); return DPM_EINVAL; }
@@ -457,7 +459,9 @@ dpm_status dpm_dd_run(dpm_dd* dd, const dpm_run_params* params, double* const st
   if (!dd || !params || !state || !opts) { set_error("NULL argument"); return DPM_EINVAL; }
   for (int i = 0; i < 4; ++i)
     if (!state[i] || !aligned_to(state[i], 8)) { set_error("volume %d is NULL or not 8-byte aligned", i); return DPM_EINVAL; }
-  if (state[0] == state[1] || state[2] == state[3]) { set_error("rho and c must be different buffers"); return DPM_EINVAL; }
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (state[i] == state[j]) { set_error("the four state volumes must be different buffers"); return DPM_EINVAL; }
   if (!opts->io_fp64) { set_error("dpm_dd_run needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
   if (!aligned16(opts->workspace)) { set_error("the workspace must be 16-byte aligned"); return DPM_EINVAL; }
   if (!(params->chi >= 0.0) || !std::isfinite(params->chi)) { set_error("chi must be finite and >= 0"); return DPM_EINVAL; }
