@@ -2,7 +2,8 @@
  * A C program that drives libdpm through its C ABI alone (no Python): one auxiliary-problem solve
  * of a sine mode checked against its closed form, the argument checks, and a short DPM time loop
  * on the unit sphere (classification, discrete boundary, densities, boundary matrix, captured
- * steps).  Prints "ok" and returns 0 on success.
+ * steps), the adaptive loop, and the adaptive loop of the domain decomposition (Case 2).  Prints
+ * "ok" and returns 0 on success.
  */
 #include <math.h>
 #include <stdio.h>
@@ -149,6 +150,52 @@ int main(void) {
       !isfinite(ri.rho_max))
     return 1;
   dpm_bep_destroy(bep);
+
+  /* ---- 5. domain decomposition, Case 2: the cap |x - (0,0,1)| < 0.5 on its own 15^3 mesh of
+   *         [-0.75, 0.75]^2 x [0, 1.5], the rest of the ball on the 31^3 mesh; Test B data;
+   *         three adaptive steps of the coupled problem */
+  const int n1 = 15;
+  const double h1 = 1.5 / (n1 + 1);
+  dpm_dd2_params dp = {{n1, h1, 1.0 / dt, -0.75 + h1}, {n, h, 1.0 / dt, x0}, {0.0, 0.0, 0.75},
+                       {0.0, 0.0, 0.0}, 1.0, 1.0, 0.5, 2.0, 4, 0, 2};
+  dpm_dd* dd = NULL;
+  CHECK(dpm_dd2_build(&dp, &o, NULL, &dd, NULL));
+  int32_t dg[2], dgi[2], drows[2], dcols = 0;
+  CHECK(dpm_dd_info(dd, dg, dgi, drows, &dcols, NULL, NULL));
+  const size_t vol1 = (size_t)n1 * n1 * n1;
+  double* st4[4] = {NULL, NULL, NULL, NULL};
+  HCHECK(hipMalloc((void**)&st4[0], sizeof(double) * vol1));
+  HCHECK(hipMalloc((void**)&st4[1], sizeof(double) * vol1));
+  HCHECK(hipMalloc((void**)&st4[2], sizeof(double) * vol));
+  HCHECK(hipMalloc((void**)&st4[3], sizeof(double) * vol));
+  const double cb[3] = {0.0, 0.0, 0.25};
+  for (int l = 0; l < 2; ++l) {
+    CHECK(dpm_dd_gauss_state(dd, l, 2000.0, 100.0, cb, st4[2 * l], NULL));
+    CHECK(dpm_dd_gauss_state(dd, l, 0.0, 1.0, cb, st4[2 * l + 1], NULL));
+  }
+  size_t dwb = 0;
+  CHECK(dpm_dd_step_workspace_size(dd, &so, &dwb));
+  void* dws = NULL;
+  HCHECK(hipMalloc(&dws, dwb + 256));
+  dpm_opts dop = so;
+  dop.workspace = dws;
+  dop.workspace_bytes = dwb + 256;
+  const dpm_run_params dr = {1.0, 1.0, 1e30, 3};
+  dpm_run_info di;
+  CHECK(dpm_dd_run(dd, &dr, st4, &dop, NULL, &di, NULL, NULL));
+  double* h1v = (double*)malloc(sizeof(double) * vol1);
+  if (!h1v) return 1;
+  HCHECK(hipMemcpy(h1v, st4[0], sizeof(double) * vol1, hipMemcpyDeviceToHost));
+  double m1 = 0.0;
+  for (size_t i = 0; i < vol1; ++i) m1 += h1v[i];
+  printf("dd case 2: rows %d + %d, %d columns, %d steps, %d rebuilds, max rho %.3e, sum rho_1 %.6e\n",
+         drows[0], drows[1], dcols, di.steps, di.rebuilds, di.rho_max, m1);
+  if (di.steps != 3 || !(m1 > 0.0) || !isfinite(m1) || !isfinite(di.rho_max) || drows[0] <= dgi[0])
+    return 1;
+  dpm_dd_destroy(dd);
+  free(h1v);
+  (void)hipFree(dws);
+  for (int i = 0; i < 4; ++i) (void)hipFree(st4[i]);
   (void)hipFree(rws);
   (void)hipFree(sws); (void)hipFree(rho); (void)hipFree(c); (void)hipFree(basis);
   (void)hipFree(dist); (void)hipFree(idx); (void)hipFree(is_in); (void)hipFree(mp);
