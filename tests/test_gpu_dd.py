@@ -339,3 +339,26 @@ def test_dd_meshes_off_powers_of_two_dense_form():
             say(f"  output {k}: rel err {err:.2e}")
             assert err <= 1e-9, (label, k, err)
         dd.close()
+
+
+def test_dd2_uncovered_nodes_rejected():
+    """With a tolerance of 0.2 mesh widths, 8 nodes of Omega_2's discrete boundary at the wedge
+    fall in neither part (the oracle counts them): the build fails with DPM_EGEOM and names the
+    count and the subdomain, and at 0.5 mesh widths it succeeds."""
+    from paper_1811_03557_amd import api
+    from paper_1811_03557_amd._lib import DPMError, DPM_EGEOM
+    dev = need_gpu()
+    case = odd.DDCase2(15, 0.75, 0.75, 31, 1.0, 0.5, 4, 2, beta=0, eps_layers=0.2)
+    missing = [int((~s["cover"]).sum()) for s in case.sub]
+    assert missing == [0, 8]
+    s1, s2 = case.sub
+    say("dd2 eps_layers 0.2 and 0.5")
+    for eps, ok in ((0.2, False), (0.5, True)):
+        prm = api.dd2_params(15, s1["h"], s1["x0"], (0.0, 0.0, 0.75), 31, s2["h"], s2["x0"],
+                             (0.0, 0.0, 0.0), 1000.0, 1.0, 1.0, 0.5, eps, 4, 0, 2)
+        if ok:
+            api.dd_build(prm, device=dev).close()
+        else:
+            with pytest.raises(DPMError, match="8 nodes of subdomain 2") as e:
+                api.dd_build(prm, device=dev)
+            assert e.value.status == DPM_EGEOM
