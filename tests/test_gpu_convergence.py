@@ -6,7 +6,8 @@ root).  The scheme is first order in time and second order in space (paper Sec. 
 7-point Laplacian, the 3-term extension; Prop. "discrete generalized Green's formula"), so with
 dt ~ h^2 (dt = T / ceil(T / (0.5 h^2))) the error at T = 0.01 must fall by about 4 per halving of
 h: in the single domain (N = 31 ... 255), and on both decomposed domains (Case 1 and Case 2, both
-meshes refined together), where it must also match the single domain's accuracy.
+meshes refined together), where it must also match the single domain's accuracy; at a fixed mesh
+the dependence on dt is first order.
 """
 import math
 
@@ -125,3 +126,37 @@ def test_decomposed_domain_second_order(case, sd_errors):
     # as accurate as the single domain on the same spacing
     for a, b in zip(e, sd_errors):
         assert a <= 1.05 * b, (a, b)
+
+
+def test_single_domain_first_order_in_time():
+    """At a fixed mesh (N = 63) the IMEX step is first order in dt: the differences between the
+    states at T = 0.02 reached with dt = T/4, T/8, T/16, T/32 halve with dt."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    geo = api.geometry("sphere", axes=(1.0,))
+    n = 63
+    h, x0 = inp.grid(n)
+    m = api.classify(n, h, x0, geo, device=dev)
+    idx, _ = api.gamma_points(m, h, x0)
+    B, _ = api.basis_zonal(n, h, x0, geo, idx, 0, 1)
+    z, y, x = inp.mesh(n)
+    c0 = _j0(np.sqrt(x * x + y * y + z * z))
+    mp = m.cpu().numpy().astype(bool)
+    tt = 0.02
+    finals = []
+    for steps in (4, 8, 16, 32):
+        dt = tt / steps
+        bep = api.build_boundary_matrix(m, B, n, h, 1.0 / dt, x0)
+        c = torch.from_numpy(c0).to(dev)
+        rho = torch.zeros_like(c)
+        st = api.Stepper(bep, dt, 0.0, rho, c)
+        st.run(steps)
+        finals.append(c.cpu().numpy()[mp])
+        st.close()
+        bep.close()
+    d = [np.max(np.abs(a - b)) for a, b in zip(finals, finals[1:])]
+    say("time differences " + ", ".join(f"{v:.3e}" for v in d) + "; ratios "
+        + ", ".join(f"{a / b:.2f}" for a, b in zip(d, d[1:])))
+    for a, b in zip(d, d[1:]):
+        assert 1.7 < a / b < 2.3, (a, b)
