@@ -23,7 +23,7 @@ loop from the paper's Test B data with 150 zonal harmonics at 127^3.
 Domain decomposition (the "domain_decomposition" object): Case 1 on the Test A setup, the
 ball on a 127^3 mesh and the shell on a 63^3 mesh, against the single domain at 255^3 with the
 same fine spacing: build and per-step times and their ratio.  The "domain_decomposition_case2"
-object: Case 2 (Z meets Gamma) on the Test B setup at 127/63 (50 harmonics on Gamma, 10 on Z),
+object: Case 2 (Z meets Gamma) on the Test B setup at 127/63 (150 harmonics on Gamma, 10 on Z),
 against the single domain at 255^3.
 
 Prints one JSON line on stdout (everything else goes to stderr).
@@ -358,20 +358,20 @@ def run_dd2(args, dev):
     """Domain decomposition, Case 2, on the paper's Test B setup (blow-up at the boundary): the
     cap of the unit ball within 0.5 of the north pole (Z: the sphere of radius 0.5 about (0, 0, 1))
     on a fine mesh (N1 = 127 on [-0.75, 0.75]^2 x [0, 1.5], h1 = 3/256) and the rest on a coarse
-    one (N2 = 63 on [-1.5, 1.5]^3, h2 = 4 h1); 50 zonal harmonics with the 2-term extension on
-    Gamma and 10 with the 3-term extension on Z (80 columns; the paper's 20 on Z leave the
-    coupled matrix numerically rank deficient, as Legendre polynomials of high degree are nearly
-    dependent on the arc of Z inside the ball, psi <= psi* = 75.5 degrees), parts with a
-    tolerance of 2 mesh widths; Test B data, dt = 0.5 h1^2 (c0 = 0: no CFL bound at the
-    start).  Against the single domain at N = 255 with the same 50 harmonics: Step 2 wall time
-    and the per-step time (eager steps, FP64)."""
+    one (N2 = 63 on [-1.5, 1.5]^3, h2 = 4 h1); the paper's 150 zonal harmonics for mesh 127/63
+    with the 2-term extension on Gamma and 10 with the 3-term extension on Z (180 columns; the
+    paper's 20 on Z leave the coupled matrix numerically rank deficient, as Legendre polynomials
+    of high degree are nearly dependent on the arc of Z inside the ball, psi <= psi* = 75.5
+    degrees), parts with a tolerance of 2 mesh widths; Test B data, dt = 0.5 h1^2 (c0 = 0: no
+    CFL bound at the start).  Against the single domain at N = 255 with the same 150 harmonics:
+    Step 2 wall time and the per-step time (eager steps, FP64)."""
     import torch
     from paper_1811_03557_amd import api
     n1, n2 = 127, 63
     h1, h2 = 1.5 / (n1 + 1), 3.0 / (n2 + 1)
     dt = 0.5 * h1 * h1
     prm = api.dd2_params(n1, h1, -0.75 + h1, (0.0, 0.0, 0.75), n2, h2, -1.5 + h2, (0.0, 0.0, 0.0),
-                         1.0 / dt, 1.0, 1.0, 0.5, 2.0, 49, 0, 9)
+                         1.0 / dt, 1.0, 1.0, 0.5, 2.0, 149, 0, 9)
     api.dd_build(prm, device=dev).close()
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -394,9 +394,9 @@ def run_dd2(args, dev):
     t_dd = (time.perf_counter() - t) / steps
     finite = all(bool(torch.isfinite(v).all()) for v in state)
     out = {"workload": "Test B data; cap |x - (0,0,1)| < 0.5 of the unit ball at N1 = 127 "
-                       "(h1 = 3/256) + the rest at N2 = 63 (h2 = 3/64); 50 zonal harmonics "
+                       "(h1 = 3/256) + the rest at N2 = 63 (h2 = 3/64); 150 zonal harmonics "
                        "(2-term) on Gamma, 10 (3-term) on Z; dt = 0.5 h1^2; single domain at "
-                       "N = 255 with 50 harmonics for comparison",
+                       "N = 255 with 150 harmonics for comparison",
            "dd2_127_63": {"columns": dd.n_cols, "rows": sum(dd.n_rows),
                           "build_s": round(build_dd, 4), "ms_per_step": round(t_dd * 1e3, 3),
                           "steps_per_s": round(1.0 / t_dd, 1), "finite": finite,
@@ -410,7 +410,7 @@ def run_dd2(args, dev):
     geo = api.geometry("sphere", axes=(1.0,))
     m = api.classify(n, h, x0, geo, device=dev)
     idx, _ = api.gamma_points(m, h, x0)
-    B, _ = api.basis_zonal(n, h, x0, geo, idx, 49, 0)
+    B, _ = api.basis_zonal(n, h, x0, geo, idx, 149, 0)
     api.build_boundary_matrix(m, B, n, h, 1.0 / dt, x0).close()
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -434,7 +434,7 @@ def run_dd2(args, dev):
     out["dt"] = dt
     out["R_S_per_step"] = round(t_sd / t_dd, 2)
     out["R_S_build"] = round(build_sd / build_dd, 2)
-    log(f"[bench] SD 255 (50 harmonics): build {build_sd * 1e3:.1f} ms, {t_sd * 1e3:.3f} ms/step")
+    log(f"[bench] SD 255 (150 harmonics): build {build_sd * 1e3:.1f} ms, {t_sd * 1e3:.3f} ms/step")
     bep.close()
     return out
 
