@@ -556,8 +556,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solve is a single-GPU "
-              "path in this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solve path measured "
+              "here is single-GPU; sharding across GPUs is a design, not an implementation.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
