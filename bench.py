@@ -280,7 +280,9 @@ def run_dd(args, dev):
     CFL-type bound of the positivity theorem at the initial data, max|grad c0| from the formula,
     which bounds the face differences; far below 0.5 h1^2 for these data).  Against the single
     domain at the same fine spacing everywhere (N = 255, 2 columns): Step 2 wall time and the
-    per-step time (eager steps, FP64), whose ratio is the per-step R_S = T_SD / T_DD."""
+    per-step time (eager steps, FP64), whose ratio is the per-step R_S = T_SD / T_DD; and the
+    adaptive loop (Steps 3-8 with rebuilds, args.adaptive_steps steps from dt0 = 0.5 h1^2) on
+    both, whose ratio is R_S for a run."""
     import torch
     from paper_1811_03557_amd import api
     n1, n2 = 127, 63
@@ -350,6 +352,34 @@ def run_dd(args, dev):
     out["R_S_build"] = round(build_sd / build_dd, 2)
     log(f"[bench] SD 255: build {build_sd * 1e3:.1f} ms, {t_sd * 1e3:.3f} ms/step; "
         f"R_S per step {t_sd / t_dd:.2f}")
+    # the adaptive loop (Steps 3-8) from Test A data and dt0 = 0.5 h1^2 on both: the CFL-type
+    # bound cuts dt at the first step and the matrices are rebuilt whenever it shrinks
+    dt0 = 0.5 * h1 * h1
+    runs = {}
+    prm0 = api.dd_params(n1, h1, -0.75 + h1, n2, h2, -1.5 + h2, 1.0 / dt0, 0.5, 1.0, 0.75, 0, 1, 0)
+    dd = api.dd_build(prm0, device=dev)
+    state = [dd.gauss_state(l, a, r) for l in (0, 1) for a, r in ((1000.0, 100.0), (500.0, 50.0))]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = api.dd_run(dd, 1.0, state, t_final=1.0, max_steps=args.adaptive_steps)
+    torch.cuda.synchronize()
+    runs["dd_127_63"] = {"run_s": round(time.perf_counter() - t, 4), "steps": res["steps"],
+                         "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"]}
+    dd.close()
+    bep.rebuild(1.0 / dt0)
+    rho = api.gauss_state(bep, geo, 1000.0, 100.0)
+    c = api.gauss_state(bep, geo, 500.0, 50.0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = api.run(bep, 1.0, rho, c, t_final=1.0, max_steps=args.adaptive_steps)
+    torch.cuda.synchronize()
+    runs["sd_255"] = {"run_s": round(time.perf_counter() - t, 4), "steps": res["steps"],
+                      "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"]}
+    runs["R_S_run"] = round(runs["sd_255"]["run_s"] / runs["dd_127_63"]["run_s"], 2)
+    out["adaptive_run"] = runs
+    log(f"[bench] adaptive {args.adaptive_steps} steps: DD {runs['dd_127_63']['run_s'] * 1e3:.1f} ms "
+        f"({runs['dd_127_63']['rebuilds']} rebuilds), SD {runs['sd_255']['run_s'] * 1e3:.1f} ms "
+        f"({runs['sd_255']['rebuilds']} rebuilds); R_S {runs['R_S_run']:.2f}")
     bep.close()
     return out
 
