@@ -339,14 +339,15 @@ def dd2_params(n1: int, h1: float, x01: float, origin1, n2: int, h2: float, x02:
                        float(q_z), float(r_z), float(eps_layers), int(m_gamma), int(beta), int(m_z))
 
 
-def dd_build(params, prec: str = "fp64", device="cuda", return_A: bool = False, stream=None):
+def dd_build(params, prec: str = "fp64", device="cuda", return_A: bool = False, stream=None,
+             rtol: float = 1e-10, max_refine: int = 0):
     """Step 2 of the domain decomposition (Case 1 for DDParams, Case 2 for DD2Params): both
     subdomains' columns, the stacked matrix and its QR.  Returns a DD handle (and the stacked
     matrix, rows x n_cols, when return_A: the row count is known only after a first build, so
     that case builds twice)."""
     lib = L.load()
     fn = lib.dpm_dd2_build if isinstance(params, L.DD2Params) else lib.dpm_dd_build
-    o = opts(prec, True)
+    o = opts(prec, True, rtol, max_refine)
     out = C.c_void_p(0)
     L.check(fn(C.byref(params), C.byref(o), C.c_void_p(_stream(stream)), C.byref(out), None))
     dd = DD(out.value, params, torch.device(device))
@@ -362,7 +363,8 @@ def dd_build(params, prec: str = "fp64", device="cuda", return_A: bool = False, 
 
 
 def dd_step(dd: DD, dt: float, chi: float, state, out=None, prec: str = "fp64",
-            workspace: torch.Tensor | None = None, stream=None):
+            workspace: torch.Tensor | None = None, stream=None, rtol: float = 1e-10,
+            max_refine: int = 0):
     """One step on both subdomains; state = (rho_1, c_1, rho_2, c_2); returns the new four."""
     for v, n in zip(state, (dd.n[0], dd.n[0], dd.n[1], dd.n[1])):
         if v.numel() != n ** 3:
@@ -370,7 +372,7 @@ def dd_step(dd: DD, dt: float, chi: float, state, out=None, prec: str = "fp64",
                              f"{dd.n[1]}^3 values")
     if out is not None and any(a.numel() != b.numel() for a, b in zip(out, state)):
         raise ValueError("out volumes must match the state volumes")
-    o = opts(prec, True)
+    o = opts(prec, True, rtol, max_refine)
     nbytes = dd.workspace_size(o)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=state[0].device)
@@ -387,14 +389,14 @@ def dd_step(dd: DD, dt: float, chi: float, state, out=None, prec: str = "fp64",
 
 def dd_run(dd: DD, chi: float, state, t_final: float, rho_cap: float = float("inf"),
            max_steps: int = 1000, prec: str = "fp64", workspace: torch.Tensor | None = None,
-           stream=None) -> dict:
+           stream=None, rtol: float = 1e-10, max_refine: int = 0) -> dict:
     """Steps 3-8 on the decomposed domain, state = (rho_1, c_1, rho_2, c_2) in place, from
     dt = 1/dd.sigma; the run summary as for run()."""
     for v, n in zip(state, (dd.n[0], dd.n[0], dd.n[1], dd.n[1])):
         if v.numel() != n ** 3:
             raise ValueError(f"state volumes must hold {dd.n[0]}^3, {dd.n[0]}^3, {dd.n[1]}^3, "
                              f"{dd.n[1]}^3 values")
-    o = opts(prec, True)
+    o = opts(prec, True, rtol, max_refine)
     nbytes = dd.workspace_size(o) + 256
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=state[0].device)

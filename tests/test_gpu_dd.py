@@ -362,3 +362,33 @@ def test_dd2_uncovered_nodes_rejected():
             with pytest.raises(DPMError, match="8 nodes of subdomain 2") as e:
                 api.dd_build(prm, device=dev)
             assert e.value.status == DPM_EGEOM
+
+
+@pytest.mark.parametrize("prec,max_refine,tol", [("fp32", 3, 1e-9), ("fp32", 0, 1e-5)])
+def test_dd_step_fp32_transforms(prec, max_refine, tol):
+    """Both cases with FP32 transforms: the columns and both steps' solves refined in FP64 to
+    1e-10 match the oracle at 1e-9; unrefined, at 1e-5 (FP32 rounding through ~8 solves)."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    dt, chi = 1e-3, 1.0
+    case = odd.DDCase(15, 0.75, 31, 0.5, 2, 2, 1)
+    case2 = odd.DDCase2(15, 0.75, 0.75, 31, 1.0, 0.5, 4, 2, beta=0)
+    runs = [("case 1", _params(case, 1.0 / dt, 2, 1, 2), odd.dd_matrix(case, 1.0 / dt),
+             list(_data(case.mesh1, case.ps1)) + list(_data(case.mesh2, case.ps2)),
+             lambda st, A: odd.dd_step(*st, case, A, dt, chi)[:4]),
+            ("case 2", _params2(case2, 1.0 / dt), odd.dd2_matrix(case2, 1.0 / dt),
+             list(_data2(case2.sub[0]["mesh"], case2.sub[0]["ps"]))
+             + list(_data2(case2.sub[1]["mesh"], case2.sub[1]["ps"])),
+             lambda st, A: odd.dd2_step(*st, case2, A, dt, chi)[:4])]
+    for label, prm, A, st, step in runs:
+        say(f"dd {label} 15/31 {prec} max_refine={max_refine}")
+        ref = step(st, A)
+        dd = api.dd_build(prm, prec=prec, max_refine=max_refine, device=dev)
+        out = api.dd_step(dd, dt, chi, [torch.from_numpy(v).to(dev) for v in st], prec=prec,
+                          max_refine=max_refine)
+        for k, (g, o) in enumerate(zip(out, ref)):
+            err = np.max(np.abs(g.cpu().numpy() - o)) / np.max(np.abs(o))
+            say(f"  output {k}: rel err {err:.2e}")
+            assert err <= tol, (label, k, err)
+        dd.close()
