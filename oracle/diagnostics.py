@@ -7,8 +7,10 @@ the two subdomains of the domain decomposition.
   E_h = sum over M+ of h^3 { rho ln rho - rho c + c^2/2
                              + (1/(8 h^2)) sum over axes (c_{+1} - c_{-1})^2 }   (eqs sd/dd-norm:free-energy)
 
-with x the node coordinates (the paper's domain is centred at the origin).  Readings: 0 ln 0 = 0;
-a negative rho makes rho ln rho (and E_h) NaN; the central differences use the neighbours in N+
+with x the node coordinates (the paper's domain is centred at the origin).  Readings: rho ln rho
+is taken as 0 for rho <= 0 (its limit at 0; the scheme keeps rho >= 0 in exact arithmetic, so
+negative values are rounding, of the order of 1e-16 times the data); a NaN rho makes it NaN; the
+central differences use the neighbours in N+
 (inside the cube, as every M+ node's are).  For the decomposed domain the maximum is taken over
 both subdomains and the sums add, each with its own h and node coordinates.
 
@@ -33,7 +35,7 @@ def second_moment(rho: np.ndarray, m_plus: np.ndarray, h: float, mesh) -> float:
 def free_energy(rho: np.ndarray, c: np.ndarray, m_plus: np.ndarray, h: float) -> float:
     with np.errstate(divide="ignore", invalid="ignore"):
         rlr = np.where(rho > 0, rho * np.log(np.where(rho > 0, rho, 1.0)),
-                       np.where(rho == 0, 0.0, np.nan))
+                       np.where(np.isnan(rho), np.nan, 0.0))
     grad = np.zeros_like(c)
     for ax in range(3):
         d = _shift(c, ax, 1) - _shift(c, ax, -1)

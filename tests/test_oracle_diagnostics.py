@@ -50,9 +50,10 @@ def test_diagnostics_against_closed_forms():
     assert errs[0] < 0.05 * grad and 3.8 < errs[0] / errs[1] < 4.2, errs
 
 
-def test_free_energy_terms_and_negative_density():
+def test_free_energy_terms_and_nonpositive_density():
     """Constant rho = a, c = b on M+: E = |M+| h^3 (a ln a - a b + b^2/2) (no gradient inside, and
-    the cube's edges are not reached); 0 ln 0 = 0; a negative rho gives NaN."""
+    the cube's edges are not reached); rho ln rho is 0 for rho <= 0 (a rounding-level negative
+    rho still enters -rho c); a NaN rho gives NaN."""
     n = 31
     h, _ = inp.grid(n)
     z, y, x = inp.mesh(n)
@@ -64,7 +65,11 @@ def test_free_energy_terms_and_negative_density():
     vol = ps.m_plus.sum() * h**3
     assert np.isclose(e, vol * (a * math.log(a) - a * b + 0.5 * b * b), rtol=1e-13)
     assert dg.free_energy(np.zeros_like(rho), c, ps.m_plus, h) == pytest.approx(vol * 0.5 * b * b, rel=1e-13)
-    rho[ps.m_plus.nonzero()[0][0], ps.m_plus.nonzero()[1][0], ps.m_plus.nonzero()[2][0]] = -1.0
+    k = tuple(v[0] for v in ps.m_plus.nonzero())
+    rho[k] = -1e-17
+    e2 = dg.free_energy(rho, c, ps.m_plus, h)
+    assert np.isclose(e2, e - h**3 * (a * math.log(a) - a * b) + h**3 * 1e-17 * b, rtol=1e-13)
+    rho[k] = np.nan
     assert math.isnan(dg.free_energy(rho, c, ps.m_plus, h))
 
 
