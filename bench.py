@@ -359,23 +359,30 @@ def run_dd(args, dev):
     prm0 = api.dd_params(n1, h1, -0.75 + h1, n2, h2, -1.5 + h2, 1.0 / dt0, 0.5, 1.0, 0.75, 0, 1, 0)
     dd = api.dd_build(prm0, device=dev)
     state = [dd.gauss_state(l, a, r) for l in (0, 1) for a, r in ((1000.0, 100.0), (500.0, 50.0))]
+    diag0 = api.dd_diagnostics(dd, state).tolist()
     torch.cuda.synchronize()
     t = time.perf_counter()
     res = api.dd_run(dd, 1.0, state, t_final=1.0, max_steps=args.adaptive_steps)
     torch.cuda.synchronize()
     runs["dd_127_63"] = {"run_s": round(time.perf_counter() - t, 4), "steps": res["steps"],
-                         "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"]}
+                         "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"],
+                         "diagnostics_start": diag0,
+                         "diagnostics_end": api.dd_diagnostics(dd, state).tolist()}
     dd.close()
     bep.rebuild(1.0 / dt0)
     rho = api.gauss_state(bep, geo, 1000.0, 100.0)
     c = api.gauss_state(bep, geo, 500.0, 50.0)
+    diag0 = api.diagnostics(bep, rho, c).tolist()
     torch.cuda.synchronize()
     t = time.perf_counter()
     res = api.run(bep, 1.0, rho, c, t_final=1.0, max_steps=args.adaptive_steps)
     torch.cuda.synchronize()
     runs["sd_255"] = {"run_s": round(time.perf_counter() - t, 4), "steps": res["steps"],
-                      "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"]}
+                      "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"],
+                      "diagnostics_start": diag0,
+                      "diagnostics_end": api.diagnostics(bep, rho, c).tolist()}
     runs["R_S_run"] = round(runs["sd_255"]["run_s"] / runs["dd_127_63"]["run_s"], 2)
+    runs["diagnostics"] = "max |rho| over M+, second moment, free energy (Sec. 4), at t = 0 and at the end"
     out["adaptive_run"] = runs
     log(f"[bench] adaptive {args.adaptive_steps} steps: DD {runs['dd_127_63']['run_s'] * 1e3:.1f} ms "
         f"({runs['dd_127_63']['rebuilds']} rebuilds), SD {runs['sd_255']['run_s'] * 1e3:.1f} ms "

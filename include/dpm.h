@@ -429,6 +429,24 @@ dpm_status dpm_dd_run(dpm_dd* dd, const dpm_run_params* params, double* const st
 void dpm_dd_destroy(dpm_dd* dd);
 
 /*
+ * Run diagnostics (paper Sec. 4, "Error metrics and quantities of interest", eqs sd-norm:max,
+ * sd-norm:second-moment, sd-norm:free-energy and their DD forms): out3[0] = max |rho| over M+,
+ * out3[1] = sum over M+ of h^3 |x|^2 rho (x the node coordinates), out3[2] = the free energy
+ * sum over M+ of h^3 (rho ln rho - rho c + c^2/2 + (1/(8 h^2)) sum over the axes of
+ * (c_{+1} - c_{-1})^2), with rho ln rho = 0 for rho <= 0 (rounding-level negatives; a NaN rho
+ * makes the free energy and the maximum NaN).  The decomposed
+ * form takes the maximum over both subdomains and adds their sums, each with its own h.
+ * rho, c (state): device FP64 volumes; out3: device, 3 FP64; workspace: device scratch of at least
+ * DPM_DIAG_WORKSPACE_BYTES.  Deterministic (fixed reduction order); asynchronous; allocates
+ * nothing.
+ */
+#define DPM_DIAG_WORKSPACE_BYTES ((size_t)24576)
+dpm_status dpm_diagnostics(const dpm_bep* bep, const double* rho, const double* c, double* out3,
+                           void* workspace, size_t workspace_bytes, void* stream);
+dpm_status dpm_dd_diagnostics(const dpm_dd* dd, const double* const state[4], double* out3,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Measurement support (not part of the method): while enabled, the sweep kernels launched for a
  * sampled chunk of right-hand sides are bracketed by hipEvents on the stream they run on.  A
  * chunk [rhs0, rhs0 + nb) of a solve call is sampled when it holds an index that is a multiple of

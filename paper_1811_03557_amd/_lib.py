@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libdpm.so")
 
 DPM_OK, DPM_EINVAL, DPM_ENOMEM, DPM_EHIP, DPM_ENOTCONV, DPM_EGEOM, DPM_ERANK = range(7)
 DPM_FP64, DPM_FP32, DPM_BF16X3, DPM_FP64_GEMM = 0, 1, 2, 3
+DPM_DIAG_WORKSPACE_BYTES = 24576  # include/dpm.h
 STATUS_NAMES = {0: "DPM_OK", 1: "DPM_EINVAL", 2: "DPM_ENOMEM", 3: "DPM_EHIP",
                 4: "DPM_ENOTCONV", 5: "DPM_EGEOM", 6: "DPM_ERANK"}
 
@@ -107,6 +108,8 @@ SIGNATURES = {
     "dpm_dd_run": (C.c_int, [_P, C.POINTER(RunParams), C.POINTER(_P), C.POINTER(Opts), _P,
                              C.POINTER(RunInfo), _P, _P]),
     "dpm_dd_destroy": (None, [_P]),
+    "dpm_diagnostics": (C.c_int, [_P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "dpm_dd_diagnostics": (C.c_int, [_P, C.POINTER(_P), _P, _P, C.c_size_t, _P]),
     "dpm_last_error": (C.c_char_p, []),
     "dpm_timing_begin": (C.c_int, [_I, _I]),
     "dpm_rhs_chunk": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(Opts), C.POINTER(_I)]),

@@ -419,6 +419,35 @@ def dd_run(dd: DD, chi: float, state, t_final: float, rho_cap: float = float("in
             "dt_hist": [dts[i] for i in range(k)], "rebuilt": [bool(rbs[i]) for i in range(k)]}
 
 
+def diagnostics(bep: BEP, rho: torch.Tensor, c: torch.Tensor, stream=None) -> torch.Tensor:
+    """(max |rho| over M+, second moment, free energy) as a device tensor of 3 FP64."""
+    out = torch.empty(3, dtype=torch.float64, device=rho.device)
+    ws = torch.empty(L.DPM_DIAG_WORKSPACE_BYTES, dtype=torch.uint8, device=rho.device)
+    n3 = bep.n ** 3
+    if rho.numel() != n3 or c.numel() != n3:
+        raise ValueError(f"rho and c must hold {bep.n}^3 values")
+    L.check(L.load().dpm_diagnostics(C.c_void_p(bep.ptr), C.c_void_p(_dev(rho, "rho", torch.float64)),
+                                     C.c_void_p(_dev(c, "c", torch.float64)),
+                                     C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                     ws.numel(), C.c_void_p(_stream(stream))))
+    return out
+
+
+def dd_diagnostics(dd: DD, state, stream=None) -> torch.Tensor:
+    """The same over both subdomains, state = (rho_1, c_1, rho_2, c_2)."""
+    for v, n in zip(state, (dd.n[0], dd.n[0], dd.n[1], dd.n[1])):
+        if v.numel() != n ** 3:
+            raise ValueError("state volumes must match the subdomains' meshes")
+    out = torch.empty(3, dtype=torch.float64, device=state[0].device)
+    ws = torch.empty(L.DPM_DIAG_WORKSPACE_BYTES, dtype=torch.uint8, device=state[0].device)
+    names = ("rho_1", "c_1", "rho_2", "c_2")
+    pst = (C.c_void_p * 4)(*[_dev(v, k, torch.float64) for v, k in zip(state, names)])
+    L.check(L.load().dpm_dd_diagnostics(C.c_void_p(dd.ptr), pst, C.c_void_p(out.data_ptr()),
+                                        C.c_void_p(ws.data_ptr()), ws.numel(),
+                                        C.c_void_p(_stream(stream))))
+    return out
+
+
 def bep_solve(bep: BEP, g: torch.Tensor, stream=None) -> torch.Tensor:
     """Least-squares coefficients for g of shape (nvec, |gamma_in|)."""
     gg = g.unsqueeze(0) if g.dim() == 1 else g

@@ -37,6 +37,11 @@ dpm_status dd_gauss_impl(const dpm_dd* d, int l, double amp, double rate, const 
                          double* out, hipStream_t s);
 void dd_destroy(dpm_dd* d);
 double dd_sigma(const dpm_dd* d);
+size_t diag_workspace_bytes();
+dpm_status diagnostics_impl(const dpm_bep* b, const double* rho, const double* c, double* out3,
+                            void* ws, hipStream_t s);
+dpm_status dd_diagnostics_impl(const dpm_dd* d, const double* const state[4], double* out3,
+                               void* ws, hipStream_t s);
 dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], int32_t n_rows[2],
                         int32_t* n_cols, double* rmin, double* rmax);
 dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStream_t s,
@@ -473,5 +478,38 @@ dpm_status dpm_dd_run(dpm_dd* dd, const dpm_run_params* params, double* const st
 }
 
 void dpm_dd_destroy(dpm_dd* dd) { dd_destroy(dd); }
+
+static dpm_status check_diag_ws(void* ws, size_t bytes) {
+  if (diag_workspace_bytes() > DPM_DIAG_WORKSPACE_BYTES) {
+    set_error("internal: diagnostics scratch exceeds DPM_DIAG_WORKSPACE_BYTES");
+    return DPM_EINVAL;
+  }
+  if (!ws || !aligned_to(ws, 8) || bytes < DPM_DIAG_WORKSPACE_BYTES) {
+    set_error("the diagnostics need an 8-byte aligned workspace of %zu bytes (%zu given)",
+              (size_t)DPM_DIAG_WORKSPACE_BYTES, bytes);
+    return DPM_EINVAL;
+  }
+  return DPM_OK;
+}
+
+dpm_status dpm_diagnostics(const dpm_bep* bep, const double* rho, const double* c, double* out3,
+                           void* workspace, size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (!bep || !rho || !c || !out3) { set_error("NULL argument"); return DPM_EINVAL; }
+  if (!aligned_to(rho, 8) || !aligned_to(c, 8) || !aligned_to(out3, 8)) { set_error("volumes and out3 must be 8-byte aligned"); return DPM_EINVAL; }
+  DPM_TRY(check_diag_ws(workspace, workspace_bytes));
+  return diagnostics_impl(bep, rho, c, out3, workspace, static_cast<hipStream_t>(stream));
+}
+
+dpm_status dpm_dd_diagnostics(const dpm_dd* dd, const double* const state[4], double* out3,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (!dd || !state || !out3) { set_error("NULL argument"); return DPM_EINVAL; }
+  for (int i = 0; i < 4; ++i)
+    if (!state[i] || !aligned_to(state[i], 8)) { set_error("volume %d is NULL or not 8-byte aligned", i); return DPM_EINVAL; }
+  if (!aligned_to(out3, 8)) { set_error("out3 must be 8-byte aligned"); return DPM_EINVAL; }
+  DPM_TRY(check_diag_ws(workspace, workspace_bytes));
+  return dd_diagnostics_impl(dd, state, out3, workspace, static_cast<hipStream_t>(stream));
+}
 
 }  // extern "C"

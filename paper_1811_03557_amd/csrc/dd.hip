@@ -638,6 +638,8 @@ dpm_status dd_rebuild_impl(dpm_dd* d, double sigma, hipStream_t s) {
 }
 
 double dd_sigma(const dpm_dd* d) { return d->prm.grid1.sigma; }
+const dpm_bep* dd_sub(const dpm_dd* d, int l) { return d->sub[l]; }
+const double* dd_origin(const dpm_dd* d, int l) { return d->origin[l]; }
 
 dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], int32_t n_rows[2],
                         int32_t* n_cols, double* rmin, double* rmax) {

@@ -130,3 +130,20 @@ def test_dd_validation_without_device():
     prm = _lib.RunParams(1.0, 1.0, float("inf"), 10)
     assert lib.dpm_dd_rebuild(None, 1.0, None) == _lib.DPM_EINVAL
     assert lib.dpm_dd_run(None, C.byref(prm), vols, C.byref(o), None, None, None, None) == _lib.DPM_EINVAL
+
+
+def test_diagnostics_workspace_constant_and_validation():
+    """The binding's scratch size equals the header's define; a missing or short scratch and a
+    missing handle are rejected before any launch."""
+    from paper_1811_03557_amd import _lib
+    src = open(os.path.join(ROOT, "include", "dpm.h")).read()
+    m = re.search(r"#define DPM_DIAG_WORKSPACE_BYTES \(\(size_t\)(\d+)\)", src)
+    assert m and int(m.group(1)) == _lib.DPM_DIAG_WORKSPACE_BYTES
+    lib = _lib.load()
+    fake = C.c_void_p(256)
+    assert lib.dpm_diagnostics(fake, fake, fake, fake, None, 0, None) == _lib.DPM_EINVAL
+    assert "workspace" in lib.dpm_last_error().decode()
+    assert lib.dpm_diagnostics(fake, fake, fake, fake, fake, 100, None) == _lib.DPM_EINVAL
+    assert lib.dpm_diagnostics(None, fake, fake, fake, fake, 1 << 20, None) == _lib.DPM_EINVAL
+    vols = (C.c_void_p * 4)(256, 512, 768, 1024)
+    assert lib.dpm_dd_diagnostics(None, vols, fake, fake, 1 << 20, None) == _lib.DPM_EINVAL
