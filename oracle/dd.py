@@ -25,7 +25,6 @@ TEST INFRASTRUCTURE: imported only by tests/, smoke() and bench.py's cpu_baselin
 from __future__ import annotations
 
 import numpy as np
-from scipy.special import eval_legendre
 
 import dpm_inputs as inp
 
@@ -129,10 +128,6 @@ def dd_step(rho1, c1, rho2, c2, case: DDCase, A: np.ndarray, dt: float, chi: flo
 # A node of gamma_l cap zeta_l carries the average of its two densities (the effective density)
 # in the difference potential, and two equations of the reduced BEP (one per density), in the
 # order Gamma row, then Z row; rows follow gamma_in of the subdomain in ascending index.
-# z_arc (an option, not the paper's): the Z densities take P_nu of cos(psi) mapped affinely from
-# [cos psi_max, 1] onto [-1, 1], psi_max = psi* + eps_layers max(h_1, h_2) / r_z, the widest Z
-# window; the same polynomial space in cos(psi) as the paper's P_nu(cos psi), but well
-# conditioned on the arc of Z inside Omega, so more harmonics fit before the matrix loses rank.
 # ---------------------------------------------------------------------------------------------
 
 
@@ -144,8 +139,7 @@ class DDCase2:
     """Grids, point sets, parts and effective densities of the two subdomains of Case 2."""
 
     def __init__(self, n1: int, half1: float, zc1: float, n2: int, q_z: float, r_z: float,
-                 m_gamma: int, m_z: int, beta: int = 0, eps_layers: float = 2.0,
-                 z_arc: bool = False):
+                 m_gamma: int, m_z: int, beta: int = 0, eps_layers: float = 2.0):
         self.q_z, self.r_z = q_z, r_z
         self.n1, self.n2 = n1, n2
         self.m_gamma, self.m_z, self.beta = m_gamma, m_z, beta
@@ -156,9 +150,6 @@ class DDCase2:
         z_star = (1.0 + q_z * q_z - r_z * r_z) / (2.0 * q_z)
         self.theta_star = float(np.arccos(z_star))
         self.psi_star = float(np.arccos((q_z - z_star) / r_z))
-        self.z_arc = z_arc
-        h_max = max(inp.grid(n1, half1)[0], inp.grid(n2)[0])
-        self.c_lo = float(np.cos(min(np.pi, self.psi_star + eps_layers * h_max / r_z)))
         self.sub = []
         for l, (n, half, zc) in enumerate(((n1, half1, zc1), (n2, inp.HALF_WIDTH, 0.0))):
             h, x0 = inp.grid(n, half)
@@ -186,12 +177,7 @@ class DDCase2:
             w = np.where(cover, 1.0 / np.maximum(k, 1.0), 0.0)
             bg = zonal_basis_matrix(rr - 1.0, theta, m_gamma, beta)
             dz = rq - r_z
-            if z_arc:
-                # nodes past the widest window (not in zeta_l, zero rows) are clipped
-                xs = np.clip(2.0 * (np.cos(psi) - self.c_lo) / (1.0 - self.c_lo) - 1.0, -1.0, 1.0)
-                p = np.array([eval_legendre(nu, xs) for nu in range(m_z + 1)])
-            else:
-                p = zonal_basis_matrix(dz, psi, m_z, 0)
+            p = zonal_basis_matrix(dz, psi, m_z, 0)
             bz = np.concatenate([p, dz[None, :] * p, 0.5 * dz[None, :] ** 2 * p], axis=0)
             B_eff = np.concatenate([bg * (in_g * w)[None, :], bz * (in_z * w)[None, :]], axis=0)
             # reduced-BEP rows of this subdomain: (position in gamma_in, part)

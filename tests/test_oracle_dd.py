@@ -196,26 +196,3 @@ def test_dd2_converges_to_single_domain():
     fine = _dd2_minus_sd(31, 63, 1.0)
     for a, b in zip(coarse, fine):
         assert b < 2e-3 and a / b > 3.5, (a, b)
-
-
-def test_dd2_arc_basis_spans_the_same_space():
-    """The arc-mapped Z densities span the same polynomials in cos(psi) as the paper's P_nu(cos
-    psi): with as many harmonics the coupled least squares gives the same step (up to the
-    conditioning), and the mapped variable stays in [-1, 1] on every zeta node."""
-    a = dd.DDCase2(15, 0.75, 0.75, 31, 1.0, 0.5, 4, 3, beta=0)
-    b = dd.DDCase2(15, 0.75, 0.75, 31, 1.0, 0.5, 4, 3, beta=0, z_arc=True)
-    for s in b.sub:
-        xs = 2.0 * (np.cos(s["psi"][s["in_z"]]) - b.c_lo) / (1.0 - b.c_lo) - 1.0
-        assert xs.min() >= -1.0 and xs.max() <= 1.0
-    dt = 1e-3
-    st = list(_data2(a.sub[0]["mesh"], a.sub[0]["ps"])) + list(_data2(a.sub[1]["mesh"], a.sub[1]["ps"]))
-    oa = dd.dd2_step(*st, a, dd.dd2_matrix(a, 1 / dt), dt, 1.0)
-    ob_ = dd.dd2_step(*st, b, dd.dd2_matrix(b, 1 / dt), dt, 1.0)
-    for x, y in zip(oa[:4], ob_[:4]):
-        assert np.max(np.abs(x - y)) <= 1e-9 * np.max(np.abs(x))
-    # and it is better conditioned: the smallest R diagonal relative to the largest
-    A = dd.dd2_matrix(a, 1 / dt)
-    B = dd.dd2_matrix(b, 1 / dt)
-    ra = np.abs(np.diag(np.linalg.qr(A, mode="r")))
-    rb = np.abs(np.diag(np.linalg.qr(B, mode="r")))
-    assert rb.min() / rb.max() > ra.min() / ra.max()
