@@ -13,6 +13,7 @@ per solve) and an FP64 QR, so 1e-10 relative to the largest entry leaves four or
 import numpy as np
 import pytest
 
+import dpm_inputs as inp
 from oracle import dd as odd
 from oracle import geometry as og
 from tests.gpu_util import need_gpu, say
@@ -416,3 +417,25 @@ def test_dd_positivity_per_subdomain():
             say(f"  subdomain {l + 1}: min {a.min():.3e}, max {a.max():.3e}")
             assert a.min() >= -1e-12 * a.max()
     dd.close()
+
+
+def test_dd_cube_without_margin_rejected():
+    """A subdomain whose N+ reaches its cube's ghost layer (Case 1: the ball r < 0.5 on a cube of
+    half-width 0.55 at N = 15; Case 2: the cap's cube shifted down to z in [-0.45, 1.05]) is
+    rejected with DPM_EGEOM, as the oracle's point sets report no margin."""
+    from paper_1811_03557_amd import api
+    from paper_1811_03557_amd._lib import DPMError, DPM_EGEOM
+    dev = need_gpu()
+    say("dd geometry without margin")
+    h1, x01 = inp.grid(15, 0.55)
+    h2, x02 = inp.grid(31)
+    z, y, x = inp.mesh(15, 0.55)
+    assert not og.PointSets(x * x + y * y + z * z < 0.25).margin_ok
+    with pytest.raises(DPMError) as e:
+        api.dd_build(api.dd_params(15, h1, x01, 31, h2, x02, 1e3, 0.5, 1.0, 0.75, 0, 1, 0), device=dev)
+    assert e.value.status == DPM_EGEOM
+    h1, x01 = inp.grid(15, 0.75)
+    with pytest.raises(DPMError) as e:
+        api.dd_build(api.dd2_params(15, h1, x01, (0.0, 0.0, 0.3), 31, h2, x02, (0.0, 0.0, 0.0), 1e3,
+                                    1.0, 1.0, 0.5, 2.0, 2, 0, 1), device=dev)
+    assert e.value.status == DPM_EGEOM
