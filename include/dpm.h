@@ -405,6 +405,21 @@ dpm_status dpm_dd_gauss_state(const dpm_dd* dd, int32_t l, double amp, double ra
                               const double c0[3], double* out, void* stream);
 
 /*
+ * dpm_dd_stepper -- the fixed-dt time loop on the decomposed domain: dpm_dd_stepper_create
+ * captures one dpm_dd_step that updates state = {rho_1, c_1, rho_2, c_2} in place (both meshes'
+ * kernels, the side stream's branch included) into a HIP graph; dpm_dd_stepper_run replays it
+ * nsteps times on `stream`.  state and opts->workspace (at least dpm_dd_step_workspace_size
+ * bytes) must stay valid and unused by other work while replays run, until
+ * dpm_dd_stepper_destroy (which synchronises the device).  The stepper keeps pointers into the
+ * handle: destroy it first; a rebuild of the handle needs a new stepper.
+ */
+typedef struct dpm_dd_stepper dpm_dd_stepper;
+dpm_status dpm_dd_stepper_create(const dpm_dd* dd, double dt, double chi, double* const state[4],
+                                 const dpm_opts* opts, dpm_dd_stepper** out);
+dpm_status dpm_dd_stepper_run(dpm_dd_stepper* st, int32_t nsteps, void* stream);
+void dpm_dd_stepper_destroy(dpm_dd_stepper* st);
+
+/*
  * dpm_dd_rebuild -- Step 4b on the decomposed domain: both subdomains' columns, the stacked
  * matrix, its QR and least-squares operator again at a new sigma (= 1/dt), in place.
  * Synchronises `stream`; allocates temporaries for the column solves.  After a failure the

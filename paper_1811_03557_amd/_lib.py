@@ -105,6 +105,9 @@ SIGNATURES = {
     "dpm_dd_step": (C.c_int, [_P, _D, _D, C.POINTER(_P), C.POINTER(_P), C.POINTER(Opts), _P]),
     "dpm_dd_gauss_state": (C.c_int, [_P, _I, _D, _D, C.POINTER(_D), _P, _P]),
     "dpm_dd_rebuild": (C.c_int, [_P, _D, _P]),
+    "dpm_dd_stepper_create": (C.c_int, [_P, _D, _D, C.POINTER(_P), C.POINTER(Opts), C.POINTER(_P)]),
+    "dpm_dd_stepper_run": (C.c_int, [_P, _I, _P]),
+    "dpm_dd_stepper_destroy": (None, [_P]),
     "dpm_dd_run": (C.c_int, [_P, C.POINTER(RunParams), C.POINTER(_P), C.POINTER(Opts), _P,
                              C.POINTER(RunInfo), _P, _P]),
     "dpm_dd_destroy": (None, [_P]),

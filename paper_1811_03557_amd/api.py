@@ -387,6 +387,45 @@ def dd_step(dd: DD, dt: float, chi: float, state, out=None, prec: str = "fp64",
     return tuple(out)
 
 
+class DDStepper:
+    """Graph-captured fixed-dt time loop on the decomposed domain, state updated in place."""
+
+    def __init__(self, dd: DD, dt: float, chi: float, state, prec: str = "fp64",
+                 rtol: float = 1e-10, max_refine: int = 0, workspace: torch.Tensor | None = None):
+        for v, n in zip(state, (dd.n[0], dd.n[0], dd.n[1], dd.n[1])):
+            if v.numel() != n ** 3:
+                raise ValueError("state volumes must match the subdomains' meshes")
+        o = opts(prec, True, rtol, max_refine)
+        nbytes = dd.workspace_size(o)
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=state[0].device)
+        o.workspace = C.c_void_p(workspace.data_ptr())
+        o.workspace_bytes = workspace.numel()
+        # the graph keeps raw pointers: hold the buffers for its lifetime
+        self.dd, self.state, self.workspace = dd, list(state), workspace
+        names = ("rho_1", "c_1", "rho_2", "c_2")
+        pst = (C.c_void_p * 4)(*[_dev(v, k, torch.float64) for v, k in zip(state, names)])
+        out = C.c_void_p(0)
+        L.check(L.load().dpm_dd_stepper_create(C.c_void_p(dd.ptr), float(dt), float(chi), pst,
+                                               C.byref(o), C.byref(out)))
+        self.ptr = out.value
+
+    def run(self, nsteps: int, stream=None) -> None:
+        L.check(L.load().dpm_dd_stepper_run(C.c_void_p(self.ptr), int(nsteps),
+                                            C.c_void_p(_stream(stream))))
+
+    def close(self):
+        if self.ptr:
+            L.load().dpm_dd_stepper_destroy(C.c_void_p(self.ptr))
+            self.ptr = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def dd_run(dd: DD, chi: float, state, t_final: float, rho_cap: float = float("inf"),
            max_steps: int = 1000, prec: str = "fp64", workspace: torch.Tensor | None = None,
            stream=None, rtol: float = 1e-10, max_refine: int = 0) -> dict:

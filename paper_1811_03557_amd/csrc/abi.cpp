@@ -47,6 +47,10 @@ dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], in
 dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStream_t s,
                           dpm_dd** out, double* A_out);
 dpm_status dd_rebuild_impl(dpm_dd* d, double sigma, hipStream_t s);
+dpm_status dd_stepper_create_impl(const dpm_dd* d, double dt, double chi, double* const state[4],
+                                  const dpm_opts& o, void** out);
+dpm_status dd_stepper_run_impl(void* h, int nsteps, hipStream_t s);
+void dd_stepper_destroy_impl(void* h);
 dpm_status dd_run_impl(dpm_dd* d, const dpm_run_params& p, double* const state[4],
                        const dpm_opts& o, hipStream_t s, dpm_run_info* info, double* dt_hist,
                        uint8_t* rebuilt_hist);
@@ -449,6 +453,38 @@ dpm_status dpm_dd_gauss_state(const dpm_dd* dd, int32_t l, double amp, double ra
   if (l != 0 && l != 1) { set_error("subdomain index must be 0 or 1"); return DPM_EINVAL; }
   return dd_gauss_impl(dd, l, amp, rate, c0, out, static_cast<hipStream_t>(stream));
 }
+
+dpm_status dpm_dd_stepper_create(const dpm_dd* dd, double dt, double chi, double* const state[4],
+                                 const dpm_opts* opts, dpm_dd_stepper** out) {
+  clear_error();
+  if (!dd || !state || !opts || !out) { set_error("NULL argument"); return DPM_EINVAL; }
+  *out = nullptr;
+  for (int i = 0; i < 4; ++i)
+    if (!state[i] || !aligned_to(state[i], 8)) { set_error("volume %d is NULL or not 8-byte aligned", i); return DPM_EINVAL; }
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (state[i] == state[j]) { set_error("the four state volumes must be different buffers"); return DPM_EINVAL; }
+  if (!opts->io_fp64) { set_error("dpm_dd_stepper_create needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
+  if (!aligned16(opts->workspace)) { set_error("the workspace must be 16-byte aligned"); return DPM_EINVAL; }
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(chi)) { set_error("dt must be finite and > 0, chi finite"); return DPM_EINVAL; }
+  if (std::fabs(dd_sigma(dd) * dt - 1.0) > 1e-12) {
+    set_error("the handle was built with sigma = %g but 1/dt = %g", dd_sigma(dd), 1.0 / dt);
+    return DPM_EINVAL;
+  }
+  void* h = nullptr;
+  DPM_TRY(dd_stepper_create_impl(dd, dt, chi, state, *opts, &h));
+  *out = static_cast<dpm_dd_stepper*>(h);
+  return DPM_OK;
+}
+
+dpm_status dpm_dd_stepper_run(dpm_dd_stepper* st, int32_t nsteps, void* stream) {
+  clear_error();
+  if (!st) { set_error("stepper is NULL"); return DPM_EINVAL; }
+  if (nsteps < 0) { set_error("nsteps must be >= 0"); return DPM_EINVAL; }
+  return dd_stepper_run_impl(st, nsteps, static_cast<hipStream_t>(stream));
+}
+
+void dpm_dd_stepper_destroy(dpm_dd_stepper* st) { dd_stepper_destroy_impl(st); }
 
 dpm_status dpm_dd_rebuild(dpm_dd* dd, double sigma, void* stream) {
   clear_error();

@@ -786,6 +786,69 @@ dpm_status dd_run_impl(dpm_dd* d, const dpm_run_params& p, double* const state[4
   return DPM_OK;
 }
 
+// A decomposed step on fixed buffers, captured into a HIP graph: the side stream's branch joins
+// the capture through the fork and join events, so one replay runs both meshes' work.
+struct DDStepper {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+dpm_status dd_stepper_create_impl(const dpm_dd* d, double dt, double chi, double* const state[4],
+                                  const dpm_opts& o, void** out) {
+  if (timing_enabled()) {
+    set_error("dpm_dd_stepper_create: sweep timing is enabled; end it before capturing a step");
+    return DPM_EINVAL;
+  }
+  for (int l = 0; l < 2; ++l) {
+    const Plan* pl = nullptr;
+    DPM_TRY(get_plan(d->sub[l]->grid.n, &pl));  // tables exist before capture
+  }
+  hipStream_t cs = nullptr;
+  DPM_TRY_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    set_error("dpm_dd_stepper_create: hipStreamBeginCapture: %s", hipGetErrorString(e));
+    return DPM_EHIP;
+  }
+  const double* in[4] = {state[0], state[1], state[2], state[3]};
+  const dpm_status st = dd_step_impl(d, dt, chi, in, state, o, cs);
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (st != DPM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    set_error("dpm_dd_stepper_create: graph capture: %s", hipGetErrorString(e));
+    return DPM_EHIP;
+  }
+  auto* p = new DDStepper;
+  p->graph = graph;
+  p->exec = exec;
+  *out = p;
+  return DPM_OK;
+}
+
+dpm_status dd_stepper_run_impl(void* h, int nsteps, hipStream_t s) {
+  auto* p = static_cast<DDStepper*>(h);
+  for (int k = 0; k < nsteps; ++k) DPM_TRY_HIP(hipGraphLaunch(p->exec, s));
+  return DPM_OK;
+}
+
+void dd_stepper_destroy_impl(void* h) {
+  auto* p = static_cast<DDStepper*>(h);
+  if (!p) return;
+  (void)hipDeviceSynchronize();  // replays still in flight finish before the graph goes
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  delete p;
+}
+
 dpm_status dd_masks_impl(const dpm_dd* d, int l, uint8_t* m_plus, uint8_t* n_plus, hipStream_t s) {
   const dpm_bep* b = d->sub[l];
   const size_t vsz = (size_t)b->grid.n * b->grid.n * b->grid.n;

@@ -439,3 +439,37 @@ def test_dd_cube_without_margin_rejected():
         api.dd_build(api.dd2_params(15, h1, x01, (0.0, 0.0, 0.3), 31, h2, x02, (0.0, 0.0, 0.0), 1e3,
                                     1.0, 1.0, 0.5, 2.0, 2, 0, 1), device=dev)
     assert e.value.status == DPM_EGEOM
+
+
+@pytest.mark.parametrize("case_no", [1, 2])
+def test_dd_stepper_replays_equal_eager_steps(case_no):
+    """The graph-captured decomposed step (both meshes, the side stream's branch inside the graph)
+    replayed three times, with eager steps and synchronisations between the replays, equals the
+    eager steps bitwise after every replay."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    dt, chi = 1e-3, 1.0
+    if case_no == 1:
+        case = odd.DDCase(15, 0.75, 31, 0.5, 2, 2, 1)
+        prm = _params(case, 1.0 / dt, 2, 1, 2)
+        st = list(_data(case.mesh1, case.ps1)) + list(_data(case.mesh2, case.ps2))
+    else:
+        case = odd.DDCase2(15, 0.75, 0.75, 31, 1.0, 0.5, 4, 2, beta=0)
+        prm = _params2(case, 1.0 / dt)
+        st = list(_data2(case.sub[0]["mesh"], case.sub[0]["ps"])) + list(_data2(case.sub[1]["mesh"], case.sub[1]["ps"]))
+    dd = api.dd_build(prm, device=dev)
+    eager = [torch.from_numpy(v).to(dev) for v in st]
+    graph_state = [v.clone() for v in eager]
+    say(f"dd stepper case {case_no}")
+    stepper = api.DDStepper(dd, dt, chi, graph_state)
+    ws = torch.empty(dd.workspace_size(api.opts("fp64")), dtype=torch.uint8, device=dev)
+    for k in range(3):
+        api.dd_step(dd, dt, chi, eager, out=eager, workspace=ws)
+        torch.cuda.synchronize()
+        stepper.run(1)
+        torch.cuda.synchronize()
+        for a, b in zip(eager, graph_state):
+            assert torch.equal(a, b), (case_no, k)
+    stepper.close()
+    dd.close()
