@@ -196,3 +196,21 @@ def test_dd2_converges_to_single_domain():
     fine = _dd2_minus_sd(31, 63, 1.0)
     for a, b in zip(coarse, fine):
         assert b < 2e-3 and a / b > 3.5, (a, b)
+
+
+def test_dd2_least_squares_well_posed_at_test_sizes(small2):
+    """The coupled least squares of the Case 2 configurations the GPU tests use is well posed:
+    LAPACK's solution and a Householder QR's give the same step to 1e-10 (with too many harmonics
+    on Z's partial arc they do not, even when the rank test passes)."""
+    from scipy.linalg import solve_triangular
+    case = small2
+    dt = 1e-3
+    A = dd.dd2_matrix(case, 1 / dt)
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(A.shape[0])
+    c1 = np.linalg.lstsq(A, g, rcond=None)[0]
+    q, r = np.linalg.qr(A)
+    c2 = solve_triangular(r, q.T @ g)
+    for s in case.sub:
+        u1, u2 = s["B_eff"].T @ c1, s["B_eff"].T @ c2
+        assert np.max(np.abs(u1 - u2)) <= 1e-10 * np.max(np.abs(u1))
