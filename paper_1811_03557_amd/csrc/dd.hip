@@ -1,7 +1,10 @@
-// Domain decomposition of the DPM, Case 1 (paper Sec. 3: "Case 1" and "BEPs for Case 1", eqs
-// interface_condition, DD1_BEP1, DD1_BEP2, reduced_DD1_BEP1, reduced_DD1_BEP2).
+// Domain decomposition of the DPM (paper Sec. 3): Case 1 ("Case 1" and "BEPs for Case 1", eqs
+// interface_condition, DD1_BEP1, DD1_BEP2, reduced_DD1_BEP1, reduced_DD1_BEP2) and Case 2
+// ("Case 2" and "BEPs for Case 2", eqs DD2_BEP, reduced_DD2_BEP, effective densities; below,
+// from k_dd2_classify on), one handle type and one step for both, plus the adaptive loop and a
+// graph-captured fixed-dt loop on the decomposed domain.
 //
-// Omega_1 = {|x - c| < r_z} (the ball inside the interface sphere Z) and Omega_2 = {r_z < |x - c|
+// Case 1: Omega_1 = {|x - c| < r_z} (the ball inside the interface sphere Z) and Omega_2 = {r_z < |x - c|
 // < r_gamma} (the shell between Z and Gamma), each on its own cube and mesh.  zeta_1 (the discrete
 // grid interface of Omega_1) is Omega_1's gamma; Omega_2's gamma is the union of the discrete grid
 // boundary near Gamma and zeta_2 near Z, split at the radius r_split.  The densities are zonal
@@ -16,7 +19,9 @@
 //
 // (A_l: the reduced-BEP matrix of subdomain l on its own densities), factored once by the FP64
 // Householder QR of the single-domain path.  A step solves the particular solutions on both
-// meshes, the coupled least squares, and each subdomain's Green's formula.
+// meshes, the coupled least squares, and each subdomain's Green's formula.  In Case 2 both
+// subdomains carry all columns, wedge nodes add a second row, and each row is mapped to its
+// node (row_idx), so the same step serves both cases.
 #include <cmath>
 #include <vector>
 
@@ -26,7 +31,7 @@ struct dpm_dd {
   dpm_dd_params prm{};
   dpm_bep* sub[2] = {nullptr, nullptr};  // per subdomain: masks, gamma lists, densities, A_l
   int n_gamma_cols = 0, n_z_cols = 0, n_cols = 0;
-  int rows = 0;           // |zeta_1,in| + |gamma_2,in|
+  int rows = 0;           // reduced-BEP rows of both subdomains (Case 1: |zeta_1,in| + |gamma_2,in|)
   double* A = nullptr;    // rows x n_cols, column-major; Householder vectors below R
   double* tau = nullptr;  // n_cols
   double* P = nullptr;    // n_cols x rows least-squares operator (row nu contiguous)
