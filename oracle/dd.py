@@ -246,7 +246,7 @@ def dd2_step(rho1, c1, rho2, c2, case: DDCase2, A: np.ndarray, dt: float, chi: f
 
 
 def dd_adaptive_run(state, case, sigma0: float, chi: float, t_final: float,
-                    rho_cap: float = np.inf, max_steps: int = 1000):
+                    rho_cap: float = np.inf, max_steps: int = 1000, rho_jump_cap: float = 0.0):
     """Steps 3-8 on the decomposed domain (either case) from dt_0 = 1/sigma0: each subdomain's
     CFL-type bound on its own mesh, dt the smallest of them and of the previous dt, Step 4b (a new
     coupled matrix) when dt shrinks, Step 8 on max |rho| over both M+.  state = (rho_1, c_1,
@@ -262,7 +262,7 @@ def dd_adaptive_run(state, case, sigma0: float, chi: float, t_final: float,
     dt_prev = 1.0 / sigma0
     A = matrix(case, sigma0)                                               # Step 2
     t, dts, rebuilt, stop = 0.0, [], [], "max_steps"
-    rmax = 0.0
+    rmax = rprev = 0.0
     while True:
         if t >= t_final:
             stop = "t_final"
@@ -280,6 +280,11 @@ def dd_adaptive_run(state, case, sigma0: float, chi: float, t_final: float,
         if rmax > rho_cap:
             stop = "rho_cap"
             break
+        # Sec. 4, Test B: stop once ||rho||_inf has grown by rho_jump_cap over one step
+        if rho_jump_cap > 0 and dts and rmax - rprev >= rho_jump_cap:
+            stop = "rho_jump"
+            break
+        rprev = rmax
         dt = min(min(cfls), dt_prev)                                       # Step 3
         rb = dt < dt_prev
         if rb:                                                             # Step 4b

@@ -121,7 +121,8 @@ def dpm_step(rho, c, ps: PointSets, basis: np.ndarray, A: np.ndarray, h: float, 
 
 
 def adaptive_run(rho, c, ps: PointSets, basis: np.ndarray, h: float, sigma0: float, chi: float,
-                 t_final: float, rho_cap: float = np.inf, max_steps: int = 1000):
+                 t_final: float, rho_cap: float = np.inf, max_steps: int = 1000,
+                 rho_jump_cap: float = 0.0):
     """Steps 3-8 from dt_0 = 1/sigma0 (the step of Step 2's matrix).
 
     Returns (rho, c, summary) with summary keys steps, rebuilds, stop, t, dt, rho_max,
@@ -129,7 +130,7 @@ def adaptive_run(rho, c, ps: PointSets, basis: np.ndarray, h: float, sigma0: flo
     dt_prev = 1.0 / sigma0
     A = bep_matrix(basis, ps, sigma0, h)                               # Step 2
     t, dts, rebuilt, cfls, stop = 0.0, [], [], [], "max_steps"
-    gmax = rmax = 0.0
+    gmax = rmax = rprev = 0.0
     while True:
         if t >= t_final:
             stop = "t_final"
@@ -145,6 +146,11 @@ def adaptive_run(rho, c, ps: PointSets, basis: np.ndarray, h: float, sigma0: flo
         if rmax > rho_cap:
             stop = "rho_cap"
             break
+        # Sec. 4, Test B: stop once ||rho||_inf has grown by rho_jump_cap over one step
+        if rho_jump_cap > 0 and dts and rmax - rprev >= rho_jump_cap:
+            stop = "rho_jump"
+            break
+        rprev = rmax
         cfl = cfl_dt(c, ps.m_plus, h, chi)
         dt = min(cfl, dt_prev)
         rb = dt < dt_prev

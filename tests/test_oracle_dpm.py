@@ -266,3 +266,29 @@ def test_adaptive_rules_test_a():
     # Step 8: a threshold below the initial max |rho| stops before the first step
     _, _, s2 = pks.adaptive_run(rho, c, ps, B, h, sigma0, 1.0, t_final=1.0, rho_cap=100.0)
     assert s2["stop"] == "rho_cap" and s2["steps"] == 0 and s2["rho_max"] == np.max(rho[ps.m_plus])
+
+
+def test_adaptive_run_jump_rule():
+    """The Test B termination rule (Sec. 4): the loop stops at the first scan whose max |rho|
+    exceeds the previous scan's by at least the cap, and never when the cap is disabled.  On Test
+    B data at 15^3 max |rho| first falls (the first step is the large dt0) and then rises."""
+    n = 15
+    h, x0 = inp.grid(n)
+    z, y, x = inp.mesh(n)
+    ps = og.PointSets(og.inside_sphere(z, y, x))
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    d, th, _ = og.project_sphere(gz, gy, gx)
+    B = ob.zonal_basis_matrix(d, th, 4, beta=0)
+    rho = np.where(ps.n_plus, 2000.0 * np.exp(-100.0 * (x**2 + y**2 + (z - 0.25) ** 2)), 0.0)
+    c = np.zeros_like(rho)
+    sigma0 = 1.0 / (0.5 * h * h)
+    # the run stopped by max_steps = k reports the scan of the state after k - 1 steps
+    maxes = [pks.adaptive_run(rho, c, ps, B, h, sigma0, 1.0, 1.0, max_steps=k)[2]["rho_max"]
+             for k in range(1, 7)]
+    jumps = np.diff(maxes)         # jumps[j]: the change over step j + 1
+    first = int(np.argmax(jumps > 0))
+    cap = 0.5 * jumps[first]
+    _, _, ref = pks.adaptive_run(rho, c, ps, B, h, sigma0, 1.0, 1.0, max_steps=10, rho_jump_cap=cap)
+    assert ref["stop"] == "rho_jump" and ref["steps"] == first + 1
+    _, _, ref = pks.adaptive_run(rho, c, ps, B, h, sigma0, 1.0, 1.0, max_steps=5, rho_jump_cap=0.0)
+    assert ref["stop"] == "max_steps"
