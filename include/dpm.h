@@ -256,7 +256,8 @@ dpm_status dpm_bep_rebuild(dpm_bep* bep, double sigma, void* stream);
  * dpm_run -- the adaptive time loop of the paper's Algorithm "Main Steps" (Steps 3-8) on (rho, c)
  * in place, starting at t = 0 with the dt of the handle (dt_0 = 1/sigma: Step 2 builds with the
  * largest step, 0.5 h^2 in the paper).  Each step: scan (dpm_cfl_scan); stop if max |rho| over
- * M+ exceeds rho_cap (Step 8) or a scanned value is not finite; dt = min(h / (6 chi max|grad c|),
+ * M+ exceeds rho_cap (Step 8), has grown by at least rho_jump_cap since the previous scan, or a
+ * scanned value is not finite; dt = min(h / (6 chi max|grad c|),
  * dt_prev) (Step 3; dt never grows, so the matrix of the last rebuild always belongs to the
  * current dt); if dt < dt_prev rebuild the matrix at sigma = 1/dt (Step 4b); one dpm_step
  * (Steps 4a-7); t += dt.  The loop ends when t >= t_final, after max_steps steps, or at a stop.
@@ -270,8 +271,14 @@ typedef struct {
   double t_final;   /* final time */
   double rho_cap;   /* Step 8 threshold on max |rho| over M+ */
   int32_t max_steps;
+  double rho_jump_cap;  /* stop once max |rho| over M+ has grown by at least this much in one
+                           step (the paper's termination rule for Test B, Sec. 4: 1000); a value
+                           <= 0 disables it */
 } dpm_run_params;
-typedef enum { DPM_RUN_TFINAL = 0, DPM_RUN_MAXSTEPS = 1, DPM_RUN_RHOCAP = 2, DPM_RUN_NONFINITE = 3 } dpm_run_stop;
+typedef enum {
+  DPM_RUN_TFINAL = 0, DPM_RUN_MAXSTEPS = 1, DPM_RUN_RHOCAP = 2, DPM_RUN_NONFINITE = 3,
+  DPM_RUN_RHOJUMP = 4
+} dpm_run_stop;
 typedef struct {
   int32_t steps;     /* steps taken */
   int32_t rebuilds;  /* Step 4b rebuilds */

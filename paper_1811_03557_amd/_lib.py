@@ -34,7 +34,7 @@ class Info(C.Structure):
 
 class RunParams(C.Structure):
     _fields_ = [("chi", C.c_double), ("t_final", C.c_double), ("rho_cap", C.c_double),
-                ("max_steps", C.c_int32)]
+                ("max_steps", C.c_int32), ("rho_jump_cap", C.c_double)]
 
 
 class RunInfo(C.Structure):
@@ -43,7 +43,7 @@ class RunInfo(C.Structure):
                 ("grad_max", C.c_double)]
 
 
-RUN_STOPS = {0: "t_final", 1: "max_steps", 2: "rho_cap", 3: "nonfinite"}
+RUN_STOPS = {0: "t_final", 1: "max_steps", 2: "rho_cap", 3: "nonfinite", 4: "rho_jump"}
 
 
 class Geometry(C.Structure):

@@ -428,7 +428,8 @@ class DDStepper:
 
 def dd_run(dd: DD, chi: float, state, t_final: float, rho_cap: float = float("inf"),
            max_steps: int = 1000, prec: str = "fp64", workspace: torch.Tensor | None = None,
-           stream=None, rtol: float = 1e-10, max_refine: int = 0) -> dict:
+           stream=None, rtol: float = 1e-10, max_refine: int = 0,
+           rho_jump_cap: float = 0.0) -> dict:
     """Steps 3-8 on the decomposed domain, state = (rho_1, c_1, rho_2, c_2) in place, from
     dt = 1/dd.sigma; the run summary as for run()."""
     for v, n in zip(state, (dd.n[0], dd.n[0], dd.n[1], dd.n[1])):
@@ -441,7 +442,7 @@ def dd_run(dd: DD, chi: float, state, t_final: float, rho_cap: float = float("in
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=state[0].device)
     o.workspace = C.c_void_p(workspace.data_ptr())
     o.workspace_bytes = workspace.numel()
-    p = L.RunParams(float(chi), float(t_final), float(rho_cap), int(max_steps))
+    p = L.RunParams(float(chi), float(t_final), float(rho_cap), int(max_steps), float(rho_jump_cap))
     info = L.RunInfo()
     dts = (C.c_double * max(int(max_steps), 1))()
     rbs = (C.c_uint8 * max(int(max_steps), 1))()
@@ -585,7 +586,7 @@ def cfl_scan(bep: BEP, rho: torch.Tensor, c: torch.Tensor, stream=None) -> torch
 def run(bep: BEP, chi: float, rho: torch.Tensor, c: torch.Tensor, t_final: float,
         rho_cap: float = float("inf"), max_steps: int = 1000, prec: str = "fp64",
         rtol: float = 1e-10, max_refine: int = 0, workspace: torch.Tensor | None = None,
-        stream=None) -> dict:
+        stream=None, rho_jump_cap: float = 0.0) -> dict:
     """Steps 3-8: the adaptive time loop on (rho, c) in place, from dt = 1/bep.sigma.
 
     Returns the run summary with the per-step dt and rebuild flags; the handle then holds the
@@ -597,7 +598,7 @@ def run(bep: BEP, chi: float, rho: torch.Tensor, c: torch.Tensor, t_final: float
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=rho.device)
     o.workspace = C.c_void_p(workspace.data_ptr())
     o.workspace_bytes = workspace.numel()
-    p = L.RunParams(float(chi), float(t_final), float(rho_cap), int(max_steps))
+    p = L.RunParams(float(chi), float(t_final), float(rho_cap), int(max_steps), float(rho_jump_cap))
     info = L.RunInfo()
     dts = (C.c_double * max(int(max_steps), 1))()
     rbs = (C.c_uint8 * max(int(max_steps), 1))()

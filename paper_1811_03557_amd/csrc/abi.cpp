@@ -323,7 +323,7 @@ dpm_status dpm_run(dpm_bep* bep, const dpm_run_params* params, double* rho, doub
   }
   if (rho == c) { set_error("rho and c must be different buffers"); return DPM_EINVAL; }
   if (!(params->chi >= 0.0) || !std::isfinite(params->chi)) { set_error("chi must be finite and >= 0"); return DPM_EINVAL; }
-  if (std::isnan(params->t_final) || std::isnan(params->rho_cap)) { set_error("t_final and rho_cap must not be NaN"); return DPM_EINVAL; }
+  if (std::isnan(params->t_final) || std::isnan(params->rho_cap) || std::isnan(params->rho_jump_cap)) { set_error("t_final, rho_cap and rho_jump_cap must not be NaN"); return DPM_EINVAL; }
   if (params->max_steps < 0) { set_error("max_steps must be >= 0"); return DPM_EINVAL; }
   if (!(bep->grid.sigma > 0.0)) { set_error("the handle's sigma must be > 0 (sigma = 1/dt)"); return DPM_EINVAL; }
   return run_impl(bep, *params, rho, c, *opts, static_cast<hipStream_t>(stream), info, dt_hist,
@@ -506,7 +506,7 @@ dpm_status dpm_dd_run(dpm_dd* dd, const dpm_run_params* params, double* const st
   if (!opts->io_fp64) { set_error("dpm_dd_run needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
   if (!aligned16(opts->workspace)) { set_error("the workspace must be 16-byte aligned"); return DPM_EINVAL; }
   if (!(params->chi >= 0.0) || !std::isfinite(params->chi)) { set_error("chi must be finite and >= 0"); return DPM_EINVAL; }
-  if (std::isnan(params->t_final) || std::isnan(params->rho_cap)) { set_error("t_final and rho_cap must not be NaN"); return DPM_EINVAL; }
+  if (std::isnan(params->t_final) || std::isnan(params->rho_cap) || std::isnan(params->rho_jump_cap)) { set_error("t_final, rho_cap and rho_jump_cap must not be NaN"); return DPM_EINVAL; }
   if (params->max_steps < 0) { set_error("max_steps must be >= 0"); return DPM_EINVAL; }
   if (!(dd_sigma(dd) > 0.0)) { set_error("the handle's sigma must be > 0 (sigma = 1/dt)"); return DPM_EINVAL; }
   return dd_run_impl(dd, *params, state, *opts, static_cast<hipStream_t>(stream), info, dt_hist,

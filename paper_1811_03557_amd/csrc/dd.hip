@@ -748,6 +748,7 @@ dpm_status dd_run_impl(dpm_dd* d, const dpm_run_params& p, double* const state[4
   dpm_run_info r{};
   r.stop = DPM_RUN_MAXSTEPS;
   double t = 0.0, dt_prev = 1.0 / d->prm.grid1.sigma;
+  double rho_prev = 0.0;  // max |rho| of the previous scan (none before the first)
   const double* in[4] = {state[0], state[1], state[2], state[3]};
   for (;;) {
     if (t >= p.t_final) { r.stop = DPM_RUN_TFINAL; break; }
@@ -766,6 +767,11 @@ dpm_status dd_run_impl(dpm_dd* d, const dpm_run_params& p, double* const state[4
       break;
     }
     if (r.rho_max > p.rho_cap) { r.stop = DPM_RUN_RHOCAP; break; }
+    if (p.rho_jump_cap > 0.0 && r.steps > 0 && r.rho_max - rho_prev >= p.rho_jump_cap) {
+      r.stop = DPM_RUN_RHOJUMP;
+      break;
+    }
+    rho_prev = r.rho_max;
     double dt = dt_prev;
     for (int l = 0; l < 2; ++l)
       if (v[2 * l] > 0.0) {

@@ -431,6 +431,7 @@ dpm_status run_impl(dpm_bep* b, const dpm_run_params& p, double* rho, double* c,
   dpm_run_info r{};
   r.stop = DPM_RUN_MAXSTEPS;
   double t = 0.0, dt_prev = 1.0 / b->grid.sigma;
+  double rho_prev = 0.0;  // max |rho| of the previous scan (none before the first)
   for (;;) {
     if (t >= p.t_final) { r.stop = DPM_RUN_TFINAL; break; }
     if (r.steps >= p.max_steps) { r.stop = DPM_RUN_MAXSTEPS; break; }
@@ -443,6 +444,11 @@ dpm_status run_impl(dpm_bep* b, const dpm_run_params& p, double* rho, double* c,
     r.rho_max = v[1];
     if (!(std::isfinite(v[0]) && std::isfinite(v[1]))) { r.stop = DPM_RUN_NONFINITE; break; }
     if (v[1] > p.rho_cap) { r.stop = DPM_RUN_RHOCAP; break; }
+    if (p.rho_jump_cap > 0.0 && r.steps > 0 && v[1] - rho_prev >= p.rho_jump_cap) {
+      r.stop = DPM_RUN_RHOJUMP;
+      break;
+    }
+    rho_prev = v[1];
     double dt = dt_prev;
     if (v[0] > 0.0) {
       const double dt_cfl = b->grid.h / (6.0 * p.chi * v[0]);

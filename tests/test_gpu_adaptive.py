@@ -173,3 +173,33 @@ def test_adaptive_run_test_b():
     say(f"  {res['steps']} steps, rebuilt {res['rebuilt']}, max rho {res['rho_max']:.4e}")
     _compare(res, ref, rg, cg, ro, co)
     bep.close()
+
+
+def test_adaptive_run_jump_rule_test_b():
+    """The Test B termination rule (Sec. 4: stop once max |rho| grows by a cap over one step) on
+    Test B data at 31^3 (max |rho| 1814 -> 780 -> 948: the second step grows it by 168): with a
+    cap of 150 the loop stops after 2 steps, like the oracle's."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    n = 31
+    h, x0 = inp.grid(n)
+    z, y, x = inp.mesh(n)
+    ps = og.PointSets(og.inside_sphere(z, y, x))
+    gz, gy, gx = og.gamma_coords(ps, x0, h)
+    d, th, ph = og.project_sphere(gz, gy, gx)
+    B = ob.zonal_basis_matrix(d, th, 10, beta=0)
+    rho = np.where(ps.n_plus, 2000.0 * np.exp(-100.0 * (x**2 + y**2 + (z - 0.25) ** 2)), 0.0)
+    c = np.zeros_like(rho)
+    sigma0 = 1.0 / (0.5 * h * h)
+    ro, co, ref = opks.adaptive_run(rho, c, ps, B, h, sigma0, 1.0, 1.0, max_steps=10,
+                                    rho_jump_cap=150.0)
+    assert ref["stop"] == "rho_jump" and ref["steps"] == 2
+    m = torch.from_numpy(ps.m_plus.astype(np.uint8)).to(dev)
+    bep = api.build_boundary_matrix(m, torch.from_numpy(B).to(dev), n, h, sigma0, x0)
+    rg, cg = torch.from_numpy(rho).to(dev), torch.from_numpy(c).to(dev)
+    say("adaptive run n=31 Test B, jump cap 150")
+    res = api.run(bep, 1.0, rg, cg, t_final=1.0, max_steps=10, rho_jump_cap=150.0)
+    say(f"  {res['stop']} after {res['steps']} steps, max rho {res['rho_max']:.1f}")
+    _compare(res, ref, rg, cg, ro, co)
+    bep.close()

@@ -473,3 +473,32 @@ def test_dd_stepper_replays_equal_eager_steps(case_no):
             assert torch.equal(a, b), (case_no, k)
     stepper.close()
     dd.close()
+
+
+def test_dd2_adaptive_run_jump_rule():
+    """The Test B termination rule on the decomposed domain (Case 2, Test B data at 15/31): the
+    same stop and states as the oracle's loop."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case = odd.DDCase2(15, 0.75, 0.75, 31, 1.0, 0.5, 4, 2, beta=0)
+    dt0 = 0.5 * case.sub[1]["h"] ** 2
+    st = []
+    for s in case.sub:
+        z, y, x = s["mesh"]
+        st += [np.where(s["ps"].n_plus, 2000.0 * np.exp(-100.0 * (x * x + y * y + (z - 0.25) ** 2)), 0.0),
+               np.zeros_like(x)]
+    maxes = [odd.dd_adaptive_run(st, case, 1.0 / dt0, 1.0, 1.0, max_steps=k)[1]["rho_max"]
+             for k in range(1, 6)]
+    jumps = np.diff(maxes)
+    first = int(np.argmax(jumps > 0))
+    cap = 0.5 * jumps[first]
+    ref_state, ref = odd.dd_adaptive_run(st, case, 1.0 / dt0, 1.0, 1.0, max_steps=10, rho_jump_cap=cap)
+    assert ref["stop"] == "rho_jump" and ref["steps"] == first + 1
+    dd = api.dd_build(_params2(case, 1.0 / dt0), device=dev)
+    state = [torch.from_numpy(v).to(dev) for v in st]
+    say(f"dd2 adaptive run, jump cap {cap:.1f}")
+    res = api.dd_run(dd, 1.0, state, t_final=1.0, max_steps=10, rho_jump_cap=cap)
+    say(f"  {res['stop']} after {res['steps']} steps")
+    _adaptive_compare(res, ref, state, ref_state)
+    dd.close()
