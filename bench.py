@@ -24,7 +24,9 @@ Domain decomposition (the "domain_decomposition" object): Case 1 on the Test A s
 ball on a 127^3 mesh and the shell on a 63^3 mesh, against the single domain at 255^3 with the
 same fine spacing: build and per-step times and their ratio.  The "domain_decomposition_case2"
 object: Case 2 (Z meets Gamma) on the Test B setup at 127/63 (150 harmonics on Gamma, 6 on Z),
-against the single domain at 255^3.
+against the single domain at 255^3.  The "paper_geometry" object: the paper's own setup (the
+ball of radius 0.5 in a cube two mesh widths wider), Test A to t = 6e-5 on the single domain at
+255^3 and Case 1 at 127/63 (R_S for the run), and Test B at 127^3 to the paper's stopping rule.
 
 Prints one JSON line on stdout (everything else goes to stderr).
 """
@@ -547,6 +549,94 @@ def oracle_by_n(args, dev, oaux, cores):
     return out
 
 
+def run_paper_geometry(args, dev):
+    """The paper's own setup (Sec. 4): Omega the ball of radius r = 0.5 in the cube
+    [-r - 2h, r + 2h]^3 (N interior nodes per axis, h = 2r/(N - 3), the paper's h = 2r/(N_cells - 4)),
+    dt0 = 0.5 h^2, the adaptive loop (Steps 3-8) throughout.
+    (i) Test A to t = 6e-5, the paper's speed-up comparison (Table 6): the single domain at
+        N = 255 against Case 1 at N1/N2 = 127/63 (Z of radius 0.25, h1 = 2 r1/(N1 - 3),
+        h2 = 2r/(N2 - 3)), one zonal harmonic per term: wall times, steps, rebuilds, max |rho|,
+        R_S = T_SD / T_DD.
+    (ii) Test B to the paper's stopping rule (the change of ||rho||_inf over one step >= 1000),
+        single domain at N = 127 with 150 zonal harmonics and the 2-term extension: steps,
+        rebuilds, final time, max |rho| and where it sits, min |rho|, wall time."""
+    import torch
+    from paper_1811_03557_amd import api
+    r, r1, t_end = 0.5, 0.25, 6e-5
+    geo = api.geometry("sphere", axes=(r,))
+    out = {"workload": "ball of radius 0.5 in [-r - 2h, r + 2h]^3, h = 2r/(N - 3), dt0 = 0.5 h^2; "
+                       "Test A to t = 6e-5 (SD 255 vs DD 127/63, one zonal harmonic per term); "
+                       "Test B to the stop rule (SD 127, 150 zonal harmonics, 2-term)"}
+    n = 255
+    h = 2 * r / (n - 3)
+    x0 = -(r + 2 * h) + h
+    n1, n2 = 127, 63
+    h1, h2 = 2 * r1 / (n1 - 3), 2 * r / (n2 - 3)
+    dt0 = 0.5 * min(h, h1) ** 2
+    m = api.classify(n, h, x0, geo, device=dev)
+    idx, _ = api.gamma_points(m, h, x0)
+    B, _ = api.basis_zonal(n, h, x0, geo, idx, 0, 1)
+    bep = api.build_boundary_matrix(m, B, n, h, 1.0 / dt0, x0)
+    rho = api.gauss_state(bep, geo, 1000.0, 100.0)
+    c = api.gauss_state(bep, geo, 500.0, 50.0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = api.run(bep, 1.0, rho, c, t_final=t_end, max_steps=100000)
+    torch.cuda.synchronize()
+    s_sd = time.perf_counter() - t
+    sd = {"n": n, "h": h, "run_s": round(s_sd, 4), "steps": res["steps"], "rebuilds": res["rebuilds"],
+          "t": res["t"], "rho_max": res["rho_max"], "diagnostics": api.diagnostics(bep, rho, c).tolist()}
+    bep.close()
+    del m, idx, B, rho, c
+    prm = api.dd_params(n1, h1, -(r1 + 2 * h1) + h1, n2, h2, -(r + 2 * h2) + h2, 1.0 / dt0, r1, r,
+                        0.5 * (r1 + r), 0, 1, 0)
+    dd = api.dd_build(prm, device=dev)
+    state = [dd.gauss_state(l, a, k) for l in (0, 1) for a, k in ((1000.0, 100.0), (500.0, 50.0))]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = api.dd_run(dd, 1.0, state, t_final=t_end, max_steps=100000)
+    torch.cuda.synchronize()
+    s_dd = time.perf_counter() - t
+    ddr = {"n": [n1, n2], "h": [h1, h2], "run_s": round(s_dd, 4), "steps": res["steps"],
+           "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"],
+           "diagnostics": api.dd_diagnostics(dd, state).tolist()}
+    dd.close()
+    del state
+    out["test_a"] = {"sd_255": sd, "dd_127_63": ddr, "R_S_run": round(s_sd / s_dd, 2)}
+    log(f"[bench] paper geometry, Test A to t = 6e-5: SD 255 {sd['steps']} steps "
+        f"({sd['rebuilds']} rebuilds) {s_sd:.3f} s, DD 127/63 {ddr['steps']} steps "
+        f"({ddr['rebuilds']} rebuilds) {s_dd:.3f} s, R_S {s_sd / s_dd:.2f}; max rho "
+        f"{sd['rho_max']:.4e} / {ddr['rho_max']:.4e}")
+    # Test B, single domain at N = 127, to the stopping rule
+    n = 127
+    h = 2 * r / (n - 3)
+    x0 = -(r + 2 * h) + h
+    dt0 = 0.5 * h * h
+    m = api.classify(n, h, x0, geo, device=dev)
+    idx, _ = api.gamma_points(m, h, x0)
+    B, _ = api.basis_zonal(n, h, x0, geo, idx, 149, 0)
+    bep = api.build_boundary_matrix(m, B, n, h, 1.0 / dt0, x0)
+    rho = api.gauss_state(bep, geo, 2000.0, 100.0, center=(0.0, 0.0, 0.25))
+    c = torch.zeros_like(rho)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = api.run(bep, 1.0, rho, c, t_final=1.0, max_steps=100000, rho_jump_cap=1000.0)
+    torch.cuda.synchronize()
+    s_b = time.perf_counter() - t
+    mm = m.bool()
+    i = int(torch.argmax(torch.where(mm, rho, torch.zeros_like(rho))))
+    at = [x0 + h * (i % n), x0 + h * ((i // n) % n), x0 + h * (i // (n * n))]
+    out["test_b"] = {"n": n, "h": h, "harmonics": 150, "stop": res["stop"], "steps": res["steps"],
+                     "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"],
+                     "argmax_xyz": [round(v, 5) for v in at], "rho_min": float(rho[mm].min()),
+                     "run_s": round(s_b, 3), "diagnostics": api.diagnostics(bep, rho, c).tolist()}
+    log(f"[bench] paper geometry, Test B (SD 127, 150 harmonics): {res['stop']} after "
+        f"{res['steps']} steps ({res['rebuilds']} rebuilds) at t = {res['t']:.5f}, max rho "
+        f"{res['rho_max']:.4e} at {[round(v, 4) for v in at]}, {s_b:.2f} s")
+    bep.close()
+    return out
+
+
 def run_boundary_matrix(args, dev):
     """Step 2 of the method at 127^3: the 242-column reduced-BEP matrix of the unit sphere
     (real Y_lm, l <= 10, beta = 1), sigma = 2/h^2, built and QR-factored by one
@@ -733,6 +823,7 @@ def main():
     test_b = run_test_b(args, dev) if args.adaptive_steps > 0 and not args.no_bmat else None
     dd = run_dd(args, dev) if args.dd_steps > 0 else None
     dd2 = run_dd2(args, dev) if args.dd_steps > 0 else None
+    paper = run_paper_geometry(args, dev) if args.dd_steps > 0 and not args.no_bmat else None
 
     ok = {k: v for k, v in results.items() if v["rel_err_sample"] <= args.rtol}
     best_name = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else None
@@ -779,6 +870,7 @@ def main():
         "test_b": test_b,
         "domain_decomposition": dd,
         "domain_decomposition_case2": dd2,
+        "paper_geometry": paper,
         "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
         "alg_hbm_frac": (round(best["solves_per_s"] * 16 * vol / (HBM_PEAK_GBS * 1e9), 4)
                          if best else None),
