@@ -509,7 +509,6 @@ dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStrea
   const double z_star = (rg * rg + qz * qz - rz * rz) / (2.0 * qz);
   const double theta_star = std::acos(z_star / rg), psi_star = std::acos((qz - z_star) / rz);
   uint8_t** parts = d->parts;  // kept for rebuilds; freed with the handle
-  auto free_parts = [&]() {};
   for (int l = 0; l < 2; ++l) {
     const dpm_grid& g = l == 0 ? prm.grid1 : prm.grid2;
     const double* org = l == 0 ? prm.origin1 : prm.origin2;
@@ -526,24 +525,24 @@ dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStrea
       (void)hipFree(unc);
     };
     if (hipMalloc(&m, vsz) != hipSuccess || hipMalloc(&unc, sizeof(int)) != hipSuccess) {
-      release(); free_parts();
+      release();
       set_error("dpm_dd2_build: device allocation failed");
       return fail(DPM_ENOMEM);
     }
     hipLaunchKernelGGL(k_dd2_classify, dim3(blocks_for(vsz)), dim3(kB), 0, s, g.n, g.h, g.x0, G, m);
     int32_t ng = 0, nin = 0;
     dpm_status st = gamma_points_impl(g, m, &ng, &nin, nullptr, nullptr, s);
-    if (st != DPM_OK) { release(); free_parts(); return fail(st); }
+    if (st != DPM_OK) { release(); return fail(st); }
     const int nb = d->n_cols;
     if (hipMalloc(&idx, sizeof(int32_t) * ng) != hipSuccess || hipMalloc(&is_in, ng) != hipSuccess ||
         hipMalloc(&basis, sizeof(double) * (size_t)nb * ng) != hipSuccess ||
         hipMalloc(&parts[l], ng) != hipSuccess) {
-      release(); free_parts();
+      release();
       set_error("dpm_dd2_build: device allocation failed");
       return fail(DPM_ENOMEM);
     }
     st = gamma_points_impl(g, m, &ng, &nin, idx, is_in, s);
-    if (st != DPM_OK) { release(); free_parts(); return fail(st); }
+    if (st != DPM_OK) { release(); return fail(st); }
     const double eps = prm.eps_layers * g.h;
     const double theta_win = l == 0 ? theta_star + eps / rg : theta_star - eps / rg;
     const double psi_win = psi_star + eps / rz;
@@ -558,12 +557,12 @@ dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStrea
     if (e == hipSuccess) e = hipMemcpyAsync(&uncovered, unc, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-      release(); free_parts();
+      release();
       set_error("dpm_dd2_build: %s", hipGetErrorString(e));
       return fail(DPM_EHIP);
     }
     if (uncovered > 0) {
-      release(); free_parts();
+      release();
       set_error("dpm_dd2_build: %d nodes of subdomain %d's discrete boundary lie in neither gamma_l "
                 "nor zeta_l: raise eps_layers", uncovered, l + 1);
       return fail(DPM_EGEOM);
@@ -571,7 +570,7 @@ dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStrea
     st = build_bep_impl(g, m, nb, basis, o, s, &d->sub[l], nullptr, false);
     (void)hipStreamSynchronize(s);
     release();
-    if (st != DPM_OK) { free_parts(); return fail(st); }
+    if (st != DPM_OK) return fail(st);
   }
   // rows: gamma_in nodes in ascending index, a Gamma row and then a Z row at wedge nodes
   std::vector<int32_t> rn[2];
@@ -583,7 +582,6 @@ dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStrea
     if (e == hipSuccess) e = hipMemcpy(pos.data(), b->pos_in, sizeof(int32_t) * b->n_in, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(idx_in.data(), b->idx_in, sizeof(int32_t) * b->n_in, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
-      free_parts();
       set_error("dpm_dd2_build: %s", hipGetErrorString(e));
       return fail(DPM_EHIP);
     }
@@ -596,14 +594,12 @@ dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStrea
     d->m_rows[l] = (int)ridx.size();
     if (hipMalloc(&d->row_idx[l], sizeof(int32_t) * (ridx.size() + 1)) != hipSuccess ||
         hipMemcpy(d->row_idx[l], ridx.data(), sizeof(int32_t) * ridx.size(), hipMemcpyHostToDevice) != hipSuccess) {
-      free_parts();
       set_error("dpm_dd2_build: device allocation or copy failed");
       return fail(DPM_ENOMEM);
     }
   }
   d->rows = d->m_rows[0] + d->m_rows[1];
   if (d->n_cols > d->rows) {
-    free_parts();
     set_error("dpm_dd2_build: %d columns exceed the %d rows of the coupled BEP", d->n_cols, d->rows);
     return fail(DPM_ERANK);
   }
