@@ -502,3 +502,41 @@ def test_dd2_adaptive_run_jump_rule():
     say(f"  {res['stop']} after {res['steps']} steps")
     _adaptive_compare(res, ref, state, ref_state)
     dd.close()
+
+
+@pytest.mark.parametrize("case_no", [1, 2])
+def test_dd_full_size_constant_state(case_no):
+    """The timed configurations at full size, 127/63: Case 1 (ball r < 0.5 on [-0.75, 0.75]^3, the
+    shell on [-1.5, 1.5]^3, one zonal harmonic per term) and Case 2 (the cap around the north pole
+    with the paper's 150 zonal harmonics on Gamma and 6 on Z, tolerance 2 mesh widths).  A
+    constant state is an exact discrete solution whatever the size (P_0 represents it on Gamma
+    and on Z): rho stays 3 and c moves to (1 - dt) 5 + 3 dt on both N+, zero elsewhere.  Bound:
+    the coupled least squares is consistent here, so the error is rounding amplified by the
+    matrix's conditioning (min/max |R_ii| 1e-7 for Case 2): 1e-8 relative."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    n1, n2 = 127, 63
+    h1, h2 = 1.5 / (n1 + 1), 3.0 / (n2 + 1)
+    dt = 0.5 * h1 * h1
+    if case_no == 1:
+        prm = api.dd_params(n1, h1, -0.75 + h1, n2, h2, -1.5 + h2, 1.0 / dt, 0.5, 1.0, 0.75, 0, 1, 0)
+    else:
+        prm = api.dd2_params(n1, h1, -0.75 + h1, (0.0, 0.0, 0.75), n2, h2, -1.5 + h2,
+                             (0.0, 0.0, 0.0), 1.0 / dt, 1.0, 1.0, 0.5, 2.0, 149, 0, 5)
+    say(f"dd case {case_no} full size 127/63 constant state")
+    dd = api.dd_build(prm, device=dev)
+    npl = [dd.masks(l)[1].bool() for l in (0, 1)]
+    state = []
+    for m in npl:
+        state += [torch.where(m, 3.0, 0.0).to(torch.float64), torch.where(m, 5.0, 0.0).to(torch.float64)]
+    out = api.dd_step(dd, dt, 1.0, state)
+    cn = (1 - dt) * 5.0 + dt * 3.0
+    for l, m in enumerate(npl):
+        r, c = out[2 * l], out[2 * l + 1]
+        er = float((r[m] - 3.0).abs().max()) / 3.0
+        ec = float((c[m] - cn).abs().max()) / cn
+        say(f"  subdomain {l + 1}: rel err rho {er:.2e}, c {ec:.2e}")
+        assert er <= 1e-8 and ec <= 1e-8, (l, er, ec)
+        assert int((r[~m] != 0).sum()) == 0 and int((c[~m] != 0).sum()) == 0
+    dd.close()
