@@ -540,3 +540,62 @@ def test_dd_full_size_constant_state(case_no):
         assert er <= 1e-8 and ec <= 1e-8, (l, er, ec)
         assert int((r[~m] != 0).sum()) == 0 and int((c[~m] != 0).sum()) == 0
     dd.close()
+
+
+def _full_size_case(case_no):
+    """The timed configurations: Case 1 with one zonal harmonic per term, Case 2 with the
+    paper's 150 zonal harmonics on Gamma and 6 on Z, both on the 127/63 meshes."""
+    n1, n2 = 127, 63
+    if case_no == 1:
+        case = odd.DDCase(n1, 0.75, n2, 0.5, 0, 0, 1)
+        h1 = case.h1
+    else:
+        case = odd.DDCase2(n1, 0.75, 0.75, n2, 1.0, 0.5, 149, 5, beta=0)
+        h1 = case.sub[0]["h"]
+    return case, 0.5 * h1 * h1
+
+
+@pytest.mark.parametrize("case_no", [1, 2])
+def test_dd_full_size_matches_oracle(case_no):
+    """Full-size parity at 127/63 (the configurations the bench times): point sets bit-exact, the
+    stacked matrix, and one step of Gaussian data, all against the oracle.
+    Tolerances: the matrix comes from FP64 AP solves (1e-14 each), so 1e-10 as at small sizes.
+    The step goes through the coupled least squares. Case 1 (5 columns) is well conditioned:
+    1e-10. Case 2 has min/max |R_ii| near 1e-7, which amplifies rounding (1e-16) to about 1e-9:
+    the step gets 1e-9 (measured 2e-12)."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case, dt = _full_size_case(case_no)
+    chi = 1.0
+    say(f"dd case {case_no} full size 127/63 against the oracle")
+    if case_no == 1:
+        prm = _params(case, 1.0 / dt, 0, 1, 0)
+        subs = [(case.mesh1, case.ps1), (case.mesh2, case.ps2)]
+        A_ref = odd.dd_matrix(case, 1.0 / dt)
+        data, step, tol_step = _data, odd.dd_step, 1e-10
+    else:
+        prm = _params2(case, 1.0 / dt)
+        subs = [(s["mesh"], s["ps"]) for s in case.sub]
+        A_ref = odd.dd2_matrix(case, 1.0 / dt)
+        data, step, tol_step = _data2, odd.dd2_step, 1e-9
+    dd, A = api.dd_build(prm, return_A=True, device=dev)
+    for l, (_, ps) in enumerate(subs):
+        mp, np_ = dd.masks(l)
+        assert np.array_equal(mp.cpu().numpy().astype(bool), ps.m_plus)
+        assert np.array_equal(np_.cpu().numpy().astype(bool), ps.n_plus)
+    assert A.shape == A_ref.shape
+    err = np.max(np.abs(A.cpu().numpy() - A_ref)) / np.max(np.abs(A_ref))
+    say(f"  matrix {A_ref.shape}: rel err {err:.2e}; min/max |R_ii| {dd.rdiag[0] / dd.rdiag[1]:.2e}")
+    assert err <= 1e-10
+    del A
+    st = []
+    for mesh, ps in subs:
+        st += list(data(mesh, ps))
+    ref = step(*st, case, A_ref, dt, chi)[:4]
+    out = api.dd_step(dd, dt, chi, [torch.from_numpy(v).to(dev) for v in st])
+    for k, (g, o) in enumerate(zip(out, ref)):
+        e = np.max(np.abs(g.cpu().numpy() - o)) / np.max(np.abs(o))
+        say(f"  step output {k}: rel err {e:.2e}")
+        assert e <= tol_step, (k, e)
+    dd.close()
