@@ -637,6 +637,29 @@ def run_paper_geometry(args, dev):
     return out
 
 
+def run_autotune(args, b, h, dev):
+    """The launch-width autotuner on the headline batch: every candidate width (right-hand sides
+    per sweep launch) timed as the best of 3 batched FP64 solves, against the library's default
+    (the width whose FP64 volumes fill the 256 MB Infinity Cache).  Runs after every other
+    measurement and resets the recorded width afterwards, so no figure above depends on it."""
+    import torch
+    from paper_1811_03557_amd import api
+    nrhs, n = int(b.shape[0]), int(b.shape[1])
+    api.autotune_reset()
+    default = api.rhs_chunk(api.grid(n, h, args.sigma), nrhs, api.opts("fp64"))
+    res = api.autotune(b, args.sigma, h, prec="fp64", reps=3)
+    api.autotune_reset()
+    torch.cuda.synchronize()
+    by = dict(zip(res["widths"], res["ms"]))
+    out = {"workload": f"aux solve {n}^3, {nrhs} RHS, FP64", "default_width": default,
+           "best_width": res["best"],
+           "ms_per_batch": {str(w): round(t, 3) for w, t in by.items()},
+           "solves_per_s": {str(w): round(nrhs / (t * 1e-3), 1) for w, t in by.items()}}
+    log(f"[bench] autotune {n}^3 x {nrhs} FP64: best width {res['best']} (default {default}); "
+        + ", ".join(f"{w}: {t:.2f} ms" for w, t in by.items()))
+    return out
+
+
 def run_boundary_matrix(args, dev):
     """Step 2 of the method at 127^3: the 242-column reduced-BEP matrix of the unit sphere
     (real Y_lm, l <= 10, beta = 1), sigma = 2/h^2, built and QR-factored by one
@@ -696,6 +719,9 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run 3 plain device copies of this many bytes (calibrates the "
                          "HBM traffic counters against a kernel of known traffic)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="after the measurements, run the launch-width autotuner on the headline "
+                         "batch (FP64) and report every candidate's time beside the default width")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -875,6 +901,8 @@ def main():
         "alg_hbm_frac": (round(best["solves_per_s"] * 16 * vol / (HBM_PEAK_GBS * 1e9), 4)
                          if best else None),
     }
+    if args.autotune:
+        line["autotune"] = run_autotune(args, b, h, dev)
     print(json.dumps(line), flush=True)
 
 

@@ -82,6 +82,40 @@ dpm_status dpm_workspace_size(const dpm_grid* grid, int32_t nrhs, const dpm_opts
  * these options (opts->rhs_chunk if set, else the library's choice for the grid size). */
 dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, int32_t* chunk);
 
+/* Autotuner of the batched launches' width: the number of right-hand sides a sweep launch
+ * carries.  The kernels' tiles are fixed at compile time; this width is the launch shape
+ * chosen at run time.  It sets the launch count and how much of a launch's working set the 256 MB
+ * Infinity Cache holds, so the best value depends on n, the precision and the chip.  (The width
+ * suits the batched right-hand sides of the boundary-matrix build, Step 2 of the paper's
+ * algorithm, and any batch of auxiliary problems.)
+ *
+ * Times aux_solve_batched(grid, nrhs, b, u, opts) for each candidate width in
+ * {1, 2, 3, 4, 6, 8, 12, 16} that is at most nrhs, whose workspace fits
+ * opts->workspace_bytes, and (for options that keep a transform workspace: FP32 with FP64 I/O,
+ * refined FP64, BF16X3) at most the library's default width, so that a workspace sized before
+ * tuning stays large enough.  opts->rhs_chunk is ignored.  Each candidate takes one untimed solve,
+ * then `reps` solves timed with HIP events on `stream`; the fastest is kept, and ties keep the
+ * narrower width.
+ *
+ * The winning width is recorded for (current device, n, prec, io_fp64, max_refine > 0).  From
+ * then on every solve with opts->rhs_chunk == 0 uses it, as do dpm_workspace_size and
+ * dpm_rhs_chunk.  A solve's results do not depend on the width; only its speed does.
+ *
+ * b and u are caller-owned device arrays as for aux_solve_batched, and u is overwritten with
+ * the solution.  The outputs are host arrays, each nullable: widths[8] and ms[8] (each candidate's
+ * best time per batched solve, in ms), *count (candidates timed) and *best (the width recorded).
+ * The call synchronises the stream.
+ *
+ * Errors: those of aux_solve_batched; DPM_EINVAL for reps outside [1, 100], for a workspace that
+ * fits no candidate, or while sweep timing is on.  The table is process-wide and guarded by a
+ * lock; a solve that runs while tuning is under way takes either the old width or the new. */
+dpm_status dpm_autotune(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, const void* b,
+                        void* u, int32_t reps, void* stream, int32_t* widths, double* ms,
+                        int32_t* count, int32_t* best);
+
+/* Forgets every recorded width: solves go back to the library's default widths. */
+void dpm_autotune_reset(void);
+
 /* Builds the per-(device, n) tables (sine/twiddle and eigenvalue tables) ahead of time.  The
  * first solve of a size does this by itself; call it first when that solve is captured into a
  * HIP graph, since building uploads with synchronous copies. */

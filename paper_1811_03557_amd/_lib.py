@@ -116,6 +116,9 @@ SIGNATURES = {
     "dpm_last_error": (C.c_char_p, []),
     "dpm_timing_begin": (C.c_int, [_I, _I]),
     "dpm_rhs_chunk": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(Opts), C.POINTER(_I)]),
+    "dpm_autotune": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(Opts), _P, _P, _I, _P, _P, _P, _P,
+                               _P]),
+    "dpm_autotune_reset": (None, []),
     "dpm_timing_end": (C.c_int, [_I, C.POINTER(_I), C.POINTER(_D)]),
 }
 

@@ -97,6 +97,45 @@ def aux_solve_batched(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64
     return res
 
 
+def autotune(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64", rtol: float = 1e-10,
+             max_refine: int = 0, reps: int = 3, out: torch.Tensor | None = None,
+             stream=None) -> dict:
+    """Time the batched solve of b (nrhs, n, n, n) at each candidate launch width (right-hand
+    sides per sweep launch) and record the fastest for this device, size and precision; later
+    solves with rhs_chunk = 0 use it.  Returns {"widths", "ms", "best"}, with ms the best time
+    per batched solve.  u (out, or a new tensor) receives the solution.  Synchronises the stream."""
+    lib = L.load()
+    if b.dim() != 4 or not (b.shape[1] == b.shape[2] == b.shape[3]):
+        raise ValueError("b must have shape (nrhs, n, n, n)")
+    nrhs, n = int(b.shape[0]), int(b.shape[1])
+    io_fp64 = b.dtype == torch.float64
+    if not io_fp64 and b.dtype != torch.float32:
+        raise ValueError("b must be float64 or float32")
+    if out is None:
+        out = torch.empty_like(b)
+    g = grid(n, h, sigma)
+    # a workspace for the widest candidate fits every narrower one
+    nbytes = workspace_size(g, nrhs, opts(prec, io_fp64, rtol, max_refine, min(16, nrhs)))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=b.device)
+    o = opts(prec, io_fp64, rtol, max_refine, 0)
+    o.workspace = C.c_void_p(ws.data_ptr())
+    o.workspace_bytes = ws.numel()
+    widths = (C.c_int32 * 8)()
+    ms = (C.c_double * 8)()
+    count, best = C.c_int32(0), C.c_int32(0)
+    L.check(lib.dpm_autotune(C.byref(g), nrhs, C.byref(o), C.c_void_p(_dev(b, "b")),
+                             C.c_void_p(_dev(out, "u", b.dtype)), int(reps),
+                             C.c_void_p(_stream(stream)), widths, ms, C.byref(count),
+                             C.byref(best)))
+    k = count.value
+    return {"widths": list(widths[:k]), "ms": list(ms[:k]), "best": best.value}
+
+
+def autotune_reset() -> None:
+    """Forget every recorded launch width (solves go back to the library's defaults)."""
+    L.load().dpm_autotune_reset()
+
+
 def aux_solve_batched_sigma(b: torch.Tensor, sigmas, h: float, prec: str = "fp64",
                             rtol: float = 1e-10, max_refine: int = 0,
                             out: torch.Tensor | None = None,

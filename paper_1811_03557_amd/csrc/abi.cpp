@@ -96,6 +96,30 @@ dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opt
   return DPM_OK;
 }
 
+dpm_status dpm_autotune(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, const void* b,
+                        void* u, int32_t reps, void* stream, int32_t* widths, double* ms,
+                        int32_t* count, int32_t* best) {
+  clear_error();
+  DPM_TRY(validate_grid(grid));
+  DPM_TRY(validate_opts(*grid, opts));
+  if (nrhs <= 0) { set_error("nrhs must be > 0"); return DPM_EINVAL; }
+  if (reps < 1 || reps > 100) { set_error("reps must be in [1, 100]"); return DPM_EINVAL; }
+  if (!b || !u) { set_error("b or u is NULL"); return DPM_EINVAL; }
+  if (!aligned_to(b, opts->io_fp64 ? 8 : 4) || !aligned_to(u, opts->io_fp64 ? 8 : 4) ||
+      !aligned16(opts->workspace)) {
+    set_error("b and u must be aligned to their element size, the workspace to 16 bytes");
+    return DPM_EINVAL;
+  }
+  const size_t bytes = (size_t)nrhs * grid->n * grid->n * grid->n * (opts->io_fp64 ? 8 : 4);
+  const char* bb = static_cast<const char*>(b);
+  const char* ub = static_cast<const char*>(u);
+  if (bb < ub + bytes && ub < bb + bytes) { set_error("b and u overlap"); return DPM_EINVAL; }
+  return autotune_impl(*grid, nrhs, *opts, b, u, reps, static_cast<hipStream_t>(stream), widths,
+                       ms, count, best);
+}
+
+void dpm_autotune_reset(void) { autotune_reset(); }
+
 dpm_status aux_solve_batched(const dpm_grid* grid, int32_t nrhs, const void* b, void* u,
                              const dpm_opts* opts, void* stream, dpm_info* info) {
   clear_error();

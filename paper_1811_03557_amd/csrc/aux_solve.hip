@@ -1,6 +1,9 @@
 // Driver of the auxiliary-problem solve: sweep sequence, FP64 iterative refinement with a
 // device-side stop test (no host synchronisation, fixed launch count), batching in chunks.
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "common.h"
 
@@ -87,13 +90,35 @@ int real_bytes_of(const dpm_opts& o) {
   return (o.prec == DPM_FP64 || o.prec == DPM_FP64_GEMM) ? 8 : 4;
 }
 
+// Widths recorded by the autotuner, per (device, n, precision, I/O type, refinement on/off).
+using TuneKey = std::tuple<int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+
+TuneKey tune_key(int n, const dpm_opts& o) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return TuneKey(dev, n, o.prec, o.io_fp64 != 0, o.max_refine > 0);
+}
+
+int tuned_width(int n, const dpm_opts& o) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tuned.empty()) return 0;  // nothing tuned: no device query
+  const auto it = g_tuned.find(tune_key(n, o));
+  return it == g_tuned.end() ? 0 : it->second;
+}
+
 }  // namespace
 
 size_t flags_bytes(int nrhs) { return flag_layout(nrhs).total; }
 
+// Right-hand sides per launch: opts->rhs_chunk if set, else the width the autotuner recorded for
+// these options, else the default; never more than nrhs.
 int rhs_chunk_of(const dpm_grid& g, int nrhs, const dpm_opts& o) {
-  return o.rhs_chunk > 0 ? (o.rhs_chunk < nrhs ? o.rhs_chunk : nrhs)
-                         : default_chunk(g.n, nrhs, real_bytes_of(o), needs_ws(o));
+  if (o.rhs_chunk > 0) return o.rhs_chunk < nrhs ? o.rhs_chunk : nrhs;
+  const int t = tuned_width(g.n, o);
+  if (t > 0) return t < nrhs ? t : nrhs;
+  return default_chunk(g.n, nrhs, real_bytes_of(o), needs_ws(o));
 }
 
 dpm_status validate_grid(const dpm_grid* g) {
@@ -143,7 +168,7 @@ dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o) {
 dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes) {
   const int rb = real_bytes_of(o);
   const bool ws = needs_ws(o);
-  int chunk = o.rhs_chunk > 0 ? (o.rhs_chunk < nrhs ? o.rhs_chunk : nrhs) : default_chunk(g.n, nrhs, rb, ws);
+  const int chunk = rhs_chunk_of(g, nrhs, o);
   size_t vol = (size_t)g.n * g.n * g.n;
   size_t total = flags_bytes(nrhs);
   if (ws) total += align_up(vol * (size_t)chunk * (size_t)rb, 256);
@@ -206,8 +231,7 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
   const int rb = real_bytes_of(o);
   const int form = o.prec == DPM_BF16X3 ? FORM_BF16X3 : o.prec == DPM_FP64_GEMM ? FORM_F64MM : FORM_FFT;
   const bool ws_needed = needs_ws(o);
-  const int chunk = o.rhs_chunk > 0 ? (o.rhs_chunk < nrhs ? o.rhs_chunk : nrhs)
-                                    : default_chunk(g.n, nrhs, rb, ws_needed);
+  const int chunk = rhs_chunk_of(g, nrhs, o);
   size_t need = 0;
   DPM_TRY(workspace_size_impl(g, nrhs, o, &need));
   if (o.workspace_bytes < need || (need > 0 && o.workspace == nullptr)) {
@@ -297,6 +321,92 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
     }
   }
   return DPM_OK;
+}
+
+
+// Autotuner of the launch width.  The sweep kernels' tiles are fixed at compile time; the number
+// of right-hand sides a sweep launch carries is the shape chosen at run time.  It trades the
+// launch count against how much of the batch's working set stays in the 256 MB Infinity Cache,
+// so the best width depends on the size, the precision and the chip, and is measured here.
+const int kTuneWidths[kTuneMaxWidths] = {1, 2, 3, 4, 6, 8, 12, 16};
+
+dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const void* b, void* u,
+                         int reps, hipStream_t s, int32_t* widths, double* ms, int32_t* count,
+                         int32_t* best) {
+  if (timing_enabled()) {
+    set_error("dpm_autotune: sweep timing is enabled; end it before tuning");
+    return DPM_EINVAL;
+  }
+  // with a transform workspace, stay at or below the default width, so that a workspace sized
+  // for the default (before tuning) fits every width the tuner may record
+  const int cap = needs_ws(o) ? default_chunk(g.n, 1 << 30, real_bytes_of(o), true) : (1 << 30);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.erase(tune_key(g.n, o));
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    set_error("dpm_autotune: event creation failed");
+    return DPM_EHIP;
+  }
+  int n_out = 0, w_best = 0;
+  double t_best = 0.0;
+  dpm_status st = DPM_OK;
+  for (int w : kTuneWidths) {
+    if (w > nrhs || w > cap) continue;
+    dpm_opts ow = o;
+    ow.rhs_chunk = w;
+    size_t need = 0;
+    st = workspace_size_impl(g, nrhs, ow, &need);
+    if (st != DPM_OK) break;
+    if (need > o.workspace_bytes) continue;
+    st = aux_solve_impl(g, nrhs, b, u, ow, s, nullptr);  // untimed: first-touch and caches
+    if (st != DPM_OK) break;
+    double t = 0.0;
+    for (int r = 0; r < reps && st == DPM_OK; ++r) {
+      hipError_t e = hipEventRecord(e0, s);
+      if (e == hipSuccess) st = aux_solve_impl(g, nrhs, b, u, ow, s, nullptr);
+      if (st != DPM_OK) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float el = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
+      if (e != hipSuccess) {
+        set_error("dpm_autotune: %s", hipGetErrorString(e));
+        st = DPM_EHIP;
+        break;
+      }
+      if (r == 0 || el < t) t = el;
+    }
+    if (st != DPM_OK) break;
+    if (widths) widths[n_out] = w;
+    if (ms) ms[n_out] = t;
+    ++n_out;
+    if (w_best == 0 || t < t_best) {  // ties keep the narrower width
+      w_best = w;
+      t_best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != DPM_OK) return st;
+  if (w_best == 0) {
+    set_error("dpm_autotune: the workspace (%zu bytes) fits no candidate width", o.workspace_bytes);
+    return DPM_EINVAL;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[tune_key(g.n, o)] = w_best;
+  }
+  if (count) *count = n_out;
+  if (best) *best = w_best;
+  return DPM_OK;
+}
+
+void autotune_reset() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.clear();
 }
 
 }  // namespace dpm

@@ -122,6 +122,12 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u,
 // Right-hand sides per sweep launch that a solve of nrhs right-hand sides uses.
 int rhs_chunk_of(const dpm_grid& g, int nrhs, const dpm_opts& o);
 dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes);
+// Launch-width autotuner (see dpm_autotune): candidate widths, timing, the recorded widths.
+constexpr int kTuneMaxWidths = 8;
+dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const void* b, void* u,
+                         int reps, hipStream_t s, int32_t* widths, double* ms, int32_t* count,
+                         int32_t* best);
+void autotune_reset();
 dpm_status validate_grid(const dpm_grid* g);
 dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o);
 

@@ -147,3 +147,25 @@ def test_diagnostics_workspace_constant_and_validation():
     assert lib.dpm_diagnostics(None, fake, fake, fake, fake, 1 << 20, None) == _lib.DPM_EINVAL
     vols = (C.c_void_p * 4)(256, 512, 768, 1024)
     assert lib.dpm_dd_diagnostics(None, vols, fake, fake, 1 << 20, None) == _lib.DPM_EINVAL
+
+
+def test_autotune_validation_without_device():
+    """dpm_autotune checks its arguments on the host before any device work; with nothing tuned,
+    dpm_rhs_chunk reports the default width (2 FP64 volumes at 255^3, about 256 MB)."""
+    from paper_1811_03557_amd import _lib
+    lib = _lib.load()
+    lib.dpm_autotune_reset()
+    g = _lib.Grid(255, 3.0 / 256, 1.0, 0.0)
+    o = _lib.Opts(_lib.DPM_FP64, 1, 1e-10, 0, 0, None, 0)
+    w = C.c_int32(0)
+    assert lib.dpm_rhs_chunk(C.byref(g), 64, C.byref(o), C.byref(w)) == _lib.DPM_OK and w.value == 2
+    widths, ms = (C.c_int32 * 8)(), (C.c_double * 8)()
+    cnt, best = C.c_int32(0), C.c_int32(0)
+    args = (widths, ms, C.byref(cnt), C.byref(best))
+    for nrhs, reps in ((0, 3), (4, 0), (4, 101)):
+        assert lib.dpm_autotune(C.byref(g), nrhs, C.byref(o), None, None, reps, None, *args) == _lib.DPM_EINVAL
+        assert lib.dpm_last_error()
+    assert lib.dpm_autotune(C.byref(g), 4, C.byref(o), None, None, 3, None, *args) == _lib.DPM_EINVAL
+    assert b"NULL" in lib.dpm_last_error()
+    bad = _lib.Grid(6, 0.1, 1.0, 0.0)
+    assert lib.dpm_autotune(C.byref(bad), 4, C.byref(o), None, None, 3, None, *args) == _lib.DPM_EINVAL

@@ -1,0 +1,49 @@
+"""The launch-width autotuner (dpm_autotune) through the C ABI: it times every candidate width
+that fits, records the fastest, and later solves with rhs_chunk = 0 take it.  A solve's result
+does not depend on the width (each right-hand side's arithmetic is the same), so solves at the
+tuned width are compared bit for bit with width-1 solves, and against the oracle at the FP64 (1e-12)
+and refined (1e-10) tolerances."""
+import numpy as np
+import pytest
+
+import dpm_inputs as inp
+from oracle import aux as oaux
+from tests.gpu_util import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec,max_refine,tol", [("fp64", 0, 1e-12), ("fp32", 3, 1e-10)])
+def test_autotune_records_fastest_width(prec, max_refine, tol):
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    n, nrhs = 63, 8
+    h, _ = inp.grid(n)
+    sigma = 1.0 / h + 1.0
+    b = inp.rhs_normal(n, nrhs, seed=11)
+    bt = torch.from_numpy(b).to(dev)
+    say(f"autotune n={n} nrhs={nrhs} {prec} max_refine={max_refine}")
+    api.autotune_reset()
+    try:
+        default = api.rhs_chunk(api.grid(n, h, sigma), nrhs, api.opts(prec, True, 1e-10, max_refine))
+        res = api.autotune(bt, sigma, h, prec=prec, max_refine=max_refine, reps=2)
+        say(f"  widths {res['widths']}, ms {[round(t, 3) for t in res['ms']]}, best {res['best']} "
+            f"(default {default})")
+        # every candidate up to nrhs (the default width at this size is far above 8)
+        assert res["widths"] == [1, 2, 3, 4, 6, 8]
+        assert all(np.isfinite(t) and t > 0 for t in res["ms"])
+        assert res["best"] == res["widths"][int(np.argmin(res["ms"]))]
+        o = api.opts(prec, True, 1e-10, max_refine)
+        assert api.rhs_chunk(api.grid(n, h, sigma), nrhs, o) == res["best"]
+        u_auto = api.aux_solve_batched(bt, sigma, h, prec=prec, max_refine=max_refine).cpu().numpy()
+        u_one = api.aux_solve_batched(bt, sigma, h, prec=prec, max_refine=max_refine,
+                                      rhs_chunk=1).cpu().numpy()
+        assert np.array_equal(u_auto, u_one)
+        ref = oaux.aux_solve(b[:2], sigma, h)
+        err = max(oaux.rel_err_inf(u_auto[i], ref[i]) for i in range(2))
+        say(f"  rel err vs oracle {err:.2e}")
+        assert err <= tol
+    finally:
+        api.autotune_reset()
+    assert api.rhs_chunk(api.grid(n, h, sigma), nrhs, api.opts(prec, True, 1e-10, max_refine)) == default
