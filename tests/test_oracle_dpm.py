@@ -92,6 +92,73 @@ def test_minmod():
     assert np.array_equal(pks.minmod3(a, b, c), [1.0, -0.5, 0.0, 0.0, 1.0, -3.0])
 
 
+def _line_volume(vals, axis):
+    """A 7^3 volume that varies along one axis only, with the values of `vals` along it."""
+    v = np.asarray(vals, dtype=np.float64)
+    shape = [1, 1, 1]
+    shape[axis] = v.size
+    return np.broadcast_to(v.reshape(shape), (v.size,) * 3).copy()
+
+
+def test_limited_slopes_hand_table():
+    """Slope limiter (Sec. 2, eq slope_limiter and the slope formula above it): each case below
+    was worked out by hand, and each of the three minmod arguments -- the doubled forward
+    difference, the centred difference over 2h and the doubled backward difference -- is the
+    selected one at some node.  h = 0.5, values along the axis (ghosts outside read 0):
+
+      node  rho_{j-1} rho_j rho_{j+1}   2(fwd)/h  central/(2h)  2(bwd)/h   slope
+        1     0.0     1.0    2.0          4.0       2.0           4.0      2.0   central
+        2     1.0     2.0    2.25         1.0       1.25          4.0      1.0   forward
+        3     2.0     2.25   3.25         4.0       1.25          1.0      1.0   backward
+        4     2.25    3.25   3.0         -1.0       -0.25         4.0      0.0   signs differ
+        5     3.25    3.0    1.0         -8.0       -2.25        -1.0     -1.0   backward (max)
+    """
+    h = 0.5
+    vals = [0.0, 1.0, 2.0, 2.25, 3.25, 3.0, 1.0]
+    expect = {1: 2.0, 2: 1.0, 3: 1.0, 4: 0.0, 5: -1.0}
+    m_plus = np.ones((7, 7, 7), dtype=bool)
+    for axis in range(3):
+        rho = _line_volume(vals, axis)
+        slopes = pks.limited_slopes(rho, m_plus, h)
+        idx = [3, 3, 3]
+        for j, s in expect.items():
+            idx[axis] = j
+            assert slopes[axis][tuple(idx)] == pytest.approx(s, abs=1e-14), (axis, j)
+        # the other two axes see a constant profile: zero slope
+        for other in range(3):
+            if other != axis:
+                idx[axis] = 3
+                assert slopes[other][tuple(idx)] == 0.0
+    # outside M+ the slope is zero by definition
+    rho = _line_volume(vals, 2)
+    mask = m_plus.copy()
+    mask[:, :, 2] = False
+    assert pks.limited_slopes(rho, mask, h)[2][3, 3, 2] == 0.0
+
+
+def test_convective_term_quadratic_rho_linear_c():
+    """Closed form that fixes the three minmod arguments together (Sec. 2, eqs slope_limiter and
+    upwind_approximation): rho = x^2 on x > 2h, c = a x with a > 0.  The three arguments are
+    2(rho' + h), rho' and 2(rho' - h) there, so the centred one, which equals rho' exactly, is
+    selected; the reconstruction is exact and the upwind (left) face value is
+    rho_j + (h/2) rho'_j.  Telescoping the fluxes gives
+    g = chi a [(rho_j - rho_{j-1}) + (h/2)(rho'_j - rho'_{j-1})]/h = chi a rho'(x_j) = 2 chi a x_j
+    exactly.  A centred difference over h instead of 2h would select 2 rho' - 2h and break the
+    identity.  (A constant bias of the slope telescopes out of g, so the one-sided arguments are
+    pinned by the hand table above, not here.)"""
+    n, h, chi, a = 15, 0.1, 0.8, 1.7
+    x = 0.3 + h * np.arange(n)                   # x > 2h everywhere (x_0 = 0.3)
+    X = np.broadcast_to(x.reshape(1, 1, n), (n, n, n)).copy()
+    rho = X ** 2
+    c = a * X
+    m_plus = np.zeros((n, n, n), dtype=bool)
+    m_plus[2:-2, 2:-2, 2:-2] = True
+    g = pks.convective_term(rho, c, m_plus, h, chi)
+    inner = np.zeros_like(m_plus)
+    inner[3:-3, 3:-3, 3:-3] = True
+    assert np.allclose(g[inner], (2.0 * chi * a * X)[inner], rtol=1e-12, atol=1e-12)
+
+
 def _sphere_case(n=31):
     h, x0 = inp.grid(n)
     z, y, x = inp.mesh(n)
