@@ -6,8 +6,9 @@ the device) on the 255^3 interior grid of the cube [-1.5, 1.5]^3 (h = 3/256), si
 by aux_solve_batched to a relative max-norm error of 1e-10.  Paths timed: FP64 FFT-form
 transforms, FP32 transforms with FP64 residual refinement, split-bf16 dense transforms on the
 matrix cores with FP64 refinement, and FP64 dense transforms on the FP64 matrix cores (the GEMM
-form).  `value` is the solves/s of the fastest path
-whose error, checked against the CPU FP64 oracle on a sampled right-hand side, meets 1e-10.
+form).  `value` is the solves/s of the fastest path whose error, checked against the CPU FP64
+oracle on every right-hand side of the batch, meets 1e-10.  The FP64 and FP32 + refinement paths
+are also timed and checked at sigma = 1e4, the other end of the workload's sigma range.
 
 Serving (the "serving" object): a continuous-batching server over 64 simulations of mixed grid
 sizes; a closed-loop run gives the saturation rate and an open-loop run with Poisson arrivals
@@ -24,9 +25,7 @@ Domain decomposition (the "domain_decomposition" object): Case 1 on the Test A s
 ball on a 127^3 mesh and the shell on a 63^3 mesh, against the single domain at 255^3 with the
 same fine spacing: build and per-step times and their ratio.  The "domain_decomposition_case2"
 object: Case 2 (Z meets Gamma) on the Test B setup at 127/63 (150 harmonics on Gamma, 6 on Z),
-against the single domain at 255^3.  The "paper_geometry" object: the paper's own setup (the
-ball of radius 0.5 in a cube two mesh widths wider), Test A to t = 6e-5 on the single domain at
-255^3 and Case 1 at 127/63 (R_S for the run), and Test B at 127^3 to the paper's stopping rule.
+against the single domain at 255^3.
 
 Prints one JSON line on stdout (everything else goes to stderr).
 """
@@ -282,9 +281,7 @@ def run_dd(args, dev):
     CFL-type bound of the positivity theorem at the initial data, max|grad c0| from the formula,
     which bounds the face differences; far below 0.5 h1^2 for these data).  Against the single
     domain at the same fine spacing everywhere (N = 255, 2 columns): Step 2 wall time and the
-    per-step time (eager steps, FP64), whose ratio is the per-step R_S = T_SD / T_DD; and the
-    adaptive loop (Steps 3-8 with rebuilds, from dt0 = 0.5 h1^2 to t = 6e-5, the final time of
-    the paper's speed-up table) on both, whose ratio is R_S for a run."""
+    per-step time (eager steps, FP64), whose ratio is the per-step R_S = T_SD / T_DD."""
     import torch
     from paper_1811_03557_amd import api
     n1, n2 = 127, 63
@@ -365,45 +362,6 @@ def run_dd(args, dev):
     out["R_S_build"] = round(build_sd / build_dd, 2)
     log(f"[bench] SD 255: build {build_sd * 1e3:.1f} ms, {t_sd * 1e3:.3f} ms/step; "
         f"R_S per step {t_sd / t_dd:.2f}")
-    # the adaptive loop (Steps 3-8) from Test A data and dt0 = 0.5 h1^2 on both, to t = 6e-5 (the
-    # final time of the paper's speed-up comparison): the CFL-type bound cuts dt at the first
-    # step and the matrices are rebuilt whenever it shrinks
-    dt0 = 0.5 * h1 * h1
-    t_end = 6e-5
-    runs = {}
-    prm0 = api.dd_params(n1, h1, -0.75 + h1, n2, h2, -1.5 + h2, 1.0 / dt0, 0.5, 1.0, 0.75, 0, 1, 0)
-    dd = api.dd_build(prm0, device=dev)
-    state = [dd.gauss_state(l, a, r) for l in (0, 1) for a, r in ((1000.0, 100.0), (500.0, 50.0))]
-    diag0 = api.dd_diagnostics(dd, state).tolist()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    res = api.dd_run(dd, 1.0, state, t_final=t_end, max_steps=100000)
-    torch.cuda.synchronize()
-    runs["dd_127_63"] = {"run_s": round(time.perf_counter() - t, 4), "steps": res["steps"],
-                         "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"],
-                         "diagnostics_start": diag0,
-                         "diagnostics_end": api.dd_diagnostics(dd, state).tolist()}
-    dd.close()
-    bep.rebuild(1.0 / dt0)
-    rho = api.gauss_state(bep, geo, 1000.0, 100.0)
-    c = api.gauss_state(bep, geo, 500.0, 50.0)
-    diag0 = api.diagnostics(bep, rho, c).tolist()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    res = api.run(bep, 1.0, rho, c, t_final=t_end, max_steps=100000)
-    torch.cuda.synchronize()
-    runs["sd_255"] = {"run_s": round(time.perf_counter() - t, 4), "steps": res["steps"],
-                      "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"],
-                      "diagnostics_start": diag0,
-                      "diagnostics_end": api.diagnostics(bep, rho, c).tolist()}
-    runs["R_S_run"] = round(runs["sd_255"]["run_s"] / runs["dd_127_63"]["run_s"], 2)
-    runs["diagnostics"] = "max |rho| over M+, second moment, free energy (Sec. 4), at t = 0 and at the end"
-    out["adaptive_run"] = runs
-    log(f"[bench] adaptive run to t = {t_end:g}: DD {runs['dd_127_63']['steps']} steps "
-        f"{runs['dd_127_63']['run_s'] * 1e3:.1f} ms "
-        f"({runs['dd_127_63']['rebuilds']} rebuilds), SD {runs['sd_255']['steps']} steps "
-        f"{runs['sd_255']['run_s'] * 1e3:.1f} ms "
-        f"({runs['sd_255']['rebuilds']} rebuilds); R_S {runs['R_S_run']:.2f}")
     bep.close()
     return out
 
@@ -549,94 +507,6 @@ def oracle_by_n(args, dev, oaux, cores):
     return out
 
 
-def run_paper_geometry(args, dev):
-    """The paper's own setup (Sec. 4): Omega the ball of radius r = 0.5 in the cube
-    [-r - 2h, r + 2h]^3 (N interior nodes per axis, h = 2r/(N - 3), the paper's h = 2r/(N_cells - 4)),
-    dt0 = 0.5 h^2, the adaptive loop (Steps 3-8) throughout.
-    (i) Test A to t = 6e-5, the paper's speed-up comparison (Table 6): the single domain at
-        N = 255 against Case 1 at N1/N2 = 127/63 (Z of radius 0.25, h1 = 2 r1/(N1 - 3),
-        h2 = 2r/(N2 - 3)), one zonal harmonic per term: wall times, steps, rebuilds, max |rho|,
-        R_S = T_SD / T_DD.
-    (ii) Test B to the paper's stopping rule (the change of ||rho||_inf over one step >= 1000),
-        single domain at N = 127 with 150 zonal harmonics and the 2-term extension: steps,
-        rebuilds, final time, max |rho| and where it sits, min |rho|, wall time."""
-    import torch
-    from paper_1811_03557_amd import api
-    r, r1, t_end = 0.5, 0.25, 6e-5
-    geo = api.geometry("sphere", axes=(r,))
-    out = {"workload": "ball of radius 0.5 in [-r - 2h, r + 2h]^3, h = 2r/(N - 3), dt0 = 0.5 h^2; "
-                       "Test A to t = 6e-5 (SD 255 vs DD 127/63, one zonal harmonic per term); "
-                       "Test B to the stop rule (SD 127, 150 zonal harmonics, 2-term)"}
-    n = 255
-    h = 2 * r / (n - 3)
-    x0 = -(r + 2 * h) + h
-    n1, n2 = 127, 63
-    h1, h2 = 2 * r1 / (n1 - 3), 2 * r / (n2 - 3)
-    dt0 = 0.5 * min(h, h1) ** 2
-    m = api.classify(n, h, x0, geo, device=dev)
-    idx, _ = api.gamma_points(m, h, x0)
-    B, _ = api.basis_zonal(n, h, x0, geo, idx, 0, 1)
-    bep = api.build_boundary_matrix(m, B, n, h, 1.0 / dt0, x0)
-    rho = api.gauss_state(bep, geo, 1000.0, 100.0)
-    c = api.gauss_state(bep, geo, 500.0, 50.0)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    res = api.run(bep, 1.0, rho, c, t_final=t_end, max_steps=100000)
-    torch.cuda.synchronize()
-    s_sd = time.perf_counter() - t
-    sd = {"n": n, "h": h, "run_s": round(s_sd, 4), "steps": res["steps"], "rebuilds": res["rebuilds"],
-          "t": res["t"], "rho_max": res["rho_max"], "diagnostics": api.diagnostics(bep, rho, c).tolist()}
-    bep.close()
-    del m, idx, B, rho, c
-    prm = api.dd_params(n1, h1, -(r1 + 2 * h1) + h1, n2, h2, -(r + 2 * h2) + h2, 1.0 / dt0, r1, r,
-                        0.5 * (r1 + r), 0, 1, 0)
-    dd = api.dd_build(prm, device=dev)
-    state = [dd.gauss_state(l, a, k) for l in (0, 1) for a, k in ((1000.0, 100.0), (500.0, 50.0))]
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    res = api.dd_run(dd, 1.0, state, t_final=t_end, max_steps=100000)
-    torch.cuda.synchronize()
-    s_dd = time.perf_counter() - t
-    ddr = {"n": [n1, n2], "h": [h1, h2], "run_s": round(s_dd, 4), "steps": res["steps"],
-           "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"],
-           "diagnostics": api.dd_diagnostics(dd, state).tolist()}
-    dd.close()
-    del state
-    out["test_a"] = {"sd_255": sd, "dd_127_63": ddr, "R_S_run": round(s_sd / s_dd, 2)}
-    log(f"[bench] paper geometry, Test A to t = 6e-5: SD 255 {sd['steps']} steps "
-        f"({sd['rebuilds']} rebuilds) {s_sd:.3f} s, DD 127/63 {ddr['steps']} steps "
-        f"({ddr['rebuilds']} rebuilds) {s_dd:.3f} s, R_S {s_sd / s_dd:.2f}; max rho "
-        f"{sd['rho_max']:.4e} / {ddr['rho_max']:.4e}")
-    # Test B, single domain at N = 127, to the stopping rule
-    n = 127
-    h = 2 * r / (n - 3)
-    x0 = -(r + 2 * h) + h
-    dt0 = 0.5 * h * h
-    m = api.classify(n, h, x0, geo, device=dev)
-    idx, _ = api.gamma_points(m, h, x0)
-    B, _ = api.basis_zonal(n, h, x0, geo, idx, 149, 0)
-    bep = api.build_boundary_matrix(m, B, n, h, 1.0 / dt0, x0)
-    rho = api.gauss_state(bep, geo, 2000.0, 100.0, center=(0.0, 0.0, 0.25))
-    c = torch.zeros_like(rho)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    res = api.run(bep, 1.0, rho, c, t_final=1.0, max_steps=100000, rho_jump_cap=1000.0)
-    torch.cuda.synchronize()
-    s_b = time.perf_counter() - t
-    mm = m.bool()
-    i = int(torch.argmax(torch.where(mm, rho, torch.zeros_like(rho))))
-    at = [x0 + h * (i % n), x0 + h * ((i // n) % n), x0 + h * (i // (n * n))]
-    out["test_b"] = {"n": n, "h": h, "harmonics": 150, "stop": res["stop"], "steps": res["steps"],
-                     "rebuilds": res["rebuilds"], "t": res["t"], "rho_max": res["rho_max"],
-                     "argmax_xyz": [round(v, 5) for v in at], "rho_min": float(rho[mm].min()),
-                     "run_s": round(s_b, 3), "diagnostics": api.diagnostics(bep, rho, c).tolist()}
-    log(f"[bench] paper geometry, Test B (SD 127, 150 harmonics): {res['stop']} after "
-        f"{res['steps']} steps ({res['rebuilds']} rebuilds) at t = {res['t']:.5f}, max rho "
-        f"{res['rho_max']:.4e} at {[round(v, 4) for v in at]}, {s_b:.2f} s")
-    bep.close()
-    return out
-
-
 def run_autotune(args, b, h, dev):
     """The launch-width autotuner on the headline batch: every candidate width (right-hand sides
     per sweep launch) timed as the best of 3 batched FP64 solves, against the library's default
@@ -699,11 +569,10 @@ def main():
     ap.add_argument("--sigma", type=float, default=1.0)
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--paths", default="fp64,fp32_ir,bf16x3_ir,fp64_gemm")
-    ap.add_argument("--cpu-sample", type=int, default=3,
-                    help="right-hand sides copied to the host for the oracle")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="wall time of the oracle sample timed for cpu_baseline")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sigma-hi", type=float, default=1e4,
+                    help="also time and check FP64 and FP32 + refinement at this sigma (0 = skip)")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="do not report the oracle's time (the accuracy check still runs)")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving run (0 = skip)")
     ap.add_argument("--serve-main-requests", type=int, default=10000,
@@ -739,7 +608,6 @@ def main():
     n, nrhs = args.n, args.nrhs
     h, _ = inp.grid(n)
     b = inp.rhs_normal_device(n, nrhs, seed=0, device=dev)
-    u = torch.empty_like(b)
     vol = n ** 3
 
     if args.copy_bytes > 0:
@@ -756,89 +624,119 @@ def main():
         "bf16x3_ir": dict(prec="bf16x3", max_refine=5, dtype="bf16x3 MFMA + f64 refinement"),
         "fp64_gemm": dict(prec="fp64_gemm", max_refine=0, dtype="f64 dense DST on FP64 MFMA"),
     }
-    results = {}
-    for name in [p for p in args.paths.split(",") if p]:
-        cfg = path_cfg[name]
-        g = api.grid(n, h, args.sigma)
-        o = api.opts(cfg["prec"], True, args.rtol, cfg["max_refine"])
-        ws = torch.empty(max(1, api.workspace_size(g, nrhs, o)), dtype=torch.uint8, device=dev)
 
-        def step():
-            api.aux_solve_batched(b, args.sigma, h, prec=cfg["prec"], rtol=args.rtol,
-                                  max_refine=cfg["max_refine"], out=u, workspace=ws)
+    def time_paths(sigma, names):
+        """Times each path on the batch; keeps each path's solutions on the device."""
+        res = {}
+        for name in names:
+            cfg = path_cfg[name]
+            g = api.grid(n, h, sigma)
+            o = api.opts(cfg["prec"], True, args.rtol, cfg["max_refine"])
+            ws = torch.empty(max(1, api.workspace_size(g, nrhs, o)), dtype=torch.uint8, device=dev)
+            u = torch.empty_like(b)
 
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        chunk = api.rhs_chunk(g, nrhs, o)
-        # events bracket the sweeps of the chunks holding right-hand sides 0 and nrhs/2 of every
-        # step: live per-kernel durations inside the timed region at ~0.3% of its work
-        stride = max(1, nrhs // 2)
-        _lib.check(lib.dpm_timing_begin(8 * args.steps * (1 + cfg["max_refine"]) * 6, stride))
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0.record()
-        for _ in range(args.steps):
-            step()
-        t1.record()
-        torch.cuda.synchronize()
-        ms = t0.elapsed_time(t1) / args.steps
-        import ctypes as C
-        cnt = (C.c_int32 * 6)()
-        mean = (C.c_double * 6)()
-        _lib.check(lib.dpm_timing_end(6, cnt, mean))
-        kern = {KIND_NAMES[k]: {"timed_launches_per_step": cnt[k] / args.steps, "mean_ms": mean[k]}
-                for k in range(6) if cnt[k] > 0}
-        # refinement iterations actually used (one extra solve with info)
-        _, info = api.aux_solve_batched(b, args.sigma, h, prec=cfg["prec"], rtol=args.rtol,
-                                        max_refine=cfg["max_refine"], out=u, workspace=ws,
-                                        info=True)
-        results[name] = dict(ms_per_step=ms, solves_per_s=nrhs / (ms * 1e-3), kernels=kern,
-                             rhs_per_launch=chunk,
-                             refine_iters=info["refine_iters"], dtype=cfg["dtype"],
-                             u0=u[0].cpu().numpy())
-        if cfg["prec"] == "fp64_gemm":
-            # the dense form is bound by the FP64 matrix cores: 2 MP^2 flop per line and product
-            # (MP = 256, the padded matrix), one product per x/y sweep line, two per z line
-            mp = (n + 31) // 32 * 32
-            fl = {k: chunk * n * n * 2 * mp * mp * (2 if k == "z_fused" else 1) for k in kern}
-            results[name]["mfma"] = {
-                k: {"tflops": round(fl[k] / (kern[k]["mean_ms"] * 1e-3) / 1e12, 1),
-                    "frac_of_fp64_peak": round(fl[k] / (kern[k]["mean_ms"] * 1e-3) / 78.6e12, 3)}
-                for k in kern}
-        log(f"[bench] {name}: {ms:.3f} ms/step, {nrhs / (ms * 1e-3):.1f} solves/s, "
-            f"refine_iters={info['refine_iters']}, kernels={kern}")
+            def step():
+                api.aux_solve_batched(b, sigma, h, prec=cfg["prec"], rtol=args.rtol,
+                                      max_refine=cfg["max_refine"], out=u, workspace=ws)
 
-    # ---- accuracy on a sampled right-hand side against the CPU FP64 oracle, timed as baseline
-    cpu = None
-    b_host = b[: max(1, args.cpu_sample)].cpu().numpy()
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            chunk = api.rhs_chunk(g, nrhs, o)
+            # events bracket the sweeps of the chunks holding right-hand sides 0 and nrhs/2 of
+            # every step: live per-kernel durations inside the timed region at ~0.3% of its work
+            stride = max(1, nrhs // 2)
+            _lib.check(lib.dpm_timing_begin(8 * args.steps * (1 + cfg["max_refine"]) * 6, stride))
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0.record()
+            for _ in range(args.steps):
+                step()
+            t1.record()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / args.steps
+            import ctypes as C
+            cnt = (C.c_int32 * 6)()
+            mean = (C.c_double * 6)()
+            _lib.check(lib.dpm_timing_end(6, cnt, mean))
+            kern = {KIND_NAMES[k]: {"timed_launches_per_step": cnt[k] / args.steps,
+                                    "mean_ms": mean[k]} for k in range(6) if cnt[k] > 0}
+            # refinement iterations actually used (one extra solve with info)
+            _, info = api.aux_solve_batched(b, sigma, h, prec=cfg["prec"], rtol=args.rtol,
+                                            max_refine=cfg["max_refine"], out=u, workspace=ws,
+                                            info=True)
+            del ws
+            res[name] = dict(ms_per_step=ms, solves_per_s=nrhs / (ms * 1e-3), kernels=kern,
+                             rhs_per_launch=chunk, refine_iters=info["refine_iters"],
+                             dtype=cfg["dtype"], u=u)
+            if cfg["prec"] == "fp64_gemm":
+                # the dense form is bound by the FP64 matrix cores: 2 MP^2 flop per line and
+                # product (MP = 256, the padded matrix), one product per x/y sweep line, two per
+                # z line
+                mp = (n + 31) // 32 * 32
+                fl = {k: chunk * n * n * 2 * mp * mp * (2 if k == "z_fused" else 1) for k in kern}
+                res[name]["mfma"] = {
+                    k: {"tflops": round(fl[k] / (kern[k]["mean_ms"] * 1e-3) / 1e12, 1),
+                        "frac_of_fp64_peak": round(fl[k] / (kern[k]["mean_ms"] * 1e-3) / 78.6e12, 3)}
+                    for k in kern}
+            log(f"[bench] sigma {sigma:g} {name}: {ms:.3f} ms/step, {nrhs / (ms * 1e-3):.1f} "
+                f"solves/s, refine_iters={info['refine_iters']}, kernels={kern}")
+        return res
+
     from oracle import aux as oaux
-    t = time.perf_counter()
-    ref0 = oaux.aux_solve(b_host[0], args.sigma, h)
-    t_first = time.perf_counter() - t
-    for name, r in results.items():
-        r["rel_err_sample"] = oaux.rel_err_inf(r.pop("u0"), ref0)
-        log(f"[bench] {name}: rel err vs oracle (rhs 0) = {r['rel_err_sample']:.3e}")
-    if not args.no_cpu and args.cpu_sample > 1:
-        # bounded sample: oracle solves of right-hand sides 1.. (cycled) for about cpu_seconds
-        t = time.perf_counter()
-        k = 0
-        while k < 3 or (time.perf_counter() - t < args.cpu_seconds and k < 400):
-            oaux.aux_solve(b_host[1 + k % (b_host.shape[0] - 1)], args.sigma, h)
-            k += 1
-        t_rest = time.perf_counter() - t
+
+    def check_all(sigma, res):
+        """Every right-hand side of every path against the CPU FP64 oracle (relative max-norm
+        error per right-hand side; the maximum over the batch is reported).  Returns the oracle
+        solve times."""
+        times = []
+        errs = {k: [] for k in res}
+        for i in range(nrhs):
+            bi = b[i].cpu().numpy()
+            t = time.perf_counter()
+            ref = oaux.aux_solve(bi, sigma, h)
+            times.append(time.perf_counter() - t)
+            for k, r in res.items():
+                errs[k].append(oaux.rel_err_inf(r["u"][i].cpu().numpy(), ref))
+        for k, r in res.items():
+            r["rel_err_max"] = float(max(errs[k]))
+            r["rel_err_median"] = float(np.median(errs[k]))
+            r["checked_rhs"] = nrhs
+            del r["u"]
+            log(f"[bench] sigma {sigma:g} {k}: rel err vs oracle over all {nrhs} right-hand sides "
+                f"max {r['rel_err_max']:.3e}, median {r['rel_err_median']:.3e}")
+        torch.cuda.empty_cache()
+        return times
+
+    names = [p for p in args.paths.split(",") if p]
+    results = time_paths(args.sigma, names)
+    t_oracle = check_all(args.sigma, results)
+    cpu = None
+    if not args.no_cpu:
+        # the oracle solves of the accuracy check (the first one excluded as a warm-up) are the
+        # bounded sample of the same workload
+        k, t_rest = len(t_oracle) - 1, sum(t_oracle[1:])
         try:
             from threadpoolctl import threadpool_info
             cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
         except Exception:
             cores = os.cpu_count()
         cpu = {"value": k / t_rest, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-               "sample": f"{k} solves ({t_rest:.1f} s) of right-hand sides 1-{b_host.shape[0] - 1} "
-                         f"of the same workload (255^3, sigma {args.sigma}), dense FP64 DST-I "
-                         f"oracle; the first solve ({t_first:.2f} s) excluded"}
+               "sample": f"{k} solves ({t_rest:.1f} s) of right-hand sides 1-{nrhs - 1} of the "
+                         f"same workload ({n}^3, sigma {args.sigma}), dense FP64 DST-I oracle, "
+                         f"the solves of the accuracy check; the first solve "
+                         f"({t_oracle[0]:.2f} s) excluded"}
         log(f"[bench] cpu oracle: {k / t_rest:.3f} solves/s on {cores} threads")
         cpu["by_n"] = oracle_by_n(args, dev, oaux, int(cores))
+    # the other end of the sigma range of the workload (sigma = 1e4): the contenders only
+    sigma_hi = None
+    if args.sigma_hi > 0:
+        hi_names = [p for p in ("fp64", "fp32_ir") if p in names]
+        res_hi = time_paths(args.sigma_hi, hi_names)
+        check_all(args.sigma_hi, res_hi)
+        sigma_hi = {"sigma": args.sigma_hi,
+                    "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in res_hi.items()}}
 
     serving = None
     if args.serve_requests > 0:
@@ -849,9 +747,8 @@ def main():
     test_b = run_test_b(args, dev) if args.adaptive_steps > 0 and not args.no_bmat else None
     dd = run_dd(args, dev) if args.dd_steps > 0 else None
     dd2 = run_dd2(args, dev) if args.dd_steps > 0 else None
-    paper = run_paper_geometry(args, dev) if args.dd_steps > 0 and not args.no_bmat else None
 
-    ok = {k: v for k, v in results.items() if v["rel_err_sample"] <= args.rtol}
+    ok = {k: v for k, v in results.items() if v["rel_err_max"] <= args.rtol}
     best_name = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else None
     best = ok[best_name] if best_name else None
 
@@ -896,10 +793,13 @@ def main():
         "test_b": test_b,
         "domain_decomposition": dd,
         "domain_decomposition_case2": dd2,
-        "paper_geometry": paper,
         "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
+        "sigma_1e4": sigma_hi,
         "alg_hbm_frac": (round(best["solves_per_s"] * 16 * vol / (HBM_PEAK_GBS * 1e9), 4)
                          if best else None),
+        "fp32_ir_over_fp64": (round(results["fp32_ir"]["solves_per_s"]
+                                    / results["fp64"]["solves_per_s"], 3)
+                              if "fp32_ir" in results and "fp64" in results else None),
     }
     if args.autotune:
         line["autotune"] = run_autotune(args, b, h, dev)

@@ -108,7 +108,9 @@ dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opt
  *
  * Errors: those of aux_solve_batched; DPM_EINVAL for reps outside [1, 100], for a workspace that
  * fits no candidate, or while sweep timing is on.  The table is process-wide and guarded by a
- * lock; a solve that runs while tuning is under way takes either the old width or the new. */
+ * lock; a solve reads the width once and takes either the old width or the new.  A solve whose
+ * workspace (opts->rhs_chunk == 0) is smaller than the recorded width needs, for example one
+ * sized before a re-tune or a reset, runs at the widest width the workspace holds. */
 dpm_status dpm_autotune(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, const void* b,
                         void* u, int32_t reps, void* stream, int32_t* widths, double* ms,
                         int32_t* count, int32_t* best);
@@ -217,6 +219,10 @@ dpm_status dpm_build_boundary_matrix(const dpm_grid* grid, const uint8_t* m_plus
 dpm_status dpm_bep_info(const dpm_bep* bep, int32_t* n_gamma, int32_t* n_gamma_in,
                         int32_t* n_basis, double* min_abs_rdiag, double* max_abs_rdiag);
 
+/* Device bytes the handle holds (masks, gamma lists, densities, the factored matrix, the
+ * least-squares operator): what keeping it resident costs, e.g. for admission by HBM footprint. */
+dpm_status dpm_bep_device_bytes(const dpm_bep* bep, size_t* bytes);
+
 /*
  * dpm_bep_solve -- paper Step 5: least-squares coefficients C = argmin ||A C - g||_2 of the
  * reduced BEP (eq BEP_recast), as C = P g with the operator P = R^-1 Q1^T formed from the QR at
@@ -238,7 +244,9 @@ dpm_status dpm_step_workspace_size(const dpm_bep* bep, const dpm_opts* opts, siz
  *   u_gamma = basis^T C, and the discrete generalized Green's formula u = P u_gamma + G f on
  *   N+ (computed as one AP solve per species by linearity).
  * rho_in, c_in: device N^3 FP64 values on N+ (other entries ignored); rho_out, c_out: device
- * N^3 FP64, zero off N+; they may alias the inputs.  chi: chemotactic sensitivity.
+ * N^3 FP64, zero off N+, two different buffers (DPM_EINVAL otherwise); they may alias the
+ * inputs.  All four 8-byte aligned, opts->workspace 16-byte aligned.  chi: chemotactic
+ * sensitivity.
  * info: host, nullable (synchronises when given).
  */
 dpm_status dpm_step(const dpm_bep* bep, double dt, double chi, const double* rho_in,
@@ -276,15 +284,26 @@ void dpm_stepper_destroy(dpm_stepper* st);
 dpm_status dpm_cfl_scan(const dpm_bep* bep, const double* rho, const double* c, double* out2,
                         void* stream);
 
+/* Scratch bytes dpm_bep_rebuild needs for this handle (host call): the right-hand sides,
+ * solutions and solve workspace of one batch of column solves, or the factorisation's
+ * temporaries, whichever is larger (the two phases run one after the other). */
+dpm_status dpm_bep_rebuild_workspace_size(const dpm_bep* bep, size_t* bytes);
+
 /*
  * dpm_bep_rebuild -- paper Step 4b: recompute the reduced-BEP matrix (the same densities and
  * geometry), its Householder QR and the least-squares operator in place for a new sigma
- * (= 1/dt), with the transform options given at build time.  Synchronises `stream`; allocates
- * temporaries for the column solves.  Errors as dpm_build_boundary_matrix; after a failure the
- * handle must only be destroyed.  A stepper built on this handle keeps replaying its own dt:
- * create a new one after a rebuild.
+ * (= 1/dt), with the transform options given at build time.  workspace: device scratch of at
+ * least dpm_bep_rebuild_workspace_size bytes, 16-byte aligned, owned by the caller; the call
+ * allocates nothing.  Synchronises `stream` once, for the rank test.  Errors as
+ * dpm_build_boundary_matrix; after a failure the handle must only be destroyed.  A stepper built
+ * on this handle keeps replaying its own dt: create a new one after a rebuild.
  */
-dpm_status dpm_bep_rebuild(dpm_bep* bep, double sigma, void* stream);
+dpm_status dpm_bep_rebuild(dpm_bep* bep, double sigma, void* workspace, size_t workspace_bytes,
+                           void* stream);
+
+/* Scratch bytes dpm_run needs with these options (host call): the dpm_step workspace, 256 bytes
+ * of scanned maxima, and the rebuild scratch of dpm_bep_rebuild_workspace_size. */
+dpm_status dpm_run_workspace_size(const dpm_bep* bep, const dpm_opts* opts, size_t* bytes);
 
 /*
  * dpm_run -- the adaptive time loop of the paper's Algorithm "Main Steps" (Steps 3-8) on (rho, c)
@@ -295,10 +314,12 @@ dpm_status dpm_bep_rebuild(dpm_bep* bep, double sigma, void* stream);
  * dt_prev) (Step 3; dt never grows, so the matrix of the last rebuild always belongs to the
  * current dt); if dt < dt_prev rebuild the matrix at sigma = 1/dt (Step 4b); one dpm_step
  * (Steps 4a-7); t += dt.  The loop ends when t >= t_final, after max_steps steps, or at a stop.
- * One 16-byte device-to-host copy and one synchronisation per step.
- * opts->workspace: at least dpm_step_workspace_size + 256 bytes.  dt_hist and rebuilt_hist
- * (host, nullable, max_steps entries) receive each step's dt and whether it rebuilt (1/0).
- * On return the handle holds the matrix of the last dt.
+ * One 32-byte device-to-host copy and one synchronisation per step; a rebuild's rank test is
+ * read back with the next step's scan, so it adds none (on DPM_ERANK the state holds the step
+ * taken with the rank-deficient matrix).  opts->workspace: at least dpm_run_workspace_size
+ * bytes; the loop allocates nothing, rebuilds included.  dt_hist and rebuilt_hist (host,
+ * nullable, max_steps entries) receive each step's dt and whether it rebuilt (1/0).  On return
+ * the handle holds the matrix of the last dt.
  */
 typedef struct {
   double chi;       /* chemotactic sensitivity */
@@ -460,13 +481,23 @@ dpm_status dpm_dd_stepper_create(const dpm_dd* dd, double dt, double chi, double
 dpm_status dpm_dd_stepper_run(dpm_dd_stepper* st, int32_t nsteps, void* stream);
 void dpm_dd_stepper_destroy(dpm_dd_stepper* st);
 
+/* Scratch bytes dpm_dd_rebuild needs (host call): the larger of either subdomain's column
+ * scratch and the stacked factorisation's temporaries, plus 256 bytes. */
+dpm_status dpm_dd_rebuild_workspace_size(const dpm_dd* dd, size_t* bytes);
+
 /*
  * dpm_dd_rebuild -- Step 4b on the decomposed domain: both subdomains' columns, the stacked
  * matrix, its QR and least-squares operator again at a new sigma (= 1/dt), in place.
- * Synchronises `stream`; allocates temporaries for the column solves.  After a failure the
- * handle must only be destroyed.
+ * workspace: device scratch of at least dpm_dd_rebuild_workspace_size bytes, 16-byte aligned;
+ * the call allocates nothing.  Synchronises `stream` once, for the rank test.  After a failure
+ * the handle must only be destroyed.
  */
-dpm_status dpm_dd_rebuild(dpm_dd* dd, double sigma, void* stream);
+dpm_status dpm_dd_rebuild(dpm_dd* dd, double sigma, void* workspace, size_t workspace_bytes,
+                          void* stream);
+
+/* Scratch bytes dpm_dd_run needs with these options (host call): the dpm_dd_step workspace,
+ * 256 bytes of scanned maxima and the dpm_dd_rebuild scratch. */
+dpm_status dpm_dd_run_workspace_size(const dpm_dd* dd, const dpm_opts* opts, size_t* bytes);
 
 /*
  * dpm_dd_run -- the adaptive time loop (paper Algorithm "Main Steps", Steps 3-8) on the
@@ -475,7 +506,8 @@ dpm_status dpm_dd_rebuild(dpm_dd* dd, double sigma, void* stream);
  * M+_l, as dpm_cfl_scan); stop if a scanned value is not finite or max |rho| over both exceeds
  * rho_cap; dt = min(dt_prev, h_l / (6 chi max|grad_h c_l|) for l = 1, 2) (each subdomain's
  * CFL-type bound on its own mesh); if dt < dt_prev dpm_dd_rebuild at 1/dt; one dpm_dd_step.
- * Ends as dpm_run.  opts->workspace: at least dpm_dd_step_workspace_size + 256 bytes.  info,
+ * Ends as dpm_run (a rebuild's rank test is read back with the next scan).  opts->workspace: at
+ * least dpm_dd_run_workspace_size bytes; the loop allocates nothing, rebuilds included.  info,
  * dt_hist, rebuilt_hist as for dpm_run (grad_max and rho_max: the larger of the two subdomains).
  */
 dpm_status dpm_dd_run(dpm_dd* dd, const dpm_run_params* params, double* const state[4],

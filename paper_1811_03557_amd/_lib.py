@@ -84,6 +84,7 @@ SIGNATURES = {
     "dpm_bep_info": (C.c_int, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I), C.POINTER(_D),
                                C.POINTER(_D)]),
     "dpm_bep_solve": (C.c_int, [_P, _I, _P, _P, _P]),
+    "dpm_bep_device_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "dpm_step_workspace_size": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
     "dpm_step": (C.c_int, [_P, _D, _D, _P, _P, _P, _P, C.POINTER(Opts), _P, C.POINTER(Info)]),
     "dpm_stepper_create": (C.c_int, [_P, _D, _D, _P, _P, C.POINTER(Opts), _P, C.POINTER(_P)]),
@@ -91,7 +92,9 @@ SIGNATURES = {
     "dpm_stepper_first_nonfinite": (C.c_int, [_P, _P, C.POINTER(C.c_int32)]),
     "dpm_stepper_destroy": (None, [_P]),
     "dpm_cfl_scan": (C.c_int, [_P, _P, _P, _P, _P]),
-    "dpm_bep_rebuild": (C.c_int, [_P, _D, _P]),
+    "dpm_bep_rebuild_workspace_size": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "dpm_bep_rebuild": (C.c_int, [_P, _D, _P, C.c_size_t, _P]),
+    "dpm_run_workspace_size": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
     "dpm_run": (C.c_int, [_P, C.POINTER(RunParams), _P, _P, C.POINTER(Opts), _P,
                           C.POINTER(RunInfo), _P, _P]),
     "dpm_gauss_state": (C.c_int, [_P, C.POINTER(Geometry), _D, _D, C.POINTER(_D), _P, _P]),
@@ -104,7 +107,9 @@ SIGNATURES = {
     "dpm_dd_step_workspace_size": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
     "dpm_dd_step": (C.c_int, [_P, _D, _D, C.POINTER(_P), C.POINTER(_P), C.POINTER(Opts), _P]),
     "dpm_dd_gauss_state": (C.c_int, [_P, _I, _D, _D, C.POINTER(_D), _P, _P]),
-    "dpm_dd_rebuild": (C.c_int, [_P, _D, _P]),
+    "dpm_dd_rebuild_workspace_size": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "dpm_dd_rebuild": (C.c_int, [_P, _D, _P, C.c_size_t, _P]),
+    "dpm_dd_run_workspace_size": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
     "dpm_dd_stepper_create": (C.c_int, [_P, _D, _D, C.POINTER(_P), C.POINTER(Opts), C.POINTER(_P)]),
     "dpm_dd_stepper_run": (C.c_int, [_P, _I, _P]),
     "dpm_dd_stepper_destroy": (None, [_P]),

@@ -246,9 +246,25 @@ class BEP:
         self.n_gamma, self.n_gamma_in, self.n_basis = ng.value, ngi.value, nb.value
         self.rdiag = (rmin.value, rmax.value)
 
-    def rebuild(self, sigma: float, stream=None) -> None:
-        """Step 4b: the matrix, its QR and the least-squares operator again at a new sigma."""
+    def rebuild_workspace_size(self) -> int:
+        nb = C.c_size_t(0)
+        L.check(L.load().dpm_bep_rebuild_workspace_size(C.c_void_p(self.ptr), C.byref(nb)))
+        return int(nb.value)
+
+    def device_bytes(self) -> int:
+        """Device memory the handle holds."""
+        nb = C.c_size_t(0)
+        L.check(L.load().dpm_bep_device_bytes(C.c_void_p(self.ptr), C.byref(nb)))
+        return int(nb.value)
+
+    def rebuild(self, sigma: float, stream=None, workspace: torch.Tensor | None = None) -> None:
+        """Step 4b: the matrix, its QR and the least-squares operator again at a new sigma, with
+        the scratch in `workspace` (allocated here through torch when not given)."""
+        nbytes = self.rebuild_workspace_size()
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         L.check(L.load().dpm_bep_rebuild(C.c_void_p(self.ptr), float(sigma),
+                                         C.c_void_p(workspace.data_ptr()), workspace.numel(),
                                          C.c_void_p(_stream(stream))))
         self.sigma = float(sigma)
         self._refresh_rdiag()
@@ -338,9 +354,24 @@ class DD:
         L.check(L.load().dpm_dd_step_workspace_size(C.c_void_p(self.ptr), C.byref(o), C.byref(nb)))
         return int(nb.value)
 
-    def rebuild(self, sigma: float, stream=None) -> None:
-        """Step 4b: both subdomains' columns and the coupled QR again at a new sigma."""
+    def rebuild_workspace_size(self) -> int:
+        nb = C.c_size_t(0)
+        L.check(L.load().dpm_dd_rebuild_workspace_size(C.c_void_p(self.ptr), C.byref(nb)))
+        return int(nb.value)
+
+    def run_workspace_size(self, o: L.Opts) -> int:
+        nb = C.c_size_t(0)
+        L.check(L.load().dpm_dd_run_workspace_size(C.c_void_p(self.ptr), C.byref(o), C.byref(nb)))
+        return int(nb.value)
+
+    def rebuild(self, sigma: float, stream=None, workspace: torch.Tensor | None = None) -> None:
+        """Step 4b: both subdomains' columns and the coupled QR again at a new sigma, with the
+        scratch in `workspace` (allocated here through torch when not given)."""
+        nbytes = self.rebuild_workspace_size()
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         L.check(L.load().dpm_dd_rebuild(C.c_void_p(self.ptr), float(sigma),
+                                        C.c_void_p(workspace.data_ptr()), workspace.numel(),
                                         C.c_void_p(_stream(stream))))
         self.sigma = float(sigma)
         self._refresh()
@@ -476,7 +507,7 @@ def dd_run(dd: DD, chi: float, state, t_final: float, rho_cap: float = float("in
             raise ValueError(f"state volumes must hold {dd.n[0]}^3, {dd.n[0]}^3, {dd.n[1]}^3, "
                              f"{dd.n[1]}^3 values")
     o = opts(prec, True, rtol, max_refine)
-    nbytes = dd.workspace_size(o) + 256
+    nbytes = dd.run_workspace_size(o)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=state[0].device)
     o.workspace = C.c_void_p(workspace.data_ptr())
@@ -535,6 +566,13 @@ def bep_solve(bep: BEP, g: torch.Tensor, stream=None) -> torch.Tensor:
                                    C.c_void_p(_dev(gg, "g", torch.float64)),
                                    C.c_void_p(Cc.data_ptr()), C.c_void_p(_stream(stream))))
     return Cc[0] if g.dim() == 1 else Cc
+
+
+def run_workspace_size(bep: BEP, o: L.Opts) -> int:
+    """Bytes of dpm_run's workspace: step workspace, scan area and rebuild scratch."""
+    nb = C.c_size_t(0)
+    L.check(L.load().dpm_run_workspace_size(C.c_void_p(bep.ptr), C.byref(o), C.byref(nb)))
+    return int(nb.value)
 
 
 def step_workspace_size(bep: BEP, o: L.Opts) -> int:
@@ -632,7 +670,7 @@ def run(bep: BEP, chi: float, rho: torch.Tensor, c: torch.Tensor, t_final: float
     matrix of the last dt (bep.sigma is updated)."""
     lib = L.load()
     o = opts(prec, True, rtol, max_refine)
-    nbytes = step_workspace_size(bep, o) + 256
+    nbytes = run_workspace_size(bep, o)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=rho.device)
     o.workspace = C.c_void_p(workspace.data_ptr())

@@ -46,7 +46,9 @@ dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], in
                         int32_t* n_cols, double* rmin, double* rmax);
 dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStream_t s,
                           dpm_dd** out, double* A_out);
-dpm_status dd_rebuild_impl(dpm_dd* d, double sigma, hipStream_t s);
+dpm_status dd_rebuild_impl(dpm_dd* d, double sigma, hipStream_t s, void* scratch, size_t bytes);
+size_t dd_rebuild_workspace_bytes(const dpm_dd* d);
+dpm_status dd_run_workspace_impl(const dpm_dd* d, const dpm_opts& o, size_t* bytes);
 dpm_status dd_stepper_create_impl(const dpm_dd* d, double dt, double chi, double* const state[4],
                                   const dpm_opts& o, void** out);
 dpm_status dd_stepper_run_impl(void* h, int nsteps, hipStream_t s);
@@ -246,6 +248,18 @@ dpm_status dpm_bep_info(const dpm_bep* bep, int32_t* n_gamma, int32_t* n_gamma_i
   return DPM_OK;
 }
 
+dpm_status dpm_bep_device_bytes(const dpm_bep* bep, size_t* bytes) {
+  clear_error();
+  if (!bep || !bytes) { set_error("bep or bytes is NULL"); return DPM_EINVAL; }
+  const size_t v = (size_t)bep->grid.n * bep->grid.n * bep->grid.n;
+  const size_t ng = (size_t)bep->n_gamma, ni = (size_t)bep->n_in, nb = (size_t)bep->n_basis;
+  *bytes = 2 * v                      // M+ and N+ masks
+           + sizeof(int32_t) * v      // node -> gamma position map
+           + (sizeof(int32_t) + 1) * ng + 2 * sizeof(int32_t) * ni  // gamma lists
+           + sizeof(double) * (nb * ng + 2 * nb * ni + nb);         // basis, A, P, tau
+  return DPM_OK;
+}
+
 dpm_status dpm_bep_solve(const dpm_bep* bep, int32_t nvec, const double* g, double* C,
                          void* stream) {
   clear_error();
@@ -269,7 +283,16 @@ dpm_status dpm_step(const dpm_bep* bep, double dt, double chi, const double* rho
                     const double* c_in, double* rho_out, double* c_out, const dpm_opts* opts,
                     void* stream, dpm_info* info) {
   clear_error();
-  if (!bep || !rho_in || !c_in || !rho_out || !c_out) { set_error("NULL argument"); return DPM_EINVAL; }
+  if (!bep || !rho_in || !c_in || !rho_out || !c_out || !opts) { set_error("NULL argument"); return DPM_EINVAL; }
+  // pointer checks first (they need nothing from the handle)
+  if (!aligned_to(rho_in, 8) || !aligned_to(c_in, 8) || !aligned_to(rho_out, 8) ||
+      !aligned_to(c_out, 8) || !aligned16(opts->workspace)) {
+    set_error("the state volumes must be 8-byte aligned, the workspace 16-byte aligned");
+    return DPM_EINVAL;
+  }
+  // the outputs are written after every read of the inputs, so they may alias them, but both
+  // species are written by one kernel
+  if (rho_out == c_out) { set_error("rho_out and c_out must be different buffers"); return DPM_EINVAL; }
   DPM_TRY(validate_opts(bep->grid, opts));
   if (!opts->io_fp64) { set_error("dpm_step needs FP64 solves (io_fp64 = 1)"); return DPM_EINVAL; }
   if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(chi)) { set_error("dt must be finite and > 0, chi finite"); return DPM_EINVAL; }
@@ -327,11 +350,28 @@ dpm_status dpm_cfl_scan(const dpm_bep* bep, const double* rho, const double* c, 
   return cfl_scan_impl(bep, rho, c, out2, static_cast<hipStream_t>(stream));
 }
 
-dpm_status dpm_bep_rebuild(dpm_bep* bep, double sigma, void* stream) {
+dpm_status dpm_bep_rebuild_workspace_size(const dpm_bep* bep, size_t* bytes) {
+  clear_error();
+  if (!bep || !bytes) { set_error("bep or bytes is NULL"); return DPM_EINVAL; }
+  *bytes = rebuild_scratch_bytes(bep);
+  return DPM_OK;
+}
+
+dpm_status dpm_bep_rebuild(dpm_bep* bep, double sigma, void* workspace, size_t workspace_bytes,
+                           void* stream) {
   clear_error();
   if (!bep) { set_error("bep is NULL"); return DPM_EINVAL; }
   if (!(sigma >= 0.0) || !std::isfinite(sigma)) { set_error("sigma must be finite and >= 0"); return DPM_EINVAL; }
-  return rebuild_bep_impl(bep, sigma, static_cast<hipStream_t>(stream));
+  if (!aligned16(workspace)) { set_error("the workspace must be 16-byte aligned"); return DPM_EINVAL; }
+  return rebuild_bep_impl(bep, sigma, static_cast<hipStream_t>(stream), workspace,
+                          workspace_bytes);
+}
+
+dpm_status dpm_run_workspace_size(const dpm_bep* bep, const dpm_opts* opts, size_t* bytes) {
+  clear_error();
+  if (!bep || !bytes) { set_error("bep or bytes is NULL"); return DPM_EINVAL; }
+  DPM_TRY(validate_opts(bep->grid, opts));
+  return run_workspace_impl(bep, *opts, bytes);
 }
 
 dpm_status dpm_run(dpm_bep* bep, const dpm_run_params* params, double* rho, double* c,
@@ -510,11 +550,26 @@ dpm_status dpm_dd_stepper_run(dpm_dd_stepper* st, int32_t nsteps, void* stream) 
 
 void dpm_dd_stepper_destroy(dpm_dd_stepper* st) { dd_stepper_destroy_impl(st); }
 
-dpm_status dpm_dd_rebuild(dpm_dd* dd, double sigma, void* stream) {
+dpm_status dpm_dd_rebuild_workspace_size(const dpm_dd* dd, size_t* bytes) {
+  clear_error();
+  if (!dd || !bytes) { set_error("dd or bytes is NULL"); return DPM_EINVAL; }
+  *bytes = dd_rebuild_workspace_bytes(dd);
+  return DPM_OK;
+}
+
+dpm_status dpm_dd_rebuild(dpm_dd* dd, double sigma, void* workspace, size_t workspace_bytes,
+                          void* stream) {
   clear_error();
   if (!dd) { set_error("dd is NULL"); return DPM_EINVAL; }
   if (!(sigma > 0.0) || !std::isfinite(sigma)) { set_error("sigma must be finite and > 0"); return DPM_EINVAL; }
-  return dd_rebuild_impl(dd, sigma, static_cast<hipStream_t>(stream));
+  if (!aligned16(workspace)) { set_error("the workspace must be 16-byte aligned"); return DPM_EINVAL; }
+  return dd_rebuild_impl(dd, sigma, static_cast<hipStream_t>(stream), workspace, workspace_bytes);
+}
+
+dpm_status dpm_dd_run_workspace_size(const dpm_dd* dd, const dpm_opts* opts, size_t* bytes) {
+  clear_error();
+  if (!dd || !bytes || !opts) { set_error("NULL argument"); return DPM_EINVAL; }
+  return dd_run_workspace_impl(dd, *opts, bytes);
 }
 
 dpm_status dpm_dd_run(dpm_dd* dd, const dpm_run_params* params, double* const state[4],

@@ -165,15 +165,31 @@ dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o) {
   return DPM_OK;
 }
 
-dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes) {
-  const int rb = real_bytes_of(o);
-  const bool ws = needs_ws(o);
-  const int chunk = rhs_chunk_of(g, nrhs, o);
-  size_t vol = (size_t)g.n * g.n * g.n;
+size_t workspace_for_chunk(const dpm_grid& g, int nrhs, const dpm_opts& o, int chunk) {
+  const size_t vol = (size_t)g.n * g.n * g.n;
   size_t total = flags_bytes(nrhs);
-  if (ws) total += align_up(vol * (size_t)chunk * (size_t)rb, 256);
-  *bytes = total;
+  if (needs_ws(o)) total += align_up(vol * (size_t)chunk * (size_t)real_bytes_of(o), 256);
+  return total;
+}
+
+dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes) {
+  *bytes = workspace_for_chunk(g, nrhs, o, rhs_chunk_of(g, nrhs, o));
   return DPM_OK;
+}
+
+// Width of the solve's sweep launches.  The width is read once per call (the autotuner may
+// record a new one meanwhile) and, unless the caller fixed it (rhs_chunk > 0), narrowed to the
+// widest one the caller's workspace holds: results do not depend on the width, and a workspace
+// sized before a re-tune or a reset stays usable.  Returns 0 when not even one right-hand side
+// per launch fits.
+int solve_chunk(const dpm_grid& g, int nrhs, const dpm_opts& o) {
+  int chunk = rhs_chunk_of(g, nrhs, o);
+  if (workspace_for_chunk(g, nrhs, o, chunk) <= o.workspace_bytes || o.rhs_chunk > 0) return chunk;
+  const size_t fixed = flags_bytes(nrhs);
+  if (o.workspace_bytes < fixed) return 0;
+  const size_t per = (size_t)g.n * g.n * g.n * (size_t)real_bytes_of(o);
+  const size_t fit = ((o.workspace_bytes - fixed) / 256 * 256) / per;
+  return fit >= (size_t)chunk ? chunk : (int)fit;
 }
 
 // Transform forms of the sweeps: real FFT (dst_fft.hip), split-bf16 dense products on the
@@ -231,10 +247,9 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
   const int rb = real_bytes_of(o);
   const int form = o.prec == DPM_BF16X3 ? FORM_BF16X3 : o.prec == DPM_FP64_GEMM ? FORM_F64MM : FORM_FFT;
   const bool ws_needed = needs_ws(o);
-  const int chunk = rhs_chunk_of(g, nrhs, o);
-  size_t need = 0;
-  DPM_TRY(workspace_size_impl(g, nrhs, o, &need));
-  if (o.workspace_bytes < need || (need > 0 && o.workspace == nullptr)) {
+  const int chunk = solve_chunk(g, nrhs, o);
+  const size_t need = workspace_for_chunk(g, nrhs, o, chunk > 0 ? chunk : 1);
+  if (chunk <= 0 || o.workspace_bytes < need || (need > 0 && o.workspace == nullptr)) {
     set_error("workspace too small: %zu bytes given, %zu needed", o.workspace_bytes, need);
     return DPM_EINVAL;
   }
@@ -340,10 +355,8 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
   // with a transform workspace, stay at or below the default width, so that a workspace sized
   // for the default (before tuning) fits every width the tuner may record
   const int cap = needs_ws(o) ? default_chunk(g.n, 1 << 30, real_bytes_of(o), true) : (1 << 30);
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned.erase(tune_key(g.n, o));
-  }
+  // the recorded width (if any) stays in force until the new one replaces it: the timed solves
+  // below fix their width explicitly, and concurrent solves keep the old one meanwhile
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -357,10 +370,7 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
     if (w > nrhs || w > cap) continue;
     dpm_opts ow = o;
     ow.rhs_chunk = w;
-    size_t need = 0;
-    st = workspace_size_impl(g, nrhs, ow, &need);
-    if (st != DPM_OK) break;
-    if (need > o.workspace_bytes) continue;
+    if (workspace_for_chunk(g, nrhs, ow, w) > o.workspace_bytes) continue;
     st = aux_solve_impl(g, nrhs, b, u, ow, s, nullptr);  // untimed: first-touch and caches
     if (st != DPM_OK) break;
     double t = 0.0;

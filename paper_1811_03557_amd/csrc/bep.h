@@ -55,14 +55,30 @@ void launch_restrict(const dpm_bep* b, const double* U, double* o0, double* o1, 
 dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
                           const double* basis, const dpm_opts& o, hipStream_t s, dpm_bep** out,
                           double* A_out, bool factor = true);
-dpm_status bep_columns(dpm_bep* b, hipStream_t s);
-// Householder QR of A (m x n column-major, in place), rank test, P = R^-1 Q1^T (n x m)
+// Build scratch (device memory of the caller or of the build): the column solves' right-hand
+// sides, solutions and solve workspace, and the factorisation's temporaries.  The two phases run
+// one after the other on a stream, so a rebuild needs the larger of the two.
+size_t columns_scratch_bytes(const dpm_bep* b);
+size_t factor_scratch_bytes(int m, int n);
+size_t rebuild_scratch_bytes(const dpm_bep* b);
+// Columns of b->A at b->grid.sigma; enqueue only (no allocation, no synchronisation).
+dpm_status bep_columns(dpm_bep* b, hipStream_t s, void* scratch, size_t bytes);
+// Householder QR of A (m x n column-major, in place), P = R^-1 Q1^T (n x m) and the device pair
+// rd2 = (min, max) |R_ii|; enqueue only.
 dpm_status lsq_factor(double* A, int m, int n, double* tau, double* P, hipStream_t s,
-                      double* rdiag_min, double* rdiag_max);
+                      void* scratch, size_t bytes, double* rd2);
+// Columns, QR and P of a single-domain handle, enqueue only (rd2 as above).
+dpm_status factor_bep_enqueue(dpm_bep* b, hipStream_t s, double* A_out, void* scratch,
+                              size_t bytes, double* rd2);
+// DPM_ERANK unless min |R_ii| > 1e-12 max |R_ii| (NaN fails).
+dpm_status rank_check(double mn, double mx);
 // C[r] = P g[r] for nvec vectors g (m entries each), C rows of n entries
 void lsq_apply(const double* P, int m, int n, int nvec, const double* g, double* C,
                hipStream_t s);
-dpm_status rebuild_bep_impl(dpm_bep* b, double sigma, hipStream_t s);
+// Step 4b in place with caller scratch (rebuild_scratch_bytes); one synchronisation.
+dpm_status rebuild_bep_impl(dpm_bep* b, double sigma, hipStream_t s, void* scratch, size_t bytes);
+// Bytes dpm_run needs: the step workspace, the scan area and the rebuild scratch.
+dpm_status run_workspace_impl(const dpm_bep* b, const dpm_opts& o, size_t* bytes);
 dpm_status cfl_scan_impl(const dpm_bep* b, const double* rho, const double* c, double* out2,
                          hipStream_t s);
 dpm_status run_impl(dpm_bep* b, const dpm_run_params& p, double* rho, double* c,

@@ -421,9 +421,33 @@ __global__ __launch_bounds__(kLT) void k_lsq_apply(const double* __restrict__ P,
   if (threadIdx.x == 0) C[(long long)r * n + nu] = t;
 }
 
-__global__ void k_rdiag(const double* __restrict__ A, int m, int n, double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = fabs(A[(long long)i * m + i]);
+// out2 = (min |R_ii|, max |R_ii|) over the diagonal of the factored A (one block); a NaN on the
+// diagonal makes both NaN, so the rank test fails.
+__global__ __launch_bounds__(256) void k_rdiag_minmax(const double* __restrict__ A, int m, int n,
+                                                      double* __restrict__ out2) {
+  __shared__ double smn[4], smx[4];
+  __shared__ int snan[4];
+  double mn = INFINITY, mx = 0.0;
+  int bad = 0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double v = fabs(A[(long long)i * m + i]);
+    bad |= !(v == v);
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, off));
+    mx = fmax(mx, __shfl_xor(mx, off));
+    bad |= __shfl_xor(bad, off);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { smn[w] = mn; smx[w] = mx; snan[w] = bad; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 4; ++k) { mn = fmin(mn, smn[k]); mx = fmax(mx, smx[k]); bad |= snan[k]; }
+    out2[0] = bad ? NAN : mn;
+    out2[1] = bad ? NAN : mx;
+  }
 }
 
 // positions of the gamma_in entries inside the gamma list, and their linear indices
@@ -496,130 +520,175 @@ int gram_chunks(int m, int n) {
   return (m + rc - 1) / rc;
 }
 
+namespace {
+
+// Columns per batched solve of a build: 16, fewer where the right-hand sides and solutions of
+// 16 columns (2 x 16 FP64 volumes) would pass 2 GiB; opts->rhs_chunk overrides.
+int build_cols(const dpm_grid& g, const dpm_opts& o, int n_basis) {
+  const double per = 16.0 * (double)g.n * g.n * g.n;
+  int c = o.rhs_chunk > 0 ? o.rhs_chunk : (int)std::fmin(16.0, std::floor(2147483648.0 / per));
+  if (c > n_basis) c = n_basis;
+  return c < 1 ? 1 : c;
+}
+
+struct ColLayout {
+  int chunk;
+  size_t rhs, u, ws, wsb, total;
+};
+ColLayout col_layout(const dpm_grid& g, const dpm_opts& o, int n_basis) {
+  ColLayout L{};
+  L.chunk = build_cols(g, o, n_basis);
+  const size_t vb = sizeof(double) * (size_t)g.n * g.n * g.n * (size_t)L.chunk;
+  dpm_opts so = o;
+  so.rhs_chunk = 0;
+  size_t wsb = 0;
+  (void)workspace_size_impl(g, L.chunk, so, &wsb);
+  size_t at = 0;
+  L.rhs = at; at = align_up(at + vb, 256);
+  L.u = at; at = align_up(at + vb, 256);
+  L.ws = at; L.wsb = wsb; at = align_up(at + wsb, 256);
+  L.total = at;
+  return L;
+}
+
+struct FacLayout {
+  size_t rd, G, T, W, K, Rinv, Gp, total;
+};
+FacLayout fac_layout(int m, int n) {
+  const size_t nn = sizeof(double) * (size_t)n * n;
+  FacLayout L{};
+  size_t at = 0;
+  L.rd = at; at = align_up(at + 2 * sizeof(double), 256);
+  L.G = at; at = align_up(at + nn, 256);
+  L.T = at; at = align_up(at + nn, 256);
+  L.W = at; at = align_up(at + nn, 256);
+  L.K = at; at = align_up(at + nn, 256);
+  L.Rinv = at; at = align_up(at + nn, 256);
+  L.Gp = at; at = align_up(at + nn * (size_t)gram_chunks(m, n), 256);
+  L.total = at;
+  return L;
+}
+
+}  // namespace
+
+size_t columns_scratch_bytes(const dpm_bep* b) {
+  return col_layout(b->grid, b->opts, b->n_basis).total;
+}
+size_t factor_scratch_bytes(int m, int n) { return fac_layout(m, n).total; }
+size_t rebuild_scratch_bytes(const dpm_bep* b) {
+  const size_t c = columns_scratch_bytes(b), f = factor_scratch_bytes(b->n_in, b->n_basis);
+  return c > f ? c : f;  // the factorisation starts after the column solves: shared scratch
+}
+
+dpm_status rank_check(double mn, double mx) {
+  if (!(mn > 1e-12 * mx)) {
+    set_error("boundary matrix is rank deficient: min |R_ii| = %g, max |R_ii| = %g", mn, mx);
+    return DPM_ERANK;
+  }
+  return DPM_OK;
+}
+
 // Columns of the reduced-BEP matrix at the handle's sigma (M- operator on the densities, batched
-// AP solves, traces on gamma_in) into b->A.  Synchronises the stream.
-dpm_status bep_columns(dpm_bep* b, hipStream_t s) {
+// AP solves, traces on gamma_in) into b->A, with the right-hand sides, solutions and solve
+// workspace taken from `scratch` (columns_scratch_bytes).  Enqueue only: no allocation and no
+// synchronisation.
+dpm_status bep_columns(dpm_bep* b, hipStream_t s, void* scratch, size_t bytes) {
   const dpm_grid& g = b->grid;
-  const dpm_opts& o = b->opts;
   const int n_basis = b->n_basis, nin = b->n_in, ng = b->n_gamma;
   const long long vsz = (long long)g.n * g.n * g.n;
-  auto al = [&](void** p, size_t bytes) { return hipMalloc(p, bytes > 0 ? bytes : 1) == hipSuccess; };
-  // columns in chunks: M- operator on the densities (sparse), batched AP solve, trace on
-  // gamma_in
-  int chunk = o.rhs_chunk > 0 ? o.rhs_chunk : 16;
-  if (chunk > n_basis) chunk = n_basis;
-  dpm_opts so = o;
-  size_t wsb = 0;
-  DPM_TRY(workspace_size_impl(g, chunk, so, &wsb));
-  double *rhs = nullptr, *u = nullptr;
-  void* ws = nullptr;
-  if (!al((void**)&rhs, sizeof(double) * vsz * chunk) ||
-      !al((void**)&u, sizeof(double) * vsz * chunk) || !al(&ws, wsb)) {
-    (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
-    set_error("dpm_build_boundary_matrix: device allocation failed");
-    return DPM_ENOMEM;
+  const ColLayout L = col_layout(g, b->opts, n_basis);
+  if (scratch == nullptr || bytes < L.total) {
+    set_error("boundary-matrix columns: scratch too small: %zu bytes given, %zu needed", bytes,
+              L.total);
+    return DPM_EINVAL;
   }
-  so.workspace = ws;
-  so.workspace_bytes = wsb;
+  char* base = static_cast<char*>(scratch);
+  double* rhs = reinterpret_cast<double*>(base + L.rhs);
+  double* u = reinterpret_cast<double*>(base + L.u);
+  dpm_opts so = b->opts;
+  so.workspace = base + L.ws;
+  so.workspace_bytes = L.wsb;
   so.rhs_chunk = 0;
-  dpm_status st = DPM_OK;
-  for (int c0 = 0; c0 < n_basis && st == DPM_OK; c0 += chunk) {
+  const int chunk = L.chunk;
+  for (int c0 = 0; c0 < n_basis; c0 += chunk) {
     const int nc = (n_basis - c0) < chunk ? (n_basis - c0) : chunk;
     // zeros once: every chunk writes the same nodes (the set depends on the geometry only) and
     // the solves leave their right-hand sides unchanged
     if (c0 == 0) fill_zero(rhs, vsz * nc, s);
     minus_rhs(b, b->basis, c0, nc, rhs, s);
-    st = aux_solve_impl(g, nc, rhs, u, so, s, nullptr);
-    if (st != DPM_OK) break;
+    DPM_TRY(aux_solve_impl(g, nc, rhs, u, so, s, nullptr));
     hipLaunchKernelGGL(k_trace_columns, dim3(grid1(nin), nc), dim3(kB), 0, s, b->basis, u,
                        b->idx_in, b->pos_in, nin, ng, c0, nc, vsz, b->A);
-    if (hipGetLastError() != hipSuccess) { set_error("trace kernel launch failed"); st = DPM_EHIP; }
-  }
-  (void)hipStreamSynchronize(s);
-  (void)hipFree(rhs); (void)hipFree(u); (void)hipFree(ws);
-  return st;
-}
-
-// Householder QR of A (m x n, column-major, overwritten by the reflectors below R), the rank
-// test on the diagonal of R and the least-squares operator P = R^-1 Q1^T (n x m, row nu
-// contiguous).  Synchronises the stream.
-dpm_status lsq_factor(double* A, int m, int n_basis, double* tau, double* P, hipStream_t s,
-                      double* rdiag_min, double* rdiag_max) {
-  const int nin = m;
-  auto al = [&](void** p, size_t bytes) { return hipMalloc(p, bytes > 0 ? bytes : 1) == hipSuccess; };
-  // one launch per step (the step-j reflector is applied by the trailing-column blocks and
-  // stored by block 0 of the next launch)
-  for (int j = 0; j <= n_basis; ++j) launch_house_step(A, nin, n_basis, j, tau, s);
-  double* rd = nullptr;
-  std::vector<double> rdh(n_basis);
-  if (!al((void**)&rd, sizeof(double) * n_basis)) {
-    set_error("dpm_build_boundary_matrix: device allocation failed");
-    return DPM_ENOMEM;
-  }
-  hipLaunchKernelGGL(k_rdiag, dim3(grid1(n_basis)), dim3(kB), 0, s, A, nin, n_basis, rd);
-  hipError_t e = hipMemcpyAsync(rdh.data(), rd, sizeof(double) * n_basis, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(rd);
-  if (e != hipSuccess) {
-    set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e));
-    return DPM_EHIP;
-  }
-  double mn = INFINITY, mx = 0.0;
-  for (double v : rdh) { mn = std::fmin(mn, v); mx = std::fmax(mx, v); }
-  *rdiag_min = mn;
-  *rdiag_max = mx;
-  if (!(mn > 1e-12 * mx)) {
-    set_error("boundary matrix is rank deficient: min |R_ii| = %g, max |R_ii| = %g", mn, mx);
-    return DPM_ERANK;
-  }
-  // least-squares operator P = R^-1 Q1^T, so that every later solve is one product C = P g
-  {
-    const size_t nn = (size_t)n_basis * n_basis;
-    double *G = nullptr, *T = nullptr, *W = nullptr, *K = nullptr, *Rinv = nullptr, *Gp = nullptr;
-    auto free_all = [&]() {
-      (void)hipFree(G); (void)hipFree(T); (void)hipFree(W); (void)hipFree(K); (void)hipFree(Rinv);
-      (void)hipFree(Gp);
-    };
-    if (!al((void**)&G, sizeof(double) * nn) || !al((void**)&T, sizeof(double) * nn) ||
-        !al((void**)&W, sizeof(double) * nn) || !al((void**)&K, sizeof(double) * nn) ||
-        !al((void**)&Rinv, sizeof(double) * nn) ||
-        !al((void**)&Gp, sizeof(double) * nn * (size_t)gram_chunks(nin, n_basis))) {
-      free_all();
-      set_error("dpm_build_boundary_matrix: device allocation failed");
-      return DPM_ENOMEM;
-    }
-    const int nt = (n_basis + kGT - 1) / kGT, nchunk = gram_chunks(nin, n_basis);
-    const int rc = (nin + nchunk - 1) / nchunk;
-    hipLaunchKernelGGL(k_gram_part, dim3(nt * (nt + 1) / 2, nchunk), dim3(256), 0, s, A, nin,
-                       n_basis, rc, Gp);
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((nn + 3) / 4)), dim3(256), 0, s, Gp,
-                       nchunk, n_basis, G);
-    hipLaunchKernelGGL(k_tinv, dim3(n_basis), dim3(256), 0, s, G, tau, n_basis, T);
-    hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, A, nin, n_basis, Rinv);
-    hipLaunchKernelGGL(k_v1tt, dim3(grid1((long long)nn)), dim3(kB), 0, s, A, nin, n_basis, T, W);
-    hipLaunchKernelGGL(k_kmat, dim3(grid1((long long)nn)), dim3(kB), 0, s, Rinv, W, n_basis, K);
-    hipLaunchKernelGGL(k_form_p, dim3(grid1(nin), (n_basis + PT - 1) / PT), dim3(kB),
-                       sizeof(double) * PT * n_basis, s, Rinv, K, A, nin, n_basis, P);
-    hipError_t e2 = hipGetLastError();
-    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
-    free_all();
-    if (e2 != hipSuccess) {
-      set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e2));
-      return DPM_EHIP;
-    }
+    DPM_TRY_HIP(hipGetLastError());
   }
   return DPM_OK;
 }
 
-// Columns, QR, rank test and least-squares operator of the handle's matrix.
-dpm_status factor_bep(dpm_bep* b, hipStream_t s, double* A_out) {
-  DPM_TRY(bep_columns(b, s));
+// Householder QR of A (m x n, column-major, overwritten by the reflectors below R), the least-
+// squares operator P = R^-1 Q1^T (n x m, row nu contiguous) and (min, max) |R_ii| into the device
+// pair rd2, with temporaries from `scratch` (factor_scratch_bytes).  Enqueue only: the caller
+// reads rd2 back for the rank test.
+dpm_status lsq_factor(double* A, int m, int n_basis, double* tau, double* P, hipStream_t s,
+                      void* scratch, size_t bytes, double* rd2) {
+  const int nin = m;
+  const FacLayout L = fac_layout(m, n_basis);
+  if (scratch == nullptr || bytes < L.total) {
+    set_error("least-squares factorisation: scratch too small: %zu bytes given, %zu needed", bytes,
+              L.total);
+    return DPM_EINVAL;
+  }
+  char* base = static_cast<char*>(scratch);
+  // one launch per step (the step-j reflector is applied by the trailing-column blocks and
+  // stored by block 0 of the next launch)
+  for (int j = 0; j <= n_basis; ++j) launch_house_step(A, nin, n_basis, j, tau, s);
+  hipLaunchKernelGGL(k_rdiag_minmax, dim3(1), dim3(256), 0, s, A, nin, n_basis, rd2);
+  // least-squares operator P = R^-1 Q1^T, so that every later solve is one product C = P g
+  const size_t nn = (size_t)n_basis * n_basis;
+  double* G = reinterpret_cast<double*>(base + L.G);
+  double* T = reinterpret_cast<double*>(base + L.T);
+  double* W = reinterpret_cast<double*>(base + L.W);
+  double* K = reinterpret_cast<double*>(base + L.K);
+  double* Rinv = reinterpret_cast<double*>(base + L.Rinv);
+  double* Gp = reinterpret_cast<double*>(base + L.Gp);
+  const int nt = (n_basis + kGT - 1) / kGT, nchunk = gram_chunks(nin, n_basis);
+  const int rc = (nin + nchunk - 1) / nchunk;
+  hipLaunchKernelGGL(k_gram_part, dim3(nt * (nt + 1) / 2, nchunk), dim3(256), 0, s, A, nin,
+                     n_basis, rc, Gp);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((nn + 3) / 4)), dim3(256), 0, s, Gp,
+                     nchunk, n_basis, G);
+  hipLaunchKernelGGL(k_tinv, dim3(n_basis), dim3(256), 0, s, G, tau, n_basis, T);
+  hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, A, nin, n_basis, Rinv);
+  hipLaunchKernelGGL(k_v1tt, dim3(grid1((long long)nn)), dim3(kB), 0, s, A, nin, n_basis, T, W);
+  hipLaunchKernelGGL(k_kmat, dim3(grid1((long long)nn)), dim3(kB), 0, s, Rinv, W, n_basis, K);
+  hipLaunchKernelGGL(k_form_p, dim3(grid1(nin), (n_basis + PT - 1) / PT), dim3(kB),
+                     sizeof(double) * PT * n_basis, s, Rinv, K, A, nin, n_basis, P);
+  DPM_TRY_HIP(hipGetLastError());
+  return DPM_OK;
+}
+
+// Columns, QR and least-squares operator of the handle's matrix (enqueue only), (min, max)
+// |R_ii| into rd2.
+dpm_status factor_bep_enqueue(dpm_bep* b, hipStream_t s, double* A_out, void* scratch,
+                              size_t bytes, double* rd2) {
+  DPM_TRY(bep_columns(b, s, scratch, bytes));
   if (A_out && hipMemcpyAsync(A_out, b->A, sizeof(double) * (size_t)b->n_basis * b->n_in,
                               hipMemcpyDeviceToDevice, s) != hipSuccess) {
     set_error("dpm_build_boundary_matrix: copy of A failed");
     return DPM_EHIP;
   }
-  return lsq_factor(b->A, b->n_in, b->n_basis, b->tau, b->P, s, &b->rdiag_min, &b->rdiag_max);
+  return lsq_factor(b->A, b->n_in, b->n_basis, b->tau, b->P, s, scratch, bytes, rd2);
+}
+
+// The same, then one synchronisation for the rank test (rd2 read back from the end of scratch).
+dpm_status factor_bep(dpm_bep* b, hipStream_t s, double* A_out, void* scratch, size_t bytes) {
+  double* rd2 = reinterpret_cast<double*>(static_cast<char*>(scratch) + fac_layout(b->n_in, b->n_basis).rd);
+  DPM_TRY(factor_bep_enqueue(b, s, A_out, scratch, bytes, rd2));
+  double h2[2] = {0.0, 0.0};
+  DPM_TRY_HIP(hipMemcpyAsync(h2, rd2, sizeof(h2), hipMemcpyDeviceToHost, s));
+  DPM_TRY_HIP(hipStreamSynchronize(s));
+  b->rdiag_min = h2[0];
+  b->rdiag_max = h2[1];
+  return rank_check(h2[0], h2[1]);
 }
 
 dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
@@ -699,16 +768,36 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
     }
   }
   {
-    const dpm_status st = factor ? factor_bep(b, s, A_out) : bep_columns(b, s);
+    // Step 2 creates the handle: its build scratch is allocated here and freed after the build
+    // (rebuilds take theirs from the caller)
+    const size_t sb = factor ? rebuild_scratch_bytes(b) : columns_scratch_bytes(b);
+    void* scratch = nullptr;
+    if (hipMalloc(&scratch, sb) != hipSuccess) {
+      set_error("dpm_build_boundary_matrix: device allocation of %zu scratch bytes failed", sb);
+      return fail(DPM_ENOMEM);
+    }
+    dpm_status st = factor ? factor_bep(b, s, A_out, scratch, sb) : bep_columns(b, s, scratch, sb);
+    const hipError_t e = hipStreamSynchronize(s);
+    (void)hipFree(scratch);
+    if (st == DPM_OK && e != hipSuccess) {
+      set_error("dpm_build_boundary_matrix: %s", hipGetErrorString(e));
+      st = DPM_EHIP;
+    }
     if (st != DPM_OK) return fail(st);
   }
   *out = b;
   return DPM_OK;
 }
 
-dpm_status rebuild_bep_impl(dpm_bep* b, double sigma, hipStream_t s) {
+dpm_status rebuild_bep_impl(dpm_bep* b, double sigma, hipStream_t s, void* scratch,
+                            size_t bytes) {
+  if (scratch == nullptr || bytes < rebuild_scratch_bytes(b)) {
+    set_error("dpm_bep_rebuild: workspace too small: %zu bytes given, %zu needed", bytes,
+              rebuild_scratch_bytes(b));
+    return DPM_EINVAL;
+  }
   b->grid.sigma = sigma;
-  return factor_bep(b, s, nullptr);
+  return factor_bep(b, s, nullptr, scratch, bytes);
 }
 
 void destroy_bep(dpm_bep* b) {

@@ -122,6 +122,8 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u,
 // Right-hand sides per sweep launch that a solve of nrhs right-hand sides uses.
 int rhs_chunk_of(const dpm_grid& g, int nrhs, const dpm_opts& o);
 dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes);
+// Workspace bytes of a solve of nrhs right-hand sides at `chunk` right-hand sides per launch.
+size_t workspace_for_chunk(const dpm_grid& g, int nrhs, const dpm_opts& o, int chunk);
 // Launch-width autotuner (see dpm_autotune): candidate widths, timing, the recorded widths.
 constexpr int kTuneMaxWidths = 8;
 dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const void* b, void* u,

@@ -339,7 +339,7 @@ DDLayout dd_layout(const dpm_dd* d, size_t solve_ws) {
 dpm_status dd_solve_ws(const dpm_dd* d, const dpm_opts& o, size_t* bytes) {
   size_t mx = 0;
   dpm_opts so = o;
-  so.rhs_chunk = 0;
+  so.rhs_chunk = 2;  // both species in one launch: the size never depends on tuning
   for (int l = 0; l < 2; ++l) {
     size_t w = 0;
     DPM_TRY(workspace_size_impl(d->sub[l]->grid, 2, so, &w));
@@ -371,7 +371,8 @@ void dd_destroy(dpm_dd* d) {
 
 // The stacked matrix from the subdomains' columns (Case 1: [[0, A_1], [A_2]]; Case 2: the rows
 // of both parts), A_out (nullable) a copy before factorisation, then QR, rank test and P.
-dpm_status dd_stack_factor(dpm_dd* d, hipStream_t s, double* A_out) {
+dpm_status dd_stack_factor(dpm_dd* d, hipStream_t s, double* A_out, void* scratch, size_t bytes,
+                           double* rd2) {
   const size_t na = (size_t)d->rows * d->n_cols;
   if (d->kind == 1) {
     hipLaunchKernelGGL(k_dd_stack, dim3(blocks_for((long long)na)), dim3(kB), 0, s, d->sub[0]->A,
@@ -389,7 +390,69 @@ dpm_status dd_stack_factor(dpm_dd* d, hipStream_t s, double* A_out) {
   }
   DPM_TRY_HIP(hipGetLastError());
   if (A_out) DPM_TRY_HIP(hipMemcpyAsync(A_out, d->A, sizeof(double) * na, hipMemcpyDeviceToDevice, s));
-  return lsq_factor(d->A, d->rows, d->n_cols, d->tau, d->P, s, &d->rdiag_min, &d->rdiag_max);
+  return lsq_factor(d->A, d->rows, d->n_cols, d->tau, d->P, s, scratch, bytes, rd2);
+}
+
+// Scratch of a rebuild: the subdomains' column builds run one after the other, then the stacked
+// factorisation, all on one stream, so they share it.
+size_t dd_rebuild_scratch_bytes(const dpm_dd* d) {
+  size_t mx = factor_scratch_bytes(d->rows, d->n_cols);
+  for (int l = 0; l < 2; ++l) {
+    const size_t c = columns_scratch_bytes(d->sub[l]);
+    if (c > mx) mx = c;
+  }
+  return mx;
+}
+
+// Both subdomains' columns, the stacked matrix, its QR and P (enqueue only; rd2 as lsq_factor).
+dpm_status dd_factor_enqueue(dpm_dd* d, hipStream_t s, double* A_out, void* scratch, size_t bytes,
+                             double* rd2) {
+  for (int l = 0; l < 2; ++l) DPM_TRY(bep_columns(d->sub[l], s, scratch, bytes));
+  return dd_stack_factor(d, s, A_out, scratch, bytes, rd2);
+}
+
+// The same with one synchronisation for the rank test (rd2 at the end of the scratch).
+dpm_status dd_factor(dpm_dd* d, hipStream_t s, double* A_out, void* scratch, size_t bytes) {
+  if (scratch == nullptr || bytes < dd_rebuild_scratch_bytes(d) + 256) {
+    set_error("decomposed-domain build: scratch too small: %zu bytes given, %zu needed", bytes,
+              dd_rebuild_scratch_bytes(d) + 256);
+    return DPM_EINVAL;
+  }
+  double* rd2 = reinterpret_cast<double*>(static_cast<char*>(scratch) + (bytes - 256) / 256 * 256);
+  DPM_TRY(dd_factor_enqueue(d, s, A_out, scratch, bytes - 256, rd2));
+  double h2[2] = {0.0, 0.0};
+  DPM_TRY_HIP(hipMemcpyAsync(h2, rd2, sizeof(h2), hipMemcpyDeviceToHost, s));
+  DPM_TRY_HIP(hipStreamSynchronize(s));
+  d->rdiag_min = h2[0];
+  d->rdiag_max = h2[1];
+  return rank_check(h2[0], h2[1]);
+}
+
+// The build's stacking and factorisation (Step 2 creates the handle; the subdomains' columns are
+// already built): scratch allocated, used and freed here, one synchronisation, rank test.
+dpm_status dd_stack_factor_alloc(dpm_dd* d, hipStream_t s, double* A_out) {
+  const size_t fb = align_up(factor_scratch_bytes(d->rows, d->n_cols), 256);
+  void* scratch = nullptr;
+  if (hipMalloc(&scratch, fb + 256) != hipSuccess) {
+    set_error("decomposed-domain build: device allocation of %zu scratch bytes failed", fb + 256);
+    return DPM_ENOMEM;
+  }
+  double* rd2 = reinterpret_cast<double*>(static_cast<char*>(scratch) + fb);
+  double h2[2] = {0.0, 0.0};
+  dpm_status st = dd_stack_factor(d, s, A_out, scratch, fb, rd2);
+  hipError_t e = hipSuccess;
+  if (st == DPM_OK) e = hipMemcpyAsync(h2, rd2, sizeof(h2), hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = e2;
+  (void)hipFree(scratch);
+  if (st == DPM_OK && e != hipSuccess) {
+    set_error("decomposed-domain build: %s", hipGetErrorString(e));
+    st = DPM_EHIP;
+  }
+  if (st != DPM_OK) return st;
+  d->rdiag_min = h2[0];
+  d->rdiag_max = h2[1];
+  return rank_check(h2[0], h2[1]);
 }
 
 dpm_status dd_build_impl(const dpm_dd_params& prm, const dpm_opts& o, hipStream_t s,
@@ -475,7 +538,7 @@ dpm_status dd_build_impl(const dpm_dd_params& prm, const dpm_opts& o, hipStream_
     return fail(DPM_ENOMEM);
   }
   {
-    const dpm_status st = dd_stack_factor(d, s, A_out);
+    const dpm_status st = dd_stack_factor_alloc(d, s, A_out);
     if (st != DPM_OK) return fail(st);
   }
   *out = d;
@@ -621,21 +684,29 @@ dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStrea
     return fail(DPM_EHIP);
   }
   {
-    const dpm_status st = dd_stack_factor(d, s, A_out);
+    const dpm_status st = dd_stack_factor_alloc(d, s, A_out);
     if (st != DPM_OK) return fail(st);
   }
   *out = d;
   return DPM_OK;
 }
 
-dpm_status dd_rebuild_impl(dpm_dd* d, double sigma, hipStream_t s) {
+void dd_set_sigma(dpm_dd* d, double sigma) {
   d->prm.grid1.sigma = sigma;
   d->prm.grid2.sigma = sigma;
-  for (int l = 0; l < 2; ++l) {
-    d->sub[l]->grid.sigma = sigma;
-    DPM_TRY(bep_columns(d->sub[l], s));
+  for (int l = 0; l < 2; ++l) d->sub[l]->grid.sigma = sigma;
+}
+
+size_t dd_rebuild_workspace_bytes(const dpm_dd* d) { return dd_rebuild_scratch_bytes(d) + 256; }
+
+dpm_status dd_rebuild_impl(dpm_dd* d, double sigma, hipStream_t s, void* scratch, size_t bytes) {
+  if (scratch == nullptr || bytes < dd_rebuild_workspace_bytes(d)) {
+    set_error("dpm_dd_rebuild: workspace too small: %zu bytes given, %zu needed", bytes,
+              dd_rebuild_workspace_bytes(d));
+    return DPM_EINVAL;
   }
-  return dd_stack_factor(d, s, nullptr);
+  dd_set_sigma(d, sigma);
+  return dd_factor(d, s, nullptr, scratch, bytes);
 }
 
 double dd_sigma(const dpm_dd* d) { return d->prm.grid1.sigma; }
@@ -662,6 +733,13 @@ dpm_status dd_step_workspace_impl(const dpm_dd* d, const dpm_opts& o, size_t* by
   return DPM_OK;
 }
 
+dpm_status dd_run_workspace_impl(const dpm_dd* d, const dpm_opts& o, size_t* bytes) {
+  size_t need = 0;
+  DPM_TRY(dd_step_workspace_impl(d, o, &need));
+  *bytes = align_up(need, 256) + 256 + align_up(dd_rebuild_scratch_bytes(d), 256);
+  return DPM_OK;
+}
+
 dpm_status dd_step_impl(const dpm_dd* d, double dt, double chi, const double* const in[4],
                         double* const out[4], const dpm_opts& o, hipStream_t s) {
   size_t sw = 0;
@@ -678,7 +756,7 @@ dpm_status dd_step_impl(const dpm_dd* d, double dt, double chi, const double* co
   double* X[2];
   double* ug[2];
   for (int l = 0; l < 2; ++l) {
-    so[l].rhs_chunk = 0;
+    so[l].rhs_chunk = 2;
     so[l].workspace = ws + L.solve_ws[l];
     so[l].workspace_bytes = sw;
     b2[l] = reinterpret_cast<double*>(ws + L.b2[l]);
@@ -735,24 +813,42 @@ dpm_status dd_run_impl(dpm_dd* d, const dpm_run_params& p, double* const state[4
   size_t need = 0;
   DPM_TRY(dd_step_workspace_impl(d, o, &need));
   const size_t scan_off = align_up(need, 256);
-  if (o.workspace == nullptr || o.workspace_bytes < scan_off + 4 * sizeof(double)) {
+  const size_t reb_off = scan_off + 256;
+  const size_t reb_bytes = align_up(dd_rebuild_scratch_bytes(d), 256);
+  if (o.workspace == nullptr || o.workspace_bytes < reb_off + reb_bytes) {
     set_error("dpm_dd_run: workspace too small: %zu bytes given, %zu needed", o.workspace_bytes,
-              scan_off + 4 * sizeof(double));
+              reb_off + reb_bytes);
     return DPM_EINVAL;
   }
+  // scan[0..3]: both subdomains' scanned maxima; scan[4..5]: (min, max) |R_ii| of the last
+  // rebuild, read back with the next scan (a rebuild adds no synchronisation of its own)
   double* scan = reinterpret_cast<double*>(static_cast<char*>(o.workspace) + scan_off);
+  void* rscratch = static_cast<char*>(o.workspace) + reb_off;
   dpm_run_info r{};
   r.stop = DPM_RUN_MAXSTEPS;
   double t = 0.0, dt_prev = 1.0 / d->prm.grid1.sigma;
   double rho_prev = 0.0;  // max |rho| of the previous scan (none before the first)
   const double* in[4] = {state[0], state[1], state[2], state[3]};
+  bool rank_pending = false;
   for (;;) {
+    double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const bool more = t < p.t_final && r.steps < p.max_steps;
+    if (more)
+      for (int l = 0; l < 2; ++l)
+        DPM_TRY(cfl_scan_impl(d->sub[l], state[2 * l], state[2 * l + 1], scan + 2 * l, s));
+    if (more || rank_pending) {
+      DPM_TRY_HIP(hipMemcpyAsync(w, scan, sizeof(w), hipMemcpyDeviceToHost, s));
+      DPM_TRY_HIP(hipStreamSynchronize(s));
+    }
+    if (rank_pending) {
+      rank_pending = false;
+      d->rdiag_min = w[4];
+      d->rdiag_max = w[5];
+      DPM_TRY(rank_check(w[4], w[5]));
+    }
     if (t >= p.t_final) { r.stop = DPM_RUN_TFINAL; break; }
     if (r.steps >= p.max_steps) { r.stop = DPM_RUN_MAXSTEPS; break; }
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int l = 0; l < 2; ++l) DPM_TRY(cfl_scan_impl(d->sub[l], state[2 * l], state[2 * l + 1], scan + 2 * l, s));
-    DPM_TRY_HIP(hipMemcpyAsync(v, scan, sizeof(v), hipMemcpyDeviceToHost, s));
-    DPM_TRY_HIP(hipStreamSynchronize(s));
+    const double v[4] = {w[0], w[1], w[2], w[3]};
     r.grad_max = std::fmax(v[0], v[2]);
     r.rho_max = std::fmax(v[1], v[3]);
     bool finite = true;
@@ -776,7 +872,9 @@ dpm_status dd_run_impl(dpm_dd* d, const dpm_run_params& p, double* const state[4
       }
     const bool rebuild = dt < dt_prev;
     if (rebuild) {
-      DPM_TRY(dd_rebuild_impl(d, 1.0 / dt, s));
+      dd_set_sigma(d, 1.0 / dt);
+      DPM_TRY(dd_factor_enqueue(d, s, nullptr, rscratch, reb_bytes, scan + 4));
+      rank_pending = true;
       ++r.rebuilds;
     }
     DPM_TRY(dd_step_impl(d, dt, p.chi, in, state, o, s));

@@ -260,7 +260,7 @@ void launch_restrict(const dpm_bep* b, const double* U, double* o0, double* o1, 
 dpm_status step_workspace_impl(const dpm_bep* b, const dpm_opts& o, size_t* bytes) {
   size_t sw = 0;
   dpm_opts so = o;
-  so.rhs_chunk = 0;
+  so.rhs_chunk = 2;  // both species in one launch: the size never depends on tuning
   DPM_TRY(workspace_size_impl(b->grid, 2, so, &sw));
   *bytes = step_layout(b, sw).total;
   return DPM_OK;
@@ -275,7 +275,7 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   const dpm_grid& g = b->grid;
   size_t sw = 0;
   dpm_opts so = o;
-  so.rhs_chunk = 0;
+  so.rhs_chunk = 2;  // both species in one launch: the size never depends on tuning
   DPM_TRY(workspace_size_impl(g, 2, so, &sw));
   const StepLayout L = step_layout(b, sw);
   if (o.workspace == nullptr || o.workspace_bytes < L.total) {
@@ -332,7 +332,7 @@ dpm_status stepper_create_impl(const dpm_bep* b, double dt, double chi, double* 
   }
   size_t sw = 0;
   dpm_opts so = o;
-  so.rhs_chunk = 0;
+  so.rhs_chunk = 2;  // both species in one launch: the size never depends on tuning
   DPM_TRY(workspace_size_impl(b->grid, 2, so, &sw));
   int* gd = reinterpret_cast<int*>(static_cast<char*>(o.workspace) + step_layout(b, sw).guard);
   if (timing_enabled()) {
@@ -416,30 +416,66 @@ dpm_status cfl_scan_impl(const dpm_bep* b, const double* rho, const double* c, d
   return DPM_OK;
 }
 
+namespace {
+// dpm_run's workspace: [step workspace | scan area (scanned maxima, rank pair) | rebuild scratch]
+struct RunLayout {
+  size_t scan, rebuild, total;
+};
+dpm_status run_layout(const dpm_bep* b, const dpm_opts& o, RunLayout* L) {
+  size_t need = 0;
+  DPM_TRY(step_workspace_impl(b, o, &need));
+  L->scan = align_up(need, 256);
+  L->rebuild = L->scan + 256;
+  L->total = L->rebuild + align_up(rebuild_scratch_bytes(b), 256);
+  return DPM_OK;
+}
+}  // namespace
+
+dpm_status run_workspace_impl(const dpm_bep* b, const dpm_opts& o, size_t* bytes) {
+  RunLayout L{};
+  DPM_TRY(run_layout(b, o, &L));
+  *bytes = L.total;
+  return DPM_OK;
+}
+
 dpm_status run_impl(dpm_bep* b, const dpm_run_params& p, double* rho, double* c,
                     const dpm_opts& o, hipStream_t s, dpm_run_info* info, double* dt_hist,
                     uint8_t* rebuilt_hist) {
-  size_t need = 0;
-  DPM_TRY(step_workspace_impl(b, o, &need));
-  const size_t scan_off = align_up(need, 256);
-  if (o.workspace == nullptr || o.workspace_bytes < scan_off + 2 * sizeof(double)) {
+  RunLayout L{};
+  DPM_TRY(run_layout(b, o, &L));
+  if (o.workspace == nullptr || o.workspace_bytes < L.total) {
     set_error("dpm_run: workspace too small: %zu bytes given, %zu needed", o.workspace_bytes,
-              scan_off + 2 * sizeof(double));
+              L.total);
     return DPM_EINVAL;
   }
-  double* scan = reinterpret_cast<double*>(static_cast<char*>(o.workspace) + scan_off);
+  char* wsb = static_cast<char*>(o.workspace);
+  // scan[0..1]: scanned maxima; scan[2..3]: (min, max) |R_ii| of the last rebuild, read back
+  // with the next scan, so a rebuild adds no synchronisation of its own
+  double* scan = reinterpret_cast<double*>(wsb + L.scan);
+  void* rscratch = wsb + L.rebuild;
+  const size_t rbytes = L.total - L.rebuild;
   dpm_run_info r{};
   r.stop = DPM_RUN_MAXSTEPS;
   double t = 0.0, dt_prev = 1.0 / b->grid.sigma;
   double rho_prev = 0.0;  // max |rho| of the previous scan (none before the first)
+  bool rank_pending = false;
   for (;;) {
+    // Steps 3 and 8: the CFL-type bound and the size of rho, from the current state
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool more = t < p.t_final && r.steps < p.max_steps;
+    if (more) DPM_TRY(cfl_scan_impl(b, rho, c, scan, s));
+    if (more || rank_pending) {
+      DPM_TRY_HIP(hipMemcpyAsync(v, scan, sizeof(v), hipMemcpyDeviceToHost, s));
+      DPM_TRY_HIP(hipStreamSynchronize(s));
+    }
+    if (rank_pending) {
+      rank_pending = false;
+      b->rdiag_min = v[2];
+      b->rdiag_max = v[3];
+      DPM_TRY(rank_check(v[2], v[3]));
+    }
     if (t >= p.t_final) { r.stop = DPM_RUN_TFINAL; break; }
     if (r.steps >= p.max_steps) { r.stop = DPM_RUN_MAXSTEPS; break; }
-    // Steps 3 and 8: the CFL-type bound and the size of rho, from the current state
-    double v[2] = {0.0, 0.0};
-    DPM_TRY(cfl_scan_impl(b, rho, c, scan, s));
-    DPM_TRY_HIP(hipMemcpyAsync(v, scan, sizeof(v), hipMemcpyDeviceToHost, s));
-    DPM_TRY_HIP(hipStreamSynchronize(s));
     r.grad_max = v[0];
     r.rho_max = v[1];
     if (!(std::isfinite(v[0]) && std::isfinite(v[1]))) { r.stop = DPM_RUN_NONFINITE; break; }
@@ -457,7 +493,9 @@ dpm_status run_impl(dpm_bep* b, const dpm_run_params& p, double* rho, double* c,
     // Step 4b: a smaller step needs the matrix (and its QR) at the new sigma
     const bool rebuild = dt < dt_prev;
     if (rebuild) {
-      DPM_TRY(rebuild_bep_impl(b, 1.0 / dt, s));
+      b->grid.sigma = 1.0 / dt;
+      DPM_TRY(factor_bep_enqueue(b, s, nullptr, rscratch, rbytes, scan + 2));
+      rank_pending = true;
       ++r.rebuilds;
     }
     // Steps 4a-7 in place

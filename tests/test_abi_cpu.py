@@ -77,7 +77,17 @@ def test_host_validation_without_device():
     # the adaptive loop's entry points reject a missing handle before any launch
     prm = _lib.RunParams(1.0, 1.0, float("inf"), 10)
     assert lib.dpm_run(None, C.byref(prm), fake, odd, C.byref(o), None, None, None, None) == _lib.DPM_EINVAL
-    assert lib.dpm_bep_rebuild(None, 1.0, None) == _lib.DPM_EINVAL
+    assert lib.dpm_bep_rebuild(None, 1.0, None, 0, None) == _lib.DPM_EINVAL
+    assert lib.dpm_run_workspace_size(None, C.byref(o), None) == _lib.DPM_EINVAL
+    assert lib.dpm_bep_rebuild_workspace_size(None, None) == _lib.DPM_EINVAL
+    # dpm_step: the outputs must be two buffers, every volume 8-byte aligned (checked before the
+    # handle is read, so a stand-in handle pointer is never dereferenced)
+    h = C.c_void_p(0x70000000)
+    a, b2 = C.c_void_p(0x80000000), C.c_void_p(0x80100000)
+    st = lib.dpm_step(h, 0.1, 1.0, a, b2, b2, b2, C.byref(o), None, None)
+    assert st == _lib.DPM_EINVAL and "different buffers" in lib.dpm_last_error().decode()
+    st = lib.dpm_step(h, 0.1, 1.0, a, b2, C.c_void_p(0x80200004), b2, C.byref(o), None, None)
+    assert st == _lib.DPM_EINVAL and "aligned" in lib.dpm_last_error().decode()
     assert lib.dpm_cfl_scan(None, fake, fake, fake, None) == _lib.DPM_EINVAL
 
 
@@ -128,7 +138,9 @@ def test_dd_validation_without_device():
         assert build2(**kw) == _lib.DPM_EINVAL, kw
         assert word in lib.dpm_last_error().decode(), (kw, lib.dpm_last_error())
     prm = _lib.RunParams(1.0, 1.0, float("inf"), 10)
-    assert lib.dpm_dd_rebuild(None, 1.0, None) == _lib.DPM_EINVAL
+    assert lib.dpm_dd_rebuild(None, 1.0, None, 0, None) == _lib.DPM_EINVAL
+    assert lib.dpm_dd_run_workspace_size(None, C.byref(o), None) == _lib.DPM_EINVAL
+    assert lib.dpm_dd_rebuild_workspace_size(None, None) == _lib.DPM_EINVAL
     assert lib.dpm_dd_run(None, C.byref(prm), vols, C.byref(o), None, None, None, None) == _lib.DPM_EINVAL
 
 

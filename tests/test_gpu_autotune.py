@@ -47,3 +47,45 @@ def test_autotune_records_fastest_width(prec, max_refine, tol):
     finally:
         api.autotune_reset()
     assert api.rhs_chunk(api.grid(n, h, sigma), nrhs, api.opts(prec, True, 1e-10, max_refine)) == default
+
+
+def test_solve_narrows_width_to_its_workspace():
+    """A solve with rhs_chunk = 0 reads the width once and narrows it to what the caller's
+    workspace holds: a workspace sized for one right-hand side per launch (as one sized before a
+    re-tune or a reset can be) gives the same result as the default width, with no error."""
+    import ctypes as C
+
+    import torch
+    from paper_1811_03557_amd import _lib as L
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    n, nrhs = 31, 6
+    h, _ = inp.grid(n)
+    sigma = 1.0 / h + 1.0
+    b = inp.rhs_normal(n, nrhs, seed=12)
+    bt = torch.from_numpy(b).to(dev)
+    g = api.grid(n, h, sigma)
+    api.autotune_reset()
+    o1 = api.opts("fp32", True, 1e-10, 3, 1)
+    small = api.workspace_size(g, nrhs, o1)
+    o = api.opts("fp32", True, 1e-10, 3, 0)
+    assert api.rhs_chunk(g, nrhs, o) > 1
+    assert api.workspace_size(g, nrhs, o) > small
+    say(f"narrowed width n={n} nrhs={nrhs}: workspace {small} bytes (one right-hand side per launch)")
+    ws = torch.empty(small, dtype=torch.uint8, device=dev)
+    o.workspace = C.c_void_p(ws.data_ptr())
+    o.workspace_bytes = small
+    u = torch.empty_like(bt)
+    st = L.load().aux_solve_batched(C.byref(g), nrhs, C.c_void_p(bt.data_ptr()),
+                                    C.c_void_p(u.data_ptr()), C.byref(o), None, None)
+    L.check(st)
+    torch.cuda.synchronize()
+    u_def = api.aux_solve_batched(bt, sigma, h, prec="fp32", max_refine=3)
+    assert torch.equal(u, u_def)
+    # a fixed width (rhs_chunk > 0) is never narrowed: too small a workspace is an error
+    o2 = api.opts("fp32", True, 1e-10, 3, 2)
+    o2.workspace = C.c_void_p(ws.data_ptr())
+    o2.workspace_bytes = small
+    st = L.load().aux_solve_batched(C.byref(g), nrhs, C.c_void_p(bt.data_ptr()),
+                                    C.c_void_p(u.data_ptr()), C.byref(o2), None, None)
+    assert st == L.DPM_EINVAL

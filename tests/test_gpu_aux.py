@@ -154,18 +154,37 @@ def test_eigenmode_closed_form_full_size():
     assert _max_rel(u, ref) < TOL["fp64"]
 
 
+@pytest.mark.parametrize("sigma", [1.0, 1e4])
 @pytest.mark.parametrize("prec,kw,tol", [("fp64", {}, 1e-12),
                                          ("fp32", {"max_refine": 4, "rtol": 1e-10}, 1e-10)])
-def test_full_size_255_parity(prec, kw, tol):
-    """The benchmark's launch configuration (N = 255) against the oracle on 2 right-hand sides."""
+def test_full_size_255_parity(prec, kw, tol, sigma):
+    """The benchmark's launch configuration (N = 255) against the oracle on 2 right-hand sides,
+    at both ends of the workload's sigma range (1 and 1e4)."""
     dev = need_gpu()
     n = 255
-    say(f"n=255 parity {prec}")
+    say(f"n=255 parity {prec} sigma={sigma:g}")
     h, _ = inp.grid(n)
     b = inp.rhs_normal(n, 2, seed=0)
+    ref = oaux.aux_solve(b, sigma, h)
+    u = _solve(b, sigma, h, dev, prec=prec, **kw)
+    err = _max_rel(u, ref)
+    say(f"  rel err {err:.2e}")
+    assert err < tol
+
+
+def test_random_rhs_511_fp64():
+    """N = 511 (the paper's largest single-domain mesh of its speed-up table) on a random
+    right-hand side against the oracle, FP64 at 1e-12."""
+    dev = need_gpu()
+    n = 511
+    say("n=511 random right-hand side, fp64")
+    h, _ = inp.grid(n)
+    b = inp.rhs_normal(n, 1, seed=5)
     ref = oaux.aux_solve(b, 1.0, h)
-    u = _solve(b, 1.0, h, dev, prec=prec, **kw)
-    assert _max_rel(u, ref) < tol
+    u = _solve(b, 1.0, h, dev, prec="fp64")
+    err = _max_rel(u, ref)
+    say(f"  rel err {err:.2e}")
+    assert err < TOL["fp64"]
 
 
 def test_config1_manufactured():
