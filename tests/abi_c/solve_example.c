@@ -132,11 +132,13 @@ int main(void) {
 
   /* ---- 4. adaptive loop (Steps 3-8) from Test A data: the CFL-type bound cuts dt below
    *         0.5 h^2 at the first step, which rebuilds the boundary matrix in place */
+  size_t rwb = 0;
+  CHECK(dpm_run_workspace_size(bep, &so, &rwb));
   void* rws = NULL;
-  HCHECK(hipMalloc(&rws, swb + 256));
+  HCHECK(hipMalloc(&rws, rwb));
   dpm_opts ro = so;
   ro.workspace = rws;
-  ro.workspace_bytes = swb + 256;
+  ro.workspace_bytes = rwb;
   CHECK(dpm_gauss_state(bep, &geo, 1000.0, 100.0, c3, rho, NULL));
   CHECK(dpm_gauss_state(bep, &geo, 500.0, 50.0, c3, c, NULL));
   const dpm_run_params rp = {1.0, 1.0, 1e30, 4};
@@ -174,12 +176,12 @@ int main(void) {
     CHECK(dpm_dd_gauss_state(dd, l, 0.0, 1.0, cb, st4[2 * l + 1], NULL));
   }
   size_t dwb = 0;
-  CHECK(dpm_dd_step_workspace_size(dd, &so, &dwb));
+  CHECK(dpm_dd_run_workspace_size(dd, &so, &dwb));
   void* dws = NULL;
-  HCHECK(hipMalloc(&dws, dwb + 256));
+  HCHECK(hipMalloc(&dws, dwb));
   dpm_opts dop = so;
   dop.workspace = dws;
-  dop.workspace_bytes = dwb + 256;
+  dop.workspace_bytes = dwb;
   const dpm_run_params dr = {1.0, 1.0, 1e30, 3};
   dpm_run_info di;
   CHECK(dpm_dd_run(dd, &dr, st4, &dop, NULL, &di, NULL, NULL));
