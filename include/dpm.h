@@ -147,6 +147,29 @@ dpm_status aux_solve_batched_sigma(const dpm_grid* grid, int32_t nrhs, const dou
                                    const void* b, void* u, const dpm_opts* opts, void* stream,
                                    dpm_info* info);
 
+/* Bytes of the device scratch that aux_solve_batched_noalloc uses (64 MiB on every device the
+ * library runs on, held from library load until the process ends).  Enough for one 255^3 FP32
+ * transform volume plus the refinement state of up to several thousand right-hand sides. */
+#define DPM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* aux_solve_batched for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The call allocates nothing: it
+ * takes no workspace from the caller (opts->workspace and opts->workspace_bytes are ignored)
+ * and puts the refinement state and the transform volumes in a library-owned static device
+ * array of DPM_NOALLOC_SCRATCH_BYTES per device.  Arguments, layouts and results are those of
+ * aux_solve_batched (the same kernels); the launch width is the one aux_solve_batched would use,
+ * narrowed to what the static scratch holds.
+ * Errors: those of aux_solve_batched; DPM_EINVAL when even one right-hand side per launch does
+ * not fit the static scratch (for example FP32 transforms at n = 511), with nrhs so large that
+ * the per-right-hand-side state alone exceeds it, or when the size's tables were never built on
+ * the current device (call dpm_prepare(n) once at set-up: building them allocates).
+ * Every call on one device shares that device's scratch and leaves its contents behind (the
+ * state that must start at zero is cleared by a kernel at the start of each call): calls that
+ * overlap on one device, on different streams or threads, race and must be serialised by the
+ * caller. */
+dpm_status aux_solve_batched_noalloc(const dpm_grid* grid, int32_t nrhs, const void* b, void* u,
+                                     const dpm_opts* opts, void* stream, dpm_info* info);
+
 /* Geometry of the domain Omega inside the cube: a sphere (axes[0] = radius) or an ellipsoid
  * with semi-axes (axes[0], axes[1], axes[2]) along (x, y, z). */
 typedef struct {

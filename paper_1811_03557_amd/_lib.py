@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libdpm.so")
 DPM_OK, DPM_EINVAL, DPM_ENOMEM, DPM_EHIP, DPM_ENOTCONV, DPM_EGEOM, DPM_ERANK = range(7)
 DPM_FP64, DPM_FP32, DPM_BF16X3, DPM_FP64_GEMM = 0, 1, 2, 3
 DPM_DIAG_WORKSPACE_BYTES = 24576  # include/dpm.h
+DPM_NOALLOC_SCRATCH_BYTES = 64 << 20  # include/dpm.h
 STATUS_NAMES = {0: "DPM_OK", 1: "DPM_EINVAL", 2: "DPM_ENOMEM", 3: "DPM_EHIP",
                 4: "DPM_ENOTCONV", 5: "DPM_EGEOM", 6: "DPM_ERANK"}
 
@@ -72,6 +73,8 @@ SIGNATURES = {
     "dpm_prepare": (C.c_int, [_I]),
     "aux_solve": (C.c_int, [C.POINTER(Grid), _P, _P, C.POINTER(Opts), _P, C.POINTER(Info)]),
     "aux_solve_batched": (C.c_int, [C.POINTER(Grid), _I, _P, _P, C.POINTER(Opts), _P, C.POINTER(Info)]),
+    "aux_solve_batched_noalloc": (C.c_int, [C.POINTER(Grid), _I, _P, _P, C.POINTER(Opts), _P,
+                                            C.POINTER(Info)]),
     "aux_solve_batched_sigma": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(_D), _P, _P,
                                           C.POINTER(Opts), _P, C.POINTER(Info)]),
     "dpm_classify": (C.c_int, [C.POINTER(Grid), C.POINTER(Geometry), _P, _P]),

@@ -97,6 +97,39 @@ def aux_solve_batched(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64
     return res
 
 
+def aux_solve_batched_noalloc(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64",
+                              rtol: float = 1e-10, max_refine: int = 0,
+                              out: torch.Tensor | None = None, stream=None, info: bool = False,
+                              rhs_chunk: int = 0):
+    """aux_solve_batched through the entry point that allocates nothing on the device: no
+    workspace is passed, the library's static device scratch is used.  `out` must be given by a
+    caller that cannot allocate either (here a new tensor is made when it is None).  The size's
+    tables must have been built first (prepare(n))."""
+    lib = L.load()
+    single = b.dim() == 3
+    bb = b.unsqueeze(0) if single else b
+    if bb.dim() != 4 or not (bb.shape[1] == bb.shape[2] == bb.shape[3]):
+        raise ValueError("b must have shape (nrhs, n, n, n) or (n, n, n)")
+    nrhs, n = int(bb.shape[0]), int(bb.shape[1])
+    io_fp64 = bb.dtype == torch.float64
+    if not io_fp64 and bb.dtype != torch.float32:
+        raise ValueError("b must be float64 or float32")
+    if out is None:
+        out = torch.empty_like(bb)
+    uu = out.view(bb.shape) if out.dim() == 3 else out
+    g = grid(n, h, sigma)
+    o = opts(prec, io_fp64, rtol, max_refine, rhs_chunk)
+    inf = L.Info()
+    st = lib.aux_solve_batched_noalloc(C.byref(g), nrhs, C.c_void_p(_dev(bb, "b")),
+                                       C.c_void_p(_dev(uu, "u", bb.dtype)), C.byref(o),
+                                       C.c_void_p(_stream(stream)), C.byref(inf) if info else None)
+    L.check(st)
+    res = out if not single else out.view(n, n, n)
+    if info:
+        return res, {"refine_iters": inf.refine_iters, "est_rel_err": inf.est_rel_err}
+    return res
+
+
 def autotune(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64", rtol: float = 1e-10,
              max_refine: int = 0, reps: int = 3, out: torch.Tensor | None = None,
              stream=None) -> dict:

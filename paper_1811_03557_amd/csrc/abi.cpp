@@ -167,6 +167,42 @@ dpm_status aux_solve_batched_sigma(const dpm_grid* grid, int32_t nrhs, const dou
   return aux_solve_impl(*grid, nrhs, b, u, *opts, static_cast<hipStream_t>(stream), info, sigma);
 }
 
+dpm_status aux_solve_batched_noalloc(const dpm_grid* grid, int32_t nrhs, const void* b, void* u,
+                                     const dpm_opts* opts, void* stream, dpm_info* info) {
+  clear_error();
+  DPM_TRY(validate_grid(grid));
+  DPM_TRY(validate_opts(*grid, opts));
+  if (nrhs <= 0) { set_error("nrhs must be > 0"); return DPM_EINVAL; }
+  if (!b || !u) { set_error("b or u is NULL"); return DPM_EINVAL; }
+  if (!aligned_to(b, opts->io_fp64 ? 8 : 4) || !aligned_to(u, opts->io_fp64 ? 8 : 4)) {
+    set_error("b and u must be aligned to their element size");
+    return DPM_EINVAL;
+  }
+  const size_t bytes = (size_t)nrhs * grid->n * grid->n * grid->n * (opts->io_fp64 ? 8 : 4);
+  const char* bb = static_cast<const char*>(b);
+  const char* ub = static_cast<const char*>(u);
+  if (bb < ub + bytes && ub < bb + bytes) { set_error("b and u overlap"); return DPM_EINVAL; }
+  // size check on the host before any device call: the static scratch must hold the
+  // per-right-hand-side state and at least one right-hand side per launch
+  dpm_opts o = *opts;
+  o.workspace = nullptr;
+  o.workspace_bytes = kStaticScratchBytes;
+  if (workspace_for_chunk(*grid, nrhs, o, 1) > kStaticScratchBytes) {
+    set_error("aux_solve_batched_noalloc: n = %d, nrhs = %d needs %zu bytes of scratch, more "
+              "than the static maximum of %zu", grid->n, nrhs, workspace_for_chunk(*grid, nrhs, o, 1),
+              kStaticScratchBytes);
+    return DPM_EINVAL;
+  }
+  if (o.rhs_chunk > 0 && workspace_for_chunk(*grid, nrhs, o, o.rhs_chunk) > kStaticScratchBytes) {
+    set_error("aux_solve_batched_noalloc: rhs_chunk = %d does not fit the static scratch of %zu "
+              "bytes", o.rhs_chunk, kStaticScratchBytes);
+    return DPM_EINVAL;
+  }
+  DPM_TRY(static_scratch(&o.workspace));
+  return aux_solve_impl(*grid, nrhs, b, u, o, static_cast<hipStream_t>(stream), info, nullptr,
+                        true);
+}
+
 dpm_status aux_solve(const dpm_grid* grid, const void* b, void* u, const dpm_opts* opts,
                      void* stream, dpm_info* info) {
   return aux_solve_batched(grid, 1, b, u, opts, stream, info);

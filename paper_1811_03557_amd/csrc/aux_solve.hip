@@ -241,9 +241,9 @@ static dpm_status five_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind 
 }
 
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, const dpm_opts& o,
-                          hipStream_t s, dpm_info* info, const double* sigma_host) {
+                          hipStream_t s, dpm_info* info, const double* sigma_host, bool no_alloc) {
   const Plan* pl = nullptr;
-  DPM_TRY(get_plan(g.n, &pl));
+  DPM_TRY(no_alloc ? find_plan(g.n, &pl) : get_plan(g.n, &pl));
   const int rb = real_bytes_of(o);
   const int form = o.prec == DPM_BF16X3 ? FORM_BF16X3 : o.prec == DPM_FP64_GEMM ? FORM_F64MM : FORM_FFT;
   const bool ws_needed = needs_ws(o);
@@ -315,18 +315,23 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
     info->est_rel_err = 0.0;
   } else if (info) {
     DPM_TRY_HIP(hipStreamSynchronize(s));
-    std::vector<int> it(nrhs), dn(nrhs);
-    std::vector<double> est(nrhs);
-    DPM_TRY_HIP(hipMemcpy(it.data(), fl.iters, sizeof(int) * nrhs, hipMemcpyDeviceToHost));
-    DPM_TRY_HIP(hipMemcpy(dn.data(), fl.done, sizeof(int) * nrhs, hipMemcpyDeviceToHost));
-    DPM_TRY_HIP(hipMemcpy(est.data(), fl.est, sizeof(double) * nrhs, hipMemcpyDeviceToHost));
     info->refine_iters = 0;
     info->est_rel_err = 0.0;
     bool all_done = true;
-    for (int i = 0; i < nrhs; ++i) {
-      if (it[i] > info->refine_iters) info->refine_iters = it[i];
-      if (est[i] > info->est_rel_err || !(est[i] == est[i])) info->est_rel_err = est[i];
-      if (!dn[i]) all_done = false;
+    // read back in fixed blocks of the per-RHS state (no host containers)
+    constexpr int kB = 256;
+    int it[kB], dn[kB];
+    double est[kB];
+    for (int r0 = 0; r0 < nrhs; r0 += kB) {
+      const int m = nrhs - r0 < kB ? nrhs - r0 : kB;
+      DPM_TRY_HIP(hipMemcpy(it, fl.iters + r0, sizeof(int) * m, hipMemcpyDeviceToHost));
+      DPM_TRY_HIP(hipMemcpy(dn, fl.done + r0, sizeof(int) * m, hipMemcpyDeviceToHost));
+      DPM_TRY_HIP(hipMemcpy(est, fl.est + r0, sizeof(double) * m, hipMemcpyDeviceToHost));
+      for (int i = 0; i < m; ++i) {
+        if (it[i] > info->refine_iters) info->refine_iters = it[i];
+        if (est[i] > info->est_rel_err || !(est[i] == est[i])) info->est_rel_err = est[i];
+        if (!dn[i]) all_done = false;
+      }
     }
     if (!refine) info->est_rel_err = 0.0;
     if (refine && !all_done) {

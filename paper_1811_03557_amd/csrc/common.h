@@ -56,6 +56,9 @@ struct Plan {
 
 // Returns the plan of the current device for size n (creating it on first use).
 dpm_status get_plan(int n, const Plan** out);
+// The same, without creating it: DPM_EINVAL when dpm_prepare(n) (or a first solve of size n)
+// has not run on the current device.  Allocates nothing.
+dpm_status find_plan(int n, const Plan** out);
 
 bool fft_size_supported(int n);  // n + 1 a power of two and 7 <= n <= 1023
 // Sizes of the dense (GEMM-form) FP64 sweeps: any 7 <= n <= kDenseMaxN (matrix padded to a
@@ -116,9 +119,16 @@ struct SolveFlags {
 };
 
 size_t flags_bytes(int nrhs);
+// no_alloc: take the plan with find_plan (never create it) and read `info` back without host
+// containers; the caller passes the library's static scratch as the workspace.
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u,
                           const dpm_opts& o, hipStream_t s, dpm_info* info,
-                          const double* sigma_host = nullptr);
+                          const double* sigma_host = nullptr, bool no_alloc = false);
+// Device scratch of aux_solve_batched_noalloc: kStaticScratchBytes per device, owned by the
+// library for the life of the process (static_scratch.hip).  Returns its device address on the
+// current device, looked up once per device.
+constexpr size_t kStaticScratchBytes = DPM_NOALLOC_SCRATCH_BYTES;
+dpm_status static_scratch(void** out);
 // Right-hand sides per sweep launch that a solve of nrhs right-hand sides uses.
 int rhs_chunk_of(const dpm_grid& g, int nrhs, const dpm_opts& o);
 dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes);

@@ -142,4 +142,18 @@ dpm_status get_plan(int n, const Plan** out) {
   return DPM_OK;
 }
 
+dpm_status find_plan(int n, const Plan** out) {
+  int dev = 0;
+  DPM_TRY_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  auto it = g_plans.find(std::make_pair(dev, n));
+  if (it == g_plans.end()) {
+    set_error("the tables of n = %d are not built on device %d: call dpm_prepare(%d) first", n,
+              dev, n);
+    return DPM_EINVAL;
+  }
+  *out = it->second;
+  return DPM_OK;
+}
+
 }  // namespace dpm
