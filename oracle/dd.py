@@ -139,8 +139,11 @@ class DDCase2:
     """Grids, point sets, parts and effective densities of the two subdomains of Case 2."""
 
     def __init__(self, n1: int, half1: float, zc1: float, n2: int, q_z: float, r_z: float,
-                 m_gamma: int, m_z: int, beta: int = 0, eps_layers: float = 2.0):
+                 m_gamma: int, m_z: int, beta: int = 0, eps_layers: float = 2.0,
+                 rcond: float | None = None):
         self.q_z, self.r_z = q_z, r_z
+        # least squares of the coupled BEPs: None plain, > 0 truncated minimum norm (dpm.least_squares)
+        self.rcond = rcond
         self.n1, self.n2 = n1, n2
         self.m_gamma, self.m_z, self.beta = m_gamma, m_z, beta
         self.n_gamma_cols = (beta + 1) * (m_gamma + 1)
@@ -234,7 +237,7 @@ def dd2_step(rho1, c1, rho2, c2, case: DDCase2, A: np.ndarray, dt: float, chi: f
     for f1, f2 in ((f1r, f2r), (f1c, f2c)):
         G = [particular_solution(f, s["ps"], sigma, s["h"]) for f, s in ((f1, s1), (f2, s2))]
         g = np.concatenate([trace(Gl, s["ps"].idx_in)[s["rows"][:, 0]] for Gl, s in zip(G, case.sub)])
-        C = least_squares(A, g)
+        C = least_squares(A, g, case.rcond)
         u = []
         for Gl, s in zip(G, case.sub):
             ug = s["B_eff"].T @ C

@@ -74,9 +74,13 @@ def bep_matrix(basis: np.ndarray, ps: PointSets, sigma: float, h: float) -> np.n
     return A
 
 
-def least_squares(A: np.ndarray, g: np.ndarray) -> np.ndarray:
-    """argmin_C ||A C - g||_2 (LAPACK via numpy)."""
-    return np.linalg.lstsq(A, g, rcond=None)[0]
+def least_squares(A: np.ndarray, g: np.ndarray, rcond: float | None = None) -> np.ndarray:
+    """argmin_C ||A C - g||_2 (Sec. 2, the reduced BEP solved by least squares; LAPACK via
+    numpy).  rcond None: the plain least-squares solution (full column rank).  rcond > 0: the
+    minimum-norm least-squares solution with every singular value s <= rcond * s_max of A taken
+    as zero (the truncated pseudo-inverse, the reading used where the coupled matrix of the
+    decomposed domain is numerically rank deficient)."""
+    return np.linalg.lstsq(A, g, rcond=rcond)[0]
 
 
 def green_formula(u_gamma: np.ndarray, f: np.ndarray, ps: PointSets, sigma: float,

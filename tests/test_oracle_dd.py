@@ -214,3 +214,32 @@ def test_dd2_least_squares_well_posed_at_test_sizes(small2):
     for s in case.sub:
         u1, u2 = s["B_eff"].T @ c1, s["B_eff"].T @ c2
         assert np.max(np.abs(u1 - u2)) <= 1e-10 * np.max(np.abs(u1))
+
+
+def test_dd2_truncated_least_squares_with_twenty_harmonics_on_z():
+    """The paper's 20 harmonics per term on Z make the coupled matrix of Case 2 numerically rank
+    deficient (singular values fall smoothly to 1e-19 of the largest).  With the truncated
+    minimum-norm reading (rcond = 1e-7, inside the gap 3.4e-7 -> 4.1e-8 of this configuration) two
+    different SVD-based LAPACK solvers, gelsd (numpy) and gelss (scipy), give the same densities
+    to 1e-9.  The constant state is a consistent right-hand side; truncation keeps it to the
+    level of the dropped singular values, not to rounding (1e-5 relative; measured 2.8e-7 on
+    Omega_1 and 1.4e-6 on Omega_2, against 1e-11 untruncated)."""
+    from scipy.linalg import lstsq as sp_lstsq
+    case = dd.DDCase2(31, 0.75, 0.75, 31, 1.0, 0.5, 19, 19, beta=0, rcond=1e-7)
+    dt = 1e-3
+    A = dd.dd2_matrix(case, 1 / dt)
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert sv[-1] < 1e-15 * sv[0]  # rank deficient without truncation
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(A.shape[0])
+    c1 = dpm.least_squares(A, g, case.rcond)
+    c2 = sp_lstsq(A, g, cond=case.rcond, lapack_driver="gelss")[0]
+    for s in case.sub:
+        u1, u2 = s["B_eff"].T @ c1, s["B_eff"].T @ c2
+        assert np.max(np.abs(u1 - u2)) <= 1e-9 * np.max(np.abs(u1))
+    st = []
+    for s in case.sub:
+        st += [np.where(s["ps"].n_plus, 3.0, 0.0), np.where(s["ps"].n_plus, 5.0, 0.0)]
+    out = dd.dd2_step(*st, case, A, dt, 1.0)
+    for (r, _), s in ((out[:2], case.sub[0]), (out[2:4], case.sub[1])):
+        assert np.max(np.abs(r[s["ps"].n_plus] - 3.0)) <= 3e-5

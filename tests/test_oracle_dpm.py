@@ -85,6 +85,30 @@ def test_bep_matrix_and_lsq(small):
 
 # ----------------------------------------------------------------------------- PKS forcing
 
+def test_truncated_least_squares_closed_form():
+    """The truncated minimum-norm least squares (rcond > 0) against its closed form on a matrix
+    built from chosen singular triplets, A = 7.3 U diag(s) V^T with s spanning 1 .. 1e-13: the
+    solution is V_k diag(1 / (7.3 s_k)) U_k^T g over the kept triplets (s > rcond, relative to the
+    largest, which is why A is scaled), it has no component along the dropped right singular
+    vectors, and without truncation it is the plain least-squares solution."""
+    rng = np.random.default_rng(11)
+    m, n = 60, 9
+    U = np.linalg.qr(rng.standard_normal((m, n)))[0]
+    V = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    s = np.array([1.0, 0.6, 0.2, 3e-2, 1e-4, 2e-6, 5e-9, 1e-11, 1e-13])
+    A = 7.3 * (U * s) @ V.T
+    g = rng.standard_normal(m)
+    for rcond, kept in ((1e-5, 5), (1e-7, 6), (1e-10, 7)):
+        C = dpm.least_squares(A, g, rcond)
+        ref = V[:, :kept] @ ((U[:, :kept].T @ g) / (7.3 * s[:kept]))
+        # rounding of A is amplified by the smallest kept singular value's inverse
+        tol = 1e-13 / s[kept - 1]
+        assert np.max(np.abs(C - ref)) <= tol * np.max(np.abs(ref)), rcond
+        assert np.max(np.abs(V[:, kept:].T @ C)) <= tol * np.max(np.abs(C))
+    B = rng.standard_normal((m, n))  # well conditioned: truncation changes nothing
+    assert np.allclose(dpm.least_squares(B, g, 1e-7), dpm.least_squares(B, g), rtol=1e-12)
+
+
 def test_minmod():
     a = np.array([1.0, -1.0, 1.0, 0.0, 3.0, -3.0])
     b = np.array([2.0, -2.0, -1.0, 1.0, 2.0, -5.0])
