@@ -67,7 +67,20 @@ typedef struct {
   int32_t rhs_chunk;   /* right-hand sides per batched launch (0 = library choice) */
   void* workspace;     /* device scratch of >= workspace_bytes, from dpm_workspace_size */
   size_t workspace_bytes;
+  int32_t sweeps;      /* dpm_sweeps: how the FFT-form transforms pass over the volume */
 } dpm_opts;
+
+/* Sweep layout of the FFT-form solves (DPM_FP64, DPM_FP32).  A solve applies the DST-I along x,
+ * y and z, divides by the eigenvalues and applies the three DST-Is again; the layouts differ in
+ * how many times the volume travels through HBM.
+ *  DPM_SWEEPS_AUTO (0): the library's choice: DPM_SWEEPS_PLANE where available, else
+ *    DPM_SWEEPS_AXIS (or the layout dpm_autotune recorded).
+ *  DPM_SWEEPS_AXIS: five per-axis sweeps (x, y, fused z, y, x).
+ *  DPM_SWEEPS_PLANE: three sweeps: both in-plane transforms of a z-plane in one pass with the
+ *    plane in LDS (n = 7, 15, 31, 63, 127), the fused z sweep, the inverse plane pass.
+ * Results agree to rounding (the transforms are the same, applied in another order of
+ * operations only where the plane is transposed).  The dense forms ignore the field. */
+typedef enum { DPM_SWEEPS_AUTO = 0, DPM_SWEEPS_AXIS = 1, DPM_SWEEPS_PLANE = 2 } dpm_sweeps;
 
 typedef struct {
   int32_t refine_iters;  /* refinement iterations actually applied (max over the batch) */
@@ -82,40 +95,44 @@ dpm_status dpm_workspace_size(const dpm_grid* grid, int32_t nrhs, const dpm_opts
  * these options (opts->rhs_chunk if set, else the library's choice for the grid size). */
 dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, int32_t* chunk);
 
-/* Autotuner of the batched launches' width: the number of right-hand sides a sweep launch
- * carries.  The kernels' tiles are fixed at compile time; this width is the launch shape
- * chosen at run time.  It sets the launch count and how much of a launch's working set the 256 MB
- * Infinity Cache holds, so the best value depends on n, the precision and the chip.  (The width
- * suits the batched right-hand sides of the boundary-matrix build, Step 2 of the paper's
- * algorithm, and any batch of auxiliary problems.)
+/* Autotuner of the batched launches' shape: the number of right-hand sides a sweep launch
+ * carries (the width) and, where the fused plane sweeps exist (FFT form, n <= 127), the sweep
+ * layout (dpm_sweeps).  The kernels' tiles are fixed at compile time; the width and the layout
+ * are the launch shape chosen at run time.  The width sets the launch count and how much of a
+ * launch's working set the 256 MB Infinity Cache holds; the layout trades two fewer passes over
+ * HBM against the plane sweep's lower occupancy; so the best pair depends on n, the precision and
+ * the chip.  (It suits the batched right-hand sides of the boundary-matrix build, Step 2 of the
+ * paper's algorithm, and any batch of auxiliary problems.)
  *
  * Times aux_solve_batched(grid, nrhs, b, u, opts) for each candidate width in
  * {1, 2, 3, 4, 6, 8, 12, 16} that is at most nrhs, whose workspace fits
  * opts->workspace_bytes, and (for options that keep a transform workspace: FP32 with FP64 I/O,
  * refined FP64, BF16X3) at most the library's default width, so that a workspace sized before
- * tuning stays large enough.  opts->rhs_chunk is ignored.  Each candidate takes one untimed solve,
- * then `reps` solves timed with HIP events on `stream`; the fastest is kept, and ties keep the
- * narrower width.
+ * tuning stays large enough; with opts->sweeps == DPM_SWEEPS_AUTO every width is timed in both
+ * layouts where both exist, else in the given layout.  opts->rhs_chunk is ignored.  Each
+ * candidate takes one untimed solve, then `reps` solves timed with HIP events on `stream`; the
+ * fastest is kept, and ties keep the earlier candidate (narrower width, per-axis layout first).
  *
- * The winning width is recorded for (current device, n, prec, io_fp64, max_refine > 0).  From
- * then on every solve with opts->rhs_chunk == 0 uses it, as do dpm_workspace_size and
- * dpm_rhs_chunk.  A solve's results do not depend on the width; only its speed does.
+ * The winning pair is recorded for (current device, n, prec, io_fp64, max_refine > 0).  From
+ * then on every solve with opts->rhs_chunk == 0 uses its width, as do dpm_workspace_size and
+ * dpm_rhs_chunk, and every solve with opts->sweeps == DPM_SWEEPS_AUTO its layout.  A solve's
+ * results do not depend on the width; the layouts agree to rounding.
  *
  * b and u are caller-owned device arrays as for aux_solve_batched, and u is overwritten with
- * the solution.  The outputs are host arrays, each nullable: widths[8] and ms[8] (each candidate's
- * best time per batched solve, in ms), *count (candidates timed) and *best (the width recorded).
- * The call synchronises the stream.
+ * the solution.  The outputs are host arrays, each nullable: widths[16], sweeps[16] and ms[16]
+ * (each candidate's width, layout and best time per batched solve, in ms), *count (candidates
+ * timed), *best and *best_sweeps (the pair recorded).  The call synchronises the stream.
  *
  * Errors: those of aux_solve_batched; DPM_EINVAL for reps outside [1, 100], for a workspace that
  * fits no candidate, or while sweep timing is on.  The table is process-wide and guarded by a
- * lock; a solve reads the width once and takes either the old width or the new.  A solve whose
+ * lock; a solve reads it once and takes either the old pair or the new.  A solve whose
  * workspace (opts->rhs_chunk == 0) is smaller than the recorded width needs, for example one
  * sized before a re-tune or a reset, runs at the widest width the workspace holds. */
 dpm_status dpm_autotune(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, const void* b,
-                        void* u, int32_t reps, void* stream, int32_t* widths, double* ms,
-                        int32_t* count, int32_t* best);
+                        void* u, int32_t reps, void* stream, int32_t* widths, int32_t* sweeps,
+                        double* ms, int32_t* count, int32_t* best, int32_t* best_sweeps);
 
-/* Forgets every recorded width: solves go back to the library's default widths. */
+/* Forgets every recorded pair: solves go back to the library's default widths and layouts. */
 void dpm_autotune_reset(void);
 
 /* Builds the per-(device, n) tables (sine/twiddle and eigenvalue tables) ahead of time.  The
@@ -451,6 +468,11 @@ typedef struct {
   int32_t m_gamma;     /* highest degree on Gamma, >= 0 */
   int32_t beta;        /* 1: 3-term extension on Gamma, 0: 2-term */
   int32_t m_z;         /* highest degree on Z, >= 0 */
+  double rcond;        /* least squares of the coupled BEPs: 0 = plain (full column rank
+                          required: DPM_ERANK otherwise); 0 < rcond < 1 = minimum-norm solution
+                          with the singular values <= rcond * s_max taken as zero (for the
+                          numerically rank-deficient matrices of many harmonics on Z's arc; at
+                          most 640 columns) */
 } dpm_dd2_params;
 dpm_status dpm_dd2_build(const dpm_dd2_params* params, const dpm_opts* opts, void* stream,
                          dpm_dd** out, double* A_out);
@@ -460,6 +482,11 @@ dpm_status dpm_dd2_build(const dpm_dd2_params* params, const dpm_opts* opts, voi
 dpm_status dpm_dd_info(const dpm_dd* dd, int32_t n_gamma[2], int32_t n_gamma_in[2],
                        int32_t n_rows[2], int32_t* n_cols, double* min_abs_rdiag,
                        double* max_abs_rdiag);
+
+/* Least squares of a built handle (host values, each nullable): the rcond it was built with,
+ * the numerical rank of the coupled matrix (its column count when rcond = 0) and the smallest
+ * kept singular value over the largest (0 when rcond = 0).  Refreshed by every rebuild. */
+dpm_status dpm_dd_lsq_info(const dpm_dd* dd, double* rcond, int32_t* rank, double* smin_ratio);
 
 /* Copies of subdomain l's (0 or 1) M+ and N+ masks (device, its N^3 uint8; each nullable). */
 dpm_status dpm_dd_masks(const dpm_dd* dd, int32_t l, uint8_t* m_plus, uint8_t* n_plus,
@@ -564,7 +591,8 @@ dpm_status dpm_dd_diagnostics(const dpm_dd* dd, const double* const state[4], do
  * rhs_stride (1 = every launch; a larger stride keeps the events' own cost out of the timed
  * work).  dpm_timing_end synchronises the events and returns, per sweep kind, the number of timed
  * launches and their mean duration in ms.  Kinds: 0 first x sweep, 1 y sweep, 2 fused z sweep,
- * 3 last x sweep, 4 residual x sweep, 5 update x sweep.  At most max_launches launches are
+ * 3 last x sweep, 4 residual x sweep, 5 update x sweep, 6 forward plane sweep (any input kind),
+ * 7 inverse plane sweep (any output kind).  At most max_launches launches are
  * recorded.  Process-wide, not thread safe.
  */
 dpm_status dpm_timing_begin(int32_t max_launches, int32_t rhs_stride);

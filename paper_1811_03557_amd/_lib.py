@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libdpm.so")
 
 DPM_OK, DPM_EINVAL, DPM_ENOMEM, DPM_EHIP, DPM_ENOTCONV, DPM_EGEOM, DPM_ERANK = range(7)
 DPM_FP64, DPM_FP32, DPM_BF16X3, DPM_FP64_GEMM = 0, 1, 2, 3
+DPM_SWEEPS_AUTO, DPM_SWEEPS_AXIS, DPM_SWEEPS_PLANE = 0, 1, 2
 DPM_DIAG_WORKSPACE_BYTES = 24576  # include/dpm.h
 DPM_NOALLOC_SCRATCH_BYTES = 64 << 20  # include/dpm.h
 STATUS_NAMES = {0: "DPM_OK", 1: "DPM_EINVAL", 2: "DPM_ENOMEM", 3: "DPM_EHIP",
@@ -26,7 +27,8 @@ class Grid(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("io_fp64", C.c_int32), ("rtol", C.c_double),
                 ("max_refine", C.c_int32), ("rhs_chunk", C.c_int32),
-                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("sweeps", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -61,7 +63,7 @@ class DD2Params(C.Structure):
     _fields_ = [("grid1", Grid), ("grid2", Grid), ("origin1", C.c_double * 3),
                 ("origin2", C.c_double * 3), ("r_gamma", C.c_double), ("q_z", C.c_double),
                 ("r_z", C.c_double), ("eps_layers", C.c_double), ("m_gamma", C.c_int32),
-                ("beta", C.c_int32), ("m_z", C.c_int32)]
+                ("beta", C.c_int32), ("m_z", C.c_int32), ("rcond", C.c_double)]
 
 
 # exported symbol -> (restype, argtypes)
@@ -106,6 +108,7 @@ SIGNATURES = {
     "dpm_dd2_build": (C.c_int, [C.POINTER(DD2Params), C.POINTER(Opts), _P, C.POINTER(_P), _P]),
     "dpm_dd_info": (C.c_int, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I), C.POINTER(_I),
                               C.POINTER(_D), C.POINTER(_D)]),
+    "dpm_dd_lsq_info": (C.c_int, [_P, C.POINTER(_D), C.POINTER(_I), C.POINTER(_D)]),
     "dpm_dd_masks": (C.c_int, [_P, _I, _P, _P, _P]),
     "dpm_dd_step_workspace_size": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
     "dpm_dd_step": (C.c_int, [_P, _D, _D, C.POINTER(_P), C.POINTER(_P), C.POINTER(Opts), _P]),
@@ -125,7 +128,7 @@ SIGNATURES = {
     "dpm_timing_begin": (C.c_int, [_I, _I]),
     "dpm_rhs_chunk": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(Opts), C.POINTER(_I)]),
     "dpm_autotune": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(Opts), _P, _P, _I, _P, _P, _P, _P,
-                               _P]),
+                               _P, _P, _P]),
     "dpm_autotune_reset": (None, []),
     "dpm_timing_end": (C.c_int, [_I, C.POINTER(_I), C.POINTER(_D)]),
 }

@@ -35,10 +35,13 @@ def grid(n: int, h: float, sigma: float = 0.0, x0: float = 0.0) -> L.Grid:
     return L.Grid(int(n), float(h), float(sigma), float(x0))
 
 
+SWEEPS = {"auto": L.DPM_SWEEPS_AUTO, "axis": L.DPM_SWEEPS_AXIS, "plane": L.DPM_SWEEPS_PLANE}
+
+
 def opts(prec: str = "fp64", io_fp64: bool = True, rtol: float = 1e-10, max_refine: int = 0,
-         rhs_chunk: int = 0) -> L.Opts:
+         rhs_chunk: int = 0, sweeps: str = "auto") -> L.Opts:
     return L.Opts(PRECISIONS[prec], 1 if io_fp64 else 0, float(rtol), int(max_refine),
-                  int(rhs_chunk), None, 0)
+                  int(rhs_chunk), None, 0, SWEEPS[sweeps])
 
 
 def workspace_size(g: L.Grid, nrhs: int, o: L.Opts) -> int:
@@ -62,7 +65,7 @@ def prepare(n: int) -> None:
 def aux_solve_batched(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64",
                       rtol: float = 1e-10, max_refine: int = 0, out: torch.Tensor | None = None,
                       workspace: torch.Tensor | None = None, stream=None, info: bool = False,
-                      rhs_chunk: int = 0):
+                      rhs_chunk: int = 0, sweeps: str = "auto"):
     """Solve (sigma I - Lap_h) u = b for b of shape (nrhs, n, n, n) (or (n, n, n)).
 
     Returns u (and a dpm_info dict when info=True; that synchronises the stream).
@@ -80,7 +83,7 @@ def aux_solve_batched(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64
         out = torch.empty_like(bb)
     uu = out.view(bb.shape) if out.dim() == 3 else out
     g = grid(n, h, sigma)
-    o = opts(prec, io_fp64, rtol, max_refine, rhs_chunk)
+    o = opts(prec, io_fp64, rtol, max_refine, rhs_chunk, sweeps)
     nbytes = workspace_size(g, nrhs, o)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=bb.device)
@@ -100,7 +103,7 @@ def aux_solve_batched(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64
 def aux_solve_batched_noalloc(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64",
                               rtol: float = 1e-10, max_refine: int = 0,
                               out: torch.Tensor | None = None, stream=None, info: bool = False,
-                              rhs_chunk: int = 0):
+                              rhs_chunk: int = 0, sweeps: str = "auto"):
     """aux_solve_batched through the entry point that allocates nothing on the device: no
     workspace is passed, the library's static device scratch is used.  `out` must be given by a
     caller that cannot allocate either (here a new tensor is made when it is None).  The size's
@@ -118,7 +121,7 @@ def aux_solve_batched_noalloc(b: torch.Tensor, sigma: float, h: float, prec: str
         out = torch.empty_like(bb)
     uu = out.view(bb.shape) if out.dim() == 3 else out
     g = grid(n, h, sigma)
-    o = opts(prec, io_fp64, rtol, max_refine, rhs_chunk)
+    o = opts(prec, io_fp64, rtol, max_refine, rhs_chunk, sweeps)
     inf = L.Info()
     st = lib.aux_solve_batched_noalloc(C.byref(g), nrhs, C.c_void_p(_dev(bb, "b")),
                                        C.c_void_p(_dev(uu, "u", bb.dtype)), C.byref(o),
@@ -130,13 +133,17 @@ def aux_solve_batched_noalloc(b: torch.Tensor, sigma: float, h: float, prec: str
     return res
 
 
+SWEEP_NAMES = {L.DPM_SWEEPS_AXIS: "axis", L.DPM_SWEEPS_PLANE: "plane"}
+
+
 def autotune(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64", rtol: float = 1e-10,
              max_refine: int = 0, reps: int = 3, out: torch.Tensor | None = None,
-             stream=None) -> dict:
+             stream=None, sweeps: str = "auto") -> dict:
     """Time the batched solve of b (nrhs, n, n, n) at each candidate launch width (right-hand
-    sides per sweep launch) and record the fastest for this device, size and precision; later
-    solves with rhs_chunk = 0 use it.  Returns {"widths", "ms", "best"}, with ms the best time
-    per batched solve.  u (out, or a new tensor) receives the solution.  Synchronises the stream."""
+    sides per sweep launch) and sweep layout, and record the fastest pair for this device, size
+    and precision; later solves with rhs_chunk = 0 / sweeps = "auto" use it.  Returns
+    {"widths", "sweeps", "ms", "best", "best_sweeps"}, with ms the best time per batched solve.
+    u (out, or a new tensor) receives the solution.  Synchronises the stream."""
     lib = L.load()
     if b.dim() != 4 or not (b.shape[1] == b.shape[2] == b.shape[3]):
         raise ValueError("b must have shape (nrhs, n, n, n)")
@@ -150,18 +157,20 @@ def autotune(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64", rtol: 
     # a workspace for the widest candidate fits every narrower one
     nbytes = workspace_size(g, nrhs, opts(prec, io_fp64, rtol, max_refine, min(16, nrhs)))
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=b.device)
-    o = opts(prec, io_fp64, rtol, max_refine, 0)
+    o = opts(prec, io_fp64, rtol, max_refine, 0, sweeps)
     o.workspace = C.c_void_p(ws.data_ptr())
     o.workspace_bytes = ws.numel()
-    widths = (C.c_int32 * 8)()
-    ms = (C.c_double * 8)()
-    count, best = C.c_int32(0), C.c_int32(0)
+    widths = (C.c_int32 * 16)()
+    lays = (C.c_int32 * 16)()
+    ms = (C.c_double * 16)()
+    count, best, best_l = C.c_int32(0), C.c_int32(0), C.c_int32(0)
     L.check(lib.dpm_autotune(C.byref(g), nrhs, C.byref(o), C.c_void_p(_dev(b, "b")),
                              C.c_void_p(_dev(out, "u", b.dtype)), int(reps),
-                             C.c_void_p(_stream(stream)), widths, ms, C.byref(count),
-                             C.byref(best)))
+                             C.c_void_p(_stream(stream)), widths, lays, ms, C.byref(count),
+                             C.byref(best), C.byref(best_l)))
     k = count.value
-    return {"widths": list(widths[:k]), "ms": list(ms[:k]), "best": best.value}
+    return {"widths": list(widths[:k]), "sweeps": [SWEEP_NAMES[v] for v in lays[:k]],
+            "ms": list(ms[:k]), "best": best.value, "best_sweeps": SWEEP_NAMES[best_l.value]}
 
 
 def autotune_reset() -> None:
@@ -365,6 +374,14 @@ class DD:
         self.n_cols = nc.value
         self.rdiag = (rmin.value, rmax.value)
 
+    def lsq_info(self) -> dict:
+        """rcond of the coupled least squares, the numerical rank of the coupled matrix and the
+        smallest kept singular value over the largest (truncated least squares only)."""
+        rc, rk, sm = C.c_double(0), C.c_int32(0), C.c_double(0)
+        L.check(L.load().dpm_dd_lsq_info(C.c_void_p(self.ptr), C.byref(rc), C.byref(rk),
+                                         C.byref(sm)))
+        return {"rcond": rc.value, "rank": rk.value, "smin_ratio": sm.value}
+
     def masks(self, l: int, stream=None):
         """(M+, N+) of subdomain l as uint8 volumes."""
         n = self.n[l]
@@ -436,10 +453,11 @@ def dd_params(n1: int, h1: float, x01: float, n2: int, h2: float, x02: float, si
 
 def dd2_params(n1: int, h1: float, x01: float, origin1, n2: int, h2: float, x02: float, origin2,
                sigma: float, r_gamma: float, q_z: float, r_z: float, eps_layers: float,
-               m_gamma: int, beta: int, m_z: int) -> L.DD2Params:
+               m_gamma: int, beta: int, m_z: int, rcond: float = 0.0) -> L.DD2Params:
     return L.DD2Params(grid(n1, h1, sigma, x01), grid(n2, h2, sigma, x02),
                        (C.c_double * 3)(*origin1), (C.c_double * 3)(*origin2), float(r_gamma),
-                       float(q_z), float(r_z), float(eps_layers), int(m_gamma), int(beta), int(m_z))
+                       float(q_z), float(r_z), float(eps_layers), int(m_gamma), int(beta), int(m_z),
+                       float(rcond))
 
 
 def dd_build(params, prec: str = "fp64", device="cuda", return_A: bool = False, stream=None,

@@ -44,6 +44,7 @@ dpm_status dd_diagnostics_impl(const dpm_dd* d, const double* const state[4], do
                                void* ws, hipStream_t s);
 dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], int32_t n_rows[2],
                         int32_t* n_cols, double* rmin, double* rmax);
+dpm_status dd_lsq_info_impl(const dpm_dd* d, double* rcond, int32_t* rank, double* smin_ratio);
 dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStream_t s,
                           dpm_dd** out, double* A_out);
 dpm_status dd_rebuild_impl(dpm_dd* d, double sigma, hipStream_t s, void* scratch, size_t bytes);
@@ -99,8 +100,8 @@ dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opt
 }
 
 dpm_status dpm_autotune(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, const void* b,
-                        void* u, int32_t reps, void* stream, int32_t* widths, double* ms,
-                        int32_t* count, int32_t* best) {
+                        void* u, int32_t reps, void* stream, int32_t* widths, int32_t* sweeps,
+                        double* ms, int32_t* count, int32_t* best, int32_t* best_sweeps) {
   clear_error();
   DPM_TRY(validate_grid(grid));
   DPM_TRY(validate_opts(*grid, opts));
@@ -117,7 +118,7 @@ dpm_status dpm_autotune(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts
   const char* ub = static_cast<const char*>(u);
   if (bb < ub + bytes && ub < bb + bytes) { set_error("b and u overlap"); return DPM_EINVAL; }
   return autotune_impl(*grid, nrhs, *opts, b, u, reps, static_cast<hipStream_t>(stream), widths,
-                       ms, count, best);
+                       sweeps, ms, count, best, best_sweeps);
 }
 
 void dpm_autotune_reset(void) { autotune_reset(); }
@@ -494,6 +495,11 @@ dpm_status dpm_dd2_build(const dpm_dd2_params* params, const dpm_opts* opts, voi
     set_error("m_gamma, m_z must be >= 0 and beta 0 or 1");
     return DPM_EINVAL;
   }
+  if (!(p.rcond >= 0.0 && p.rcond < 1.0)) { set_error("rcond must be in [0, 1)"); return DPM_EINVAL; }
+  if (p.rcond > 0.0 && !svd_shape((p.beta + 1) * (p.m_gamma + 1) + 3 * (p.m_z + 1)).ok) {
+    set_error("rcond > 0 supports at most 640 columns");
+    return DPM_EINVAL;
+  }
   if ((p.beta + 1) * (p.m_gamma + 1) + 3 * (p.m_z + 1) > 1024) {
     set_error("more than 1024 columns");
     return DPM_EINVAL;
@@ -507,6 +513,12 @@ dpm_status dpm_dd_info(const dpm_dd* dd, int32_t n_gamma[2], int32_t n_gamma_in[
   clear_error();
   if (!dd) { set_error("dd is NULL"); return DPM_EINVAL; }
   return dd_info_impl(dd, n_gamma, n_gamma_in, n_rows, n_cols, min_abs_rdiag, max_abs_rdiag);
+}
+
+dpm_status dpm_dd_lsq_info(const dpm_dd* dd, double* rcond, int32_t* rank, double* smin_ratio) {
+  clear_error();
+  if (!dd) { set_error("dd is NULL"); return DPM_EINVAL; }
+  return dd_lsq_info_impl(dd, rcond, rank, smin_ratio);
 }
 
 dpm_status dpm_dd_masks(const dpm_dd* dd, int32_t l, uint8_t* m_plus, uint8_t* n_plus,

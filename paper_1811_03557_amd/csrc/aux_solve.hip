@@ -90,10 +90,15 @@ int real_bytes_of(const dpm_opts& o) {
   return (o.prec == DPM_FP64 || o.prec == DPM_FP64_GEMM) ? 8 : 4;
 }
 
-// Widths recorded by the autotuner, per (device, n, precision, I/O type, refinement on/off).
+// Widths and sweep layouts recorded by the autotuner, per (device, n, precision, I/O type,
+// refinement on/off).
 using TuneKey = std::tuple<int, int, int, int, int>;
+struct Tuned {
+  int width;
+  int sweeps;  // DPM_SWEEPS_AXIS or DPM_SWEEPS_PLANE
+};
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tuned;
+std::map<TuneKey, Tuned> g_tuned;
 
 TuneKey tune_key(int n, const dpm_opts& o) {
   int dev = 0;
@@ -101,12 +106,13 @@ TuneKey tune_key(int n, const dpm_opts& o) {
   return TuneKey(dev, n, o.prec, o.io_fp64 != 0, o.max_refine > 0);
 }
 
-int tuned_width(int n, const dpm_opts& o) {
+Tuned tuned_entry(int n, const dpm_opts& o) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  if (g_tuned.empty()) return 0;  // nothing tuned: no device query
+  if (g_tuned.empty()) return Tuned{0, DPM_SWEEPS_AUTO};  // nothing tuned: no device query
   const auto it = g_tuned.find(tune_key(n, o));
-  return it == g_tuned.end() ? 0 : it->second;
+  return it == g_tuned.end() ? Tuned{0, DPM_SWEEPS_AUTO} : it->second;
 }
+int tuned_width(int n, const dpm_opts& o) { return tuned_entry(n, o).width; }
 
 }  // namespace
 
@@ -151,6 +157,16 @@ dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o) {
     return DPM_EINVAL;
   }
   if (o->rhs_chunk < 0) { set_error("rhs_chunk must be >= 0"); return DPM_EINVAL; }
+  if (o->sweeps != DPM_SWEEPS_AUTO && o->sweeps != DPM_SWEEPS_AXIS && o->sweeps != DPM_SWEEPS_PLANE) {
+    set_error("unknown sweep layout %d", o->sweeps);
+    return DPM_EINVAL;
+  }
+  if (o->sweeps == DPM_SWEEPS_PLANE &&
+      (!(o->prec == DPM_FP64 || o->prec == DPM_FP32) || !xy_fusion_supported(g.n))) {
+    set_error("DPM_SWEEPS_PLANE needs DPM_FP64 or DPM_FP32 transforms and n in {7, 15, 31, 63, "
+              "127} (n = %d)", g.n);
+    return DPM_EINVAL;
+  }
   if (o->prec == DPM_FP64_GEMM) {
     if (!dense_size_supported(g.n) || o->max_refine != 0) {
       set_error("DPM_FP64_GEMM supports 7 <= n <= %d without refinement", kDenseMaxN);
@@ -196,14 +212,24 @@ int solve_chunk(const dpm_grid& g, int nrhs, const dpm_opts& o) {
 // bf16 matrix cores, FP64 dense products on the FP64 matrix cores.
 enum { FORM_FFT = 0, FORM_BF16X3 = 1, FORM_F64MM = 2 };
 
-// One solve (five sweeps) of nb right-hand sides.  in_kind/out_kind select the first and last
-// sweeps; vol_in/vol_out are the first sweep's source and the last sweep's destination, ws the
-// volume the middle sweeps work on.
-static dpm_status five_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind in_kind,
+// Sweep layout of a solve: the per-axis sweeps, or the fused plane sweeps where they exist
+// (FFT form, n <= 127).  DPM_SWEEPS_AUTO takes the layout the autotuner recorded for these
+// options, else the plane sweeps.
+static bool use_plane_sweeps(const dpm_grid& g, const dpm_opts& o, int form) {
+  if (form != FORM_FFT || !xy_fusion_supported(g.n)) return false;
+  if (o.sweeps != DPM_SWEEPS_AUTO) return o.sweeps == DPM_SWEEPS_PLANE;
+  return tuned_entry(g.n, o).sweeps != DPM_SWEEPS_AXIS;
+}
+
+// One solve of nb right-hand sides: five per-axis sweeps, or (plane) two fused plane sweeps
+// around the z sweep.  in_kind/out_kind select the first and last sweeps; src/dst are the
+// first sweep's source and the last sweep's destination, ws the volume the middle sweeps work
+// on.
+static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind in_kind,
                               const void* src, OutKind out_kind, void* dst, void* ws,
                               const double* b, const double* u, const SolveFlags* fl, int rhs0,
                               int nb, bool gated, int form, const double* sig_rhs,
-                              hipStream_t s) {
+                              hipStream_t s, bool plane) {
   PassArgs a{};
   a.sigma_rhs = sig_rhs;
   a.tw = rb == 4 ? (const void*)pl->tw_f : (const void*)pl->tw_d;
@@ -232,6 +258,24 @@ static dpm_status five_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind 
     if (tm) timing_after(s, kind);
     return st;
   };
+  if (plane) {
+    auto xy = [&](InKind ik, OutKind ok, const void* i, void* o, bool track, int kind) {
+      PassArgs q = a;
+      q.in = i;
+      q.out = o;
+      q.cmax = track ? fl->cmax : nullptr;
+      q.umax = track ? fl->umax : nullptr;
+      const bool tm = timing_on(rhs0, nb);
+      if (tm) timing_before(s);
+      dpm_status st = launch_xy_pass(rb, g.n, ik, ok, q, nb, s);
+      if (tm) timing_after(s, kind);
+      return st;
+    };
+    DPM_TRY(xy(in_kind, OUT_WS, src, ws, false, SW_XY_FWD));
+    DPM_TRY(pass(AX_Z, true, IN_WS, OUT_WS, ws, ws, false, false));
+    DPM_TRY(xy(IN_WS, out_kind, ws, dst, fl != nullptr, SW_XY_INV));
+    return DPM_OK;
+  }
   DPM_TRY(pass(AX_X, false, in_kind, OUT_WS, src, ws, false, true));
   DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, ws, ws, false, false));
   DPM_TRY(pass(AX_Z, true, IN_WS, OUT_WS, ws, ws, false, false));
@@ -246,6 +290,7 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
   DPM_TRY(no_alloc ? find_plan(g.n, &pl) : get_plan(g.n, &pl));
   const int rb = real_bytes_of(o);
   const int form = o.prec == DPM_BF16X3 ? FORM_BF16X3 : o.prec == DPM_FP64_GEMM ? FORM_F64MM : FORM_FFT;
+  const bool plane = use_plane_sweeps(g, o, form);
   const bool ws_needed = needs_ws(o);
   const int chunk = solve_chunk(g, nrhs, o);
   const size_t need = workspace_for_chunk(g, nrhs, o, chunk > 0 ? chunk : 1);
@@ -287,22 +332,22 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
     if ((o.prec == DPM_FP64 && !refine) || o.prec == DPM_FP64_GEMM) {
       // FP64 transforms in place in u: no workspace traffic beyond u itself
       // (no max-norm tracking: only refinement uses it)
-      DPM_TRY(five_sweeps(pl, 8, g, IN_WS, bc, OUT_F64, uc, uc, nullptr, nullptr, nullptr, c0, nb,
-                          false, form, sig_dev, s));
+      DPM_TRY(solve_sweeps(pl, 8, g, IN_WS, bc, OUT_F64, uc, uc, nullptr, nullptr, nullptr, c0, nb,
+                          false, form, sig_dev, s, plane));
     } else if (o.prec == DPM_FP32 && !o.io_fp64) {
-      DPM_TRY(five_sweeps(pl, 4, g, IN_WS, bc, OUT_WS, uc, uc, nullptr, nullptr, nullptr, c0, nb,
-                          false, form, sig_dev, s));
+      DPM_TRY(solve_sweeps(pl, 4, g, IN_WS, bc, OUT_WS, uc, uc, nullptr, nullptr, nullptr, c0, nb,
+                          false, form, sig_dev, s, plane));
     } else {
       // reduced-precision (or FP64) transforms on the workspace, FP64 iterate in u
       const double* bd = reinterpret_cast<const double*>(bc);
       double* ud = reinterpret_cast<double*>(uc);
-      DPM_TRY(five_sweeps(pl, rb, g, IN_F64, bc, OUT_F64, uc, vol_ws, nullptr, nullptr, &fl, c0,
-                          nb, false, form, sig_dev, s));
+      DPM_TRY(solve_sweeps(pl, rb, g, IN_F64, bc, OUT_F64, uc, vol_ws, nullptr, nullptr, &fl, c0,
+                          nb, false, form, sig_dev, s, plane));
       hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, 0, o.rtol);
       DPM_TRY_HIP(hipGetLastError());
       for (int k = 1; k <= o.max_refine; ++k) {
-        DPM_TRY(five_sweeps(pl, rb, g, IN_RESID, nullptr, OUT_UPD, uc, vol_ws, bd, ud, &fl, c0,
-                            nb, true, form, sig_dev, s));
+        DPM_TRY(solve_sweeps(pl, rb, g, IN_RESID, nullptr, OUT_UPD, uc, vol_ws, bd, ud, &fl, c0,
+                            nb, true, form, sig_dev, s, plane));
         hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, k, o.rtol);
         DPM_TRY_HIP(hipGetLastError());
       }
@@ -344,15 +389,18 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
 }
 
 
-// Autotuner of the launch width.  The sweep kernels' tiles are fixed at compile time; the number
-// of right-hand sides a sweep launch carries is the shape chosen at run time.  It trades the
-// launch count against how much of the batch's working set stays in the 256 MB Infinity Cache,
-// so the best width depends on the size, the precision and the chip, and is measured here.
+// Autotuner of the launch shape.  The sweep kernels' tiles are fixed at compile time; chosen at
+// run time are the number of right-hand sides a sweep launch carries and, where the fused plane
+// sweeps exist, the sweep layout (five per-axis sweeps or three with the plane in LDS).  The
+// width trades the launch count against how much of the batch's working set stays in the 256 MB
+// Infinity Cache, the layout trades HBM passes against the plane sweep's occupancy (one 160 KB
+// block per CU at n = 127 in FP64), so the best pair depends on the size, the precision and the
+// chip, and is measured here.
 const int kTuneWidths[kTuneMaxWidths] = {1, 2, 3, 4, 6, 8, 12, 16};
 
 dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const void* b, void* u,
-                         int reps, hipStream_t s, int32_t* widths, double* ms, int32_t* count,
-                         int32_t* best) {
+                         int reps, hipStream_t s, int32_t* widths, int32_t* sweeps, double* ms,
+                         int32_t* count, int32_t* best, int32_t* best_sweeps) {
   if (timing_enabled()) {
     set_error("dpm_autotune: sweep timing is enabled; end it before tuning");
     return DPM_EINVAL;
@@ -360,47 +408,58 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
   // with a transform workspace, stay at or below the default width, so that a workspace sized
   // for the default (before tuning) fits every width the tuner may record
   const int cap = needs_ws(o) ? default_chunk(g.n, 1 << 30, real_bytes_of(o), true) : (1 << 30);
-  // the recorded width (if any) stays in force until the new one replaces it: the timed solves
-  // below fix their width explicitly, and concurrent solves keep the old one meanwhile
+  // layouts to try: the caller's fixed one, else both where the plane sweeps exist
+  const int form = o.prec == DPM_BF16X3 ? FORM_BF16X3 : o.prec == DPM_FP64_GEMM ? FORM_F64MM : FORM_FFT;
+  int layouts[2] = {DPM_SWEEPS_AXIS, DPM_SWEEPS_PLANE};
+  int nl = 1;
+  if (o.sweeps != DPM_SWEEPS_AUTO) layouts[0] = o.sweeps;
+  else if (form == FORM_FFT && xy_fusion_supported(g.n)) nl = 2;
+  // the recorded pair (if any) stays in force until the new one replaces it: the timed solves
+  // below fix their width and layout explicitly, and concurrent solves keep the old one meanwhile
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
     set_error("dpm_autotune: event creation failed");
     return DPM_EHIP;
   }
-  int n_out = 0, w_best = 0;
+  int n_out = 0, w_best = 0, l_best = DPM_SWEEPS_AXIS;
   double t_best = 0.0;
   dpm_status st = DPM_OK;
-  for (int w : kTuneWidths) {
-    if (w > nrhs || w > cap) continue;
-    dpm_opts ow = o;
-    ow.rhs_chunk = w;
-    if (workspace_for_chunk(g, nrhs, ow, w) > o.workspace_bytes) continue;
-    st = aux_solve_impl(g, nrhs, b, u, ow, s, nullptr);  // untimed: first-touch and caches
-    if (st != DPM_OK) break;
-    double t = 0.0;
-    for (int r = 0; r < reps && st == DPM_OK; ++r) {
-      hipError_t e = hipEventRecord(e0, s);
-      if (e == hipSuccess) st = aux_solve_impl(g, nrhs, b, u, ow, s, nullptr);
+  for (int li = 0; li < nl && st == DPM_OK; ++li) {
+    for (int w : kTuneWidths) {
+      if (w > nrhs || w > cap) continue;
+      dpm_opts ow = o;
+      ow.rhs_chunk = w;
+      ow.sweeps = layouts[li];
+      if (workspace_for_chunk(g, nrhs, ow, w) > o.workspace_bytes) continue;
+      st = aux_solve_impl(g, nrhs, b, u, ow, s, nullptr);  // untimed: first-touch and caches
       if (st != DPM_OK) break;
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float el = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
-      if (e != hipSuccess) {
-        set_error("dpm_autotune: %s", hipGetErrorString(e));
-        st = DPM_EHIP;
-        break;
+      double t = 0.0;
+      for (int r = 0; r < reps && st == DPM_OK; ++r) {
+        hipError_t e = hipEventRecord(e0, s);
+        if (e == hipSuccess) st = aux_solve_impl(g, nrhs, b, u, ow, s, nullptr);
+        if (st != DPM_OK) break;
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float el = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
+        if (e != hipSuccess) {
+          set_error("dpm_autotune: %s", hipGetErrorString(e));
+          st = DPM_EHIP;
+          break;
+        }
+        if (r == 0 || el < t) t = el;
       }
-      if (r == 0 || el < t) t = el;
-    }
-    if (st != DPM_OK) break;
-    if (widths) widths[n_out] = w;
-    if (ms) ms[n_out] = t;
-    ++n_out;
-    if (w_best == 0 || t < t_best) {  // ties keep the narrower width
-      w_best = w;
-      t_best = t;
+      if (st != DPM_OK) break;
+      if (widths) widths[n_out] = w;
+      if (sweeps) sweeps[n_out] = layouts[li];
+      if (ms) ms[n_out] = t;
+      ++n_out;
+      if (w_best == 0 || t < t_best) {  // ties keep the earlier candidate (narrower, per-axis)
+        w_best = w;
+        l_best = layouts[li];
+        t_best = t;
+      }
     }
   }
   (void)hipEventDestroy(e0);
@@ -412,10 +471,11 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
   }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[tune_key(g.n, o)] = w_best;
+    g_tuned[tune_key(g.n, o)] = Tuned{w_best, l_best};
   }
   if (count) *count = n_out;
   if (best) *best = w_best;
+  if (best_sweeps) *best_sweeps = l_best;
   return DPM_OK;
 }
 

@@ -64,9 +64,25 @@ size_t rebuild_scratch_bytes(const dpm_bep* b);
 // Columns of b->A at b->grid.sigma; enqueue only (no allocation, no synchronisation).
 dpm_status bep_columns(dpm_bep* b, hipStream_t s, void* scratch, size_t bytes);
 // Householder QR of A (m x n column-major, in place), P = R^-1 Q1^T (n x m) and the device pair
-// rd2 = (min, max) |R_ii|; enqueue only.
+// rd2 = (min, max) |R_ii|; enqueue only.  rcond > 0: P = R+ Q1^T with R+ the pseudo-inverse of R
+// truncated at rcond (singular values <= rcond s_max dropped: the minimum-norm least-squares
+// operator), and rd2[2], rd2[3] = numerical rank and smallest kept s / s_max (rd2 holds 4 values).
 dpm_status lsq_factor(double* A, int m, int n, double* tau, double* P, hipStream_t s,
-                      void* scratch, size_t bytes, double* rd2);
+                      void* scratch, size_t bytes, double* rd2, double rcond = 0.0);
+
+// One-sided Jacobi SVD of the n x n triangle R of a factored A and its truncated pseudo-inverse
+// Rp (n x n row-major), with W, V (np x np column-major), inv (n) and flags (2) as scratch
+// (lsq_svd.hip).  The column count is padded to np, a multiple of 2 bs.
+struct SvdShape {
+  int bs, np, nb;
+  bool ok;
+};
+SvdShape svd_shape(int n);
+dpm_status pinv_of_r(const double* A, int m, int n, double rcond, double* Rp, double* W,
+                     double* V, double* inv, unsigned long long* flags, double* rd,
+                     hipStream_t s);
+// K = Rp Wy for general (not triangular) n x n Rp.
+void kmat_full(const double* Rp, const double* Wy, int n, double* K, hipStream_t s);
 // Columns, QR and P of a single-domain handle, enqueue only (rd2 as above).
 dpm_status factor_bep_enqueue(dpm_bep* b, hipStream_t s, double* A_out, void* scratch,
                               size_t bytes, double* rd2);

@@ -552,19 +552,26 @@ ColLayout col_layout(const dpm_grid& g, const dpm_opts& o, int n_basis) {
 }
 
 struct FacLayout {
-  size_t rd, G, T, W, K, Rinv, Gp, total;
+  size_t rd, G, T, W, K, Rinv, Gp, Ws, Vs, inv, flg, total;
 };
 FacLayout fac_layout(int m, int n) {
   const size_t nn = sizeof(double) * (size_t)n * n;
+  const SvdShape sh = svd_shape(n);
+  const size_t npp = sizeof(double) * (size_t)sh.np * sh.np;
   FacLayout L{};
   size_t at = 0;
-  L.rd = at; at = align_up(at + 2 * sizeof(double), 256);
+  L.rd = at; at = align_up(at + 4 * sizeof(double), 256);
   L.G = at; at = align_up(at + nn, 256);
   L.T = at; at = align_up(at + nn, 256);
   L.W = at; at = align_up(at + nn, 256);
   L.K = at; at = align_up(at + nn, 256);
   L.Rinv = at; at = align_up(at + nn, 256);
   L.Gp = at; at = align_up(at + nn * (size_t)gram_chunks(m, n), 256);
+  // truncated least squares (rcond > 0): the Jacobi SVD's W, V, inverse squares and flags
+  L.Ws = at; at = align_up(at + npp, 256);
+  L.Vs = at; at = align_up(at + npp, 256);
+  L.inv = at; at = align_up(at + sizeof(double) * (size_t)n, 256);
+  L.flg = at; at = align_up(at + 2 * sizeof(unsigned long long), 256);
   L.total = at;
   return L;
 }
@@ -629,7 +636,7 @@ dpm_status bep_columns(dpm_bep* b, hipStream_t s, void* scratch, size_t bytes) {
 // pair rd2, with temporaries from `scratch` (factor_scratch_bytes).  Enqueue only: the caller
 // reads rd2 back for the rank test.
 dpm_status lsq_factor(double* A, int m, int n_basis, double* tau, double* P, hipStream_t s,
-                      void* scratch, size_t bytes, double* rd2) {
+                      void* scratch, size_t bytes, double* rd2, double rcond) {
   const int nin = m;
   const FacLayout L = fac_layout(m, n_basis);
   if (scratch == nullptr || bytes < L.total) {
@@ -657,9 +664,17 @@ dpm_status lsq_factor(double* A, int m, int n_basis, double* tau, double* P, hip
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((nn + 3) / 4)), dim3(256), 0, s, Gp,
                      nchunk, n_basis, G);
   hipLaunchKernelGGL(k_tinv, dim3(n_basis), dim3(256), 0, s, G, tau, n_basis, T);
-  hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, A, nin, n_basis, Rinv);
   hipLaunchKernelGGL(k_v1tt, dim3(grid1((long long)nn)), dim3(kB), 0, s, A, nin, n_basis, T, W);
-  hipLaunchKernelGGL(k_kmat, dim3(grid1((long long)nn)), dim3(kB), 0, s, Rinv, W, n_basis, K);
+  if (rcond > 0.0) {
+    // truncated pseudo-inverse of R in place of R^-1 (a general, not triangular, matrix)
+    DPM_TRY(pinv_of_r(A, nin, n_basis, rcond, Rinv, reinterpret_cast<double*>(base + L.Ws),
+                      reinterpret_cast<double*>(base + L.Vs), reinterpret_cast<double*>(base + L.inv),
+                      reinterpret_cast<unsigned long long*>(base + L.flg), rd2, s));
+    kmat_full(Rinv, W, n_basis, K, s);
+  } else {
+    hipLaunchKernelGGL(k_rinv, dim3(n_basis), dim3(256), 0, s, A, nin, n_basis, Rinv);
+    hipLaunchKernelGGL(k_kmat, dim3(grid1((long long)nn)), dim3(kB), 0, s, Rinv, W, n_basis, K);
+  }
   hipLaunchKernelGGL(k_form_p, dim3(grid1(nin), (n_basis + PT - 1) / PT), dim3(kB),
                      sizeof(double) * PT * n_basis, s, Rinv, K, A, nin, n_basis, P);
   DPM_TRY_HIP(hipGetLastError());

@@ -91,6 +91,13 @@ struct PassArgs {
 dpm_status launch_dst_pass(int real_bytes, int n, AxisKind ax, bool zpass, InKind in,
                            OutKind out, const PassArgs& a, int nrhs, hipStream_t s);
 
+// Fused plane sweep (both in-plane transforms of each z-plane, plane in LDS) over `nrhs`
+// consecutive volumes; n = 7, 15, 31, 63, 127.  The forward pass (input kinds) writes the
+// spectral planes transposed, the inverse pass (output kinds) reads them so.
+bool xy_fusion_supported(int n);
+dpm_status launch_xy_pass(int real_bytes, int n, InKind in, OutKind out, const PassArgs& a,
+                          int nrhs, hipStream_t s);
+
 // ---------------------------------------------------------------- BF16x3 MFMA dense DST
 dpm_status launch_bf16x3_pass(int n, AxisKind ax, bool zpass, InKind in, OutKind out,
                               const PassArgs& a, const Plan* plan, int nrhs, hipStream_t s);
@@ -102,7 +109,7 @@ dpm_status launch_f64mm_pass(int n, AxisKind ax, bool zpass, const PassArgs& a, 
 // ---------------------------------------------------------------- measurement support
 // Sweep kinds reported by dpm_timing_end.
 enum SweepKind { SW_X_FIRST = 0, SW_Y = 1, SW_Z = 2, SW_X_LAST = 3, SW_X_RESID = 4, SW_X_UPD = 5,
-                 SW_KINDS = 6 };
+                 SW_XY_FWD = 6, SW_XY_INV = 7, SW_KINDS = 8 };
 bool timing_enabled();
 bool timing_on(int rhs0, int nb);
 void timing_before(hipStream_t s);
@@ -134,11 +141,13 @@ int rhs_chunk_of(const dpm_grid& g, int nrhs, const dpm_opts& o);
 dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes);
 // Workspace bytes of a solve of nrhs right-hand sides at `chunk` right-hand sides per launch.
 size_t workspace_for_chunk(const dpm_grid& g, int nrhs, const dpm_opts& o, int chunk);
-// Launch-width autotuner (see dpm_autotune): candidate widths, timing, the recorded widths.
+// Launch-shape autotuner (see dpm_autotune): candidate widths x sweep layouts, timing, the
+// recorded pairs.
 constexpr int kTuneMaxWidths = 8;
+constexpr int kTuneMaxCands = 2 * kTuneMaxWidths;
 dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const void* b, void* u,
-                         int reps, hipStream_t s, int32_t* widths, double* ms, int32_t* count,
-                         int32_t* best);
+                         int reps, hipStream_t s, int32_t* widths, int32_t* sweeps, double* ms,
+                         int32_t* count, int32_t* best, int32_t* best_sweeps);
 void autotune_reset();
 dpm_status validate_grid(const dpm_grid* g);
 dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o);

@@ -36,6 +36,11 @@ struct dpm_dd {
   double* tau = nullptr;  // n_cols
   double* P = nullptr;    // n_cols x rows least-squares operator (row nu contiguous)
   double rdiag_min = 0.0, rdiag_max = 0.0;
+  // least squares of the coupled BEPs: rcond 0 plain, > 0 truncated minimum norm; the numerical
+  // rank and smallest kept singular value ratio of the last factorisation
+  double rcond = 0.0;
+  int rank = 0;
+  double smin_ratio = 0.0;
   int kind = 1;                       // 1: Z inside Omega; 2: Z meets Gamma
   int c_off[2] = {0, 0};              // first coefficient of each subdomain's densities
   int m_rows[2] = {0, 0};             // reduced-BEP rows of each subdomain
@@ -390,7 +395,27 @@ dpm_status dd_stack_factor(dpm_dd* d, hipStream_t s, double* A_out, void* scratc
   }
   DPM_TRY_HIP(hipGetLastError());
   if (A_out) DPM_TRY_HIP(hipMemcpyAsync(A_out, d->A, sizeof(double) * na, hipMemcpyDeviceToDevice, s));
-  return lsq_factor(d->A, d->rows, d->n_cols, d->tau, d->P, s, scratch, bytes, rd2);
+  return lsq_factor(d->A, d->rows, d->n_cols, d->tau, d->P, s, scratch, bytes, rd2, d->rcond);
+}
+
+// Result of a factorisation read back from rd[0..3]: (min, max) |R_ii|, and with truncation the
+// numerical rank and smallest kept singular value ratio.  Plain least squares needs full column
+// rank (rank_check); the truncated one has no such condition.
+dpm_status dd_rank_result(dpm_dd* d, const double* rd) {
+  d->rdiag_min = rd[0];
+  d->rdiag_max = rd[1];
+  if (d->rcond > 0.0) {
+    d->rank = (int)rd[2];
+    d->smin_ratio = rd[3];
+    if (!(d->rank > 0)) {
+      set_error("truncated least squares kept no singular value (rank %d)", d->rank);
+      return DPM_ERANK;
+    }
+    return DPM_OK;
+  }
+  d->rank = d->n_cols;
+  d->smin_ratio = 0.0;
+  return rank_check(rd[0], rd[1]);
 }
 
 // Scratch of a rebuild: the subdomains' column builds run one after the other, then the stacked
@@ -420,12 +445,10 @@ dpm_status dd_factor(dpm_dd* d, hipStream_t s, double* A_out, void* scratch, siz
   }
   double* rd2 = reinterpret_cast<double*>(static_cast<char*>(scratch) + (bytes - 256) / 256 * 256);
   DPM_TRY(dd_factor_enqueue(d, s, A_out, scratch, bytes - 256, rd2));
-  double h2[2] = {0.0, 0.0};
-  DPM_TRY_HIP(hipMemcpyAsync(h2, rd2, sizeof(h2), hipMemcpyDeviceToHost, s));
+  double h4[4] = {0.0, 0.0, 0.0, 0.0};
+  DPM_TRY_HIP(hipMemcpyAsync(h4, rd2, sizeof(h4), hipMemcpyDeviceToHost, s));
   DPM_TRY_HIP(hipStreamSynchronize(s));
-  d->rdiag_min = h2[0];
-  d->rdiag_max = h2[1];
-  return rank_check(h2[0], h2[1]);
+  return dd_rank_result(d, h4);
 }
 
 // The build's stacking and factorisation (Step 2 creates the handle; the subdomains' columns are
@@ -438,7 +461,7 @@ dpm_status dd_stack_factor_alloc(dpm_dd* d, hipStream_t s, double* A_out) {
     return DPM_ENOMEM;
   }
   double* rd2 = reinterpret_cast<double*>(static_cast<char*>(scratch) + fb);
-  double h2[2] = {0.0, 0.0};
+  double h2[4] = {0.0, 0.0, 0.0, 0.0};
   dpm_status st = dd_stack_factor(d, s, A_out, scratch, fb, rd2);
   hipError_t e = hipSuccess;
   if (st == DPM_OK) e = hipMemcpyAsync(h2, rd2, sizeof(h2), hipMemcpyDeviceToHost, s);
@@ -450,9 +473,7 @@ dpm_status dd_stack_factor_alloc(dpm_dd* d, hipStream_t s, double* A_out) {
     st = DPM_EHIP;
   }
   if (st != DPM_OK) return st;
-  d->rdiag_min = h2[0];
-  d->rdiag_max = h2[1];
-  return rank_check(h2[0], h2[1]);
+  return dd_rank_result(d, h2);
 }
 
 dpm_status dd_build_impl(const dpm_dd_params& prm, const dpm_opts& o, hipStream_t s,
@@ -549,6 +570,7 @@ dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStrea
                           dpm_dd** out, double* A_out) {
   dpm_dd* d = new dpm_dd();
   d->kind = 2;
+  d->rcond = prm.rcond;
   d->n_gamma_cols = (prm.beta + 1) * (prm.m_gamma + 1);
   d->n_z_cols = 3 * (prm.m_z + 1);
   d->n_cols = d->n_gamma_cols + d->n_z_cols;
@@ -713,6 +735,13 @@ double dd_sigma(const dpm_dd* d) { return d->prm.grid1.sigma; }
 const dpm_bep* dd_sub(const dpm_dd* d, int l) { return d->sub[l]; }
 const double* dd_origin(const dpm_dd* d, int l) { return d->origin[l]; }
 
+dpm_status dd_lsq_info_impl(const dpm_dd* d, double* rcond, int32_t* rank, double* smin_ratio) {
+  if (rcond) *rcond = d->rcond;
+  if (rank) *rank = d->rank;
+  if (smin_ratio) *smin_ratio = d->smin_ratio;
+  return DPM_OK;
+}
+
 dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], int32_t n_rows[2],
                         int32_t* n_cols, double* rmin, double* rmax) {
   for (int l = 0; l < 2; ++l) {
@@ -820,8 +849,9 @@ dpm_status dd_run_impl(dpm_dd* d, const dpm_run_params& p, double* const state[4
               reb_off + reb_bytes);
     return DPM_EINVAL;
   }
-  // scan[0..3]: both subdomains' scanned maxima; scan[4..5]: (min, max) |R_ii| of the last
-  // rebuild, read back with the next scan (a rebuild adds no synchronisation of its own)
+  // scan[0..3]: both subdomains' scanned maxima; scan[4..7]: (min, max) |R_ii|, rank and
+  // smallest kept singular value ratio of the last rebuild, read back with the next scan (a
+  // rebuild adds no synchronisation of its own)
   double* scan = reinterpret_cast<double*>(static_cast<char*>(o.workspace) + scan_off);
   void* rscratch = static_cast<char*>(o.workspace) + reb_off;
   dpm_run_info r{};
@@ -831,7 +861,7 @@ dpm_status dd_run_impl(dpm_dd* d, const dpm_run_params& p, double* const state[4
   const double* in[4] = {state[0], state[1], state[2], state[3]};
   bool rank_pending = false;
   for (;;) {
-    double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double w[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const bool more = t < p.t_final && r.steps < p.max_steps;
     if (more)
       for (int l = 0; l < 2; ++l)
@@ -842,9 +872,7 @@ dpm_status dd_run_impl(dpm_dd* d, const dpm_run_params& p, double* const state[4
     }
     if (rank_pending) {
       rank_pending = false;
-      d->rdiag_min = w[4];
-      d->rdiag_max = w[5];
-      DPM_TRY(rank_check(w[4], w[5]));
+      DPM_TRY(dd_rank_result(d, w + 4));
     }
     if (t >= p.t_final) { r.stop = DPM_RUN_TFINAL; break; }
     if (r.steps >= p.max_steps) { r.stop = DPM_RUN_MAXSTEPS; break; }

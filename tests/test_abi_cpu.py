@@ -58,6 +58,16 @@ def test_host_validation_without_device():
     g36 = _lib.Grid(36, 3.0 / 37, 1.0, 0.0)
     assert lib.dpm_workspace_size(C.byref(g36), 1, C.byref(o), C.byref(nb)) == _lib.DPM_EINVAL
     assert "DPM_FP64_GEMM" in lib.dpm_last_error().decode()
+    # sweep layouts: the plane sweeps exist for FFT-form FP64/FP32 at n <= 127 only
+    g127 = _lib.Grid(127, 3.0 / 128, 1.0, 0.0)
+    op = _lib.Opts(_lib.DPM_FP64, 1, 1e-10, 0, 0, None, 0, _lib.DPM_SWEEPS_PLANE)
+    assert lib.dpm_workspace_size(C.byref(g127), 1, C.byref(op), C.byref(nb)) == _lib.DPM_OK
+    assert lib.dpm_workspace_size(C.byref(g), 1, C.byref(op), C.byref(nb)) == _lib.DPM_EINVAL
+    assert "DPM_SWEEPS_PLANE" in lib.dpm_last_error().decode()
+    ob = _lib.Opts(_lib.DPM_BF16X3, 1, 1e-10, 2, 0, None, 0, _lib.DPM_SWEEPS_PLANE)
+    assert lib.dpm_workspace_size(C.byref(g127), 1, C.byref(ob), C.byref(nb)) == _lib.DPM_EINVAL
+    ox = _lib.Opts(_lib.DPM_FP64, 1, 1e-10, 0, 0, None, 0, 7)
+    assert lib.dpm_workspace_size(C.byref(g127), 1, C.byref(ox), C.byref(nb)) == _lib.DPM_EINVAL
     og = _lib.Opts(_lib.DPM_FP64_GEMM, 1, 1e-10, 0, 0, None, 0)
     assert lib.dpm_workspace_size(C.byref(g36), 1, C.byref(og), C.byref(nb)) == _lib.DPM_OK
     g600 = _lib.Grid(600, 3.0 / 601, 1.0, 0.0)
@@ -122,6 +132,7 @@ def test_dd_validation_without_device():
     assert lib.dpm_dd_masks(None, 0, fake, fake, None) == _lib.DPM_EINVAL
     assert lib.dpm_dd_gauss_state(None, 0, 1.0, 1.0, (C.c_double * 3)(0, 0, 0), fake, None) == _lib.DPM_EINVAL
     assert lib.dpm_dd_info(None, None, None, None, None, None, None) == _lib.DPM_EINVAL
+    assert lib.dpm_dd_lsq_info(None, None, None, None) == _lib.DPM_EINVAL
     # Case 2: Z must meet Gamma
     g1b = _lib.Grid(15, 0.09375, 1000.0, -0.75 + 0.09375)
 
@@ -134,7 +145,9 @@ def test_dd_validation_without_device():
         return lib.dpm_dd2_build(C.byref(prm), C.byref(o), None, C.byref(out), None)
 
     for kw, word in [({"q_z": 2.0}, "meets"), ({"q_z": 0.3}, "meets"), ({"eps_layers": 0.0}, "eps"),
-                     ({"beta": 3}, "beta"), ({"origin1": (C.c_double * 3)(0, float("nan"), 0)}, "origins")]:
+                     ({"beta": 3}, "beta"), ({"origin1": (C.c_double * 3)(0, float("nan"), 0)}, "origins"),
+                     ({"rcond": -1e-7}, "rcond"), ({"rcond": 1.0}, "rcond"),
+                     ({"rcond": 1e-7, "m_gamma": 700}, "640 columns")]:
         assert build2(**kw) == _lib.DPM_EINVAL, kw
         assert word in lib.dpm_last_error().decode(), (kw, lib.dpm_last_error())
     prm = _lib.RunParams(1.0, 1.0, float("inf"), 10)
@@ -171,9 +184,9 @@ def test_autotune_validation_without_device():
     o = _lib.Opts(_lib.DPM_FP64, 1, 1e-10, 0, 0, None, 0)
     w = C.c_int32(0)
     assert lib.dpm_rhs_chunk(C.byref(g), 64, C.byref(o), C.byref(w)) == _lib.DPM_OK and w.value == 2
-    widths, ms = (C.c_int32 * 8)(), (C.c_double * 8)()
-    cnt, best = C.c_int32(0), C.c_int32(0)
-    args = (widths, ms, C.byref(cnt), C.byref(best))
+    widths, lays, ms = (C.c_int32 * 16)(), (C.c_int32 * 16)(), (C.c_double * 16)()
+    cnt, best, bl = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    args = (widths, lays, ms, C.byref(cnt), C.byref(best), C.byref(bl))
     for nrhs, reps in ((0, 3), (4, 0), (4, 101)):
         assert lib.dpm_autotune(C.byref(g), nrhs, C.byref(o), None, None, reps, None, *args) == _lib.DPM_EINVAL
         assert lib.dpm_last_error()

@@ -1,5 +1,6 @@
-"""The launch-width autotuner (dpm_autotune) through the C ABI: it times every candidate width
-that fits, records the fastest, and later solves with rhs_chunk = 0 take it.  A solve's result
+"""The launch-shape autotuner (dpm_autotune) through the C ABI: it times every candidate width
+that fits, in both sweep layouts where the plane sweeps exist, records the fastest pair, and
+later solves with rhs_chunk = 0 (sweeps = auto) take it.  A solve's result
 does not depend on the width (each right-hand side's arithmetic is the same), so solves at the
 tuned width are compared bit for bit with width-1 solves, and against the oracle at the FP64 (1e-12)
 and refined (1e-10) tolerances."""
@@ -28,18 +29,25 @@ def test_autotune_records_fastest_width(prec, max_refine, tol):
     try:
         default = api.rhs_chunk(api.grid(n, h, sigma), nrhs, api.opts(prec, True, 1e-10, max_refine))
         res = api.autotune(bt, sigma, h, prec=prec, max_refine=max_refine, reps=2)
-        say(f"  widths {res['widths']}, ms {[round(t, 3) for t in res['ms']]}, best {res['best']} "
-            f"(default {default})")
-        # every candidate up to nrhs (the default width at this size is far above 8)
-        assert res["widths"] == [1, 2, 3, 4, 6, 8]
+        say(f"  widths {res['widths']}, layouts {res['sweeps']}, ms {[round(t, 3) for t in res['ms']]}, "
+            f"best {res['best']} {res['best_sweeps']} (default {default})")
+        # every candidate width up to nrhs (the default width at this size is far above 8), in
+        # both sweep layouts (the plane sweeps exist at 63)
+        assert res["widths"] == [1, 2, 3, 4, 6, 8] * 2
+        assert res["sweeps"] == ["axis"] * 6 + ["plane"] * 6
         assert all(np.isfinite(t) and t > 0 for t in res["ms"])
-        assert res["best"] == res["widths"][int(np.argmin(res["ms"]))]
+        k = int(np.argmin(res["ms"]))
+        assert res["best"] == res["widths"][k] and res["best_sweeps"] == res["sweeps"][k]
+        # solves that leave the layout to the library take the recorded one
+        u_fixed = api.aux_solve_batched(bt, sigma, h, prec=prec, max_refine=max_refine,
+                                        sweeps=res["best_sweeps"]).cpu().numpy()
         o = api.opts(prec, True, 1e-10, max_refine)
         assert api.rhs_chunk(api.grid(n, h, sigma), nrhs, o) == res["best"]
         u_auto = api.aux_solve_batched(bt, sigma, h, prec=prec, max_refine=max_refine).cpu().numpy()
         u_one = api.aux_solve_batched(bt, sigma, h, prec=prec, max_refine=max_refine,
                                       rhs_chunk=1).cpu().numpy()
         assert np.array_equal(u_auto, u_one)
+        assert np.array_equal(u_auto, u_fixed)
         ref = oaux.aux_solve(b[:2], sigma, h)
         err = max(oaux.rel_err_inf(u_auto[i], ref[i]) for i in range(2))
         say(f"  rel err vs oracle {err:.2e}")

@@ -216,6 +216,62 @@ def test_batch_chunks_and_ragged_count():
     assert _max_rel(us[0], ref) < TOL["refined"]
 
 
+@pytest.mark.parametrize("n", [7, 15, 31, 63, 127])
+@pytest.mark.parametrize("prec,kw,tol", [
+    ("fp64", {}, 1e-12),
+    ("fp64", {"max_refine": 2, "rtol": 1e-14}, 1e-12),
+    ("fp32", {"max_refine": 4, "rtol": 1e-10}, 1e-10),
+])
+def test_plane_and_axis_sweeps(n, prec, kw, tol):
+    """The fused plane sweeps (both in-plane transforms of a z-plane in one pass, three sweeps
+    per solve) and the five per-axis sweeps each meet the oracle on a ragged batch of 3 at two
+    shifts, and agree with each other to the same bar."""
+    dev = need_gpu()
+    h, _ = inp.grid(n)
+    for sigma in (1.0, 1e4):
+        say(f"plane vs axis n={n} {prec} {kw} sigma={sigma:g}")
+        b = inp.rhs_normal(n, 3, seed=n + 17)
+        ref = oaux.aux_solve(b, sigma, h)
+        up = _solve(b, sigma, h, dev, prec=prec, sweeps="plane", rhs_chunk=2, **kw)
+        ua = _solve(b, sigma, h, dev, prec=prec, sweeps="axis", rhs_chunk=2, **kw)
+        ep, ea = _max_rel(up, ref), _max_rel(ua, ref)
+        say(f"  rel err plane {ep:.2e}, axis {ea:.2e}")
+        assert ep < tol and ea < tol
+        assert _max_rel(up, ua) < tol
+
+
+@pytest.mark.parametrize("n", [31, 127])
+def test_plane_sweeps_fp32_io(n):
+    """FP32 input and output through the plane sweeps: the FP32 bar (1e-5) against the
+    oracle."""
+    dev = need_gpu()
+    h, _ = inp.grid(n)
+    b = inp.rhs_normal(n, 2, seed=n + 3)
+    ref = oaux.aux_solve(b, 1.0, h)
+    u = _solve(b.astype(np.float32), 1.0, h, dev, prec="fp32", sweeps="plane")
+    assert _max_rel(u.astype(np.float64), ref) < TOL["fp32"]
+
+
+def test_plane_sweeps_sine_modes_127():
+    """Closed form through the plane sweeps: b = s_k1 x s_k2 x s_k3 (the DST-I eigenvectors) gives
+    u = b / (sigma + lambda_k1 + lambda_k2 + lambda_k3), with k1 != k2 so that a transposed
+    spectral plane read the wrong way round would show."""
+    dev = need_gpu()
+    n = 127
+    h, _ = inp.grid(n)
+    j = np.arange(1, n + 1)
+    sigma = 3.0
+    bs, refs = [], []
+    for (k1, k2, k3) in [(1, 2, 3), (127, 5, 64), (40, 90, 1)]:
+        s = [np.sin(np.pi * ((j * k) % (2 * (n + 1))) / (n + 1)) for k in (k1, k2, k3)]
+        bm = s[2][:, None, None] * s[1][None, :, None] * s[0][None, None, :]
+        lam = sum(4.0 / h**2 * np.sin(np.pi * k / (2 * (n + 1))) ** 2 for k in (k1, k2, k3))
+        bs.append(bm)
+        refs.append(bm / (sigma + lam))
+    u = _solve(np.stack(bs), sigma, h, dev, prec="fp64", sweeps="plane")
+    assert _max_rel(u, np.stack(refs)) < TOL["fp64"]
+
+
 def test_invalid_arguments_raise():
     import torch
     from paper_1811_03557_amd import api, _lib

@@ -162,7 +162,7 @@ def _params2(case, sigma):
     s1, s2 = case.sub
     return api.dd2_params(case.n1, s1["h"], s1["x0"], (0.0, 0.0, s1["zc"]), case.n2, s2["h"],
                           s2["x0"], (0.0, 0.0, 0.0), sigma, 1.0, case.q_z, case.r_z, 2.0,
-                          case.m_gamma, case.beta, case.m_z)
+                          case.m_gamma, case.beta, case.m_z, case.rcond or 0.0)
 
 
 def _data2(mesh, ps):
@@ -598,4 +598,45 @@ def test_dd_full_size_matches_oracle(case_no):
         e = np.max(np.abs(g.cpu().numpy() - o)) / np.max(np.abs(o))
         say(f"  step output {k}: rel err {e:.2e}")
         assert e <= tol_step, (k, e)
+    dd.close()
+
+
+# Truncated minimum-norm least squares (rcond > 0): the paper's 20 harmonics per term on Z.
+# The coupled matrix is numerically rank deficient (its singular values fall smoothly to 1e-19
+# of the largest); rcond sits in a gap of each configuration's spectrum (31/31: 3.4e-7 -> 4.1e-8;
+# 127/63: 7.7e-7 -> 1.0e-7), so both sides keep the same singular triplets.  The kept part has
+# condition up to 1/rcond, which amplifies rounding (1e-16) to about 1e-16/rcond: steps compared
+# at 1e-8 (31/31) and 1e-7 (127/63).
+TRUNC = [(31, 31, 19, 19, 1e-7, 1e-8), (127, 63, 149, 19, 3e-7, 1e-7)]
+
+
+@pytest.mark.parametrize("n1,n2,mg,mz,rcond,tol", TRUNC)
+def test_dd2_truncated_least_squares_matches_oracle(n1, n2, mg, mz, rcond, tol):
+    """Case 2 with 20 harmonics per term on Z and the truncated least squares: the numerical
+    rank and the smallest kept singular value of the GPU's Jacobi SVD of R agree with LAPACK's SVD
+    of the stacked matrix, and one step of Test B-like data matches the oracle's step with the
+    same rcond (gelsd)."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case = odd.DDCase2(n1, 0.75, 0.75, n2, 1.0, 0.5, mg, mz, beta=0, rcond=rcond)
+    s1, s2 = case.sub
+    dt, chi = 0.5 * s1["h"] ** 2, 1.0
+    say(f"dd2 truncated least squares n1={n1} n2={n2} mg={mg} mz={mz} rcond={rcond:g}")
+    A = odd.dd2_matrix(case, 1.0 / dt)
+    sv = np.linalg.svd(A, compute_uv=False)
+    rank = int(np.sum(sv > rcond * sv[0]))
+    dd = api.dd_build(_params2(case, 1.0 / dt), device=dev)
+    info = dd.lsq_info()
+    say(f"  rank {info['rank']} (LAPACK {rank} of {A.shape[1]}), smallest kept "
+        f"{info['smin_ratio']:.3e} (LAPACK {sv[rank - 1] / sv[0]:.3e})")
+    assert info["rcond"] == rcond and info["rank"] == rank
+    assert abs(info["smin_ratio"] / (sv[rank - 1] / sv[0]) - 1.0) < 1e-6
+    st = list(_data2(s1["mesh"], s1["ps"])) + list(_data2(s2["mesh"], s2["ps"]))
+    ref = odd.dd2_step(*st, case, A, dt, chi)[:4]
+    out = api.dd_step(dd, dt, chi, [torch.from_numpy(v).to(dev) for v in st])
+    for k, (g, o) in enumerate(zip(out, ref)):
+        err = np.max(np.abs(g.cpu().numpy() - o)) / np.max(np.abs(o))
+        say(f"  output {k}: rel err {err:.2e}")
+        assert err <= tol, (k, err)
     dd.close()
