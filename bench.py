@@ -24,7 +24,8 @@ loop from the paper's Test B data with 150 zonal harmonics at 127^3.
 Domain decomposition (the "domain_decomposition" object): Case 1 on the Test A setup, the
 ball on a 127^3 mesh and the shell on a 63^3 mesh, against the single domain at 255^3 with the
 same fine spacing: build and per-step times and their ratio.  The "domain_decomposition_case2"
-object: Case 2 (Z meets Gamma) on the Test B setup at 127/63 (150 harmonics on Gamma, 6 on Z),
+object: Case 2 (Z meets Gamma) on the Test B setup at 127/63 (150 harmonics on Gamma, the paper's 20
+per term on Z with the truncated least squares, and 6 with the plain one),
 against the single domain at 255^3.
 
 Prints one JSON line on stdout (everything else goes to stderr).
@@ -49,8 +50,8 @@ KIND_NAMES = ["x_first", "y", "z_fused", "x_last", "x_residual", "x_update"]
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dst_sweeps_fp64_aux255_64rhs_hbm_traffic.txt")
-KERNEL_SOURCES = ["paper_1811_03557_amd/csrc/dst_fft.hip", "paper_1811_03557_amd/csrc/common.h",
-                  "paper_1811_03557_amd/csrc/aux_solve.hip"]
+KERNEL_SOURCES = ["paper_1811_03557_amd/csrc/dst_fft.hip", "paper_1811_03557_amd/csrc/dst_line.h",
+                  "paper_1811_03557_amd/csrc/common.h"]
 
 
 def counted_traffic(kind, path_name, n, rhs_per_launch):
@@ -371,52 +372,75 @@ def run_dd2(args, dev):
     cap of the unit ball within 0.5 of the north pole (Z: the sphere of radius 0.5 about (0, 0, 1))
     on a fine mesh (N1 = 127 on [-0.75, 0.75]^2 x [0, 1.5], h1 = 3/256) and the rest on a coarse
     one (N2 = 63 on [-1.5, 1.5]^3, h2 = 4 h1); the paper's 150 zonal harmonics for mesh 127/63
-    with the 2-term extension on Gamma and 6 with the 3-term extension on Z (168 columns; more
-    on Z make the coupled least squares ill-posed, as Legendre polynomials of higher degree are
-    nearly dependent on the arc of Z inside the ball, psi <= psi* = 75.5 degrees: 20 fail the
-    rank test, 10 pass it but leave the solution solver-dependent at 1e-2), parts with a
-    tolerance of 2 mesh widths; Test B data, dt = 0.5 h1^2 (c0 = 0: no
-    CFL bound at the start).  Against the single domain at N = 255 with the same 150 harmonics:
-    Step 2 wall time and the per-step time (eager steps, FP64)."""
+    with the 2-term extension on Gamma, and on Z the paper's 20 per term of the 3-term extension
+    (210 columns), solved by the truncated minimum-norm least squares at rcond = 3e-7 (the coupled
+    matrix is numerically rank deficient; rcond sits in a gap of its spectrum), beside 6 per term
+    with the plain least squares; parts with a tolerance of 2 mesh widths; Test B data,
+    dt = 0.5 h1^2 (c0 = 0: no CFL bound at the start).  Against the single domain at N = 255 with
+    the same 150 harmonics: Step 2 wall time, the per-step time (eager steps, FP64) and the
+    relative change of the mass sum(rho) h^3 over the fixed window of timed steps."""
     import torch
     from paper_1811_03557_amd import api
     n1, n2 = 127, 63
     h1, h2 = 1.5 / (n1 + 1), 3.0 / (n2 + 1)
     dt = 0.5 * h1 * h1
-    prm = api.dd2_params(n1, h1, -0.75 + h1, (0.0, 0.0, 0.75), n2, h2, -1.5 + h2, (0.0, 0.0, 0.0),
-                         1.0 / dt, 1.0, 1.0, 0.5, 2.0, 149, 0, 5)
-    api.dd_build(prm, device=dev).close()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    dd = api.dd_build(prm, device=dev)
-    torch.cuda.synchronize()
-    build_dd = time.perf_counter() - t
-    state = []
-    for l in (0, 1):
-        state += [dd.gauss_state(l, 2000.0, 100.0, (0.0, 0.0, 0.25)),
-                  torch.zeros((dd.n[l],) * 3, dtype=torch.float64, device=dev)]
-    ws = torch.empty(dd.workspace_size(api.opts("fp64")), dtype=torch.uint8, device=dev)
     steps = args.dd_steps
-    for _ in range(2):
-        api.dd_step(dd, dt, 1.0, state, out=state, workspace=ws)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(steps):
-        api.dd_step(dd, dt, 1.0, state, out=state, workspace=ws)
-    torch.cuda.synchronize()
-    t_dd = (time.perf_counter() - t) / steps
-    finite = all(bool(torch.isfinite(v).all()) for v in state)
     out = {"workload": "Test B data; cap |x - (0,0,1)| < 0.5 of the unit ball at N1 = 127 "
                        "(h1 = 3/256) + the rest at N2 = 63 (h2 = 3/64); 150 zonal harmonics "
-                       "(2-term) on Gamma, 6 (3-term) on Z; dt = 0.5 h1^2; single domain at "
-                       "N = 255 with 150 harmonics for comparison",
-           "dd2_127_63": {"columns": dd.n_cols, "rows": sum(dd.n_rows),
-                          "build_s": round(build_dd, 4), "ms_per_step": round(t_dd * 1e3, 3),
-                          "steps_per_s": round(1.0 / t_dd, 1), "finite": finite,
-                          "rdiag_min_over_max": float(f"{dd.rdiag[0] / dd.rdiag[1]:.3e}")}}
-    log(f"[bench] DD2 127/63: build {build_dd * 1e3:.1f} ms, {t_dd * 1e3:.3f} ms/step")
-    dd.close()
-    del state, ws
+                       "(2-term) on Gamma; on Z 20 (3-term, truncated least squares, rcond "
+                       "3e-7) or 6 (plain); dt = 0.5 h1^2; single domain at N = 255 with 150 "
+                       "harmonics for comparison",
+           "window_steps": steps}
+
+    def run(m_z, rcond):
+        prm = api.dd2_params(n1, h1, -0.75 + h1, (0.0, 0.0, 0.75), n2, h2, -1.5 + h2,
+                             (0.0, 0.0, 0.0), 1.0 / dt, 1.0, 1.0, 0.5, 2.0, 149, 0, m_z, rcond)
+        api.dd_build(prm, device=dev).close()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        dd = api.dd_build(prm, device=dev)
+        torch.cuda.synchronize()
+        build = time.perf_counter() - t
+        state = []
+        for l in (0, 1):
+            state += [dd.gauss_state(l, 2000.0, 100.0, (0.0, 0.0, 0.25)),
+                      torch.zeros((dd.n[l],) * 3, dtype=torch.float64, device=dev)]
+        mplus = [dd.masks(l)[0].to(torch.float64) for l in (0, 1)]
+        hh = (h1, h2)
+
+        def mass():
+            return sum(float((state[2 * l] * mplus[l]).sum()) * hh[l] ** 3 for l in (0, 1))
+
+        ws = torch.empty(dd.workspace_size(api.opts("fp64")), dtype=torch.uint8, device=dev)
+        m0 = mass()
+        for _ in range(2):
+            api.dd_step(dd, dt, 1.0, state, out=state, workspace=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            api.dd_step(dd, dt, 1.0, state, out=state, workspace=ws)
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t) / steps
+        m1 = mass()
+        li = dd.lsq_info()
+        res = {"m_z": m_z, "rcond": rcond, "columns": dd.n_cols, "rows": sum(dd.n_rows),
+               "rank": li["rank"], "build_s": round(build, 4),
+               "ms_per_step": round(t_step * 1e3, 3), "steps_per_s": round(1.0 / t_step, 1),
+               "finite": all(bool(torch.isfinite(v).all()) for v in state),
+               "mass_change_rel": float(f"{(m1 - m0) / m0:.3e}"),
+               "rho_min": float(f"{min(float(state[0].min()), float(state[2].min())):.3e}")}
+        if rcond > 0:
+            res["smallest_kept_sigma_over_max"] = float(f"{li['smin_ratio']:.3e}")
+        else:
+            res["rdiag_min_over_max"] = float(f"{dd.rdiag[0] / dd.rdiag[1]:.3e}")
+        log(f"[bench] DD2 127/63 m_z={m_z} rcond={rcond:g}: build {build * 1e3:.1f} ms, "
+            f"{t_step * 1e3:.3f} ms/step, rank {li['rank']}/{dd.n_cols}, mass change "
+            f"{res['mass_change_rel']:.2e} over {steps + 2} steps")
+        dd.close()
+        return res
+
+    out["dd2_127_63"] = run(19, 3e-7)
+    out["dd2_127_63_six_on_z"] = run(5, 0.0)
     n = 255
     h = 3.0 / (n + 1)
     x0 = -1.5 + h
@@ -432,6 +456,8 @@ def run_dd2(args, dev):
     build_sd = time.perf_counter() - t
     rho = api.gauss_state(bep, geo, 2000.0, 100.0, center=(0.0, 0.0, 0.25))
     c = torch.zeros_like(rho)
+    mp = m.to(torch.float64)
+    m0 = float((rho * mp).sum()) * h ** 3
     ws = torch.empty(api.step_workspace_size(bep, api.opts("fp64")), dtype=torch.uint8, device=dev)
     for _ in range(2):
         api.dpm_step(bep, dt, 1.0, rho, c, rho, c, workspace=ws)
@@ -441,13 +467,17 @@ def run_dd2(args, dev):
         api.dpm_step(bep, dt, 1.0, rho, c, rho, c, workspace=ws)
     torch.cuda.synchronize()
     t_sd = (time.perf_counter() - t) / steps
+    m1 = float((rho * mp).sum()) * h ** 3
     out["sd_255"] = {"columns": bep.n_basis, "rows": bep.n_gamma_in, "build_s": round(build_sd, 4),
                      "ms_per_step": round(t_sd * 1e3, 3), "steps_per_s": round(1.0 / t_sd, 1),
-                     "finite": bool(torch.isfinite(rho).all() and torch.isfinite(c).all())}
+                     "finite": bool(torch.isfinite(rho).all() and torch.isfinite(c).all()),
+                     "mass_change_rel": float(f"{(m1 - m0) / m0:.3e}")}
     out["dt"] = dt
+    t_dd = out["dd2_127_63"]["ms_per_step"] * 1e-3
     out["R_S_per_step"] = round(t_sd / t_dd, 2)
-    out["R_S_build"] = round(build_sd / build_dd, 2)
-    log(f"[bench] SD 255 (150 harmonics): build {build_sd * 1e3:.1f} ms, {t_sd * 1e3:.3f} ms/step")
+    out["R_S_build"] = round(build_sd / out["dd2_127_63"]["build_s"], 2)
+    log(f"[bench] SD 255 (150 harmonics): build {build_sd * 1e3:.1f} ms, {t_sd * 1e3:.3f} ms/step, "
+        f"mass change {out['sd_255']['mass_change_rel']:.2e}")
     bep.close()
     return out
 

@@ -70,9 +70,10 @@ const char* dpm_last_error(void) { return last_error_text(); }
 
 dpm_status dpm_prepare(int32_t n) {
   clear_error();
-  if (!fft_size_supported(n) && !dense_size_supported(n)) {
-    set_error("n = %d: no transform for this size (n + 1 a power of two up to 1023, or "
-              "7 <= n <= %d for DPM_FP64_GEMM)", n, kDenseMaxN);
+  if (!fft_size_supported(n) && !dense_size_supported(n) && !blue_size_supported(n)) {
+    set_error("n = %d: no transform for this size (n + 1 a power of two up to 1023, "
+              "7 <= n <= %d for DPM_FP64, 7 <= n <= %d for DPM_FP64_GEMM)", n, kBlueMaxN,
+              kDenseMaxN);
     return DPM_EINVAL;
   }
   const Plan* p = nullptr;

@@ -173,9 +173,18 @@ dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o) {
       return DPM_EINVAL;
     }
   } else if (!fft_size_supported(g.n)) {
-    set_error("n = %d: the FFT-form and split-bf16 transforms need n + 1 a power of two "
-              "(DPM_FP64_GEMM takes any 7 <= n <= %d)", g.n, kDenseMaxN);
-    return DPM_EINVAL;
+    // n + 1 not a power of two: the FP64 FFT form runs Bluestein's sweeps (plain solve)
+    if (o->prec == DPM_FP64 && blue_size_supported(g.n)) {
+      if (o->max_refine != 0) {
+        set_error("n = %d (n + 1 not a power of two): DPM_FP64 runs without refinement", g.n);
+        return DPM_EINVAL;
+      }
+    } else {
+      set_error("n = %d: the FP32 and split-bf16 transforms need n + 1 a power of two; DPM_FP64 "
+                "takes any 7 <= n <= %d (Bluestein), DPM_FP64_GEMM any 7 <= n <= %d", g.n,
+                kBlueMaxN, kDenseMaxN);
+      return DPM_EINVAL;
+    }
   }
   if (o->prec == DPM_BF16X3 && g.n > 255) { set_error("DPM_BF16X3 supports n <= 255"); return DPM_EINVAL; }
   return DPM_OK;
@@ -210,7 +219,13 @@ int solve_chunk(const dpm_grid& g, int nrhs, const dpm_opts& o) {
 
 // Transform forms of the sweeps: real FFT (dst_fft.hip), split-bf16 dense products on the
 // bf16 matrix cores, FP64 dense products on the FP64 matrix cores.
-enum { FORM_FFT = 0, FORM_BF16X3 = 1, FORM_F64MM = 2 };
+enum { FORM_FFT = 0, FORM_BF16X3 = 1, FORM_F64MM = 2, FORM_BLUE = 3 };
+
+int form_of(const dpm_grid& g, const dpm_opts& o) {
+  if (o.prec == DPM_BF16X3) return FORM_BF16X3;
+  if (o.prec == DPM_FP64_GEMM) return FORM_F64MM;
+  return fft_size_supported(g.n) ? FORM_FFT : FORM_BLUE;
+}
 
 // Sweep layout of a solve: the per-axis sweeps, or the fused plane sweeps where they exist
 // (FFT form, n <= 127).  DPM_SWEEPS_AUTO takes the layout the autotuner recorded for these
@@ -252,7 +267,8 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
                    : first ? SW_X_FIRST : SW_X_LAST;
     const bool tm = timing_on(rhs0, nb);
     if (tm) timing_before(s);
-    dpm_status st = form == FORM_BF16X3 ? launch_bf16x3_pass(g.n, ax, z, ik, ok, q, pl, nb, s)
+    dpm_status st = form == FORM_BLUE ? launch_blue_pass(g.n, ax, z, q, pl, nb, s)
+                  : form == FORM_BF16X3 ? launch_bf16x3_pass(g.n, ax, z, ik, ok, q, pl, nb, s)
                   : form == FORM_F64MM  ? launch_f64mm_pass(g.n, ax, z, q, pl, nb, s)
                                         : launch_dst_pass(rb, g.n, ax, z, ik, ok, q, nb, s);
     if (tm) timing_after(s, kind);
@@ -289,7 +305,7 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
   const Plan* pl = nullptr;
   DPM_TRY(no_alloc ? find_plan(g.n, &pl) : get_plan(g.n, &pl));
   const int rb = real_bytes_of(o);
-  const int form = o.prec == DPM_BF16X3 ? FORM_BF16X3 : o.prec == DPM_FP64_GEMM ? FORM_F64MM : FORM_FFT;
+  const int form = form_of(g, o);
   const bool plane = use_plane_sweeps(g, o, form);
   const bool ws_needed = needs_ws(o);
   const int chunk = solve_chunk(g, nrhs, o);
@@ -409,7 +425,7 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
   // for the default (before tuning) fits every width the tuner may record
   const int cap = needs_ws(o) ? default_chunk(g.n, 1 << 30, real_bytes_of(o), true) : (1 << 30);
   // layouts to try: the caller's fixed one, else both where the plane sweeps exist
-  const int form = o.prec == DPM_BF16X3 ? FORM_BF16X3 : o.prec == DPM_FP64_GEMM ? FORM_F64MM : FORM_FFT;
+  const int form = form_of(g, o);
   int layouts[2] = {DPM_SWEEPS_AXIS, DPM_SWEEPS_PLANE};
   int nl = 1;
   if (o.sweeps != DPM_SWEEPS_AUTO) layouts[0] = o.sweeps;

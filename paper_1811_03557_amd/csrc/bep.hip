@@ -571,7 +571,7 @@ FacLayout fac_layout(int m, int n) {
   L.Ws = at; at = align_up(at + npp, 256);
   L.Vs = at; at = align_up(at + npp, 256);
   L.inv = at; at = align_up(at + sizeof(double) * (size_t)n, 256);
-  L.flg = at; at = align_up(at + 2 * sizeof(unsigned long long), 256);
+  L.flg = at; at = align_up(at + 3 * sizeof(unsigned long long), 256);
   L.total = at;
   return L;
 }

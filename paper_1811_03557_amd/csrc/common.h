@@ -52,6 +52,13 @@ struct Plan {
   int mpad = 0;
   // the same matrix in FP64 for the FP64 matrix-core path (n <= kDenseMaxN, else null)
   double* s_d = nullptr;
+  // Bluestein tables (n + 1 not a power of two, FP64 FFT form): FFT length L = 2^blue_logl >= 3n,
+  // twiddles e^{-2 pi i e/L} (L complex), chirp w_j = e^{i pi j^2/(2(n+1))} (j <= n + 1,
+  // complex), the chirp filter's transform FFT_L(c) / L (L complex); 0 / null otherwise
+  int blue_logl = 0;
+  double* blue_tw = nullptr;
+  double* blue_w = nullptr;
+  double* blue_ch = nullptr;
 };
 
 // Returns the plan of the current device for size n (creating it on first use).
@@ -61,6 +68,11 @@ dpm_status get_plan(int n, const Plan** out);
 dpm_status find_plan(int n, const Plan** out);
 
 bool fft_size_supported(int n);  // n + 1 a power of two and 7 <= n <= 1023
+// Bluestein sizes (FP64 FFT form for n + 1 not a power of two): 7 <= n <= kBlueMaxN (L = 2048
+// at most, L >= 3n); blue_logl(n) = log2 L, or 0 when n is beyond the range.
+constexpr int kBlueMaxN = 682;
+int blue_logl(int n);
+bool blue_size_supported(int n);
 // Sizes of the dense (GEMM-form) FP64 sweeps: any 7 <= n <= kDenseMaxN (matrix padded to a
 // multiple of 32, at most 544)
 constexpr int kDenseMaxN = 543;
@@ -97,6 +109,10 @@ dpm_status launch_dst_pass(int real_bytes, int n, AxisKind ax, bool zpass, InKin
 bool xy_fusion_supported(int n);
 dpm_status launch_xy_pass(int real_bytes, int n, InKind in, OutKind out, const PassArgs& a,
                           int nrhs, hipStream_t s);
+
+// Bluestein DST-I sweep (FP64, n + 1 not a power of two; plain solve kinds only).
+dpm_status launch_blue_pass(int n, AxisKind ax, bool zpass, const PassArgs& a, const Plan* pl,
+                            int nrhs, hipStream_t s);
 
 // ---------------------------------------------------------------- BF16x3 MFMA dense DST
 dpm_status launch_bf16x3_pass(int n, AxisKind ax, bool zpass, InKind in, OutKind out,

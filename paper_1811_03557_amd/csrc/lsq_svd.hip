@@ -24,10 +24,35 @@ namespace {
 constexpr int kST = 256;           // threads of a pair-sweep workgroup
 constexpr double kRotTol = 1e-15;  // rotate a pair whose cosine exceeds this
 constexpr double kConvTol = 1e-14; // a sweep whose largest cosine is below this ends the SVD
-constexpr int kMaxSweeps = 24;
+constexpr int kMaxSweeps = 32;
 
 // flags[0]: largest pair cosine of the running sweep (bit pattern of a non-negative double),
-// flags[1]: converged (set once, read by every later launch).
+// flags[1]: converged (set once, read by every later launch), flags[2]: squared norm below which
+// a column is negligible (bit pattern): rcond^2 ||R||_F^2 / (100 n) <= (rcond s_max / 10)^2, so
+// such a column stays below the truncation; a pair of two negligible columns is neither rotated
+// nor counted for convergence (their mutual angle does not enter the truncated pseudo-inverse).
+__global__ __launch_bounds__(1024) void k_svd_neg(const double* __restrict__ A, int m, int n,
+                                                  double rcond,
+                                                  unsigned long long* __restrict__ flags) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (long long e = threadIdx.x; e < (long long)n * n; e += 1024) {
+    const int c = (int)(e / n), r = (int)(e - (long long)c * n);
+    if (r <= c) {
+      const double v = A[(long long)c * m + r];
+      s += v * v;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    flags[2] = (unsigned long long)__double_as_longlong(rcond * rcond * t / (100.0 * n));
+  }
+}
+
 __global__ void k_svd_init(const double* __restrict__ A, int m, int n, int np,
                            double* __restrict__ W, double* __restrict__ V,
                            unsigned long long* __restrict__ flags) {
@@ -62,6 +87,7 @@ __global__ __launch_bounds__(kST) void k_svd_round(double* __restrict__ W, doubl
                                                    unsigned long long* __restrict__ flags) {
   __shared__ double sm[kSvdLds];
   if (flags[1] != 0ull) return;   // converged in an earlier sweep: uniform exit
+  const double neg2 = __longlong_as_double((long long)flags[2]);
   constexpr int C2 = 2 * BS;      // columns held
   constexpr int TPP = kST / BS;   // threads per column pair
   double* wl = sm;
@@ -96,7 +122,7 @@ __global__ __launch_bounds__(kST) void k_svd_round(double* __restrict__ W, doubl
       be += __shfl_xor(be, off, TPP);
       ga += __shfl_xor(ga, off, TPP);
     }
-    if (al > 0.0 && be > 0.0) {
+    if (al > 0.0 && be > 0.0 && fmax(al, be) >= neg2) {
       const double cosv = fabs(ga) / sqrt(al * be);
       cmax = fmax(cmax, cosv);
       if (cosv > kRotTol) {
@@ -239,6 +265,7 @@ dpm_status pinv_of_r(const double* A, int m, int n, double rcond, double* Rp, do
   const long long nn = (long long)sh.np * sh.np;
   hipLaunchKernelGGL(k_svd_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, m, n,
                      sh.np, W, V, flags);
+  hipLaunchKernelGGL(k_svd_neg, dim3(1), dim3(1024), 0, s, A, m, n, rcond, flags);
   for (int sw = 0; sw < kMaxSweeps; ++sw) {
     for (int r = 0; r < sh.nb - 1; ++r) {
       if (sh.bs == 16)

@@ -52,6 +52,58 @@ bool fft_size_supported(int n) {
 
 bool dense_size_supported(int n) { return n >= 7 && n <= kDenseMaxN; }
 
+// Bluestein tables of the DST-I of length n (M = n + 1): the chirp w_j = e^{i pi j^2/(2M)} with
+// the phase reduced exactly (j^2 mod 4M), the filter c_d = conj(w_|d|) at d mod L for
+// 1 - n <= d <= 2M - 2, its DFT divided by L (direct sum in long double), and the FFT twiddles.
+static dpm_status build_blue(int n, Plan* p) {
+  const int lg = blue_logl(n);
+  const int L = 1 << lg, M = n + 1;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  auto chirp = [&](long long d) {  // e^{i pi d^2 / (2M)}
+    const long long r = (d * d) % (4LL * M);
+    const long double a = pi * (long double)r / (2.0L * (long double)M);
+    return std::make_pair(std::cos(a), std::sin(a));
+  };
+  std::vector<double> tw(2 * (size_t)L), w(2 * (size_t)(M + 1)), ch(2 * (size_t)L);
+  std::vector<long double> cr(L, 0.0L), ci(L, 0.0L), tr(L), ti(L);
+  for (int e = 0; e < L; ++e) {
+    const long double a = -2.0L * pi * (long double)e / (long double)L;
+    tr[e] = std::cos(a);
+    ti[e] = std::sin(a);
+    tw[2 * e] = (double)tr[e];
+    tw[2 * e + 1] = (double)ti[e];
+  }
+  for (int j = 0; j <= M; ++j) {
+    const auto c = chirp(j);
+    w[2 * j] = (double)c.first;
+    w[2 * j + 1] = (double)c.second;
+  }
+  for (long long d = 1 - n; d <= 2LL * M - 2; ++d) {
+    const auto c = chirp(d < 0 ? -d : d);
+    const int pos = (int)(((d % L) + L) % L);
+    cr[pos] = c.first;
+    ci[pos] = -c.second;  // conj
+  }
+  for (int k = 0; k < L; ++k) {
+    long double sr = 0.0L, si = 0.0L;
+    for (int q = 0; q < L; ++q) {
+      const int e = (int)(((long long)q * k) % L);
+      sr += cr[q] * tr[e] - ci[q] * ti[e];
+      si += cr[q] * ti[e] + ci[q] * tr[e];
+    }
+    ch[2 * k] = (double)(sr / (long double)L);
+    ch[2 * k + 1] = (double)(si / (long double)L);
+  }
+  p->blue_logl = lg;
+  DPM_TRY_HIP(hipMalloc(&p->blue_tw, sizeof(double) * tw.size()));
+  DPM_TRY_HIP(hipMalloc(&p->blue_w, sizeof(double) * w.size()));
+  DPM_TRY_HIP(hipMalloc(&p->blue_ch, sizeof(double) * ch.size()));
+  DPM_TRY_HIP(hipMemcpy(p->blue_tw, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice));
+  DPM_TRY_HIP(hipMemcpy(p->blue_w, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice));
+  DPM_TRY_HIP(hipMemcpy(p->blue_ch, ch.data(), sizeof(double) * ch.size(), hipMemcpyHostToDevice));
+  return DPM_OK;
+}
+
 static dpm_status build_plan(int n, Plan* p) {
   p->n = n;
   const int M = n + 1;
@@ -112,6 +164,7 @@ static dpm_status build_plan(int n, Plan* p) {
     DPM_TRY_HIP(hipMalloc(&p->s_d, sizeof(double) * sd.size()));
     DPM_TRY_HIP(hipMemcpy(p->s_d, sd.data(), sizeof(double) * sd.size(), hipMemcpyHostToDevice));
   }
+  if (blue_size_supported(n)) DPM_TRY(build_blue(n, p));
   return DPM_OK;
 }
 
@@ -134,6 +187,9 @@ dpm_status get_plan(int n, const Plan** out) {
     (void)hipFree(p->s_hi);
     (void)hipFree(p->s_lo);
     (void)hipFree(p->s_d);
+    (void)hipFree(p->blue_tw);
+    (void)hipFree(p->blue_w);
+    (void)hipFree(p->blue_ch);
     delete p;
     return st;
   }

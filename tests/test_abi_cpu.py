@@ -54,10 +54,18 @@ def test_host_validation_without_device():
     o3 = _lib.Opts(_lib.DPM_FP32, 1, 1e-10, 2, 1, None, 0)
     assert lib.dpm_workspace_size(C.byref(g), 4, C.byref(o3), C.byref(nb)) == _lib.DPM_OK
     assert nb.value >= 255**3 * 4
-    # N + 1 not a power of two: only the dense FP64 form takes it (N = 36, a mesh of the paper)
+    # N + 1 not a power of two (N = 36, a mesh of the paper): FP64 takes it (Bluestein's sweeps,
+    # without refinement), FP32 does not and names the forms that do
     g36 = _lib.Grid(36, 3.0 / 37, 1.0, 0.0)
-    assert lib.dpm_workspace_size(C.byref(g36), 1, C.byref(o), C.byref(nb)) == _lib.DPM_EINVAL
-    assert "DPM_FP64_GEMM" in lib.dpm_last_error().decode()
+    assert lib.dpm_workspace_size(C.byref(g36), 1, C.byref(o), C.byref(nb)) == _lib.DPM_OK
+    o36r = _lib.Opts(_lib.DPM_FP64, 1, 1e-10, 2, 0, None, 0)
+    assert lib.dpm_workspace_size(C.byref(g36), 1, C.byref(o36r), C.byref(nb)) == _lib.DPM_EINVAL
+    o36f = _lib.Opts(_lib.DPM_FP32, 1, 1e-10, 2, 0, None, 0)
+    assert lib.dpm_workspace_size(C.byref(g36), 1, C.byref(o36f), C.byref(nb)) == _lib.DPM_EINVAL
+    msg = lib.dpm_last_error().decode()
+    assert "DPM_FP64_GEMM" in msg and "Bluestein" in msg
+    g700 = _lib.Grid(700, 3.0 / 701, 1.0, 0.0)  # beyond both the Bluestein and the dense sizes
+    assert lib.dpm_workspace_size(C.byref(g700), 1, C.byref(o), C.byref(nb)) == _lib.DPM_EINVAL
     # sweep layouts: the plane sweeps exist for FFT-form FP64/FP32 at n <= 127 only
     g127 = _lib.Grid(127, 3.0 / 128, 1.0, 0.0)
     op = _lib.Opts(_lib.DPM_FP64, 1, 1e-10, 0, 0, None, 0, _lib.DPM_SWEEPS_PLANE)
@@ -122,7 +130,7 @@ def test_dd_validation_without_device():
                      ({"r_z": 0.0}, "radii"), ({"beta": 2}, "beta"), ({"m_z": -1}, "m_gamma"),
                      ({"m_gamma": 600}, "columns"),
                      ({"grid2": _lib.Grid(31, 0.09375, 999.0, -1.5 + 0.09375)}, "sigma"),
-                     ({"grid1": _lib.Grid(36, 0.09375, 1000.0, -0.75)}, "n + 1")]:
+                     ({"grid1": _lib.Grid(700, 0.09375, 1000.0, -0.75)}, "n + 1")]:
         assert build(**kw) == _lib.DPM_EINVAL, kw
         assert word in lib.dpm_last_error().decode(), (kw, lib.dpm_last_error())
     assert out.value is None

@@ -366,8 +366,59 @@ def test_fp64_gemm_rejects_refinement_and_large_n():
         api.aux_solve_batched(b, 1.0, 3.0 / 601, prec="fp64_gemm")
     assert "n <= 543" in str(e.value)
     del b
-    # the FFT form needs N + 1 a power of two, and says where to go otherwise
+    # the FP32 FFT form needs N + 1 a power of two, and says where to go otherwise
     b = torch.zeros((1, 36, 36, 36), dtype=torch.float64, device=dev)
     with pytest.raises(_lib.DPMError) as e:
-        api.aux_solve_batched(b, 1.0, 3.0 / 37, prec="fp64")
-    assert "DPM_FP64_GEMM" in str(e.value)
+        api.aux_solve_batched(b, 1.0, 3.0 / 37, prec="fp32", max_refine=2)
+    assert "DPM_FP64_GEMM" in str(e.value) and "Bluestein" in str(e.value)
+
+
+# Bluestein's sweeps: the FP64 FFT form for N + 1 not a power of two.  36, 68, 132, 260 and 516
+# are meshes of the paper's tables; 9, 100 and 341 (the longest line at L = 1024) and 342 (the
+# shortest at L = 2048) cover the table sizes' edges.
+@pytest.mark.parametrize("n", [9, 36, 68, 100, 132, 260, 341, 342, 516])
+def test_bluestein_parity(n):
+    """Random right-hand sides against the oracle's dense DST-I at the FP64 bar (1e-12), at two
+    shifts; a ragged batch of 3 at n <= 132."""
+    dev = need_gpu()
+    say(f"bluestein parity n={n}")
+    h, _ = inp.grid(n)
+    nrhs = 3 if n <= 132 else 1
+    b = inp.rhs_normal(n, nrhs, seed=n + 7)
+    for sigma in (1.0, 1e4):
+        ref = oaux.aux_solve(b, sigma, h)
+        u = _solve(b, sigma, h, dev, prec="fp64")
+        err = _max_rel(u, ref)
+        say(f"  sigma {sigma:g}: rel err {err:.2e}")
+        assert err < TOL["fp64"]
+
+
+@pytest.mark.parametrize("n", [36, 260, 516])
+def test_bluestein_sine_modes(n):
+    """Closed form through Bluestein's sweeps: b = s_k1 x s_k2 x s_k3 gives
+    u = b / (sigma + lambda_k1 + lambda_k2 + lambda_k3), with the highest and middle modes."""
+    dev = need_gpu()
+    h, _ = inp.grid(n)
+    j = np.arange(1, n + 1)
+    sigma = 2.0
+    bs, refs = [], []
+    for (k1, k2, k3) in [(1, 2, 3), (n, (n + 1) // 2, 7)]:
+        s = [np.sin(np.pi * ((j * k) % (2 * (n + 1))) / (n + 1)) for k in (k1, k2, k3)]
+        bm = s[2][:, None, None] * s[1][None, :, None] * s[0][None, None, :]
+        lam = sum(4.0 / h**2 * np.sin(np.pi * k / (2 * (n + 1))) ** 2 for k in (k1, k2, k3))
+        bs.append(bm)
+        refs.append(bm / (sigma + lam))
+    u = _solve(np.stack(bs), sigma, h, dev, prec="fp64")
+    assert _max_rel(u, np.stack(refs)) < TOL["fp64"]
+
+
+def test_bluestein_agrees_with_dense_form():
+    """The two FP64 forms for N + 1 not a power of two, Bluestein's FFT sweeps and the dense
+    products on the FP64 matrix cores, agree to the FP64 bar at N = 260."""
+    dev = need_gpu()
+    n = 260
+    h, _ = inp.grid(n)
+    b = inp.rhs_normal(n, 2, seed=3)
+    u1 = _solve(b, 1.0, h, dev, prec="fp64")
+    u2 = _solve(b, 1.0, h, dev, prec="fp64_gemm")
+    assert _max_rel(u1, u2) < TOL["fp64"]
