@@ -77,9 +77,9 @@ int main(void) {
   if (!(err <= 1e-12 * mx)) return 1;
 
   /* ---- 2. argument checks: nothing is launched, the error text names the problem */
-  dpm_grid bad = {30, h, sigma, x0};
+  dpm_grid bad = {700, h, sigma, x0};  /* beyond every transform's sizes: rejected before launch */
   if (aux_solve(&bad, db, du, &o, NULL, NULL) != DPM_EINVAL) return 1;
-  printf("n = 30 rejected: %s\n", dpm_last_error());
+  printf("n = 700 rejected: %s\n", dpm_last_error());
   dpm_grid negs = {n, h, -1.0, x0};
   if (aux_solve(&negs, db, du, &o, NULL, NULL) != DPM_EINVAL) return 1;
 
