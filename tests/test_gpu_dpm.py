@@ -119,12 +119,13 @@ def test_boundary_matrix_config2(prec, max_refine, tol):
     bep.close()
 
 
-@pytest.mark.parametrize("n,shape,lmax", [(31, "ellipsoid", 3), (127, "sphere", 10),
-                                            (255, "sphere", 2)])
+@pytest.mark.parametrize("n,shape,lmax", [(31, "ellipsoid", 3), (63, "sphere", 7),
+                                            (127, "sphere", 10), (255, "sphere", 2)])
 def test_least_squares_against_lapack(n, shape, lmax):
     """The device QR and least-squares operator against LAPACK on the same matrix A.  The QR
     keeps up to 20 rows per thread in registers and streams the rest: |gamma_in| = 702 at
-    31^3 (ellipsoid), 18,690 at 127^3 (242 columns) and 75,434 at 255^3 (streamed rows)."""
+    31^3 (ellipsoid), 18,690 at 127^3 (242 columns) and 75,434 at 255^3 (streamed rows);
+    63^3 with 128 columns (l <= 7) in between."""
     import torch
     from paper_1811_03557_amd import api
     dev = need_gpu()
