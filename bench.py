@@ -46,12 +46,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "aux solves/s at 255³ FP32 vs FP64 @1e-10 rel; p50/p99 latency; % HBM peak"
 HBM_PEAK_GBS = 8000.0
-KIND_NAMES = ["x_first", "y", "z_fused", "x_last", "x_residual", "x_update"]
+KIND_NAMES = ["x_first", "y", "z", "x_last", "x_residual", "x_update"]
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dst_sweeps_fp64_aux255_64rhs_hbm_traffic.txt")
 KERNEL_SOURCES = ["paper_1811_03557_amd/csrc/dst_fft.hip", "paper_1811_03557_amd/csrc/dst_line.h",
-                  "paper_1811_03557_amd/csrc/common.h"]
+                  "paper_1811_03557_amd/csrc/common.h", "paper_1811_03557_amd/csrc/z_tri.hip"]
 
 
 def counted_traffic(kind, path_name, n, rhs_per_launch):
@@ -705,7 +705,7 @@ def main():
                 # product (MP = 256, the padded matrix), one product per x/y sweep line, two per
                 # z line
                 mp = (n + 31) // 32 * 32
-                fl = {k: chunk * n * n * 2 * mp * mp * (2 if k == "z_fused" else 1) for k in kern}
+                fl = {k: chunk * n * n * 2 * mp * mp * (2 if k == "z" else 1) for k in kern}
                 res[name]["mfma"] = {
                     k: {"tflops": round(fl[k] / (kern[k]["mean_ms"] * 1e-3) / 1e12, 1),
                         "frac_of_fp64_peak": round(fl[k] / (kern[k]["mean_ms"] * 1e-3) / 78.6e12, 3)}

@@ -267,7 +267,12 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
                    : first ? SW_X_FIRST : SW_X_LAST;
     const bool tm = timing_on(rhs0, nb);
     if (tm) timing_before(s);
-    dpm_status st = form == FORM_BLUE ? launch_blue_pass(g.n, ax, z, q, pl, nb, s)
+    // FFT and Bluestein forms: the z pass is the tridiagonal solve in the (kx, ky) basis; the
+    // four unnormalised in-plane transforms carry (sqrt(2/M)/2)^4 = 1/(4 M^2)
+    const double m1 = g.n + 1.0;
+    dpm_status st = z && (form == FORM_FFT || form == FORM_BLUE)
+                      ? launch_z_tri(form == FORM_BLUE ? 8 : rb, g.n, q, 1.0 / (a.inv_h2 * 4.0 * m1 * m1), nb, s)
+                  : form == FORM_BLUE ? launch_blue_pass(g.n, ax, z, q, pl, nb, s)
                   : form == FORM_BF16X3 ? launch_bf16x3_pass(g.n, ax, z, ik, ok, q, pl, nb, s)
                   : form == FORM_F64MM  ? launch_f64mm_pass(g.n, ax, z, q, pl, nb, s)
                                         : launch_dst_pass(rb, g.n, ax, z, ik, ok, q, nb, s);

@@ -110,6 +110,13 @@ bool xy_fusion_supported(int n);
 dpm_status launch_xy_pass(int real_bytes, int n, InKind in, OutKind out, const PassArgs& a,
                           int nrhs, hipStream_t s);
 
+// Middle pass of the FFT-form solves: the tridiagonal solve along z of every spectral column
+// (kx, ky), in place on the volume the forward x and y sweeps left (either plane order).
+// fscale multiplies the input: h^2 times the normalisation of the four in-plane transforms.
+bool z_tri_supported(int n);  // 1 <= n <= 1024
+dpm_status launch_z_tri(int real_bytes, int n, const PassArgs& a, double fscale, int nrhs,
+                        hipStream_t s);
+
 // Bluestein DST-I sweep (FP64, n + 1 not a power of two; plain solve kinds only).
 dpm_status launch_blue_pass(int n, AxisKind ax, bool zpass, const PassArgs& a, const Plan* pl,
                             int nrhs, hipStream_t s);

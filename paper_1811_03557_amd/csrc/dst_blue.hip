@@ -13,10 +13,11 @@
 // keeps the cyclic convolution free of wrap-around.  The tables (twiddles of length L, chirp,
 // and FFT_L(c) / L) are computed on the host in FP64 (plan.cpp).
 //
-// Output convention as the power-of-two sweeps: unnormalised, 2 X_k per transform, so the fused
-// z sweep's factor 1/(8 M^3) normalises the six transforms of a solve.
+// Output convention as the power-of-two sweeps: unnormalised, 2 X_k per transform, so the z
+// pass's factor 1/(4 M^2) normalises the four transforms of a solve (x and y, forward and
+// inverse; the z direction is the tridiagonal solve of z_tri.hip).
 //
-// Layout: a block loads a tile of 16 lines (8 FP64 = 128-byte runs along y and z) into LDS,
+// Layout: a block loads a tile of 16 lines (runs of 8 FP64 = 128 bytes along y) into LDS,
 // each wavefront transforms line pairs with G lanes per pair (L/8 up to 64 lanes), the complex
 // FFT exchanging through a padded buffer per pair, and the block stores the tile.
 #include "dst_line.h"
@@ -78,7 +79,7 @@ __device__ __forceinline__ void blue_transform(C2<double>* a, int g, C2<double>*
   wave_sync();  // every read of the buffer done before the next transform writes it
 }
 
-template <int LOGL, int AX, bool ZPASS>
+template <int LOGL, int AX>
 __global__ __launch_bounds__(BCfg<LOGL>::T) void k_dst_blue(PassArgs p, const double* __restrict__ twd,
                                                            const double* __restrict__ wchd,
                                                            const double* __restrict__ chfd, int N,
@@ -102,7 +103,6 @@ __global__ __launch_bounds__(BCfg<LOGL>::T) void k_dst_blue(PassArgs p, const do
   const int logical = xcd_remap(blockIdx.x, nblocks);
   const int rhs = logical / tiles;
   const int t = logical - rhs * tiles;
-  const double sig = p.sigma_rhs != nullptr ? p.sigma_rhs[p.rhs0 + rhs] : p.sigma;
   const int row = t / TILES_PER_ROW;
   const int line0 = (t - row * TILES_PER_ROW) * W;
   const int nlines = min(W, LINES_PER_ROW - line0);
@@ -144,24 +144,6 @@ __global__ __launch_bounds__(BCfg<LOGL>::T) void k_dst_blue(PassArgs p, const do
         o2[s] = 0.0;
       }
       blue_transform<LOGL>(a, g, buf, N, M, tw, wch, chf, o1, o2);
-      if constexpr (ZPASS) {
-        // divide by sigma + lambda_x + lambda_y + lambda_z (the two lines differ in x), with the
-        // normalisation (sqrt(2/M)/2)^6 of the six unnormalised transforms of the solve
-        const double kNorm = 1.0 / (8.0 * (double)M * (double)M * (double)M);
-        const int x1 = line0 + 2 * pr;
-        const double by = sig + p.inv_h2 * p.lam_hat[row];
-        const double b1 = by + p.inv_h2 * p.lam_hat[x1];
-        const double b2 = by + p.inv_h2 * p.lam_hat[min(x1 + 1, N - 1)];
-#pragma unroll
-        for (int s = 0; s < V; ++s) {
-          const int k = 1 + g + s * G;
-          const double lz = p.inv_h2 * p.lam_hat[min(k, N) - 1];
-          const double v1 = o1[s] * (kNorm / (b1 + lz));
-          const double v2 = o2[s] * (kNorm / (b2 + lz));
-          a[s] = k <= N ? cmul(C2<double>{v1, v2}, wch[k]) : C2<double>{0.0, 0.0};
-        }
-        blue_transform<LOGL>(a, g, buf, N, M, tw, wch, chf, o1, o2);
-      }
 #pragma unroll
       for (int s = 0; s < V; ++s) {
         const int k = 1 + g + s * G;
@@ -195,13 +177,10 @@ dpm_status launch_b(int n, AxisKind ax, const PassArgs& a, const Plan* pl, int n
   const dim3 grid((unsigned)nb), block(B::T);
   const int ti = (int)tiles, nbi = (int)nb;
   if (ax == AX_X)
-    hipLaunchKernelGGL((k_dst_blue<LOGL, AX_X, false>), grid, block, 0, s, a, pl->blue_tw,
-                       pl->blue_w, pl->blue_ch, n, ti, nbi);
-  else if (ax == AX_Y)
-    hipLaunchKernelGGL((k_dst_blue<LOGL, AX_Y, false>), grid, block, 0, s, a, pl->blue_tw,
+    hipLaunchKernelGGL((k_dst_blue<LOGL, AX_X>), grid, block, 0, s, a, pl->blue_tw,
                        pl->blue_w, pl->blue_ch, n, ti, nbi);
   else
-    hipLaunchKernelGGL((k_dst_blue<LOGL, AX_Z, true>), grid, block, 0, s, a, pl->blue_tw,
+    hipLaunchKernelGGL((k_dst_blue<LOGL, AX_Y>), grid, block, 0, s, a, pl->blue_tw,
                        pl->blue_w, pl->blue_ch, n, ti, nbi);
   DPM_TRY_HIP(hipGetLastError());
   return DPM_OK;
@@ -221,7 +200,7 @@ bool blue_size_supported(int n) { return !fft_size_supported(n) && blue_logl(n) 
 dpm_status launch_blue_pass(int n, AxisKind ax, bool zpass, const PassArgs& a, const Plan* pl,
                             int nrhs, hipStream_t s) {
   if (nrhs <= 0) return DPM_OK;
-  if ((ax == AX_Z) != zpass) { set_error("the fused scaling belongs to the z sweep"); return DPM_EINVAL; }
+  if (ax == AX_Z || zpass) { set_error("the z direction is the tridiagonal pass"); return DPM_EINVAL; }
   if (a.cmax != nullptr || a.done != nullptr) {
     set_error("the Bluestein sweeps serve the plain FP64 solve (no refinement)");
     return DPM_EINVAL;

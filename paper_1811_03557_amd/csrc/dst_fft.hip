@@ -2,8 +2,10 @@
 //
 // The AP (sigma I - Lap_h) u = b with zero Dirichlet data is diagonalised by the orthonormal
 // DST-I S (S = S^T = S^-1) along each axis: u = S3 D^-1 S3 b, D = sigma + lambda_kx + lambda_ky
-// + lambda_kz.  One solve is five sweeps over the volume: forward x, forward y, a fused z sweep
-// (forward, eigenvalue scaling, inverse), inverse y, inverse x.
+// + lambda_kz.  One solve is five passes over the volume: forward x, forward y, the z pass,
+// inverse y, inverse x.  The z pass (z_tri.hip) solves the tridiagonal system along z of each
+// spectral column (kx, ky) instead of transforming z, scaling and transforming back; the
+// sweeps here are the x and y transforms.
 //
 // Sweep layout.  A block moves a tile of W whole lines (W * sizeof(real) = 128 bytes of every
 // row of the tile, so each global access is a run of 128 contiguous bytes) into LDS with a
@@ -24,20 +26,20 @@ namespace dpm {
 namespace {
 
 // FP64 sweeps at N = 127 and 255 read their tables from global memory (L1/L2 resident) and are
-// compiled for 4 waves per SIMD: with at most 38.7 KB of LDS per block, 4 blocks share a CU
-// (the fused z sweep, two transforms per line, is bound by LDS latency at 3).  FP32 sweeps and
-// N >= 511 (two blocks per CU at most) keep the tables in LDS.
-template <typename T, int LOGM, bool ZPASS>
+// compiled for 4 waves per SIMD: with at most 38.7 KB of LDS per block, 4 blocks share a CU.
+// FP32 sweeps and N >= 511 (two blocks per CU at most) keep the tables in LDS.
+template <typename T, int LOGM>
 struct ZOcc {
   static constexpr bool gtab = sizeof(T) == 8 && Cfg<T, LOGM>::G % 8 == 0 && LOGM <= 8;
   static constexpr int waves = gtab ? 4 : 1;
 };
 
-template <typename T, int LOGM, int AX, bool ZPASS, int IN, int OUT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ZOcc<T, LOGM, ZPASS>::waves)))
+template <typename T, int LOGM, int AX, int IN, int OUT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ZOcc<T, LOGM>::waves)))
 void k_dst_pass(PassArgs p, int tiles, int nblocks) {
+  static_assert(AX == AX_X || AX == AX_Y, "the z direction is the tridiagonal pass");
   using K = Cfg<T, LOGM>;
-  constexpr bool GTAB = ZOcc<T, LOGM, ZPASS>::gtab;
+  constexpr bool GTAB = ZOcc<T, LOGM>::gtab;
   constexpr int M = K::M, N = K::N, G = K::G, W = K::W, P = K::P;
   constexpr long long VOL = (long long)N * N * N;
   constexpr int LINES_PER_ROW = (AX == AX_X) ? N * N : N;
@@ -48,8 +50,6 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
 
   __shared__ __align__(16) T tile[W * P];
   __shared__ __align__(16) T tab[GTAB ? 2 : 3 * M];
-  // eigenvalue table of the z sweep: lamt[0] = 0, lamt[i] = lam_hat_i (i = 1..N)
-  __shared__ __align__(16) double lamt[ZPASS ? M : 2];
   __shared__ unsigned long long red[2][kBlock / 64];
 
   const int logical = xcd_remap(blockIdx.x, nblocks);
@@ -75,9 +75,6 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
 #pragma unroll
       for (int i = 0; i < TP; ++i)
         if (tid + i * kBlock < 3 * M) tab[tid + i * kBlock] = tv[i];
-    }
-    if constexpr (ZPASS) {
-      for (int i = tid; i < M; i += kBlock) lamt[i] = i == 0 ? 0.0 : p.lam_hat[i - 1];
     }
   }
 
@@ -230,43 +227,9 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
         C2<T> o[K::V];
         C2<T>* ob = reinterpret_cast<C2<T>*>(line) + g;
         dst1_regs<T, LOGM, false>(line, g, ttab, gtab_k, o);
-        if constexpr (ZPASS) {
-          // scale X_i by (sqrt(2/M)/2)^6 / (sigma + lambda_x + lambda_y + lambda_z), i = 2k, 2k+1
-          const double bxy = sig + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]);
-          constexpr double kNorm = 1.0 / (8.0 * (double)M * (double)M * (double)M);
-          // (lambda_2k, lambda_2k+1) as one aligned 16-byte read
-          const C2<double>* lp = reinterpret_cast<const C2<double>*>(lamt) + g;
-#pragma unroll
-          for (int s2 = 0; s2 < K::V; ++s2) {
-            const C2<double> lv = lp[s2 * G];
-            const double d0 = kNorm * recip(bxy + p.inv_h2 * lv.x);
-            const double d1 = kNorm * recip(bxy + p.inv_h2 * lv.y);
-            o[s2].x = (T)((double)o[s2].x * d0);
-            o[s2].y = (T)((double)o[s2].y * d1);
-            ob[s2 * G] = o[s2];
-          }
-          wave_sync();
-          dst1_regs<T, LOGM, true>(line, g, ttab, gtab_k, o);
-        }
 #pragma unroll
         for (int s2 = 0; s2 < K::V; ++s2) ob[s2 * G] = o[s2];
         wave_sync();
-      } else if constexpr (ZPASS) {
-        // forward DST scaled by 1/(sigma + lambda), then the inverse DST: one code path run
-        // twice keeps the register footprint of a single transform
-        const double bxy = sig + p.inv_h2 * (p.lam_hat[line0 + l] + p.lam_hat[row]);
-        // (sqrt(2/M) / 2)^6: normalisation of the six unnormalised transforms of the solve
-        constexpr double kNorm = 1.0 / (8.0 * (double)M * (double)M * (double)M);
-#pragma unroll 1
-        for (int rep = 0; rep < 2; ++rep) {
-          dst1_line<T, LOGM>(line, g, tab);
-          if (rep == 0) {
-#pragma unroll 4
-            for (int i = 1 + g; i <= N; i += G)
-              line[i] *= (T)(kNorm / (bxy + p.inv_h2 * p.lam_hat[i - 1]));
-            wave_sync();
-          }
-        }
       } else {
         dst1_line<T, LOGM>(line, g, tab);
       }
@@ -389,20 +352,17 @@ dpm_status launch_t(AxisKind ax, bool zpass, InKind in, OutKind out, const PassA
   if (nb > 0x7fffffffLL) { set_error("launch too large"); return DPM_EINVAL; }
   dim3 grid((unsigned)nb), block(kBlock);
   const int ti = (int)tiles, nbi = (int)nb;
+  if (zpass || ax == AX_Z) { set_error("the z direction is the tridiagonal pass"); return DPM_EINVAL; }
   if (ax == AX_X) {
-    if (zpass) { set_error("z sweep requested on the x axis"); return DPM_EINVAL; }
-    if (in == IN_WS && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, false, IN_WS, OUT_WS>), grid, block, 0, s, a, ti, nbi);
-    else if (in == IN_F64 && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, false, IN_F64, OUT_WS>), grid, block, 0, s, a, ti, nbi);
-    else if (in == IN_RESID && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, false, IN_RESID, OUT_WS>), grid, block, 0, s, a, ti, nbi);
-    else if (in == IN_WS && out == OUT_F64) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, false, IN_WS, OUT_F64>), grid, block, 0, s, a, ti, nbi);
-    else if (in == IN_WS && out == OUT_UPD) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, false, IN_WS, OUT_UPD>), grid, block, 0, s, a, ti, nbi);
+    if (in == IN_WS && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_WS, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+    else if (in == IN_F64 && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_F64, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+    else if (in == IN_RESID && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_RESID, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+    else if (in == IN_WS && out == OUT_F64) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_WS, OUT_F64>), grid, block, 0, s, a, ti, nbi);
+    else if (in == IN_WS && out == OUT_UPD) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_WS, OUT_UPD>), grid, block, 0, s, a, ti, nbi);
     else { set_error("unsupported x sweep kind (%d,%d)", (int)in, (int)out); return DPM_EINVAL; }
-  } else if (ax == AX_Y) {
-    if (zpass || in != IN_WS || out != OUT_WS) { set_error("unsupported y sweep kind"); return DPM_EINVAL; }
-    hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_Y, false, IN_WS, OUT_WS>), grid, block, 0, s, a, ti, nbi);
   } else {
-    if (!zpass || in != IN_WS || out != OUT_WS) { set_error("unsupported z sweep kind"); return DPM_EINVAL; }
-    hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_Z, true, IN_WS, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+    if (in != IN_WS || out != OUT_WS) { set_error("unsupported y sweep kind"); return DPM_EINVAL; }
+    hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_Y, IN_WS, OUT_WS>), grid, block, 0, s, a, ti, nbi);
   }
   DPM_TRY_HIP(hipGetLastError());
   return DPM_OK;
