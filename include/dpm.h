@@ -70,14 +70,15 @@ typedef struct {
   int32_t sweeps;      /* dpm_sweeps: how the FFT-form transforms pass over the volume */
 } dpm_opts;
 
-/* Sweep layout of the FFT-form solves (DPM_FP64, DPM_FP32).  A solve applies the DST-I along x,
- * y and z, divides by the eigenvalues and applies the three DST-Is again; the layouts differ in
- * how many times the volume travels through HBM.
+/* Sweep layout of the FFT-form solves (DPM_FP64, DPM_FP32).  A solve applies the DST-I along x
+ * and y, solves the tridiagonal system along z of every spectral column (the same result as the
+ * DST along z, the division by the eigenvalues and the DST back) and applies the two DST-Is
+ * again; the layouts differ in how many times the volume travels through HBM.
  *  DPM_SWEEPS_AUTO (0): the library's choice: DPM_SWEEPS_PLANE where available, else
  *    DPM_SWEEPS_AXIS (or the layout dpm_autotune recorded).
- *  DPM_SWEEPS_AXIS: five per-axis sweeps (x, y, fused z, y, x).
+ *  DPM_SWEEPS_AXIS: five per-axis passes (x, y, z, y, x).
  *  DPM_SWEEPS_PLANE: three sweeps: both in-plane transforms of a z-plane in one pass with the
- *    plane in LDS (n = 7, 15, 31, 63, 127), the fused z sweep, the inverse plane pass.
+ *    plane in LDS (n = 7, 15, 31, 63, 127), the z pass, the inverse plane pass.
  * Results agree to rounding (the transforms are the same, applied in another order of
  * operations only where the plane is transposed).  The dense forms ignore the field. */
 typedef enum { DPM_SWEEPS_AUTO = 0, DPM_SWEEPS_AXIS = 1, DPM_SWEEPS_PLANE = 2 } dpm_sweeps;
@@ -590,7 +591,7 @@ dpm_status dpm_dd_diagnostics(const dpm_dd* dd, const double* const state[4], do
  * chunk [rhs0, rhs0 + nb) of a solve call is sampled when it holds an index that is a multiple of
  * rhs_stride (1 = every launch; a larger stride keeps the events' own cost out of the timed
  * work).  dpm_timing_end synchronises the events and returns, per sweep kind, the number of timed
- * launches and their mean duration in ms.  Kinds: 0 first x sweep, 1 y sweep, 2 fused z sweep,
+ * launches and their mean duration in ms.  Kinds: 0 first x sweep, 1 y sweep, 2 z pass,
  * 3 last x sweep, 4 residual x sweep, 5 update x sweep, 6 forward plane sweep (any input kind),
  * 7 inverse plane sweep (any output kind).  At most max_launches launches are
  * recorded.  Process-wide, not thread safe.

@@ -236,8 +236,8 @@ static bool use_plane_sweeps(const dpm_grid& g, const dpm_opts& o, int form) {
   return tuned_entry(g.n, o).sweeps != DPM_SWEEPS_AXIS;
 }
 
-// One solve of nb right-hand sides: five per-axis sweeps, or (plane) two fused plane sweeps
-// around the z sweep.  in_kind/out_kind select the first and last sweeps; src/dst are the
+// One solve of nb right-hand sides: five per-axis passes, or (plane) two fused plane sweeps
+// around the z pass.  in_kind/out_kind select the first and last sweeps; src/dst are the
 // first sweep's source and the last sweep's destination, ws the volume the middle sweeps work
 // on.
 static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind in_kind,

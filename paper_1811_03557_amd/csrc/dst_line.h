@@ -200,7 +200,8 @@ __device__ __forceinline__ T group_scan(T v, int g) {
 
 // In-place DST-I of one line by the G threads g = 0..G-1 of the line, unnormalised: on exit
 // line[i] = 2 X_i with X_i = sum_j x_j sin(pi i j/M) (the orthonormal transform is
-// sqrt(2/M) X; the factors of all six transforms of a solve are applied once, in the z sweep).
+// sqrt(2/M) X; the factors of the four x and y transforms of a solve are applied once, by the
+// z pass).
 // Slot layout (P reals): x_j at line[j], j = 1..N, line[0] = 0, and again line[0] = 0 on exit.  The slot doubles as the
 // padded FFT buffer (pad8 positions).  Thread g owns the strided elements g + s*G, so that every
 // LDS access of a stage touches consecutive positions.

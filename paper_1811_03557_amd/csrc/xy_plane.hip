@@ -3,11 +3,12 @@
 //
 // With the plane held in LDS, a solve reads and writes the volume three times instead of five:
 //   forward plane sweep: b[z][y][x] -> DST_y DST_x b, stored transposed as B[z][kx][ky];
-//   fused z sweep (per-axis kernel of dst_fft.hip) on B: forward DST along z, division by
-//   sigma + lambda_kx + lambda_ky + lambda_kz, inverse DST along z;
+//   z pass (z_tri.hip) on B: the tridiagonal solve along z of every spectral column, which
+//   equals forward DST along z, division by sigma + lambda_kx + lambda_ky + lambda_kz and
+//   inverse DST along z;
 //   inverse plane sweep: B[z][kx][ky] -> DST_x DST_y B = u[z][y][x].
-// The z sweep's scaling is symmetric in its two in-plane indices, so it runs unchanged on the
-// transposed spectral planes.
+// The z pass is symmetric in its two in-plane indices, so it runs unchanged on the transposed
+// spectral planes.
 //
 // A block owns one plane: it loads the plane's N rows into LDS slots (one slot per row, the
 // slot doubling as the row's padded FFT buffer), transforms every row in place, transposes the
