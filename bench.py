@@ -575,7 +575,7 @@ def run_boundary_matrix(args, dev):
     idx, _ = api.gamma_points(m, h, x0)
     B, _ = api.basis(n, h, x0, geo, idx, 10, 1)
     out = {"workload": f"unit sphere, N = {n}, sigma = 2/h^2, 242 columns (l <= 10, beta = 1), "
-                       "solves + traces + Householder QR"}
+                       "solves + traces + QR (CholeskyQR2) and least-squares operator"}
     for name, prec, mr in (("fp32", "fp32", 0), ("fp32_ir", "fp32", 3), ("fp64", "fp64", 0)):
         api.build_boundary_matrix(m, B, n, h, sigma, x0, prec=prec, max_refine=mr).close()
         torch.cuda.synchronize()

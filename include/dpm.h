@@ -245,8 +245,10 @@ dpm_status dpm_basis_zonal(const dpm_grid* grid, const dpm_geometry* geom, int32
  * dpm_build_boundary_matrix -- paper Algorithm "Main Steps", Step 2: the reduced-BEP matrix
  * (eq BEP_recast) A[:, nu] = Tr_gamma_in (I - P_gamma) basis_nu, one AP solve per column with
  * right-hand side 1_{M-} (sigma - Lap_h)[basis_nu extended by zero] (Def. "DP" in sigma-form),
- * followed by an FP64 Householder QR A = Q R and the least-squares operator P = R^-1 Q1^T
- * (Q1: the first n_basis columns of Q), both kept in the handle.
+ * followed by an FP64 QR A = Q R and the least-squares operator P = R^-1 Q1^T (Q1: the first
+ * n_basis columns of Q), kept in the handle.  The QR is CholeskyQR2 (two Gram/Cholesky passes);
+ * when a Cholesky factor breaks down or the second pass finds the first far from orthogonal,
+ * the Householder QR of the untouched A is used instead.
  * m_plus: device N^3 uint8; basis: device n_basis x n_gamma FP64 in the order of
  * dpm_gamma_points.  opts selects the precision of the solves (refinement applies).
  * A_out: nullable device |gamma_in| x n_basis FP64, column-major.  Allocates the handle's
@@ -332,10 +334,11 @@ dpm_status dpm_bep_rebuild_workspace_size(const dpm_bep* bep, size_t* bytes);
 
 /*
  * dpm_bep_rebuild -- paper Step 4b: recompute the reduced-BEP matrix (the same densities and
- * geometry), its Householder QR and the least-squares operator in place for a new sigma
- * (= 1/dt), with the transform options given at build time.  workspace: device scratch of at
- * least dpm_bep_rebuild_workspace_size bytes, 16-byte aligned, owned by the caller; the call
- * allocates nothing.  Synchronises `stream` once, for the rank test.  Errors as
+ * geometry), its QR (as dpm_build_boundary_matrix) and the least-squares operator in place for a
+ * new sigma (= 1/dt), with the transform options given at build time.  workspace: device
+ * scratch of at least dpm_bep_rebuild_workspace_size bytes, 16-byte aligned, owned by the
+ * caller; the call allocates nothing.  Synchronises `stream` twice: once inside the QR (its
+ * CholeskyQR2 check) and once for the rank test.  Errors as
  * dpm_build_boundary_matrix; after a failure the handle must only be destroyed.  A stepper built
  * on this handle keeps replaying its own dt: create a new one after a rebuild.
  */
@@ -355,9 +358,9 @@ dpm_status dpm_run_workspace_size(const dpm_bep* bep, const dpm_opts* opts, size
  * dt_prev) (Step 3; dt never grows, so the matrix of the last rebuild always belongs to the
  * current dt); if dt < dt_prev rebuild the matrix at sigma = 1/dt (Step 4b); one dpm_step
  * (Steps 4a-7); t += dt.  The loop ends when t >= t_final, after max_steps steps, or at a stop.
- * One 32-byte device-to-host copy and one synchronisation per step; a rebuild's rank test is
- * read back with the next step's scan, so it adds none (on DPM_ERANK the state holds the step
- * taken with the rank-deficient matrix).  opts->workspace: at least dpm_run_workspace_size
+ * One 32-byte device-to-host copy and one synchronisation per step; a rebuild adds one more
+ * (the CholeskyQR2 check inside its QR), and its rank test is read back with the next step's
+ * scan (on DPM_ERANK the state holds the step taken with the rank-deficient matrix).  opts->workspace: at least dpm_run_workspace_size
  * bytes; the loop allocates nothing, rebuilds included.  dt_hist and rebuilt_hist (host,
  * nullable, max_steps entries) receive each step's dt and whether it rebuilt (1/0).  On return
  * the handle holds the matrix of the last dt.
@@ -411,7 +414,7 @@ void dpm_bep_destroy(dpm_bep* bep);
  * the same coefficients on both sides of Z, which imposes the continuity of u and of its first
  * two normal derivatives.  Columns: [Gamma part, (beta + 1)(m_gamma + 1) ; Z part,
  * 3 (m_z + 1)].  The two reduced BEPs are solved together as one least-squares problem,
- * rows [zeta_1,in ; gamma_in of Omega_2], with the FP64 Householder QR of the single domain.
+ * rows [zeta_1,in ; gamma_in of Omega_2], with the FP64 QR of the single domain.
  */
 typedef struct dpm_dd dpm_dd; /* library-owned: both subdomains' point sets, densities, QR */
 typedef struct {
@@ -540,8 +543,9 @@ dpm_status dpm_dd_rebuild_workspace_size(const dpm_dd* dd, size_t* bytes);
  * dpm_dd_rebuild -- Step 4b on the decomposed domain: both subdomains' columns, the stacked
  * matrix, its QR and least-squares operator again at a new sigma (= 1/dt), in place.
  * workspace: device scratch of at least dpm_dd_rebuild_workspace_size bytes, 16-byte aligned;
- * the call allocates nothing.  Synchronises `stream` once, for the rank test.  After a failure
- * the handle must only be destroyed.
+ * the call allocates nothing.  Synchronises `stream` twice (the CholeskyQR2 check of the plain
+ * least squares, then the rank test; rcond > 0 only the second).  After a failure the handle
+ * must only be destroyed.
  */
 dpm_status dpm_dd_rebuild(dpm_dd* dd, double sigma, void* workspace, size_t workspace_bytes,
                           void* stream);

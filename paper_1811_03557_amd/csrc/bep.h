@@ -63,12 +63,31 @@ size_t factor_scratch_bytes(int m, int n);
 size_t rebuild_scratch_bytes(const dpm_bep* b);
 // Columns of b->A at b->grid.sigma; enqueue only (no allocation, no synchronisation).
 dpm_status bep_columns(dpm_bep* b, hipStream_t s, void* scratch, size_t bytes);
-// Householder QR of A (m x n column-major, in place), P = R^-1 Q1^T (n x m) and the device pair
-// rd2 = (min, max) |R_ii|; enqueue only.  rcond > 0: P = R+ Q1^T with R+ the pseudo-inverse of R
+// QR of A (m x n column-major, in place), P = R^-1 Q1^T (n x m) and the device pair
+// rd2 = (min, max) |R_ii|.  rcond = 0: CholeskyQR2 (one stream synchronisation), falling back to
+// the Householder QR when it breaks down or A is too ill-conditioned for it; rcond > 0 always
+// takes the Householder QR (enqueue only).  rcond > 0: P = R+ Q1^T with R+ the pseudo-inverse of R
 // truncated at rcond (singular values <= rcond s_max dropped: the minimum-norm least-squares
 // operator), and rd2[2], rd2[3] = numerical rank and smallest kept s / s_max (rd2 holds 4 values).
 dpm_status lsq_factor(double* A, int m, int n, double* tau, double* P, hipStream_t s,
                       void* scratch, size_t bytes, double* rd2, double rcond = 0.0);
+
+// Row chunks of the Gram products of an m x n matrix (partials n x n per chunk).
+int gram_chunks(int m, int n);
+
+// CholeskyQR2 scratch (cqr.hip): partial and reduced Gram matrices, the two Cholesky factors,
+// their inverses and R^-1 (n x n row-major each), two breakdown counters and two check values.
+struct CqrScratch {
+  double *Gp, *G, *R1, *R2, *Ri1, *Ri2, *Ri, *q;
+  int* bad;
+};
+// P = R^-1 Q^T from CholeskyQR2 of A (m x n column-major); A's buffer ends up holding Q^T
+// (n x m row-major) and rd2[0..1] the (min, max) |R_ii|.  Synchronises the stream once, after
+// the second Cholesky: when either factorisation broke down or pass 2 finds pass 1's Q1 far
+// from orthogonal, *used = false, A is untouched and P holds scratch values (the caller then
+// factors A by Householder QR).
+dpm_status cqr2_operator(double* A, int m, int n, double* P, const CqrScratch& w, double* rd2,
+                         hipStream_t s, bool* used);
 
 // One-sided Jacobi SVD of the n x n triangle R of a factored A and its truncated pseudo-inverse
 // Rp (n x n row-major), with W, V (np x np column-major), inv (n) and flags (2) as scratch

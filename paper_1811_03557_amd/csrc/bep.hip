@@ -552,7 +552,7 @@ ColLayout col_layout(const dpm_grid& g, const dpm_opts& o, int n_basis) {
 }
 
 struct FacLayout {
-  size_t rd, G, T, W, K, Rinv, Gp, Ws, Vs, inv, flg, total;
+  size_t rd, G, T, W, K, Rinv, Gp, Ws, Vs, inv, flg, Ri, cq, total;
 };
 FacLayout fac_layout(int m, int n) {
   const size_t nn = sizeof(double) * (size_t)n * n;
@@ -572,6 +572,9 @@ FacLayout fac_layout(int m, int n) {
   L.Vs = at; at = align_up(at + npp, 256);
   L.inv = at; at = align_up(at + sizeof(double) * (size_t)n, 256);
   L.flg = at; at = align_up(at + 3 * sizeof(unsigned long long), 256);
+  // CholeskyQR2: R^-1, then two check values and two breakdown counters
+  L.Ri = at; at = align_up(at + nn, 256);
+  L.cq = at; at = align_up(at + 2 * sizeof(double) + 2 * sizeof(int), 256);
   L.total = at;
   return L;
 }
@@ -645,6 +648,23 @@ dpm_status lsq_factor(double* A, int m, int n_basis, double* tau, double* P, hip
     return DPM_EINVAL;
   }
   char* base = static_cast<char*>(scratch);
+  if (rcond <= 0.0) {
+    // CholeskyQR2 (BLAS-3 shaped); the Householder QR below when it reports a breakdown or a
+    // matrix too ill-conditioned for it (A is then untouched)
+    CqrScratch w;
+    w.Gp = reinterpret_cast<double*>(base + L.Gp);
+    w.G = reinterpret_cast<double*>(base + L.G);
+    w.R1 = reinterpret_cast<double*>(base + L.T);
+    w.R2 = reinterpret_cast<double*>(base + L.W);
+    w.Ri1 = reinterpret_cast<double*>(base + L.K);
+    w.Ri2 = reinterpret_cast<double*>(base + L.Rinv);
+    w.Ri = reinterpret_cast<double*>(base + L.Ri);
+    w.q = reinterpret_cast<double*>(base + L.cq);
+    w.bad = reinterpret_cast<int*>(base + L.cq + 2 * sizeof(double));
+    bool used = false;
+    DPM_TRY(cqr2_operator(A, nin, n_basis, P, w, rd2, s, &used));
+    if (used) return DPM_OK;
+  }
   // one launch per step (the step-j reflector is applied by the trailing-column blocks and
   // stored by block 0 of the next launch)
   for (int j = 0; j <= n_basis; ++j) launch_house_step(A, nin, n_basis, j, tau, s);

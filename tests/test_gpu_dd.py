@@ -601,6 +601,22 @@ def test_dd_full_size_matches_oracle(case_no):
     dd.close()
 
 
+def test_dd2_plain_least_squares_rejects_rank_deficient_matrix():
+    """Case 2 with 20 harmonics per term on Z and the plain least squares (rcond = 0): the
+    stacked matrix is numerically rank deficient (singular values down to 1e-19 of the largest),
+    so the CholeskyQR2 factorisation breaks down or fails its orthogonality check, the
+    Householder QR takes over on the untouched matrix, and its rank test rejects the build."""
+    from paper_1811_03557_amd import api
+    from paper_1811_03557_amd._lib import DPMError
+    dev = need_gpu()
+    case = odd.DDCase2(31, 0.75, 0.75, 31, 1.0, 0.5, 19, 19, beta=0)
+    dt = 0.5 * case.sub[0]["h"] ** 2
+    say("dd2 plain least squares, 20 harmonics on Z: expect DPM_ERANK")
+    with pytest.raises(DPMError) as ei:
+        api.dd_build(_params2(case, 1.0 / dt), device=dev)
+    assert "rank deficient" in str(ei.value), str(ei.value)
+
+
 # Truncated minimum-norm least squares (rcond > 0): the paper's 20 harmonics per term on Z.
 # The coupled matrix is numerically rank deficient (its singular values fall smoothly to 1e-19
 # of the largest); rcond sits in a gap of each configuration's spectrum (31/31: 3.4e-7 -> 4.1e-8;
