@@ -155,18 +155,20 @@ __device__ __forceinline__ void wave_chol_inv(double (*a)[kT + 1], double (*ui)[
 // U^-1), from tiles of earlier launches.  Padding rows and columns past n act as the identity.
 // A pivot <= 0 or not finite sets *bad and is replaced by 1 (the driver then discards the
 // result).
+constexpr int kCh = 7;  // tiles staged per chunk (2 x 7 tiles: 118 KB of LDS)
 __global__ __launch_bounds__(256) void k_chol_panel(const double* __restrict__ G,
                                                     double* __restrict__ R,
                                                     double* __restrict__ X, int n, int p,
                                                     int* __restrict__ bad) {
   __shared__ double sp[kT][kT + 1], sj[kT][kT + 1], ui[kT][kT + 1];
-  __shared__ double ta2[2][kT][kT + 1], tb2[2][kT][kT + 1];
+  __shared__ double ta[kCh][kT][kT + 1], tb[kCh][kT][kT + 1];
   const int nt = (n + kT - 1) / kT;
   const bool rblock = (int)blockIdx.x < nt - p;
   const int j = rblock ? p + (int)blockIdx.x : p;           // R: tile column
   const int xi = rblock ? 0 : (int)blockIdx.x - (nt - p);   // X: tile row
-  const int r0 = p * kT, c0 = j * kT;
+  const int r0 = p * kT, c0 = j * kT, i0 = xi * kT;
   const int t = threadIdx.x;
+  // accp: S_pp; accj: S_pj (R blocks) or T = sum_{xi <= k < p} X_{xi,k} R_kp (X blocks)
   double accp[4], accj[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -175,40 +177,59 @@ __global__ __launch_bounds__(256) void k_chol_panel(const double* __restrict__ G
     accp[q] = (rin && r0 + col < n) ? G[(long long)(r0 + row) * n + r0 + col] : (row == col ? 1.0 : 0.0);
     accj[q] = (rblock && rin && c0 + col < n) ? G[(long long)(r0 + row) * n + c0 + col] : 0.0;
   }
-  // previous tile rows q < p: tiles staged through two LDS buffers, the next tile's loads in
-  // flight while the current one is used (one barrier per tile)
-  auto load_s = [&](int qt, double* va, double* vb) {
-    const int q0 = qt * kT;
+  // the earlier tile rows q < p, kCh at a time: every load of a chunk is issued before the
+  // first store to LDS (one memory latency per chunk).  ta[u] = R_qp; tb[u] = R_qj (R blocks,
+  // j > p) or X_{xi,q} (X blocks, q >= xi).
+  for (int qb = 0; qb < p; qb += kCh) {
+    const int cnt = min(kCh, p - qb);
+    double va[kCh][4], vb[kCh][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q, row = e >> 5, col = e & 31;
-      va[q] = (r0 + col < n) ? R[(long long)(q0 + row) * n + r0 + col] : 0.0;
-      vb[q] = (rblock && j != p && c0 + col < n) ? R[(long long)(q0 + row) * n + c0 + col] : 0.0;
-    }
-  };
-  double va[4], vb[4];
-  if (p > 0) load_s(0, va, vb);
-  for (int qt = 0; qt < p; ++qt) {
-    const int bsel = qt & 1;
+    for (int u = 0; u < kCh; ++u) {
+      const int qt = qb + u;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q, row = e >> 5, col = e & 31;
-      ta2[bsel][row][col] = va[q];
-      tb2[bsel][row][col] = vb[q];
-    }
-    __syncthreads();
-    if (qt + 1 < p) load_s(qt + 1, va, vb);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q, row = e >> 5, col = e & 31;
-      double sp_ = 0.0, sj_ = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < kT; ++k) {
-        sp_ += ta2[bsel][k][row] * ta2[bsel][k][col];
-        sj_ += ta2[bsel][k][row] * tb2[bsel][k][col];
+      for (int q = 0; q < 4; ++q) {
+        const int e = t + 256 * q, row = e >> 5, col = e & 31;
+        const int q0 = qt * kT;
+        va[u][q] = (u < cnt && r0 + col < n) ? R[(long long)(q0 + row) * n + r0 + col] : 0.0;
+        if (rblock)
+          vb[u][q] = (u < cnt && j != p && c0 + col < n) ? R[(long long)(q0 + row) * n + c0 + col] : 0.0;
+        else
+          vb[u][q] = (u < cnt && qt >= xi) ? X[(long long)(i0 + row) * n + q0 + col] : 0.0;
       }
-      accp[q] -= sp_;
-      accj[q] -= sj_;
+    }
+    if (qb > 0) __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+    for (int u = 0; u < kCh; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = t + 256 * q, row = e >> 5, col = e & 31;
+        ta[u][row][col] = va[u][q];
+        tb[u][row][col] = vb[u][q];
+      }
+    __syncthreads();
+    for (int u = 0; u < cnt; ++u) {
+      const bool tx = !rblock && qb + u >= xi;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = t + 256 * q, row = e >> 5, col = e & 31;
+        double sp_ = 0.0, sj_ = 0.0;
+        if (rblock) {
+#pragma unroll 8
+          for (int k = 0; k < kT; ++k) {
+            sp_ += ta[u][k][row] * ta[u][k][col];
+            sj_ += ta[u][k][row] * tb[u][k][col];
+          }
+          accj[q] -= sj_;
+        } else {
+#pragma unroll 8
+          for (int k = 0; k < kT; ++k) {
+            sp_ += ta[u][k][row] * ta[u][k][col];
+            sj_ += tb[u][row][k] * ta[u][k][col];
+          }
+          if (tx) accj[q] += sj_;
+        }
+        accp[q] -= sp_;
+      }
     }
   }
 #pragma unroll
@@ -221,72 +242,26 @@ __global__ __launch_bounds__(256) void k_chol_panel(const double* __restrict__ G
   // S_pp = U^T U by one wavefront, with U^-1 in ui
   if (t < kT) wave_chol_inv(sp, ui, bad);
   __syncthreads();
-  if (rblock) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q, row = e >> 5, col = e & 31;
-      double a;
+  for (int q = 0; q < 4; ++q) {
+    const int e = t + 256 * q, row = e >> 5, col = e & 31;
+    double a = 0.0;
+    if (rblock) {
       if (j == p) {
         a = sp[row][col];
       } else {  // R_pj = U^-T S_pj (U^-T lower: terms k <= row)
-        a = 0.0;
         for (int k = 0; k <= row; ++k) a += ui[k][row] * sj[k][col];
       }
       if (r0 + row < n && c0 + col < n) R[(long long)(r0 + row) * n + c0 + col] = a;
+    } else {
+      if (xi == p) {
+        a = ui[row][col];
+      } else {  // X_{xi,p} = -T U^-1 (U^-1 upper: terms k <= col)
+        for (int k = 0; k <= col; ++k) a += sj[row][k] * ui[k][col];
+        a = -a;
+      }
+      if (i0 + row < n && r0 + col < n) X[(long long)(i0 + row) * n + r0 + col] = a;
     }
-    return;
-  }
-  // tile column p of X: T = sum_{xi <= k < p} X_{xi,k} R_kp into sj, then X_{xi,p} = -T U^-1
-  const int i0 = xi * kT;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  auto load_t = [&](int kt, double* xa, double* xb) {
-    const int k0 = kt * kT;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q, row = e >> 5, col = e & 31;
-      xa[q] = X[(long long)(i0 + row) * n + k0 + col];  // full tiles: xi <= kt < p
-      xb[q] = (r0 + col < n) ? R[(long long)(k0 + row) * n + r0 + col] : 0.0;
-    }
-  };
-  __syncthreads();  // the S loop's last buffer reads are done (ta2/tb2 are reused)
-  if (xi < p) load_t(xi, va, vb);
-  for (int kt = xi; kt < p; ++kt) {
-    const int bsel = kt & 1;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q, row = e >> 5, col = e & 31;
-      ta2[bsel][row][col] = va[q];
-      tb2[bsel][row][col] = vb[q];
-    }
-    __syncthreads();
-    if (kt + 1 < p) load_t(kt + 1, va, vb);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q, row = e >> 5, col = e & 31;
-      double a = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < kT; ++k) a += ta2[bsel][row][k] * tb2[bsel][k][col];
-      acc[q] += a;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = t + 256 * q, row = e >> 5, col = e & 31;
-    sj[row][col] = acc[q];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = t + 256 * q, row = e >> 5, col = e & 31;
-    double a;
-    if (xi == p) {
-      a = ui[row][col];
-    } else {  // -(T U^-1), U^-1 upper: terms k <= col
-      a = 0.0;
-      for (int k = 0; k <= col; ++k) a += sj[row][k] * ui[k][col];
-      a = -a;
-    }
-    if (i0 + row < n && r0 + col < n) X[(long long)(i0 + row) * n + r0 + col] = a;
   }
 }
 
