@@ -538,10 +538,11 @@ def oracle_by_n(args, dev, oaux, cores):
 
 
 def run_autotune(args, b, h, dev):
-    """The launch-width autotuner on the headline batch: every candidate width (right-hand sides
+    """The launch-shape autotuner on the headline batch: every candidate width (right-hand sides
     per sweep launch) timed as the best of 3 batched FP64 solves, against the library's default
-    (the width whose FP64 volumes fill the 256 MB Infinity Cache).  Runs after every other
-    measurement and resets the recorded width afterwards, so no figure above depends on it."""
+    (the width whose FP64 volumes fill the 256 MB Infinity Cache), then the z pass's columns per
+    block at the best width.  Runs after every other measurement and resets the recorded shape
+    afterwards, so no figure above depends on it."""
     import torch
     from paper_1811_03557_amd import api
     nrhs, n = int(b.shape[0]), int(b.shape[1])
@@ -550,13 +551,17 @@ def run_autotune(args, b, h, dev):
     res = api.autotune(b, args.sigma, h, prec="fp64", reps=3)
     api.autotune_reset()
     torch.cuda.synchronize()
-    by = dict(zip(res["widths"], res["ms"]))
+    by = {w: t for w, z, t in zip(res["widths"], res["zcols"], res["ms"]) if z == 0}
+    byz = {z: t for z, t in zip(res["zcols"], res["ms"]) if z != 0}
     out = {"workload": f"aux solve {n}^3, {nrhs} RHS, FP64", "default_width": default,
-           "best_width": res["best"],
+           "best_width": res["best"], "best_z_columns": res["best_zcols"],
            "ms_per_batch": {str(w): round(t, 3) for w, t in by.items()},
-           "solves_per_s": {str(w): round(nrhs / (t * 1e-3), 1) for w, t in by.items()}}
-    log(f"[bench] autotune {n}^3 x {nrhs} FP64: best width {res['best']} (default {default}); "
-        + ", ".join(f"{w}: {t:.2f} ms" for w, t in by.items()))
+           "solves_per_s": {str(w): round(nrhs / (t * 1e-3), 1) for w, t in by.items()},
+           "ms_per_batch_by_z_columns": {str(z): round(t, 3) for z, t in byz.items()}}
+    log(f"[bench] autotune {n}^3 x {nrhs} FP64: best width {res['best']} (default {default}), "
+        f"z columns {res['best_zcols'] or 'default'}; "
+        + ", ".join(f"{w}: {t:.2f} ms" for w, t in by.items())
+        + "; z columns " + ", ".join(f"{z}: {t:.2f} ms" for z, t in byz.items()))
     return out
 
 

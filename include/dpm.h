@@ -97,13 +97,14 @@ dpm_status dpm_workspace_size(const dpm_grid* grid, int32_t nrhs, const dpm_opts
 dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, int32_t* chunk);
 
 /* Autotuner of the batched launches' shape: the number of right-hand sides a sweep launch
- * carries (the width) and, where the fused plane sweeps exist (FFT form, n <= 127), the sweep
- * layout (dpm_sweeps).  The kernels' tiles are fixed at compile time; the width and the layout
- * are the launch shape chosen at run time.  The width sets the launch count and how much of a
- * launch's working set the 256 MB Infinity Cache holds; the layout trades two fewer passes over
- * HBM against the plane sweep's lower occupancy; so the best pair depends on n, the precision and
- * the chip.  (It suits the batched right-hand sides of the boundary-matrix build, Step 2 of the
- * paper's algorithm, and any batch of auxiliary problems.)
+ * carries (the width); where the fused plane sweeps exist (FFT form, n <= 127), the sweep layout
+ * (dpm_sweeps); and, for the FFT and Bluestein forms, the tile of the z pass (columns per block:
+ * 16, 32 or 64, each thread one 16-row segment of a column).  The width sets the launch count
+ * and how much of a launch's working set the 256 MB Infinity Cache holds; the layout trades two
+ * fewer passes over HBM against the plane sweep's lower occupancy; the z tile trades the width
+ * of a wavefront's contiguous runs against blocks per CU; so the best shape depends on n, the
+ * precision and the chip.  (It suits the batched right-hand sides of the boundary-matrix build,
+ * Step 2 of the paper's algorithm, and any batch of auxiliary problems.)
  *
  * Times aux_solve_batched(grid, nrhs, b, u, opts) for each candidate width in
  * {1, 2, 3, 4, 6, 8, 12, 16} that is at most nrhs, whose workspace fits
@@ -113,27 +114,36 @@ dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opt
  * layouts where both exist, else in the given layout.  opts->rhs_chunk is ignored.  Each
  * candidate takes one untimed solve, then `reps` solves timed with HIP events on `stream`; the
  * fastest is kept, and ties keep the earlier candidate (narrower width, per-axis layout first).
+ * Then, at the winning width and layout, the z pass is timed at each column count whose
+ * segments fit one block (ceil((n + 1) / 16) * columns <= 1024); one replaces the default only
+ * when strictly faster than every candidate before it.
  *
- * The winning pair is recorded for (current device, n, prec, io_fp64, max_refine > 0).  From
+ * The winning shape is recorded for (current device, n, prec, io_fp64, max_refine > 0).  From
  * then on every solve with opts->rhs_chunk == 0 uses its width, as do dpm_workspace_size and
- * dpm_rhs_chunk, and every solve with opts->sweeps == DPM_SWEEPS_AUTO its layout.  A solve's
- * results do not depend on the width; the layouts agree to rounding.
+ * dpm_rhs_chunk, every solve with opts->sweeps == DPM_SWEEPS_AUTO its layout, and every solve its
+ * z tile.  A solve's results do not depend on the width or the z tile; the layouts agree to
+ * rounding.
  *
  * b and u are caller-owned device arrays as for aux_solve_batched, and u is overwritten with
- * the solution.  The outputs are host arrays, each nullable: widths[16], sweeps[16] and ms[16]
- * (each candidate's width, layout and best time per batched solve, in ms), *count (candidates
- * timed), *best and *best_sweeps (the pair recorded).  The call synchronises the stream.
+ * the solution.  The outputs are host arrays, each nullable: widths, sweeps, zcols and ms of
+ * DPM_TUNE_MAX_CANDIDATES entries (each candidate's width, layout, z-pass columns per block --
+ * 0 for the default -- and best time per batched solve, in ms), *count (candidates timed),
+ * *best, *best_sweeps and *best_zcols (the shape recorded; 0: the default z tile).  The call
+ * synchronises the stream.
  *
  * Errors: those of aux_solve_batched; DPM_EINVAL for reps outside [1, 100], for a workspace that
  * fits no candidate, or while sweep timing is on.  The table is process-wide and guarded by a
  * lock; a solve reads it once and takes either the old pair or the new.  A solve whose
  * workspace (opts->rhs_chunk == 0) is smaller than the recorded width needs, for example one
  * sized before a re-tune or a reset, runs at the widest width the workspace holds. */
+#define DPM_TUNE_MAX_CANDIDATES 24
 dpm_status dpm_autotune(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, const void* b,
                         void* u, int32_t reps, void* stream, int32_t* widths, int32_t* sweeps,
-                        double* ms, int32_t* count, int32_t* best, int32_t* best_sweeps);
+                        int32_t* zcols, double* ms, int32_t* count, int32_t* best,
+                        int32_t* best_sweeps, int32_t* best_zcols);
 
-/* Forgets every recorded pair: solves go back to the library's default widths and layouts. */
+/* Forgets every recorded shape: solves go back to the library's default widths, layouts and z
+ * tiles. */
 void dpm_autotune_reset(void);
 
 /* Builds the per-(device, n) tables (sine/twiddle and eigenvalue tables) ahead of time.  The

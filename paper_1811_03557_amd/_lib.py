@@ -16,6 +16,7 @@ DPM_FP64, DPM_FP32, DPM_BF16X3, DPM_FP64_GEMM = 0, 1, 2, 3
 DPM_SWEEPS_AUTO, DPM_SWEEPS_AXIS, DPM_SWEEPS_PLANE = 0, 1, 2
 DPM_DIAG_WORKSPACE_BYTES = 24576  # include/dpm.h
 DPM_NOALLOC_SCRATCH_BYTES = 64 << 20  # include/dpm.h
+DPM_TUNE_MAX_CANDIDATES = 24
 STATUS_NAMES = {0: "DPM_OK", 1: "DPM_EINVAL", 2: "DPM_ENOMEM", 3: "DPM_EHIP",
                 4: "DPM_ENOTCONV", 5: "DPM_EGEOM", 6: "DPM_ERANK"}
 
@@ -128,7 +129,7 @@ SIGNATURES = {
     "dpm_timing_begin": (C.c_int, [_I, _I]),
     "dpm_rhs_chunk": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(Opts), C.POINTER(_I)]),
     "dpm_autotune": (C.c_int, [C.POINTER(Grid), _I, C.POINTER(Opts), _P, _P, _I, _P, _P, _P, _P,
-                               _P, _P, _P]),
+                               _P, _P, _P, _P, _P]),
     "dpm_autotune_reset": (None, []),
     "dpm_timing_end": (C.c_int, [_I, C.POINTER(_I), C.POINTER(_D)]),
 }

@@ -140,10 +140,11 @@ def autotune(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64", rtol: 
              max_refine: int = 0, reps: int = 3, out: torch.Tensor | None = None,
              stream=None, sweeps: str = "auto") -> dict:
     """Time the batched solve of b (nrhs, n, n, n) at each candidate launch width (right-hand
-    sides per sweep launch) and sweep layout, and record the fastest pair for this device, size
-    and precision; later solves with rhs_chunk = 0 / sweeps = "auto" use it.  Returns
-    {"widths", "sweeps", "ms", "best", "best_sweeps"}, with ms the best time per batched solve.
-    u (out, or a new tensor) receives the solution.  Synchronises the stream."""
+    sides per sweep launch) and sweep layout, then the z pass's columns per block at the best
+    pair, and record the fastest shape for this device, size and precision; later solves with
+    rhs_chunk = 0 / sweeps = "auto" use it.  Returns {"widths", "sweeps", "zcols", "ms", "best",
+    "best_sweeps", "best_zcols"}, with ms the best time per batched solve and zcols 0 for the
+    default z tile.  u (out, or a new tensor) receives the solution.  Synchronises the stream."""
     lib = L.load()
     if b.dim() != 4 or not (b.shape[1] == b.shape[2] == b.shape[3]):
         raise ValueError("b must have shape (nrhs, n, n, n)")
@@ -160,21 +161,24 @@ def autotune(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64", rtol: 
     o = opts(prec, io_fp64, rtol, max_refine, 0, sweeps)
     o.workspace = C.c_void_p(ws.data_ptr())
     o.workspace_bytes = ws.numel()
-    widths = (C.c_int32 * 16)()
-    lays = (C.c_int32 * 16)()
-    ms = (C.c_double * 16)()
-    count, best, best_l = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    nc = L.DPM_TUNE_MAX_CANDIDATES
+    widths = (C.c_int32 * nc)()
+    lays = (C.c_int32 * nc)()
+    zc = (C.c_int32 * nc)()
+    ms = (C.c_double * nc)()
+    count, best, best_l, best_z = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int32(0)
     L.check(lib.dpm_autotune(C.byref(g), nrhs, C.byref(o), C.c_void_p(_dev(b, "b")),
                              C.c_void_p(_dev(out, "u", b.dtype)), int(reps),
-                             C.c_void_p(_stream(stream)), widths, lays, ms, C.byref(count),
-                             C.byref(best), C.byref(best_l)))
+                             C.c_void_p(_stream(stream)), widths, lays, zc, ms, C.byref(count),
+                             C.byref(best), C.byref(best_l), C.byref(best_z)))
     k = count.value
     return {"widths": list(widths[:k]), "sweeps": [SWEEP_NAMES[v] for v in lays[:k]],
-            "ms": list(ms[:k]), "best": best.value, "best_sweeps": SWEEP_NAMES[best_l.value]}
+            "zcols": list(zc[:k]), "ms": list(ms[:k]), "best": best.value,
+            "best_sweeps": SWEEP_NAMES[best_l.value], "best_zcols": best_z.value}
 
 
 def autotune_reset() -> None:
-    """Forget every recorded launch width (solves go back to the library's defaults)."""
+    """Forget every recorded launch shape (solves go back to the library's defaults)."""
     L.load().dpm_autotune_reset()
 
 

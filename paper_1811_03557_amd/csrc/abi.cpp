@@ -102,7 +102,8 @@ dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opt
 
 dpm_status dpm_autotune(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, const void* b,
                         void* u, int32_t reps, void* stream, int32_t* widths, int32_t* sweeps,
-                        double* ms, int32_t* count, int32_t* best, int32_t* best_sweeps) {
+                        int32_t* zcols, double* ms, int32_t* count, int32_t* best,
+                        int32_t* best_sweeps, int32_t* best_zcols) {
   clear_error();
   DPM_TRY(validate_grid(grid));
   DPM_TRY(validate_opts(*grid, opts));
@@ -119,7 +120,7 @@ dpm_status dpm_autotune(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts
   const char* ub = static_cast<const char*>(u);
   if (bb < ub + bytes && ub < bb + bytes) { set_error("b and u overlap"); return DPM_EINVAL; }
   return autotune_impl(*grid, nrhs, *opts, b, u, reps, static_cast<hipStream_t>(stream), widths,
-                       sweeps, ms, count, best, best_sweeps);
+                       sweeps, zcols, ms, count, best, best_sweeps, best_zcols);
 }
 
 void dpm_autotune_reset(void) { autotune_reset(); }

@@ -96,6 +96,7 @@ using TuneKey = std::tuple<int, int, int, int, int>;
 struct Tuned {
   int width;
   int sweeps;  // DPM_SWEEPS_AXIS or DPM_SWEEPS_PLANE
+  int zcols;   // columns per block of the z pass (0: the default)
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, Tuned> g_tuned;
@@ -108,9 +109,9 @@ TuneKey tune_key(int n, const dpm_opts& o) {
 
 Tuned tuned_entry(int n, const dpm_opts& o) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  if (g_tuned.empty()) return Tuned{0, DPM_SWEEPS_AUTO};  // nothing tuned: no device query
+  if (g_tuned.empty()) return Tuned{0, DPM_SWEEPS_AUTO, 0};  // nothing tuned: no device query
   const auto it = g_tuned.find(tune_key(n, o));
-  return it == g_tuned.end() ? Tuned{0, DPM_SWEEPS_AUTO} : it->second;
+  return it == g_tuned.end() ? Tuned{0, DPM_SWEEPS_AUTO, 0} : it->second;
 }
 int tuned_width(int n, const dpm_opts& o) { return tuned_entry(n, o).width; }
 
@@ -244,7 +245,7 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
                               const void* src, OutKind out_kind, void* dst, void* ws,
                               const double* b, const double* u, const SolveFlags* fl, int rhs0,
                               int nb, bool gated, int form, const double* sig_rhs,
-                              hipStream_t s, bool plane) {
+                              hipStream_t s, bool plane, int zcols) {
   PassArgs a{};
   a.sigma_rhs = sig_rhs;
   a.tw = rb == 4 ? (const void*)pl->tw_f : (const void*)pl->tw_d;
@@ -271,7 +272,7 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
     // four unnormalised in-plane transforms carry (sqrt(2/M)/2)^4 = 1/(4 M^2)
     const double m1 = g.n + 1.0;
     dpm_status st = z && (form == FORM_FFT || form == FORM_BLUE)
-                      ? launch_z_tri(form == FORM_BLUE ? 8 : rb, g.n, q, 1.0 / (a.inv_h2 * 4.0 * m1 * m1), nb, s)
+                      ? launch_z_tri(form == FORM_BLUE ? 8 : rb, g.n, q, 1.0 / (a.inv_h2 * 4.0 * m1 * m1), nb, s, zcols)
                   : form == FORM_BLUE ? launch_blue_pass(g.n, ax, z, q, pl, nb, s)
                   : form == FORM_BF16X3 ? launch_bf16x3_pass(g.n, ax, z, ik, ok, q, pl, nb, s)
                   : form == FORM_F64MM  ? launch_f64mm_pass(g.n, ax, z, q, pl, nb, s)
@@ -306,12 +307,14 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
 }
 
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, const dpm_opts& o,
-                          hipStream_t s, dpm_info* info, const double* sigma_host, bool no_alloc) {
+                          hipStream_t s, dpm_info* info, const double* sigma_host, bool no_alloc,
+                          int zcols) {
   const Plan* pl = nullptr;
   DPM_TRY(no_alloc ? find_plan(g.n, &pl) : get_plan(g.n, &pl));
   const int rb = real_bytes_of(o);
   const int form = form_of(g, o);
   const bool plane = use_plane_sweeps(g, o, form);
+  if (zcols <= 0) zcols = tuned_entry(g.n, o).zcols;
   const bool ws_needed = needs_ws(o);
   const int chunk = solve_chunk(g, nrhs, o);
   const size_t need = workspace_for_chunk(g, nrhs, o, chunk > 0 ? chunk : 1);
@@ -354,21 +357,21 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
       // FP64 transforms in place in u: no workspace traffic beyond u itself
       // (no max-norm tracking: only refinement uses it)
       DPM_TRY(solve_sweeps(pl, 8, g, IN_WS, bc, OUT_F64, uc, uc, nullptr, nullptr, nullptr, c0, nb,
-                          false, form, sig_dev, s, plane));
+                          false, form, sig_dev, s, plane, zcols));
     } else if (o.prec == DPM_FP32 && !o.io_fp64) {
       DPM_TRY(solve_sweeps(pl, 4, g, IN_WS, bc, OUT_WS, uc, uc, nullptr, nullptr, nullptr, c0, nb,
-                          false, form, sig_dev, s, plane));
+                          false, form, sig_dev, s, plane, zcols));
     } else {
       // reduced-precision (or FP64) transforms on the workspace, FP64 iterate in u
       const double* bd = reinterpret_cast<const double*>(bc);
       double* ud = reinterpret_cast<double*>(uc);
       DPM_TRY(solve_sweeps(pl, rb, g, IN_F64, bc, OUT_F64, uc, vol_ws, nullptr, nullptr, &fl, c0,
-                          nb, false, form, sig_dev, s, plane));
+                          nb, false, form, sig_dev, s, plane, zcols));
       hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, 0, o.rtol);
       DPM_TRY_HIP(hipGetLastError());
       for (int k = 1; k <= o.max_refine; ++k) {
         DPM_TRY(solve_sweeps(pl, rb, g, IN_RESID, nullptr, OUT_UPD, uc, vol_ws, bd, ud, &fl, c0,
-                            nb, true, form, sig_dev, s, plane));
+                            nb, true, form, sig_dev, s, plane, zcols));
         hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, k, o.rtol);
         DPM_TRY_HIP(hipGetLastError());
       }
@@ -420,8 +423,9 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
 const int kTuneWidths[kTuneMaxWidths] = {1, 2, 3, 4, 6, 8, 12, 16};
 
 dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const void* b, void* u,
-                         int reps, hipStream_t s, int32_t* widths, int32_t* sweeps, double* ms,
-                         int32_t* count, int32_t* best, int32_t* best_sweeps) {
+                         int reps, hipStream_t s, int32_t* widths, int32_t* sweeps,
+                         int32_t* zcols, double* ms, int32_t* count, int32_t* best,
+                         int32_t* best_sweeps, int32_t* best_zcols) {
   if (timing_enabled()) {
     set_error("dpm_autotune: sweep timing is enabled; end it before tuning");
     return DPM_EINVAL;
@@ -443,7 +447,26 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
     set_error("dpm_autotune: event creation failed");
     return DPM_EHIP;
   }
-  int n_out = 0, w_best = 0, l_best = DPM_SWEEPS_AXIS;
+  // one candidate: an untimed solve (first touch, caches), then the best of `reps` timed ones
+  auto time_solve = [&](const dpm_opts& ow, int zc, double* t) {
+    dpm_status st = aux_solve_impl(g, nrhs, b, u, ow, s, nullptr, nullptr, false, zc);
+    for (int r = 0; r < reps && st == DPM_OK; ++r) {
+      hipError_t e = hipEventRecord(e0, s);
+      if (e == hipSuccess) st = aux_solve_impl(g, nrhs, b, u, ow, s, nullptr, nullptr, false, zc);
+      if (st != DPM_OK) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float el = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
+      if (e != hipSuccess) {
+        set_error("dpm_autotune: %s", hipGetErrorString(e));
+        return DPM_EHIP;
+      }
+      if (r == 0 || el < *t) *t = el;
+    }
+    return st;
+  };
+  int n_out = 0, w_best = 0, l_best = DPM_SWEEPS_AXIS, z_best = 0;
   double t_best = 0.0;
   dpm_status st = DPM_OK;
   for (int li = 0; li < nl && st == DPM_OK; ++li) {
@@ -453,32 +476,39 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
       ow.rhs_chunk = w;
       ow.sweeps = layouts[li];
       if (workspace_for_chunk(g, nrhs, ow, w) > o.workspace_bytes) continue;
-      st = aux_solve_impl(g, nrhs, b, u, ow, s, nullptr);  // untimed: first-touch and caches
-      if (st != DPM_OK) break;
       double t = 0.0;
-      for (int r = 0; r < reps && st == DPM_OK; ++r) {
-        hipError_t e = hipEventRecord(e0, s);
-        if (e == hipSuccess) st = aux_solve_impl(g, nrhs, b, u, ow, s, nullptr);
-        if (st != DPM_OK) break;
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float el = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
-        if (e != hipSuccess) {
-          set_error("dpm_autotune: %s", hipGetErrorString(e));
-          st = DPM_EHIP;
-          break;
-        }
-        if (r == 0 || el < t) t = el;
-      }
+      st = time_solve(ow, 0, &t);
       if (st != DPM_OK) break;
       if (widths) widths[n_out] = w;
       if (sweeps) sweeps[n_out] = layouts[li];
+      if (zcols) zcols[n_out] = 0;
       if (ms) ms[n_out] = t;
       ++n_out;
       if (w_best == 0 || t < t_best) {  // ties keep the earlier candidate (narrower, per-axis)
         w_best = w;
         l_best = layouts[li];
+        t_best = t;
+      }
+    }
+  }
+  // the z pass's columns per block (FFT and Bluestein forms), at the winning width and layout;
+  // the default (0) stays unless a column count is strictly faster
+  if (st == DPM_OK && w_best > 0 && (form == FORM_FFT || form == FORM_BLUE)) {
+    dpm_opts ow = o;
+    ow.rhs_chunk = w_best;
+    ow.sweeps = l_best;
+    for (int zc : {16, 32, 64}) {
+      if (!z_tri_cols_valid(g.n, zc)) continue;
+      double t = 0.0;
+      st = time_solve(ow, zc, &t);
+      if (st != DPM_OK) break;
+      if (widths) widths[n_out] = w_best;
+      if (sweeps) sweeps[n_out] = l_best;
+      if (zcols) zcols[n_out] = zc;
+      if (ms) ms[n_out] = t;
+      ++n_out;
+      if (t < t_best) {
+        z_best = zc;
         t_best = t;
       }
     }
@@ -492,11 +522,12 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
   }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[tune_key(g.n, o)] = Tuned{w_best, l_best};
+    g_tuned[tune_key(g.n, o)] = Tuned{w_best, l_best, z_best};
   }
   if (count) *count = n_out;
   if (best) *best = w_best;
   if (best_sweeps) *best_sweeps = l_best;
+  if (best_zcols) *best_zcols = z_best;
   return DPM_OK;
 }
 

@@ -113,9 +113,11 @@ dpm_status launch_xy_pass(int real_bytes, int n, InKind in, OutKind out, const P
 // Middle pass of the FFT-form solves: the tridiagonal solve along z of every spectral column
 // (kx, ky), in place on the volume the forward x and y sweeps left (either plane order).
 // fscale multiplies the input: h^2 times the normalisation of the four in-plane transforms.
-bool z_tri_supported(int n);  // 1 <= n <= 1024
+// cols: columns per block (16, 32 or 64 with ceil((n + 1) / 16) * cols <= 1024), 0 = default.
+bool z_tri_supported(int n);  // 1 <= n <= 1023
+bool z_tri_cols_valid(int n, int cols);
 dpm_status launch_z_tri(int real_bytes, int n, const PassArgs& a, double fscale, int nrhs,
-                        hipStream_t s);
+                        hipStream_t s, int cols = 0);
 
 // Bluestein DST-I sweep (FP64, n + 1 not a power of two; plain solve kinds only).
 dpm_status launch_blue_pass(int n, AxisKind ax, bool zpass, const PassArgs& a, const Plan* pl,
@@ -151,9 +153,12 @@ struct SolveFlags {
 size_t flags_bytes(int nrhs);
 // no_alloc: take the plan with find_plan (never create it) and read `info` back without host
 // containers; the caller passes the library's static scratch as the workspace.
+// zcols > 0: the z pass's columns per block (the autotuner's candidates), else the recorded
+// or default one.
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u,
                           const dpm_opts& o, hipStream_t s, dpm_info* info,
-                          const double* sigma_host = nullptr, bool no_alloc = false);
+                          const double* sigma_host = nullptr, bool no_alloc = false,
+                          int zcols = 0);
 // Device scratch of aux_solve_batched_noalloc: kStaticScratchBytes per device, owned by the
 // library for the life of the process (static_scratch.hip).  Returns its device address on the
 // current device, looked up once per device.
@@ -167,10 +172,13 @@ size_t workspace_for_chunk(const dpm_grid& g, int nrhs, const dpm_opts& o, int c
 // Launch-shape autotuner (see dpm_autotune): candidate widths x sweep layouts, timing, the
 // recorded pairs.
 constexpr int kTuneMaxWidths = 8;
-constexpr int kTuneMaxCands = 2 * kTuneMaxWidths;
+constexpr int kTuneZCols = 3;
+constexpr int kTuneMaxCands = 2 * kTuneMaxWidths + kTuneZCols;
+static_assert(kTuneMaxCands <= DPM_TUNE_MAX_CANDIDATES, "candidate arrays of the ABI");
 dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const void* b, void* u,
-                         int reps, hipStream_t s, int32_t* widths, int32_t* sweeps, double* ms,
-                         int32_t* count, int32_t* best, int32_t* best_sweeps);
+                         int reps, hipStream_t s, int32_t* widths, int32_t* sweeps,
+                         int32_t* zcols, double* ms, int32_t* count, int32_t* best,
+                         int32_t* best_sweeps, int32_t* best_zcols);
 void autotune_reset();
 dpm_status validate_grid(const dpm_grid* g);
 dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o);

@@ -183,9 +183,9 @@ __global__ __launch_bounds__(1024) void k_z_tri(PassArgs p, int n, int nseg, int
   if (!last) st(outb, roff(kSegRows - 1), (T)zr);
 }
 
-// Columns per block: W * P <= 1024 threads, 16 <= W <= 32 (runs of >= 128 bytes in FP64).  At
-// n = 255 (P = 16), W = 32 measured 98.5 us per 2-RHS FP64 launch against 101 at W = 64, and
-// 75 against 84 us in FP32.
+// Default columns per block: W * P <= 1024 threads, 16 <= W <= 32 (runs of >= 128 bytes in
+// FP64).  At n = 255 (P = 16), W = 32 measured 98.5 us per 2-RHS FP64 launch against 101 at
+// W = 64, and 75 against 84 us in FP32; dpm_autotune measures 16, 32 and 64 per size.
 int z_tri_logw(int nseg) {
   int logw = 5;
   while (logw > 4 && (nseg << logw) > 1024) --logw;
@@ -196,12 +196,21 @@ int z_tri_logw(int nseg) {
 
 bool z_tri_supported(int n) { return n >= 1 && n + 1 <= 64 * kSegRows; }
 
+bool z_tri_cols_valid(int n, int cols) {
+  const int nseg = (n + kSegRows) / kSegRows;
+  return (cols == 16 || cols == 32 || cols == 64) && nseg * cols <= 1024;
+}
+
 dpm_status launch_z_tri(int real_bytes, int n, const PassArgs& a, double fscale, int nrhs,
-                        hipStream_t s) {
+                        hipStream_t s, int cols) {
   if (nrhs <= 0) return DPM_OK;
   if (!z_tri_supported(n)) { set_error("no tridiagonal z pass for n = %d", n); return DPM_EINVAL; }
   const int nseg = (n + kSegRows) / kSegRows;  // ceil((n + 1) / 16)
-  const int logw = z_tri_logw(nseg);
+  if (cols != 0 && !z_tri_cols_valid(n, cols)) {
+    set_error("z pass: %d columns per block do not fit n = %d", cols, n);
+    return DPM_EINVAL;
+  }
+  const int logw = cols == 0 ? z_tri_logw(nseg) : (cols == 16 ? 4 : cols == 32 ? 5 : 6);
   const long long plane = (long long)n * n;
   const long long tiles = (plane + (1LL << logw) - 1) >> logw;
   const long long nb = tiles * nrhs;

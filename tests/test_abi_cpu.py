@@ -192,9 +192,10 @@ def test_autotune_validation_without_device():
     o = _lib.Opts(_lib.DPM_FP64, 1, 1e-10, 0, 0, None, 0)
     w = C.c_int32(0)
     assert lib.dpm_rhs_chunk(C.byref(g), 64, C.byref(o), C.byref(w)) == _lib.DPM_OK and w.value == 2
-    widths, lays, ms = (C.c_int32 * 16)(), (C.c_int32 * 16)(), (C.c_double * 16)()
-    cnt, best, bl = C.c_int32(0), C.c_int32(0), C.c_int32(0)
-    args = (widths, lays, ms, C.byref(cnt), C.byref(best), C.byref(bl))
+    nc = _lib.DPM_TUNE_MAX_CANDIDATES
+    widths, lays, zc, ms = (C.c_int32 * nc)(), (C.c_int32 * nc)(), (C.c_int32 * nc)(), (C.c_double * nc)()
+    cnt, best, bl, bz = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    args = (widths, lays, zc, ms, C.byref(cnt), C.byref(best), C.byref(bl), C.byref(bz))
     for nrhs, reps in ((0, 3), (4, 0), (4, 101)):
         assert lib.dpm_autotune(C.byref(g), nrhs, C.byref(o), None, None, reps, None, *args) == _lib.DPM_EINVAL
         assert lib.dpm_last_error()

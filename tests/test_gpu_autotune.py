@@ -1,9 +1,10 @@
 """The launch-shape autotuner (dpm_autotune) through the C ABI: it times every candidate width
-that fits, in both sweep layouts where the plane sweeps exist, records the fastest pair, and
-later solves with rhs_chunk = 0 (sweeps = auto) take it.  A solve's result
-does not depend on the width (each right-hand side's arithmetic is the same), so solves at the
-tuned width are compared bit for bit with width-1 solves, and against the oracle at the FP64 (1e-12)
-and refined (1e-10) tolerances."""
+that fits, in both sweep layouts where the plane sweeps exist, then the z pass's columns per
+block at the best pair, records the fastest shape, and later solves with rhs_chunk = 0
+(sweeps = auto) take it.  A solve's result depends neither on the width (each right-hand side's
+arithmetic is the same) nor on the z tile (each column's is), so solves at the tuned shape are
+compared bit for bit with width-1 solves and with default-shape solves, and against the oracle
+at the FP64 (1e-12) and refined (1e-10) tolerances."""
 import numpy as np
 import pytest
 
@@ -29,15 +30,20 @@ def test_autotune_records_fastest_width(prec, max_refine, tol):
     try:
         default = api.rhs_chunk(api.grid(n, h, sigma), nrhs, api.opts(prec, True, 1e-10, max_refine))
         res = api.autotune(bt, sigma, h, prec=prec, max_refine=max_refine, reps=2)
-        say(f"  widths {res['widths']}, layouts {res['sweeps']}, ms {[round(t, 3) for t in res['ms']]}, "
-            f"best {res['best']} {res['best_sweeps']} (default {default})")
+        say(f"  widths {res['widths']}, layouts {res['sweeps']}, z columns {res['zcols']}, "
+            f"ms {[round(t, 3) for t in res['ms']]}, best {res['best']} {res['best_sweeps']} "
+            f"z {res['best_zcols']} (default width {default})")
         # every candidate width up to nrhs (the default width at this size is far above 8), in
-        # both sweep layouts (the plane sweeps exist at 63)
-        assert res["widths"] == [1, 2, 3, 4, 6, 8] * 2
-        assert res["sweeps"] == ["axis"] * 6 + ["plane"] * 6
+        # both sweep layouts (the plane sweeps exist at 63), then 16, 32 and 64 z columns per
+        # block (4 segments of 16 rows per column at 63: all fit) at the best pair
+        k = int(np.argmin(res["ms"][:12]))
+        assert res["widths"] == [1, 2, 3, 4, 6, 8] * 2 + [res["widths"][k]] * 3
+        assert res["sweeps"] == ["axis"] * 6 + ["plane"] * 6 + [res["sweeps"][k]] * 3
+        assert res["zcols"] == [0] * 12 + [16, 32, 64]
         assert all(np.isfinite(t) and t > 0 for t in res["ms"])
-        k = int(np.argmin(res["ms"]))
         assert res["best"] == res["widths"][k] and res["best_sweeps"] == res["sweeps"][k]
+        kz = int(np.argmin(res["ms"]))
+        assert res["best_zcols"] == (res["zcols"][kz] if res["ms"][kz] < res["ms"][k] else 0)
         # solves that leave the layout to the library take the recorded one
         u_fixed = api.aux_solve_batched(bt, sigma, h, prec=prec, max_refine=max_refine,
                                         sweeps=res["best_sweeps"]).cpu().numpy()
@@ -54,6 +60,10 @@ def test_autotune_records_fastest_width(prec, max_refine, tol):
         assert err <= tol
     finally:
         api.autotune_reset()
+    # the default shape (every z tile default) gives the same bits in the same layout
+    u_def = api.aux_solve_batched(bt, sigma, h, prec=prec, max_refine=max_refine,
+                                  sweeps=res["best_sweeps"]).cpu().numpy()
+    assert np.array_equal(u_def, u_fixed)
     assert api.rhs_chunk(api.grid(n, h, sigma), nrhs, api.opts(prec, True, 1e-10, max_refine)) == default
 
 
