@@ -245,7 +245,8 @@ def run_test_b(args, dev):
     dt = time.perf_counter() - t
     out["build_500"] = {"n": n, "columns": bep.n_basis, "gamma_in": bep.n_gamma_in,
                         "build_s": round(dt, 4), "columns_per_s": round(bep.n_basis / dt, 1),
-                        "rdiag_min_over_max": round(bep.rdiag[0] / bep.rdiag[1], 4)}
+                        "rdiag_min_over_max": round(bep.rdiag[0] / bep.rdiag[1], 4),
+                        "lsq_method": bep.lsq_method()}
     log(f"[bench] test B build: {bep.n_basis} zonal columns at {n}^3 in {dt * 1e3:.1f} ms")
     bep.close()
     del m, idx, B
@@ -424,7 +425,7 @@ def run_dd2(args, dev):
         m1 = mass()
         li = dd.lsq_info()
         res = {"m_z": m_z, "rcond": rcond, "columns": dd.n_cols, "rows": sum(dd.n_rows),
-               "rank": li["rank"], "build_s": round(build, 4),
+               "rank": li["rank"], "lsq_method": li["method"], "build_s": round(build, 4),
                "ms_per_step": round(t_step * 1e3, 3), "steps_per_s": round(1.0 / t_step, 1),
                "finite": all(bool(torch.isfinite(v).all()) for v in state),
                "mass_change_rel": float(f"{(m1 - m0) / m0:.3e}"),
@@ -588,7 +589,8 @@ def run_boundary_matrix(args, dev):
         bep = api.build_boundary_matrix(m, B, n, h, sigma, x0, prec=prec, max_refine=mr)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        out[name] = {"build_s": round(dt, 4), "columns_per_s": round(bep.n_basis / dt, 1)}
+        out[name] = {"build_s": round(dt, 4), "columns_per_s": round(bep.n_basis / dt, 1),
+                     "lsq_method": bep.lsq_method()}
         log(f"[bench] boundary matrix {name}: {dt * 1e3:.1f} ms for {bep.n_basis} columns")
         bep.close()
     return out

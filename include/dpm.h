@@ -272,6 +272,20 @@ dpm_status dpm_build_boundary_matrix(const dpm_grid* grid, const uint8_t* m_plus
 dpm_status dpm_bep_info(const dpm_bep* bep, int32_t* n_gamma, int32_t* n_gamma_in,
                         int32_t* n_basis, double* min_abs_rdiag, double* max_abs_rdiag);
 
+/* The QR behind a handle's least-squares operator, as of its last build or rebuild:
+ * CholeskyQR2 where both Cholesky factors exist, the second pass finds the first close to
+ * orthogonal (every |R2_ii - 1| <= 0.05) and min / max |R_ii| >= 1e-5; the Householder QR
+ * otherwise; the Householder QR with the truncated pseudo-inverse of R when rcond > 0
+ * (domain decomposition, Case 2).  The least-squares solution is the same; the methods differ in
+ * cost (CholeskyQR2 is two Gram products and small factorisations, the Householder QR one
+ * dependent launch per column) and in rounding. */
+typedef enum {
+  DPM_LSQ_CHOLESKY_QR2 = 1,
+  DPM_LSQ_HOUSEHOLDER = 2,
+  DPM_LSQ_HOUSEHOLDER_TRUNCATED = 3
+} dpm_lsq_method;
+dpm_status dpm_bep_lsq_method(const dpm_bep* bep, int32_t* method);
+
 /* Device bytes the handle holds (masks, gamma lists, densities, the factored matrix, the
  * least-squares operator): what keeping it resident costs, e.g. for admission by HBM footprint. */
 dpm_status dpm_bep_device_bytes(const dpm_bep* bep, size_t* bytes);
@@ -501,6 +515,8 @@ dpm_status dpm_dd_info(const dpm_dd* dd, int32_t n_gamma[2], int32_t n_gamma_in[
  * the numerical rank of the coupled matrix (its column count when rcond = 0) and the smallest
  * kept singular value over the largest (0 when rcond = 0).  Refreshed by every rebuild. */
 dpm_status dpm_dd_lsq_info(const dpm_dd* dd, double* rcond, int32_t* rank, double* smin_ratio);
+/* The QR of the coupled least squares (dpm_lsq_method; see dpm_bep_lsq_method). */
+dpm_status dpm_dd_lsq_method(const dpm_dd* dd, int32_t* method);
 
 /* Copies of subdomain l's (0 or 1) M+ and N+ masks (device, its N^3 uint8; each nullable). */
 dpm_status dpm_dd_masks(const dpm_dd* dd, int32_t l, uint8_t* m_plus, uint8_t* n_plus,

@@ -17,6 +17,7 @@ DPM_SWEEPS_AUTO, DPM_SWEEPS_AXIS, DPM_SWEEPS_PLANE = 0, 1, 2
 DPM_DIAG_WORKSPACE_BYTES = 24576  # include/dpm.h
 DPM_NOALLOC_SCRATCH_BYTES = 64 << 20  # include/dpm.h
 DPM_TUNE_MAX_CANDIDATES = 24
+DPM_LSQ_CHOLESKY_QR2, DPM_LSQ_HOUSEHOLDER, DPM_LSQ_HOUSEHOLDER_TRUNCATED = 1, 2, 3
 STATUS_NAMES = {0: "DPM_OK", 1: "DPM_EINVAL", 2: "DPM_ENOMEM", 3: "DPM_EHIP",
                 4: "DPM_ENOTCONV", 5: "DPM_EGEOM", 6: "DPM_ERANK"}
 
@@ -110,6 +111,8 @@ SIGNATURES = {
     "dpm_dd_info": (C.c_int, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I), C.POINTER(_I),
                               C.POINTER(_D), C.POINTER(_D)]),
     "dpm_dd_lsq_info": (C.c_int, [_P, C.POINTER(_D), C.POINTER(_I), C.POINTER(_D)]),
+    "dpm_dd_lsq_method": (C.c_int, [_P, C.POINTER(_I)]),
+    "dpm_bep_lsq_method": (C.c_int, [_P, C.POINTER(_I)]),
     "dpm_dd_masks": (C.c_int, [_P, _I, _P, _P, _P]),
     "dpm_dd_step_workspace_size": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
     "dpm_dd_step": (C.c_int, [_P, _D, _D, C.POINTER(_P), C.POINTER(_P), C.POINTER(Opts), _P]),

@@ -134,6 +134,7 @@ def aux_solve_batched_noalloc(b: torch.Tensor, sigma: float, h: float, prec: str
 
 
 SWEEP_NAMES = {L.DPM_SWEEPS_AXIS: "axis", L.DPM_SWEEPS_PLANE: "plane"}
+LSQ_METHOD_NAMES = {0: "none", 1: "cholesky_qr2", 2: "householder", 3: "householder_truncated"}
 
 
 def autotune(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64", rtol: float = 1e-10,
@@ -321,6 +322,13 @@ class BEP:
                                       C.byref(rmax)))
         self.rdiag = (rmin.value, rmax.value)
 
+    def lsq_method(self) -> str:
+        """The QR behind the least-squares operator of the last build or rebuild:
+        "cholesky_qr2" or "householder"."""
+        m = C.c_int32(0)
+        L.check(L.load().dpm_bep_lsq_method(C.c_void_p(self.ptr), C.byref(m)))
+        return LSQ_METHOD_NAMES[m.value]
+
     def close(self):
         if self.ptr:
             L.load().dpm_bep_destroy(C.c_void_p(self.ptr))
@@ -379,12 +387,15 @@ class DD:
         self.rdiag = (rmin.value, rmax.value)
 
     def lsq_info(self) -> dict:
-        """rcond of the coupled least squares, the numerical rank of the coupled matrix and the
-        smallest kept singular value over the largest (truncated least squares only)."""
-        rc, rk, sm = C.c_double(0), C.c_int32(0), C.c_double(0)
-        L.check(L.load().dpm_dd_lsq_info(C.c_void_p(self.ptr), C.byref(rc), C.byref(rk),
-                                         C.byref(sm)))
-        return {"rcond": rc.value, "rank": rk.value, "smin_ratio": sm.value}
+        """rcond of the coupled least squares, the numerical rank of the coupled matrix, the
+        smallest kept singular value over the largest (truncated least squares only) and the QR
+        used ("cholesky_qr2", "householder" or "householder_truncated")."""
+        rc, rk, sm, me = C.c_double(0), C.c_int32(0), C.c_double(0), C.c_int32(0)
+        lib = L.load()
+        L.check(lib.dpm_dd_lsq_info(C.c_void_p(self.ptr), C.byref(rc), C.byref(rk), C.byref(sm)))
+        L.check(lib.dpm_dd_lsq_method(C.c_void_p(self.ptr), C.byref(me)))
+        return {"rcond": rc.value, "rank": rk.value, "smin_ratio": sm.value,
+                "method": LSQ_METHOD_NAMES[me.value]}
 
     def masks(self, l: int, stream=None):
         """(M+, N+) of subdomain l as uint8 volumes."""

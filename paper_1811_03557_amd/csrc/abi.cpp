@@ -45,6 +45,7 @@ dpm_status dd_diagnostics_impl(const dpm_dd* d, const double* const state[4], do
 dpm_status dd_info_impl(const dpm_dd* d, int32_t n_gamma[2], int32_t n_in[2], int32_t n_rows[2],
                         int32_t* n_cols, double* rmin, double* rmax);
 dpm_status dd_lsq_info_impl(const dpm_dd* d, double* rcond, int32_t* rank, double* smin_ratio);
+int dd_lsq_method(const dpm_dd* d);
 dpm_status dd2_build_impl(const dpm_dd2_params& prm, const dpm_opts& o, hipStream_t s,
                           dpm_dd** out, double* A_out);
 dpm_status dd_rebuild_impl(dpm_dd* d, double sigma, hipStream_t s, void* scratch, size_t bytes);
@@ -521,6 +522,20 @@ dpm_status dpm_dd_lsq_info(const dpm_dd* dd, double* rcond, int32_t* rank, doubl
   clear_error();
   if (!dd) { set_error("dd is NULL"); return DPM_EINVAL; }
   return dd_lsq_info_impl(dd, rcond, rank, smin_ratio);
+}
+
+dpm_status dpm_dd_lsq_method(const dpm_dd* dd, int32_t* method) {
+  clear_error();
+  if (!dd || !method) { set_error("dd or method is NULL"); return DPM_EINVAL; }
+  *method = dd_lsq_method(dd);
+  return DPM_OK;
+}
+
+dpm_status dpm_bep_lsq_method(const dpm_bep* bep, int32_t* method) {
+  clear_error();
+  if (!bep || !method) { set_error("bep or method is NULL"); return DPM_EINVAL; }
+  *method = bep->lsq_method;
+  return DPM_OK;
 }
 
 dpm_status dpm_dd_masks(const dpm_dd* dd, int32_t l, uint8_t* m_plus, uint8_t* n_plus,

@@ -14,11 +14,12 @@ struct dpm_bep {
   int32_t* idx_in = nullptr;  // linear indices of gamma_in (rows of A)
   int32_t* pos_in = nullptr;  // position of each gamma_in node inside the gamma list
   double* basis = nullptr;    // n_basis x n_gamma densities (row nu contiguous)
-  double* A = nullptr;        // n_in x n_basis, column-major: Householder vectors below R
+  double* A = nullptr;        // n_in x n_basis, column-major: Q^T, or Householder vectors below R
   double* tau = nullptr;      // n_basis reflector scalars
   double* P = nullptr;        // n_basis x n_in least-squares operator R^-1 Q1^T (row nu contiguous)
   int32_t* gpos = nullptr;    // N^3: position of each node in the gamma list, -1 off gamma
   double rdiag_min = 0.0, rdiag_max = 0.0;
+  int lsq_method = 0;         // dpm_lsq_method of the last factorisation
 };
 
 // A captured time step (dpm_step in place on fixed buffers) replayed as a HIP graph.
@@ -69,8 +70,10 @@ dpm_status bep_columns(dpm_bep* b, hipStream_t s, void* scratch, size_t bytes);
 // takes the Householder QR (enqueue only).  rcond > 0: P = R+ Q1^T with R+ the pseudo-inverse of R
 // truncated at rcond (singular values <= rcond s_max dropped: the minimum-norm least-squares
 // operator), and rd2[2], rd2[3] = numerical rank and smallest kept s / s_max (rd2 holds 4 values).
+// method (nullable): the dpm_lsq_method used.
 dpm_status lsq_factor(double* A, int m, int n, double* tau, double* P, hipStream_t s,
-                      void* scratch, size_t bytes, double* rd2, double rcond = 0.0);
+                      void* scratch, size_t bytes, double* rd2, double rcond = 0.0,
+                      int* method = nullptr);
 
 // Row chunks of the Gram products of an m x n matrix (partials n x n per chunk).
 int gram_chunks(int m, int n);

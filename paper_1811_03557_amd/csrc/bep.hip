@@ -574,7 +574,7 @@ FacLayout fac_layout(int m, int n) {
   L.flg = at; at = align_up(at + 3 * sizeof(unsigned long long), 256);
   // CholeskyQR2: R^-1, then two check values and two breakdown counters
   L.Ri = at; at = align_up(at + nn, 256);
-  L.cq = at; at = align_up(at + 2 * sizeof(double) + 2 * sizeof(int), 256);
+  L.cq = at; at = align_up(at + 3 * sizeof(double) + 2 * sizeof(int), 256);
   L.total = at;
   return L;
 }
@@ -639,7 +639,7 @@ dpm_status bep_columns(dpm_bep* b, hipStream_t s, void* scratch, size_t bytes) {
 // pair rd2, with temporaries from `scratch` (factor_scratch_bytes).  Enqueue only: the caller
 // reads rd2 back for the rank test.
 dpm_status lsq_factor(double* A, int m, int n_basis, double* tau, double* P, hipStream_t s,
-                      void* scratch, size_t bytes, double* rd2, double rcond) {
+                      void* scratch, size_t bytes, double* rd2, double rcond, int* method) {
   const int nin = m;
   const FacLayout L = fac_layout(m, n_basis);
   if (scratch == nullptr || bytes < L.total) {
@@ -660,11 +660,15 @@ dpm_status lsq_factor(double* A, int m, int n_basis, double* tau, double* P, hip
     w.Ri2 = reinterpret_cast<double*>(base + L.Rinv);
     w.Ri = reinterpret_cast<double*>(base + L.Ri);
     w.q = reinterpret_cast<double*>(base + L.cq);
-    w.bad = reinterpret_cast<int*>(base + L.cq + 2 * sizeof(double));
+    w.bad = reinterpret_cast<int*>(base + L.cq + 3 * sizeof(double));
     bool used = false;
     DPM_TRY(cqr2_operator(A, nin, n_basis, P, w, rd2, s, &used));
-    if (used) return DPM_OK;
+    if (used) {
+      if (method) *method = DPM_LSQ_CHOLESKY_QR2;
+      return DPM_OK;
+    }
   }
+  if (method) *method = rcond > 0.0 ? DPM_LSQ_HOUSEHOLDER_TRUNCATED : DPM_LSQ_HOUSEHOLDER;
   // one launch per step (the step-j reflector is applied by the trailing-column blocks and
   // stored by block 0 of the next launch)
   for (int j = 0; j <= n_basis; ++j) launch_house_step(A, nin, n_basis, j, tau, s);
@@ -711,7 +715,8 @@ dpm_status factor_bep_enqueue(dpm_bep* b, hipStream_t s, double* A_out, void* sc
     set_error("dpm_build_boundary_matrix: copy of A failed");
     return DPM_EHIP;
   }
-  return lsq_factor(b->A, b->n_in, b->n_basis, b->tau, b->P, s, scratch, bytes, rd2);
+  return lsq_factor(b->A, b->n_in, b->n_basis, b->tau, b->P, s, scratch, bytes, rd2, 0.0,
+                    &b->lsq_method);
 }
 
 // The same, then one synchronisation for the rank test (rd2 read back from the end of scratch).

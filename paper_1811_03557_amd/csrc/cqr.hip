@@ -7,8 +7,9 @@
 // and the least-squares operator P = R^-1 Q^T (n x m, row-major), so that C = P g.  Pass 1
 // alone loses orthogonality like kappa(A)^2 u; pass 2 restores it to O(u) while
 // kappa(Q1) stays near 1, i.e. while G2 stays near the identity.  The driver therefore checks
-// that neither Cholesky broke down and that every diagonal entry of R2 lies within 0.05 of 1
-// (kappa(A)^2 u well below 1); otherwise A is still intact and the Householder QR takes over.
+// that neither Cholesky broke down, that every diagonal entry of R2 lies within 0.05 of 1
+// (kappa(A)^2 u well below 1) and that min / max |R_ii| >= 1e-5 (a well-conditioned matrix);
+// otherwise A is still intact and the Householder QR takes over.
 //
 // Work is BLAS-3 shaped: two Gram products (m n^2 flops each, upper tiles, row chunks reduced
 // in a fixed order), three products of a triangular n x n factor with an n x m row-major
@@ -335,7 +336,8 @@ __global__ void k_trmm_small(const double* __restrict__ A, const double* __restr
 }
 
 // Checks of the two Cholesky factors and the rank figures: q[0] = number of breakdowns,
-// q[1] = max_i |R2_ii - 1|; rd2 = (min, max) |R1_ii R2_ii| (the diagonal of R = R2 R1).
+// q[1] = max_i |R2_ii - 1|, q[2] = min / max |R_ii|; rd2 = (min, max) |R1_ii R2_ii| (the
+// diagonal of R = R2 R1).
 __global__ void k_cqr_check(const double* __restrict__ R1, const double* __restrict__ R2, int n,
                             const int* __restrict__ bad, double* __restrict__ q,
                             double* __restrict__ rd2) {
@@ -363,6 +365,7 @@ __global__ void k_cqr_check(const double* __restrict__ R1, const double* __restr
   if (threadIdx.x == 0) {
     q[0] = (double)(bad[0] + bad[1]);
     q[1] = sdev[0];
+    q[2] = smax[0] > 0.0 ? smin[0] / smax[0] : 0.0;
     rd2[0] = smin[0];
     rd2[1] = smax[0];
   }
@@ -398,8 +401,13 @@ void tri_apply(bool trans, const double* Rm, int n, const double* In, int m, dou
 
 }  // namespace
 
-// Largest accepted max_i |R2_ii - 1| (pass 1's loss of orthogonality seen by pass 2).
+// Largest accepted max_i |R2_ii - 1| (pass 1's loss of orthogonality seen by pass 2), and the
+// smallest accepted min / max |R_ii|: below it (the coupled Case 2 systems, kappa 1e8 - 1e10
+// with columns of very different norms) CholeskyQR2's coefficients carried 50 - 100 times the
+// Householder QR's error at the same residual in a NumPy emulation, while at the boundary
+// matrices of one domain (kappa up to 5e4) the two agree.
 constexpr double kCqrDev = 0.05;
+constexpr double kCqrRdiag = 1e-5;
 
 dpm_status cqr2_operator(double* A, int m, int n, double* P, const CqrScratch& w, double* rd2,
                          hipStream_t s, bool* used) {
@@ -415,10 +423,10 @@ dpm_status cqr2_operator(double* A, int m, int n, double* P, const CqrScratch& w
   chol_inv(w.G, w.R2, w.Ri2, n, w.bad + 1, s);
   hipLaunchKernelGGL(k_cqr_check, dim3(1), dim3(256), 0, s, w.R1, w.R2, n, w.bad, w.q, rd2);
   DPM_TRY_HIP(hipGetLastError());
-  double q[2] = {1.0, 0.0};
+  double q[3] = {1.0, 0.0, 0.0};
   DPM_TRY_HIP(hipMemcpyAsync(q, w.q, sizeof(q), hipMemcpyDeviceToHost, s));
   DPM_TRY_HIP(hipStreamSynchronize(s));
-  if (q[0] != 0.0 || !(q[1] <= kCqrDev)) return DPM_OK;  // not used: Householder on A
+  if (q[0] != 0.0 || !(q[1] <= kCqrDev) || !(q[2] >= kCqrRdiag)) return DPM_OK;  // Householder on A
   // Q^T = R2^-T Q1^T into A's buffer, R^-1 = R1^-1 R2^-1, P = R^-1 Q^T
   tri_apply(true, w.Ri2, n, P, m, A, s);
   hipLaunchKernelGGL(k_trmm_small, dim3((unsigned)(((long long)n * n + 255) / 256)), dim3(256), 0,

@@ -32,10 +32,11 @@ struct dpm_dd {
   dpm_bep* sub[2] = {nullptr, nullptr};  // per subdomain: masks, gamma lists, densities, A_l
   int n_gamma_cols = 0, n_z_cols = 0, n_cols = 0;
   int rows = 0;           // reduced-BEP rows of both subdomains (Case 1: |zeta_1,in| + |gamma_2,in|)
-  double* A = nullptr;    // rows x n_cols, column-major; Householder vectors below R
+  double* A = nullptr;    // rows x n_cols, column-major; Q^T, or Householder vectors below R
   double* tau = nullptr;  // n_cols
   double* P = nullptr;    // n_cols x rows least-squares operator (row nu contiguous)
   double rdiag_min = 0.0, rdiag_max = 0.0;
+  int lsq_method = 0;  // dpm_lsq_method of the last factorisation
   // least squares of the coupled BEPs: rcond 0 plain, > 0 truncated minimum norm; the numerical
   // rank and smallest kept singular value ratio of the last factorisation
   double rcond = 0.0;
@@ -395,7 +396,8 @@ dpm_status dd_stack_factor(dpm_dd* d, hipStream_t s, double* A_out, void* scratc
   }
   DPM_TRY_HIP(hipGetLastError());
   if (A_out) DPM_TRY_HIP(hipMemcpyAsync(A_out, d->A, sizeof(double) * na, hipMemcpyDeviceToDevice, s));
-  return lsq_factor(d->A, d->rows, d->n_cols, d->tau, d->P, s, scratch, bytes, rd2, d->rcond);
+  return lsq_factor(d->A, d->rows, d->n_cols, d->tau, d->P, s, scratch, bytes, rd2, d->rcond,
+                    &d->lsq_method);
 }
 
 // Result of a factorisation read back from rd[0..3]: (min, max) |R_ii|, and with truncation the
@@ -734,6 +736,8 @@ dpm_status dd_rebuild_impl(dpm_dd* d, double sigma, hipStream_t s, void* scratch
 double dd_sigma(const dpm_dd* d) { return d->prm.grid1.sigma; }
 const dpm_bep* dd_sub(const dpm_dd* d, int l) { return d->sub[l]; }
 const double* dd_origin(const dpm_dd* d, int l) { return d->origin[l]; }
+
+int dd_lsq_method(const dpm_dd* d) { return d->lsq_method; }
 
 dpm_status dd_lsq_info_impl(const dpm_dd* d, double* rcond, int32_t* rank, double* smin_ratio) {
   if (rcond) *rcond = d->rcond;

@@ -141,6 +141,9 @@ def test_dd_validation_without_device():
     assert lib.dpm_dd_gauss_state(None, 0, 1.0, 1.0, (C.c_double * 3)(0, 0, 0), fake, None) == _lib.DPM_EINVAL
     assert lib.dpm_dd_info(None, None, None, None, None, None, None) == _lib.DPM_EINVAL
     assert lib.dpm_dd_lsq_info(None, None, None, None) == _lib.DPM_EINVAL
+    m = C.c_int32(0)
+    assert lib.dpm_dd_lsq_method(None, C.byref(m)) == _lib.DPM_EINVAL
+    assert lib.dpm_bep_lsq_method(None, C.byref(m)) == _lib.DPM_EINVAL
     # Case 2: Z must meet Gamma
     g1b = _lib.Grid(15, 0.09375, 1000.0, -0.75 + 0.09375)
 

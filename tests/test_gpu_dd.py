@@ -601,6 +601,24 @@ def test_dd_full_size_matches_oracle(case_no):
     dd.close()
 
 
+def test_dd2_ill_conditioned_system_takes_householder_qr():
+    """Case 2 with 6 harmonics per term on Z: the coupled matrix has full rank but widely
+    different column norms (min / max |R_ii| about 5e-7, kappa 8e7), below the CholeskyQR2
+    threshold of 1e-5, so the plain least squares is factored by the Householder QR; the solution
+    matches LAPACK's (one step against the oracle is the subject of the Case 2 parity tests)."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    case = odd.DDCase2(31, 0.75, 0.75, 31, 1.0, 0.5, 19, 5, beta=0)
+    dt = 0.5 * case.sub[0]["h"] ** 2
+    dd = api.dd_build(_params2(case, 1.0 / dt), device=dev)
+    info = dd.lsq_info()
+    say(f"dd2 31/31 with 6 harmonics on Z: QR {info['method']}, min/max |R_ii| "
+        f"{dd.rdiag[0] / dd.rdiag[1]:.2e}")
+    assert info["method"] == "householder" and info["rank"] == dd.n_cols
+    dd.close()
+
+
 def test_dd2_plain_least_squares_rejects_rank_deficient_matrix():
     """Case 2 with 20 harmonics per term on Z and the plain least squares (rcond = 0): the
     stacked matrix is numerically rank deficient (singular values down to 1e-19 of the largest),
@@ -647,6 +665,7 @@ def test_dd2_truncated_least_squares_matches_oracle(n1, n2, mg, mz, rcond, tol):
     say(f"  rank {info['rank']} (LAPACK {rank} of {A.shape[1]}), smallest kept "
         f"{info['smin_ratio']:.3e} (LAPACK {sv[rank - 1] / sv[0]:.3e})")
     assert info["rcond"] == rcond and info["rank"] == rank
+    assert info["method"] == "householder_truncated"
     assert abs(info["smin_ratio"] / (sv[rank - 1] / sv[0]) - 1.0) < 1e-6
     st = list(_data2(s1["mesh"], s1["ps"])) + list(_data2(s2["mesh"], s2["ps"]))
     ref = odd.dd2_step(*st, case, A, dt, chi)[:4]

@@ -150,6 +150,17 @@ def test_least_squares_against_lapack(n, shape, lmax):
         e = np.linalg.norm(C[r] - Cref) / np.linalg.norm(Cref)
         say(f"  rhs {r}: rel err {e:.2e}, bound {tol:.2e} (kappa {kappa:.3g}, eta {eta:.3g})")
         assert e < tol, (r, e, tol)
+    # the QR follows the documented rule: CholeskyQR2 for min / max |R_ii| >= 1e-5 (these
+    # matrices factor without breakdown and pass the orthogonality check), Householder below;
+    # near the threshold either is allowed
+    d = np.abs(np.diag(np.linalg.qr(A, mode="r")))
+    ratio = d.min() / d.max()
+    method = bep.lsq_method()
+    say(f"  QR: {method} (min/max |R_ii| {ratio:.2e})")
+    if ratio >= 2e-5:
+        assert method == "cholesky_qr2"
+    elif ratio <= 5e-6:
+        assert method == "householder"
     bep.close()
 
 
