@@ -46,12 +46,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "aux solves/s at 255³ FP32 vs FP64 @1e-10 rel; p50/p99 latency; % HBM peak"
 HBM_PEAK_GBS = 8000.0
-KIND_NAMES = ["x_first", "y", "z", "x_last", "x_residual", "x_update"]
+KIND_NAMES = ["x_first", "y", "z", "x_last", "x_residual", "x_update", "xy_forward", "xy_inverse",
+              "xz_forward", "z_separators", "xz_inverse"]
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dst_sweeps_fp64_aux255_64rhs_hbm_traffic.txt")
 KERNEL_SOURCES = ["paper_1811_03557_amd/csrc/dst_fft.hip", "paper_1811_03557_amd/csrc/dst_line.h",
-                  "paper_1811_03557_amd/csrc/common.h", "paper_1811_03557_amd/csrc/z_tri.hip"]
+                  "paper_1811_03557_amd/csrc/common.h", "paper_1811_03557_amd/csrc/z_tri.hip",
+                  "paper_1811_03557_amd/csrc/xz_split.hip"]
 
 
 def counted_traffic(kind, path_name, n, rhs_per_launch):
@@ -684,6 +686,7 @@ def main():
             # every step: live per-kernel durations inside the timed region at ~0.3% of its work
             stride = max(1, nrhs // 2)
             _lib.check(lib.dpm_timing_begin(8 * args.steps * (1 + cfg["max_refine"]) * 6, stride))
+            nk = len(KIND_NAMES)
             t0 = torch.cuda.Event(enable_timing=True)
             t1 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
@@ -694,11 +697,11 @@ def main():
             torch.cuda.synchronize()
             ms = t0.elapsed_time(t1) / args.steps
             import ctypes as C
-            cnt = (C.c_int32 * 6)()
-            mean = (C.c_double * 6)()
-            _lib.check(lib.dpm_timing_end(6, cnt, mean))
+            cnt = (C.c_int32 * nk)()
+            mean = (C.c_double * nk)()
+            _lib.check(lib.dpm_timing_end(nk, cnt, mean))
             kern = {KIND_NAMES[k]: {"timed_launches_per_step": cnt[k] / args.steps,
-                                    "mean_ms": mean[k]} for k in range(6) if cnt[k] > 0}
+                                    "mean_ms": mean[k]} for k in range(nk) if cnt[k] > 0}
             # refinement iterations actually used (one extra solve with info)
             _, info = api.aux_solve_batched(b, sigma, h, prec=cfg["prec"], rtol=args.rtol,
                                             max_refine=cfg["max_refine"], out=u, workspace=ws,

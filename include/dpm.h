@@ -74,14 +74,27 @@ typedef struct {
  * and y, solves the tridiagonal system along z of every spectral column (the same result as the
  * DST along z, the division by the eigenvalues and the DST back) and applies the two DST-Is
  * again; the layouts differ in how many times the volume travels through HBM.
- *  DPM_SWEEPS_AUTO (0): the library's choice: DPM_SWEEPS_PLANE where available, else
- *    DPM_SWEEPS_AXIS (or the layout dpm_autotune recorded).
+ *  DPM_SWEEPS_AUTO (0): the library's choice: the layout dpm_autotune recorded, else
+ *    DPM_SWEEPS_PLANE where available, else DPM_SWEEPS_SPLIT at n = 511 (plain solves), else
+ *    DPM_SWEEPS_AXIS.
  *  DPM_SWEEPS_AXIS: five per-axis passes (x, y, z, y, x).
  *  DPM_SWEEPS_PLANE: three sweeps: both in-plane transforms of a z-plane in one pass with the
  *    plane in LDS (n = 7, 15, 31, 63, 127), the z pass, the inverse plane pass.
- * Results agree to rounding (the transforms are the same, applied in another order of
- * operations only where the plane is transposed).  The dense forms ignore the field. */
-typedef enum { DPM_SWEEPS_AUTO = 0, DPM_SWEEPS_AXIS = 1, DPM_SWEEPS_PLANE = 2 } dpm_sweeps;
+ *  DPM_SWEEPS_SPLIT: four passes and a small one, for plain solves (DPM_FP64 without refinement,
+ *    DPM_FP32 with FP32 I/O) at n = 255 and 511: the y transforms; the x transforms of 16
+ *    consecutive z-rows fused with the segment-local elimination of the z solve, and back with
+ *    its reconstruction; between them the separators' reduced system, which reads 2/16 and writes
+ *    1/16 of a volume.  The workspace then holds ((n + 1)/16 - 1) n^2 reals of the transform type
+ *    per right-hand side of a launch (dpm_workspace_size counts them); under DPM_SWEEPS_AUTO a
+ *    workspace too small for them runs the per-axis sweeps instead.
+ * Results agree to rounding (the transforms and the z solve are the same, applied in another
+ * order of operations).  The dense forms ignore the field. */
+typedef enum {
+  DPM_SWEEPS_AUTO = 0,
+  DPM_SWEEPS_AXIS = 1,
+  DPM_SWEEPS_PLANE = 2,
+  DPM_SWEEPS_SPLIT = 3
+} dpm_sweeps;
 
 typedef struct {
   int32_t refine_iters;  /* refinement iterations actually applied (max over the batch) */
@@ -97,11 +110,12 @@ dpm_status dpm_workspace_size(const dpm_grid* grid, int32_t nrhs, const dpm_opts
 dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opts, int32_t* chunk);
 
 /* Autotuner of the batched launches' shape: the number of right-hand sides a sweep launch
- * carries (the width); where the fused plane sweeps exist (FFT form, n <= 127), the sweep layout
- * (dpm_sweeps); and, for the FFT and Bluestein forms, the tile of the z pass (columns per block:
+ * carries (the width); where a fused layout exists (FFT form: the plane sweeps at n <= 127, the
+ * split layout at n = 255, 511 for plain solves), the sweep layout (dpm_sweeps); and, for the
+ * FFT and Bluestein forms, the tile of the z pass (columns per block:
  * 16, 32 or 64, each thread one 16-row segment of a column).  The width sets the launch count
  * and how much of a launch's working set the 256 MB Infinity Cache holds; the layout trades two
- * fewer passes over HBM against the plane sweep's lower occupancy; the z tile trades the width
+ * fewer passes over HBM against the fused kernels' lower occupancy; the z tile trades the width
  * of a wavefront's contiguous runs against blocks per CU; so the best shape depends on n, the
  * precision and the chip.  (It suits the batched right-hand sides of the boundary-matrix build,
  * Step 2 of the paper's algorithm, and any batch of auxiliary problems.)
@@ -114,7 +128,8 @@ dpm_status dpm_rhs_chunk(const dpm_grid* grid, int32_t nrhs, const dpm_opts* opt
  * layouts where both exist, else in the given layout.  opts->rhs_chunk is ignored.  Each
  * candidate takes one untimed solve, then `reps` solves timed with HIP events on `stream`; the
  * fastest is kept, and ties keep the earlier candidate (narrower width, per-axis layout first).
- * Then, at the winning width and layout, the z pass is timed at each column count whose
+ * Then, at the winning width and layout (unless it is the split layout, which has no z pass),
+ * the z pass is timed at each column count whose
  * segments fit one block (ceil((n + 1) / 16) * columns <= 1024); one replaces the default only
  * when strictly faster than every candidate before it.
  *
@@ -623,7 +638,9 @@ dpm_status dpm_dd_diagnostics(const dpm_dd* dd, const double* const state[4], do
  * work).  dpm_timing_end synchronises the events and returns, per sweep kind, the number of timed
  * launches and their mean duration in ms.  Kinds: 0 first x sweep, 1 y sweep, 2 z pass,
  * 3 last x sweep, 4 residual x sweep, 5 update x sweep, 6 forward plane sweep (any input kind),
- * 7 inverse plane sweep (any output kind).  At most max_launches launches are
+ * 7 inverse plane sweep (any output kind), 8 x sweep with the z elimination, 9 separator pass,
+ * 10 x sweep with the z reconstruction (the last three: split layout, whose y sweeps count as
+ * kind 1).  At most max_launches launches are
  * recorded.  Process-wide, not thread safe.
  */
 dpm_status dpm_timing_begin(int32_t max_launches, int32_t rhs_stride);

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libdpm.so")
 
 DPM_OK, DPM_EINVAL, DPM_ENOMEM, DPM_EHIP, DPM_ENOTCONV, DPM_EGEOM, DPM_ERANK = range(7)
 DPM_FP64, DPM_FP32, DPM_BF16X3, DPM_FP64_GEMM = 0, 1, 2, 3
-DPM_SWEEPS_AUTO, DPM_SWEEPS_AXIS, DPM_SWEEPS_PLANE = 0, 1, 2
+DPM_SWEEPS_AUTO, DPM_SWEEPS_AXIS, DPM_SWEEPS_PLANE, DPM_SWEEPS_SPLIT = 0, 1, 2, 3
 DPM_DIAG_WORKSPACE_BYTES = 24576  # include/dpm.h
 DPM_NOALLOC_SCRATCH_BYTES = 64 << 20  # include/dpm.h
 DPM_TUNE_MAX_CANDIDATES = 24

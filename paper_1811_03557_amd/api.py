@@ -35,7 +35,8 @@ def grid(n: int, h: float, sigma: float = 0.0, x0: float = 0.0) -> L.Grid:
     return L.Grid(int(n), float(h), float(sigma), float(x0))
 
 
-SWEEPS = {"auto": L.DPM_SWEEPS_AUTO, "axis": L.DPM_SWEEPS_AXIS, "plane": L.DPM_SWEEPS_PLANE}
+SWEEPS = {"auto": L.DPM_SWEEPS_AUTO, "axis": L.DPM_SWEEPS_AXIS, "plane": L.DPM_SWEEPS_PLANE,
+          "split": L.DPM_SWEEPS_SPLIT}
 
 
 def opts(prec: str = "fp64", io_fp64: bool = True, rtol: float = 1e-10, max_refine: int = 0,
@@ -133,7 +134,7 @@ def aux_solve_batched_noalloc(b: torch.Tensor, sigma: float, h: float, prec: str
     return res
 
 
-SWEEP_NAMES = {L.DPM_SWEEPS_AXIS: "axis", L.DPM_SWEEPS_PLANE: "plane"}
+SWEEP_NAMES = {L.DPM_SWEEPS_AXIS: "axis", L.DPM_SWEEPS_PLANE: "plane", L.DPM_SWEEPS_SPLIT: "split"}
 LSQ_METHOD_NAMES = {0: "none", 1: "cholesky_qr2", 2: "householder", 3: "householder_truncated"}
 
 
@@ -187,7 +188,7 @@ def aux_solve_batched_sigma(b: torch.Tensor, sigmas, h: float, prec: str = "fp64
                             rtol: float = 1e-10, max_refine: int = 0,
                             out: torch.Tensor | None = None,
                             workspace: torch.Tensor | None = None, stream=None,
-                            rhs_chunk: int = 0):
+                            rhs_chunk: int = 0, sweeps: str = "auto"):
     """Batched solve with one shift per right-hand side: b (nrhs, n, n, n), sigmas (nrhs,)."""
     lib = L.load()
     nrhs, n = int(b.shape[0]), int(b.shape[1])
@@ -197,7 +198,7 @@ def aux_solve_batched_sigma(b: torch.Tensor, sigmas, h: float, prec: str = "fp64
     io_fp64 = b.dtype == torch.float64
     out = torch.empty_like(b) if out is None else out
     g = grid(n, h, 0.0)
-    o = opts(prec, io_fp64, rtol, max_refine, rhs_chunk)
+    o = opts(prec, io_fp64, rtol, max_refine, rhs_chunk, sweeps)
     nbytes = workspace_size(g, nrhs, o)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=b.device)

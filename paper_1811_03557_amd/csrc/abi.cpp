@@ -191,6 +191,10 @@ dpm_status aux_solve_batched_noalloc(const dpm_grid* grid, int32_t nrhs, const v
   dpm_opts o = *opts;
   o.workspace = nullptr;
   o.workspace_bytes = kStaticScratchBytes;
+  // the library's layout choice takes the per-axis sweeps when the split layout's separator
+  // planes do not fit beside the rest
+  if (o.sweeps == DPM_SWEEPS_AUTO && workspace_for_chunk(*grid, nrhs, o, 1) > kStaticScratchBytes)
+    o.sweeps = DPM_SWEEPS_AXIS;
   if (workspace_for_chunk(*grid, nrhs, o, 1) > kStaticScratchBytes) {
     set_error("aux_solve_batched_noalloc: n = %d, nrhs = %d needs %zu bytes of scratch, more "
               "than the static maximum of %zu", grid->n, nrhs, workspace_for_chunk(*grid, nrhs, o, 1),

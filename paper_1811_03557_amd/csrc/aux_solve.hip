@@ -95,7 +95,7 @@ int real_bytes_of(const dpm_opts& o) {
 using TuneKey = std::tuple<int, int, int, int, int>;
 struct Tuned {
   int width;
-  int sweeps;  // DPM_SWEEPS_AXIS or DPM_SWEEPS_PLANE
+  int sweeps;  // DPM_SWEEPS_AXIS, DPM_SWEEPS_PLANE or DPM_SWEEPS_SPLIT
   int zcols;   // columns per block of the z pass (0: the default)
 };
 std::mutex g_tune_mu;
@@ -158,8 +158,16 @@ dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o) {
     return DPM_EINVAL;
   }
   if (o->rhs_chunk < 0) { set_error("rhs_chunk must be >= 0"); return DPM_EINVAL; }
-  if (o->sweeps != DPM_SWEEPS_AUTO && o->sweeps != DPM_SWEEPS_AXIS && o->sweeps != DPM_SWEEPS_PLANE) {
+  if (o->sweeps != DPM_SWEEPS_AUTO && o->sweeps != DPM_SWEEPS_AXIS && o->sweeps != DPM_SWEEPS_PLANE &&
+      o->sweeps != DPM_SWEEPS_SPLIT) {
     set_error("unknown sweep layout %d", o->sweeps);
+    return DPM_EINVAL;
+  }
+  if (o->sweeps == DPM_SWEEPS_SPLIT &&
+      (!((o->prec == DPM_FP64 && o->max_refine == 0) || (o->prec == DPM_FP32 && !o->io_fp64)) ||
+       !split_size_supported(g.n))) {
+    set_error("DPM_SWEEPS_SPLIT needs a plain solve (DPM_FP64 without refinement, or DPM_FP32 "
+              "with FP32 I/O) and n in {255, 511} (n = %d)", g.n);
     return DPM_EINVAL;
   }
   if (o->sweeps == DPM_SWEEPS_PLANE &&
@@ -191,11 +199,61 @@ dpm_status validate_opts(const dpm_grid& g, const dpm_opts* o) {
   return DPM_OK;
 }
 
-size_t workspace_for_chunk(const dpm_grid& g, int nrhs, const dpm_opts& o, int chunk) {
+// Transform forms of the sweeps: real FFT (dst_fft.hip), split-bf16 dense products on the
+// bf16 matrix cores, FP64 dense products on the FP64 matrix cores.
+enum { FORM_FFT = 0, FORM_BF16X3 = 1, FORM_F64MM = 2, FORM_BLUE = 3 };
+
+int form_of(const dpm_grid& g, const dpm_opts& o) {
+  if (o.prec == DPM_BF16X3) return FORM_BF16X3;
+  if (o.prec == DPM_FP64_GEMM) return FORM_F64MM;
+  return fft_size_supported(g.n) ? FORM_FFT : FORM_BLUE;
+}
+
+// The split layout serves the plain solves (no refinement): FP64, or FP32 with FP32 I/O.
+static bool split_opts(const dpm_opts& o) {
+  return (o.prec == DPM_FP64 && o.max_refine == 0) || (o.prec == DPM_FP32 && !o.io_fp64);
+}
+
+// Sweep layout of a solve (DPM_SWEEPS_AXIS, _PLANE or _SPLIT): the caller's, else the one the
+// autotuner recorded for these options, else the plane sweeps where they exist (FFT form,
+// n <= 127), the split layout at n = 511 (plain solves: measured 3% faster than the per-axis
+// sweeps in FP64 and 16% in FP32 on MI355X, while at 255 the per-axis sweeps are 2-3% faster),
+// the per-axis sweeps otherwise.  A layout that does not exist for the size falls back to the
+// per-axis sweeps.
+static int layout_of(const dpm_grid& g, const dpm_opts& o, int form) {
+  if (form != FORM_FFT) return DPM_SWEEPS_AXIS;
+  const bool plane_ok = xy_fusion_supported(g.n);
+  const bool split_ok = split_size_supported(g.n) && split_opts(o);
+  int want = o.sweeps;
+  if (want == DPM_SWEEPS_AUTO) want = tuned_entry(g.n, o).sweeps;
+  if (want == DPM_SWEEPS_AUTO)
+    want = plane_ok ? DPM_SWEEPS_PLANE : (split_ok && g.n == 511) ? DPM_SWEEPS_SPLIT : DPM_SWEEPS_AXIS;
+  if (want == DPM_SWEEPS_PLANE && plane_ok) return DPM_SWEEPS_PLANE;
+  if (want == DPM_SWEEPS_SPLIT && split_ok) return DPM_SWEEPS_SPLIT;
+  return DPM_SWEEPS_AXIS;
+}
+
+// Workspace bytes per right-hand side of a launch: the transform volume (when the solve needs
+// one) and the split layout's separator planes.
+static size_t ws_per_rhs(const dpm_grid& g, const dpm_opts& o, int layout) {
+  const size_t vol = (size_t)g.n * g.n * g.n;
+  size_t per = needs_ws(o) ? vol * (size_t)real_bytes_of(o) : 0;
+  if (layout == DPM_SWEEPS_SPLIT) per += split_side_values(g.n) * (size_t)real_bytes_of(o);
+  return per;
+}
+
+static size_t workspace_for_layout(const dpm_grid& g, int nrhs, const dpm_opts& o, int chunk,
+                                   int layout) {
   const size_t vol = (size_t)g.n * g.n * g.n;
   size_t total = flags_bytes(nrhs);
   if (needs_ws(o)) total += align_up(vol * (size_t)chunk * (size_t)real_bytes_of(o), 256);
+  if (layout == DPM_SWEEPS_SPLIT)
+    total += align_up(split_side_values(g.n) * (size_t)chunk * (size_t)real_bytes_of(o), 256);
   return total;
+}
+
+size_t workspace_for_chunk(const dpm_grid& g, int nrhs, const dpm_opts& o, int chunk) {
+  return workspace_for_layout(g, nrhs, o, chunk, layout_of(g, o, form_of(g, o)));
 }
 
 dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, size_t* bytes) {
@@ -208,44 +266,28 @@ dpm_status workspace_size_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, s
 // widest one the caller's workspace holds: results do not depend on the width, and a workspace
 // sized before a re-tune or a reset stays usable.  Returns 0 when not even one right-hand side
 // per launch fits.
-int solve_chunk(const dpm_grid& g, int nrhs, const dpm_opts& o) {
+static int solve_chunk(const dpm_grid& g, int nrhs, const dpm_opts& o, int layout) {
   int chunk = rhs_chunk_of(g, nrhs, o);
-  if (workspace_for_chunk(g, nrhs, o, chunk) <= o.workspace_bytes || o.rhs_chunk > 0) return chunk;
+  if (workspace_for_layout(g, nrhs, o, chunk, layout) <= o.workspace_bytes || o.rhs_chunk > 0)
+    return chunk;
   const size_t fixed = flags_bytes(nrhs);
   if (o.workspace_bytes < fixed) return 0;
-  const size_t per = (size_t)g.n * g.n * g.n * (size_t)real_bytes_of(o);
+  const size_t per = ws_per_rhs(g, o, layout);
+  if (per == 0) return chunk;
   const size_t fit = ((o.workspace_bytes - fixed) / 256 * 256) / per;
   return fit >= (size_t)chunk ? chunk : (int)fit;
 }
 
-// Transform forms of the sweeps: real FFT (dst_fft.hip), split-bf16 dense products on the
-// bf16 matrix cores, FP64 dense products on the FP64 matrix cores.
-enum { FORM_FFT = 0, FORM_BF16X3 = 1, FORM_F64MM = 2, FORM_BLUE = 3 };
-
-int form_of(const dpm_grid& g, const dpm_opts& o) {
-  if (o.prec == DPM_BF16X3) return FORM_BF16X3;
-  if (o.prec == DPM_FP64_GEMM) return FORM_F64MM;
-  return fft_size_supported(g.n) ? FORM_FFT : FORM_BLUE;
-}
-
-// Sweep layout of a solve: the per-axis sweeps, or the fused plane sweeps where they exist
-// (FFT form, n <= 127).  DPM_SWEEPS_AUTO takes the layout the autotuner recorded for these
-// options, else the plane sweeps.
-static bool use_plane_sweeps(const dpm_grid& g, const dpm_opts& o, int form) {
-  if (form != FORM_FFT || !xy_fusion_supported(g.n)) return false;
-  if (o.sweeps != DPM_SWEEPS_AUTO) return o.sweeps == DPM_SWEEPS_PLANE;
-  return tuned_entry(g.n, o).sweeps != DPM_SWEEPS_AXIS;
-}
-
-// One solve of nb right-hand sides: five per-axis passes, or (plane) two fused plane sweeps
-// around the z pass.  in_kind/out_kind select the first and last sweeps; src/dst are the
-// first sweep's source and the last sweep's destination, ws the volume the middle sweeps work
-// on.
+// One solve of nb right-hand sides: five per-axis passes, two fused plane sweeps around the z
+// pass (plane layout), or the y sweeps around the split z solve (split layout: x transforms
+// fused with its elimination and reconstruction, zside its separator planes).  in_kind/out_kind
+// select the first and last sweeps; src/dst are the first sweep's source and the last sweep's
+// destination, ws the volume the middle sweeps work on.
 static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind in_kind,
                               const void* src, OutKind out_kind, void* dst, void* ws,
                               const double* b, const double* u, const SolveFlags* fl, int rhs0,
                               int nb, bool gated, int form, const double* sig_rhs,
-                              hipStream_t s, bool plane, int zcols) {
+                              hipStream_t s, int layout, int zcols, void* zside) {
   PassArgs a{};
   a.sigma_rhs = sig_rhs;
   a.tw = rb == 4 ? (const void*)pl->tw_f : (const void*)pl->tw_d;
@@ -280,7 +322,34 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
     if (tm) timing_after(s, kind);
     return st;
   };
-  if (plane) {
+  if (layout == DPM_SWEEPS_SPLIT) {
+    // plain solves only: FP64 output is the transform type (FP32 output has FP32 transforms)
+    if (in_kind == IN_F64 && rb == 8) in_kind = IN_WS;
+    if (out_kind == OUT_F64 && rb == 8) out_kind = OUT_WS;
+    if (in_kind != IN_WS || out_kind != OUT_WS || fl != nullptr) {
+      set_error("split layout: plain solves only");
+      return DPM_EINVAL;
+    }
+    const double m1 = g.n + 1.0;
+    const double fscale = 1.0 / (a.inv_h2 * 4.0 * m1 * m1);
+    auto split = [&](int phase, int kind) {
+      PassArgs q = a;
+      q.in = ws;
+      q.out = ws;
+      const bool tm = timing_on(rhs0, nb);
+      if (tm) timing_before(s);
+      dpm_status st = launch_split_pass(rb, g.n, phase, q, zside, fscale, nb, s);
+      if (tm) timing_after(s, kind);
+      return st;
+    };
+    DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, src, ws, false, false));
+    DPM_TRY(split(0, SW_XZ_FWD));
+    DPM_TRY(split(1, SW_Z_SEP));
+    DPM_TRY(split(2, SW_XZ_INV));
+    DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, ws, dst, false, false));
+    return DPM_OK;
+  }
+  if (layout == DPM_SWEEPS_PLANE) {
     auto xy = [&](InKind ik, OutKind ok, const void* i, void* o, bool track, int kind) {
       PassArgs q = a;
       q.in = i;
@@ -313,11 +382,17 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
   DPM_TRY(no_alloc ? find_plan(g.n, &pl) : get_plan(g.n, &pl));
   const int rb = real_bytes_of(o);
   const int form = form_of(g, o);
-  const bool plane = use_plane_sweeps(g, o, form);
+  int layout = layout_of(g, o, form);
   if (zcols <= 0) zcols = tuned_entry(g.n, o).zcols;
   const bool ws_needed = needs_ws(o);
-  const int chunk = solve_chunk(g, nrhs, o);
-  const size_t need = workspace_for_chunk(g, nrhs, o, chunk > 0 ? chunk : 1);
+  int chunk = solve_chunk(g, nrhs, o, layout);
+  if (layout == DPM_SWEEPS_SPLIT && o.sweeps == DPM_SWEEPS_AUTO &&
+      (chunk <= 0 || workspace_for_layout(g, nrhs, o, chunk, layout) > o.workspace_bytes)) {
+    // a workspace sized without the separator planes: the per-axis sweeps need none
+    layout = DPM_SWEEPS_AXIS;
+    chunk = solve_chunk(g, nrhs, o, layout);
+  }
+  const size_t need = workspace_for_layout(g, nrhs, o, chunk > 0 ? chunk : 1, layout);
   if (chunk <= 0 || o.workspace_bytes < need || (need > 0 && o.workspace == nullptr)) {
     set_error("workspace too small: %zu bytes given, %zu needed", o.workspace_bytes, need);
     return DPM_EINVAL;
@@ -332,6 +407,10 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
   fl.prev = reinterpret_cast<double*>(wsb + fo.prev);
   fl.est = reinterpret_cast<double*>(wsb + fo.est);
   void* vol_ws = ws_needed ? (void*)(wsb + fo.total) : nullptr;
+  void* zside = layout == DPM_SWEEPS_SPLIT
+                    ? (void*)(wsb + fo.total +
+                              (ws_needed ? align_up((size_t)g.n * g.n * g.n * (size_t)chunk * (size_t)rb, 256) : 0))
+                    : nullptr;
   double* sig_dev = nullptr;
   if (sigma_host != nullptr) {
     sig_dev = reinterpret_cast<double*>(wsb + fo.sig);
@@ -357,21 +436,21 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
       // FP64 transforms in place in u: no workspace traffic beyond u itself
       // (no max-norm tracking: only refinement uses it)
       DPM_TRY(solve_sweeps(pl, 8, g, IN_WS, bc, OUT_F64, uc, uc, nullptr, nullptr, nullptr, c0, nb,
-                          false, form, sig_dev, s, plane, zcols));
+                          false, form, sig_dev, s, layout, zcols, zside));
     } else if (o.prec == DPM_FP32 && !o.io_fp64) {
       DPM_TRY(solve_sweeps(pl, 4, g, IN_WS, bc, OUT_WS, uc, uc, nullptr, nullptr, nullptr, c0, nb,
-                          false, form, sig_dev, s, plane, zcols));
+                          false, form, sig_dev, s, layout, zcols, zside));
     } else {
       // reduced-precision (or FP64) transforms on the workspace, FP64 iterate in u
       const double* bd = reinterpret_cast<const double*>(bc);
       double* ud = reinterpret_cast<double*>(uc);
       DPM_TRY(solve_sweeps(pl, rb, g, IN_F64, bc, OUT_F64, uc, vol_ws, nullptr, nullptr, &fl, c0,
-                          nb, false, form, sig_dev, s, plane, zcols));
+                          nb, false, form, sig_dev, s, layout, zcols, zside));
       hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, 0, o.rtol);
       DPM_TRY_HIP(hipGetLastError());
       for (int k = 1; k <= o.max_refine; ++k) {
         DPM_TRY(solve_sweeps(pl, rb, g, IN_RESID, nullptr, OUT_UPD, uc, vol_ws, bd, ud, &fl, c0,
-                            nb, true, form, sig_dev, s, plane, zcols));
+                            nb, true, form, sig_dev, s, layout, zcols, zside));
         hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, k, o.rtol);
         DPM_TRY_HIP(hipGetLastError());
       }
@@ -433,12 +512,19 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
   // with a transform workspace, stay at or below the default width, so that a workspace sized
   // for the default (before tuning) fits every width the tuner may record
   const int cap = needs_ws(o) ? default_chunk(g.n, 1 << 30, real_bytes_of(o), true) : (1 << 30);
-  // layouts to try: the caller's fixed one, else both where the plane sweeps exist
+  // layouts to try: the caller's fixed one, else the per-axis sweeps and the fused layout of
+  // the size (plane or split) where it exists
   const int form = form_of(g, o);
   int layouts[2] = {DPM_SWEEPS_AXIS, DPM_SWEEPS_PLANE};
   int nl = 1;
-  if (o.sweeps != DPM_SWEEPS_AUTO) layouts[0] = o.sweeps;
-  else if (form == FORM_FFT && xy_fusion_supported(g.n)) nl = 2;
+  if (o.sweeps != DPM_SWEEPS_AUTO) {
+    layouts[0] = o.sweeps;
+  } else if (form == FORM_FFT && xy_fusion_supported(g.n)) {
+    nl = 2;
+  } else if (form == FORM_FFT && split_size_supported(g.n) && split_opts(o)) {
+    layouts[1] = DPM_SWEEPS_SPLIT;
+    nl = 2;
+  }
   // the recorded pair (if any) stays in force until the new one replaces it: the timed solves
   // below fix their width and layout explicitly, and concurrent solves keep the old one meanwhile
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -475,7 +561,7 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
       dpm_opts ow = o;
       ow.rhs_chunk = w;
       ow.sweeps = layouts[li];
-      if (workspace_for_chunk(g, nrhs, ow, w) > o.workspace_bytes) continue;
+      if (workspace_for_layout(g, nrhs, ow, w, layout_of(g, ow, form)) > o.workspace_bytes) continue;
       double t = 0.0;
       st = time_solve(ow, 0, &t);
       if (st != DPM_OK) break;
@@ -492,8 +578,10 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
     }
   }
   // the z pass's columns per block (FFT and Bluestein forms), at the winning width and layout;
-  // the default (0) stays unless a column count is strictly faster
-  if (st == DPM_OK && w_best > 0 && (form == FORM_FFT || form == FORM_BLUE)) {
+  // the default (0) stays unless a column count is strictly faster (the split layout has no
+  // z pass)
+  if (st == DPM_OK && w_best > 0 && (form == FORM_FFT || form == FORM_BLUE) &&
+      l_best != DPM_SWEEPS_SPLIT) {
     dpm_opts ow = o;
     ow.rhs_chunk = w_best;
     ow.sweeps = l_best;

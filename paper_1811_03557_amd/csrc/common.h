@@ -119,6 +119,16 @@ bool z_tri_cols_valid(int n, int cols);
 dpm_status launch_z_tri(int real_bytes, int n, const PassArgs& a, double fscale, int nrhs,
                         hipStream_t s, int cols = 0);
 
+// Split layout of the FFT-form solve (n = 255, 511; plain solves): the z solve cut into the
+// segment-local elimination fused with the forward x transforms (phase 0), the separators'
+// reduced system (phase 1, written to zside: split_side_values(n) reals per right-hand side)
+// and the reconstruction fused with the inverse x transforms (phase 2), in place on the volume
+// the forward y sweep left; fscale as for launch_z_tri.
+bool split_size_supported(int n);
+size_t split_side_values(int n);
+dpm_status launch_split_pass(int real_bytes, int n, int phase, const PassArgs& a, void* zside,
+                             double fscale, int nrhs, hipStream_t s);
+
 // Bluestein DST-I sweep (FP64, n + 1 not a power of two; plain solve kinds only).
 dpm_status launch_blue_pass(int n, AxisKind ax, bool zpass, const PassArgs& a, const Plan* pl,
                             int nrhs, hipStream_t s);
@@ -134,7 +144,8 @@ dpm_status launch_f64mm_pass(int n, AxisKind ax, bool zpass, const PassArgs& a, 
 // ---------------------------------------------------------------- measurement support
 // Sweep kinds reported by dpm_timing_end.
 enum SweepKind { SW_X_FIRST = 0, SW_Y = 1, SW_Z = 2, SW_X_LAST = 3, SW_X_RESID = 4, SW_X_UPD = 5,
-                 SW_XY_FWD = 6, SW_XY_INV = 7, SW_KINDS = 8 };
+                 SW_XY_FWD = 6, SW_XY_INV = 7, SW_XZ_FWD = 8, SW_Z_SEP = 9, SW_XZ_INV = 10,
+                 SW_KINDS = 11 };
 bool timing_enabled();
 bool timing_on(int rhs0, int nb);
 void timing_before(hipStream_t s);

@@ -48,9 +48,33 @@ def test_host_validation_without_device():
     # FP32 I/O only without refinement
     o2 = _lib.Opts(_lib.DPM_FP32, 0, 1e-10, 2, 0, None, 0)
     assert lib.dpm_workspace_size(C.byref(g), 1, C.byref(o2), C.byref(nb)) == _lib.DPM_EINVAL
-    # plain FP64 needs no volume workspace; FP32 + FP64 I/O needs one FP32 volume per chunk
+    # plain FP64 needs no volume workspace in the per-axis layout (the library's choice at
+    # 255), and the separator planes of a launch in the split layout (its choice at 511: 31
+    # planes of 511^2 reals per right-hand side); FP32 + FP64 I/O needs one FP32 volume per chunk
     assert lib.dpm_workspace_size(C.byref(g), 1, C.byref(o), C.byref(nb)) == _lib.DPM_OK
     assert nb.value < 4096
+    osp = _lib.Opts(_lib.DPM_FP64, 1, 1e-10, 0, 0, None, 0, _lib.DPM_SWEEPS_SPLIT)
+    assert lib.dpm_workspace_size(C.byref(g), 1, C.byref(osp), C.byref(nb)) == _lib.DPM_OK
+    assert 15 * 255**2 * 8 <= nb.value < 15 * 255**2 * 8 + 4096
+    assert lib.dpm_workspace_size(C.byref(g), 64, C.byref(osp), C.byref(nb)) == _lib.DPM_OK
+    assert 2 * 15 * 255**2 * 8 <= nb.value < 2 * 15 * 255**2 * 8 + 8192
+    g511 = _lib.Grid(511, 3.0 / 512, 1.0, 0.0)
+    assert lib.dpm_workspace_size(C.byref(g511), 1, C.byref(o), C.byref(nb)) == _lib.DPM_OK
+    assert 31 * 511**2 * 8 <= nb.value < 31 * 511**2 * 8 + 4096
+    oax = _lib.Opts(_lib.DPM_FP64, 1, 1e-10, 0, 0, None, 0, _lib.DPM_SWEEPS_AXIS)
+    assert lib.dpm_workspace_size(C.byref(g511), 1, C.byref(oax), C.byref(nb)) == _lib.DPM_OK
+    assert nb.value < 4096
+    # the split layout: plain solves at n = 255, 511 only
+    g127s = _lib.Grid(127, 3.0 / 128, 1.0, 0.0)
+    assert lib.dpm_workspace_size(C.byref(g127s), 1, C.byref(osp), C.byref(nb)) == _lib.DPM_EINVAL
+    assert "DPM_SWEEPS_SPLIT" in lib.dpm_last_error().decode()
+    for bad in (_lib.Opts(_lib.DPM_FP64, 1, 1e-10, 2, 0, None, 0, _lib.DPM_SWEEPS_SPLIT),
+                _lib.Opts(_lib.DPM_FP32, 1, 1e-10, 2, 0, None, 0, _lib.DPM_SWEEPS_SPLIT),
+                _lib.Opts(_lib.DPM_BF16X3, 1, 1e-10, 2, 0, None, 0, _lib.DPM_SWEEPS_SPLIT)):
+        assert lib.dpm_workspace_size(C.byref(g), 1, C.byref(bad), C.byref(nb)) == _lib.DPM_EINVAL
+    of32 = _lib.Opts(_lib.DPM_FP32, 0, 1e-10, 0, 0, None, 0, _lib.DPM_SWEEPS_SPLIT)
+    assert lib.dpm_workspace_size(C.byref(g), 1, C.byref(of32), C.byref(nb)) == _lib.DPM_OK
+    assert nb.value >= 15 * 255**2 * 4
     o3 = _lib.Opts(_lib.DPM_FP32, 1, 1e-10, 2, 1, None, 0)
     assert lib.dpm_workspace_size(C.byref(g), 4, C.byref(o3), C.byref(nb)) == _lib.DPM_OK
     assert nb.value >= 255**3 * 4
