@@ -29,12 +29,14 @@ __device__ __forceinline__ double minmod3(double a, double b, double c) {
   return 0.0;
 }
 
-// b2[0] = sigma 1_{M+} f_rho, b2[1] = sigma 1_{M+} f_c
+// b2[0] = sigma 1_{M+} f_rho, b2[1] = sigma 1_{M+} f_c.  With a stepper guard, the first
+// thread also advances the step number (guard[0]) that the step's restriction records.
 __global__ void k_pks_rhs(const double* __restrict__ rho, const double* __restrict__ c,
                           const uint8_t* __restrict__ mp, int n, double h, double dt, double chi,
-                          double sigma, double* __restrict__ b2) {
+                          double sigma, double* __restrict__ b2, int* __restrict__ guard) {
   const long long vsz = (long long)n * n * n;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (guard != nullptr && i == 0) guard[0] += 1;
   if (i >= vsz) return;
   if (!mp[i]) {
     b2[i] = 0.0;
@@ -121,16 +123,13 @@ __global__ void k_restrict(const double* __restrict__ U, const uint8_t* __restri
   }
 }
 
-// guard[0] = step number (from 1), guard[1] = first step with a non-finite output
+// guard[0] = step number (steps count from 1: each step's forcing kernel advances it first),
+// guard[1] = first step with a non-finite output
 __global__ void k_guard_init(int* guard) {
   if (threadIdx.x == 0) {
-    guard[0] = 1;
+    guard[0] = 0;
     guard[1] = INT_MAX;
   }
-}
-
-__global__ void k_guard_tick(int* guard) {
-  if (threadIdx.x == 0) guard[0] += 1;
 }
 
 // amp exp(-rate |x - x_c|^2) at M+ nodes; phase 1 overwrites gamma nodes with the value at
@@ -243,7 +242,7 @@ void launch_pks_rhs(const dpm_bep* b, const double* rho, const double* c, double
   const dpm_grid& g = b->grid;
   const long long vsz = (long long)g.n * g.n * g.n;
   hipLaunchKernelGGL(k_pks_rhs, dim3(grid1(vsz)), dim3(kB), 0, s, rho, c, b->m_plus, g.n, g.h,
-                     dt, chi, g.sigma, b2);
+                     dt, chi, g.sigma, b2, nullptr);
 }
 
 void launch_density(const dpm_bep* b, const double* C, int ldc, double* ug, hipStream_t s) {
@@ -294,7 +293,7 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   const double sigma = g.sigma;
   // Step 4a: right-hand sides and particular solutions
   hipLaunchKernelGGL(k_pks_rhs, dim3(grid1(vsz)), dim3(kB), 0, s, rho_in, c_in, b->m_plus, g.n,
-                     g.h, dt, chi, sigma, b2);
+                     g.h, dt, chi, sigma, b2, gd);
   DPM_TRY_HIP(hipGetLastError());
   DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, nullptr));
   // Step 5: Tr_gamma_in G f, least squares, densities
@@ -308,7 +307,6 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, info));
   hipLaunchKernelGGL(k_restrict, dim3(grid1(vsz)), dim3(kB), 0, s, X, b->n_plus, vsz, rho_out,
                      c_out, gd);
-  if (gd != nullptr) hipLaunchKernelGGL(k_guard_tick, dim3(1), dim3(64), 0, s, gd);
   DPM_TRY_HIP(hipGetLastError());
   return DPM_OK;
 }

@@ -112,10 +112,14 @@ void k_xy_pass(PassArgs p, int nblocks) {
           const double a5 = z < N - 1 ? u[ep + NN] : 0.0;
           v[k] = (T)(rb - (sig + 6.0 * p.inv_h2) * uc +
                      p.inv_h2 * ((a0 + a1) + (a2 + a3) + (a4 + a5)));
-        } else if constexpr (IN == IN_F64) {
-          v[k] = (T)(static_cast<const double*>(p.in) + wbase)[e];
         } else {
-          v[k] = (static_cast<const T*>(p.in) + wbase)[e];
+          // wave-uniform base of the step (clamped into the wavefront's rows), one 32-bit lane
+          // offset in [0, 63]
+          const int sk = min(64 * (c0 + k), cnt - 1);
+          if constexpr (IN == IN_F64)
+            v[k] = (T)ld(static_cast<const double*>(p.in) + wbase + sk, (unsigned)(e - sk) * 8u);
+          else
+            v[k] = ld(static_cast<const T*>(p.in) + wbase + sk, (unsigned)(e - sk) * (unsigned)sizeof(T));
         }
       }
 #pragma unroll
@@ -198,23 +202,27 @@ void k_xy_pass(PassArgs p, int nblocks) {
         const int e = min(lane + (c0 + k) * 64, cnt - 1);
         const int r = e / N;
         v[k] = wplane[r * P + (e - r * N) + 1];
-        if constexpr (OUT == OUT_UPD) old[k] = (static_cast<const double*>(p.out) + wbase)[e];
+        if constexpr (OUT == OUT_UPD) {
+          const int sk = min(64 * (c0 + k), cnt - 1);
+          old[k] = ld(static_cast<const double*>(p.out) + wbase + sk, (unsigned)(e - sk) * 8u);
+        }
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         if (c0 + k >= KMAX) break;
         const int e = lane + (c0 + k) * 64;
         if (e >= cnt) break;
+        const long long sb = wbase + 64 * (c0 + k);  // wave-uniform base of the step (e < cnt)
         if constexpr (OUT == OUT_UPD) {
           const double nu = old[k] + (double)v[k];
-          (static_cast<double*>(p.out) + wbase)[e] = nu;
+          st(static_cast<double*>(p.out) + sb, (unsigned)lane * 8u, nu);
           cm = fmax(cm, fabs((double)v[k]));
           um = fmax(um, fabs(nu));
         } else if constexpr (OUT == OUT_F64) {
-          (static_cast<double*>(p.out) + wbase)[e] = (double)v[k];
+          st(static_cast<double*>(p.out) + sb, (unsigned)lane * 8u, (double)v[k]);
           cm = fmax(cm, fabs((double)v[k]));
         } else {
-          (static_cast<T*>(p.out) + wbase)[e] = v[k];
+          st(static_cast<T*>(p.out) + sb, (unsigned)lane * (unsigned)sizeof(T), v[k]);
         }
       }
     }
