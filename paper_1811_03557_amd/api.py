@@ -157,8 +157,14 @@ def autotune(b: torch.Tensor, sigma: float, h: float, prec: str = "fp64", rtol: 
     if out is None:
         out = torch.empty_like(b)
     g = grid(n, h, sigma)
-    # a workspace for the widest candidate fits every narrower one
+    # a workspace for the widest candidate fits every narrower one, in every layout the size has
+    # (the split layout's separator planes included where it exists)
     nbytes = workspace_size(g, nrhs, opts(prec, io_fp64, rtol, max_refine, min(16, nrhs)))
+    try:
+        nbytes = max(nbytes, workspace_size(g, nrhs, opts(prec, io_fp64, rtol, max_refine,
+                                                          min(16, nrhs), "split")))
+    except L.DPMError:
+        pass
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=b.device)
     o = opts(prec, io_fp64, rtol, max_refine, 0, sweeps)
     o.workspace = C.c_void_p(ws.data_ptr())

@@ -1,5 +1,6 @@
 """The launch-shape autotuner (dpm_autotune) through the C ABI: it times every candidate width
-that fits, in both sweep layouts where the plane sweeps exist, then the z pass's columns per
+that fits, in both sweep layouts where a fused layout exists (plane at n <= 127, split at 255
+and 511), then the z pass's columns per
 block at the best pair, records the fastest shape, and later solves with rhs_chunk = 0
 (sweeps = auto) take it.  A solve's result depends neither on the width (each right-hand side's
 arithmetic is the same) nor on the z tile (each column's is), so solves at the tuned shape are
@@ -107,3 +108,43 @@ def test_solve_narrows_width_to_its_workspace():
     st = L.load().aux_solve_batched(C.byref(g), nrhs, C.c_void_p(bt.data_ptr()),
                                     C.c_void_p(u.data_ptr()), C.byref(o2), None, None)
     assert st == L.DPM_EINVAL
+
+
+def test_autotune_times_split_layout_255():
+    """At 255 the autotuner times every width in the per-axis and the split layouts (the z
+    tiles only when the per-axis layout wins: the split layout has no z pass), records the
+    fastest, and a later solve that leaves the layout to the library takes it: bitwise equal to
+    a solve with that layout fixed, and within the FP64 bar of the oracle."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    n, nrhs = 255, 4
+    h, _ = inp.grid(n)
+    sigma = 1.0
+    b = inp.rhs_normal(n, nrhs, seed=13)
+    bt = torch.from_numpy(b).to(dev)
+    say(f"autotune n={n} nrhs={nrhs} fp64 (per-axis and split layouts)")
+    api.autotune_reset()
+    try:
+        res = api.autotune(bt, sigma, h, prec="fp64", reps=2)
+        say(f"  widths {res['widths']}, layouts {res['sweeps']}, z columns {res['zcols']}, "
+            f"ms {[round(t, 3) for t in res['ms']]}, best {res['best']} {res['best_sweeps']} "
+            f"z {res['best_zcols']}")
+        k = int(np.argmin(res["ms"][:8]))
+        assert res["widths"][:8] == [1, 2, 3, 4] * 2
+        assert res["sweeps"][:8] == ["axis"] * 4 + ["split"] * 4
+        if res["sweeps"][k] == "split":
+            assert len(res["ms"]) == 8 and res["best_zcols"] == 0
+        else:
+            assert res["zcols"] == [0] * 8 + [16, 32, 64]
+        assert res["best"] == res["widths"][k] and res["best_sweeps"] == res["sweeps"][k]
+        u_auto = api.aux_solve_batched(bt, sigma, h, prec="fp64").cpu().numpy()
+        u_fixed = api.aux_solve_batched(bt, sigma, h, prec="fp64", rhs_chunk=res["best"],
+                                        sweeps=res["best_sweeps"]).cpu().numpy()
+        assert np.array_equal(u_auto, u_fixed)
+        ref = oaux.aux_solve(b[:2], sigma, h)
+        err = max(oaux.rel_err_inf(u_auto[i], ref[i]) for i in range(2))
+        say(f"  rel err vs oracle {err:.2e}")
+        assert err <= 1e-12
+    finally:
+        api.autotune_reset()
