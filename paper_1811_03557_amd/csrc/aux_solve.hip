@@ -287,8 +287,14 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
                               const void* src, OutKind out_kind, void* dst, void* ws,
                               const double* b, const double* u, const SolveFlags* fl, int rhs0,
                               int nb, bool gated, int form, const double* sig_rhs,
-                              hipStream_t s, int layout, int zcols, void* zside) {
+                              hipStream_t s, int layout, int zcols, void* zside,
+                              const RestrictOut* ro = nullptr) {
   PassArgs a{};
+  if (ro != nullptr) {
+    a.mask = ro->mask;
+    a.out1 = ro->out1;
+    a.guard = ro->guard;
+  }
   a.sigma_rhs = sig_rhs;
   a.tw = rb == 4 ? (const void*)pl->tw_f : (const void*)pl->tw_d;
   a.lam_hat = pl->lam;
@@ -375,9 +381,19 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
   return DPM_OK;
 }
 
+bool restrict_fusable(const dpm_grid& g, const dpm_opts& o) {
+  const int form = form_of(g, o);
+  return o.prec == DPM_FP64 && o.max_refine == 0 && form == FORM_FFT &&
+         layout_of(g, o, form) == DPM_SWEEPS_PLANE && rhs_chunk_of(g, 2, o) >= 2;
+}
+
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, const dpm_opts& o,
                           hipStream_t s, dpm_info* info, const double* sigma_host, bool no_alloc,
-                          int zcols) {
+                          int zcols, const RestrictOut* ro) {
+  if (ro != nullptr && !(nrhs == 2 && restrict_fusable(g, o))) {
+    set_error("fused restriction: needs a plain FP64 plane-sweep solve of two right-hand sides");
+    return DPM_EINVAL;
+  }
   const Plan* pl = nullptr;
   DPM_TRY(no_alloc ? find_plan(g.n, &pl) : get_plan(g.n, &pl));
   const int rb = real_bytes_of(o);
@@ -420,9 +436,8 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
   const size_t vol = (size_t)g.n * g.n * g.n;
   const size_t io_bytes = o.io_fp64 ? 8 : 4;
   const bool refine = o.max_refine > 0;
-  // the flags serve the paths that track max-norms (FP64 iterate with workspace transforms)
-  const bool plain = (o.prec == DPM_FP64 && !refine) || (o.prec == DPM_FP32 && !o.io_fp64) ||
-                     o.prec == DPM_FP64_GEMM;
+  // the flags (max-norms, stop test) serve refinement only: without it a solve tracks nothing
+  const bool plain = !refine;
   if (!plain) {
     hipLaunchKernelGGL(k_flags_reset, dim3((nrhs + 255) / 256), dim3(256), 0, s, fl, nrhs);
     DPM_TRY_HIP(hipGetLastError());
@@ -434,9 +449,15 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
     char* uc = static_cast<char*>(u) + (size_t)c0 * vol * io_bytes;
     if ((o.prec == DPM_FP64 && !refine) || o.prec == DPM_FP64_GEMM) {
       // FP64 transforms in place in u: no workspace traffic beyond u itself
-      // (no max-norm tracking: only refinement uses it)
-      DPM_TRY(solve_sweeps(pl, 8, g, IN_WS, bc, OUT_F64, uc, uc, nullptr, nullptr, nullptr, c0, nb,
-                          false, form, sig_dev, s, layout, zcols, zside));
+      // (no max-norm tracking: only refinement uses it); with a fused restriction the last pass
+      // writes the masked solutions to the caller's two volumes instead
+      if (ro != nullptr && chunk < 2) {
+        set_error("fused restriction: both right-hand sides must share one launch");
+        return DPM_EINVAL;
+      }
+      DPM_TRY(solve_sweeps(pl, 8, g, IN_WS, bc, ro ? OUT_RESTRICT : OUT_F64, ro ? (void*)ro->out0 : uc,
+                          uc, nullptr, nullptr, nullptr, c0, nb, false, form, sig_dev, s, layout,
+                          zcols, zside, ro));
     } else if (o.prec == DPM_FP32 && !o.io_fp64) {
       DPM_TRY(solve_sweeps(pl, 4, g, IN_WS, bc, OUT_WS, uc, uc, nullptr, nullptr, nullptr, c0, nb,
                           false, form, sig_dev, s, layout, zcols, zside));
@@ -444,10 +465,13 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
       // reduced-precision (or FP64) transforms on the workspace, FP64 iterate in u
       const double* bd = reinterpret_cast<const double*>(bc);
       double* ud = reinterpret_cast<double*>(uc);
-      DPM_TRY(solve_sweeps(pl, rb, g, IN_F64, bc, OUT_F64, uc, vol_ws, nullptr, nullptr, &fl, c0,
-                          nb, false, form, sig_dev, s, layout, zcols, zside));
-      hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, 0, o.rtol);
-      DPM_TRY_HIP(hipGetLastError());
+      DPM_TRY(solve_sweeps(pl, rb, g, IN_F64, bc, OUT_F64, uc, vol_ws, nullptr, nullptr,
+                          refine ? &fl : nullptr, c0, nb, false, form, sig_dev, s, layout, zcols,
+                          zside));
+      if (refine) {
+        hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, 0, o.rtol);
+        DPM_TRY_HIP(hipGetLastError());
+      }
       for (int k = 1; k <= o.max_refine; ++k) {
         DPM_TRY(solve_sweeps(pl, rb, g, IN_RESID, nullptr, OUT_UPD, uc, vol_ws, bd, ud, &fl, c0,
                             nb, true, form, sig_dev, s, layout, zcols, zside));

@@ -80,7 +80,9 @@ bool dense_size_supported(int n);
 
 // ---------------------------------------------------------------- DST pass kernels
 enum InKind { IN_WS = 0, IN_F64 = 1, IN_RESID = 2 };
-enum OutKind { OUT_WS = 0, OUT_F64 = 1, OUT_UPD = 2 };
+// OUT_RESTRICT: FP64 output restricted to a mask, right-hand side 0 to `out`, 1 to `out1`
+// (the DPM step's restriction to N+, fused into the last plane sweep of its second solve)
+enum OutKind { OUT_WS = 0, OUT_F64 = 1, OUT_UPD = 2, OUT_RESTRICT = 3 };
 enum AxisKind { AX_X = 0, AX_Y = 1, AX_Z = 2 };
 
 struct PassArgs {
@@ -97,6 +99,10 @@ struct PassArgs {
   unsigned long long* cmax;  // per rhs: max |correction| (update/store passes, nullable)
   unsigned long long* umax;  // per rhs: max |u_new|
   int rhs0;                  // index of the chunk's first right-hand side in the batch
+  const uint8_t* mask;       // OUT_RESTRICT: N^3 mask (1 keeps the value, 0 writes zero)
+  double* out1;              // OUT_RESTRICT: output volume of right-hand side 1
+  int* guard;                // OUT_RESTRICT: stepper guard (nullable): a non-finite output
+                             // records guard[0] into guard[1] by atomic minimum
 };
 
 // Launch one sweep over `nrhs` consecutive volumes.  real_bytes = 4 (FP32) or 8 (FP64).
@@ -166,10 +172,20 @@ size_t flags_bytes(int nrhs);
 // containers; the caller passes the library's static scratch as the workspace.
 // zcols > 0: the z pass's columns per block (the autotuner's candidates), else the recorded
 // or default one.
+// The DPM step's restriction to N+ fused into the solve's last pass (out0/out1 receive the two
+// right-hand sides' solutions masked; u is then only the transform volume).  Only where
+// restrict_fusable holds: a plain FP64 solve of two right-hand sides in one plane-sweep launch.
+struct RestrictOut {
+  const uint8_t* mask;
+  double* out0;
+  double* out1;
+  int* guard;
+};
+bool restrict_fusable(const dpm_grid& g, const dpm_opts& o);
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u,
                           const dpm_opts& o, hipStream_t s, dpm_info* info,
                           const double* sigma_host = nullptr, bool no_alloc = false,
-                          int zcols = 0);
+                          int zcols = 0, const RestrictOut* ro = nullptr);
 // Device scratch of aux_solve_batched_noalloc: kStaticScratchBytes per device, owned by the
 // library for the life of the process (static_scratch.hip).  Returns its device address on the
 // current device, looked up once per device.

@@ -827,8 +827,15 @@ dpm_status dd_step_impl(const dpm_dd* d, double dt, double chi, const double* co
   for (int l = 0; l < 2; ++l) {
     minus_rhs(d->sub[l], ug[l], 0, 2, b2[l], st[l]);
     DPM_TRY_HIP(hipGetLastError());
-    DPM_TRY(aux_solve_impl(d->sub[l]->grid, 2, b2[l], X[l], so[l], st[l], nullptr));
-    launch_restrict(d->sub[l], X[l], out[2 * l], out[2 * l + 1], st[l]);
+    if (restrict_fusable(d->sub[l]->grid, so[l])) {
+      // the restriction to N+ in the solve's last pass
+      const RestrictOut ro{d->sub[l]->n_plus, out[2 * l], out[2 * l + 1], nullptr};
+      DPM_TRY(aux_solve_impl(d->sub[l]->grid, 2, b2[l], X[l], so[l], st[l], nullptr, nullptr,
+                             false, 0, &ro));
+    } else {
+      DPM_TRY(aux_solve_impl(d->sub[l]->grid, 2, b2[l], X[l], so[l], st[l], nullptr));
+      launch_restrict(d->sub[l], X[l], out[2 * l], out[2 * l + 1], st[l]);
+    }
     DPM_TRY_HIP(hipGetLastError());
   }
   DPM_TRY_HIP(hipEventRecord(d->ev[3], d->side));

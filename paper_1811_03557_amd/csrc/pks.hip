@@ -304,9 +304,16 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   // b2 holds sigma 1_{M+} f, zero on M-: add the M- part (sigma - Lap_h)[u_gamma] in place
   minus_rhs(b, ug, 0, 2, b2, s);
   DPM_TRY_HIP(hipGetLastError());
-  DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, info));
-  hipLaunchKernelGGL(k_restrict, dim3(grid1(vsz)), dim3(kB), 0, s, X, b->n_plus, vsz, rho_out,
-                     c_out, gd);
+  // restriction to N+ (and the stepper's finiteness guard): fused into the solve's last pass
+  // where it is a plain FP64 plane-sweep solve, else its own kernel
+  if (restrict_fusable(g, so)) {
+    const RestrictOut ro{b->n_plus, rho_out, c_out, gd};
+    DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, info, nullptr, false, 0, &ro));
+  } else {
+    DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, info));
+    hipLaunchKernelGGL(k_restrict, dim3(grid1(vsz)), dim3(kB), 0, s, X, b->n_plus, vsz, rho_out,
+                       c_out, gd);
+  }
   DPM_TRY_HIP(hipGetLastError());
   return DPM_OK;
 }

@@ -190,6 +190,10 @@ void k_xy_pass(PassArgs p, int nblocks) {
 
   // ------------------------------------------------------------------ store the rows
   double cm = 0.0, um = 0.0;
+  bool bad = false;  // OUT_RESTRICT: a non-finite output in this thread
+  // OUT_RESTRICT: the right-hand side's own output volume, addressed within the plane
+  double* const rout = OUT == OUT_RESTRICT ? (rhs == 0 ? static_cast<double*>(p.out) : p.out1) : nullptr;
+  const long long lbase = (long long)z * NN + (long long)row0 * N;  // wavefront's rows, no rhs offset
   {
     constexpr int CH = 8;
 #pragma unroll
@@ -221,6 +225,11 @@ void k_xy_pass(PassArgs p, int nblocks) {
         } else if constexpr (OUT == OUT_F64) {
           st(static_cast<double*>(p.out) + sb, (unsigned)lane * 8u, (double)v[k]);
           cm = fmax(cm, fabs((double)v[k]));
+        } else if constexpr (OUT == OUT_RESTRICT) {
+          const long long rb = lbase + 64 * (c0 + k);
+          const double vr = p.mask[rb + lane] ? (double)v[k] : 0.0;
+          st(rout + rb, (unsigned)lane * 8u, vr);
+          bad |= !isfinite(vr);
         } else {
           st(static_cast<T*>(p.out) + sb, (unsigned)lane * (unsigned)sizeof(T), v[k]);
         }
@@ -228,7 +237,14 @@ void k_xy_pass(PassArgs p, int nblocks) {
     }
   }
 
-  if constexpr (OUT != OUT_WS) {
+  if constexpr (OUT == OUT_RESTRICT) {
+    // a non-finite output records the current step number (guard[0]) into guard[1]: one
+    // atomic per block that holds one, skipped once the step is recorded
+    if (p.guard != nullptr && __syncthreads_or(bad) && tid == 0) {
+      const int step = p.guard[0];
+      if (p.guard[1] > step) atomicMin(&p.guard[1], step);
+    }
+  } else if constexpr (OUT != OUT_WS) {
     if (p.cmax != nullptr) {
       if constexpr (OUT != OUT_UPD) um = cm;  // the first solve's correction is u itself
       // block max of cm, um -> one atomicMax each (max is order independent: deterministic)
@@ -272,7 +288,10 @@ dpm_status launch_xy_t(InKind in, OutKind out, const PassArgs& a, int nrhs, hipS
     else if (in == IN_RESID && out == OUT_WS) hipLaunchKernelGGL((k_xy_pass<T, LOGM, IN_RESID, OUT_WS>), grid, block, 0, s, a, nbi);
     else if (in == IN_WS && out == OUT_F64) hipLaunchKernelGGL((k_xy_pass<T, LOGM, IN_WS, OUT_F64>), grid, block, 0, s, a, nbi);
     else if (in == IN_WS && out == OUT_UPD) hipLaunchKernelGGL((k_xy_pass<T, LOGM, IN_WS, OUT_UPD>), grid, block, 0, s, a, nbi);
-    else { set_error("unsupported plane sweep kind (%d,%d)", (int)in, (int)out); return DPM_EINVAL; }
+    else if (sizeof(T) == 8 && in == IN_WS && out == OUT_RESTRICT) {
+      if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL((k_xy_pass<T, LOGM, IN_WS, OUT_RESTRICT>), grid, block, 0, s, a, nbi);
+    } else { set_error("unsupported plane sweep kind (%d,%d)", (int)in, (int)out); return DPM_EINVAL; }
     DPM_TRY_HIP(hipGetLastError());
     return DPM_OK;
   }
