@@ -288,12 +288,18 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
                               const double* b, const double* u, const SolveFlags* fl, int rhs0,
                               int nb, bool gated, int form, const double* sig_rhs,
                               hipStream_t s, int layout, int zcols, void* zside,
-                              const RestrictOut* ro = nullptr) {
+                              const RestrictOut* ro = nullptr, const TraceOut* to = nullptr) {
   PassArgs a{};
   if (ro != nullptr) {
     a.mask = ro->mask;
     a.out1 = ro->out1;
     a.guard = ro->guard;
+  }
+  if (to != nullptr) {
+    a.tr_idx = to->idx;
+    a.tr_zoff = to->zoff;
+    a.tr_out = to->out;
+    a.tr_m = to->m;
   }
   a.sigma_rhs = sig_rhs;
   a.tw = rb == 4 ? (const void*)pl->tw_f : (const void*)pl->tw_d;
@@ -383,15 +389,20 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
 
 bool restrict_fusable(const dpm_grid& g, const dpm_opts& o) {
   const int form = form_of(g, o);
-  return o.prec == DPM_FP64 && o.max_refine == 0 && form == FORM_FFT &&
-         layout_of(g, o, form) == DPM_SWEEPS_PLANE && rhs_chunk_of(g, 2, o) >= 2;
+  return (o.prec == DPM_FP64 || (o.prec == DPM_FP32 && o.io_fp64)) && o.max_refine == 0 &&
+         form == FORM_FFT && layout_of(g, o, form) == DPM_SWEEPS_PLANE && rhs_chunk_of(g, 2, o) >= 2;
 }
 
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, const dpm_opts& o,
                           hipStream_t s, dpm_info* info, const double* sigma_host, bool no_alloc,
-                          int zcols, const RestrictOut* ro) {
-  if (ro != nullptr && !(nrhs == 2 && restrict_fusable(g, o))) {
-    set_error("fused restriction: needs a plain FP64 plane-sweep solve of two right-hand sides");
+                          int zcols, const RestrictOut* ro, const TraceOut* to) {
+  if ((ro != nullptr || to != nullptr) && !(nrhs == 2 && restrict_fusable(g, o))) {
+    set_error("fused restriction or traces: need an unrefined plane-sweep solve of two "
+              "right-hand sides");
+    return DPM_EINVAL;
+  }
+  if (ro != nullptr && to != nullptr) {
+    set_error("fused restriction and traces in one solve");
     return DPM_EINVAL;
   }
   const Plan* pl = nullptr;
@@ -451,13 +462,13 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
       // FP64 transforms in place in u: no workspace traffic beyond u itself
       // (no max-norm tracking: only refinement uses it); with a fused restriction the last pass
       // writes the masked solutions to the caller's two volumes instead
-      if (ro != nullptr && chunk < 2) {
-        set_error("fused restriction: both right-hand sides must share one launch");
+      if ((ro != nullptr || to != nullptr) && chunk < 2) {
+        set_error("fused restriction or traces: both right-hand sides must share one launch");
         return DPM_EINVAL;
       }
-      DPM_TRY(solve_sweeps(pl, 8, g, IN_WS, bc, ro ? OUT_RESTRICT : OUT_F64, ro ? (void*)ro->out0 : uc,
+      DPM_TRY(solve_sweeps(pl, 8, g, IN_WS, bc, ro ? OUT_RESTRICT : to ? OUT_TRACE : OUT_F64, ro ? (void*)ro->out0 : uc,
                           uc, nullptr, nullptr, nullptr, c0, nb, false, form, sig_dev, s, layout,
-                          zcols, zside, ro));
+                          zcols, zside, ro, to));
     } else if (o.prec == DPM_FP32 && !o.io_fp64) {
       DPM_TRY(solve_sweeps(pl, 4, g, IN_WS, bc, OUT_WS, uc, uc, nullptr, nullptr, nullptr, c0, nb,
                           false, form, sig_dev, s, layout, zcols, zside));
@@ -465,9 +476,14 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
       // reduced-precision (or FP64) transforms on the workspace, FP64 iterate in u
       const double* bd = reinterpret_cast<const double*>(bc);
       double* ud = reinterpret_cast<double*>(uc);
-      DPM_TRY(solve_sweeps(pl, rb, g, IN_F64, bc, OUT_F64, uc, vol_ws, nullptr, nullptr,
+      if ((ro != nullptr || to != nullptr) && chunk < 2) {
+        set_error("fused restriction or traces: both right-hand sides must share one launch");
+        return DPM_EINVAL;
+      }
+      DPM_TRY(solve_sweeps(pl, rb, g, IN_F64, bc, ro ? OUT_RESTRICT : to ? OUT_TRACE : OUT_F64,
+                          ro ? (void*)ro->out0 : uc, vol_ws, nullptr, nullptr,
                           refine ? &fl : nullptr, c0, nb, false, form, sig_dev, s, layout, zcols,
-                          zside));
+                          zside, ro, to));
       if (refine) {
         hipLaunchKernelGGL(k_flags_check, dim3((nb + 255) / 256), dim3(256), 0, s, fl, c0, nb, 0, o.rtol);
         DPM_TRY_HIP(hipGetLastError());

@@ -13,6 +13,7 @@ struct dpm_bep {
   uint8_t* is_in = nullptr;   // gamma_in flags
   int32_t* idx_in = nullptr;  // linear indices of gamma_in (rows of A)
   int32_t* pos_in = nullptr;  // position of each gamma_in node inside the gamma list
+  int32_t* in_zoff = nullptr; // n + 1: first gamma_in row of each z-plane (idx_in ascends)
   double* basis = nullptr;    // n_basis x n_gamma densities (row nu contiguous)
   double* A = nullptr;        // n_in x n_basis, column-major: Q^T, or Householder vectors below R
   double* tau = nullptr;      // n_basis reflector scalars

@@ -758,6 +758,7 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
       !al((void**)&b->idx, sizeof(int32_t) * ng) || !al((void**)&b->is_in, ng) ||
       !al((void**)&b->idx_in, sizeof(int32_t) * nin) ||
       !al((void**)&b->pos_in, sizeof(int32_t) * nin) ||
+      !al((void**)&b->in_zoff, sizeof(int32_t) * (g.n + 1)) ||
       !al((void**)&b->basis, sizeof(double) * (size_t)n_basis * ng) ||
       !al((void**)&b->A, sizeof(double) * (size_t)n_basis * nin) ||
       !al((void**)&b->tau, sizeof(double) * n_basis) ||
@@ -786,6 +787,22 @@ dpm_status build_bep_impl(const dpm_grid& g, const uint8_t* m_plus, int n_basis,
     }
     int r = 0;
     for (int i = 0; i < ng; ++i) { rk[i] = r; r += fl[i]; }
+    // first gamma_in row of each z-plane (the lists ascend in linear index)
+    {
+      std::vector<int32_t> ix(ng), zo(g.n + 1, 0);
+      if (hipMemcpy(ix.data(), b->idx, sizeof(int32_t) * ng, hipMemcpyDeviceToHost) != hipSuccess) {
+        set_error("dpm_build_boundary_matrix: copy failed");
+        return fail(DPM_EHIP);
+      }
+      const long long nn = (long long)g.n * g.n;
+      for (int i = 0; i < ng; ++i)
+        if (fl[i]) ++zo[(int)(ix[i] / nn) + 1];
+      for (int z = 0; z < g.n; ++z) zo[z + 1] += zo[z];
+      if (hipMemcpy(b->in_zoff, zo.data(), sizeof(int32_t) * (g.n + 1), hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("dpm_build_boundary_matrix: copy failed");
+        return fail(DPM_EHIP);
+      }
+    }
     int32_t* drk = nullptr;
     if (hipMalloc(&drk, sizeof(int32_t) * ng) != hipSuccess) {
       set_error("dpm_build_boundary_matrix: device allocation failed");
@@ -848,6 +865,7 @@ void destroy_bep(dpm_bep* b) {
   (void)hipFree(b->is_in);
   (void)hipFree(b->idx_in);
   (void)hipFree(b->pos_in);
+  (void)hipFree(b->in_zoff);
   (void)hipFree(b->basis);
   (void)hipFree(b->A);
   (void)hipFree(b->tau);

@@ -81,8 +81,10 @@ bool dense_size_supported(int n);
 // ---------------------------------------------------------------- DST pass kernels
 enum InKind { IN_WS = 0, IN_F64 = 1, IN_RESID = 2 };
 // OUT_RESTRICT: FP64 output restricted to a mask, right-hand side 0 to `out`, 1 to `out1`
-// (the DPM step's restriction to N+, fused into the last plane sweep of its second solve)
-enum OutKind { OUT_WS = 0, OUT_F64 = 1, OUT_UPD = 2, OUT_RESTRICT = 3 };
+// (the DPM step's restriction to N+, fused into the last plane sweep of its second solve);
+// OUT_TRACE: FP64 output and the values at listed nodes (the step's traces on gamma_in, from the
+// last plane sweep of its first solve)
+enum OutKind { OUT_WS = 0, OUT_F64 = 1, OUT_UPD = 2, OUT_RESTRICT = 3, OUT_TRACE = 4 };
 enum AxisKind { AX_X = 0, AX_Y = 1, AX_Z = 2 };
 
 struct PassArgs {
@@ -103,6 +105,12 @@ struct PassArgs {
   double* out1;              // OUT_RESTRICT: output volume of right-hand side 1
   int* guard;                // OUT_RESTRICT: stepper guard (nullable): a non-finite output
                              // records guard[0] into guard[1] by atomic minimum
+  // OUT_TRACE: the solution at listed nodes as well:
+  // tr_out[r tr_m + i] = u_r[tr_idx[i]], the nodes of z-plane z being i in [tr_zoff[z], tr_zoff[z+1])
+  const int32_t* tr_idx;
+  const int32_t* tr_zoff;
+  double* tr_out;
+  int tr_m;
 };
 
 // Launch one sweep over `nrhs` consecutive volumes.  real_bytes = 4 (FP32) or 8 (FP64).
@@ -173,8 +181,9 @@ size_t flags_bytes(int nrhs);
 // zcols > 0: the z pass's columns per block (the autotuner's candidates), else the recorded
 // or default one.
 // The DPM step's restriction to N+ fused into the solve's last pass (out0/out1 receive the two
-// right-hand sides' solutions masked; u is then only the transform volume).  Only where
-// restrict_fusable holds: a plain FP64 solve of two right-hand sides in one plane-sweep launch.
+// right-hand sides' solutions masked; u is not written).  Only where restrict_fusable holds: an
+// FP64, or FP32-transform with FP64 I/O, solve without refinement of two right-hand sides in
+// one plane-sweep launch.
 struct RestrictOut {
   const uint8_t* mask;
   double* out0;
@@ -182,10 +191,20 @@ struct RestrictOut {
   int* guard;
 };
 bool restrict_fusable(const dpm_grid& g, const dpm_opts& o);
+// The solution's values at listed nodes (the DPM step's traces on gamma_in) written by the last
+// pass of a solve as well, under the same conditions: out[r m + i] = u_r[idx[i]], idx ascending
+// in linear index with zoff[z] the first entry in z-plane z.
+struct TraceOut {
+  const int32_t* idx;
+  const int32_t* zoff;
+  double* out;
+  int m;
+};
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u,
                           const dpm_opts& o, hipStream_t s, dpm_info* info,
                           const double* sigma_host = nullptr, bool no_alloc = false,
-                          int zcols = 0, const RestrictOut* ro = nullptr);
+                          int zcols = 0, const RestrictOut* ro = nullptr,
+                          const TraceOut* to = nullptr);
 // Device scratch of aux_solve_batched_noalloc: kStaticScratchBytes per device, owned by the
 // library for the life of the process (static_scratch.hip).  Returns its device address on the
 // current device, looked up once per device.

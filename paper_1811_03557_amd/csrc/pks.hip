@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void k_cfl_scan(const double* __restrict__ rho
 unsigned grid1(long long n) { return (unsigned)((n + kB - 1) / kB); }
 
 struct StepLayout {
-  size_t b2, X, C, ug, guard, solve_ws, total;
+  size_t b2, X, C, ug, guard, tr, solve_ws, total;
 };
 
 StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
@@ -230,6 +230,7 @@ StepLayout step_layout(const dpm_bep* b, size_t solve_ws) {
   L.C = o; o = align_up(o + 2 * sizeof(double) * b->n_basis, 256);
   L.ug = o; o = align_up(o + 2 * sizeof(double) * b->n_gamma, 256);
   L.guard = o; o = align_up(o + 2 * sizeof(int), 256);
+  L.tr = o; o = align_up(o + 2 * sizeof(double) * b->n_in, 256);
   L.solve_ws = o; o = align_up(o + solve_ws, 256);
   L.total = o;
   return L;
@@ -295,9 +296,18 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   hipLaunchKernelGGL(k_pks_rhs, dim3(grid1(vsz)), dim3(kB), 0, s, rho_in, c_in, b->m_plus, g.n,
                      g.h, dt, chi, sigma, b2, gd);
   DPM_TRY_HIP(hipGetLastError());
-  DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, nullptr));
-  // Step 5: Tr_gamma_in G f, least squares, densities
-  qr_solve_traces(b, 2, X, vsz, C, s);
+  // Step 5: Tr_gamma_in G f (written by the solve's last pass where it fuses, else gathered from
+  // the solutions), least squares, densities
+  const bool fuse = restrict_fusable(g, so);
+  if (fuse) {
+    double* tr = reinterpret_cast<double*>(ws + L.tr);
+    const TraceOut to{b->idx_in, b->in_zoff, tr, b->n_in};
+    DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, nullptr, nullptr, false, 0, nullptr, &to));
+    qr_solve(b, 2, tr, C, s);
+  } else {
+    DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, nullptr));
+    qr_solve_traces(b, 2, X, vsz, C, s);
+  }
   hipLaunchKernelGGL(k_density, dim3(grid1(b->n_gamma)), dim3(kB), 0, s, b->basis, C,
                      b->n_basis, b->n_basis, b->n_gamma, ug);
   // Steps 6-7: Green's formula as one AP solve per species
@@ -306,7 +316,7 @@ dpm_status step_enqueue(const dpm_bep* b, double dt, double chi, const double* r
   DPM_TRY_HIP(hipGetLastError());
   // restriction to N+ (and the stepper's finiteness guard): fused into the solve's last pass
   // where it is a plain FP64 plane-sweep solve, else its own kernel
-  if (restrict_fusable(g, so)) {
+  if (fuse) {
     const RestrictOut ro{b->n_plus, rho_out, c_out, gd};
     DPM_TRY(aux_solve_impl(g, 2, b2, X, so, s, info, nullptr, false, 0, &ro));
   } else {

@@ -222,7 +222,7 @@ void k_xy_pass(PassArgs p, int nblocks) {
           st(static_cast<double*>(p.out) + sb, (unsigned)lane * 8u, nu);
           cm = fmax(cm, fabs((double)v[k]));
           um = fmax(um, fabs(nu));
-        } else if constexpr (OUT == OUT_F64) {
+        } else if constexpr (OUT == OUT_F64 || OUT == OUT_TRACE) {
           st(static_cast<double*>(p.out) + sb, (unsigned)lane * 8u, (double)v[k]);
           cm = fmax(cm, fabs((double)v[k]));
         } else if constexpr (OUT == OUT_RESTRICT) {
@@ -237,6 +237,19 @@ void k_xy_pass(PassArgs p, int nblocks) {
     }
   }
 
+  if constexpr (OUT == OUT_TRACE) {
+    {
+      // the solution at the listed nodes of this plane: every wavefront's final rows sit in LDS
+      // once all have passed the barrier
+      __syncthreads();
+      const int i1 = p.tr_zoff[z + 1];
+      for (int i = p.tr_zoff[z] + tid; i < i1; i += TH) {
+        const int ep = p.tr_idx[i] - z * NN;
+        const int y = ep / N;
+        p.tr_out[(long long)(p.rhs0 + rhs) * p.tr_m + i] = (double)plane[y * P + (ep - y * N) + 1];
+      }
+    }
+  }
   if constexpr (OUT == OUT_RESTRICT) {
     // a non-finite output records the current step number (guard[0]) into guard[1]: one
     // atomic per block that holds one, skipped once the step is recorded
@@ -244,7 +257,7 @@ void k_xy_pass(PassArgs p, int nblocks) {
       const int step = p.guard[0];
       if (p.guard[1] > step) atomicMin(&p.guard[1], step);
     }
-  } else if constexpr (OUT != OUT_WS) {
+  } else if constexpr (OUT != OUT_WS && OUT != OUT_TRACE) {
     if (p.cmax != nullptr) {
       if constexpr (OUT != OUT_UPD) um = cm;  // the first solve's correction is u itself
       // block max of cm, um -> one atomicMax each (max is order independent: deterministic)
@@ -288,10 +301,9 @@ dpm_status launch_xy_t(InKind in, OutKind out, const PassArgs& a, int nrhs, hipS
     else if (in == IN_RESID && out == OUT_WS) hipLaunchKernelGGL((k_xy_pass<T, LOGM, IN_RESID, OUT_WS>), grid, block, 0, s, a, nbi);
     else if (in == IN_WS && out == OUT_F64) hipLaunchKernelGGL((k_xy_pass<T, LOGM, IN_WS, OUT_F64>), grid, block, 0, s, a, nbi);
     else if (in == IN_WS && out == OUT_UPD) hipLaunchKernelGGL((k_xy_pass<T, LOGM, IN_WS, OUT_UPD>), grid, block, 0, s, a, nbi);
-    else if (sizeof(T) == 8 && in == IN_WS && out == OUT_RESTRICT) {
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((k_xy_pass<T, LOGM, IN_WS, OUT_RESTRICT>), grid, block, 0, s, a, nbi);
-    } else { set_error("unsupported plane sweep kind (%d,%d)", (int)in, (int)out); return DPM_EINVAL; }
+    else if (in == IN_WS && out == OUT_RESTRICT) hipLaunchKernelGGL((k_xy_pass<T, LOGM, IN_WS, OUT_RESTRICT>), grid, block, 0, s, a, nbi);
+    else if (in == IN_WS && out == OUT_TRACE) hipLaunchKernelGGL((k_xy_pass<T, LOGM, IN_WS, OUT_TRACE>), grid, block, 0, s, a, nbi);
+    else { set_error("unsupported plane sweep kind (%d,%d)", (int)in, (int)out); return DPM_EINVAL; }
     DPM_TRY_HIP(hipGetLastError());
     return DPM_OK;
   }
