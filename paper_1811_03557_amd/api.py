@@ -657,10 +657,11 @@ def step_workspace_size(bep: BEP, o: L.Opts) -> int:
 def dpm_step(bep: BEP, dt: float, chi: float, rho: torch.Tensor, c: torch.Tensor,
              rho_out: torch.Tensor | None = None, c_out: torch.Tensor | None = None,
              prec: str = "fp64", rtol: float = 1e-10, max_refine: int = 0,
-             workspace: torch.Tensor | None = None, stream=None, info: bool = False):
+             workspace: torch.Tensor | None = None, stream=None, info: bool = False,
+             sweeps: str = "auto"):
     """Steps 4a-7 for (rho, c) on N+; returns (rho_new, c_new)."""
     lib = L.load()
-    o = opts(prec, True, rtol, max_refine)
+    o = opts(prec, True, rtol, max_refine, 0, sweeps)
     nbytes = step_workspace_size(bep, o)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=rho.device)

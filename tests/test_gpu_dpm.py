@@ -197,6 +197,35 @@ def test_dpm_step_parity(n, shape, prec):
     bep.close()
 
 
+@pytest.mark.parametrize("n,prec,tol", [(31, "fp64", 1e-12), (127, "fp64", 1e-12),
+                                         (31, "fp32", 1e-5), (127, "fp32", 1e-5)])
+def test_step_fused_and_separate_kernels_agree(n, prec, tol):
+    """Where a step's solves run on the plane sweeps unrefined, the traces on gamma_in and the
+    restriction to N+ come out of the solves' last passes; with the per-axis sweeps the traces
+    are gathered from the solution volumes and the restriction is its own kernel.  Both paths
+    give the same step to the precision's bar, and zero off N+."""
+    import torch
+    from paper_1811_03557_amd import api
+    dev = need_gpu()
+    say(f"fused vs separate step kernels n={n} {prec}")
+    h, _ = inp.grid(n)
+    dt = 0.5 * h * h
+    h, x0, mp, ps, Bref, bep, A, geo = _bep_case(n, "ellipsoid", 2, 1.0 / dt, dev, prec=prec)
+    z, y, x = inp.mesh(n)
+    r2 = x**2 + y**2 + z**2
+    rho = torch.from_numpy(np.where(ps.n_plus, 10 * np.exp(-4 * r2), 0.0)).to(dev)
+    c = torch.from_numpy(np.where(ps.n_plus, 5 * np.exp(-2 * r2), 0.0)).to(dev)
+    rf, cf = api.dpm_step(bep, dt, 1.0, rho, c, prec=prec)
+    ra, ca = api.dpm_step(bep, dt, 1.0, rho, c, prec=prec, sweeps="axis")
+    rf, cf, ra, ca = (t.cpu().numpy() for t in (rf, cf, ra, ca))
+    er = np.max(np.abs(rf - ra)) / np.max(np.abs(ra))
+    ec = np.max(np.abs(cf - ca)) / np.max(np.abs(ca))
+    say(f"  rel diff rho {er:.2e}, c {ec:.2e}")
+    assert er < tol and ec < tol
+    assert np.all(rf[~ps.n_plus] == 0) and np.all(cf[~ps.n_plus] == 0)
+    bep.close()
+
+
 def test_gauss_state():
     import torch
     from paper_1811_03557_amd import api
