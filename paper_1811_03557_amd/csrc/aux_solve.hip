@@ -396,7 +396,12 @@ bool restrict_fusable(const dpm_grid& g, const dpm_opts& o) {
 dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, const dpm_opts& o,
                           hipStream_t s, dpm_info* info, const double* sigma_host, bool no_alloc,
                           int zcols, const RestrictOut* ro, const TraceOut* to) {
-  if ((ro != nullptr || to != nullptr) && !(nrhs == 2 && restrict_fusable(g, o))) {
+  // a fused restriction or trace output is the caller's decision (restrict_fusable, which reads
+  // the recorded layout once): the solve then runs the plane sweeps without consulting the
+  // autotuner's table again, so a re-tune in between cannot change the layout under it
+  const bool fused_out = ro != nullptr || to != nullptr;
+  if (fused_out && !(nrhs == 2 && (o.prec == DPM_FP64 || (o.prec == DPM_FP32 && o.io_fp64)) &&
+                     o.max_refine == 0 && form_of(g, o) == FORM_FFT && xy_fusion_supported(g.n))) {
     set_error("fused restriction or traces: need an unrefined plane-sweep solve of two "
               "right-hand sides");
     return DPM_EINVAL;
@@ -409,7 +414,7 @@ dpm_status aux_solve_impl(const dpm_grid& g, int nrhs, const void* b, void* u, c
   DPM_TRY(no_alloc ? find_plan(g.n, &pl) : get_plan(g.n, &pl));
   const int rb = real_bytes_of(o);
   const int form = form_of(g, o);
-  int layout = layout_of(g, o, form);
+  int layout = fused_out ? DPM_SWEEPS_PLANE : layout_of(g, o, form);
   if (zcols <= 0) zcols = tuned_entry(g.n, o).zcols;
   const bool ws_needed = needs_ws(o);
   int chunk = solve_chunk(g, nrhs, o, layout);
