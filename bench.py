@@ -568,6 +568,68 @@ def run_autotune(args, b, h, dev):
     return out
 
 
+def run_layouts(args, dev):
+    """The per-axis and split sweep layouts side by side (plain solves at 255^3 and 511^3, FP64
+    and FP32 with FP32 I/O): ms per batch as the best of 3 event-timed batched solves after one
+    untimed, per-kind sweep times from the library's timing events, and the largest difference
+    between the two layouts' results relative to the per-axis result's max norm."""
+    import ctypes as C
+    import torch
+    import dpm_inputs as inp
+    from paper_1811_03557_amd import _lib, api
+    lib = _lib.load()
+    out = {"workload": "N(0,1) right-hand sides (torch generator, seed 0), sigma 1: 64 at 255^3, "
+                       "8 at 511^3; rhs per launch the library's default"}
+    nk = len(KIND_NAMES)
+    for n, nrhs in ((255, 64), (511, 8)):
+        h, _ = inp.grid(n)
+        for prec in ("fp64", "fp32"):
+            dt = torch.float64 if prec == "fp64" else torch.float32
+            b = torch.randn((nrhs, n, n, n), dtype=dt, device=dev,
+                            generator=torch.Generator(device=dev).manual_seed(0))
+            res, us = {}, {}
+            for sw in ("axis", "split"):
+                u = torch.empty_like(b)
+                g = api.grid(n, h, 1.0)
+                ws = torch.empty(max(api.workspace_size(g, nrhs, api.opts(prec, prec == "fp64",
+                                                                          sweeps=sw)), 1),
+                                 dtype=torch.uint8, device=dev)
+                run = lambda: api.aux_solve_batched(b, 1.0, h, prec=prec, out=u, workspace=ws,
+                                                    sweeps=sw)
+                run()
+                torch.cuda.synchronize()
+                best = None
+                for _ in range(3):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    run()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    t = e0.elapsed_time(e1)
+                    best = t if best is None or t < best else best
+                _lib.check(lib.dpm_timing_begin(4096, 1))
+                run()
+                torch.cuda.synchronize()
+                cnt = (C.c_int32 * nk)()
+                mean = (C.c_double * nk)()
+                _lib.check(lib.dpm_timing_end(nk, cnt, mean))
+                res[sw] = {"ms_per_batch": round(best, 3),
+                           "solves_per_s": round(nrhs / (best * 1e-3), 1),
+                           "sweep_us": {KIND_NAMES[k]: round(mean[k] * 1e3, 1)
+                                        for k in range(nk) if cnt[k] > 0}}
+                us[sw] = u[:1].double().clone()
+                del ws, u
+            res["max_rel_diff"] = float((us["axis"] - us["split"]).abs().max()
+                                        / us["axis"].abs().max())
+            out[f"{n}_{prec}"] = res
+            log(f"[bench] layouts {n}^3 x {nrhs} {prec}: axis {res['axis']['ms_per_batch']} ms, "
+                f"split {res['split']['ms_per_batch']} ms, max rel diff {res['max_rel_diff']:.1e}")
+            del b
+            torch.cuda.empty_cache()
+    return out
+
+
 def run_boundary_matrix(args, dev):
     """Step 2 of the method at 127^3: the 242-column reduced-BEP matrix of the unit sphere
     (real Y_lm, l <= 10, beta = 1), sigma = 2/h^2, built and QR-factored by one
@@ -627,6 +689,9 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run 3 plain device copies of this many bytes (calibrates the "
                          "HBM traffic counters against a kernel of known traffic)")
+    ap.add_argument("--layouts", action="store_true",
+                    help="after the measurements, time the per-axis and split sweep layouts at "
+                         "255^3 and 511^3 (plain FP64 and FP32 solves)")
     ap.add_argument("--autotune", action="store_true",
                     help="after the measurements, run the launch-width autotuner on the headline "
                          "batch (FP64) and report every candidate's time beside the default width")
@@ -843,6 +908,10 @@ def main():
     }
     if args.autotune:
         line["autotune"] = run_autotune(args, b, h, dev)
+    if args.layouts:
+        del b
+        torch.cuda.empty_cache()
+        line["layouts"] = run_layouts(args, dev)
     print(json.dumps(line), flush=True)
 
 
