@@ -334,6 +334,9 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
     if (tm) timing_after(s, kind);
     return st;
   };
+  // the caller's right-hand sides, read out of place by the first sweep, are streamed past the
+  // caches (FFT form)
+  const bool stream_first = form == FORM_FFT && src != ws;
   if (layout == DPM_SWEEPS_SPLIT) {
     // plain solves only: FP64 output is the transform type (FP32 output has FP32 transforms)
     if (in_kind == IN_F64 && rb == 8) in_kind = IN_WS;
@@ -354,7 +357,7 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
       if (tm) timing_after(s, kind);
       return st;
     };
-    DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, src, ws, false, false));
+    DPM_TRY(pass(AX_Y, false, stream_first ? IN_STREAM : IN_WS, OUT_WS, src, ws, false, false));
     DPM_TRY(split(0, SW_XZ_FWD));
     DPM_TRY(split(1, SW_Z_SEP));
     DPM_TRY(split(2, SW_XZ_INV));
@@ -379,7 +382,10 @@ static dpm_status solve_sweeps(const Plan* pl, int rb, const dpm_grid& g, InKind
     DPM_TRY(xy(IN_WS, out_kind, ws, dst, fl != nullptr, SW_XY_INV));
     return DPM_OK;
   }
-  DPM_TRY(pass(AX_X, false, in_kind, OUT_WS, src, ws, false, true));
+  InKind first_in = in_kind;
+  if (stream_first)
+    first_in = in_kind == IN_WS ? IN_STREAM : in_kind == IN_F64 ? IN_F64_STREAM : in_kind;
+  DPM_TRY(pass(AX_X, false, first_in, OUT_WS, src, ws, false, true));
   DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, ws, ws, false, false));
   DPM_TRY(pass(AX_Z, true, IN_WS, OUT_WS, ws, ws, false, false));
   DPM_TRY(pass(AX_Y, false, IN_WS, OUT_WS, ws, ws, false, false));

@@ -79,7 +79,13 @@ constexpr int kDenseMaxN = 543;
 bool dense_size_supported(int n);
 
 // ---------------------------------------------------------------- DST pass kernels
-enum InKind { IN_WS = 0, IN_F64 = 1, IN_RESID = 2 };
+// IN_STREAM / IN_F64_STREAM: IN_WS / IN_F64 for a first sweep that reads the caller's
+// right-hand sides out of place: they are read once, so non-temporal loads keep them from
+// displacing the launch's working volumes from the 256 MB Infinity Cache.  Used at n = 255,
+// where those volumes are about the cache's size (measured 3-5% faster solves); below, they fit
+// beside the input, and at 511 one volume exceeds the cache four times over and the plain loads
+// measure faster, so other sizes take the plain kinds.
+enum InKind { IN_WS = 0, IN_F64 = 1, IN_RESID = 2, IN_STREAM = 3, IN_F64_STREAM = 4 };
 // OUT_RESTRICT: FP64 output restricted to a mask, right-hand side 0 to `out`, 1 to `out1`
 // (the DPM step's restriction to N+, fused into the last plane sweep of its second solve);
 // OUT_TRACE: FP64 output and the values at listed nodes (the step's traces on gamma_in, from the

@@ -136,7 +136,8 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
           const double* __restrict__ ub = p.u + base + step;
           const double* __restrict__ bb = p.b + base + step;
           const int x = i < IFULL ? j0 + JPI * i : min(j0 + JPI * i, N - 1);
-          const double uc = ld(ub, off), rb = ld(bb, off);
+          const double uc = ld(ub, off);
+          const double rb = LOGM == 8 ? ld_nt(bb, off) : ld(bb, off);  // b: read once
           // neighbours move the (uniform) pointer, never the unsigned offset below zero
           const double a0 = x > 0 ? ld(ub - 1, off) : 0.0;
           const double a1 = x < N - 1 ? ld(ub + 1, off) : 0.0;
@@ -148,6 +149,10 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
                      p.inv_h2 * ((a0 + a1) + (a2 + a3) + (a4 + a5)));
         } else if constexpr (IN == IN_F64) {
           v[k] = (T)ld(in_d + step, off);
+        } else if constexpr (IN == IN_F64_STREAM) {
+          v[k] = (T)ld_nt(in_d + step, off);
+        } else if constexpr (IN == IN_STREAM) {
+          v[k] = ld_nt(in_t + step, off);
         } else {
           v[k] = ld(in_t + step, off);
         }
@@ -181,7 +186,7 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
             const int y = ln - z * N;
             const double* __restrict__ u = p.u + base;
             uc[k] = u[e];
-            rb[k] = p.b[base + e];
+            rb[k] = LOGM == 8 ? __builtin_nontemporal_load(p.b + base + e) : p.b[base + e];
             double a0 = x > 0 ? u[e - 1] : 0.0;
             double a1 = x < N - 1 ? u[e + 1] : 0.0;
             double a2 = y > 0 ? u[e - N] : 0.0;
@@ -199,6 +204,8 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
         for (int i = 0; i < CH; ++i) {
           const int e = min(tid + (c0 + i) * kBlock, cnt - 1);
           if constexpr (IN == IN_F64) v[i] = (T)in_d[e];
+          else if constexpr (IN == IN_F64_STREAM) v[i] = (T)__builtin_nontemporal_load(in_d + e);
+          else if constexpr (IN == IN_STREAM) v[i] = __builtin_nontemporal_load(in_t + e);
           else v[i] = in_t[e];
         }
       }
@@ -356,13 +363,30 @@ dpm_status launch_t(AxisKind ax, bool zpass, InKind in, OutKind out, const PassA
   if (ax == AX_X) {
     if (in == IN_WS && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_WS, OUT_WS>), grid, block, 0, s, a, ti, nbi);
     else if (in == IN_F64 && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_F64, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+    else if ((in == IN_STREAM || in == IN_F64_STREAM) && out == OUT_WS) {
+      // streamed kinds exist at n = 255 (launch_dst_pass maps other sizes to the plain kinds)
+      if constexpr (LOGM == 8) {
+        if (in == IN_STREAM) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_STREAM, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+        else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_F64_STREAM, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+        else { set_error("FP64 transforms read FP64 input as IN_STREAM"); return DPM_EINVAL; }
+      } else {
+        set_error("streamed input kind at n != 255");
+        return DPM_EINVAL;
+      }
+    }
     else if (in == IN_RESID && out == OUT_WS) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_RESID, OUT_WS>), grid, block, 0, s, a, ti, nbi);
     else if (in == IN_WS && out == OUT_F64) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_WS, OUT_F64>), grid, block, 0, s, a, ti, nbi);
     else if (in == IN_WS && out == OUT_UPD) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_X, IN_WS, OUT_UPD>), grid, block, 0, s, a, ti, nbi);
     else { set_error("unsupported x sweep kind (%d,%d)", (int)in, (int)out); return DPM_EINVAL; }
   } else {
-    if (in != IN_WS || out != OUT_WS) { set_error("unsupported y sweep kind"); return DPM_EINVAL; }
-    hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_Y, IN_WS, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+    if ((in != IN_WS && in != IN_STREAM) || out != OUT_WS) { set_error("unsupported y sweep kind"); return DPM_EINVAL; }
+    if (in == IN_WS) {
+      hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_Y, IN_WS, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+    } else {
+      // the split layout's first sweep
+      if constexpr (LOGM == 8) hipLaunchKernelGGL((k_dst_pass<T, LOGM, AX_Y, IN_STREAM, OUT_WS>), grid, block, 0, s, a, ti, nbi);
+      else { set_error("streamed input kind at n != 255"); return DPM_EINVAL; }
+    }
   }
   DPM_TRY_HIP(hipGetLastError());
   return DPM_OK;
@@ -389,9 +413,13 @@ dpm_status launch_size(int n, AxisKind ax, bool zpass, InKind in, OutKind out, c
 dpm_status launch_dst_pass(int real_bytes, int n, AxisKind ax, bool zpass, InKind in,
                            OutKind out, const PassArgs& a, int nrhs, hipStream_t s) {
   if (nrhs <= 0) return DPM_OK;
+  // streamed input at n = 255 only (the plain loads elsewhere)
+  if (n != 255 && in == IN_STREAM) in = IN_WS;
+  if (n != 255 && in == IN_F64_STREAM) in = IN_F64;
   if (real_bytes == 4) return launch_size<float>(n, ax, zpass, in, out, a, nrhs, s);
   // FP64 transforms: FP64 input is the native type
   if (in == IN_F64) in = IN_WS;
+  if (in == IN_F64_STREAM) in = IN_STREAM;
   return launch_size<double>(n, ax, zpass, in, out, a, nrhs, s);
 }
 

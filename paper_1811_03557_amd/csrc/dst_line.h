@@ -481,6 +481,12 @@ __device__ __forceinline__ T ld(const T* base, unsigned byte_off) {
   const DPM_GLOBAL char* b = (const DPM_GLOBAL char*)sbase(base);
   return *(const DPM_GLOBAL T*)(b + byte_off);
 }
+// The same load with the non-temporal hint: data read once, not to be kept in the caches.
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T* base, unsigned byte_off) {
+  const DPM_GLOBAL char* b = (const DPM_GLOBAL char*)sbase(base);
+  return __builtin_nontemporal_load((const DPM_GLOBAL T*)(b + byte_off));
+}
 template <typename T>
 __device__ __forceinline__ void st(T* base, unsigned byte_off, T v) {
   DPM_GLOBAL char* b = (DPM_GLOBAL char*)sbase(base);
