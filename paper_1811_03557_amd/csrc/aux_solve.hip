@@ -69,8 +69,7 @@ __global__ void k_flags_check(SolveFlags f, int rhs0, int nb, int k, double rtol
 // Right-hand sides per launch: the chunk's transform volumes total about the 256 MB Infinity
 // Cache (rounded to the nearest count; measured at 255^3: 2 FP64 or 4 FP32 volumes per launch
 // beat 1 and 3).
-int default_chunk(int n, int nrhs, int real_bytes, bool need_ws) {
-  (void)need_ws;
+static int default_chunk(int n, int nrhs, int real_bytes) {
   const double vol = (double)n * n * n * real_bytes;
   int c = (int)std::lround(256.0e6 / vol);
   if (c < 1) c = 1;
@@ -125,7 +124,7 @@ int rhs_chunk_of(const dpm_grid& g, int nrhs, const dpm_opts& o) {
   if (o.rhs_chunk > 0) return o.rhs_chunk < nrhs ? o.rhs_chunk : nrhs;
   const int t = tuned_width(g.n, o);
   if (t > 0) return t < nrhs ? t : nrhs;
-  return default_chunk(g.n, nrhs, real_bytes_of(o), needs_ws(o));
+  return default_chunk(g.n, nrhs, real_bytes_of(o));
 }
 
 dpm_status validate_grid(const dpm_grid* g) {
@@ -562,7 +561,7 @@ dpm_status autotune_impl(const dpm_grid& g, int nrhs, const dpm_opts& o, const v
   }
   // with a transform workspace, stay at or below the default width, so that a workspace sized
   // for the default (before tuning) fits every width the tuner may record
-  const int cap = needs_ws(o) ? default_chunk(g.n, 1 << 30, real_bytes_of(o), true) : (1 << 30);
+  const int cap = needs_ws(o) ? default_chunk(g.n, 1 << 30, real_bytes_of(o)) : (1 << 30);
   // layouts to try: the caller's fixed one, else the per-axis sweeps and the fused layout of
   // the size (plane or split) where it exists
   const int form = form_of(g, o);
