@@ -165,41 +165,60 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
         else tile[w * P + jl + 1] = v[k];
       }
     }
+  } else if constexpr (IN == IN_RESID) {
+    // FP64 residual into narrow reals along x: one line per wavefront at a time, lane l
+    // holding x = l + 64 s.  The line's base is uniform, so every load is the saddr form at
+    // the lane's 32-bit offset (512-byte runs) and the y and z neighbour tests are uniform; the
+    // x neighbours come from the adjacent lanes (across a step boundary from the previous or
+    // next step's end lane) instead of two more loads of the line.
+    constexpr int XS = (N + 63) / 64;                  // steps per line
+    constexpr int NWV = kBlock / 64;                   // wavefronts per block
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double a6 = sig + 6.0 * p.inv_h2;
+#pragma unroll 1
+    for (int wl0 = wv; wl0 < nlines; wl0 += NWV) {     // uniform in the wavefront
+      const int ln = line0 + wl0;
+      const int z = ln / N;
+      const int y = ln - z * N;
+      const double* __restrict__ ub = p.u + base + (long long)wl0 * N;
+      const double* __restrict__ bb = p.b + base + (long long)wl0 * N;
+      double uc[XS], rb[XS], ys[XS], zs[XS];
+#pragma unroll
+      for (int s2 = 0; s2 < XS; ++s2) {
+        const int x = min(lane + 64 * s2, N - 1);       // the last step's spare lanes reload
+        const unsigned off = (unsigned)x * 8u;
+        uc[s2] = ld(ub, off);
+        rb[s2] = LOGM == 8 ? ld_nt(bb, off) : ld(bb, off);  // b: read once
+        // neighbours move the (uniform) pointer, never the unsigned offset below zero
+        const double a2 = y > 0 ? ld(ub - N, off) : 0.0;
+        const double a3 = y < N - 1 ? ld(ub + N, off) : 0.0;
+        const double a4 = z > 0 ? ld(ub - (long long)N * N, off) : 0.0;
+        const double a5 = z < N - 1 ? ld(ub + (long long)N * N, off) : 0.0;
+        ys[s2] = a2 + a3;
+        zs[s2] = a4 + a5;
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < XS; ++s2) {
+        const int x = lane + 64 * s2;
+        const double lm = __shfl_up(uc[s2], 1);         // lane - 1 (lane 0 keeps its own)
+        const double lp = __shfl_down(uc[s2], 1);       // lane + 1 (lane 63 keeps its own)
+        const double prev = s2 > 0 ? lane_value(uc[s2 > 0 ? s2 - 1 : 0], 63) : 0.0;
+        const double next = s2 < XS - 1 ? lane_value(uc[s2 < XS - 1 ? s2 + 1 : 0], 0) : 0.0;
+        const double a0 = x == 0 ? 0.0 : (lane == 0 ? prev : lm);
+        const double a1 = x >= N - 1 ? 0.0 : (lane == 63 ? next : lp);
+        // the stencil's sum in the order (x pair) + (y pair) + (z pair)
+        const double r = rb[s2] - a6 * uc[s2] + p.inv_h2 * ((a0 + a1) + ys[s2] + zs[s2]);
+        if (x < N) tile[wl0 * P + x + 1] = (T)r;
+      }
+    }
   } else {
     // flat mapping: thread owns tile elements e = tid + i*kBlock (x lines, narrow reals)
     const int cnt = nlines * N;
 #pragma unroll 1
     for (int c0 = 0; c0 < PER; c0 += CH) {
       T v[CH];
-      if constexpr (IN == IN_RESID) {
-#pragma unroll
-        for (int i0 = 0; i0 < CH; i0 += 4) {
-          constexpr int K4 = CH < 4 ? CH : 4;
-          double rb[K4], uc[K4], nb[K4];
-#pragma unroll
-          for (int k = 0; k < K4; ++k) {
-            const int e = min(tid + (c0 + i0 + k) * kBlock, cnt - 1);
-            const int ww = e / N;
-            const int x = e - ww * N;
-            const int ln = line0 + ww;
-            const int z = ln / N;
-            const int y = ln - z * N;
-            const double* __restrict__ u = p.u + base;
-            uc[k] = u[e];
-            rb[k] = LOGM == 8 ? __builtin_nontemporal_load(p.b + base + e) : p.b[base + e];
-            double a0 = x > 0 ? u[e - 1] : 0.0;
-            double a1 = x < N - 1 ? u[e + 1] : 0.0;
-            double a2 = y > 0 ? u[e - N] : 0.0;
-            double a3 = y < N - 1 ? u[e + N] : 0.0;
-            double a4 = z > 0 ? u[e - N * N] : 0.0;
-            double a5 = z < N - 1 ? u[e + N * N] : 0.0;
-            nb[k] = (a0 + a1) + (a2 + a3) + (a4 + a5);
-          }
-#pragma unroll
-          for (int k = 0; k < K4; ++k)
-            v[i0 + k] = (T)(rb[k] - (sig + 6.0 * p.inv_h2) * uc[k] + p.inv_h2 * nb[k]);
-        }
-      } else {
+      {
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
           const int e = min(tid + (c0 + i) * kBlock, cnt - 1);

@@ -481,6 +481,14 @@ __device__ __forceinline__ T ld(const T* base, unsigned byte_off) {
   const DPM_GLOBAL char* b = (const DPM_GLOBAL char*)sbase(base);
   return *(const DPM_GLOBAL T*)(b + byte_off);
 }
+// Lane l's value of v, read into scalar registers (l must be uniform).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // The same load with the non-temporal hint: data read once, not to be kept in the caches.
 template <typename T>
 __device__ __forceinline__ T ld_nt(const T* base, unsigned byte_off) {
