@@ -166,36 +166,48 @@ void k_dst_pass(PassArgs p, int tiles, int nblocks) {
       }
     }
   } else if constexpr (IN == IN_RESID) {
-    // FP64 residual into narrow reals along x: one line per wavefront at a time, lane l
-    // holding x = l + 64 s.  The line's base is uniform, so every load is the saddr form at
-    // the lane's 32-bit offset (512-byte runs) and the y and z neighbour tests are uniform; the
-    // x neighbours come from the adjacent lanes (across a step boundary from the previous or
-    // next step's end lane) instead of two more loads of the line.
+    // FP64 residual into narrow reals along x: each wavefront takes a run of consecutive lines
+    // of the tile, one line at a time, lane l holding x = l + 64 s.  The line's base is
+    // uniform, so every load is the saddr form at the lane's 32-bit offset (512-byte runs) and
+    // the y and z neighbour tests are uniform.  Along the run the y neighbours slide: a line's
+    // own values and its y - 1 neighbour are the previous line's y + 1 neighbour and own values
+    // (reloaded at the run's start and where a new z plane begins).  The x neighbours come from
+    // the adjacent lanes (across a step boundary from the previous or next step's end lane).
     constexpr int XS = (N + 63) / 64;                  // steps per line
     constexpr int NWV = kBlock / 64;                   // wavefronts per block
+    constexpr int LPW = (W + NWV - 1) / NWV;           // lines per wavefront
     const int lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double a6 = sig + 6.0 * p.inv_h2;
+    double uc[XS], un[XS];                             // this line, and its y + 1 neighbour
 #pragma unroll 1
-    for (int wl0 = wv; wl0 < nlines; wl0 += NWV) {     // uniform in the wavefront
+    for (int i = 0; i < LPW; ++i) {
+      const int wl0 = wv * LPW + i;                    // uniform in the wavefront
+      if (wl0 >= nlines) break;
       const int ln = line0 + wl0;
       const int z = ln / N;
       const int y = ln - z * N;
+      const bool fresh = i == 0 || y == 0;             // no previous line of this plane held
       const double* __restrict__ ub = p.u + base + (long long)wl0 * N;
       const double* __restrict__ bb = p.b + base + (long long)wl0 * N;
-      double uc[XS], rb[XS], ys[XS], zs[XS];
+      double rb[XS], ys[XS], zs[XS];
 #pragma unroll
       for (int s2 = 0; s2 < XS; ++s2) {
         const int x = min(lane + 64 * s2, N - 1);       // the last step's spare lanes reload
         const unsigned off = (unsigned)x * 8u;
-        uc[s2] = ld(ub, off);
+        double a2;
+        if (fresh) {
+          a2 = y > 0 ? ld(ub - N, off) : 0.0;           // pointer moves, never the offset
+          uc[s2] = ld(ub, off);
+        } else {
+          a2 = uc[s2];
+          uc[s2] = un[s2];
+        }
+        un[s2] = y < N - 1 ? ld(ub + N, off) : 0.0;
         rb[s2] = LOGM == 8 ? ld_nt(bb, off) : ld(bb, off);  // b: read once
-        // neighbours move the (uniform) pointer, never the unsigned offset below zero
-        const double a2 = y > 0 ? ld(ub - N, off) : 0.0;
-        const double a3 = y < N - 1 ? ld(ub + N, off) : 0.0;
         const double a4 = z > 0 ? ld(ub - (long long)N * N, off) : 0.0;
         const double a5 = z < N - 1 ? ld(ub + (long long)N * N, off) : 0.0;
-        ys[s2] = a2 + a3;
+        ys[s2] = a2 + un[s2];
         zs[s2] = a4 + a5;
       }
 #pragma unroll
