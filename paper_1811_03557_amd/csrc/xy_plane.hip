@@ -88,8 +88,58 @@ void k_xy_pass(PassArgs p, int nblocks) {
   }
 
   // ------------------------------------------------------------------ load the rows
-  {
-    constexpr int CH = IN == IN_RESID ? 4 : 8;
+  if constexpr (IN == IN_RESID) {
+    // FP64 residual b - (sigma - Lap_h) u of the wavefront's rows, one row at a time with lane l
+    // holding x = l + 64 s: every load is the saddr form at a uniform row base, the x
+    // neighbours come from the adjacent lanes (across a step boundary from the previous or next
+    // step's end lane), and along the rows a row's own values and its y - 1 neighbour are the
+    // previous row's loads.
+    constexpr int XS = (N + 63) / 64;                  // steps per row
+    const int r0 = __builtin_amdgcn_readfirstlane(row0);
+    const int rows = __builtin_amdgcn_readfirstlane(cnt) / N;
+    const double a6 = sig + 6.0 * p.inv_h2;
+    double uc[XS], un[XS];                             // this row, and its y + 1 neighbour
+#pragma unroll 1
+    for (int r = 0; r < rows; ++r) {
+      const int y = r0 + r;
+      const double* __restrict__ ub = p.u + wbase + (long long)r * N;
+      const double* __restrict__ bb = p.b + wbase + (long long)r * N;
+      double rb[XS], ys[XS], zs[XS];
+#pragma unroll
+      for (int s2 = 0; s2 < XS; ++s2) {
+        const int x = min(lane + 64 * s2, N - 1);       // the last step's spare lanes reload
+        const unsigned off = (unsigned)x * 8u;
+        double a2;
+        if (r == 0) {
+          a2 = y > 0 ? ld(ub - N, off) : 0.0;           // pointer moves, never the offset
+          uc[s2] = ld(ub, off);
+        } else {
+          a2 = uc[s2];
+          uc[s2] = un[s2];
+        }
+        un[s2] = y < N - 1 ? ld(ub + N, off) : 0.0;
+        rb[s2] = ld(bb, off);
+        const double a4 = z > 0 ? ld(ub - NN, off) : 0.0;
+        const double a5 = z < N - 1 ? ld(ub + NN, off) : 0.0;
+        ys[s2] = a2 + un[s2];
+        zs[s2] = a4 + a5;
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < XS; ++s2) {
+        const int x = lane + 64 * s2;
+        const double lm = __shfl_up(uc[s2], 1);         // lane - 1 (lane 0 keeps its own)
+        const double lp = __shfl_down(uc[s2], 1);       // lane + 1 (lane 63 keeps its own)
+        const double prev = s2 > 0 ? lane_value(uc[s2 > 0 ? s2 - 1 : 0], 63) : 0.0;
+        const double next = s2 < XS - 1 ? lane_value(uc[s2 < XS - 1 ? s2 + 1 : 0], 0) : 0.0;
+        const double a0 = x == 0 ? 0.0 : (lane == 0 ? prev : lm);
+        const double a1 = x >= N - 1 ? 0.0 : (lane == 63 ? next : lp);
+        // the stencil's sum in the order (x pair) + (y pair) + (z pair)
+        const double res = rb[s2] - a6 * uc[s2] + p.inv_h2 * ((a0 + a1) + ys[s2] + zs[s2]);
+        if (x < N) wplane[r * P + x + 1] = (T)res;
+      }
+    }
+  } else {
+    constexpr int CH = 8;
 #pragma unroll
     for (int c0 = 0; c0 < KMAX; c0 += CH) {
       T v[CH];
@@ -97,22 +147,7 @@ void k_xy_pass(PassArgs p, int nblocks) {
       for (int k = 0; k < CH; ++k) {
         if (c0 + k >= KMAX) break;
         const int e = min(lane + (c0 + k) * 64, cnt - 1);
-        if constexpr (IN == IN_RESID) {
-          const int ep = row0 * N + e;  // element of the plane
-          const int y = ep / N;
-          const int x = ep - y * N;
-          const double* __restrict__ u = p.u + base;
-          const double uc = u[ep];
-          const double rb = p.b[base + ep];
-          const double a0 = x > 0 ? u[ep - 1] : 0.0;
-          const double a1 = x < N - 1 ? u[ep + 1] : 0.0;
-          const double a2 = y > 0 ? u[ep - N] : 0.0;
-          const double a3 = y < N - 1 ? u[ep + N] : 0.0;
-          const double a4 = z > 0 ? u[ep - NN] : 0.0;
-          const double a5 = z < N - 1 ? u[ep + NN] : 0.0;
-          v[k] = (T)(rb - (sig + 6.0 * p.inv_h2) * uc +
-                     p.inv_h2 * ((a0 + a1) + (a2 + a3) + (a4 + a5)));
-        } else {
+        {
           // wave-uniform base of the step (clamped into the wavefront's rows), one 32-bit lane
           // offset in [0, 63]
           const int sk = min(64 * (c0 + k), cnt - 1);
