@@ -554,16 +554,23 @@ def run_autotune(args, b, h, dev):
     res = api.autotune(b, args.sigma, h, prec="fp64", reps=3)
     api.autotune_reset()
     torch.cuda.synchronize()
-    by = {w: t for w, z, t in zip(res["widths"], res["zcols"], res["ms"]) if z == 0}
+    # candidates per sweep layout (the per-axis sweeps, and the split layout where it exists)
+    by = {}
+    for w, sw, z, t in zip(res["widths"], res["sweeps"], res["zcols"], res["ms"]):
+        if z == 0:
+            by.setdefault(sw, {})[w] = t
     byz = {z: t for z, t in zip(res["zcols"], res["ms"]) if z != 0}
     out = {"workload": f"aux solve {n}^3, {nrhs} RHS, FP64", "default_width": default,
-           "best_width": res["best"], "best_z_columns": res["best_zcols"],
-           "ms_per_batch": {str(w): round(t, 3) for w, t in by.items()},
-           "solves_per_s": {str(w): round(nrhs / (t * 1e-3), 1) for w, t in by.items()},
+           "best_width": res["best"], "best_sweeps": res["best_sweeps"],
+           "best_z_columns": res["best_zcols"],
+           "ms_per_batch": {sw: {str(w): round(t, 3) for w, t in d.items()} for sw, d in by.items()},
+           "solves_per_s": {sw: {str(w): round(nrhs / (t * 1e-3), 1) for w, t in d.items()}
+                            for sw, d in by.items()},
            "ms_per_batch_by_z_columns": {str(z): round(t, 3) for z, t in byz.items()}}
-    log(f"[bench] autotune {n}^3 x {nrhs} FP64: best width {res['best']} (default {default}), "
-        f"z columns {res['best_zcols'] or 'default'}; "
-        + ", ".join(f"{w}: {t:.2f} ms" for w, t in by.items())
+    log(f"[bench] autotune {n}^3 x {nrhs} FP64: best width {res['best']} {res['best_sweeps']} "
+        f"(default {default}), z columns {res['best_zcols'] or 'default'}; "
+        + "; ".join(sw + " " + ", ".join(f"{w}: {t:.2f} ms" for w, t in d.items())
+                    for sw, d in by.items())
         + "; z columns " + ", ".join(f"{z}: {t:.2f} ms" for z, t in byz.items()))
     return out
 
